@@ -1,0 +1,143 @@
+/*
+ * vr_ref.h -- CPU oracle for the phase-space halo-finder hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, FP64 reference written
+ * from the paper (Elahi et al., "Hunting for Galaxies and Halos in
+ * simulations with VELOCIraptor").  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * All pointers are HOST pointers owned by the caller.  Every function returns
+ * 0 on success or a negative status (-1 invalid argument, -5 not converged).
+ *
+ * Parity caveats (also listed in the design notes): the face-neighbour rule
+ * and the minimum-entropy split choice of the cell tree are readings of an
+ * under-specified passage ("parity unpinned" by the paper itself; they are
+ * pinned only by structural invariants).
+ */
+#ifndef VR_REF_H
+#define VR_REF_H
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Particle set in structure-of-arrays form.  q* are grid coordinates in
+ * [0, 2^grid_bits); one grid unit is box / 2^grid_bits length units.
+ * mass == NULL means every particle has mass mass_value. */
+typedef struct {
+    int64_t n;
+    const uint32_t *qx, *qy, *qz;
+    const float *vx, *vy, *vz;
+    const float *mass;
+    double mass_value;
+    double box;
+    int32_t grid_bits;
+} vr_ref_particles;
+
+/* Number of worker threads used by the embarrassingly parallel loops
+ * (per host, per particle, per group).  1 = serial.  Returns the value set. */
+int vr_ref_set_threads(int n_threads);
+
+/* Quantise positions: q = floor(x * 2^grid_bits / box) mod 2^grid_bits,
+ * with the scale computed once in FP64. */
+int vr_ref_quantize(int64_t n, const float* x, const float* y, const float* z,
+                    double box, int32_t grid_bits,
+                    uint32_t* qx, uint32_t* qy, uint32_t* qz);
+
+/* Squared linking length in grid units: (ellx * 2^grid_bits / box)^2. */
+double vr_ref_ell2_grid(double ell, double box, int32_t grid_bits);
+
+/* 3D friends-of-friends (Eq. fof3d, Sec. 2.1): periodic minimum image,
+ * exact integer squared distance, link iff (double)d2 < ell2.
+ * label[i] = smallest particle index of i's component. */
+int vr_ref_fof3d(const vr_ref_particles* p, double ellx, int32_t* label);
+
+/* Groups of a labelling: components with size >= n_min (labels < 0 are
+ * ignored), ordered by size descending then smallest member index ascending;
+ * members ascending inside a group.  group_of[i] = group id or -1.
+ * offsets has n_groups+1 entries. */
+int vr_ref_groups(int64_t n, const int32_t* label, int32_t n_min,
+                  int32_t* n_groups, int32_t* group_of,
+                  int32_t* offsets, int32_t* members);
+
+/* Entropy of a binned mass distribution (Sec. 2.2, unlabelled entropy
+ * equation): S = -sum_k p_k ln p_k / ln nb, p_k = h_k / sum h. */
+double vr_ref_entropy(int32_t nb, const double* hist);
+
+typedef struct {
+    double f_cell;        /* 0.01 */
+    int32_t ncell_floor;  /* 100 */
+    int32_t ncell_div;    /* 8 */
+    int32_t nbins;        /* 16 */
+    int32_t split_rule;   /* 0 = split the minimum-entropy dimension, 1 = maximum */
+} vr_ref_cell_params;
+
+#define VR_REF_CELL_COLS 28
+
+/* Entropy KD cells, per-cell moments and inverse-distance interpolation
+ * (Sec. 2.2, Eqs. meanpos, meanvel, meandispvel, cellinterp).
+ * Hosts are given as ascending member lists.  For every host member writes
+ * vbar[3*n] (component-major), sigma[6*n] (xx,yy,zz,xy,xz,yz), rho_cell[n],
+ * cell_of[n].  Cells are numbered per host, hosts in the order given, and
+ * inside a host by ascending smallest member index.  If cell_table != NULL it
+ * receives VR_REF_CELL_COLS doubles per cell (layout in the .cpp). */
+int vr_ref_cell_moments(const vr_ref_particles* p, int32_t n_hosts,
+                        const int32_t* host_offsets, const int32_t* host_members,
+                        const vr_ref_cell_params* cp,
+                        float* vbar, float* sigma, float* rho_cell, int32_t* cell_of,
+                        int64_t cell_capacity, double* cell_table, int64_t* n_cells);
+
+/* Local velocity density ratio R = ln(f_l / f_bg) (Sec. 2.2, Eq. fvbg and
+ * the unlabelled R equation).  Processes every member of every host, or only
+ * the listed subset (each entry must be a host member).  Writes R only for
+ * processed particles.  Optional FP64 side outputs (may be NULL):
+ * lnfl[n], lnfbg[n]; nbr_s[n_proc*n_se] and nbr_v[n_proc*n_v] hold the
+ * spatial and velocity neighbour sets of the processed particles in
+ * processing order (ascending by their ordering key). */
+int vr_ref_local_vdensity(const vr_ref_particles* p, int32_t n_hosts,
+                          const int32_t* host_offsets, const int32_t* host_members,
+                          const float* vbar, const float* sigma,
+                          int32_t n_se, int32_t n_v,
+                          const int32_t* subset, int64_t n_subset,
+                          float* R, double* lnfl, double* lnfbg,
+                          int32_t* nbr_s, int32_t* nbr_v);
+
+/* Velocity linking length per host: alpha_v * (det Sigma_H)^(1/6), Sigma_H
+ * the mass-weighted dispersion tensor of all host members about their
+ * mass-weighted mean velocity (Sec. 2.1 with the sigV definition of the
+ * property table). */
+int vr_ref_host_ellv(const vr_ref_particles* p, int32_t n_hosts,
+                     const int32_t* host_offsets, const int32_t* host_members,
+                     double alpha_v, double* ellv_host);
+
+/* 6D friends-of-friends over outliers (Eq. fof6d): participants are hosted
+ * particles (host_of >= 0) with R >= R_threshold (all hosted ones if R is
+ * NULL); link iff same host and d2/ellxs2 + dv2/ellv^2 < 1.
+ * label6 = smallest participant index of the component, -1 otherwise. */
+int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of,
+                 const double* ellv_host, double ellx_s,
+                 const float* R, float R_threshold, int32_t* label6);
+
+typedef struct {
+    double G, eps, beta_E, frac_ref;
+    int32_t n_min, n_ref_min, frame_type, max_iter;
+} vr_ref_unbind_params;
+
+/* Unbinding (Sec. 2.2, Eq. binding) by direct FP64 summation of
+ * Plummer-softened pair potentials.  bound[i] (0/1) for every member,
+ * phi[i] = potential of i in the last pass it took part in, iters[g] =
+ * passes run.  min_margin[g] (may be NULL) = smallest |beta_E T + W| / |W|
+ * met in any pass of group g (used to excuse classifications that sit on
+ * the threshold). */
+int vr_ref_unbind(const vr_ref_particles* p, int32_t n_groups,
+                  const int32_t* offsets, const int32_t* members,
+                  const vr_ref_unbind_params* up,
+                  uint8_t* bound, double* phi, int32_t* iters, double* min_margin);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

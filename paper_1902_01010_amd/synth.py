@@ -1,0 +1,307 @@
+"""Seeded synthetic workloads shaped like the paper's simulations.
+
+The paper measures on SURFS N-body snapshots (L40N512, L210N1536, Table
+"Simulation parameters"), which are not available here; these generators stand
+in for them.  They only draw particles: positions (float32, length units,
+inside a periodic box), velocities (float32, km/s) and masses.  They contain
+none of the halo finder's arithmetic, and both the GPU path and the CPU oracle
+consume their output.
+
+Units: Mpc/h, km/s, Msun/h.  Every generator shuffles the particle order so
+that index order carries no spatial structure.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+from scipy.special import lambertw
+
+RHO_CRIT = 2.7754e11     # critical density, h^2 Msun / Mpc^3
+OMEGA_M = 0.3121         # matter density implied by the particle masses of the simulation table
+G_GRAV = 4.30091e-9      # gravitational constant, Mpc (km/s)^2 / Msun
+GRID_BITS = 21
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    x: np.ndarray            # (3, n) float32 positions in [0, box)
+    v: np.ndarray            # (3, n) float32 velocities
+    mass: np.ndarray | None  # (n,) float32, or None for uniform mass
+    mass_value: float
+    box: float
+    grid_bits: int
+    params: dict             # method parameters for this workload
+    meta: dict               # generator bookkeeping (component counts, seeds)
+    groups: tuple | None = None   # (offsets, members) for group-level workloads
+
+    @property
+    def n(self) -> int:
+        return self.x.shape[1]
+
+
+# ---------------------------------------------------------------------------
+# Profile samplers
+
+def _unit_vectors(rng, n):
+    u = rng.normal(size=(3, n))
+    u /= np.linalg.norm(u, axis=0, keepdims=True)
+    return u
+
+
+def _nfw_mu(x):
+    return np.log1p(x) - x / (1.0 + x)
+
+
+def nfw_radii(rng, n, r200, c):
+    """Radii of an NFW profile truncated at r200 (inverse enclosed mass via Lambert W)."""
+    c = np.broadcast_to(np.asarray(c, np.float64), (n,))
+    r200 = np.broadcast_to(np.asarray(r200, np.float64), (n,))
+    mu = rng.random(n) * _nfw_mu(c)
+    w = lambertw(-np.exp(-1.0 - mu), 0).real
+    x = -1.0 / w - 1.0
+    return x * (r200 / c)
+
+
+def plummer_radii(rng, n, a, umax=0.985):
+    """Radii of a Plummer sphere, truncated near 10a by capping the mass fraction."""
+    u = rng.random(n) * umax
+    return np.asarray(a) / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+
+
+def power_law_sizes(rng, lo, hi, total, slope=0.9):
+    """Integer sizes from dN/dlnN ~ N^-slope on [lo, hi], drawn until they sum
+    to at least `total`; the last draw is truncated so the sum is exact."""
+    out, acc = [], 0
+    a, b = lo ** (-slope), hi ** (-slope)
+    while acc < total:
+        u = rng.random(4096)
+        s = np.floor((a - u * (a - b)) ** (-1.0 / slope)).astype(np.int64)
+        s = np.clip(s, lo, hi)
+        cs = np.cumsum(s) + acc
+        k = int(np.searchsorted(cs, total))
+        if k < len(s):
+            s = s[:k + 1].copy()
+            s[-1] -= cs[k] - total
+            out.append(s)
+            acc = total
+        else:
+            out.append(s)
+            acc = int(cs[-1])
+    sizes = np.concatenate(out)
+    return sizes[sizes > 0]
+
+
+def _nfw_phi(r, m200, r200, c):
+    """Potential of an NFW sphere truncated at r200 (for escape speeds)."""
+    rs = r200 / c
+    x = np.maximum(r, 1e-12) / rs
+    k = G_GRAV * m200 / _nfw_mu(c)
+    inside = -k * (np.log1p(x) / np.maximum(r, 1e-12) - np.log1p(c) / r200) - G_GRAV * m200 / r200
+    return np.where(r <= r200, inside, -G_GRAV * m200 / np.maximum(r, 1e-12))
+
+
+def _finish(name, rng, pos, vel, box, mass, mass_value, params, meta, groups_of=None, extra=None):
+    n = pos.shape[1]
+    perm = rng.permutation(n)
+    for k, a in (extra or {}).items():
+        meta[k] = a[perm]
+    pos = np.mod(pos[:, perm], box)
+    # float32 rounding can map a coordinate just below the box edge onto it
+    x = pos.astype(np.float32)
+    x[x >= np.float32(box)] = 0.0
+    v = vel[:, perm].astype(np.float32)
+    m = None if mass is None else mass[perm].astype(np.float32)
+    groups = None
+    if groups_of is not None:
+        gid = groups_of[perm]
+        order = np.lexsort((np.arange(n), gid))
+        order = order[gid[order] >= 0]
+        counts = np.bincount(gid[gid >= 0], minlength=int(gid.max()) + 1)
+        offsets = np.zeros(len(counts) + 1, np.int32)
+        offsets[1:] = np.cumsum(counts)
+        groups = (offsets, order.astype(np.int32))
+    return Workload(name, x, v, m, mass_value, float(box), GRID_BITS, params, meta, groups)
+
+
+def mean_spacing_for_mass(m_p):
+    """Cosmological mean inter-particle spacing for a particle mass."""
+    return (m_p / (OMEGA_M * RHO_CRIT)) ** (1.0 / 3.0)
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+
+def isolated_halo(seed=1, n_host=100_000, n_sub=5, sub_range=(1000, 10000), box=1.0, m=1e8):
+    """Single isolated halo: an NFW host (c=10, r200=0.3 Mpc/h at 1e5 particles)
+    with Plummer subhalos (a = 5-15 kpc/h at radii 30-250 kpc/h), Gaussian
+    velocities (host sigma 200, subhalo sigma 10-30 km/s, subhalo bulk
+    N(0, 200) per axis), equal masses 1e8 Msun/h, 1 Mpc/h periodic box."""
+    rng = np.random.default_rng(seed)
+    scale = (n_host / 1e5) ** (1.0 / 3.0)
+    r200, c = 0.3 * scale, 10.0
+    centre = np.full((3, 1), 0.5 * box)
+    r = nfw_radii(rng, n_host, r200, c)
+    pos = [centre + _unit_vectors(rng, n_host) * r]
+    vel = [rng.normal(0.0, 200.0, size=(3, n_host))]
+    subs = []
+    for _ in range(n_sub):
+        ns = int(rng.integers(sub_range[0], sub_range[1] + 1))
+        a = rng.uniform(0.005, 0.015) * scale
+        rc = rng.uniform(0.030, 0.250) * scale
+        sc = centre + _unit_vectors(rng, 1) * rc
+        rr = plummer_radii(rng, ns, a)
+        pos.append(sc + _unit_vectors(rng, ns) * rr)
+        sig = rng.uniform(10.0, 30.0)
+        bulk = rng.normal(0.0, 200.0, size=(3, 1))
+        vel.append(bulk + rng.normal(0.0, sig, size=(3, ns)))
+        subs.append(dict(n=ns, a=a, r=rc, sigma=sig))
+    pos = np.concatenate(pos, axis=1)
+    vel = np.concatenate(vel, axis=1)
+    spacing = mean_spacing_for_mass(m)
+    params = dict(ellx=0.2 * spacing, n_se=32, n_v=8, R_threshold=2.0, alpha_v=1.25,
+                  alpha_xs=0.5, eps=0.02 * spacing, G=G_GRAV, beta_E=0.95, n_min=20,
+                  host_min=256)
+    meta = dict(seed=seed, n_host=n_host, subhalos=subs, spacing=spacing)
+    return _finish("isolated_halo", rng, pos, vel, box, None, m, params, meta)
+
+
+def cosmo_box(seed=2, n_side=256, box=None, halo_frac=0.45, sub_frac=0.10, n_max=None):
+    """Synthetic cosmological box: a fraction of the particles in NFW halos
+    whose sizes follow dN/dlnN ~ N^-0.9 on [20, n_max], each with Plummer
+    subhalos holding 10% of its particles; the rest is a uniform background.
+    Halo dispersion 300 (N/1e5)^(1/3) km/s, halo bulk N(0, 400), background
+    N(0, 300).  The box keeps the mean spacing of 256^3 particles in 100 Mpc/h
+    unless given."""
+    rng = np.random.default_rng(seed)
+    n_tot = n_side ** 3
+    if box is None:
+        box = 100.0 * n_side / 256.0
+    if n_max is None:
+        n_max = int(min(2_000_000, max(1000, 2_000_000 * n_tot / 256 ** 3)))
+    m_p = OMEGA_M * RHO_CRIT * box ** 3 / n_tot
+    sizes = power_law_sizes(rng, 20, n_max, int(round(halo_frac * n_tot)))
+    nh = len(sizes)
+    conc = rng.uniform(5.0, 15.0, nh)
+    r200 = (3.0 * sizes * m_p / (4.0 * np.pi * 200.0 * RHO_CRIT)) ** (1.0 / 3.0)
+    sig_h = 300.0 * (sizes / 1e5) ** (1.0 / 3.0)
+    centres = rng.random((3, nh)) * box
+    bulk = rng.normal(0.0, 400.0, size=(3, nh))
+    # Subhalo components (part of their halo's particle count).
+    s_host, s_size = [], []
+    for h in np.nonzero(sub_frac * sizes >= 20)[0]:
+        ss = power_law_sizes(rng, 20, int(sub_frac * sizes[h]), int(sub_frac * sizes[h]))
+        ss = ss[ss >= 2]
+        s_host.append(np.full(len(ss), h))
+        s_size.append(ss)
+    s_host = np.concatenate(s_host) if s_host else np.zeros(0, np.int64)
+    s_size = np.concatenate(s_size) if s_size else np.zeros(0, np.int64)
+    n_in_subs = np.bincount(s_host, weights=s_size, minlength=nh).astype(np.int64)
+    n_nfw = sizes - n_in_subs
+    # NFW part of every halo.
+    hid = np.repeat(np.arange(nh), n_nfw)
+    r = nfw_radii(rng, len(hid), r200[hid], conc[hid])
+    pos_h = centres[:, hid] + _unit_vectors(rng, len(hid)) * r
+    vel_h = bulk[:, hid] + rng.normal(size=(3, len(hid))) * sig_h[hid]
+    # Plummer subhalos.
+    ns = len(s_size)
+    ha = s_host
+    a = rng.uniform(0.005, 0.015, ns) * r200[ha] / 0.3
+    rc = rng.uniform(0.1, 0.83, ns) * r200[ha]
+    sc = centres[:, ha] + _unit_vectors(rng, ns) * rc
+    sig_s = rng.uniform(10.0, 30.0, ns) * sig_h[ha] / 200.0
+    sb = bulk[:, ha] + rng.normal(size=(3, ns)) * sig_h[ha]
+    sid = np.repeat(np.arange(ns), s_size)
+    rr = plummer_radii(rng, len(sid), a[sid])
+    pos_s = sc[:, sid] + _unit_vectors(rng, len(sid)) * rr
+    vel_s = sb[:, sid] + rng.normal(size=(3, len(sid))) * sig_s[sid]
+    # Uniform background.
+    nb = n_tot - int(sizes.sum())
+    pos_b = rng.random((3, nb)) * box
+    vel_b = rng.normal(0.0, 300.0, size=(3, nb))
+    pos = np.concatenate([pos_h, pos_s, pos_b], axis=1)
+    vel = np.concatenate([vel_h, vel_s, vel_b], axis=1)
+    spacing = box / n_side
+    params = dict(ellx=0.2 * spacing, n_se=32, n_v=8, R_threshold=2.0, alpha_v=1.25,
+                  alpha_xs=0.5, eps=0.02 * spacing, G=G_GRAV, beta_E=0.95, n_min=20,
+                  host_min=256)
+    meta = dict(seed=seed, n_side=n_side, n_halos=nh, n_subhalos=ns, n_background=nb,
+                m_p=m_p, spacing=spacing, n_max=n_max)
+    return _finish("cosmo_box", rng, pos, vel, box, None, m_p, params, meta)
+
+
+def unbind_groups(seed=3, n_groups=50_000, n_max=2_000_000, box=100.0, m=1e8,
+                  contam_frac=0.2, n_sub=5):
+    """Groups for batched unbinding: C1-style NFW hosts (c = 10, r200 and
+    sigma scaled by (N/1e5)^(1/3)) with Plummer subhalos of 1-10% of N, plus
+    round(0.2 N) contaminants at twice the local escape speed.  Returns the
+    particle set and the (offsets, members) group table."""
+    rng = np.random.default_rng(seed)
+    a0, b0 = 20.0 ** -0.9, float(n_max) ** -0.9
+    u = rng.random(n_groups)
+    sizes = np.clip(np.floor((a0 - u * (a0 - b0)) ** (-1.0 / 0.9)), 20, n_max).astype(np.int64)
+    scale = (sizes / 1e5) ** (1.0 / 3.0)
+    r200, c = 0.3 * scale, 10.0
+    sig = 200.0 * scale
+    m200 = sizes * m
+    centres = rng.random((3, n_groups)) * box
+    # subhalo sizes (part of N)
+    fr = rng.uniform(0.01, 0.1, size=(n_groups, n_sub))
+    sub_n = np.floor(fr * sizes[:, None]).astype(np.int64)
+    sub_n[sub_n < 20] = 0
+    n_nfw = sizes - sub_n.sum(1)
+    n_con = np.rint(contam_frac * sizes).astype(np.int64)
+    gid_h = np.repeat(np.arange(n_groups), n_nfw)
+    r = nfw_radii(rng, len(gid_h), r200[gid_h], c)
+    pos_h = centres[:, gid_h] + _unit_vectors(rng, len(gid_h)) * r
+    vel_h = rng.normal(size=(3, len(gid_h))) * sig[gid_h]
+    # subhalos
+    sg = np.repeat(np.arange(n_groups), n_sub)
+    sn = sub_n.reshape(-1)
+    keep = sn > 0
+    sg, sn = sg[keep], sn[keep]
+    nsb = len(sn)
+    a = rng.uniform(0.005, 0.015, nsb) * scale[sg]
+    rc = rng.uniform(0.030, 0.250, nsb) * scale[sg]
+    sc = centres[:, sg] + _unit_vectors(rng, nsb) * rc
+    ss = rng.uniform(10.0, 30.0, nsb) * scale[sg]
+    sb = rng.normal(size=(3, nsb)) * sig[sg]
+    sid = np.repeat(np.arange(nsb), sn)
+    pos_s = sc[:, sid] + _unit_vectors(rng, len(sid)) * plummer_radii(rng, len(sid), a[sid])
+    vel_s = sb[:, sid] + rng.normal(size=(3, len(sid))) * ss[sid]
+    gid_s = sg[sid]
+    # contaminants at twice the escape speed of the host profile
+    gid_c = np.repeat(np.arange(n_groups), n_con)
+    rcn = nfw_radii(rng, len(gid_c), r200[gid_c], c)
+    pos_c = centres[:, gid_c] + _unit_vectors(rng, len(gid_c)) * rcn
+    vesc = np.sqrt(-2.0 * _nfw_phi(rcn, m200[gid_c], r200[gid_c], c))
+    vel_c = _unit_vectors(rng, len(gid_c)) * (2.0 * vesc)
+    pos = np.concatenate([pos_h, pos_s, pos_c], axis=1)
+    vel = np.concatenate([vel_h, vel_s, vel_c], axis=1)
+    gid = np.concatenate([gid_h, gid_s, gid_c])
+    is_con = np.concatenate([np.zeros(len(gid_h) + len(gid_s), bool), np.ones(len(gid_c), bool)])
+    spacing = mean_spacing_for_mass(m)
+    params = dict(eps=0.02 * spacing, G=G_GRAV, beta_E=0.95, n_min=20)
+    meta = dict(seed=seed, n_groups=n_groups, sizes=sizes, n_contaminants=n_con,
+                sum_n2=float(((sizes + n_con) ** 2).sum()))
+    return _finish("unbind_groups", rng, pos, vel, box, None, m, params, meta,
+                   groups_of=gid, extra=dict(is_contaminant=is_con))
+
+
+def maxwellian_host(seed=7, n=4096, box=1.0, extent=0.2, sigma=150.0, m=1.0):
+    """Uniform positions in a cube of side `extent` inside the box and
+    isotropic Gaussian velocities: a smooth background with no substructure."""
+    rng = np.random.default_rng(seed)
+    pos = 0.5 * box + (rng.random((3, n)) - 0.5) * extent
+    vel = rng.normal(0.0, sigma, size=(3, n))
+    params = dict(sigma=sigma, extent=extent)
+    return _finish("maxwellian", rng, pos, vel, box, None, m, params, dict(seed=seed))
+
+
+def plummer_sphere(seed=8, n=20000, a=0.01, box=1.0, m=1.0, sigma=50.0):
+    rng = np.random.default_rng(seed)
+    r = plummer_radii(rng, n, a, umax=0.999)
+    pos = 0.5 * box + _unit_vectors(rng, n) * r
+    vel = rng.normal(0.0, sigma, size=(3, n))
+    return _finish("plummer", rng, pos, vel, box, None, m, dict(a=a), dict(seed=seed))
