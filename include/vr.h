@@ -1,0 +1,179 @@
+/*
+ * vr.h -- C ABI of libvr, the MI355X (gfx950) hot path of the VELOCIraptor
+ * phase-space halo finder (Elahi et al.): 3D friends-of-friends, entropy KD
+ * cells with velocity moments, the local velocity-density ratio R, 6D
+ * friends-of-friends over the outliers, and unbinding by summed potentials.
+ *
+ * Conventions shared by every call
+ *  - Array arguments are DEVICE pointers, caller-owned, structure-of-arrays.
+ *    The library never frees caller memory.  Particle counts n < 2^31.
+ *  - Grid coordinates q are uint32 in [0, 2^grid_bits); one grid unit is
+ *    box / 2^grid_bits length units; the box is periodic.
+ *  - Every call enqueues its kernels on `stream` (a hipStream_t passed as
+ *    void*, NULL = the default stream) and returns a status.  Arguments are
+ *    validated on the host before any device work; outputs are undefined when
+ *    a call returns non-zero; vr_last_error() gives the message.
+ *  - Calls marked "syncs" wait for the stream because they return a count to
+ *    the host.
+ *  - Temporary device memory comes from the context's workspace pool, capped
+ *    by max_workspace_bytes (VR_ERR_OUT_OF_MEMORY when exceeded).
+ *  - A context serves one stream at a time and is not thread-safe; several
+ *    contexts may coexist.
+ */
+#ifndef VR_H
+#define VR_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VR_OK = 0,
+    VR_ERR_INVALID_ARG = -1,
+    VR_ERR_NO_DEVICE = -2,
+    VR_ERR_OUT_OF_MEMORY = -3,
+    VR_ERR_HIP = -4,
+    VR_ERR_NOT_CONVERGED = -5,
+    VR_ERR_UNSUPPORTED = -6
+};
+
+typedef struct vr_ctx vr_ctx;
+
+/* Create a context on `device`.  max_workspace_bytes = 0 means no cap.
+ * Returns VR_ERR_NO_DEVICE when no gfx950 device with that ordinal exists. */
+int vr_create(vr_ctx** ctx, int device, size_t max_workspace_bytes);
+void vr_destroy(vr_ctx* ctx);
+/* Message for the last failure on ctx (or of vr_create when ctx is NULL). */
+const char* vr_last_error(const vr_ctx* ctx);
+/* Wait for the stream and report a pending asynchronous HIP error. */
+int vr_sync(vr_ctx* ctx, void* stream);
+/* Bytes of workspace currently held by the context. */
+size_t vr_workspace_bytes(const vr_ctx* ctx);
+
+/* Particle set.  mass == NULL means every particle has mass mass_value. */
+typedef struct {
+    int64_t n;
+    const uint32_t *qx, *qy, *qz;
+    const float *vx, *vy, *vz;
+    const float *mass;
+    double mass_value;
+    double box;
+    int32_t grid_bits;   /* 1..21 */
+} vr_particles;
+
+/* Quantisation onto the integer grid of the periodic box (the workloads fix
+ * 2^21-grid coordinates): q = floor(x * 2^grid_bits / box) mod 2^grid_bits,
+ * the scale computed once in FP64, x promoted exactly from float. */
+int vr_quantize(vr_ctx* ctx, int64_t n, const float* x, const float* y, const float* z,
+                double box, int32_t grid_bits, uint32_t* qx, uint32_t* qy, uint32_t* qz,
+                void* stream);
+
+/* 3D friends-of-friends (Sec. 2.1, Eq. fof3d): i and j are linked iff
+ * |x_i - x_j|^2 < ellx^2 with the periodic minimum image.  The squared
+ * distance is exact (integer grid); the test is (double)d2 < ell2 with
+ * ell2 = (ellx * 2^grid_bits / box)^2 in FP64.  ellx is in length units and
+ * must satisfy 0 < ellx < box/2.
+ * label[i] (out, n int32) = smallest particle index of i's component. */
+int vr_fof3d(vr_ctx* ctx, const vr_particles* p, double ellx, int32_t* label, void* stream);
+
+/* Groups of a canonical labelling (label[label[i]] == label[i], or < 0 for
+ * no group): components of at least n_min members (N_min, Sec. 2.2),
+ * ordered by size descending then smallest member ascending; members
+ * ascending inside a group.  Outputs: *n_groups (HOST), group_of[n] (group
+ * id or -1), offsets[n_groups+1] (capacity n+1), members[offsets[n_groups]]
+ * (capacity n).  Syncs. */
+int vr_groups(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t n_min, int32_t* n_groups,
+              int32_t* group_of, int32_t* offsets, int32_t* members, void* stream);
+
+typedef struct {
+    double f_cell;        /* N_cell = f_cell N_H (0.01) ...                  */
+    int32_t ncell_floor;  /* ... raised to at least this (100) ...           */
+    int32_t ncell_div;    /* ... and capped at N_H / ncell_div (8)           */
+    int32_t nbins;        /* bins of the entropy histogram (16, <= 64)       */
+    int32_t split_rule;   /* 0 = split the minimum-entropy dimension, 1 = max */
+} vr_cell_params;
+
+#define VR_CELL_COLS 28
+
+/* Entropy KD cells, per-cell moments and interpolation (Sec. 2.2, the
+ * entropy equation and Eqs. meanpos, meanvel, meandispvel, cellinterp).
+ * Hosts: host_offsets[n_hosts+1], host_members (ascending inside each host,
+ * every host of at least ncell_div members).  Each host is unwrapped by the
+ * minimum image relative to its first member, split recursively at the
+ * median of the chosen dimension until a node holds at most N_cell members
+ * (N_cell = min(max(ceil(f_cell N_H), ncell_floor), N_H / ncell_div)).  For
+ * every host member writes vbar[3*n] (component-major), sigma[6*n]
+ * (xx,yy,zz,xy,xz,yz), rho_cell[n] and cell_of[n]; other entries are not
+ * touched.  Cells are numbered per host (hosts in order, cells by ascending
+ * smallest member).  cell_table (may be NULL) receives VR_CELL_COLS doubles
+ * per cell: host, n, M, xbar[3], vbar[3], sigma[6], lo[3], hi[3], face
+ * neighbours[6] (-x,+x,-y,+y,-z,+z; -1 none), volume.  *n_cells (HOST).
+ * Syncs. */
+int vr_cell_moments(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
+                    const int32_t* host_offsets, const int32_t* host_members,
+                    const vr_cell_params* cp, float* vbar, float* sigma, float* rho_cell,
+                    int32_t* cell_of, int64_t cell_capacity, double* cell_table,
+                    int64_t* n_cells, void* stream);
+
+/* Local velocity density ratio R = ln(f_l / f_bg) (Sec. 2.2, Eq. fvbg and
+ * the ratio that follows the interpolation equation).  For particle k of a
+ * host: S_k = the n_se members nearest in space (self included, ties by
+ * index); V_k = the n_v members of S_k nearest in velocity; h = velocity
+ * distance to the n_v-th; f_l = sum_V m_j W(|dv_j|/h) / (h^3 sum_S m_j) with
+ * the 3D Epanechnikov kernel W(u) = 15/(8 pi) (1 - u^2); f_bg = Gaussian at
+ * vbar(x_k), sigma(x_k).  2 <= n_v <= n_se <= 64, every host has >= n_se
+ * members.  subset (may be NULL = all host members) lists the particles to
+ * process; R is written only for them (NaN if sigma is not positive
+ * definite, +inf if h = 0). */
+int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
+                      const int32_t* host_offsets, const int32_t* host_members,
+                      const float* vbar, const float* sigma, int32_t n_se, int32_t n_v,
+                      const int32_t* subset, int64_t n_subset, float* R, void* stream);
+
+/* Velocity linking length per host (Sec. 2.1: ellv = alpha_v sigma_v with
+ * sigma_v = (det Sigma_H)^(1/6), Sigma_H the mass-weighted dispersion tensor
+ * of all members about their mass-weighted mean).  ellv_host[n_hosts]. */
+int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
+                 const int32_t* host_offsets, const int32_t* host_members, double alpha_v,
+                 double* ellv_host, void* stream);
+
+/* 6D friends-of-friends over outliers (Eq. fof6d with the substructure
+ * linking length ellx_s = alpha_xS ellx): participants are particles with
+ * host_of[i] >= 0 and R[i] >= R_threshold (all hosted ones if R is NULL);
+ * i and j are linked iff both participate, share a host h, and
+ * d2/ells2 + dv2/ellv_host[h]^2 < 1 (FP64, that evaluation order).
+ * label6[i] = smallest participant index of i's component, -1 otherwise. */
+int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of,
+             const double* ellv_host, int32_t n_hosts, double ellx_s, const float* R,
+             float R_threshold, int32_t* label6, void* stream);
+
+typedef struct {
+    double G;          /* gravitational constant in the particle units       */
+    double eps;        /* Plummer softening length                            */
+    double beta_E;     /* remove beta_E T + W >= 0 (0.95)                     */
+    double frac_ref;   /* fraction of members defining the velocity frame (0.1) */
+    int32_t n_min;     /* dissolve below this many members (20)               */
+    int32_t n_ref_min; /* at least this many frame members (10)               */
+    int32_t frame_type;/* 1 = around the potential minimum, 0 = whole group    */
+    int32_t max_iter;  /* VR_ERR_NOT_CONVERGED beyond this many passes (100)  */
+    int32_t persistent;/* 1 = one persistent launch per pass over all groups  */
+    int32_t tile;      /* j-tile of the potential kernel, 0 = autotuned       */
+} vr_unbind_params;
+
+/* Unbinding (Sec. 2.2, Eq. binding), groups treated in isolation: per pass,
+ * phi_i = -G sum_{j != i} m_j / sqrt(r_ij^2 + eps^2) over the current set
+ * (FP32 pair terms, FP64 accumulation), a velocity frame from the members
+ * nearest the potential minimum, removal of beta_E T + W >= 0, repeated until
+ * nothing is removed; a group falling below n_min is dissolved.
+ * Outputs for every member: bound[i] (0/1), phi[i] (FP64, potential in the
+ * last pass i took part in); iters[g] = passes run.  Syncs. */
+int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, const int32_t* offsets,
+              const int32_t* members, const vr_unbind_params* up, uint8_t* bound, double* phi,
+              int32_t* iters, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

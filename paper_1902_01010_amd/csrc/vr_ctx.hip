@@ -1,0 +1,142 @@
+// vr_ctx.hip -- context, workspace pool, errors and argument checks.
+#include "vr_internal.h"
+
+#include <cstring>
+
+namespace {
+thread_local std::string g_create_err;
+}
+
+namespace vr {
+
+int set_err(vr_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf; else g_create_err = buf;
+    return code;
+}
+
+void* ws(vr_ctx* ctx, int slot, size_t bytes) {
+    if ((int)ctx->slots.size() < WS_NSLOTS) ctx->slots.resize(WS_NSLOTS);
+    vr_buf& b = ctx->slots[slot];
+    if (b.bytes >= bytes && b.ptr) return b.ptr;
+    size_t want = bytes + bytes / 4 + 4096;
+    size_t newheld = ctx->held - b.bytes + want;
+    if (ctx->max_ws && newheld > ctx->max_ws) {
+        want = bytes;
+        newheld = ctx->held - b.bytes + want;
+        if (newheld > ctx->max_ws) {
+            set_err(ctx, VR_ERR_OUT_OF_MEMORY, "workspace cap of %zu bytes exceeded (%zu requested)",
+                    ctx->max_ws, newheld);
+            return nullptr;
+        }
+    }
+    if (b.ptr) {
+        (void)hipFree(b.ptr);
+        ctx->held -= b.bytes;
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(ctx, VR_ERR_OUT_OF_MEMORY, "hipMalloc of %zu workspace bytes failed", want);
+        return nullptr;
+    }
+    b.ptr = p;
+    b.bytes = want;
+    ctx->held += want;
+    return p;
+}
+
+int check_particles(vr_ctx* ctx, const vr_particles* p, bool need_vel) {
+    if (!p) return set_err(ctx, VR_ERR_INVALID_ARG, "particles is NULL");
+    if (p->n < 0 || p->n >= (int64_t(1) << 31))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "n = %lld out of range [0, 2^31)", (long long)p->n);
+    if (p->grid_bits < 1 || p->grid_bits > 21)
+        return set_err(ctx, VR_ERR_INVALID_ARG, "grid_bits = %d not in 1..21", p->grid_bits);
+    if (!(p->box > 0)) return set_err(ctx, VR_ERR_INVALID_ARG, "box must be positive");
+    if (p->n > 0 && (!p->qx || !p->qy || !p->qz))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "NULL coordinate array");
+    if (need_vel && p->n > 0 && (!p->vx || !p->vy || !p->vz))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "NULL velocity array");
+    if (!p->mass && !(p->mass_value > 0))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "uniform mass_value must be positive");
+    return VR_OK;
+}
+
+int check_hosts(vr_ctx* ctx, int32_t n_hosts, const int32_t* off, const int32_t* mem) {
+    if (n_hosts < 0) return set_err(ctx, VR_ERR_INVALID_ARG, "n_hosts < 0");
+    if (n_hosts > 0 && (!off || !mem)) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL host arrays");
+    return VR_OK;
+}
+
+int read_back(vr_ctx* ctx, const void* dev, void* host, size_t bytes, hipStream_t s) {
+    VR_HIP(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    VR_HIP(ctx, hipStreamSynchronize(s));
+    return VR_OK;
+}
+
+}  // namespace vr
+
+extern "C" {
+
+int vr_create(vr_ctx** out, int device, size_t max_workspace_bytes) {
+    if (!out) return vr::set_err(nullptr, VR_ERR_INVALID_ARG, "ctx pointer is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return vr::set_err(nullptr, VR_ERR_NO_DEVICE, "no HIP device visible");
+    }
+    if (device < 0 || device >= count)
+        return vr::set_err(nullptr, VR_ERR_NO_DEVICE, "device %d not in [0, %d)", device, count);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return vr::set_err(nullptr, VR_ERR_NO_DEVICE, "cannot query device %d", device);
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return vr::set_err(nullptr, VR_ERR_UNSUPPORTED, "device %d is %s, libvr is built for gfx950",
+                           device, prop.gcnArchName);
+    if (hipSetDevice(device) != hipSuccess)
+        return vr::set_err(nullptr, VR_ERR_HIP, "hipSetDevice(%d) failed", device);
+    vr_ctx* c = new vr_ctx();
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->max_ws = max_workspace_bytes;
+    if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return vr::set_err(nullptr, VR_ERR_HIP, "hipHostMalloc failed");
+    }
+    c->slots.resize(vr::WS_NSLOTS);
+    *out = c;
+    return VR_OK;
+}
+
+void vr_destroy(vr_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& b : ctx->slots)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+const char* vr_last_error(const vr_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int vr_sync(vr_ctx* ctx, void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    VR_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    VR_HIP(ctx, hipGetLastError());
+    return VR_OK;
+}
+
+size_t vr_workspace_bytes(const vr_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+// vr_fof6d.hip -- velocity linking length of a host and 6D friends-of-
+// friends over the outliers (Sec. 2.1, Eq. fof6d, with the substructure
+// linking length of Sec. 2.2).
+//
+// Participants (hosted particles with R at or above the threshold) are
+// compacted, put on their own integer-grid cell list with cells of side
+// 2^s >= ellx_s, and every candidate pair is tested with the FP64 predicate
+// d2 / ells2 + dv2 / ellv^2 < 1 evaluated in exactly that order, d2 being the
+// exact integer squared distance.  Components come from the same lock-free
+// union-find as the 3D search; labels are the smallest participant index.
+#include "vr_grid.h"
+
+#include <cmath>
+
+namespace vr {
+namespace {
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int N>
+__device__ __forceinline__ void bsum(double (&v)[N], double* sm) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = 0; i < N; ++i) {
+        double s = wsum(v[i]);
+        if (lane == 0) sm[w * N + i] = s;
+    }
+    __syncthreads();
+    for (int i = 0; i < N; ++i) {
+        double s = 0;
+        for (int ww = 0; ww < nw; ++ww) s += sm[ww * N + i];
+        v[i] = s;
+    }
+    __syncthreads();
+}
+
+// sigma_v of a host from the mass-weighted dispersion tensor of all members
+// about their mass-weighted mean velocity; one workgroup per host.
+__global__ __launch_bounds__(256) void k_host_ellv(const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
+                                                   const float* __restrict__ vx, const float* __restrict__ vy,
+                                                   const float* __restrict__ vz, const float* __restrict__ mass,
+                                                   double mass_value, double alpha_v, double* __restrict__ ellv) {
+    __shared__ double sm[4 * 6];
+    const int h = blockIdx.x;
+    const int s = off[h], e = off[h + 1];
+    double a[4] = {0, 0, 0, 0};
+    for (int k = s + threadIdx.x; k < e; k += blockDim.x) {
+        const int i = mem[k];
+        const double m = mass ? (double)mass[i] : mass_value;
+        a[0] += m;
+        a[1] += m * (double)vx[i];
+        a[2] += m * (double)vy[i];
+        a[3] += m * (double)vz[i];
+    }
+    bsum<4>(a, sm);
+    const double M = a[0];
+    const double mv[3] = {a[1] / M, a[2] / M, a[3] / M};
+    double c[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = s + threadIdx.x; k < e; k += blockDim.x) {
+        const int i = mem[k];
+        const double m = mass ? (double)mass[i] : mass_value;
+        const double d0 = (double)vx[i] - mv[0], d1 = (double)vy[i] - mv[1], d2 = (double)vz[i] - mv[2];
+        c[0] += m * d0 * d0;
+        c[1] += m * d1 * d1;
+        c[2] += m * d2 * d2;
+        c[3] += m * d0 * d1;
+        c[4] += m * d0 * d2;
+        c[5] += m * d1 * d2;
+    }
+    bsum<6>(c, sm);
+    if (threadIdx.x == 0) {
+        const double s00 = c[0] / M, s11 = c[1] / M, s22 = c[2] / M, s01 = c[3] / M, s02 = c[4] / M, s12 = c[5] / M;
+        const double det = s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) + s02 * (s01 * s12 - s11 * s02);
+        ellv[h] = alpha_v * pow(det, 1.0 / 6.0);
+    }
+}
+
+__global__ void k_participants(int64_t n, const int32_t* __restrict__ host_of, const float* __restrict__ R,
+                               float thr, int32_t n_hosts, uint32_t* __restrict__ flag, int* __restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int h = host_of[i];
+    if (h >= n_hosts) atomicOr(bad, 1);
+    flag[i] = (h >= 0 && h < n_hosts && (R == nullptr || R[i] >= thr)) ? 1u : 0u;
+}
+
+__global__ void k_compact_part(int64_t n, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                               const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
+                               const uint32_t* __restrict__ qz, uint32_t* __restrict__ cx, uint32_t* __restrict__ cy,
+                               uint32_t* __restrict__ cz, int32_t* __restrict__ orig) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const uint32_t k = pos[i];
+    cx[k] = qx[i];
+    cy[k] = qy[i];
+    cz[k] = qz[i];
+    orig[k] = (int32_t)i;
+}
+
+// per sorted position: original particle index, velocity and host
+__global__ void k_sorted_attrs(int64_t np, const uint32_t* __restrict__ cidx, const int32_t* __restrict__ orig,
+                               const float* __restrict__ vx, const float* __restrict__ vy, const float* __restrict__ vz,
+                               const int32_t* __restrict__ host_of, int32_t* __restrict__ sorig,
+                               float* __restrict__ svx, float* __restrict__ svy, float* __restrict__ svz,
+                               int32_t* __restrict__ shost) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int32_t i = orig[cidx[p]];
+    sorig[p] = i;
+    svx[p] = vx[i];
+    svy[p] = vy[i];
+    svz[p] = vz[i];
+    shost[p] = host_of[i];
+}
+
+template <bool HALF>
+__global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __restrict__ key,
+                                                const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
+                                                const uint32_t* __restrict__ sz, const float* __restrict__ svx,
+                                                const float* __restrict__ svy, const float* __restrict__ svz,
+                                                const int32_t* __restrict__ shost, const double* __restrict__ ellv,
+                                                const uint32_t* __restrict__ cell_start,
+                                                const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                                uint32_t hmask, int b, int gb, double ell2, int* parent) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const uint32_t k = key[p];
+    const int nc = 1 << b;
+    const int cx = k & (nc - 1), cy = (k >> b) & (nc - 1), cz = k >> (2 * b);
+    const int px = (int)sx[p], py = (int)sy[p], pz = (int)sz[p];
+    const double vpx = (double)svx[p], vpy = (double)svy[p], vpz = (double)svz[p];
+    const int hp = shost[p];
+    const double ev = ellv[hp];
+    const double ev2 = ev * ev;
+    uint32_t seen[HALF ? 1 : 27];
+    int nseen = 0;
+    for (int o = 0; o < 27; ++o) {
+        const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+        const int lin = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        if (HALF && lin < 13) continue;
+        const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
+        const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
+        const uint32_t nz = (uint32_t)((cz + dz + nc) & (nc - 1));
+        const uint32_t nk = (nz << (2 * b)) | (ny << b) | nx;
+        if constexpr (!HALF) {
+            bool dup = false;
+            for (int t = 0; t < nseen; ++t) dup |= seen[t] == nk;
+            if (dup) continue;
+            seen[nseen++] = nk;
+        }
+        const int c = hash_find(hkeys, hvals, hmask, nk);
+        if (c < 0) continue;
+        uint32_t s = cell_start[c], e = cell_start[c + 1];
+        if (((nk == k) || !HALF) && s <= (uint32_t)p) s = (uint32_t)p + 1;
+        for (uint32_t q = s; q < e; ++q) {
+            if (shost[q] != hp) continue;
+            const int ddx = min_image((int)sx[q] - px, gb);
+            const int ddy = min_image((int)sy[q] - py, gb);
+            const int ddz = min_image((int)sz[q] - pz, gb);
+            const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+            const double ax = vpx - (double)svx[q], ay = vpy - (double)svy[q], az = vpz - (double)svz[q];
+            const double dv2 = ax * ax + ay * ay + az * az;
+            const double t = d2 / ell2 + dv2 / ev2;
+            if (t < 1.0) uf_union(parent, (int)p, (int)q);
+        }
+    }
+}
+
+__global__ void k_iota_i(int64_t n, int* p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int)i;
+}
+
+__global__ void k_compress_min(int64_t np, int* parent, const int32_t* __restrict__ sorig, int* __restrict__ mn) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    int r = (int)p;
+    while (parent[r] != r) r = parent[r];
+    parent[p] = r;
+    atomicMin(&mn[r], sorig[p]);
+}
+
+__global__ void k_label6(int64_t np, const int* __restrict__ parent, const int32_t* __restrict__ sorig,
+                         const int* __restrict__ mn, int32_t* __restrict__ label6) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    label6[sorig[p]] = mn[parent[p]];
+}
+
+}  // namespace
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
+                            const int32_t* host_members, double alpha_v, double* ellv_host, void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    int rc = check_particles(ctx, p, true);
+    if (rc) return rc;
+    if ((rc = check_hosts(ctx, n_hosts, host_offsets, host_members))) return rc;
+    if (!(alpha_v > 0)) return set_err(ctx, VR_ERR_INVALID_ARG, "alpha_v must be positive");
+    if (n_hosts == 0) return VR_OK;
+    if (!ellv_host) return set_err(ctx, VR_ERR_INVALID_ARG, "ellv_host is NULL");
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_host_ellv, dim3(n_hosts), dim3(256), 0, (hipStream_t)stream, host_offsets, host_members, p->vx,
+                       p->vy, p->vz, p->mass, p->mass_value, alpha_v, ellv_host);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, const double* ellv_host,
+                        int32_t n_hosts, double ellx_s, const float* R, float R_threshold, int32_t* label6,
+                        void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    int rc = check_particles(ctx, p, true);
+    if (rc) return rc;
+    const int gb = p->grid_bits;
+    const double u = ellx_s * ldexp(1.0, gb) / p->box;
+    if (!(u > 0) || !(u < ldexp(1.0, gb - 1)))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "ellx_s must satisfy 0 < ellx_s < box/2");
+    if (n_hosts < 0) return set_err(ctx, VR_ERR_INVALID_ARG, "n_hosts < 0");
+    const int64_t n = p->n;
+    if (n == 0) return VR_OK;
+    if (!host_of || !label6 || (n_hosts > 0 && !ellv_host)) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (n_hosts > 0) {
+        std::vector<double> ev(n_hosts);
+        VR_HIP(ctx, hipMemcpyAsync(ev.data(), ellv_host, n_hosts * sizeof(double), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipStreamSynchronize(st));
+        for (int h = 0; h < n_hosts; ++h)
+            if (!(ev[h] > 0) || !std::isfinite(ev[h]))
+                return set_err(ctx, VR_ERR_INVALID_ARG, "ellv_host[%d] = %g is not a positive number", h, ev[h]);
+    }
+    const double ell2 = u * u;
+    VR_WS(flag, ctx, uint32_t, WS_C0, n);
+    VR_WS(pos, ctx, uint32_t, WS_C1, n);
+    VR_WS(bad, ctx, int, WS_FLAG2, 4);
+    VR_WS(tot, ctx, uint32_t, WS_C9, 4);
+    rc = fill_i32(ctx, bad, 0, 1, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_participants, dim3(grid_for(n, 256)), dim3(256), 0, st, n, host_of, R, R_threshold, n_hosts,
+                       flag, bad);
+    VR_LAUNCH_CHECK(ctx);
+    rc = scan_u32(ctx, flag, pos, n, tot, st);
+    if (rc) return rc;
+    int32_t* hostpin = reinterpret_cast<int32_t*>(ctx->pinned);
+    VR_HIP(ctx, hipMemcpyAsync(hostpin, tot, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipMemcpyAsync(hostpin + 1, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t np = (uint32_t)hostpin[0];
+    if (hostpin[1]) return set_err(ctx, VR_ERR_INVALID_ARG, "host_of holds a host id >= n_hosts");
+    rc = fill_i32(ctx, label6, -1, n, st);
+    if (rc) return rc;
+    if (np == 0) return VR_OK;
+    VR_WS(cx, ctx, uint32_t, WS_C2, np);
+    VR_WS(cy, ctx, uint32_t, WS_C3, np);
+    VR_WS(cz, ctx, uint32_t, WS_C4, np);
+    VR_WS(orig, ctx, int32_t, WS_C5, np);
+    hipLaunchKernelGGL(k_compact_part, dim3(grid_for(n, 256)), dim3(256), 0, st, n, flag, pos, p->qx, p->qy, p->qz, cx,
+                       cy, cz, orig);
+    VR_LAUNCH_CHECK(ctx);
+    int s = 0;
+    while ((double)(1 << s) < u && s < gb) ++s;
+    CellList cl;
+    rc = build_cell_list(ctx, np, cx, cy, cz, gb, s, cl, st);
+    if (rc) return rc;
+    VR_WS(sorig, ctx, int32_t, WS_C6, np);
+    VR_WS(svx, ctx, float, WS_C7, np);
+    VR_WS(svy, ctx, float, WS_C8, np);
+    VR_WS(svz, ctx, float, WS_D0, np);
+    VR_WS(shost, ctx, int32_t, WS_D1, np);
+    VR_WS(parent, ctx, int, WS_D2, np);
+    VR_WS(mn, ctx, int, WS_D3, np);
+    hipLaunchKernelGGL(k_sorted_attrs, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.idx, orig, p->vx, p->vy,
+                       p->vz, host_of, sorig, svx, svy, svz, shost);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_iota_i, dim3(grid_for(np, 256)), dim3(256), 0, st, np, parent);
+    VR_LAUNCH_CHECK(ctx);
+    const int b = gb - s;
+    if ((1 << b) >= 3)
+        hipLaunchKernelGGL(k_link6d<true>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz,
+                           svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2,
+                           parent);
+    else
+        hipLaunchKernelGGL(k_link6d<false>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz,
+                           svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2,
+                           parent);
+    VR_LAUNCH_CHECK(ctx);
+    rc = fill_i32(ctx, mn, 0x7FFFFFFF, np, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_compress_min, dim3(grid_for(np, 256)), dim3(256), 0, st, np, parent, sorig, mn);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_label6, dim3(grid_for(np, 256)), dim3(256), 0, st, np, parent, sorig, mn, label6);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}

@@ -1,0 +1,68 @@
+// vr_grid.h -- integer-grid cell lists and lock-free union-find shared by
+// the 3D and 6D friends-of-friends kernels.
+#pragma once
+#include "vr_internal.h"
+
+namespace vr {
+
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t hash32(uint32_t k, uint32_t mask) {
+    k ^= k >> 16;
+    k *= 0x7feb352du;
+    k ^= k >> 15;
+    k *= 0x846ca68bu;
+    k ^= k >> 16;
+    return k & mask;
+}
+
+__device__ __forceinline__ int hash_find(const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                         uint32_t hmask, uint32_t k) {
+    uint32_t h = hash32(k, hmask);
+    for (;;) {
+        uint32_t kk = hkeys[h];
+        if (kk == k) return (int)hvals[h];
+        if (kk == EMPTY) return -1;
+        h = (h + 1) & hmask;
+    }
+}
+
+__device__ __forceinline__ int uf_find(int* parent, int a) {
+    int p = parent[a];
+    while (p != a) {
+        int g = parent[p];
+        if (g != p) parent[a] = g;  // path halving; every write points closer to the root
+        a = p;
+        p = g;
+    }
+    return a;
+}
+
+__device__ __forceinline__ void uf_union(int* parent, int a, int b) {
+    for (;;) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return;
+        if (a > b) { int t = a; a = b; b = t; }
+        int old = atomicCAS(&parent[b], b, a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+
+// Cell list of a point set on the periodic grid: sorted keys, sorted
+// original indices, sorted coordinates, cell starts and an open-addressing
+// hash from occupied cell keys to cell numbers.
+struct CellList {
+    uint32_t *key, *idx, *sx, *sy, *sz, *cell_start, *hkeys, *hvals;
+    uint32_t hmask;
+    int64_t n_cells;
+};
+
+// Cell list of n points with cells of side 2^s grid units.  Uses workspace
+// slots A0..A8, FLAG and the sort slots.
+int build_cell_list(vr_ctx* ctx, int64_t n, const uint32_t* qx, const uint32_t* qy, const uint32_t* qz, int gb,
+                    int s, CellList& cl, hipStream_t st);
+
+}  // namespace vr

@@ -1,0 +1,114 @@
+// vr_internal.h -- shared internals of libvr (context, workspace, errors,
+// device helpers).  gfx950 only: wave64, 160 KiB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/vr.h"
+
+#define VR_WAVE 64
+
+struct vr_buf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct vr_ctx {
+    int device = 0;
+    int num_cus = 256;
+    size_t max_ws = 0;      // 0 = no cap
+    size_t held = 0;        // bytes currently held by slots
+    std::vector<vr_buf> slots;
+    std::string err;
+    // host-pinned scalars for counts returned by syncing calls
+    int64_t* pinned = nullptr;
+    int tuned_tile = 0;     // potential j-tile picked by the autotuner (0 = default)
+};
+
+namespace vr {
+
+// Workspace slot identifiers: every call takes its temporaries from fixed
+// slots, grown on demand and reused across calls.
+enum Slot {
+    WS_SORT_KEYS_A, WS_SORT_KEYS_B, WS_SORT_VALS_A, WS_SORT_VALS_B, WS_SORT_HIST,
+    WS_SCAN_TMP, WS_SCAN_TMP2,
+    WS_A0, WS_A1, WS_A2, WS_A3, WS_A4, WS_A5, WS_A6, WS_A7, WS_A8, WS_A9,
+    WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7, WS_B8, WS_B9,
+    WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8, WS_C9,
+    WS_D0, WS_D1, WS_D2, WS_D3, WS_D4, WS_D5, WS_D6, WS_D7, WS_D8, WS_D9,
+    WS_FLAG, WS_FLAG2,
+    WS_NSLOTS
+};
+
+int set_err(vr_ctx* ctx, int code, const char* fmt, ...);
+
+// Grow-only workspace slot; returns nullptr (and sets the error) on failure.
+void* ws(vr_ctx* ctx, int slot, size_t bytes);
+
+template <class T>
+inline T* wsT(vr_ctx* ctx, int slot, size_t count) {
+    return static_cast<T*>(ws(ctx, slot, count * sizeof(T) + 16));
+}
+
+#define VR_HIP(ctx, call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::vr::set_err(ctx, VR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define VR_LAUNCH_CHECK(ctx) VR_HIP(ctx, hipGetLastError())
+
+#define VR_WS(ptr, ctx, T, slot, count)                       \
+    T* ptr = ::vr::wsT<T>(ctx, slot, (size_t)(count));        \
+    if (!ptr) return VR_ERR_OUT_OF_MEMORY;
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Host-side validation shared by the entry points.
+int check_particles(vr_ctx* ctx, const vr_particles* p, bool need_vel);
+int check_hosts(vr_ctx* ctx, int32_t n_hosts, const int32_t* off, const int32_t* mem);
+
+// ---- device-wide primitives (vr_prims.hip) --------------------------------
+// Exclusive prefix sum of n uint32 values (in may equal out).  Returns total
+// through *total_dev (device pointer, may be null).
+int scan_u32(vr_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev,
+             hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).  Keys
+// and values are sorted in place (the buffers are overwritten).
+int sort_pairs_u32(vr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits,
+                   hipStream_t s);
+int sort_pairs_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits,
+                   hipStream_t s);
+// Fill helpers (kernels, never memset nodes, so they are safe to capture).
+int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s);
+int fill_u32(vr_ctx* ctx, uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+int iota_u32(vr_ctx* ctx, uint32_t* p, int64_t n, hipStream_t s);
+// Copy one device scalar to the host and wait.
+int read_back(vr_ctx* ctx, const void* dev, void* host, size_t bytes, hipStream_t s);
+
+// ---- device helpers --------------------------------------------------------
+__device__ __forceinline__ int min_image(int d, int gb) {
+    // ((d + half) mod size) - half for a power-of-two size
+    const int half = 1 << (gb - 1);
+    const int mask = (1 << gb) - 1;
+    return ((d + half) & mask) - half;
+}
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const unsigned l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+}  // namespace vr

@@ -1,0 +1,319 @@
+// vr_knn.hip -- local velocity density ratio R = ln(f_l / f_bg) (Sec. 2.2).
+//
+// Each host gets a median-split KD tree (widest dimension, leaves of at most
+// 64 members) built by the level-synchronous builder; members end up in leaf
+// order, so 64 consecutive queries share leaves.  One wavefront serves 64
+// queries, one per lane: the wave walks the tree of a host with a shared
+// depth-first stack, visiting a node when any lane's ball (radius = its
+// current n_se-th neighbour) reaches the node's bounding box, and every lane
+// keeps its n_se best (d2, member) keys in a max-heap in LDS.  The key packs
+// the exact integer squared distance above the member's position in the host
+// (position order = particle-index order), so ties break by index exactly as
+// the definition says.  The n_v velocity neighbours are then selected among
+// the n_se by (FP64 dv2, index) and the Epanechnikov estimate and the
+// Gaussian background follow in FP64.
+#include "vr_kd.h"
+
+#include <cmath>
+
+namespace vr {
+namespace {
+
+constexpr int POS_BITS = 22;
+constexpr uint64_t POS_MASK = (uint64_t(1) << POS_BITS) - 1;
+constexpr int STACK = 128;
+
+__global__ void k_elem_host(int n_hosts, const int32_t* __restrict__ off, int* __restrict__ elem_host) {
+    const int h = blockIdx.x;
+    for (int k = off[h] + threadIdx.x; k < off[h + 1]; k += blockDim.x) elem_host[k] = h;
+}
+
+__global__ void k_gather_vel(int64_t M, const int* __restrict__ gidx, const float* __restrict__ vx,
+                             const float* __restrict__ vy, const float* __restrict__ vz, float* __restrict__ px,
+                             float* __restrict__ py, float* __restrict__ pz) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const int g = gidx[k];
+    px[k] = vx[g];
+    py[k] = vy[g];
+    pz[k] = vz[g];
+}
+
+__global__ void k_pos_of(int64_t M, const int* __restrict__ gidx, int* __restrict__ pos_of) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < M) pos_of[gidx[k]] = (int)k;
+}
+
+__global__ void k_subset_pos(int64_t ns, int64_t n, const int32_t* __restrict__ subset, const int* __restrict__ pos_of,
+                             uint32_t* __restrict__ qpos, uint32_t* __restrict__ qval, int* __restrict__ bad) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const int i = subset[s];
+    int p = (i >= 0 && i < n) ? pos_of[i] : -1;
+    if (p < 0) { atomicOr(bad, 1); p = 0; }
+    qpos[s] = (uint32_t)p;
+    qval[s] = (uint32_t)s;
+}
+
+template <int NSE>
+__device__ __forceinline__ void heap_push(uint64_t (*heap)[64], int lane, int& count, uint64_t key) {
+    int i = count++;
+    while (i > 0) {
+        const int par = (i - 1) >> 1;
+        const uint64_t pk = heap[par][lane];
+        if (pk >= key) break;
+        heap[i][lane] = pk;
+        i = par;
+    }
+    heap[i][lane] = key;
+}
+
+template <int NSE>
+__device__ __forceinline__ void heap_replace_top(uint64_t (*heap)[64], int lane, int count, uint64_t key) {
+    int i = 0;
+    for (;;) {
+        const int l = 2 * i + 1;
+        if (l >= count) break;
+        int c = l;
+        uint64_t ck = heap[l][lane];
+        if (l + 1 < count) {
+            const uint64_t rk = heap[l + 1][lane];
+            if (rk > ck) { c = l + 1; ck = rk; }
+        }
+        if (ck <= key) break;
+        heap[i][lane] = ck;
+        i = c;
+    }
+    heap[i][lane] = key;
+}
+
+template <int NSE, int NV>
+__global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, int64_t nq,
+                                            const KdNode* __restrict__ nodes, Elems F, const float* __restrict__ Vx,
+                                            const float* __restrict__ Vy, const float* __restrict__ Vz,
+                                            const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
+                                            const float* __restrict__ vbar, const float* __restrict__ sigma, int64_t n,
+                                            int n_se, int n_v, int use_mass, double mass_value, int gb,
+                                            float* __restrict__ R) {
+    __shared__ uint64_t heap[NSE][64];
+    __shared__ double vd[NV][64];
+    __shared__ int vp[NV][64];
+    __shared__ int stack[STACK];
+    const int lane = threadIdx.x;
+    const int64_t qi = (int64_t)blockIdx.x * 64 + lane;
+    const bool active = qi < nq;
+    const int e = active ? (qpos ? (int)qpos[qi] : (int)qi) : 0;
+    const int h = active ? elem_host[e] : -1;
+    const int base = active ? host_off[h] : 0;
+    const int px = F.u[0][e], py = F.u[1][e], pz = F.u[2][e];
+    int count = 0;
+    uint64_t worst = ~0ull;
+    bool pending = active;
+    while (__ballot(pending)) {
+        const uint64_t pm = __ballot(pending);
+        const int fl = __ffsll((unsigned long long)pm) - 1;
+        const int hh = __shfl(h, fl, 64);
+        const bool mine = pending && h == hh;
+        int sp = 0;
+        if (lane == 0) stack[0] = hh;
+        sp = 1;
+        __builtin_amdgcn_wave_barrier();
+        while (sp > 0) {
+            const int node = stack[--sp];
+            __builtin_amdgcn_wave_barrier();
+            const KdNode& nd = nodes[node];
+            const int64_t dx = max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
+            const int64_t dy = max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
+            const int64_t dz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
+            int64_t md2 = dx * dx + dy * dy + dz * dz;
+            if (md2 > (int64_t(1) << 41)) md2 = int64_t(1) << 41;
+            const bool need = mine && (count < n_se || ((uint64_t)md2 << POS_BITS) <= worst);
+            if (!__ballot(need)) continue;
+            if (nd.dim < 0) {
+                const int s = nd.start, t = nd.end;
+                for (int j = s; j < t; ++j) {
+                    const int ddx = min_image(F.u[0][j] - px, gb);
+                    const int ddy = min_image(F.u[1][j] - py, gb);
+                    const int ddz = min_image(F.u[2][j] - pz, gb);
+                    const uint64_t d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
+                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)(j - base);
+                    if (mine) {
+                        if (count < n_se) {
+                            heap_push<NSE>(heap, lane, count, key);
+                            if (count == n_se) worst = heap[0][lane];
+                        } else if (key < worst) {
+                            heap_replace_top<NSE>(heap, lane, count, key);
+                            worst = heap[0][lane];
+                        }
+                    }
+                }
+            } else {
+                if (sp + 2 > STACK) break;  // cannot happen for trees of depth < 64
+                const int c = nd.dim == 0 ? px : (nd.dim == 1 ? py : pz);
+                const int cf = __shfl(c, fl, 64);
+                const int nearc = cf < nd.t ? nd.left : nd.right;
+                const int farc = cf < nd.t ? nd.right : nd.left;
+                if (lane == 0) {
+                    stack[sp] = farc;
+                    stack[sp + 1] = nearc;
+                }
+                sp += 2;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        pending = pending && !mine;
+    }
+    if (!active) return;
+    // velocity neighbours among the spatial ones, by (dv2, index)
+    const double vqx = (double)Vx[e], vqy = (double)Vy[e], vqz = (double)Vz[e];
+    double msum = 0.0;
+    int nv = 0;
+    for (int a = 0; a < n_se; ++a) {
+        const int pos = (int)(heap[a][lane] & POS_MASK);
+        const int gp = base + pos;
+        msum += use_mass ? (double)F.mass[gp] : mass_value;
+        const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
+        const double dv2 = ax * ax + ay * ay + az * az;
+        if (nv == n_v) {
+            const double wd = vd[n_v - 1][lane];
+            const int wp = vp[n_v - 1][lane];
+            if (!(dv2 < wd || (dv2 == wd && pos < wp))) continue;
+            --nv;
+        }
+        int i = nv++;
+        while (i > 0) {
+            const double pd = vd[i - 1][lane];
+            const int pp = vp[i - 1][lane];
+            if (pd < dv2 || (pd == dv2 && pp < pos)) break;
+            vd[i][lane] = pd;
+            vp[i][lane] = pp;
+            --i;
+        }
+        vd[i][lane] = dv2;
+        vp[i][lane] = pos;
+    }
+    const double h2 = vd[n_v - 1][lane];
+    double lfl;
+    if (h2 == 0.0) {
+        lfl = INFINITY;
+    } else {
+        const double kW = 15.0 / (8.0 * M_PI);
+        double sw = 0.0;
+        for (int a = 0; a < n_v; ++a) {
+            const double m = use_mass ? (double)F.mass[base + vp[a][lane]] : mass_value;
+            sw += m * kW * (1.0 - vd[a][lane] / h2);
+        }
+        lfl = log(sw) - 1.5 * log(h2) - log(msum);
+    }
+    const int g = F.gidx[e];
+    const double S00 = sigma[0 * n + g], S11 = sigma[1 * n + g], S22 = sigma[2 * n + g];
+    const double S10 = sigma[3 * n + g], S20 = sigma[4 * n + g], S21 = sigma[5 * n + g];
+    double lfb = NAN;
+    if (S00 > 0) {
+        const double L00 = sqrt(S00);
+        const double L10 = S10 / L00, L20 = S20 / L00;
+        const double r11 = S11 - L10 * L10;
+        if (r11 > 0) {
+            const double L11 = sqrt(r11);
+            const double L21 = (S21 - L20 * L10) / L11;
+            const double r22 = S22 - L20 * L20 - L21 * L21;
+            if (r22 > 0) {
+                const double L22 = sqrt(r22);
+                const double d0 = vqx - (double)vbar[0 * n + g];
+                const double d1 = vqy - (double)vbar[1 * n + g];
+                const double d2 = vqz - (double)vbar[2 * n + g];
+                const double y0 = d0 / L00;
+                const double y1 = (d1 - L10 * y0) / L11;
+                const double y2 = (d2 - L20 * y0 - L21 * y1) / L22;
+                const double quad = y0 * y0 + y1 * y1 + y2 * y2;
+                const double lndet = 2.0 * (log(L00) + log(L11) + log(L22));
+                lfb = -0.5 * quad - 1.5 * log(2.0 * M_PI) - 0.5 * lndet;
+            }
+        }
+    }
+    R[g] = (float)(lfl - lfb);
+}
+
+template <int NSE, int NV>
+int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx, const float* Vy,
+               const float* Vz, const int* elem_host, const int32_t* host_off, const vr_particles* p, const float* vbar,
+               const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
+    hipLaunchKernelGGL((k_knn<NSE, NV>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes, tree.F, Vx,
+                       Vy, Vz, elem_host, host_off, vbar, sigma, p->n, n_se, n_v, tree.use_mass, p->mass_value,
+                       p->grid_bits, R);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+}  // namespace
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
+                                 const int32_t* host_members, const float* vbar, const float* sigma, int32_t n_se,
+                                 int32_t n_v, const int32_t* subset, int64_t n_subset, float* R, void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    int rc = check_particles(ctx, p, true);
+    if (rc) return rc;
+    if ((rc = check_hosts(ctx, n_hosts, host_offsets, host_members))) return rc;
+    if (n_v < 2 || n_v > n_se || n_se > 64)
+        return set_err(ctx, VR_ERR_INVALID_ARG, "need 2 <= n_v <= n_se <= 64 (got n_se=%d, n_v=%d)", n_se, n_v);
+    if (subset && n_subset < 0) return set_err(ctx, VR_ERR_INVALID_ARG, "n_subset < 0");
+    if (n_hosts == 0 || (subset && n_subset == 0)) return VR_OK;
+    if (!vbar || !sigma || !R) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> off;
+    rc = read_host_offsets(ctx, n_hosts, host_offsets, p->n, n_se, off, st);
+    if (rc) return rc;
+    for (int h = 0; h < n_hosts; ++h)
+        if ((int64_t)off[h + 1] - off[h] > (int64_t(1) << POS_BITS))
+            return set_err(ctx, VR_ERR_UNSUPPORTED, "host %d has more than 2^%d members", h, POS_BITS);
+    std::vector<int> nc(n_hosts, 64);
+    KdTree tree;
+    rc = kd_build(ctx, p, n_hosts, host_offsets, host_members, off, nc, KD_WIDEST, 2, tree, st);
+    if (rc) return rc;
+    const int64_t M = off[n_hosts];
+    VR_WS(Vx, ctx, float, WS_C0, M);
+    VR_WS(Vy, ctx, float, WS_C1, M);
+    VR_WS(Vz, ctx, float, WS_C2, M);
+    VR_WS(elem_host, ctx, int, WS_C3, M);
+    hipLaunchKernelGGL(k_gather_vel, dim3(grid_for(M, 256)), dim3(256), 0, st, M, tree.F.gidx, p->vx, p->vy, p->vz, Vx,
+                       Vy, Vz);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_elem_host, dim3(n_hosts), dim3(256), 0, st, n_hosts, host_offsets, elem_host);
+    VR_LAUNCH_CHECK(ctx);
+    const uint32_t* qpos = nullptr;
+    int64_t nq = M;
+    if (subset) {
+        VR_WS(pos_of, ctx, int, WS_C4, p->n);
+        VR_WS(qp, ctx, uint32_t, WS_C5, n_subset);
+        VR_WS(qv, ctx, uint32_t, WS_C6, n_subset);
+        VR_WS(bad, ctx, int, WS_FLAG2, 4);
+        rc = fill_i32(ctx, pos_of, -1, p->n, st);
+        if (rc) return rc;
+        rc = fill_i32(ctx, bad, 0, 1, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_pos_of, dim3(grid_for(M, 256)), dim3(256), 0, st, M, tree.F.gidx, pos_of);
+        VR_LAUNCH_CHECK(ctx);
+        hipLaunchKernelGGL(k_subset_pos, dim3(grid_for(n_subset, 256)), dim3(256), 0, st, n_subset, p->n, subset, pos_of,
+                           qp, qv, bad);
+        VR_LAUNCH_CHECK(ctx);
+        int badh = 0;
+        rc = read_back(ctx, bad, &badh, sizeof badh, st);
+        if (rc) return rc;
+        if (badh) return set_err(ctx, VR_ERR_INVALID_ARG, "subset lists a particle that is in no host");
+        int bits = 1;
+        while ((int64_t(1) << bits) < M) ++bits;
+        rc = sort_pairs_u32(ctx, qp, qv, n_subset, bits, st);
+        if (rc) return rc;
+        qpos = qp;
+        nq = n_subset;
+    }
+    if (n_se <= 32 && n_v <= 8)
+        return launch_knn<32, 8>(ctx, qpos, nq, tree, Vx, Vy, Vz, elem_host, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    if (n_se <= 32)
+        return launch_knn<32, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, elem_host, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    return launch_knn<64, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, elem_host, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+}

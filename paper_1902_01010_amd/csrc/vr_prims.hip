@@ -1,0 +1,283 @@
+// vr_prims.hip -- device-wide primitives: exclusive scan, stable LSD radix
+// sort of (key, index) pairs, fills.  Written for wave64: ranks inside a
+// wavefront come from 64-bit ballots, tiles are staged through LDS so that the
+// scatter writes contiguous runs per digit.
+#include "vr_internal.h"
+
+namespace vr {
+namespace {
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim = 256).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem /*>= 4*/, uint32_t* total) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) smem[w] = inc;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        if (i < w) wpre += smem[i];
+        tot += smem[i];
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return wpre + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t* in, int64_t n, uint32_t* part) {
+    __shared__ uint32_t sm[8];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j * SCAN_BLOCK + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, sm, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
+                                                           const uint32_t* part_scanned,
+                                                           uint32_t* total_dev, int64_t nblocks,
+                                                           const uint32_t* part_raw) {
+    __shared__ uint32_t sm[8];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        v[j] = (i < n) ? in[i] : 0u;
+        s += v[j];
+    }
+    uint32_t off = block_excl_scan(s, sm, nullptr) + (part_scanned ? part_scanned[blockIdx.x] : 0u);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = off;
+        off += v[j];
+    }
+    if (total_dev && blockIdx.x == nblocks - 1 && threadIdx.x == SCAN_BLOCK - 1)
+        *total_dev = off;
+    (void)part_raw;
+}
+
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_iota(uint32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
+}
+
+// ---- radix sort ------------------------------------------------------------
+constexpr int RS_BLOCK = 256;
+constexpr int RS_WAVES = RS_BLOCK / 64;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;   // 4096 keys per tile
+constexpr int RS_RADIX = 256;
+
+template <class K>
+__global__ __launch_bounds__(RS_BLOCK) void k_radix_count(const K* keys, int64_t n, int shift,
+                                                           uint32_t* hist, int num_tiles) {
+    __shared__ uint32_t h[RS_RADIX];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        int64_t i = base + j * RS_BLOCK + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             int64_t n, int shift,
+                                                             const uint32_t* __restrict__ offs, int num_tiles) {
+    __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
+    __shared__ uint32_t toff[RS_RADIX];
+    __shared__ uint32_t goff[RS_RADIX];
+    __shared__ uint32_t sm[8];
+    __shared__ K lk[RS_TILE];
+    __shared__ uint32_t lv[RS_TILE];
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    for (int i = tid; i < RS_WAVES * RS_RADIX; i += RS_BLOCK) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t base = tbase + (int64_t)w * (RS_ITEMS * 64);
+    K key[RS_ITEMS];
+    uint32_t val[RS_ITEMS];
+    uint32_t rank[RS_ITEMS];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t i = base + j * 64 + lane;
+        const bool valid = i < n;
+        key[j] = valid ? kin[i] : K(0);
+        val[j] = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t before = 0;
+        if (valid) before = wcnt[w][d];
+        rank[j] = before + (uint32_t)__popcll(m & lt);
+        // the highest peer lane publishes the new running count of the digit
+        if (valid && lane == 63 - __clzll(m)) wcnt[w][d] = before + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // digit totals, per-wave prefixes and the tile-level exclusive offsets
+    {
+        const int d = tid;
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < RS_WAVES; ++ww) {
+            uint32_t c = wcnt[ww][d];
+            wcnt[ww][d] = run;
+            run += c;
+        }
+        uint32_t ex = block_excl_scan(run, sm, nullptr);
+        toff[d] = ex;
+        goff[d] = offs[(int64_t)d * num_tiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t i = base + j * 64 + lane;
+        if (i < n) {
+            const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+            const uint32_t pos = toff[d] + wcnt[w][d] + rank[j];
+            lk[pos] = key[j];
+            lv[pos] = val[j];
+        }
+    }
+    __syncthreads();
+    const int cnt = (int)((n - tbase) < RS_TILE ? (n - tbase) : RS_TILE);
+    for (int i = tid; i < cnt; i += RS_BLOCK) {
+        const K k = lk[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t g = goff[d] + (uint32_t)i - toff[d];
+        kout[g] = k;
+        vout[g] = lv[i];
+    }
+}
+
+template <class K>
+int sort_pairs_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return VR_OK;
+    const int num_tiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    VR_WS(kalt, ctx, K, WS_SORT_KEYS_B, n);
+    VR_WS(valt, ctx, uint32_t, WS_SORT_VALS_B, n);
+    VR_WS(hist, ctx, uint32_t, WS_SORT_HIST, (int64_t)RS_RADIX * num_tiles);
+    K* k0 = keys; K* k1 = kalt;
+    uint32_t* v0 = vals; uint32_t* v1 = valt;
+    const int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * 8;
+        hipLaunchKernelGGL(k_radix_count<K>, dim3(num_tiles), dim3(RS_BLOCK), 0, s, k0, n, shift, hist,
+                           num_tiles);
+        VR_LAUNCH_CHECK(ctx);
+        int rc = scan_u32(ctx, hist, hist, (int64_t)RS_RADIX * num_tiles, nullptr, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(num_tiles), dim3(RS_BLOCK), 0, s, k0, v0, k1, v1, n,
+                           shift, hist, num_tiles);
+        VR_LAUNCH_CHECK(ctx);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    if (k0 != keys) {
+        VR_HIP(ctx, hipMemcpyAsync(keys, k0, n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        VR_HIP(ctx, hipMemcpyAsync(vals, v0, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
+    return VR_OK;
+}
+
+}  // namespace
+
+int scan_u32(vr_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev, hipStream_t s) {
+    if (n <= 0) {
+        if (total_dev) return fill_u32(ctx, total_dev, 0u, 1, s);
+        return VR_OK;
+    }
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(SCAN_BLOCK), 0, s, in, out, n, nullptr, total_dev,
+                           (int64_t)1, nullptr);
+        VR_LAUNCH_CHECK(ctx);
+        return VR_OK;
+    }
+    // partial sums live in a fresh region per recursion level
+    static const int slots[2] = {WS_SCAN_TMP, WS_SCAN_TMP2};
+    static thread_local int depth = 0;
+    if (depth >= 2) return set_err(ctx, VR_ERR_UNSUPPORTED, "scan of %lld elements too deep", (long long)n);
+    uint32_t* part = wsT<uint32_t>(ctx, slots[depth], nb);
+    if (!part) return VR_ERR_OUT_OF_MEMORY;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part);
+    VR_LAUNCH_CHECK(ctx);
+    ++depth;
+    int rc = scan_u32(ctx, part, part, nb, nullptr, s);
+    --depth;
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part, total_dev,
+                       nb, nullptr);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+int sort_pairs_u32(vr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
+    return sort_pairs_impl<uint32_t>(ctx, keys, vals, n, bits, s);
+}
+
+int sort_pairs_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
+    return sort_pairs_impl<uint64_t>(ctx, keys, vals, n, bits, s);
+}
+
+int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return VR_OK;
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+int fill_u32(vr_ctx* ctx, uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return VR_OK;
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+int iota_u32(vr_ctx* ctx, uint32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return VR_OK;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+}  // namespace vr

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libvr (include/vr.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libvr.so.
+PyTorch supplies device memory and the current stream.  There is no fallback:
+if libvr.so is missing, or no gfx950 device is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvr.so")
+
+VR_OK, VR_ERR_INVALID_ARG, VR_ERR_NO_DEVICE, VR_ERR_OUT_OF_MEMORY = 0, -1, -2, -3
+VR_ERR_HIP, VR_ERR_NOT_CONVERGED, VR_ERR_UNSUPPORTED = -4, -5, -6
+CELL_COLS = 28
+
+# Entry points declared in include/vr.h (checked by the CPU test-suite).
+ENTRY_POINTS = (
+    "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
+    "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
+    "vr_host_ellv", "vr_fof6d", "vr_unbind",
+)
+
+
+class VrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libvr status {code}: {msg}")
+        self.code = code
+
+
+class _Particles(C.Structure):
+    _fields_ = [("n", C.c_int64),
+                ("qx", C.c_void_p), ("qy", C.c_void_p), ("qz", C.c_void_p),
+                ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
+                ("mass", C.c_void_p), ("mass_value", C.c_double),
+                ("box", C.c_double), ("grid_bits", C.c_int32)]
+
+
+class _CellParams(C.Structure):
+    _fields_ = [("f_cell", C.c_double), ("ncell_floor", C.c_int32), ("ncell_div", C.c_int32),
+                ("nbins", C.c_int32), ("split_rule", C.c_int32)]
+
+
+class _UnbindParams(C.Structure):
+    _fields_ = [("G", C.c_double), ("eps", C.c_double), ("beta_E", C.c_double),
+                ("frac_ref", C.c_double), ("n_min", C.c_int32), ("n_ref_min", C.c_int32),
+                ("frame_type", C.c_int32), ("max_iter", C.c_int32), ("persistent", C.c_int32),
+                ("tile", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libvr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1902_01010_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl, flt, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_float, C.c_size_t
+        P = C.POINTER(_Particles)
+        L.vr_create.argtypes = [C.POINTER(vp), C.c_int, sz]
+        L.vr_destroy.argtypes = [vp]
+        L.vr_destroy.restype = None
+        L.vr_last_error.argtypes = [vp]
+        L.vr_last_error.restype = C.c_char_p
+        L.vr_sync.argtypes = [vp, vp]
+        L.vr_workspace_bytes.argtypes = [vp]
+        L.vr_workspace_bytes.restype = sz
+        L.vr_quantize.argtypes = [vp, i64, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+        L.vr_fof3d.argtypes = [vp, P, dbl, vp, vp]
+        L.vr_groups.argtypes = [vp, i64, vp, i32, C.POINTER(i32), vp, vp, vp, vp]
+        if hasattr(L, "vr_cell_moments"):
+            L.vr_cell_moments.argtypes = [vp, P, i32, vp, vp, C.POINTER(_CellParams), vp, vp, vp, vp,
+                                          i64, vp, C.POINTER(i64), vp]
+        if hasattr(L, "vr_local_vdensity"):
+            L.vr_local_vdensity.argtypes = [vp, P, i32, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
+        if hasattr(L, "vr_host_ellv"):
+            L.vr_host_ellv.argtypes = [vp, P, i32, vp, vp, dbl, vp, vp]
+        if hasattr(L, "vr_fof6d"):
+            L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
+        if hasattr(L, "vr_unbind"):
+            L.vr_unbind.argtypes = [vp, P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libvr takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libvr takes contiguous tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Particles:
+    """Device particle set: q (3, n) int32 grid coordinates, v (3, n) float32,
+    optional mass (n,) float32."""
+
+    def __init__(self, q, v, mass, mass_value, box, grid_bits):
+        self.q = q.contiguous()
+        self.v = None if v is None else v.contiguous()
+        self.mass = None if mass is None else mass.contiguous()
+        self.mass_value = float(mass_value)
+        self.box = float(box)
+        self.grid_bits = int(grid_bits)
+        s = _Particles()
+        s.n = self.q.shape[1]
+        s.qx, s.qy, s.qz = (C.c_void_p(self.q[d].data_ptr()) for d in range(3))
+        if self.v is not None:
+            s.vx, s.vy, s.vz = (C.c_void_p(self.v[d].data_ptr()) for d in range(3))
+        s.mass = None if self.mass is None else C.c_void_p(self.mass.data_ptr())
+        s.mass_value = self.mass_value
+        s.box = self.box
+        s.grid_bits = self.grid_bits
+        self.s = s
+
+    @property
+    def n(self):
+        return self.q.shape[1]
+
+    @property
+    def device(self):
+        return self.q.device
+
+
+class Context:
+    """A libvr context on one device (workspace pool, autotune state)."""
+
+    def __init__(self, device: int = 0, max_workspace_bytes: int = 0):
+        self.lib = load_library()
+        h = C.c_void_p()
+        rc = self.lib.vr_create(C.byref(h), int(device), int(max_workspace_bytes))
+        if rc != VR_OK:
+            raise VrError(rc, self.lib.vr_last_error(None).decode())
+        self.h = h
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != VR_OK:
+            raise VrError(rc, self.lib.vr_last_error(self.h).decode())
+
+    def sync(self):
+        self._check(self.lib.vr_sync(self.h, _stream()))
+
+    def workspace_bytes(self):
+        return int(self.lib.vr_workspace_bytes(self.h))
+
+    # -- entry points -------------------------------------------------------
+    def quantize(self, x, box, grid_bits=21):
+        n = x.shape[1]
+        q = torch.empty((3, n), dtype=torch.int32, device=x.device)
+        x = x.contiguous()
+        self._check(self.lib.vr_quantize(self.h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), float(box),
+                                         int(grid_bits), _ptr(q[0]), _ptr(q[1]), _ptr(q[2]), _stream()))
+        return q
+
+    def fof3d(self, P: Particles, ellx, label=None):
+        if label is None:
+            label = torch.empty(P.n, dtype=torch.int32, device=P.device)
+        self._check(self.lib.vr_fof3d(self.h, C.byref(P.s), float(ellx), _ptr(label), _stream()))
+        return label
+
+    def groups(self, label, n_min):
+        n = label.shape[0]
+        dev = label.device
+        ng = C.c_int32(0)
+        gof = torch.empty(n, dtype=torch.int32, device=dev)
+        off = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        mem = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self._check(self.lib.vr_groups(self.h, n, _ptr(label), int(n_min), C.byref(ng), _ptr(gof),
+                                       _ptr(off), _ptr(mem), _stream()))
+        g = ng.value
+        off = off[:g + 1]
+        return g, gof, off, mem
+
+    def cell_moments(self, P: Particles, host_offsets, host_members, f_cell=0.01, ncell_floor=100,
+                     ncell_div=8, nbins=16, split_rule=0, want_table=True, out=None):
+        dev = P.device
+        n = P.n
+        nh = host_offsets.shape[0] - 1
+        if out is None:
+            out = dict(vbar=torch.full((3, n), float("nan"), device=dev),
+                       sigma=torch.full((6, n), float("nan"), device=dev),
+                       rho_cell=torch.full((n,), float("nan"), device=dev),
+                       cell_of=torch.full((n,), -1, dtype=torch.int32, device=dev))
+        cp = _CellParams(f_cell, ncell_floor, ncell_div, nbins, split_rule)
+        ncell = C.c_int64(0)
+        cap = 0
+        table = None
+        if want_table:
+            # an upper bound on the number of leaves: every leaf holds >= 1 member
+            cap = int(host_members.shape[0]) if nh > 0 else 0
+            table = torch.empty((max(cap, 1), CELL_COLS), dtype=torch.float64, device=dev)
+        self._check(self.lib.vr_cell_moments(self.h, C.byref(P.s), nh, _ptr(host_offsets), _ptr(host_members),
+                                             C.byref(cp), _ptr(out["vbar"]), _ptr(out["sigma"]),
+                                             _ptr(out["rho_cell"]), _ptr(out["cell_of"]), cap,
+                                             _ptr(table), C.byref(ncell), _stream()))
+        out["n_cells"] = ncell.value
+        if want_table:
+            out["cells"] = table[:ncell.value]
+        return out
+
+    def local_vdensity(self, P: Particles, host_offsets, host_members, vbar, sigma, n_se, n_v,
+                       subset=None, R=None):
+        if R is None:
+            R = torch.full((P.n,), float("nan"), device=P.device)
+        nh = host_offsets.shape[0] - 1
+        ns = 0 if subset is None else subset.shape[0]
+        self._check(self.lib.vr_local_vdensity(self.h, C.byref(P.s), nh, _ptr(host_offsets),
+                                               _ptr(host_members), _ptr(vbar), _ptr(sigma), int(n_se),
+                                               int(n_v), _ptr(subset), ns, _ptr(R), _stream()))
+        return R
+
+    def host_ellv(self, P: Particles, host_offsets, host_members, alpha_v=1.25):
+        nh = host_offsets.shape[0] - 1
+        out = torch.empty(max(nh, 1), dtype=torch.float64, device=P.device)
+        self._check(self.lib.vr_host_ellv(self.h, C.byref(P.s), nh, _ptr(host_offsets), _ptr(host_members),
+                                          float(alpha_v), _ptr(out), _stream()))
+        return out[:nh]
+
+    def fof6d(self, P: Particles, host_of, ellv_host, ellx_s, R=None, R_threshold=2.0, label6=None):
+        if label6 is None:
+            label6 = torch.empty(P.n, dtype=torch.int32, device=P.device)
+        self._check(self.lib.vr_fof6d(self.h, C.byref(P.s), _ptr(host_of), _ptr(ellv_host),
+                                      int(ellv_host.shape[0]), float(ellx_s), _ptr(R), float(R_threshold),
+                                      _ptr(label6), _stream()))
+        return label6
+
+    def unbind(self, P: Particles, offsets, members, G, eps, beta_E=0.95, frac_ref=0.1, n_min=20,
+               n_ref_min=10, frame_type=1, max_iter=100, persistent=1, tile=0):
+        ng = offsets.shape[0] - 1
+        dev = P.device
+        bound = torch.zeros(P.n, dtype=torch.uint8, device=dev)
+        phi = torch.full((P.n,), float("nan"), dtype=torch.float64, device=dev)
+        iters = torch.zeros(max(ng, 1), dtype=torch.int32, device=dev)
+        up = _UnbindParams(G, eps, beta_E, frac_ref, n_min, n_ref_min, frame_type, max_iter, persistent, tile)
+        self._check(self.lib.vr_unbind(self.h, C.byref(P.s), ng, _ptr(offsets), _ptr(members), C.byref(up),
+                                       _ptr(bound), _ptr(phi), _ptr(iters), _stream()))
+        return dict(bound=bound, phi=phi, iters=iters[:ng])

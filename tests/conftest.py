@@ -16,4 +16,5 @@ def pytest_configure(config):
 def ref():
     import oracle
     oracle.lib()
+    oracle.set_threads(min(16, os.cpu_count() or 1))
     return oracle

@@ -1,0 +1,94 @@
+"""GPU parity of quantisation, 3D FOF and group tables against the oracle
+(bit-exact: these are integer results)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1902_01010_amd import synth
+from tests.gpu_common import both, dev_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vr():
+    from paper_1902_01010_amd import vr as _vr
+    return _vr
+
+
+@pytest.fixture(scope="module")
+def ctx(vr):
+    return vr.Context(0)
+
+
+WORKLOADS = {
+    "halo20k": lambda: synth.isolated_halo(seed=5, n_host=20000, n_sub=3, sub_range=(500, 2000)),
+    "box32": lambda: synth.cosmo_box(seed=6, n_side=32),
+    "box64": lambda: synth.cosmo_box(seed=2, n_side=64),
+}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_quantize_bit_exact(ctx, vr, ref, name):
+    w = WORKLOADS[name]()
+    q = ctx.quantize(dev_tensor(w.x), w.box, w.grid_bits).cpu().numpy().view(np.uint32)
+    assert (q == ref.quantize(w.x, w.box, w.grid_bits)).all()
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_fof3d_bit_exact(ctx, vr, ref, name):
+    w = WORKLOADS[name]()
+    P, Pr = both(ctx, vr, ref, w)
+    ell = w.params["ellx"]
+    lab = ctx.fof3d(P, ell).cpu().numpy()
+    exp = ref.fof3d(Pr, ell)
+    assert (lab == exp).all()
+    # determinism despite the racy union-find
+    lab2 = ctx.fof3d(P, ell).cpu().numpy()
+    assert (lab2 == lab).all()
+
+
+def test_fof3d_edge_cases(ctx, vr, ref):
+    size = 1 << 21
+    # strict inequality on a lattice, periodic straddle, coarse grid (< 3 cells a side)
+    s = 1 << 12
+    g = np.arange(6) * s + 1000
+    qx, qy, qz = np.meshgrid(g, g, g, indexing="ij")
+    q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()]).astype(np.uint32)
+    Pd = vr.Particles(dev_tensor(q.view(np.int32)), None, None, 1.0, 1.0, 21)
+    Pr = ref.Particles(q, None, None, 1.0, 1.0, 21)
+    for ell in [s / size, (s + 0.5) / size, 0.3]:
+        assert (ctx.fof3d(Pd, ell).cpu().numpy() == ref.fof3d(Pr, ell)).all()
+    q2 = np.array([[5, size - 5, 1000], [7, 7, 7], [9, 9, 9]], np.uint32)
+    Pd2 = vr.Particles(dev_tensor(q2.view(np.int32)), None, None, 1.0, 1.0, 21)
+    assert ctx.fof3d(Pd2, 11.0 / size).cpu().numpy().tolist() == [0, 0, 2]
+    # a single particle and an empty set
+    q1 = np.array([[3], [4], [5]], np.uint32)
+    P1 = vr.Particles(dev_tensor(q1.view(np.int32)), None, None, 1.0, 1.0, 21)
+    assert ctx.fof3d(P1, 0.01).cpu().numpy().tolist() == [0]
+    q0 = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
+    P0 = vr.Particles(q0, None, None, 1.0, 1.0, 21)
+    assert ctx.fof3d(P0, 0.01).numel() == 0
+
+
+def test_fof3d_rejects_bad_args(ctx, vr):
+    q = torch.zeros((3, 4), dtype=torch.int32, device="cuda")
+    P = vr.Particles(q, None, None, 1.0, 1.0, 21)
+    with pytest.raises(vr.VrError):
+        ctx.fof3d(P, 0.5)
+    with pytest.raises(vr.VrError):
+        ctx.fof3d(P, 0.0)
+
+
+@pytest.mark.parametrize("name", ["halo20k", "box64"])
+def test_groups_bit_exact(ctx, vr, ref, name):
+    w = WORKLOADS[name]()
+    P, Pr = both(ctx, vr, ref, w)
+    lab = ctx.fof3d(P, w.params["ellx"])
+    for n_min in (20, 256):
+        ng, gof, off, mem = ctx.groups(lab, n_min)
+        eng, egof, eoff, emem = ref.groups(lab.cpu().numpy(), n_min)
+        assert ng == eng
+        assert (gof.cpu().numpy() == egof).all()
+        assert (off.cpu().numpy() == eoff).all()
+        assert (mem[:eoff[-1]].cpu().numpy() == emem).all()

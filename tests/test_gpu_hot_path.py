@@ -1,0 +1,184 @@
+"""GPU parity of the cells, R, 6D FOF and unbinding entry points against the
+CPU oracle, on the same seeded inputs.
+
+Tolerances: integer results (cell partitions, neighbour-derived labels,
+bound flags) are bit-exact; FP64 reductions agree to round-off (rtol 1e-10);
+R agrees to 1e-4 max(1, |R|) (the outlier classification is compared outside
+that band); potentials agree to 1e-5 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1902_01010_amd import synth
+from tests.gpu_common import both, dev_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vr():
+    from paper_1902_01010_amd import vr as _vr
+    return _vr
+
+
+@pytest.fixture(scope="module")
+def ctx(vr):
+    return vr.Context(0)
+
+
+def hosts_of(ref, Pr, w, host_min=256):
+    lab = ref.fof3d(Pr, w.params["ellx"])
+    ng, gof, off, mem = ref.groups(lab, 20)
+    sizes = np.diff(off)
+    nh = int((sizes >= host_min).sum())
+    hoff = off[:nh + 1].copy()
+    hmem = mem[:hoff[-1]].copy()
+    host_of = np.where((gof >= 0) & (gof < nh), gof, -1).astype(np.int32)
+    return hoff, hmem, host_of
+
+
+CASES = {
+    "halo12k": lambda: synth.isolated_halo(seed=21, n_host=12000, n_sub=3, sub_range=(400, 1500)),
+    "box48": lambda: synth.cosmo_box(seed=22, n_side=48),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request, ctx, vr, ref):
+    w = CASES[request.param]()
+    P, Pr = both(ctx, vr, ref, w)
+    hoff, hmem, host_of = hosts_of(ref, Pr, w)
+    assert len(hoff) > 1
+    return dict(w=w, P=P, Pr=Pr, hoff=hoff, hmem=hmem, host_of=host_of)
+
+
+def test_cell_moments_parity(ctx, ref, case):
+    P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
+    exp = ref.cell_moments(Pr, hoff, hmem)
+    got = ctx.cell_moments(P, dev_tensor(hoff), dev_tensor(hmem))
+    assert got["n_cells"] == exp["cells"].shape[0]
+    gc = got["cells"].cpu().numpy()
+    ec = exp["cells"]
+    ints = [0, 1] + list(range(15, 27))
+    assert (gc[:, ints] == ec[:, ints]).all()
+    np.testing.assert_allclose(gc[:, [2, 27]], ec[:, [2, 27]], rtol=1e-12)
+    np.testing.assert_allclose(gc[:, 3:6], ec[:, 3:6], rtol=1e-12)
+    np.testing.assert_allclose(gc[:, 6:15], ec[:, 6:15], rtol=1e-9, atol=1e-9 * np.abs(ec[:, 6:15]).max())
+    assert (got["cell_of"].cpu().numpy() == exp["cell_of"]).all()
+    for k in ("vbar", "sigma", "rho_cell"):
+        g = got[k].cpu().numpy()
+        e = exp[k]
+        fin = np.isfinite(e)
+        assert (np.isfinite(g) == fin).all()
+        np.testing.assert_allclose(g[fin], e[fin], rtol=2e-6, atol=1e-6 * np.abs(e[fin]).max())
+
+
+def test_host_ellv_parity(ctx, ref, case):
+    P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
+    exp = ref.host_ellv(Pr, hoff, hmem, 1.25)
+    got = ctx.host_ellv(P, dev_tensor(hoff), dev_tensor(hmem), 1.25).cpu().numpy()
+    np.testing.assert_allclose(got, exp, rtol=1e-12)
+
+
+def _R_close(g, e):
+    fin = np.isfinite(e)
+    assert (np.isnan(g) == np.isnan(e)).all()
+    assert (np.isposinf(g) == np.isposinf(e)).all()
+    err = np.abs(g[fin] - e[fin]) / np.maximum(1.0, np.abs(e[fin]))
+    assert err.max() <= 1e-4, err.max()
+    # classification at the threshold, outside the tolerance band
+    band = np.abs(e - 2.0) <= 2e-4
+    cls_g = g >= 2.0
+    cls_e = e >= 2.0
+    assert (cls_g[~band] == cls_e[~band]).all()
+
+
+def test_local_vdensity_parity_same_inputs(ctx, ref, case):
+    P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    exp = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], 32, 8)["R"]
+    got = ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(cm["vbar"]),
+                             dev_tensor(cm["sigma"]), 32, 8).cpu().numpy()
+    _R_close(got, exp)
+
+
+def test_local_vdensity_end_to_end(ctx, ref, case):
+    P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    exp = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], 32, 8)["R"]
+    dh, dm = dev_tensor(hoff), dev_tensor(hmem)
+    gm = ctx.cell_moments(P, dh, dm, want_table=False)
+    got = ctx.local_vdensity(P, dh, dm, gm["vbar"], gm["sigma"], 32, 8).cpu().numpy()
+    _R_close(got, exp)
+
+
+def test_local_vdensity_subset_and_other_sizes(ctx, ref, case):
+    P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    rng = np.random.default_rng(3)
+    sub = np.sort(rng.choice(hmem, size=min(500, len(hmem)), replace=False)).astype(np.int32)
+    rng.shuffle(sub)
+    for n_se, n_v in [(32, 8), (16, 4), (48, 16)]:
+        exp = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], n_se, n_v, subset=sub)["R"]
+        got = ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(cm["vbar"]),
+                                 dev_tensor(cm["sigma"]), n_se, n_v, subset=dev_tensor(sub)).cpu().numpy()
+        _R_close(got, exp)
+        untouched = np.ones(P.n, bool)
+        untouched[sub] = False
+        assert np.isnan(got[untouched]).all()
+
+
+def test_fof6d_parity(ctx, ref, case):
+    P, Pr, hoff, hmem, host_of = case["P"], case["Pr"], case["hoff"], case["hmem"], case["host_of"]
+    w = case["w"]
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], 32, 8)["R"]
+    ellv = ref.host_ellv(Pr, hoff, hmem, 1.25)
+    ellxs = 0.5 * w.params["ellx"]
+    for RR in (R, None):
+        exp = ref.fof6d(Pr, host_of, ellv, ellxs, RR, 2.0)
+        got = ctx.fof6d(P, dev_tensor(host_of), dev_tensor(ellv), ellxs,
+                        None if RR is None else dev_tensor(RR), 2.0).cpu().numpy()
+        assert (got == exp).all()
+
+
+def _unbind_case(seed, n_groups, n_max, masses=False):
+    w = synth.unbind_groups(seed=seed, n_groups=n_groups, n_max=n_max)
+    if masses:
+        rng = np.random.default_rng(seed)
+        w.mass = rng.uniform(0.5, 1.5, w.n).astype(np.float32) * np.float32(w.mass_value)
+    return w
+
+
+@pytest.mark.parametrize("seed,ng,nmax,masses,frame", [(3, 40, 4000, False, 1), (4, 25, 3000, True, 1),
+                                                        (5, 25, 3000, False, 0)])
+def test_unbind_parity(ctx, vr, ref, seed, ng, nmax, masses, frame):
+    w = _unbind_case(seed, ng, nmax, masses)
+    P, Pr = both(ctx, vr, ref, w)
+    off, mem = w.groups
+    G, eps = w.params["G"], w.params["eps"]
+    exp = ref.unbind(Pr, off, mem, G, eps, frame_type=frame)
+    got = ctx.unbind(P, dev_tensor(off), dev_tensor(mem), G, eps, frame_type=frame)
+    gb, gphi, git = (got[k].cpu().numpy() for k in ("bound", "phi", "iters"))
+    clean = exp["min_margin"] > 1e-5
+    assert clean.mean() > 0.8
+    for g in np.nonzero(clean)[0]:
+        m = mem[off[g]:off[g + 1]]
+        assert (gb[m] == exp["bound"][m]).all(), g
+        assert git[g] == exp["iters"][g], g
+        e = exp["phi"][m]
+        fin = np.isfinite(e)
+        assert (np.isfinite(gphi[m]) == fin).all()
+        np.testing.assert_allclose(gphi[m][fin], e[fin], rtol=1e-5)
+    con = w.meta["is_contaminant"]
+    assert (gb[con] == 0).all()
+
+
+def test_unbind_not_converged(ctx, vr, ref):
+    w = _unbind_case(3, 3, 800)
+    P, _ = both(ctx, vr, ref, w)
+    off, mem = w.groups
+    with pytest.raises(vr.VrError) as e:
+        ctx.unbind(P, dev_tensor(off), dev_tensor(mem), w.params["G"], w.params["eps"], max_iter=1)
+    assert e.value.code == vr.VR_ERR_NOT_CONVERGED
