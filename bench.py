@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the phase-space halo-finder hot path on one MI355X.
+
+One step = one pass of the whole hot path (quantise, 3D FOF, groups, entropy
+KD cells and moments, R, host velocity linking lengths, 6D FOF over the
+outliers, candidate groups, unbinding) over the synthetic 256^3 cosmological
+box (16,777,216 particles in a 100 Mpc/h periodic box), inputs resident in
+HBM.  Prints one JSON line with particles/s, the roofline of the dominant
+kernel (timed live with HIP events on its launch stream) and the CPU oracle
+timed on a bounded sub-box sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic work per unit of each timed kernel (the unit is what the
+# library accumulates per launch): bytes for memory-bound kernels, flops for
+# the potential.
+KERNEL_MODEL = {
+    # (bound, per-unit amount, unit label)
+    "radix_scatter": ("hbm", 16.0, "key: read key+index, write key+index"),
+    "fof_link3d": ("hbm", 20.0, "particle: 12 B coordinates + 4 B parent in, 4 B out"),
+    "kd_level": ("hbm", 32.0, "member visit: 16 B member record read + written"),
+    "knn": ("hbm", 68.0, "query: q 12, v 12, m 4, vbar 12, sigma 24 in; R 4 out"),
+    "fof_link6d": ("hbm", 32.0, "participant: q 12, v 12, host 4, parent 4"),
+    "unbind_potential": ("alu", 6.0, "ordered pair: 12 flop per unordered pair"),
+    "unbind_group": ("hbm", 40.0, "member: coordinates, velocity, potential"),
+}
+
+
+def cpu_baseline(w, prm, side):
+    """The oracle pipeline on the particles of the sub-box [0, side)^3."""
+    import oracle
+    import oracle.pipeline as opipe
+    from paper_1902_01010_amd import synth
+
+    sel = np.all(w.x < np.float32(side), axis=0)
+    sub = synth.Workload("cosmo_box_subbox", np.ascontiguousarray(w.x[:, sel]), np.ascontiguousarray(w.v[:, sel]),
+                         None, w.mass_value, w.box, w.grid_bits, w.params, {})
+    # the host's CPU share for one GPU (OMP_NUM_THREADS), at most the visible cores
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1), os.cpu_count() or 1)
+    oracle.lib()
+    oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    opipe.run(sub, prm)
+    dt = time.perf_counter() - t0
+    return {"value": sub.n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"all particles of the sub-box [0, {side:g})^3 Mpc/h of the same 256^3 box "
+                      f"({sub.n} particles, {dt:.1f} s on {threads} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-side", type=int, default=256, help="particles per side of the box (256 = the benchmark)")
+    ap.add_argument("--cpu-sample-side", type=float, default=31.25, help="side (Mpc/h) of the oracle's sub-box")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1902_01010_amd import pipeline, synth, vr
+
+    w = synth.cosmo_box(n_side=args.n_side)
+    prm = pipeline.Params.from_workload(w)
+    ctx = vr.Context(0)
+    x, v, m = pipeline.device_inputs(w)
+    if args.calib_copy_mib:
+        a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    print(f"[bench] {w.n} particles, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+
+    def step():
+        return pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = w.n / (ms_per_step / 1e3)
+
+    kernels = {}
+    for name in pipeline.KERNELS:
+        launches, ms, work = ctx.kernel_time(name)
+        if launches == 0:
+            continue
+        bound, per_unit, _ = KERNEL_MODEL[name]
+        amount = work * per_unit / launches          # bytes or flops per launch
+        avg_s = ms / launches / 1e3
+        if bound == "alu":
+            achieved, peak, unit = amount / avg_s / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+        else:
+            achieved, peak, unit = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        kernels[name] = {"bound": bound, "launches_per_step": launches / args.steps,
+                         "ms_per_step": ms / args.steps, "avg_launch_ms": ms / launches,
+                         "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    d = kernels[dom]
+    roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
+                "frac": round(d["frac"], 5), "traffic": None, "kernel": dom}
+
+    ub = out.get("unbind")
+    summary = {"groups_3d": out["n_groups"], "hosts_searched": out["n_hosts"], "particles_searched": out["n_searched"],
+               "outliers": int((out["R"] >= prm.R_threshold).sum().item()),
+               "candidates_6d": out.get("n_candidates", 0)}
+    if ub is not None:
+        summary["bound_particles"] = int(ub["bound"].sum().item())
+        summary["max_unbind_passes"] = int(ub["iters"].max().item())
+
+    rec = {"metric": "particles/s for R+3D/6D FOF+unbind, 256^3 (exact path)", "value": round(value, 1),
+           "unit": "particles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int32 grid + f64 tests/moments + f32 potential tiles", "data": "synthetic",
+           "config": {"workload": f"synthetic cosmological box {args.n_side}^3 particles, "
+                                  f"{w.box:g} Mpc/h periodic, 2^21 grid; NFW halos (dN/dlnN ~ N^-0.9) with "
+                                  f"Plummer subhalos + uniform background",
+                      "n_particles": w.n, "box_mpc_h": w.box, "b": 0.2, "n_se": prm.n_se, "n_v": prm.n_v,
+                      "R_threshold": prm.R_threshold, "parallelism": "1 GPU"},
+           "roofline": roofline, "kernels": kernels, "summary": summary}
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sub-box sample", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, prm, args.cpu_sample_side)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

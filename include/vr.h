@@ -52,6 +52,18 @@ int vr_sync(vr_ctx* ctx, void* stream);
 /* Bytes of workspace currently held by the context. */
 size_t vr_workspace_bytes(const vr_ctx* ctx);
 
+/* Kernel timing, for measurement.  While enabled, the library brackets its
+ * main kernels with HIP events recorded on the stream each kernel is
+ * launched on, and accumulates per kernel name the number of launches, the
+ * summed duration and the algorithmic work of the launches (the unit is per
+ * kernel: "fof_link3d" particles, "kd_level" member visits, "knn" queries,
+ * "fof_link6d" participants, "unbind_potential" ordered pairs i != j,
+ * "unbind_group" members, "radix_scatter" keys).  vr_set_timing also clears
+ * the totals.  vr_kernel_time waits for the recorded events. */
+int vr_set_timing(vr_ctx* ctx, int enabled);
+int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms,
+                   double* work);
+
 /* Particle set.  mass == NULL means every particle has mass mass_value. */
 typedef struct {
     int64_t n;
@@ -141,7 +153,9 @@ int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
 
 /* 6D friends-of-friends over outliers (Eq. fof6d with the substructure
  * linking length ellx_s = alpha_xS ellx): participants are particles with
- * host_of[i] >= 0 and R[i] >= R_threshold (all hosted ones if R is NULL);
+ * 0 <= host_of[i] < n_hosts and R[i] >= R_threshold (all hosted ones if R is
+ * NULL; other host_of values, e.g. -1 or the id of an unsearched group, do
+ * not take part);
  * i and j are linked iff both participate, share a host h, and
  * d2/ells2 + dv2/ellv_host[h]^2 < 1 (FP64, that evaluation order).
  * label6[i] = smallest participant index of i's component, -1 otherwise. */

@@ -75,7 +75,7 @@ def lib():
         L.vr_ref_local_vdensity.argtypes = [P, i32, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp, vp,
                                             vp, vp]
         L.vr_ref_host_ellv.argtypes = [P, i32, vp, vp, dbl, vp]
-        L.vr_ref_fof6d.argtypes = [P, vp, vp, dbl, vp, flt, vp]
+        L.vr_ref_fof6d.argtypes = [P, vp, i32, vp, dbl, vp, flt, vp]
         L.vr_ref_unbind.argtypes = [P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -216,11 +216,12 @@ def host_ellv(P: Particles, host_offsets, host_members, alpha_v=1.25):
 def fof6d(P: Particles, host_of, ellv_host, ellx_s, R=None, R_threshold=2.0):
     hof = np.ascontiguousarray(host_of, dtype=np.int32)
     ev = np.ascontiguousarray(ellv_host, dtype=np.float64)
+    nh = ev.shape[0]
     if ev.shape[0] == 0:
         ev = np.ones(1)
     Rr = None if R is None else np.ascontiguousarray(R, dtype=np.float32)
     lab = np.zeros(P.n, np.int32)
-    _check(lib().vr_ref_fof6d(C.byref(P.s), _p(hof), _p(ev), float(ellx_s), _p(Rr),
+    _check(lib().vr_ref_fof6d(C.byref(P.s), _p(hof), nh, _p(ev), float(ellx_s), _p(Rr),
                               float(R_threshold), _p(lab)), "fof6d")
     return lab
 

@@ -1,0 +1,45 @@
+"""The hot path end to end through the CPU oracle (test infrastructure):
+same chain of steps as the GPU pipeline, every step an oracle call."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as ref
+
+
+def run(w, prm, timings=None):
+    import time
+
+    def tick(name, t0):
+        if timings is not None:
+            timings[name] = time.perf_counter() - t0
+        return time.perf_counter()
+
+    t = time.perf_counter()
+    q = ref.quantize(w.x, w.box, w.grid_bits)
+    P = ref.Particles(q, w.v, w.mass, w.mass_value, w.box, w.grid_bits)
+    t = tick("quantize", t)
+    label = ref.fof3d(P, prm.ellx)
+    t = tick("fof3d", t)
+    ng, group_of, off, mem = ref.groups(label, prm.n_min)
+    sizes = np.diff(off)
+    nh = int((sizes >= prm.host_min).sum())
+    hoff, hmem = off[:nh + 1], mem[:off[nh]]
+    t = tick("groups", t)
+    out = dict(q=q, label=label, n_groups=ng, group_of=group_of, offsets=off, members=mem, n_hosts=nh)
+    if nh == 0:
+        return out
+    cm = ref.cell_moments(P, hoff, hmem)
+    t = tick("cells", t)
+    R = ref.local_vdensity(P, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
+    t = tick("R", t)
+    ellv = ref.host_ellv(P, hoff, hmem, prm.alpha_v)
+    label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
+    t = tick("fof6d", t)
+    nc, sub_of, sub_off, sub_mem = ref.groups(label6, prm.n_min)
+    t = tick("subgroups", t)
+    ub = ref.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc else None
+    tick("unbind", t)
+    out.update(cells=cm, R=R, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
+               sub_members=sub_mem, unbind=ub)
+    return out

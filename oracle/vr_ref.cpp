@@ -656,7 +656,7 @@ extern "C" int vr_ref_host_ellv(const vr_ref_particles* p, int32_t n_hosts,
 }
 
 // 6D FOF over outliers (Eq. fof6d with the substructure linking length).
-extern "C" int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of,
+extern "C" int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of, int32_t n_hosts,
                             const double* ellv_host, double ellx_s, const float* R,
                             float R_threshold, int32_t* label6) {
     if (!valid_particles(p) || !has_vel(p) || (p->n > 0 && (!host_of || !ellv_host || !label6)))
@@ -665,7 +665,7 @@ extern "C" int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of,
     if (!(ell2 > 0) || !(std::sqrt(ell2) < std::ldexp(1.0, p->grid_bits - 1))) return -1;
     std::vector<int32_t> part;
     for (int64_t i = 0; i < p->n; ++i) {
-        bool in = host_of[i] >= 0 && (R == nullptr || R[i] >= R_threshold);
+        bool in = host_of[i] >= 0 && host_of[i] < n_hosts && (R == nullptr || R[i] >= R_threshold);
         if (in) {
             if (!(ellv_host[host_of[i]] > 0)) return -1;
             part.push_back((int32_t)i);

@@ -114,10 +114,10 @@ int vr_ref_host_ellv(const vr_ref_particles* p, int32_t n_hosts,
                      double alpha_v, double* ellv_host);
 
 /* 6D friends-of-friends over outliers (Eq. fof6d): participants are hosted
- * particles (host_of >= 0) with R >= R_threshold (all hosted ones if R is
- * NULL); link iff same host and d2/ellxs2 + dv2/ellv^2 < 1.
+ * particles (0 <= host_of < n_hosts) with R >= R_threshold (all hosted ones
+ * if R is NULL); link iff same host and d2/ellxs2 + dv2/ellv^2 < 1.
  * label6 = smallest participant index of the component, -1 otherwise. */
-int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of,
+int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of, int32_t n_hosts,
                  const double* ellv_host, double ellx_s,
                  const float* R, float R_threshold, int32_t* label6);
 

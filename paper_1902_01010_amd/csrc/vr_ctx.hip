@@ -9,6 +9,8 @@ thread_local std::string g_create_err;
 
 namespace vr {
 
+static void timers_drain(vr_ctx* ctx);
+
 int set_err(vr_ctx* ctx, int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -50,6 +52,49 @@ void* ws(vr_ctx* ctx, int slot, size_t bytes) {
     b.bytes = want;
     ctx->held += want;
     return p;
+}
+
+hipEvent_t timer_event(vr_ctx* ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void timer_push(vr_ctx* ctx, const char* name, hipEvent_t e0, hipEvent_t e1, double work) {
+    for (auto& t : ctx->timers)
+        if (t.name == name) {
+            t.pending.push_back(e0);
+            t.pending.push_back(e1);
+            t.pending_work.push_back(work);
+            return;
+        }
+    vr_timer t;
+    t.name = name;
+    t.pending = {e0, e1};
+    t.pending_work = {work};
+    ctx->timers.push_back(t);
+}
+
+static void timers_drain(vr_ctx* ctx) {
+    for (auto& t : ctx->timers) {
+        for (size_t k = 0; k + 1 < t.pending.size(); k += 2) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(t.pending[k + 1]);
+            (void)hipEventElapsedTime(&ms, t.pending[k], t.pending[k + 1]);
+            t.ms += ms;
+            t.launches += 1;
+            t.work += t.pending_work[k / 2];
+            ctx->event_pool.push_back(t.pending[k]);
+            ctx->event_pool.push_back(t.pending[k + 1]);
+        }
+        t.pending.clear();
+        t.pending_work.clear();
+    }
 }
 
 int check_particles(vr_ctx* ctx, const vr_particles* p, bool need_vel) {
@@ -119,6 +164,8 @@ void vr_destroy(vr_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    vr::timers_drain(ctx);
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     for (auto& b : ctx->slots)
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -138,5 +185,30 @@ int vr_sync(vr_ctx* ctx, void* stream) {
 }
 
 size_t vr_workspace_bytes(const vr_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+int vr_set_timing(vr_ctx* ctx, int enabled) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    vr::timers_drain(ctx);
+    ctx->timers.clear();
+    ctx->timing = enabled ? 1 : 0;
+    return VR_OK;
+}
+
+int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms, double* work) {
+    if (!ctx || !kernel || !launches || !total_ms || !work) return VR_ERR_INVALID_ARG;
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    vr::timers_drain(ctx);
+    *launches = 0;
+    *total_ms = 0.0;
+    *work = 0.0;
+    for (auto& t : ctx->timers)
+        if (t.name == kernel) {
+            *launches = t.launches;
+            *total_ms = t.ms;
+            *work = t.work;
+        }
+    return VR_OK;
+}
 
 }  // extern "C"

@@ -303,11 +303,15 @@ extern "C" int vr_fof3d(vr_ctx* ctx, const vr_particles* p, double ellx, int32_t
     hipLaunchKernelGGL(k_iota_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, n, parent);
     VR_LAUNCH_CHECK(ctx);
     if ((1 << (gb - s)) >= 3)
-        hipLaunchKernelGGL(k_link3d<true>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cl.key, cl.sx, cl.sy,
-                           cl.sz, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, gb - s, gb, ell2, parent);
+        VR_TIMED(ctx, "fof_link3d", st, n,
+                 hipLaunchKernelGGL(k_link3d<true>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cl.key, cl.sx,
+                                    cl.sy, cl.sz, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, gb - s, gb, ell2,
+                                    parent));
     else
-        hipLaunchKernelGGL(k_link3d<false>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cl.key, cl.sx, cl.sy,
-                           cl.sz, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, gb - s, gb, ell2, parent);
+        VR_TIMED(ctx, "fof_link3d", st, n,
+                 hipLaunchKernelGGL(k_link3d<false>, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cl.key, cl.sx,
+                                    cl.sy, cl.sz, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, gb - s, gb, ell2,
+                                    parent));
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_compress, dim3(grid_for(n, 256)), dim3(256), 0, st, n, parent);
     VR_LAUNCH_CHECK(ctx);

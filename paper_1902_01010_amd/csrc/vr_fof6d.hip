@@ -83,7 +83,6 @@ __global__ void k_participants(int64_t n, const int32_t* __restrict__ host_of, c
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int h = host_of[i];
-    if (h >= n_hosts) atomicOr(bad, 1);
     flag[i] = (h >= 0 && h < n_hosts && (R == nullptr || R[i] >= thr)) ? 1u : 0u;
 }
 
@@ -282,13 +281,15 @@ extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_
     VR_LAUNCH_CHECK(ctx);
     const int b = gb - s;
     if ((1 << b) >= 3)
-        hipLaunchKernelGGL(k_link6d<true>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz,
-                           svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2,
-                           parent);
+        VR_TIMED(ctx, "fof_link6d", st, np,
+                 hipLaunchKernelGGL(k_link6d<true>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx,
+                                    cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals,
+                                    cl.hmask, b, gb, ell2, parent));
     else
-        hipLaunchKernelGGL(k_link6d<false>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz,
-                           svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2,
-                           parent);
+        VR_TIMED(ctx, "fof_link6d", st, np,
+                 hipLaunchKernelGGL(k_link6d<false>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx,
+                                    cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals,
+                                    cl.hmask, b, gb, ell2, parent));
     VR_LAUNCH_CHECK(ctx);
     rc = fill_i32(ctx, mn, 0x7FFFFFFF, np, st);
     if (rc) return rc;

@@ -19,7 +19,19 @@ struct vr_buf {
     size_t bytes = 0;
 };
 
+struct vr_timer {
+    std::string name;
+    std::vector<hipEvent_t> pending;  // start/stop pairs not yet read
+    std::vector<double> pending_work;
+    int64_t launches = 0;
+    double ms = 0.0;
+    double work = 0.0;
+};
+
 struct vr_ctx {
+    int timing = 0;
+    std::vector<vr_timer> timers;
+    std::vector<hipEvent_t> event_pool;
     int device = 0;
     int num_cus = 256;
     size_t max_ws = 0;      // 0 = no cap
@@ -73,6 +85,27 @@ inline unsigned grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : g);
 }
+
+// Kernel timing (measurement support).  When ctx->timing is set, launches
+// wrapped in VR_TIMED are bracketed by events on their stream and their
+// durations and algorithmic work are accumulated under `name`.
+hipEvent_t timer_event(vr_ctx* ctx);
+void timer_push(vr_ctx* ctx, const char* name, hipEvent_t e0, hipEvent_t e1, double work);
+
+#define VR_TIMED(ctx, name, st, work, ...)                                   \
+    do {                                                                     \
+        hipEvent_t e0_ = nullptr, e1_ = nullptr;                             \
+        if ((ctx)->timing) {                                                 \
+            e0_ = ::vr::timer_event(ctx);                                    \
+            (void)hipEventRecord(e0_, st);                                   \
+        }                                                                    \
+        __VA_ARGS__;                                                         \
+        if ((ctx)->timing) {                                                 \
+            e1_ = ::vr::timer_event(ctx);                                    \
+            (void)hipEventRecord(e1_, st);                                   \
+            ::vr::timer_push(ctx, name, e0_, e1_, (double)(work));           \
+        }                                                                    \
+    } while (0)
 
 // Host-side validation shared by the entry points.
 int check_particles(vr_ctx* ctx, const vr_particles* p, bool need_vel);

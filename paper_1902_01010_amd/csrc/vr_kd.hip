@@ -88,7 +88,7 @@ __global__ void k_kd_init(int n_hosts, const int32_t* __restrict__ off, const in
 
 __global__ __launch_bounds__(KB) void k_kd_roots(const int32_t* __restrict__ off, const int* __restrict__ ncell,
                                                  Elems A, KdNode* nodes, int* active, int* n_active, int* leaves,
-                                                 int* n_leaves) {
+                                                 int* n_leaves, int* active_members) {
     __shared__ int smn[3][4], smx[3][4];
     __shared__ int s_mn[3], s_mx[3];
     const int h = blockIdx.x;
@@ -103,16 +103,21 @@ __global__ __launch_bounds__(KB) void k_kd_roots(const int32_t* __restrict__ off
         }
         nd.dim = -1; nd.t = 0; nd.left = nd.right = -1;
         nodes[h] = nd;
-        if (e - s > ncell[h]) active[atomicAdd(n_active, 1)] = h;
-        else leaves[atomicAdd(n_leaves, 1)] = h;
+        if (e - s > ncell[h]) {
+            active[atomicAdd(n_active, 1)] = h;
+            atomicAdd(active_members, e - s);
+        } else {
+            leaves[atomicAdd(n_leaves, 1)] = h;
+        }
     }
 }
 
 __global__ __launch_bounds__(KB) void k_kd_level(KdNode* __restrict__ nodes, const int* __restrict__ active,
                                                  int* __restrict__ next_active, int* __restrict__ n_next,
                                                  int* __restrict__ leaves, int* __restrict__ n_leaves,
-                                                 int* __restrict__ n_nodes, Elems A, Elems B,
-                                                 const int* __restrict__ ncell, int nb, int mode, int use_mass) {
+                                                 int* __restrict__ n_nodes, int* __restrict__ next_members, Elems A,
+                                                 Elems B, const int* __restrict__ ncell, int nb, int mode,
+                                                 int use_mass) {
     __shared__ int smn[3][4], smx[3][4];
     __shared__ double hist[3][64];
     __shared__ uint32_t sel[2048];
@@ -257,8 +262,12 @@ __global__ __launch_bounds__(KB) void k_kd_level(KdNode* __restrict__ nodes, con
         nodes[id].left = c0;
         nodes[id].right = c0 + 1;
         const int nc = ncell[nd.host];
-        if (nl > nc) next_active[atomicAdd(n_next, 1)] = c0; else leaves[atomicAdd(n_leaves, 1)] = c0;
-        if (n - nl > nc) next_active[atomicAdd(n_next, 1)] = c0 + 1; else leaves[atomicAdd(n_leaves, 1)] = c0 + 1;
+        int grow = 0;
+        if (nl > nc) { next_active[atomicAdd(n_next, 1)] = c0; grow += nl; }
+        else leaves[atomicAdd(n_leaves, 1)] = c0;
+        if (n - nl > nc) { next_active[atomicAdd(n_next, 1)] = c0 + 1; grow += n - nl; }
+        else leaves[atomicAdd(n_leaves, 1)] = c0 + 1;
+        if (grow) atomicAdd(next_members, grow);  // members the next level will visit
     }
 }
 
@@ -330,31 +339,38 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     VR_WS(act1, ctx, int, WS_A7, node_cap);
     VR_WS(leaves, ctx, int, WS_A8, node_cap);
     VR_WS(ncell_d, ctx, int, WS_B5, n_hosts);
-    VR_WS(counters, ctx, int, WS_FLAG, 8);  // 0: active now, 1: next level, 2: leaves, 3: nodes
+    // counters: 0 active nodes now, 1 active next, 2 leaves, 3 nodes, 4 members now, 5 members next
+    VR_WS(counters, ctx, int, WS_FLAG, 8);
     VR_HIP(ctx, hipMemcpyAsync(ncell_d, ncell.data(), n_hosts * sizeof(int), hipMemcpyHostToDevice, st));
     int* init_counts = reinterpret_cast<int*>(ctx->pinned);
-    init_counts[0] = 0; init_counts[1] = 0; init_counts[2] = 0; init_counts[3] = n_hosts;
-    VR_HIP(ctx, hipMemcpyAsync(counters, init_counts, 4 * sizeof(int), hipMemcpyHostToDevice, st));
+    for (int k = 0; k < 8; ++k) init_counts[k] = 0;
+    init_counts[3] = n_hosts;
+    VR_HIP(ctx, hipMemcpyAsync(counters, init_counts, 8 * sizeof(int), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_kd_init, dim3(n_hosts), dim3(256), 0, st, n_hosts, host_offsets, host_members, p->qx, p->qy,
                        p->qz, p->mass, p->grid_bits, A);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_kd_roots, dim3(n_hosts), dim3(KB), 0, st, host_offsets, ncell_d, A, nodes, act0, counters + 0,
-                       leaves, counters + 2);
+                       leaves, counters + 2, counters + 4);
     VR_LAUNCH_CHECK(ctx);
     int* cur = act0;
     int* nxt = act1;
     for (int level = 0;; ++level) {
-        int na = 0;
-        int rc = read_back(ctx, counters + 0, &na, sizeof na, st);
+        int cnt[8];
+        int rc = read_back(ctx, counters, cnt, sizeof cnt, st);
         if (rc) return rc;
+        const int na = cnt[0];
         if (na == 0) break;
         if (level >= 64) return set_err(ctx, VR_ERR_NOT_CONVERGED, "KD build exceeded 64 levels");
         rc = fill_i32(ctx, counters + 1, 0, 1, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_kd_level, dim3(na), dim3(KB), 0, st, nodes, cur, nxt, counters + 1, leaves, counters + 2,
-                           counters + 3, A, B, ncell_d, nbins, mode, use_mass);
+        rc = fill_i32(ctx, counters + 5, 0, 1, st);
+        if (rc) return rc;
+        VR_TIMED(ctx, "kd_level", st, cnt[4],
+                 hipLaunchKernelGGL(k_kd_level, dim3(na), dim3(KB), 0, st, nodes, cur, nxt, counters + 1, leaves,
+                                    counters + 2, counters + 3, counters + 5, A, B, ncell_d, nbins, mode, use_mass));
         VR_LAUNCH_CHECK(ctx);
         VR_HIP(ctx, hipMemcpyAsync(counters + 0, counters + 1, sizeof(int), hipMemcpyDeviceToDevice, st));
+        VR_HIP(ctx, hipMemcpyAsync(counters + 4, counters + 5, sizeof(int), hipMemcpyDeviceToDevice, st));
         std::swap(cur, nxt);
     }
     int nleaf = 0;

@@ -238,9 +238,10 @@ template <int NSE, int NV>
 int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx, const float* Vy,
                const float* Vz, const int* elem_host, const int32_t* host_off, const vr_particles* p, const float* vbar,
                const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
-    hipLaunchKernelGGL((k_knn<NSE, NV>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes, tree.F, Vx,
-                       Vy, Vz, elem_host, host_off, vbar, sigma, p->n, n_se, n_v, tree.use_mass, p->mass_value,
-                       p->grid_bits, R);
+    VR_TIMED(ctx, "knn", st, nq,
+             hipLaunchKernelGGL((k_knn<NSE, NV>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
+                                tree.F, Vx, Vy, Vz, elem_host, host_off, vbar, sigma, p->n, n_se, n_v, tree.use_mass,
+                                p->mass_value, p->grid_bits, R));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }

@@ -206,8 +206,9 @@ int sort_pairs_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, h
         VR_LAUNCH_CHECK(ctx);
         int rc = scan_u32(ctx, hist, hist, (int64_t)RS_RADIX * num_tiles, nullptr, s);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(num_tiles), dim3(RS_BLOCK), 0, s, k0, v0, k1, v1, n,
-                           shift, hist, num_tiles);
+        VR_TIMED(ctx, "radix_scatter", s, n,
+                 hipLaunchKernelGGL(k_radix_scatter<K>, dim3(num_tiles), dim3(RS_BLOCK), 0, s, k0, v0, k1, v1, n,
+                                    shift, hist, num_tiles));
         VR_LAUNCH_CHECK(ctx);
         std::swap(k0, k1);
         std::swap(v0, v1);

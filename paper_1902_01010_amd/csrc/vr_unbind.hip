@@ -406,10 +406,13 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
         VR_HIP(ctx, hipStreamSynchronize(st));
         hact.clear();
         items.clear();
+        double pairs = 0.0, nmem = 0.0;
         for (int g = 0; g < n_groups; ++g) {
             if (hstate[g] != ST_ACTIVE) continue;
             hact.push_back(g);
             const int n = hcnt[g];
+            pairs += (double)n * (double)(n - 1);
+            nmem += n;
             const int jchunk = 4096;
             for (int i0 = 0; i0 < n; i0 += UB)
                 for (int j0 = 0; j0 < n; j0 += jchunk) items.push_back(make_int4(g, i0, j0, std::min(n, j0 + jchunk)));
@@ -427,15 +430,18 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
         VR_LAUNCH_CHECK(ctx);
         const size_t lds = (size_t)tile * sizeof(float4);
         if (uniform)
-            hipLaunchKernelGGL(k_ub_potential<true>, dim3((unsigned)ni), dim3(UB), lds, st, items_d, offsets, cnt, W,
-                               eps2f, acc, tile);
+            VR_TIMED(ctx, "unbind_potential", st, pairs,
+                     hipLaunchKernelGGL(k_ub_potential<true>, dim3((unsigned)ni), dim3(UB), lds, st, items_d, offsets,
+                                        cnt, W, eps2f, acc, tile));
         else
-            hipLaunchKernelGGL(k_ub_potential<false>, dim3((unsigned)ni), dim3(UB), lds, st, items_d, offsets, cnt, W,
-                               eps2f, acc, tile);
+            VR_TIMED(ctx, "unbind_potential", st, pairs,
+                     hipLaunchKernelGGL(k_ub_potential<false>, dim3((unsigned)ni), dim3(UB), lds, st, items_d, offsets,
+                                        cnt, W, eps2f, acc, tile));
         VR_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_ub_group, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, acc, eps2g, scale,
-                           p->mass_value, up->beta_E, up->frac_ref, up->n_min, up->n_ref_min, up->frame_type,
-                           p->grid_bits, bound, phi, ovf);
+        VR_TIMED(ctx, "unbind_group", st, nmem,
+                 hipLaunchKernelGGL(k_ub_group, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, acc,
+                                    eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min, up->n_ref_min,
+                                    up->frame_type, p->grid_bits, bound, phi, ovf));
         VR_LAUNCH_CHECK(ctx);
     }
     return VR_OK;

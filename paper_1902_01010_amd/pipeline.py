@@ -1,0 +1,91 @@
+"""The hot path end to end on the GPU: quantise -> 3D FOF -> groups -> KD
+cells and moments -> R -> host velocity linking lengths -> 6D FOF over the
+outliers -> candidate groups -> unbinding.  Every step is a libvr call;
+this module only chains them and selects the searched hosts.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import vr as _vr
+
+KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group")
+
+
+@dataclasses.dataclass
+class Params:
+    ellx: float
+    n_se: int = 32
+    n_v: int = 8
+    R_threshold: float = 2.0
+    alpha_v: float = 1.25
+    alpha_xs: float = 0.5
+    eps: float = 0.0
+    G: float = 4.30091e-9
+    beta_E: float = 0.95
+    n_min: int = 20
+    host_min: int = 256
+
+    @classmethod
+    def from_workload(cls, w):
+        keys = {f.name for f in dataclasses.fields(cls)}
+        return cls(**{k: v for k, v in w.params.items() if k in keys})
+
+
+def device_inputs(w, device="cuda"):
+    x = torch.from_numpy(np.ascontiguousarray(w.x)).to(device)
+    v = torch.from_numpy(np.ascontiguousarray(w.v)).to(device)
+    m = None if w.mass is None else torch.from_numpy(np.ascontiguousarray(w.mass)).to(device)
+    return x, v, m
+
+
+def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, stage_events=False):
+    """One pass of the hot path over device-resident inputs.  Returns the
+    outputs (device tensors) and counts."""
+    ev = []
+
+    def mark(name):
+        if stage_events:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            ev.append((name, e))
+
+    mark("start")
+    q = ctx.quantize(x, box, grid_bits)
+    P = _vr.Particles(q, v, mass, mass_value, box, grid_bits)
+    mark("quantize")
+    label = ctx.fof3d(P, prm.ellx)
+    mark("fof3d")
+    ng, group_of, offsets, members = ctx.groups(label, prm.n_min)
+    sizes = np.diff(offsets.cpu().numpy())
+    n_hosts = int((sizes >= prm.host_min).sum())
+    host_offsets = offsets[:n_hosts + 1]
+    mark("groups")
+    out = dict(q=q, label=label, n_groups=ng, group_of=group_of, offsets=offsets, members=members,
+               n_hosts=n_hosts, n_searched=int(sizes[:n_hosts].sum()))
+    if n_hosts == 0:
+        out["R"] = torch.full((P.n,), float("nan"), device=x.device)
+        return out, ev
+    cm = ctx.cell_moments(P, host_offsets, members, want_table=False)
+    mark("cells")
+    R = ctx.local_vdensity(P, host_offsets, members, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)
+    mark("R")
+    ellv = ctx.host_ellv(P, host_offsets, members, prm.alpha_v)
+    label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
+    mark("fof6d")
+    nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
+    mark("subgroups")
+    ub = ctx.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc > 0 else None
+    mark("unbind")
+    out.update(cells=cm, R=R, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
+               sub_members=sub_mem, unbind=ub)
+    return out, ev
+
+
+def stage_times(ev):
+    """Milliseconds between consecutive stage markers."""
+    torch.cuda.synchronize()
+    return {ev[k][0]: ev[k - 1][1].elapsed_time(ev[k][1]) for k in range(1, len(ev))}

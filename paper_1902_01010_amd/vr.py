@@ -21,6 +21,7 @@ CELL_COLS = 28
 # Entry points declared in include/vr.h (checked by the CPU test-suite).
 ENTRY_POINTS = (
     "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
+    "vr_set_timing", "vr_kernel_time",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
     "vr_host_ellv", "vr_fof6d", "vr_unbind",
 )
@@ -72,6 +73,8 @@ def load_library():
         L.vr_sync.argtypes = [vp, vp]
         L.vr_workspace_bytes.argtypes = [vp]
         L.vr_workspace_bytes.restype = sz
+        L.vr_set_timing.argtypes = [vp, C.c_int]
+        L.vr_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]
         L.vr_quantize.argtypes = [vp, i64, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
         L.vr_fof3d.argtypes = [vp, P, dbl, vp, vp]
         L.vr_groups.argtypes = [vp, i64, vp, i32, C.POINTER(i32), vp, vp, vp, vp]
@@ -167,6 +170,17 @@ class Context:
 
     def workspace_bytes(self):
         return int(self.lib.vr_workspace_bytes(self.h))
+
+    def set_timing(self, enabled: bool):
+        self._check(self.lib.vr_set_timing(self.h, 1 if enabled else 0))
+
+    def kernel_time(self, name: str):
+        """(launches, total ms, algorithmic work units) accumulated for a kernel."""
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        work = C.c_double(0.0)
+        self._check(self.lib.vr_kernel_time(self.h, name.encode(), C.byref(n), C.byref(ms), C.byref(work)))
+        return n.value, ms.value, work.value
 
     # -- entry points -------------------------------------------------------
     def quantize(self, x, box, grid_bits=21):
