@@ -45,13 +45,13 @@ __device__ __forceinline__ void block_sum_d(double (&v)[N], double* sm /* >= 4*N
 
 __device__ __forceinline__ int floor_half(int a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
 
-__global__ void k_leaf_keys(int nleaf, const int* __restrict__ leaves, const KdNode* __restrict__ nodes, Elems src,
-                            uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+__global__ void k_leaf_keys(int nleaf, const int* __restrict__ leaves, const KdNode* __restrict__ nodes,
+                            const int* __restrict__ leaf_min, uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
-    const KdNode nd = nodes[leaves[i]];
-    key[i] = ((uint64_t)nd.host << 32) | (uint32_t)src.gidx[nd.start];
-    val[i] = (uint32_t)leaves[i];
+    const int id = leaves[i];
+    key[i] = ((uint64_t)nodes[id].host << 32) | (uint32_t)leaf_min[id];
+    val[i] = (uint32_t)id;
 }
 
 __global__ void k_leaf_cell(int nleaf, const uint32_t* __restrict__ sorted_node, int* __restrict__ leaf_cell) {
@@ -243,13 +243,14 @@ extern "C" int vr_cell_moments(vr_ctx* ctx, const vr_particles* p, int32_t n_hos
     *n_cells = nleaf;
     if (cell_table && cell_capacity < nleaf)
         return set_err(ctx, VR_ERR_INVALID_ARG, "cell_capacity %lld < %d cells", (long long)cell_capacity, nleaf);
+    // node ids are below 2 * leaves: every split adds two nodes
     VR_WS(leaf_cell, ctx, int, WS_A9, (int64_t)tree.n_leaves * 2 + 2 * n_hosts + 8);
     VR_WS(lkey, ctx, uint64_t, WS_B6, nleaf);
     VR_WS(lval, ctx, uint32_t, WS_B7, nleaf);
     VR_WS(table, ctx, double, WS_B8, (int64_t)nleaf * VR_CELL_COLS);
     KdNode* nodes = tree.nodes;
-    hipLaunchKernelGGL(k_leaf_keys, dim3(grid_for(nleaf, 256)), dim3(256), 0, st, nleaf, tree.leaves, nodes, tree.F,
-                       lkey, lval);
+    hipLaunchKernelGGL(k_leaf_keys, dim3(grid_for(nleaf, 256)), dim3(256), 0, st, nleaf, tree.leaves, nodes,
+                       tree.leaf_min, lkey, lval);
     VR_LAUNCH_CHECK(ctx);
     int hb = 1;
     while ((1 << hb) <= n_hosts) ++hb;

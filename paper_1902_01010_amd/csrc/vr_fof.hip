@@ -137,8 +137,8 @@ __global__ void k_compress(int64_t n, int* parent) {
 __global__ void k_min_orig(int64_t n, const int* __restrict__ parent, const uint32_t* __restrict__ idx,
                            int* __restrict__ mn) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    atomicMin(&mn[parent[p]], (int)idx[p]);
+    const bool valid = p < n;
+    wave_atomic_min(mn, valid ? parent[p] : 0, valid ? (int)idx[p] : 0x7FFFFFFF, valid);
 }
 
 __global__ void k_write_label(int64_t n, const int* __restrict__ parent, const uint32_t* __restrict__ idx,
@@ -149,56 +149,76 @@ __global__ void k_write_label(int64_t n, const int* __restrict__ parent, const u
 }
 
 // ---- groups -----------------------------------------------------------------
-__global__ void k_count_labels(int64_t n, const int32_t* __restrict__ label, uint32_t* __restrict__ cnt) {
+// Labels are sorted with their particle indices (stable, so members of one
+// label stay in index order); label runs become segments, kept segments are
+// ordered by (size desc, label asc) and scattered into the member table.
+__global__ void k_label_keys(int64_t n, const int32_t* __restrict__ label, uint32_t* __restrict__ key,
+                             uint32_t* __restrict__ val) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int l = label[i];
-    if (l >= 0 && l < n) atomicAdd(&cnt[l], 1u);
+    const int l = label[i];
+    key[i] = (l >= 0 && l < n) ? (uint32_t)l : (uint32_t)n;  // no label: after every label
+    val[i] = (uint32_t)i;
 }
 
-__global__ void k_root_flags(int64_t n, const int32_t* __restrict__ label, const uint32_t* __restrict__ cnt,
-                             int32_t n_min, uint32_t* __restrict__ flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    flag[i] = (label[i] == (int32_t)i && cnt[i] >= (uint32_t)n_min) ? 1u : 0u;
+__global__ void k_run_flags(int64_t n, const uint32_t* __restrict__ key, uint32_t* __restrict__ flag) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
 }
 
-__global__ void k_root_keys(int64_t n, const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
-                            const uint32_t* __restrict__ cnt, uint32_t* __restrict__ key, uint32_t* __restrict__ root) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !flag[i]) return;
-    uint32_t g = pos[i];
-    key[g] = (uint32_t)n - cnt[i];  // ascending key = descending size
-    root[g] = (uint32_t)i;
+__global__ void k_run_starts(int64_t n, const uint32_t* __restrict__ key, const uint32_t* __restrict__ scan,
+                             uint32_t* __restrict__ run_start) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const bool start = (p == 0 || key[p] != key[p - 1]);
+    if (start) run_start[scan[p]] = (uint32_t)p;
+    if (p == n - 1) run_start[start ? scan[p] + 1 : scan[p]] = (uint32_t)n;
 }
 
-__global__ void k_group_ids(int64_t ng, const uint32_t* __restrict__ root, const uint32_t* __restrict__ cnt,
-                            int32_t* __restrict__ gid, uint32_t* __restrict__ gsize) {
+__global__ void k_run_keep(int64_t nrun, int64_t n, const uint32_t* __restrict__ key,
+                           const uint32_t* __restrict__ run_start, int32_t n_min, uint32_t* __restrict__ keep) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nrun) return;
+    const uint32_t a = run_start[s], b = run_start[s + 1];
+    keep[s] = (key[a] < (uint32_t)n && b - a >= (uint32_t)n_min) ? 1u : 0u;
+}
+
+__global__ void k_run_compact(int64_t nrun, int64_t n, const uint32_t* __restrict__ keep,
+                              const uint32_t* __restrict__ pos, const uint32_t* __restrict__ run_start,
+                              uint32_t* __restrict__ gkey, uint32_t* __restrict__ grun, int32_t* __restrict__ run_group) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nrun) return;
+    run_group[s] = -1;
+    if (!keep[s]) return;
+    const uint32_t g = pos[s];
+    gkey[g] = (uint32_t)n - (run_start[s + 1] - run_start[s]);  // ascending key = descending size
+    grun[g] = (uint32_t)s;
+}
+
+__global__ void k_group_sizes(int64_t ng, const uint32_t* __restrict__ grun, const uint32_t* __restrict__ run_start,
+                              uint32_t* __restrict__ gsize, int32_t* __restrict__ run_group) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
-    gid[root[g]] = (int32_t)g;
-    gsize[g] = cnt[root[g]];
+    if (g > ng) return;
+    if (g == ng) { gsize[g] = 0; return; }
+    const uint32_t s = grun[g];
+    gsize[g] = run_start[s + 1] - run_start[s];
+    run_group[s] = (int32_t)g;
 }
 
-__global__ void k_group_of(int64_t n, const int32_t* __restrict__ label, const int32_t* __restrict__ gid,
-                           int32_t* __restrict__ group_of, uint32_t* __restrict__ flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int l = label[i];
-    int g = (l >= 0 && l < n) ? gid[l] : -1;
+__global__ void k_group_scatter(int64_t n, const uint32_t* __restrict__ runid, const uint32_t* __restrict__ run_start,
+                                const int32_t* __restrict__ run_group, const uint32_t* __restrict__ goff,
+                                const uint32_t* __restrict__ val, int32_t* __restrict__ group_of,
+                                int32_t* __restrict__ members) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    // runid holds the exclusive scan of run starts: the run of p is the
+    // number of starts up to and including p, minus one
+    const uint32_t s0 = runid[p];
+    const uint32_t s = (run_start[s0] == (uint32_t)p) ? s0 : s0 - 1;
+    const int g = run_group[s];
+    const uint32_t i = val[p];
     group_of[i] = g;
-    flag[i] = g >= 0 ? 1u : 0u;
-}
-
-__global__ void k_member_keys(int64_t n, const int32_t* __restrict__ group_of, const uint32_t* __restrict__ pos,
-                              uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int g = group_of[i];
-    if (g < 0) return;
-    uint32_t j = pos[i];
-    key[j] = (uint32_t)g;
-    val[j] = (uint32_t)i;
+    if (g >= 0) members[goff[g] + ((uint32_t)p - run_start[s])] = (int32_t)i;
 }
 
 __global__ void k_u32_to_i32(int64_t n, const uint32_t* __restrict__ a, int32_t* __restrict__ b) {
@@ -336,61 +356,56 @@ extern "C" int vr_groups(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t n
     VR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     if (n == 0) return VR_OK;
-    VR_WS(cnt, ctx, uint32_t, WS_B2, n);
-    VR_WS(flag, ctx, uint32_t, WS_B3, n);
-    VR_WS(pos, ctx, uint32_t, WS_B4, n);
-    VR_WS(gid, ctx, int32_t, WS_B5, n);
+    VR_WS(key, ctx, uint32_t, WS_B2, n);
+    VR_WS(val, ctx, uint32_t, WS_B3, n);
+    VR_WS(runid, ctx, uint32_t, WS_B4, n);
+    VR_WS(run_start, ctx, uint32_t, WS_B5, n + 1);
+    VR_WS(keep, ctx, uint32_t, WS_B6, n);
+    VR_WS(kpos, ctx, uint32_t, WS_B7, n);
+    VR_WS(run_group, ctx, int32_t, WS_B8, n);
     VR_WS(tot, ctx, uint32_t, WS_FLAG, 4);
-    int rc = fill_u32(ctx, cnt, 0u, n, st);
+    hipLaunchKernelGGL(k_label_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, key, val);
+    VR_LAUNCH_CHECK(ctx);
+    int rc = sort_pairs_u32(ctx, key, val, n, bits_for((uint64_t)n), st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_count_labels, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, cnt);
+    hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, runid);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_root_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, cnt, n_min, flag);
+    rc = scan_u32(ctx, runid, runid, n, tot, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_run_starts, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, runid, run_start);
     VR_LAUNCH_CHECK(ctx);
-    rc = scan_u32(ctx, flag, pos, n, tot, st);
+    uint32_t nrun = 0;
+    rc = read_back(ctx, tot, &nrun, sizeof nrun, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_run_keep, dim3(grid_for(nrun, 256)), dim3(256), 0, st, (int64_t)nrun, n, key, run_start,
+                       n_min, keep);
+    VR_LAUNCH_CHECK(ctx);
+    rc = scan_u32(ctx, keep, kpos, nrun, tot, st);
     if (rc) return rc;
     uint32_t ng = 0;
     rc = read_back(ctx, tot, &ng, sizeof ng, st);
     if (rc) return rc;
     *n_groups = (int32_t)ng;
-    rc = fill_i32(ctx, gid, -1, n, st);
-    if (rc) return rc;
-    if (ng > 0) {
-        VR_WS(rkey, ctx, uint32_t, WS_B6, ng);
-        VR_WS(root, ctx, uint32_t, WS_B7, ng);
-        VR_WS(gsize, ctx, uint32_t, WS_B8, ng + 1);
-        hipLaunchKernelGGL(k_root_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, n, flag, pos, cnt, rkey, root);
-        VR_LAUNCH_CHECK(ctx);
-        rc = sort_pairs_u32(ctx, rkey, root, ng, bits_for((uint64_t)n), st);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_group_ids, dim3(grid_for(ng, 256)), dim3(256), 0, st, (int64_t)ng, root, cnt, gid,
-                           gsize);
-        VR_LAUNCH_CHECK(ctx);
-        rc = fill_u32(ctx, gsize + ng, 0u, 1, st);
-        if (rc) return rc;
-        rc = scan_u32(ctx, gsize, gsize, (int64_t)ng + 1, nullptr, st);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_u32_to_i32, dim3(grid_for(ng + 1, 256)), dim3(256), 0, st, (int64_t)ng + 1, gsize,
-                           offsets);
-        VR_LAUNCH_CHECK(ctx);
-    } else {
-        rc = fill_i32(ctx, offsets, 0, 1, st);
-        if (rc) return rc;
-    }
-    hipLaunchKernelGGL(k_group_of, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, gid, group_of, flag);
+    VR_WS(gkey, ctx, uint32_t, WS_B9, ng + 1);
+    VR_WS(grun, ctx, uint32_t, WS_C0, ng + 1);
+    VR_WS(gsize, ctx, uint32_t, WS_C1, ng + 1);
+    hipLaunchKernelGGL(k_run_compact, dim3(grid_for(nrun, 256)), dim3(256), 0, st, (int64_t)nrun, n, keep, kpos,
+                       run_start, gkey, grun, run_group);
     VR_LAUNCH_CHECK(ctx);
-    rc = scan_u32(ctx, flag, pos, n, tot, st);
-    if (rc) return rc;
-    uint32_t nm = 0;
-    rc = read_back(ctx, tot, &nm, sizeof nm, st);
-    if (rc) return rc;
-    if (nm > 0) {
-        VR_WS(mkey, ctx, uint32_t, WS_B9, nm);
-        uint32_t* mval = reinterpret_cast<uint32_t*>(members);
-        hipLaunchKernelGGL(k_member_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, n, group_of, pos, mkey, mval);
-        VR_LAUNCH_CHECK(ctx);
-        rc = sort_pairs_u32(ctx, mkey, mval, nm, bits_for((uint64_t)ng), st);
+    if (ng > 0) {
+        rc = sort_pairs_u32(ctx, gkey, grun, ng, bits_for((uint64_t)n), st);
         if (rc) return rc;
     }
+    hipLaunchKernelGGL(k_group_sizes, dim3(grid_for((int64_t)ng + 1, 256)), dim3(256), 0, st, (int64_t)ng, grun,
+                       run_start, gsize, run_group);
+    VR_LAUNCH_CHECK(ctx);
+    rc = scan_u32(ctx, gsize, gsize, (int64_t)ng + 1, nullptr, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_u32_to_i32, dim3(grid_for((int64_t)ng + 1, 256)), dim3(256), 0, st, (int64_t)ng + 1, gsize,
+                       offsets);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_group_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, n, runid, run_start, run_group,
+                       gsize, val, group_of, members);
+    VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }

@@ -51,6 +51,24 @@ __device__ __forceinline__ void uf_union(int* parent, int a, int b) {
 }
 
 
+// atomicMin(&base[key], val) for every valid lane.  When all valid lanes of
+// the wavefront share one key (a dense component), the wave reduces first and
+// issues a single atomic, which removes the contention on big components.
+__device__ __forceinline__ void wave_atomic_min(int* base, int key, int val, bool valid) {
+    const uint64_t act = __ballot(valid);
+    if (act == 0) return;
+    const int first = __ffsll((unsigned long long)act) - 1;
+    const int k0 = __shfl(key, first, 64);
+    if (__ballot(valid && key == k0) == act) {
+        int v = valid ? val : 0x7FFFFFFF;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+        if ((int)__lane_id() == first) atomicMin(&base[k0], v);
+    } else if (valid) {
+        atomicMin(&base[key], val);
+    }
+}
+
 // Cell list of a point set on the periodic grid: sorted keys, sorted
 // original indices, sorted coordinates, cell starts and an open-addressing
 // hash from occupied cell keys to cell numbers.

@@ -54,8 +54,21 @@ enum Slot {
     WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7, WS_B8, WS_B9,
     WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8, WS_C9,
     WS_D0, WS_D1, WS_D2, WS_D3, WS_D4, WS_D5, WS_D6, WS_D7, WS_D8, WS_D9,
-    WS_FLAG, WS_FLAG2,
+    WS_FLAG, WS_FLAG2, WS_KD, WS_KD_HIST,
     WS_NSLOTS
+};
+
+// Carves aligned sub-arrays out of one workspace slot: call add() for every
+// array (first pass sizes, second pass assigns), then alloc().
+struct Carve {
+    size_t bytes = 0;
+    char* base = nullptr;
+    template <class T>
+    T* add(size_t count) {
+        size_t off = bytes;
+        bytes += (count * sizeof(T) + 255) & ~size_t(255);
+        return base ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
 };
 
 int set_err(vr_ctx* ctx, int code, const char* fmt, ...);

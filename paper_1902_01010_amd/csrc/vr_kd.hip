@@ -1,12 +1,17 @@
-// vr_kd.hip -- level-synchronous KD trees over the members of many hosts.
+// vr_kd.hip -- level-synchronous KD trees over the members of many hosts,
+// built from presorted lists.
 //
-// Each active node is one workgroup: it reduces the members' bounding box,
-// chooses the split dimension (normalised Shannon entropy of the binned
-// member masses, Sec. 2.2, or the widest extent for the neighbour-search
-// tree), finds the member of rank floor(n/2) in (coordinate, index) order with
-// a two-pass 11-bit radix select, and writes a stable partition into the other
-// element buffer.  Node segments therefore stay in ascending particle-index
-// order, which makes every split exactly reproducible.
+// For each dimension d the members are sorted once by (host, u_d, index)
+// with the device radix sort.  Every node then owns the same position range
+// in the three lists, and the list of dimension d holds its members in
+// (u_d, index) order, so the member of rank floor(n/2) -- the split point --
+// and the bounding box are read off directly.  One level costs a handful of
+// element-parallel passes for all nodes of all hosts at once: entropy
+// histograms (cells tree), the split decision per node, a left/right flag
+// per member, and a stable partition of each list by a global prefix sum
+// (subtracting the prefix at the segment start makes it segmented).  No
+// node is ever handled by a single workgroup, so the few huge top-level
+// nodes cost no more per member than the many small ones.
 #include "vr_kd.h"
 
 #include <climits>
@@ -16,284 +21,298 @@ namespace vr {
 namespace {
 
 constexpr int KB = 256;
+constexpr int HCH = 2048;  // positions per histogram block
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u(uint32_t v) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
+// Element arrays by element id, and the sort keys of the presort.
+__global__ void k_elems(int64_t M, int n_hosts, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
+                        const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
+                        const uint32_t* __restrict__ qz, const float* __restrict__ mass, int gb, int* __restrict__ u0,
+                        int* __restrict__ u1, int* __restrict__ u2, int* __restrict__ g, float* __restrict__ m,
+                        int* __restrict__ host) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M) return;
+    int lo = 0, hi = n_hosts - 1;  // host with off[h] <= e < off[h+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    return v;
-}
-
-__device__ __forceinline__ uint32_t block_excl_scan_u(uint32_t v, uint32_t* sm, uint32_t* total) {
-    const int lane = __lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint32_t inc = wave_incl_scan_u(v);
-    if (lane == 63) sm[w] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int i = 0; i < nw; ++i) {
-        if (i < w) pre += sm[i];
-        tot += sm[i];
-    }
-    __syncthreads();
-    *total = tot;
-    return pre + inc - v;
-}
-
-// Bounding box of positions [s, e) reduced over the block into smn/smx.
-__device__ void block_bbox(const Elems& src, int s, int e, int* s_mn, int* s_mx, int (*smn)[4], int (*smx)[4]) {
-    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
-    for (int k = s + (int)threadIdx.x; k < e; k += blockDim.x)
-        for (int d = 0; d < 3; ++d) {
-            int u = src.u[d][k];
-            mn[d] = min(mn[d], u);
-            mx[d] = max(mx[d], u);
-        }
-    const int lane = __lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int d = 0; d < 3; ++d) {
-        for (int o = 32; o > 0; o >>= 1) {
-            mn[d] = min(mn[d], __shfl_xor(mn[d], o, 64));
-            mx[d] = max(mx[d], __shfl_xor(mx[d], o, 64));
-        }
-        if (lane == 0) { smn[d][w] = mn[d]; smx[d][w] = mx[d]; }
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        int a = INT_MAX, b = INT_MIN;
-        for (int ww = 0; ww < nw; ++ww) { a = min(a, smn[threadIdx.x][ww]); b = max(b, smx[threadIdx.x][ww]); }
-        s_mn[threadIdx.x] = a;
-        s_mx[threadIdx.x] = b;
-    }
-    __syncthreads();
-}
-
-__global__ void k_kd_init(int n_hosts, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
-                          const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
-                          const uint32_t* __restrict__ qz, const float* __restrict__ mass, int gb, Elems A) {
-    const int h = blockIdx.x;
-    const int s = off[h], e = off[h + 1];
-    const int r = mem[s];
+    const int h = lo;
+    const int r = mem[off[h]];
+    const int i = mem[e];
     const int rx = (int)qx[r], ry = (int)qy[r], rz = (int)qz[r];
-    for (int k = s + threadIdx.x; k < e; k += blockDim.x) {
-        const int i = mem[k];
-        A.u[0][k] = rx + min_image((int)qx[i] - rx, gb);
-        A.u[1][k] = ry + min_image((int)qy[i] - ry, gb);
-        A.u[2][k] = rz + min_image((int)qz[i] - rz, gb);
-        A.gidx[k] = i;
-        if (mass) A.mass[k] = mass[i];
-    }
+    u0[e] = rx + min_image((int)qx[i] - rx, gb);
+    u1[e] = ry + min_image((int)qy[i] - ry, gb);
+    u2[e] = rz + min_image((int)qz[i] - rz, gb);
+    g[e] = i;
+    host[e] = h;
+    if (mass) m[e] = mass[i];
 }
 
-__global__ __launch_bounds__(KB) void k_kd_roots(const int32_t* __restrict__ off, const int* __restrict__ ncell,
-                                                 Elems A, KdNode* nodes, int* active, int* n_active, int* leaves,
-                                                 int* n_leaves, int* active_members) {
-    __shared__ int smn[3][4], smx[3][4];
-    __shared__ int s_mn[3], s_mx[3];
-    const int h = blockIdx.x;
-    const int s = off[h], e = off[h + 1];
-    block_bbox(A, s, e, s_mn, s_mx, smn, smx);
-    if (threadIdx.x == 0) {
-        KdNode nd;
-        nd.host = h; nd.start = s; nd.end = e; nd.buf = 0;
-        for (int d = 0; d < 3; ++d) {
-            nd.lo[d] = nd.bmin[d] = s_mn[d];
-            nd.hi[d] = nd.bmax[d] = s_mx[d];
-        }
-        nd.dim = -1; nd.t = 0; nd.left = nd.right = -1;
-        nodes[h] = nd;
-        if (e - s > ncell[h]) {
-            active[atomicAdd(n_active, 1)] = h;
-            atomicAdd(active_members, e - s);
-        } else {
-            leaves[atomicAdd(n_leaves, 1)] = h;
-        }
-    }
+__global__ void k_presort_keys(int64_t M, const int* __restrict__ u, const int* __restrict__ host,
+                               uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M) return;
+    // unwrapped coordinates lie in [-2^20, 3 * 2^20): 22 bits after the shift
+    key[e] = ((uint64_t)host[e] << 22) | (uint64_t)(uint32_t)(u[e] + (1 << 20));
+    val[e] = (uint32_t)e;
 }
 
-__global__ __launch_bounds__(KB) void k_kd_level(KdNode* __restrict__ nodes, const int* __restrict__ active,
-                                                 int* __restrict__ next_active, int* __restrict__ n_next,
-                                                 int* __restrict__ leaves, int* __restrict__ n_leaves,
-                                                 int* __restrict__ n_nodes, int* __restrict__ next_members, Elems A,
-                                                 Elems B, const int* __restrict__ ncell, int nb, int mode,
-                                                 int use_mass) {
-    __shared__ int smn[3][4], smx[3][4];
-    __shared__ double hist[3][64];
-    __shared__ uint32_t sel[2048];
-    __shared__ uint32_t scan_sm[8];
-    __shared__ int s_best, s_b1, s_below1, s_b2, s_below2;
-    __shared__ int s_mn[3], s_mx[3];
+__global__ void k_roots(int n_hosts, const int32_t* __restrict__ off, const int* __restrict__ ncell, KdNode* nodes,
+                        int* active, int* counters, int* leaves, int* __restrict__ seg_node_unused) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hosts) return;
+    KdNode nd;
+    nd.host = h;
+    nd.start = off[h];
+    nd.end = off[h + 1];
+    nd.slot = -1;
+    nd.dim = -1;
+    nd.t = 0;
+    nd.left = nd.right = -1;
+    for (int d = 0; d < 3; ++d) nd.lo[d] = nd.hi[d] = nd.bmin[d] = nd.bmax[d] = 0;
+    nodes[h] = nd;
+    if (nd.end - nd.start > ncell[h]) {
+        active[atomicAdd(&counters[0], 1)] = h;
+        atomicAdd(&counters[4], nd.end - nd.start);
+    } else {
+        leaves[atomicAdd(&counters[2], 1)] = h;
+    }
+    (void)seg_node_unused;
+}
 
-    const int id = active[blockIdx.x];
-    const KdNode nd = nodes[id];
-    const Elems src = nd.buf ? B : A;
-    const Elems dst = nd.buf ? A : B;
-    const int start = nd.start, end = nd.end, n = end - start;
-    const int tid = threadIdx.x;
+__global__ void k_seg_init(int64_t M, const int* __restrict__ host, int* __restrict__ seg_node) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < M) seg_node[p] = host[p];  // hosts keep their ranges in every list
+}
 
-    if (mode != KD_WIDEST)
-        for (int i = tid; i < 3 * 64; i += blockDim.x) (&hist[0][0])[i] = 0.0;
-    block_bbox(src, start, end, s_mn, s_mx, smn, smx);
-    if (mode != KD_WIDEST) {
-        // mass histograms of the non-degenerate dimensions
-        for (int k = start + tid; k < end; k += blockDim.x) {
-            const double wgt = use_mass ? (double)src.mass[k] : 1.0;
-            for (int d = 0; d < 3; ++d) {
-                if (s_mx[d] == s_mn[d]) continue;
-                const int64_t bin = ((int64_t)(src.u[d][k] - s_mn[d]) * nb) / ((int64_t)s_mx[d] - s_mn[d] + 1);
-                atomicAdd(&hist[d][bin], wgt);
-            }
-        }
+// Bounding box of every active node from the sorted lists; the root region is
+// its bounding box.
+__global__ void k_bbox(int na, const int* __restrict__ active, KdNode* nodes, const int* __restrict__ l0,
+                       const int* __restrict__ l1, const int* __restrict__ l2, const int* __restrict__ u0,
+                       const int* __restrict__ u1, const int* __restrict__ u2, int n_hosts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= na) return;
+    const int id = active[i];
+    KdNode& nd = nodes[id];
+    const int s = nd.start, e = nd.end - 1;
+    nd.bmin[0] = u0[l0[s]]; nd.bmax[0] = u0[l0[e]];
+    nd.bmin[1] = u1[l1[s]]; nd.bmax[1] = u1[l1[e]];
+    nd.bmin[2] = u2[l2[s]]; nd.bmax[2] = u2[l2[e]];
+    nd.slot = i;
+    if (id < n_hosts)
+        for (int d = 0; d < 3; ++d) { nd.lo[d] = nd.bmin[d]; nd.hi[d] = nd.bmax[d]; }
+}
+
+// Mass histograms (counts for uniform mass) of the active nodes, nb bins per
+// dimension spanning the members' extent.  A block whose positions all
+// belong to one node accumulates in LDS first.
+template <bool COUNTS>
+__global__ __launch_bounds__(KB) void k_hist(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
+                                             const int* __restrict__ l0, const int* __restrict__ u0,
+                                             const int* __restrict__ u1, const int* __restrict__ u2,
+                                             const float* __restrict__ mass, int nb, uint32_t* __restrict__ hc,
+                                             double* __restrict__ hm) {
+    __shared__ uint32_t lc[3 * 64];
+    __shared__ double lm[3 * 64];
+    const int64_t p0 = (int64_t)blockIdx.x * HCH;
+    const int64_t p1 = min(p0 + HCH, M);
+    const int first = seg_node[p0], last = seg_node[p1 - 1];
+    const bool one = first == last;
+    if (one) {
+        if (nodes[first].slot < 0 || nodes[first].dim >= 0) return;  // not an active node this level
+        for (int k = threadIdx.x; k < 3 * nb; k += blockDim.x) { if (COUNTS) lc[k] = 0; else lm[k] = 0.0; }
         __syncthreads();
     }
-    if (tid == 0) {
-        int best = -1;
-        if (mode == KD_WIDEST) {
-            for (int d = 0; d < 3; ++d)
-                if (s_mx[d] > s_mn[d] && (best < 0 || s_mx[d] - s_mn[d] > s_mx[best] - s_mn[best])) best = d;
-        } else {
-            double S[3];
-            for (int d = 0; d < 3; ++d) {
-                S[d] = 0.0;
-                if (s_mx[d] == s_mn[d]) continue;
-                double tot = 0.0;
-                for (int k = 0; k < nb; ++k) tot += hist[d][k];
-                double sacc = 0.0;
-                for (int k = 0; k < nb; ++k)
-                    if (hist[d][k] > 0) {
-                        double pk = hist[d][k] / tot;
-                        sacc -= pk * log(pk);
-                    }
-                S[d] = sacc / log((double)nb);
-            }
-            for (int d = 0; d < 3; ++d) {
-                if (s_mx[d] == s_mn[d]) continue;
-                if (best < 0) { best = d; continue; }
-                bool better = mode == KD_MIN_ENTROPY ? (S[d] < S[best] - 1e-12) : (S[d] > S[best] + 1e-12);
-                if (better) best = d;
-            }
-        }
-        s_best = best;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int id = one ? first : seg_node[p];
+        const KdNode& nd = nodes[id];
+        if (nd.slot < 0 || nd.dim >= 0) continue;
+        const int e = l0[p];
+        const int u[3] = {u0[e], u1[e], u2[e]};
+        const double w = COUNTS ? 1.0 : (double)mass[e];
         for (int d = 0; d < 3; ++d) {
-            nodes[id].bmin[d] = s_mn[d];
-            nodes[id].bmax[d] = s_mx[d];
+            if (nd.bmax[d] == nd.bmin[d]) continue;
+            const int bin = (int)(((int64_t)(u[d] - nd.bmin[d]) * nb) / ((int64_t)nd.bmax[d] - nd.bmin[d] + 1));
+            if (one) {
+                if (COUNTS) atomicAdd(&lc[d * nb + bin], 1u); else atomicAdd(&lm[d * nb + bin], w);
+            } else {
+                const int64_t at = ((int64_t)nd.slot * 3 + d) * nb + bin;
+                if (COUNTS) atomicAdd(&hc[at], 1u); else atomicAdd(&hm[at], w);
+            }
         }
     }
-    __syncthreads();
-    const int best = s_best;
-    if (best < 0) {  // all members coincide: the node stays a leaf
-        if (tid == 0) leaves[atomicAdd(n_leaves, 1)] = id;
+    if (one) {
+        __syncthreads();
+        const int slot = nodes[first].slot;
+        for (int k = threadIdx.x; k < 3 * nb; k += blockDim.x) {
+            const int64_t at = (int64_t)slot * 3 * nb + k;
+            if (COUNTS) { if (lc[k]) atomicAdd(&hc[at], lc[k]); }
+            else if (lm[k] != 0.0) atomicAdd(&hm[at], lm[k]);
+        }
+    }
+}
+
+// Split decision of every active node and creation of its children.
+__global__ void k_split(int na, const int* __restrict__ active, KdNode* nodes, const int* __restrict__ l0,
+                        const int* __restrict__ l1, const int* __restrict__ l2, const int* __restrict__ u0,
+                        const int* __restrict__ u1, const int* __restrict__ u2, int mode, int nb, int counts,
+                        const uint32_t* __restrict__ hc, const double* __restrict__ hm, const int* __restrict__ ncell,
+                        int* next_active, int* leaves, int* counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= na) return;
+    const int id = active[i];
+    const KdNode nd = nodes[id];
+    int best = -1;
+    if (mode == KD_WIDEST) {
+        for (int d = 0; d < 3; ++d)
+            if (nd.bmax[d] > nd.bmin[d] && (best < 0 || nd.bmax[d] - nd.bmin[d] > nd.bmax[best] - nd.bmin[best]))
+                best = d;
+    } else {
+        // normalised Shannon entropy of each dimension's mass histogram
+        double S[3];
+        for (int d = 0; d < 3; ++d) {
+            S[d] = 0.0;
+            if (nd.bmax[d] == nd.bmin[d]) continue;
+            const int64_t b0 = ((int64_t)i * 3 + d) * nb;
+            double tot = 0.0;
+            for (int k = 0; k < nb; ++k) tot += counts ? (double)hc[b0 + k] : hm[b0 + k];
+            double sacc = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                const double h = counts ? (double)hc[b0 + k] : hm[b0 + k];
+                if (h > 0) {
+                    const double pk = h / tot;
+                    sacc -= pk * log(pk);
+                }
+            }
+            S[d] = sacc / log((double)nb);
+        }
+        for (int d = 0; d < 3; ++d) {
+            if (nd.bmax[d] == nd.bmin[d]) continue;
+            if (best < 0) { best = d; continue; }
+            const bool better = mode == KD_MIN_ENTROPY ? (S[d] < S[best] - 1e-12) : (S[d] > S[best] + 1e-12);
+            if (better) best = d;
+        }
+    }
+    if (best < 0) {  // every member coincides: the node stays a leaf
+        nodes[id].slot = -1;
+        leaves[atomicAdd(&counters[2], 1)] = id;
         return;
     }
-    const int dmin = s_mn[best];
-    const int nl = n / 2;
-    const int* ub = src.u[best];
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int i = tid; i < 2048; i += blockDim.x) sel[i] = 0;
-        __syncthreads();
-        const int b1 = pass ? s_b1 : 0;
-        for (int k = start + tid; k < end; k += blockDim.x) {
-            const uint32_t v = (uint32_t)(ub[k] - dmin);
-            if (pass == 0) atomicAdd(&sel[v >> 11], 1u);
-            else if ((int)(v >> 11) == b1) atomicAdd(&sel[v & 2047u], 1u);
-        }
-        __syncthreads();
-        const int want = pass ? nl - s_below1 : nl;
-        uint32_t loc = 0;
-        for (int i = 0; i < 8; ++i) loc += sel[tid * 8 + i];
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan_u(loc, scan_sm, &tot);
-        if ((uint32_t)want >= ex && (uint32_t)want < ex + loc) {
-            uint32_t c = ex;
-            for (int i = 0; i < 8; ++i) {
-                const uint32_t h = sel[tid * 8 + i];
-                if ((uint32_t)want < c + h) {
-                    if (pass == 0) { s_b1 = tid * 8 + i; s_below1 = (int)c; }
-                    else { s_b2 = tid * 8 + i; s_below2 = (int)c; }
-                    break;
-                }
-                c += h;
-            }
-        }
-        __syncthreads();
-    }
-    const int t = dmin + ((s_b1 << 11) | s_b2);
-    const int need = nl - (s_below1 + s_below2);  // members equal to t that go left
-    uint32_t carry_l = 0, carry_e = 0, carry_r = 0;
-    for (int base = start; base < end; base += blockDim.x) {
-        const int k = base + tid;
-        const bool valid = k < end;
-        const int v = valid ? ub[k] : 0;
-        const bool is_less = valid && v < t;
-        const bool is_eq = valid && v == t;
-        uint32_t tot_e;
-        const uint32_t eq_before = block_excl_scan_u(is_eq ? 1u : 0u, scan_sm, &tot_e) + carry_e;
-        const bool left = is_less || (is_eq && (int)eq_before < need);
-        const bool right = valid && !left;
-        uint32_t tot_lr;
-        const uint32_t pk = block_excl_scan_u((left ? 1u : 0u) | (right ? (1u << 10) : 0u), scan_sm, &tot_lr);
-        if (valid) {
-            const int pos = left ? start + (int)(carry_l + (pk & 1023u)) : start + nl + (int)(carry_r + (pk >> 10));
-            dst.u[0][pos] = src.u[0][k];
-            dst.u[1][pos] = src.u[1][k];
-            dst.u[2][pos] = src.u[2][k];
-            dst.gidx[pos] = src.gidx[k];
-            if (use_mass) dst.mass[pos] = src.mass[k];
-        }
-        carry_e += tot_e;
-        carry_l += tot_lr & 1023u;
-        carry_r += tot_lr >> 10;
-    }
-    if (tid == 0) {
-        const int c0 = atomicAdd(n_nodes, 2);
-        KdNode L = nd, R = nd;
-        L.buf = R.buf = nd.buf ^ 1;
-        L.end = start + nl;
-        R.start = start + nl;
-        L.hi[best] = t - 1;
-        R.lo[best] = t;
-        L.dim = R.dim = -1;
-        L.left = L.right = R.left = R.right = -1;
-        nodes[c0] = L;
-        nodes[c0 + 1] = R;
-        nodes[id].dim = best;
-        nodes[id].t = t;
-        nodes[id].left = c0;
-        nodes[id].right = c0 + 1;
-        const int nc = ncell[nd.host];
-        int grow = 0;
-        if (nl > nc) { next_active[atomicAdd(n_next, 1)] = c0; grow += nl; }
-        else leaves[atomicAdd(n_leaves, 1)] = c0;
-        if (n - nl > nc) { next_active[atomicAdd(n_next, 1)] = c0 + 1; grow += n - nl; }
-        else leaves[atomicAdd(n_leaves, 1)] = c0 + 1;
-        if (grow) atomicAdd(next_members, grow);  // members the next level will visit
-    }
+    const int n = nd.end - nd.start, nl = n / 2;
+    const int* lb = best == 0 ? l0 : (best == 1 ? l1 : l2);
+    const int* ub = best == 0 ? u0 : (best == 1 ? u1 : u2);
+    const int t = ub[lb[nd.start + nl]];
+    const int c0 = atomicAdd(&counters[3], 2);
+    KdNode L = nd, R = nd;
+    L.end = nd.start + nl;
+    R.start = nd.start + nl;
+    L.hi[best] = t - 1;
+    R.lo[best] = t;
+    L.slot = R.slot = -1;
+    L.dim = R.dim = -1;
+    L.left = L.right = R.left = R.right = -1;
+    nodes[c0] = L;
+    nodes[c0 + 1] = R;
+    nodes[id].dim = best;
+    nodes[id].t = t;
+    nodes[id].left = c0;
+    nodes[id].right = c0 + 1;
+    const int nc = ncell[nd.host];
+    int grow = 0;
+    if (nl > nc) { next_active[atomicAdd(&counters[1], 1)] = c0; grow += nl; }
+    else leaves[atomicAdd(&counters[2], 1)] = c0;
+    if (n - nl > nc) { next_active[atomicAdd(&counters[1], 1)] = c0 + 1; grow += n - nl; }
+    else leaves[atomicAdd(&counters[2], 1)] = c0 + 1;
+    if (grow) atomicAdd(&counters[5], grow);
 }
 
-// Leaves: bounding box of the members, and their segment moved into buffer A.
-__global__ __launch_bounds__(KB) void k_kd_leaves(const int* __restrict__ leaves, KdNode* __restrict__ nodes, Elems A,
-                                                  Elems B, int use_mass) {
-    __shared__ int smn[3][4], smx[3][4];
-    __shared__ int s_mn[3], s_mx[3];
-    const int id = leaves[blockIdx.x];
-    const KdNode nd = nodes[id];
-    if (nd.buf)
-        for (int k = nd.start + threadIdx.x; k < nd.end; k += blockDim.x) {
-            A.u[0][k] = B.u[0][k];
-            A.u[1][k] = B.u[1][k];
-            A.u[2][k] = B.u[2][k];
-            A.gidx[k] = B.gidx[k];
-            if (use_mass) A.mass[k] = B.mass[k];
-        }
-    __syncthreads();
-    block_bbox(A, nd.start, nd.end, s_mn, s_mx, smn, smx);
-    if (threadIdx.x == 0) {
-        for (int d = 0; d < 3; ++d) {
-            nodes[id].bmin[d] = s_mn[d];
-            nodes[id].bmax[d] = s_mx[d];
-        }
-        nodes[id].buf = 0;
+// flag[e] = 1 if element e goes to the left child of its (split) node.
+__global__ void k_flags(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
+                        const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
+                        uint8_t* __restrict__ flag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const KdNode& nd = nodes[seg_node[p]];
+    if (nd.dim < 0) return;
+    const int* l = nd.dim == 0 ? l0 : (nd.dim == 1 ? l1 : l2);
+    flag[l[p]] = (p - nd.start) < (nd.end - nd.start) / 2 ? 1 : 0;
+}
+
+__global__ void k_lflag(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
+                        const int* __restrict__ l, const uint8_t* __restrict__ flag, uint32_t* __restrict__ lf) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    lf[p] = nodes[seg_node[p]].dim >= 0 ? (uint32_t)flag[l[p]] : 0u;
+}
+
+// Stable partition of one list inside every split node.
+__global__ void k_part(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
+                       const int* __restrict__ l, const uint8_t* __restrict__ flag, const uint32_t* __restrict__ scan,
+                       int* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const KdNode& nd = nodes[seg_node[p]];
+    const int e = l[p];
+    if (nd.dim < 0) { out[p] = e; return; }
+    const int s = nd.start, nl = (nd.end - nd.start) / 2;
+    const int rl = (int)(scan[p] - scan[s]);  // left members before p in the node
+    const int np = flag[e] ? s + rl : s + nl + ((int)p - s - rl);
+    out[np] = e;
+}
+
+__global__ void k_segnode(int64_t M, int* __restrict__ seg_node, const KdNode* __restrict__ nodes) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const KdNode& nd = nodes[seg_node[p]];
+    if (nd.dim < 0) return;
+    seg_node[p] = p < nd.start + (nd.end - nd.start) / 2 ? nd.left : nd.right;
+}
+
+__global__ void k_leaf_bbox(int nl, const int* __restrict__ leaves, KdNode* nodes, const int* __restrict__ l0,
+                            const int* __restrict__ l1, const int* __restrict__ l2, const int* __restrict__ u0,
+                            const int* __restrict__ u1, const int* __restrict__ u2, int* __restrict__ leaf_min,
+                            int n_hosts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int id = leaves[i];
+    KdNode& nd = nodes[id];
+    const int s = nd.start, e = nd.end - 1;
+    nd.bmin[0] = u0[l0[s]]; nd.bmax[0] = u0[l0[e]];
+    nd.bmin[1] = u1[l1[s]]; nd.bmax[1] = u1[l1[e]];
+    nd.bmin[2] = u2[l2[s]]; nd.bmax[2] = u2[l2[e]];
+    if (id < n_hosts)  // a root that was never split: its region is its bounding box
+        for (int d = 0; d < 3; ++d) { nd.lo[d] = nd.bmin[d]; nd.hi[d] = nd.bmax[d]; }
+    leaf_min[id] = 0x7FFFFFFF;
+}
+
+// Members by position in list-0 order, and the smallest index of each leaf.
+__global__ void k_final(int64_t M, const int* __restrict__ l0, const int* __restrict__ seg_node,
+                        const int* __restrict__ u0, const int* __restrict__ u1, const int* __restrict__ u2,
+                        const int* __restrict__ g, const float* __restrict__ m, Elems F, int* __restrict__ leaf_min) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < M;
+    const int e = valid ? l0[p] : 0;
+    const int gi = valid ? g[e] : 0x7FFFFFFF;
+    if (valid) {
+        F.u[0][p] = u0[e];
+        F.u[1][p] = u1[e];
+        F.u[2][p] = u2[e];
+        F.gidx[p] = gi;
+        F.eid[p] = e;
+        if (m) F.mass[p] = m[e];
+    }
+    // smallest particle index per leaf (wave-reduced when the wave is in one leaf)
+    const int key = valid ? seg_node[p] : 0;
+    const uint64_t act = __ballot(valid);
+    if (act == 0) return;
+    const int first = __ffsll((unsigned long long)act) - 1;
+    const int k0 = __shfl(key, first, 64);
+    if (__ballot(valid && key == k0) == act) {
+        int v = gi;
+        for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+        if ((int)__lane_id() == first) atomicMin(&leaf_min[k0], v);
+    } else if (valid) {
+        atomicMin(&leaf_min[key], gi);
     }
 }
 
@@ -327,61 +346,150 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     }
     const int64_t M = off[n_hosts];
     const int use_mass = p->mass ? 1 : 0;
-    Elems A, B;
-    VR_WS(a0, ctx, int, WS_A0, M); VR_WS(a1, ctx, int, WS_A1, M); VR_WS(a2, ctx, int, WS_A2, M);
-    VR_WS(ag, ctx, int, WS_A3, M); VR_WS(am, ctx, float, WS_A4, use_mass ? M : 1);
-    VR_WS(b0, ctx, int, WS_B0, M); VR_WS(b1, ctx, int, WS_B1, M); VR_WS(b2, ctx, int, WS_B2, M);
-    VR_WS(bg, ctx, int, WS_B3, M); VR_WS(bm, ctx, float, WS_B4, use_mass ? M : 1);
-    A.u[0] = a0; A.u[1] = a1; A.u[2] = a2; A.gidx = ag; A.mass = am;
-    B.u[0] = b0; B.u[1] = b1; B.u[2] = b2; B.gidx = bg; B.mass = bm;
-    VR_WS(nodes, ctx, KdNode, WS_A5, node_cap);
-    VR_WS(act0, ctx, int, WS_A6, node_cap);
-    VR_WS(act1, ctx, int, WS_A7, node_cap);
-    VR_WS(leaves, ctx, int, WS_A8, node_cap);
-    VR_WS(ncell_d, ctx, int, WS_B5, n_hosts);
-    // counters: 0 active nodes now, 1 active next, 2 leaves, 3 nodes, 4 members now, 5 members next
-    VR_WS(counters, ctx, int, WS_FLAG, 8);
+    const int counts = use_mass ? 0 : 1;
+    int hb = 1;
+    while ((1 << hb) <= n_hosts) ++hb;
+    // one workspace region holds every array of the build
+    Carve cv;
+    int *U[3], *G, *H, *L[3], *Lalt, *seg, *leaf_min, *act0, *act1, *leaves, *ncell_d, *counters;
+    float* Ms;
+    uint8_t* flag;
+    uint32_t* lf;
+    uint64_t* pkey;
+    KdNode* nodes;
+    Elems F;
+    auto layout = [&]() {
+        for (int d = 0; d < 3; ++d) U[d] = cv.add<int>(M);
+        G = cv.add<int>(M);
+        H = cv.add<int>(M);
+        Ms = cv.add<float>(use_mass ? M : 1);
+        for (int d = 0; d < 3; ++d) L[d] = cv.add<int>(M);
+        Lalt = cv.add<int>(M);
+        seg = cv.add<int>(M);
+        flag = cv.add<uint8_t>(M);
+        lf = cv.add<uint32_t>(M + 1);
+        pkey = cv.add<uint64_t>(M);
+        nodes = cv.add<KdNode>(node_cap);
+        act0 = cv.add<int>(node_cap);
+        act1 = cv.add<int>(node_cap);
+        leaves = cv.add<int>(node_cap);
+        leaf_min = cv.add<int>(node_cap);
+        for (int d = 0; d < 3; ++d) F.u[d] = cv.add<int>(M);
+        F.gidx = cv.add<int>(M);
+        F.eid = cv.add<int>(M);
+        F.mass = cv.add<float>(use_mass ? M : 1);
+        ncell_d = cv.add<int>(n_hosts);
+        counters = cv.add<int>(8);
+    };
+    layout();
+    const size_t total = cv.bytes;
+    cv.bytes = 0;
+    cv.base = static_cast<char*>(ws(ctx, WS_KD, total));
+    if (!cv.base) return VR_ERR_OUT_OF_MEMORY;
+    layout();
+    if (!use_mass) F.mass = nullptr;
+    // counters: 0 active nodes, 1 active next level, 2 leaves, 3 nodes, 4 members now, 5 members next
     VR_HIP(ctx, hipMemcpyAsync(ncell_d, ncell.data(), n_hosts * sizeof(int), hipMemcpyHostToDevice, st));
-    int* init_counts = reinterpret_cast<int*>(ctx->pinned);
-    for (int k = 0; k < 8; ++k) init_counts[k] = 0;
-    init_counts[3] = n_hosts;
-    VR_HIP(ctx, hipMemcpyAsync(counters, init_counts, 8 * sizeof(int), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_kd_init, dim3(n_hosts), dim3(256), 0, st, n_hosts, host_offsets, host_members, p->qx, p->qy,
-                       p->qz, p->mass, p->grid_bits, A);
+    int* init = reinterpret_cast<int*>(ctx->pinned);
+    for (int k = 0; k < 8; ++k) init[k] = 0;
+    init[3] = n_hosts;
+    VR_HIP(ctx, hipMemcpyAsync(counters, init, 8 * sizeof(int), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_elems, dim3(grid_for(M, 256)), dim3(256), 0, st, M, n_hosts, host_offsets, host_members,
+                       p->qx, p->qy, p->qz, p->mass, p->grid_bits, U[0], U[1], U[2], G, Ms, H);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_kd_roots, dim3(n_hosts), dim3(KB), 0, st, host_offsets, ncell_d, A, nodes, act0, counters + 0,
-                       leaves, counters + 2, counters + 4);
+    for (int d = 0; d < 3; ++d) {
+        hipLaunchKernelGGL(k_presort_keys, dim3(grid_for(M, 256)), dim3(256), 0, st, M, U[d], H, pkey,
+                           reinterpret_cast<uint32_t*>(L[d]));
+        VR_LAUNCH_CHECK(ctx);
+        int rc = sort_pairs_u64(ctx, pkey, reinterpret_cast<uint32_t*>(L[d]), M, 22 + hb, st);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_roots, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, host_offsets, ncell_d, nodes,
+                       act0, counters, leaves, seg);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_seg_init, dim3(grid_for(M, 256)), dim3(256), 0, st, M, H, seg);
     VR_LAUNCH_CHECK(ctx);
     int* cur = act0;
     int* nxt = act1;
+    const unsigned gM = grid_for(M, 256);
     for (int level = 0;; ++level) {
-        int cnt[8];
-        int rc = read_back(ctx, counters, cnt, sizeof cnt, st);
+        int c[8];
+        int rc = read_back(ctx, counters, c, sizeof c, st);
         if (rc) return rc;
-        const int na = cnt[0];
+        const int na = c[0];
         if (na == 0) break;
         if (level >= 64) return set_err(ctx, VR_ERR_NOT_CONVERGED, "KD build exceeded 64 levels");
-        rc = fill_i32(ctx, counters + 1, 0, 1, st);
-        if (rc) return rc;
-        rc = fill_i32(ctx, counters + 5, 0, 1, st);
-        if (rc) return rc;
-        VR_TIMED(ctx, "kd_level", st, cnt[4],
-                 hipLaunchKernelGGL(k_kd_level, dim3(na), dim3(KB), 0, st, nodes, cur, nxt, counters + 1, leaves,
-                                    counters + 2, counters + 3, counters + 5, A, B, ncell_d, nbins, mode, use_mass));
+        hipEvent_t e0 = nullptr;
+        if (ctx->timing) {
+            e0 = timer_event(ctx);
+            (void)hipEventRecord(e0, st);
+        }
+        if ((rc = fill_i32(ctx, counters + 1, 0, 1, st))) return rc;
+        if ((rc = fill_i32(ctx, counters + 5, 0, 1, st))) return rc;
+        hipLaunchKernelGGL(k_bbox, dim3(grid_for(na, 256)), dim3(256), 0, st, na, cur, nodes, L[0], L[1], L[2], U[0],
+                           U[1], U[2], n_hosts);
+        VR_LAUNCH_CHECK(ctx);
+        uint32_t* hc = nullptr;
+        double* hm = nullptr;
+        if (mode != KD_WIDEST) {
+            const int64_t hn = (int64_t)na * 3 * nbins;
+            if (counts) {
+                hc = static_cast<uint32_t*>(ws(ctx, WS_KD_HIST, hn * sizeof(uint32_t)));
+                if (!hc) return VR_ERR_OUT_OF_MEMORY;
+                if ((rc = fill_u32(ctx, hc, 0u, hn, st))) return rc;
+                hipLaunchKernelGGL(k_hist<true>, dim3(grid_for(M, HCH)), dim3(KB), 0, st, M, seg, nodes, L[0], U[0],
+                                   U[1], U[2], Ms, nbins, hc, hm);
+            } else {
+                hm = static_cast<double*>(ws(ctx, WS_KD_HIST, hn * sizeof(double)));
+                if (!hm) return VR_ERR_OUT_OF_MEMORY;
+                if ((rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hm), 0u, 2 * hn, st))) return rc;
+                hipLaunchKernelGGL(k_hist<false>, dim3(grid_for(M, HCH)), dim3(KB), 0, st, M, seg, nodes, L[0], U[0],
+                                   U[1], U[2], Ms, nbins, hc, hm);
+            }
+            VR_LAUNCH_CHECK(ctx);
+        }
+        hipLaunchKernelGGL(k_split, dim3(grid_for(na, 256)), dim3(256), 0, st, na, cur, nodes, L[0], L[1], L[2], U[0],
+                           U[1], U[2], mode, nbins, counts, hc, hm, ncell_d, nxt, leaves, counters);
+        VR_LAUNCH_CHECK(ctx);
+        hipLaunchKernelGGL(k_flags, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag);
+        VR_LAUNCH_CHECK(ctx);
+        for (int j = 0; j < 3; ++j) {
+            hipLaunchKernelGGL(k_lflag, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[j], flag, lf);
+            VR_LAUNCH_CHECK(ctx);
+            if ((rc = scan_u32(ctx, lf, lf, M, nullptr, st))) return rc;
+            hipLaunchKernelGGL(k_part, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[j], flag, lf, Lalt);
+            VR_LAUNCH_CHECK(ctx);
+            std::swap(L[j], Lalt);
+        }
+        hipLaunchKernelGGL(k_segnode, dim3(gM), dim3(256), 0, st, M, seg, nodes);
         VR_LAUNCH_CHECK(ctx);
         VR_HIP(ctx, hipMemcpyAsync(counters + 0, counters + 1, sizeof(int), hipMemcpyDeviceToDevice, st));
         VR_HIP(ctx, hipMemcpyAsync(counters + 4, counters + 5, sizeof(int), hipMemcpyDeviceToDevice, st));
+        if (ctx->timing) {
+            hipEvent_t e1 = timer_event(ctx);
+            (void)hipEventRecord(e1, st);
+            timer_push(ctx, "kd_level", e0, e1, (double)c[4]);
+        }
         std::swap(cur, nxt);
     }
-    int nleaf = 0;
-    int rc = read_back(ctx, counters + 2, &nleaf, sizeof nleaf, st);
+    int c[8];
+    int rc = read_back(ctx, counters, c, sizeof c, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_kd_leaves, dim3(nleaf), dim3(KB), 0, st, leaves, nodes, A, B, use_mass);
+    const int nleaf = c[2];
+    hipLaunchKernelGGL(k_leaf_bbox, dim3(grid_for(nleaf, 256)), dim3(256), 0, st, nleaf, leaves, nodes, L[0], L[1],
+                       L[2], U[0], U[1], U[2], leaf_min, n_hosts);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_final, dim3(gM), dim3(256), 0, st, M, L[0], seg, U[0], U[1], U[2], G,
+                       use_mass ? Ms : nullptr, F, leaf_min);
     VR_LAUNCH_CHECK(ctx);
     tree.nodes = nodes;
     tree.leaves = leaves;
     tree.n_leaves = nleaf;
-    tree.F = A;
+    tree.seg_node = seg;
+    tree.leaf_min = leaf_min;
+    tree.F = F;
+    for (int d = 0; d < 3; ++d) tree.elem_u[d] = U[d];
+    tree.elem_host = H;
     tree.use_mass = use_mass;
     return VR_OK;
 }

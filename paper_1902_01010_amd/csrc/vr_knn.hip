@@ -23,20 +23,18 @@ constexpr int POS_BITS = 22;
 constexpr uint64_t POS_MASK = (uint64_t(1) << POS_BITS) - 1;
 constexpr int STACK = 128;
 
-__global__ void k_elem_host(int n_hosts, const int32_t* __restrict__ off, int* __restrict__ elem_host) {
-    const int h = blockIdx.x;
-    for (int k = off[h] + threadIdx.x; k < off[h + 1]; k += blockDim.x) elem_host[k] = h;
-}
-
-__global__ void k_gather_vel(int64_t M, const int* __restrict__ gidx, const float* __restrict__ vx,
-                             const float* __restrict__ vy, const float* __restrict__ vz, float* __restrict__ px,
-                             float* __restrict__ py, float* __restrict__ pz) {
+// Velocities (and masses) by element id, i.e. in host-member order.
+__global__ void k_gather_vel(int64_t M, const int* __restrict__ mem, const float* __restrict__ vx,
+                             const float* __restrict__ vy, const float* __restrict__ vz, const float* __restrict__ mass,
+                             float* __restrict__ px, float* __restrict__ py, float* __restrict__ pz,
+                             float* __restrict__ pm) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
-    const int g = gidx[k];
+    const int g = mem[k];
     px[k] = vx[g];
     py[k] = vy[g];
     pz[k] = vz[g];
+    if (mass) pm[k] = mass[g];
 }
 
 __global__ void k_pos_of(int64_t M, const int* __restrict__ gidx, int* __restrict__ pos_of) {
@@ -91,7 +89,8 @@ template <int NSE, int NV>
 __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, int64_t nq,
                                             const KdNode* __restrict__ nodes, Elems F, const float* __restrict__ Vx,
                                             const float* __restrict__ Vy, const float* __restrict__ Vz,
-                                            const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
+                                            const float* __restrict__ Me, const int* __restrict__ elem_host,
+                                            const int32_t* __restrict__ host_off,
                                             const float* __restrict__ vbar, const float* __restrict__ sigma, int64_t n,
                                             int n_se, int n_v, int use_mass, double mass_value, int gb,
                                             float* __restrict__ R) {
@@ -136,7 +135,8 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                     const int ddy = min_image(F.u[1][j] - py, gb);
                     const int ddz = min_image(F.u[2][j] - pz, gb);
                     const uint64_t d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
-                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)(j - base);
+                    // rank of the member in its host's ascending index order breaks ties
+                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)(F.eid[j] - base);
                     if (mine) {
                         if (count < n_se) {
                             heap_push<NSE>(heap, lane, count, key);
@@ -164,14 +164,16 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         pending = pending && !mine;
     }
     if (!active) return;
-    // velocity neighbours among the spatial ones, by (dv2, index)
-    const double vqx = (double)Vx[e], vqy = (double)Vy[e], vqz = (double)Vz[e];
+    // velocity neighbours among the spatial ones, by (dv2, index); velocities
+    // and masses are indexed by element id = host base + rank
+    const int qe = F.eid[e];
+    const double vqx = (double)Vx[qe], vqy = (double)Vy[qe], vqz = (double)Vz[qe];
     double msum = 0.0;
     int nv = 0;
     for (int a = 0; a < n_se; ++a) {
         const int pos = (int)(heap[a][lane] & POS_MASK);
         const int gp = base + pos;
-        msum += use_mass ? (double)F.mass[gp] : mass_value;
+        msum += use_mass ? (double)Me[gp] : mass_value;
         const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
         const double dv2 = ax * ax + ay * ay + az * az;
         if (nv == n_v) {
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         const double kW = 15.0 / (8.0 * M_PI);
         double sw = 0.0;
         for (int a = 0; a < n_v; ++a) {
-            const double m = use_mass ? (double)F.mass[base + vp[a][lane]] : mass_value;
+            const double m = use_mass ? (double)Me[base + vp[a][lane]] : mass_value;
             sw += m * kW * (1.0 - vd[a][lane] / h2);
         }
         lfl = log(sw) - 1.5 * log(h2) - log(msum);
@@ -236,12 +238,12 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
 
 template <int NSE, int NV>
 int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx, const float* Vy,
-               const float* Vz, const int* elem_host, const int32_t* host_off, const vr_particles* p, const float* vbar,
+               const float* Vz, const float* Me, const int32_t* host_off, const vr_particles* p, const float* vbar,
                const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
     VR_TIMED(ctx, "knn", st, nq,
              hipLaunchKernelGGL((k_knn<NSE, NV>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
-                                tree.F, Vx, Vy, Vz, elem_host, host_off, vbar, sigma, p->n, n_se, n_v, tree.use_mass,
-                                p->mass_value, p->grid_bits, R));
+                                tree.F, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n, n_se, n_v,
+                                tree.use_mass, p->mass_value, p->grid_bits, R));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
@@ -279,11 +281,9 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     VR_WS(Vx, ctx, float, WS_C0, M);
     VR_WS(Vy, ctx, float, WS_C1, M);
     VR_WS(Vz, ctx, float, WS_C2, M);
-    VR_WS(elem_host, ctx, int, WS_C3, M);
-    hipLaunchKernelGGL(k_gather_vel, dim3(grid_for(M, 256)), dim3(256), 0, st, M, tree.F.gidx, p->vx, p->vy, p->vz, Vx,
-                       Vy, Vz);
-    VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_elem_host, dim3(n_hosts), dim3(256), 0, st, n_hosts, host_offsets, elem_host);
+    VR_WS(Me, ctx, float, WS_C3, p->mass ? M : 1);
+    hipLaunchKernelGGL(k_gather_vel, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, p->vx, p->vy, p->vz,
+                       p->mass, Vx, Vy, Vz, Me);
     VR_LAUNCH_CHECK(ctx);
     const uint32_t* qpos = nullptr;
     int64_t nq = M;
@@ -313,8 +313,8 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         nq = n_subset;
     }
     if (n_se <= 32 && n_v <= 8)
-        return launch_knn<32, 8>(ctx, qpos, nq, tree, Vx, Vy, Vz, elem_host, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 8>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
     if (n_se <= 32)
-        return launch_knn<32, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, elem_host, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
-    return launch_knn<64, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, elem_host, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    return launch_knn<64, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
 }
