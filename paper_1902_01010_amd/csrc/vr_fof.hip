@@ -315,6 +315,8 @@ extern "C" int vr_fof3d(vr_ctx* ctx, const vr_particles* p, double ellx, int32_t
     hipStream_t st = (hipStream_t)stream;
     int s = 0;
     while ((double)(1 << s) < u && s < gb) ++s;
+    if (fof3d_fine_applicable(gb, s)) return fof3d_fine(ctx, p, ell2, s, label, st);
+    // very coarse grids (fewer than 4 cells a side): one level, all 27 neighbours
     CellList cl;
     rc = build_cell_list(ctx, n, p->qx, p->qy, p->qz, gb, s, cl, st);
     if (rc) return rc;

@@ -78,6 +78,11 @@ struct CellList {
     int64_t n_cells;
 };
 
+// 3D FOF on the two-level grid (coarse cells of side 2^s, fine cells whose
+// members are all linked); applicable for 4 .. 4096 coarse cells a side.
+bool fof3d_fine_applicable(int gb, int s);
+int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* label, hipStream_t st);
+
 // Cell list of n points with cells of side 2^s grid units.  Uses workspace
 // slots A0..A8, FLAG and the sort slots.
 int build_cell_list(vr_ctx* ctx, int64_t n, const uint32_t* qx, const uint32_t* qy, const uint32_t* qz, int gb,

@@ -92,3 +92,22 @@ def test_groups_bit_exact(ctx, vr, ref, name):
         assert (gof.cpu().numpy() == egof).all()
         assert (off.cpu().numpy() == eoff).all()
         assert (mem[:eoff[-1]].cpu().numpy() == emem).all()
+
+
+@pytest.mark.parametrize("ell_units,spread", [(1638.4, 3000.0), (4100.0, 20000.0), (700.0, 900.0)])
+def test_fof3d_clumps_across_box_edges(ctx, vr, ref, ell_units, spread):
+    # dense clumps centred on the corners and faces of the periodic box
+    rng = np.random.default_rng(int(ell_units))
+    size = 1 << 21
+    centres = np.array([[0, 0, 0], [size - 1, 5, 9], [size // 2, 0, size - 3], [123456, 654321, 0]], float)
+    pts = []
+    for c in centres:
+        pts.append(c[:, None] + rng.normal(0, spread, (3, 3000)))
+        pts.append(c[:, None] + rng.normal(0, spread * 0.05, (3, 1000)))  # very dense core
+    q = np.mod(np.rint(np.concatenate(pts, 1)), size).astype(np.uint32)
+    perm = rng.permutation(q.shape[1])
+    q = np.ascontiguousarray(q[:, perm])
+    Pd = vr.Particles(dev_tensor(q.view(np.int32)), None, None, 1.0, 1.0, 21)
+    Pr = ref.Particles(q, None, None, 1.0, 1.0, 21)
+    ell = ell_units / size
+    assert (ctx.fof3d(Pd, ell).cpu().numpy() == ref.fof3d(Pr, ell)).all()
