@@ -61,6 +61,15 @@ size_t vr_workspace_bytes(const vr_ctx* ctx);
  * "unbind_group" members, "radix_scatter" keys).  vr_set_timing also clears
  * the totals.  vr_kernel_time waits for the recorded events. */
 int vr_set_timing(vr_ctx* ctx, int enabled);
+
+/* Launch-shape knobs of the context (results never depend on them):
+ * "knn_leaf"      members per leaf of the neighbour-search tree (16..64, 64)
+ * "unbind_tile"   j-tile of the potential kernel staged in LDS (64..4096, 256)
+ * "unbind_jchunk" j-range of one potential work item (256..65536, 4096)
+ * Returns VR_ERR_INVALID_ARG for an unknown knob or a value out of range;
+ * vr_get_tune reads a knob back. */
+int vr_tune(vr_ctx* ctx, const char* knob, int value);
+int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value);
 int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms,
                    double* work);
 

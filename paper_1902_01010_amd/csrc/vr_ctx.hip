@@ -195,6 +195,35 @@ int vr_set_timing(vr_ctx* ctx, int enabled) {
     return VR_OK;
 }
 
+int vr_tune(vr_ctx* ctx, const char* knob, int value) {
+    if (!ctx || !knob) return VR_ERR_INVALID_ARG;
+    const std::string k = knob;
+    if (k == "knn_leaf") {
+        if (value < 16 || value > 64) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "knn_leaf must be in 16..64");
+        ctx->knn_leaf = value;
+    } else if (k == "unbind_tile") {
+        if (value < 64 || value > 4096 || (value & 63))
+            return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_tile must be a multiple of 64 in 64..4096");
+        ctx->tuned_tile = value;
+    } else if (k == "unbind_jchunk") {
+        if (value < 256 || value > 65536) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_jchunk must be in 256..65536");
+        ctx->unbind_jchunk = value;
+    } else {
+        return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unknown knob '%s'", knob);
+    }
+    return VR_OK;
+}
+
+int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value) {
+    if (!ctx || !knob || !value) return VR_ERR_INVALID_ARG;
+    const std::string k = knob;
+    if (k == "knn_leaf") *value = ctx->knn_leaf;
+    else if (k == "unbind_tile") *value = ctx->tuned_tile ? ctx->tuned_tile : 256;
+    else if (k == "unbind_jchunk") *value = ctx->unbind_jchunk;
+    else return VR_ERR_INVALID_ARG;
+    return VR_OK;
+}
+
 int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms, double* work) {
     if (!ctx || !kernel || !launches || !total_ms || !work) return VR_ERR_INVALID_ARG;
     VR_HIP(ctx, hipSetDevice(ctx->device));

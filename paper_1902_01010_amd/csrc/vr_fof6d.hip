@@ -38,16 +38,19 @@ __device__ __forceinline__ void bsum(double (&v)[N], double* sm) {
 }
 
 // sigma_v of a host from the mass-weighted dispersion tensor of all members
-// about their mass-weighted mean velocity; one workgroup per host.
-__global__ __launch_bounds__(256) void k_host_ellv(const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
+// about their mass-weighted mean velocity.  Members are cut into chunks of
+// ELLV_CHUNK; one workgroup sums a chunk and one thread per host adds its
+// chunks in order, so the result does not depend on scheduling.
+constexpr int ELLV_CHUNK = 8192;
+
+__global__ __launch_bounds__(256) void k_ellv_mean(const int4* __restrict__ chunks, const int32_t* __restrict__ mem,
                                                    const float* __restrict__ vx, const float* __restrict__ vy,
                                                    const float* __restrict__ vz, const float* __restrict__ mass,
-                                                   double mass_value, double alpha_v, double* __restrict__ ellv) {
-    __shared__ double sm[4 * 6];
-    const int h = blockIdx.x;
-    const int s = off[h], e = off[h + 1];
+                                                   double mass_value, double* __restrict__ part) {
+    __shared__ double sm[4 * 4];
+    const int4 c = chunks[blockIdx.x];
     double a[4] = {0, 0, 0, 0};
-    for (int k = s + threadIdx.x; k < e; k += blockDim.x) {
+    for (int k = c.y + threadIdx.x; k < c.z; k += blockDim.x) {
         const int i = mem[k];
         const double m = mass ? (double)mass[i] : mass_value;
         a[0] += m;
@@ -56,26 +59,57 @@ __global__ __launch_bounds__(256) void k_host_ellv(const int32_t* __restrict__ o
         a[3] += m * (double)vz[i];
     }
     bsum<4>(a, sm);
-    const double M = a[0];
-    const double mv[3] = {a[1] / M, a[2] / M, a[3] / M};
-    double c[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = s + threadIdx.x; k < e; k += blockDim.x) {
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) part[(int64_t)blockIdx.x * 8 + q] = a[q];
+}
+
+__global__ void k_ellv_hostmean(int n_hosts, const int* __restrict__ chunk_off, const double* __restrict__ part,
+                                double* __restrict__ hmean) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hosts) return;
+    double a[4] = {0, 0, 0, 0};
+    for (int c = chunk_off[h]; c < chunk_off[h + 1]; ++c)
+        for (int q = 0; q < 4; ++q) a[q] += part[(int64_t)c * 8 + q];
+    hmean[h * 4 + 0] = a[0];
+    for (int d = 0; d < 3; ++d) hmean[h * 4 + 1 + d] = a[1 + d] / a[0];
+}
+
+__global__ __launch_bounds__(256) void k_ellv_disp(const int4* __restrict__ chunks, const int32_t* __restrict__ mem,
+                                                   const float* __restrict__ vx, const float* __restrict__ vy,
+                                                   const float* __restrict__ vz, const float* __restrict__ mass,
+                                                   double mass_value, const double* __restrict__ hmean,
+                                                   double* __restrict__ part) {
+    __shared__ double sm[4 * 6];
+    const int4 c = chunks[blockIdx.x];
+    const double mv0 = hmean[c.x * 4 + 1], mv1 = hmean[c.x * 4 + 2], mv2 = hmean[c.x * 4 + 3];
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = c.y + threadIdx.x; k < c.z; k += blockDim.x) {
         const int i = mem[k];
         const double m = mass ? (double)mass[i] : mass_value;
-        const double d0 = (double)vx[i] - mv[0], d1 = (double)vy[i] - mv[1], d2 = (double)vz[i] - mv[2];
-        c[0] += m * d0 * d0;
-        c[1] += m * d1 * d1;
-        c[2] += m * d2 * d2;
-        c[3] += m * d0 * d1;
-        c[4] += m * d0 * d2;
-        c[5] += m * d1 * d2;
+        const double d0 = (double)vx[i] - mv0, d1 = (double)vy[i] - mv1, d2 = (double)vz[i] - mv2;
+        a[0] += m * d0 * d0;
+        a[1] += m * d1 * d1;
+        a[2] += m * d2 * d2;
+        a[3] += m * d0 * d1;
+        a[4] += m * d0 * d2;
+        a[5] += m * d1 * d2;
     }
-    bsum<6>(c, sm);
-    if (threadIdx.x == 0) {
-        const double s00 = c[0] / M, s11 = c[1] / M, s22 = c[2] / M, s01 = c[3] / M, s02 = c[4] / M, s12 = c[5] / M;
-        const double det = s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) + s02 * (s01 * s12 - s11 * s02);
-        ellv[h] = alpha_v * pow(det, 1.0 / 6.0);
-    }
+    bsum<6>(a, sm);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) part[(int64_t)blockIdx.x * 8 + q] = a[q];
+}
+
+__global__ void k_ellv_final(int n_hosts, const int* __restrict__ chunk_off, const double* __restrict__ part,
+                             const double* __restrict__ hmean, double alpha_v, double* __restrict__ ellv) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hosts) return;
+    double c[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = chunk_off[h]; k < chunk_off[h + 1]; ++k)
+        for (int q = 0; q < 6; ++q) c[q] += part[(int64_t)k * 8 + q];
+    const double M = hmean[h * 4];
+    const double s00 = c[0] / M, s11 = c[1] / M, s22 = c[2] / M, s01 = c[3] / M, s02 = c[4] / M, s12 = c[5] / M;
+    const double det = s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) + s02 * (s01 * s12 - s11 * s02);
+    ellv[h] = alpha_v * pow(det, 1.0 / 6.0);
 }
 
 __global__ void k_participants(int64_t n, const int32_t* __restrict__ host_of, const float* __restrict__ R,
@@ -204,9 +238,40 @@ extern "C" int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
     if (n_hosts == 0) return VR_OK;
     if (!ellv_host) return set_err(ctx, VR_ERR_INVALID_ARG, "ellv_host is NULL");
     VR_HIP(ctx, hipSetDevice(ctx->device));
-    hipLaunchKernelGGL(k_host_ellv, dim3(n_hosts), dim3(256), 0, (hipStream_t)stream, host_offsets, host_members, p->vx,
-                       p->vy, p->vz, p->mass, p->mass_value, alpha_v, ellv_host);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> off(n_hosts + 1);
+    VR_HIP(ctx, hipMemcpyAsync(off.data(), host_offsets, (n_hosts + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipStreamSynchronize(st));
+    if (off[0] != 0) return set_err(ctx, VR_ERR_INVALID_ARG, "host_offsets[0] must be 0");
+    std::vector<int4> chunks;
+    std::vector<int> coff(n_hosts + 1, 0);
+    for (int h = 0; h < n_hosts; ++h) {
+        if (off[h + 1] <= off[h] || off[h + 1] > p->n)
+            return set_err(ctx, VR_ERR_INVALID_ARG, "host %d is empty or out of range", h);
+        for (int s = off[h]; s < off[h + 1]; s += ELLV_CHUNK)
+            chunks.push_back(make_int4(h, s, std::min(off[h + 1], s + ELLV_CHUNK), 0));
+        coff[h + 1] = (int)chunks.size();
+    }
+    const int nch = (int)chunks.size();
+    VR_WS(chunks_d, ctx, int4, WS_D4, nch);
+    VR_WS(coff_d, ctx, int, WS_D5, n_hosts + 1);
+    VR_WS(part, ctx, double, WS_D6, (int64_t)nch * 8);
+    VR_WS(hmean, ctx, double, WS_D7, (int64_t)n_hosts * 4);
+    VR_HIP(ctx, hipMemcpyAsync(chunks_d, chunks.data(), nch * sizeof(int4), hipMemcpyHostToDevice, st));
+    VR_HIP(ctx, hipMemcpyAsync(coff_d, coff.data(), (n_hosts + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_ellv_mean, dim3(nch), dim3(256), 0, st, chunks_d, host_members, p->vx, p->vy, p->vz, p->mass,
+                       p->mass_value, part);
     VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ellv_hostmean, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, coff_d, part, hmean);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ellv_disp, dim3(nch), dim3(256), 0, st, chunks_d, host_members, p->vx, p->vy, p->vz, p->mass,
+                       p->mass_value, hmean, part);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ellv_final, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, coff_d, part, hmean,
+                       alpha_v, ellv_host);
+    VR_LAUNCH_CHECK(ctx);
+    // the host vectors above are copied asynchronously: wait before they go away
+    VR_HIP(ctx, hipStreamSynchronize(st));
     return VR_OK;
 }
 

@@ -173,10 +173,19 @@ __global__ void k_compress_f(int64_t n, int* parent) {
     parent[p] = r;
 }
 
+// Smallest original index per component: every root first stores its own
+// index (no atomics for the many singletons), then the other members lower
+// it atomically.
+__global__ void k_root_idx_f(int64_t n, const int* __restrict__ parent, const uint32_t* __restrict__ idx,
+                             int* __restrict__ mn) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n && parent[p] == (int)p) mn[p] = (int)idx[p];
+}
+
 __global__ void k_min_orig_f(int64_t n, const int* __restrict__ parent, const uint32_t* __restrict__ idx,
                              int* __restrict__ mn) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = p < n;
+    const bool valid = p < n && parent[p] != (int)p;
     wave_atomic_min(mn, valid ? parent[p] : 0, valid ? (int)idx[p] : 0x7FFFFFFF, valid);
 }
 
@@ -244,7 +253,8 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_compress_f, dim3(gn), dim3(256), 0, st, n, parent);
     VR_LAUNCH_CHECK(ctx);
-    if ((rc = fill_i32(ctx, mn, 0x7FFFFFFF, n, st))) return rc;
+    hipLaunchKernelGGL(k_root_idx_f, dim3(gn), dim3(256), 0, st, n, parent, idx, mn);
+    VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_min_orig_f, dim3(gn), dim3(256), 0, st, n, parent, idx, mn);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_label_f, dim3(gn), dim3(256), 0, st, n, parent, idx, mn, label);

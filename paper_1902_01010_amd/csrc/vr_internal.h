@@ -41,6 +41,8 @@ struct vr_ctx {
     // host-pinned scalars for counts returned by syncing calls
     int64_t* pinned = nullptr;
     int tuned_tile = 0;     // potential j-tile picked by the autotuner (0 = default)
+    int knn_leaf = 64;      // members per leaf of the neighbour-search tree
+    int unbind_jchunk = 4096;
 };
 
 namespace vr {

@@ -1,17 +1,19 @@
 // vr_knn.hip -- local velocity density ratio R = ln(f_l / f_bg) (Sec. 2.2).
 //
 // Each host gets a median-split KD tree (widest dimension, leaves of at most
-// 64 members) built by the level-synchronous builder; members end up in leaf
-// order, so 64 consecutive queries share leaves.  One wavefront serves 64
-// queries, one per lane: the wave walks the tree of a host with a shared
-// depth-first stack, visiting a node when any lane's ball (radius = its
-// current n_se-th neighbour) reaches the node's bounding box, and every lane
-// keeps its n_se best (d2, member) keys in a max-heap in LDS.  The key packs
-// the exact integer squared distance above the member's position in the host
-// (position order = particle-index order), so ties break by index exactly as
-// the definition says.  The n_v velocity neighbours are then selected among
-// the n_se by (FP64 dv2, index) and the Epanechnikov estimate and the
-// Gaussian background follow in FP64.
+// 64 members, built by the presorted level-synchronous builder); members sit
+// in leaf order, so 64 consecutive queries share leaves.  One wavefront
+// serves 64 queries, one per lane: the wave walks the tree of a host with a
+// shared depth-first stack (near child first), visiting a node when any
+// lane's ball -- radius = its current n_se-th neighbour -- reaches the node's
+// bounding box.  A visited leaf is loaded once, one member per lane, and its
+// members are broadcast lane to lane, so the inner loop touches no memory.
+// Every lane keeps its n_se best keys in a max-heap in LDS; a key packs the
+// exact integer squared distance above the member's rank in its host's
+// ascending index order, so ties break by particle index exactly as the
+// definition says.  The n_v velocity neighbours are then chosen among the
+// n_se by (FP64 dv2, index) and the Epanechnikov estimate and the Gaussian
+// background follow in FP64.
 #include "vr_kd.h"
 
 #include <cmath>
@@ -53,7 +55,6 @@ __global__ void k_subset_pos(int64_t ns, int64_t n, const int32_t* __restrict__ 
     qval[s] = (uint32_t)s;
 }
 
-template <int NSE>
 __device__ __forceinline__ void heap_push(uint64_t (*heap)[64], int lane, int& count, uint64_t key) {
     int i = count++;
     while (i > 0) {
@@ -66,7 +67,6 @@ __device__ __forceinline__ void heap_push(uint64_t (*heap)[64], int lane, int& c
     heap[i][lane] = key;
 }
 
-template <int NSE>
 __device__ __forceinline__ void heap_replace_top(uint64_t (*heap)[64], int lane, int count, uint64_t key) {
     int i = 0;
     for (;;) {
@@ -85,18 +85,22 @@ __device__ __forceinline__ void heap_replace_top(uint64_t (*heap)[64], int lane,
     heap[i][lane] = key;
 }
 
-template <int NSE, int NV>
+__device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { return a < b || (a == b && pa < pb); }
+
+// NVR > 0: exactly NVR velocity neighbours kept in registers (sorted by an
+// unrolled insertion network); NVR == 0: any n_v, kept in LDS.
+template <int NSE, int NVR>
 __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, int64_t nq,
                                             const KdNode* __restrict__ nodes, Elems F, const float* __restrict__ Vx,
                                             const float* __restrict__ Vy, const float* __restrict__ Vz,
                                             const float* __restrict__ Me, const int* __restrict__ elem_host,
-                                            const int32_t* __restrict__ host_off,
-                                            const float* __restrict__ vbar, const float* __restrict__ sigma, int64_t n,
-                                            int n_se, int n_v, int use_mass, double mass_value, int gb,
-                                            float* __restrict__ R) {
+                                            const int32_t* __restrict__ host_off, const float* __restrict__ vbar,
+                                            const float* __restrict__ sigma, int64_t n, int n_se, int n_v, int use_mass,
+                                            double mass_value, int gb, float* __restrict__ R) {
+    constexpr int NVL = NVR > 0 ? 1 : NSE;
     __shared__ uint64_t heap[NSE][64];
-    __shared__ double vd[NV][64];
-    __shared__ int vp[NV][64];
+    __shared__ double vd[NVL][64];
+    __shared__ int vp[NVL][64];
     __shared__ int stack[STACK];
     const int lane = threadIdx.x;
     const int64_t qi = (int64_t)blockIdx.x * 64 + lane;
@@ -107,15 +111,24 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     const int px = F.u[0][e], py = F.u[1][e], pz = F.u[2][e];
     int count = 0;
     uint64_t worst = ~0ull;
+    // the leaf chunk being scanned: x, y, z (exact integers as float) and rank
+    __shared__ float4 cand[64];
     bool pending = active;
     while (__ballot(pending)) {
         const uint64_t pm = __ballot(pending);
         const int fl = __ffsll((unsigned long long)pm) - 1;
         const int hh = __shfl(h, fl, 64);
+        const int hbase = host_off[hh];
         const bool mine = pending && h == hh;
-        int sp = 0;
+        // a host narrower than half the box needs no minimum image: its
+        // unwrapped coordinate differences are the periodic ones
+        const KdNode& root = nodes[hh];
+        const int half = 1 << (gb - 1);
+        const bool nowrap = root.bmax[0] - root.bmin[0] < half && root.bmax[1] - root.bmin[1] < half &&
+                            root.bmax[2] - root.bmin[2] < half;
+        const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
         if (lane == 0) stack[0] = hh;
-        sp = 1;
+        int sp = 1;
         __builtin_amdgcn_wave_barrier();
         while (sp > 0) {
             const int node = stack[--sp];
@@ -129,21 +142,69 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
             const bool need = mine && (count < n_se || ((uint64_t)md2 << POS_BITS) <= worst);
             if (!__ballot(need)) continue;
             if (nd.dim < 0) {
-                const int s = nd.start, t = nd.end;
-                for (int j = s; j < t; ++j) {
-                    const int ddx = min_image(F.u[0][j] - px, gb);
-                    const int ddy = min_image(F.u[1][j] - py, gb);
-                    const int ddz = min_image(F.u[2][j] - pz, gb);
-                    const uint64_t d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
-                    // rank of the member in its host's ascending index order breaks ties
-                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)(F.eid[j] - base);
-                    if (mine) {
-                        if (count < n_se) {
-                            heap_push<NSE>(heap, lane, count, key);
-                            if (count == n_se) worst = heap[0][lane];
-                        } else if (key < worst) {
-                            heap_replace_top<NSE>(heap, lane, count, key);
-                            worst = heap[0][lane];
+                const int s = nd.start, t_end = nd.end;
+                for (int c0 = s; c0 < t_end; c0 += 64) {
+                    // one member per lane, then broadcast lane by lane
+                    const int j = c0 + lane;
+                    const bool vj = j < t_end;
+                    const int lx = vj ? F.u[0][j] : 0, ly = vj ? F.u[1][j] : 0, lz = vj ? F.u[2][j] : 0;
+                    const int le = vj ? F.eid[j] - hbase : 0;
+                    const int m = min(64, t_end - c0);
+                    if (nowrap) {
+                        // FP32 prefilter: coordinates are integers below 2^24, so the
+                        // differences are exact and the rounded sum of squares is within
+                        // 2e-7 of the exact one; only candidates that may beat the
+                        // current worst key get the exact integer key.
+                        cand[lane] = make_float4((float)lx, (float)ly, (float)lz, __builtin_bit_cast(float, le));
+                        __builtin_amdgcn_wave_barrier();
+                        float wf = count < n_se ? INFINITY : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                        for (int t = 0; t < m; ++t) {
+                            const float4 c4 = cand[t];  // same address for every lane: a broadcast
+                            const float dxf = c4.x - pxf, dyf = c4.y - pyf, dzf = c4.z - pzf;
+                            const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
+                            if (!(mine && d2f <= wf)) continue;
+                            // |d| < 2^21: unsigned 32-bit squares, exact 64-bit sum
+                            const uint32_t ax = (uint32_t)abs((int)dxf), ay = (uint32_t)abs((int)dyf),
+                                           az = (uint32_t)abs((int)dzf);
+                            const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+                            const uint64_t key = (d2 << POS_BITS) | (uint64_t)__builtin_bit_cast(uint32_t, c4.w);
+                            if (count < n_se) {
+                                heap_push(heap, lane, count, key);
+                                if (count == n_se) {
+                                    worst = heap[0][lane];
+                                    wf = (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                                }
+                            } else if (key < worst) {
+                                heap_replace_top(heap, lane, count, key);
+                                worst = heap[0][lane];
+                                wf = (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                            }
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        continue;
+                    }
+                    for (int t = 0; t < m; ++t) {
+                        const int cx = __builtin_amdgcn_readlane(lx, t);
+                        const int cy = __builtin_amdgcn_readlane(ly, t);
+                        const int cz = __builtin_amdgcn_readlane(lz, t);
+                        const int ce = __builtin_amdgcn_readlane(le, t);
+                        const int ddx = min_image(cx - px, gb);
+                        const int ddy = min_image(cy - py, gb);
+                        const int ddz = min_image(cz - pz, gb);
+                        uint64_t d2;
+                        if (max(max(abs(ddx), abs(ddy)), abs(ddz)) < 32768)
+                            d2 = (uint64_t)((uint32_t)(ddx * ddx) + (uint32_t)(ddy * ddy) + (uint32_t)(ddz * ddz));
+                        else
+                            d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
+                        const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)ce;
+                        if (mine && (count < n_se || key < worst)) {
+                            if (count < n_se) {
+                                heap_push(heap, lane, count, key);
+                                if (count == n_se) worst = heap[0][lane];
+                            } else {
+                                heap_replace_top(heap, lane, count, key);
+                                worst = heap[0][lane];
+                            }
                         }
                     }
                 }
@@ -169,44 +230,65 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     const int qe = F.eid[e];
     const double vqx = (double)Vx[qe], vqy = (double)Vy[qe], vqz = (double)Vz[qe];
     double msum = 0.0;
-    int nv = 0;
-    for (int a = 0; a < n_se; ++a) {
-        const int pos = (int)(heap[a][lane] & POS_MASK);
-        const int gp = base + pos;
-        msum += use_mass ? (double)Me[gp] : mass_value;
-        const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
-        const double dv2 = ax * ax + ay * ay + az * az;
-        if (nv == n_v) {
-            const double wd = vd[n_v - 1][lane];
-            const int wp = vp[n_v - 1][lane];
-            if (!(dv2 < wd || (dv2 == wd && pos < wp))) continue;
-            --nv;
+    double h2, sw = 0.0;
+    const double kW = 15.0 / (8.0 * M_PI);
+    if constexpr (NVR > 0) {
+        double vdr[NVR];
+        int vpr[NVR];
+#pragma unroll
+        for (int i = 0; i < NVR; ++i) { vdr[i] = INFINITY; vpr[i] = 0x7FFFFFFF; }
+        for (int a = 0; a < n_se; ++a) {
+            const int pos = (int)(heap[a][lane] & POS_MASK);
+            const int gp = base + pos;
+            msum += use_mass ? (double)Me[gp] : mass_value;
+            const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
+            const double dv2 = ax * ax + ay * ay + az * az;
+#pragma unroll
+            for (int i = NVR - 1; i > 0; --i) {
+                const bool lp = vless(dv2, pos, vdr[i - 1], vpr[i - 1]);
+                const bool lc = vless(dv2, pos, vdr[i], vpr[i]);
+                vdr[i] = lp ? vdr[i - 1] : (lc ? dv2 : vdr[i]);
+                vpr[i] = lp ? vpr[i - 1] : (lc ? pos : vpr[i]);
+            }
+            if (vless(dv2, pos, vdr[0], vpr[0])) { vdr[0] = dv2; vpr[0] = pos; }
         }
-        int i = nv++;
-        while (i > 0) {
-            const double pd = vd[i - 1][lane];
-            const int pp = vp[i - 1][lane];
-            if (pd < dv2 || (pd == dv2 && pp < pos)) break;
-            vd[i][lane] = pd;
-            vp[i][lane] = pp;
-            --i;
+        h2 = vdr[NVR - 1];
+        if (h2 != 0.0) {
+#pragma unroll
+            for (int a = 0; a < NVR; ++a) {
+                const double m = use_mass ? (double)Me[base + vpr[a]] : mass_value;
+                sw += m * kW * (1.0 - vdr[a] / h2);
+            }
         }
-        vd[i][lane] = dv2;
-        vp[i][lane] = pos;
-    }
-    const double h2 = vd[n_v - 1][lane];
-    double lfl;
-    if (h2 == 0.0) {
-        lfl = INFINITY;
     } else {
-        const double kW = 15.0 / (8.0 * M_PI);
-        double sw = 0.0;
-        for (int a = 0; a < n_v; ++a) {
-            const double m = use_mass ? (double)Me[base + vp[a][lane]] : mass_value;
-            sw += m * kW * (1.0 - vd[a][lane] / h2);
+        int nv = 0;
+        for (int a = 0; a < n_se; ++a) {
+            const int pos = (int)(heap[a][lane] & POS_MASK);
+            const int gp = base + pos;
+            msum += use_mass ? (double)Me[gp] : mass_value;
+            const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
+            const double dv2 = ax * ax + ay * ay + az * az;
+            if (nv == n_v) {
+                if (!vless(dv2, pos, vd[n_v - 1][lane], vp[n_v - 1][lane])) continue;
+                --nv;
+            }
+            int i = nv++;
+            while (i > 0 && vless(dv2, pos, vd[i - 1][lane], vp[i - 1][lane])) {
+                vd[i][lane] = vd[i - 1][lane];
+                vp[i][lane] = vp[i - 1][lane];
+                --i;
+            }
+            vd[i][lane] = dv2;
+            vp[i][lane] = pos;
         }
-        lfl = log(sw) - 1.5 * log(h2) - log(msum);
+        h2 = vd[n_v - 1][lane];
+        if (h2 != 0.0)
+            for (int a = 0; a < n_v; ++a) {
+                const double m = use_mass ? (double)Me[base + vp[a][lane]] : mass_value;
+                sw += m * kW * (1.0 - vd[a][lane] / h2);
+            }
     }
+    const double lfl = h2 == 0.0 ? INFINITY : log(sw) - 1.5 * log(h2) - log(msum);
     const int g = F.gidx[e];
     const double S00 = sigma[0 * n + g], S11 = sigma[1 * n + g], S22 = sigma[2 * n + g];
     const double S10 = sigma[3 * n + g], S20 = sigma[4 * n + g], S21 = sigma[5 * n + g];
@@ -236,12 +318,12 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     R[g] = (float)(lfl - lfb);
 }
 
-template <int NSE, int NV>
+template <int NSE, int NVR>
 int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx, const float* Vy,
                const float* Vz, const float* Me, const int32_t* host_off, const vr_particles* p, const float* vbar,
                const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
     VR_TIMED(ctx, "knn", st, nq,
-             hipLaunchKernelGGL((k_knn<NSE, NV>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
+             hipLaunchKernelGGL((k_knn<NSE, NVR>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
                                 tree.F, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n, n_se, n_v,
                                 tree.use_mass, p->mass_value, p->grid_bits, R));
     VR_LAUNCH_CHECK(ctx);
@@ -273,7 +355,7 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     for (int h = 0; h < n_hosts; ++h)
         if ((int64_t)off[h + 1] - off[h] > (int64_t(1) << POS_BITS))
             return set_err(ctx, VR_ERR_UNSUPPORTED, "host %d has more than 2^%d members", h, POS_BITS);
-    std::vector<int> nc(n_hosts, 64);
+    std::vector<int> nc(n_hosts, ctx->knn_leaf);
     KdTree tree;
     rc = kd_build(ctx, p, n_hosts, host_offsets, host_members, off, nc, KD_WIDEST, 2, tree, st);
     if (rc) return rc;
@@ -312,9 +394,9 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         qpos = qp;
         nq = n_subset;
     }
-    if (n_se <= 32 && n_v <= 8)
+    if (n_se <= 32 && n_v == 8)
         return launch_knn<32, 8>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
     if (n_se <= 32)
-        return launch_knn<32, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
-    return launch_knn<64, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 0>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    return launch_knn<64, 0>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
 }

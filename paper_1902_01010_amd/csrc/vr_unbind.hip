@@ -413,7 +413,7 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
             const int n = hcnt[g];
             pairs += (double)n * (double)(n - 1);
             nmem += n;
-            const int jchunk = 4096;
+            const int jchunk = ctx->unbind_jchunk;
             for (int i0 = 0; i0 < n; i0 += UB)
                 for (int j0 = 0; j0 < n; j0 += jchunk) items.push_back(make_int4(g, i0, j0, std::min(n, j0 + jchunk)));
         }

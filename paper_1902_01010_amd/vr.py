@@ -21,7 +21,7 @@ CELL_COLS = 28
 # Entry points declared in include/vr.h (checked by the CPU test-suite).
 ENTRY_POINTS = (
     "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
-    "vr_set_timing", "vr_kernel_time",
+    "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
     "vr_host_ellv", "vr_fof6d", "vr_unbind",
 )
@@ -75,6 +75,8 @@ def load_library():
         L.vr_workspace_bytes.restype = sz
         L.vr_set_timing.argtypes = [vp, C.c_int]
         L.vr_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]
+        L.vr_tune.argtypes = [vp, C.c_char_p, C.c_int]
+        L.vr_get_tune.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
         L.vr_quantize.argtypes = [vp, i64, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
         L.vr_fof3d.argtypes = [vp, P, dbl, vp, vp]
         L.vr_groups.argtypes = [vp, i64, vp, i32, C.POINTER(i32), vp, vp, vp, vp]
@@ -173,6 +175,14 @@ class Context:
 
     def set_timing(self, enabled: bool):
         self._check(self.lib.vr_set_timing(self.h, 1 if enabled else 0))
+
+    def tune(self, knob: str, value: int):
+        self._check(self.lib.vr_tune(self.h, knob.encode(), int(value)))
+
+    def get_tune(self, knob: str) -> int:
+        v = C.c_int(0)
+        self._check(self.lib.vr_get_tune(self.h, knob.encode(), C.byref(v)))
+        return v.value
 
     def kernel_time(self, name: str):
         """(launches, total ms, algorithmic work units) accumulated for a kernel."""
