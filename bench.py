@@ -34,6 +34,7 @@ KERNEL_MODEL = {
     "fof_link6d": ("hbm", 32.0, "participant: q 12, v 12, host 4, parent 4"),
     "unbind_potential": ("alu", 6.0, "ordered pair: 12 flop per unordered pair"),
     "unbind_group": ("hbm", 40.0, "member: coordinates, velocity, potential"),
+    "unbind_persistent": ("alu", 6.0, "ordered pair, whole graph-replayed unbinding of one call"),
 }
 
 

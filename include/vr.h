@@ -58,14 +58,19 @@ size_t vr_workspace_bytes(const vr_ctx* ctx);
  * summed duration and the algorithmic work of the launches (the unit is per
  * kernel: "fof_link3d" particles, "kd_level" member visits, "knn" queries,
  * "fof_link6d" participants, "unbind_potential" ordered pairs i != j,
- * "unbind_group" members, "radix_scatter" keys).  vr_set_timing also clears
+ * "unbind_group" members, "radix_scatter" keys, "unbind_persistent" ordered
+ * pairs i != j, timed from the first to the last graph replay of one call).  vr_set_timing also clears
  * the totals.  vr_kernel_time waits for the recorded events. */
 int vr_set_timing(vr_ctx* ctx, int enabled);
 
-/* Launch-shape knobs of the context (results never depend on them):
+/* Launch-shape knobs of the context (integer results never depend on them;
+ * FP64 potentials only through the order of their partial sums):
  * "knn_leaf"      members per leaf of the neighbour-search tree (16..64, 64)
- * "unbind_tile"   j-tile of the potential kernel staged in LDS (64..4096, 256)
+ * "unbind_tile"   j-tile of the potential kernel staged in LDS (64..4096, 256;
+ *                 the persistent kernel uses at most 1024 per wavefront)
  * "unbind_jchunk" j-range of one potential work item (256..65536, 4096)
+ * "unbind_bpc"    workgroups per CU of the persistent potential kernel
+ *                 (0..8, 0 = as many as fit)
  * Returns VR_ERR_INVALID_ARG for an unknown knob or a value out of range;
  * vr_get_tune reads a knob back. */
 int vr_tune(vr_ctx* ctx, const char* knob, int value);
@@ -181,7 +186,10 @@ typedef struct {
     int32_t n_ref_min; /* at least this many frame members (10)               */
     int32_t frame_type;/* 1 = around the potential minimum, 0 = whole group    */
     int32_t max_iter;  /* VR_ERR_NOT_CONVERGED beyond this many passes (100)  */
-    int32_t persistent;/* 1 = one persistent launch per pass over all groups  */
+    int32_t persistent;/* 1 = passes replayed from a cached graph, each with one
+                          persistent potential launch over a work queue of
+                          (group, 64-row tile, j-range) items for all groups;
+                          0 = host-planned passes                           */
     int32_t tile;      /* j-tile of the potential kernel, 0 = autotuned       */
 } vr_unbind_params;
 
@@ -191,7 +199,8 @@ typedef struct {
  * nearest the potential minimum, removal of beta_E T + W >= 0, repeated until
  * nothing is removed; a group falling below n_min is dissolved.
  * Outputs for every member: bound[i] (0/1), phi[i] (FP64, potential in the
- * last pass i took part in); iters[g] = passes run.  Syncs. */
+ * last pass i took part in); iters[g] = passes run.  Syncs.  Returns
+ * VR_ERR_NOT_CONVERGED if a group still loses members in pass max_iter. */
 int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, const int32_t* offsets,
               const int32_t* members, const vr_unbind_params* up, uint8_t* bound, double* phi,
               int32_t* iters, void* stream);

@@ -165,6 +165,8 @@ void vr_destroy(vr_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     vr::timers_drain(ctx);
+    vr::unbind_release(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy((hipStream_t)ctx->cap_stream);
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     for (auto& b : ctx->slots)
         if (b.ptr) (void)hipFree(b.ptr);
@@ -208,6 +210,9 @@ int vr_tune(vr_ctx* ctx, const char* knob, int value) {
     } else if (k == "unbind_jchunk") {
         if (value < 256 || value > 65536) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_jchunk must be in 256..65536");
         ctx->unbind_jchunk = value;
+    } else if (k == "unbind_bpc") {
+        if (value < 0 || value > 8) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_bpc must be in 0..8");
+        ctx->unbind_bpc = value;
     } else {
         return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unknown knob '%s'", knob);
     }
@@ -220,6 +225,7 @@ int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value) {
     if (k == "knn_leaf") *value = ctx->knn_leaf;
     else if (k == "unbind_tile") *value = ctx->tuned_tile ? ctx->tuned_tile : 256;
     else if (k == "unbind_jchunk") *value = ctx->unbind_jchunk;
+    else if (k == "unbind_bpc") *value = ctx->unbind_bpc;
     else return VR_ERR_INVALID_ARG;
     return VR_OK;
 }

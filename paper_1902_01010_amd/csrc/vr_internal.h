@@ -43,6 +43,12 @@ struct vr_ctx {
     int tuned_tile = 0;     // potential j-tile picked by the autotuner (0 = default)
     int knn_leaf = 64;      // members per leaf of the neighbour-search tree
     int unbind_jchunk = 4096;
+    int unbind_bpc = 0;     // workgroups per CU of the persistent potential kernel (0 = occupancy limit)
+    // graph of the persistent unbinding passes, reused while its arguments match
+    void* cap_stream = nullptr;
+    void* ub_graph = nullptr;
+    void* ub_exec = nullptr;
+    std::string ub_key;
 };
 
 namespace vr {
@@ -121,6 +127,9 @@ void timer_push(vr_ctx* ctx, const char* name, hipEvent_t e0, hipEvent_t e1, dou
             ::vr::timer_push(ctx, name, e0_, e1_, (double)(work));           \
         }                                                                    \
     } while (0)
+
+// Drops the cached unbinding graph (vr_unbind.hip).
+void unbind_release(vr_ctx* ctx);
 
 // Host-side validation shared by the entry points.
 int check_particles(vr_ctx* ctx, const vr_particles* p, bool need_vel);

@@ -15,7 +15,9 @@
 // in place (stable, so index order is kept).
 #include "vr_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 
 namespace vr {
 namespace {
@@ -165,17 +167,18 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
                                                  const double* __restrict__ acc, double eps2g, double scale,
                                                  double mass_value, double beta_E, double frac_ref, int n_min,
                                                  int n_ref_min, int frame_type, int gb, uint8_t* __restrict__ bound,
-                                                 double* __restrict__ phi, int* __restrict__ overflow) {
+                                                 double* __restrict__ phi, int max_iter) {
     __shared__ double smd[4 * 8];
     __shared__ uint32_t smu[8];
     __shared__ uint32_t hist[2048];
     __shared__ int cand[MAX_CAND];
-    __shared__ double cacc[MAX_CAND];
-    __shared__ int s_ncand, s_p, s_bucket;
+    __shared__ int s_p, s_bucket;
     __shared__ uint32_t s_below;
     __shared__ double s_min;
     __shared__ int s_minpos;
-    const int g = active[blockIdx.x];
+    // with no active list every group has a block and finished ones leave
+    const int g = active ? active[blockIdx.x] : (int)blockIdx.x;
+    if (!active && (state[g] != ST_ACTIVE || iters[g] >= max_iter)) return;
     const int base = off[g];
     const int n = cnt[g];
     const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6, nw = blockDim.x >> 6;
@@ -194,7 +197,6 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
         if (ob > best || (ob == best && op < bpos)) { best = ob; bpos = op; }
     }
     if (lane == 0) { smd[w] = best; smu[w] = (uint32_t)bpos; }
-    if (tid == 0) s_ncand = 0;
     __syncthreads();
     if (tid == 0) {
         double b = smd[0];
@@ -205,41 +207,43 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
         s_minpos = bp;
     }
     __syncthreads();
-    // 2. candidates within the FP32 error band of the extreme
+    // 2-3. every member within the FP32 error band of the extreme gets an
+    // exact FP64 sum; candidates are enumerated in position order, MAX_CAND
+    // at a time, so the result does not depend on how many there are.
     const double thr = s_min * (1.0 - REFINE_TOL);
-    for (int k = tid; k < n; k += blockDim.x)
-        if (acc[base + k] >= thr) {
-            const int c = atomicAdd(&s_ncand, 1);
-            if (c < MAX_CAND) cand[c] = k;
+    double cbest = -1.0;
+    int cpos = s_minpos;
+    for (uint32_t first = 0;; first += MAX_CAND) {
+        uint32_t seen = 0;
+        for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+            const int k = c0 + tid;
+            const bool in = k < n && acc[base + k] >= thr;
+            uint32_t tot;
+            const uint32_t r = seen + bscan(in ? 1u : 0u, smu, &tot);
+            if (in && r >= first && r < first + MAX_CAND) cand[r - first] = k;
+            seen += tot;
         }
-    __syncthreads();
-    const int ncand = min(s_ncand, MAX_CAND);
-    if (tid == 0 && s_ncand > MAX_CAND) atomicAdd(overflow, 1);
-    // 3. exact FP64 sums for the candidates
-    for (int c = 0; c < ncand; ++c) {
-        const int pc = cand[c];
-        const double cx = (double)W.x[base + pc], cy = (double)W.y[base + pc], cz = (double)W.z[base + pc];
-        double s1[1] = {0.0};
-        for (int k = tid; k < n; k += blockDim.x) {
-            if (k == pc) continue;
-            const double dx = cx - (double)W.x[base + k], dy = cy - (double)W.y[base + k],
-                         dz = cz - (double)W.z[base + k];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (eps2g == 0.0 && r2 == 0.0) continue;
-            const double m = uniform ? 1.0 : (double)W.m[base + k];
-            s1[0] += m / sqrt(r2 + eps2g);
+        __syncthreads();
+        const int ncand = (int)min(seen - first, (uint32_t)MAX_CAND);
+        for (int c = 0; c < ncand; ++c) {
+            const int pc = cand[c];
+            const double cx = (double)W.x[base + pc], cy = (double)W.y[base + pc], cz = (double)W.z[base + pc];
+            double s1[1] = {0.0};
+            for (int k = tid; k < n; k += blockDim.x) {
+                if (k == pc) continue;
+                const double dx = cx - (double)W.x[base + k], dy = cy - (double)W.y[base + k],
+                             dz = cz - (double)W.z[base + k];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (eps2g == 0.0 && r2 == 0.0) continue;
+                const double m = uniform ? 1.0 : (double)W.m[base + k];
+                s1[0] += m / sqrt(r2 + eps2g);
+            }
+            bsum<1>(s1, smd);
+            if (s1[0] > cbest || (s1[0] == cbest && pc < cpos)) { cbest = s1[0]; cpos = pc; }
         }
-        bsum<1>(s1, smd);
-        if (tid == 0) cacc[c] = s1[0];
+        if (first + MAX_CAND >= seen) break;
     }
-    __syncthreads();
-    if (tid == 0) {
-        int bp = s_minpos;
-        double b = -1.0;
-        for (int c = 0; c < ncand; ++c)
-            if (cacc[c] > b || (cacc[c] == b && cand[c] < bp)) { b = cacc[c]; bp = cand[c]; }
-        s_p = bp;
-    }
+    if (tid == 0) s_p = cpos;
     __syncthreads();
     const int p = s_p;
     // 4. velocity frame
@@ -343,10 +347,286 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
     }
 }
 
+// ---- persistent, graph-replayed passes -------------------------------------
+// Device-side plan of one pass: the active groups in the given order (the
+// group tables come in decreasing size, so the largest work is queued first)
+// and the prefix of their work-item counts; item = (i-tile of 64, j-range).
+struct UbPlan {
+    int n_active;     // groups scheduled in this pass
+    int total_items;
+    int head;         // work-queue head
+    int remaining;    // groups still active after the pass (read by the host)
+    int stuck;        // active groups that reached max_iter
+    int pad[3];
+    double pairs;     // ordered pairs scheduled since the last reset
+};
+
+__global__ void k_ub_plan_reset(UbPlan* plan) {
+    if (threadIdx.x == 0) plan->pairs = 0.0;
+}
+
+constexpr int PLAN_T = 1024;
+
+__global__ __launch_bounds__(PLAN_T) void k_ub_plan(int ng, const int* __restrict__ cnt, const int* __restrict__ state,
+                                                    const int32_t* __restrict__ iters, int max_iter, int jchunk,
+                                                    int* __restrict__ act, int* __restrict__ item_off, UbPlan* plan) {
+    __shared__ uint32_t sm[32];
+    __shared__ double smd[PLAN_T / 64];
+    uint32_t carry_g = 0, carry_i = 0;
+    double pairs = 0.0;
+    for (int base = 0; base < ng; base += PLAN_T) {
+        const int g = base + (int)threadIdx.x;
+        const bool on = g < ng && state[g] == ST_ACTIVE && iters[g] < max_iter;
+        const int n = on ? cnt[g] : 0;
+        pairs += (double)n * (double)(n > 0 ? n - 1 : 0);
+        const uint32_t items = on ? (uint32_t)(((n + 63) / 64) * ((n + jchunk - 1) / jchunk)) : 0u;
+        uint32_t tg, ti;
+        const uint32_t pg = bscan(on ? 1u : 0u, sm, &tg);
+        const uint32_t pi = bscan(items, sm, &ti);
+        if (on) {
+            act[carry_g + pg] = g;
+            item_off[carry_g + pg] = (int)(carry_i + pi);
+        }
+        carry_g += tg;
+        carry_i += ti;
+    }
+    pairs = wsum(pairs);
+    if (__lane_id() == 0) smd[threadIdx.x >> 6] = pairs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tp = 0.0;
+        for (int k = 0; k < PLAN_T / 64; ++k) tp += smd[k];
+        item_off[carry_g] = (int)carry_i;
+        plan->n_active = (int)carry_g;
+        plan->total_items = (int)carry_i;
+        plan->head = 0;
+        plan->pairs += tp;
+    }
+}
+
+__global__ void k_ub_zero_p(const UbPlan* __restrict__ plan, const int* __restrict__ act,
+                            const int32_t* __restrict__ off, const int* __restrict__ cnt, double* __restrict__ acc) {
+    if ((int)blockIdx.x >= plan->n_active) return;
+    const int g = act[blockIdx.x];
+    const int s = off[g], e = s + cnt[g];
+    for (int k = s + threadIdx.x; k < e; k += blockDim.x) acc[k] = 0.0;
+}
+
+// Persistent potential kernel: every wavefront pops items until the queue is
+// empty; lane = one i of a 64-row tile, j staged through the wave's LDS slice.
+template <bool UNIFORM>
+__global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* __restrict__ act,
+                                                       const int* __restrict__ item_off, const int32_t* __restrict__ off,
+                                                       const int* __restrict__ cnt, Members W, float eps2,
+                                                       double* __restrict__ acc, int jchunk, int tile) {
+    extern __shared__ float4 sjall[];
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    float4* sj = sjall + wv * tile;
+    const int na = plan->n_active, total = plan->total_items;
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(&plan->head, 1);
+        it = __shfl(it, 0, 64);
+        if (it >= total) break;
+        // the group holding item `it`
+        int lo = 0, hi = na - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_off[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const int g = act[lo];
+        const int base = off[g], n = cnt[g];
+        const int njc = (n + jchunk - 1) / jchunk;
+        const int local = it - item_off[lo];
+        const int i0 = (local / njc) * 64, j0 = (local % njc) * jchunk;
+        const int j1 = min(n, j0 + jchunk);
+        const int i = i0 + lane;
+        const bool valid = i < n;
+        const float xi = valid ? W.x[base + i] : 0.f, yi = valid ? W.y[base + i] : 0.f, zi = valid ? W.z[base + i] : 0.f;
+        double accd = 0.0;
+        for (int jb = j0; jb < j1; jb += tile) {
+            const int jn = min(tile, j1 - jb);
+            __builtin_amdgcn_wave_barrier();
+            for (int t = lane; t < jn; t += 64) {
+                const int k = base + jb + t;
+                sj[t] = make_float4(W.x[k], W.y[k], W.z[k], UNIFORM ? 1.f : W.m[k]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int t0 = 0; t0 < jn; t0 += 64) {
+                const int t1 = min(t0 + 64, jn);
+                float accf = 0.f;
+                for (int t = t0; t < t1; ++t) {
+                    const float4 q = sj[t];
+                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+                    const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                    const float rinv = (jb + t != i && s2 > 0.f) ? rsqrtf(s2) : 0.f;
+                    accf = UNIFORM ? accf + rinv : fmaf(q.w, rinv, accf);
+                }
+                accd += (double)accf;
+            }
+        }
+        if (valid) atomicAdd(&acc[base + i], accd);
+    }
+}
+
+__global__ __launch_bounds__(PLAN_T) void k_ub_count(int ng, const int* __restrict__ state,
+                                                     const int32_t* __restrict__ iters, int max_iter, UbPlan* plan) {
+    __shared__ uint32_t sm[32];
+    uint32_t rem = 0, stuck = 0;
+    for (int g = threadIdx.x; g < ng; g += PLAN_T) {
+        if (state[g] != ST_ACTIVE) continue;
+        if (iters[g] < max_iter) ++rem; else ++stuck;
+    }
+    uint32_t tr, ts;
+    bscan(rem, sm, &tr);
+    bscan(stuck, sm, &ts);
+    if (threadIdx.x == 0) {
+        plan->remaining = (int)tr;
+        plan->stuck = (int)ts;
+    }
+}
+
 }  // namespace
 }  // namespace vr
 
 using namespace vr;
+
+namespace {
+
+constexpr int PERSIST_MAX_TILE = 1024;  // 4 waves x tile x 16 B of LDS per workgroup
+constexpr int PASSES_PER_GRAPH = 4;
+
+// Everything a captured pass depends on; a cached graph is reused only when
+// all of it is unchanged.
+struct UbGraphKey {
+    const void* ptrs[16];
+    int ints[12];
+    double dbls[6];
+};
+
+void ub_graph_release(vr_ctx* ctx) {
+    if (ctx->ub_exec) (void)hipGraphExecDestroy((hipGraphExec_t)ctx->ub_exec);
+    if (ctx->ub_graph) (void)hipGraphDestroy((hipGraph_t)ctx->ub_graph);
+    ctx->ub_exec = nullptr;
+    ctx->ub_graph = nullptr;
+    ctx->ub_key.clear();
+}
+
+// One pass = plan (active list and work items) -> zero the accumulators of
+// the active groups -> persistent potential over the item queue -> one
+// workgroup per active group for frame, energies and compaction.  Passes are
+// captured PASSES_PER_GRAPH at a time in a graph that is replayed until no
+// group is active; the host reads two counters per replay.
+int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int32_t* offsets,
+                      const vr_unbind_params* up, const Members& W, double* acc, int* cnt, int* state,
+                      int32_t* iters, uint8_t* bound, double* phi, int* act, float eps2f, double eps2g,
+                      double scale, int tile, hipStream_t st) {
+    VR_WS(plan, ctx, UbPlan, WS_D4, 1);
+    VR_WS(item_off, ctx, int, WS_D5, (int64_t)ng + 1);
+    const bool uniform = W.m == nullptr;
+    const int jchunk = ctx->unbind_jchunk;
+    const size_t lds = (size_t)(UB / 64) * tile * sizeof(float4);
+    int bpc = 0;
+    if (uniform)
+        VR_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_ub_potential_p<true>, UB, lds));
+    else
+        VR_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_ub_potential_p<false>, UB, lds));
+    if (ctx->unbind_bpc > 0 && ctx->unbind_bpc < bpc) bpc = ctx->unbind_bpc;
+    if (bpc < 1) bpc = 1;
+    const unsigned pgrid = (unsigned)(ctx->num_cus * bpc);
+
+    UbGraphKey key;
+    std::memset(&key, 0, sizeof key);
+    const void* kp[16] = {offsets, W.gidx, W.x, W.y, W.z, W.vx, W.vy, W.vz, W.m, acc, cnt, state, iters, bound, phi,
+                          act};
+    std::memcpy(key.ptrs, kp, sizeof kp);
+    const int ki[12] = {ng, up->max_iter, jchunk, tile, (int)pgrid, up->n_min, up->n_ref_min, up->frame_type,
+                        p->grid_bits, uniform ? 1 : 0, 0, 0};
+    std::memcpy(key.ints, ki, sizeof ki);
+    const double kd[6] = {(double)eps2f, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref};
+    std::memcpy(key.dbls, kd, sizeof kd);
+    // plan and item_off are workspace too: their addresses are part of the key
+    std::string kbytes((const char*)&key, sizeof key);
+    kbytes.append((const char*)&plan, sizeof plan);
+    kbytes.append((const char*)&item_off, sizeof item_off);
+
+    if (!ctx->ub_exec || ctx->ub_key != kbytes) {
+        ub_graph_release(ctx);
+        if (!ctx->cap_stream) VR_HIP(ctx, hipStreamCreateWithFlags((hipStream_t*)&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = (hipStream_t)ctx->cap_stream;
+        VR_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < PASSES_PER_GRAPH; ++k) {
+            hipLaunchKernelGGL(k_ub_plan, dim3(1), dim3(PLAN_T), 0, cs, ng, cnt, state, iters, up->max_iter, jchunk,
+                               act, item_off, plan);
+            hipLaunchKernelGGL(k_ub_zero_p, dim3(ng), dim3(256), 0, cs, plan, act, offsets, cnt, acc);
+            if (uniform)
+                hipLaunchKernelGGL(k_ub_potential_p<true>, dim3(pgrid), dim3(UB), lds, cs, plan, act, item_off,
+                                   offsets, cnt, W, eps2f, acc, jchunk, tile);
+            else
+                hipLaunchKernelGGL(k_ub_potential_p<false>, dim3(pgrid), dim3(UB), lds, cs, plan, act, item_off,
+                                   offsets, cnt, W, eps2f, acc, jchunk, tile);
+            hipLaunchKernelGGL(k_ub_group, dim3(ng), dim3(UB), 0, cs, (const int*)nullptr, offsets, cnt, state,
+                               iters, W, acc, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min,
+                               up->n_ref_min, up->frame_type, p->grid_bits, bound, phi, up->max_iter);
+        }
+        hipLaunchKernelGGL(k_ub_count, dim3(1), dim3(PLAN_T), 0, cs, ng, state, iters, up->max_iter, plan);
+        hipGraph_t graph = nullptr;
+        const hipError_t le = hipGetLastError();
+        const hipError_t ce = hipStreamEndCapture(cs, &graph);
+        if (le != hipSuccess || ce != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return set_err(ctx, VR_ERR_HIP, "capturing the unbinding passes failed: %s",
+                           hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        ctx->ub_graph = graph;
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            ub_graph_release(ctx);
+            return set_err(ctx, VR_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        }
+        ctx->ub_exec = exec;
+        ctx->ub_key = kbytes;
+    }
+
+    hipLaunchKernelGGL(k_ub_plan_reset, dim3(1), dim3(64), 0, st, plan);
+    VR_LAUNCH_CHECK(ctx);
+    hipEvent_t e0 = nullptr;
+    if (ctx->timing) {
+        e0 = timer_event(ctx);
+        (void)hipEventRecord(e0, st);
+    }
+    int* counters = reinterpret_cast<int*>(ctx->pinned);
+    for (int launch = 0;; ++launch) {
+        VR_HIP(ctx, hipGraphLaunch((hipGraphExec_t)ctx->ub_exec, st));
+        VR_HIP(ctx, hipMemcpyAsync(counters, &plan->remaining, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipStreamSynchronize(st));
+        if (counters[0] == 0) break;
+        // every replay advances each remaining group by PASSES_PER_GRAPH
+        // passes, so the loop ends after max_iter / PASSES_PER_GRAPH replays
+        if ((int64_t)launch * PASSES_PER_GRAPH > (int64_t)up->max_iter + PASSES_PER_GRAPH)
+            return set_err(ctx, VR_ERR_HIP, "unbinding replays did not advance");
+    }
+    const int stuck = counters[1];
+    double pairs = 0.0;
+    if (ctx->timing) {
+        hipEvent_t e1 = timer_event(ctx);
+        (void)hipEventRecord(e1, st);
+        VR_HIP(ctx, hipMemcpyAsync(ctx->pinned, &plan->pairs, sizeof(double), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipStreamSynchronize(st));
+        std::memcpy(&pairs, ctx->pinned, sizeof(double));
+        timer_push(ctx, "unbind_persistent", e0, e1, pairs);
+    }
+    if (stuck > 0)
+        return set_err(ctx, VR_ERR_NOT_CONVERGED, "%d groups still lose members after %d passes", stuck, up->max_iter);
+    return VR_OK;
+}
+
+}  // namespace
+
+namespace vr {
+void unbind_release(vr_ctx* ctx) { ub_graph_release(ctx); }
+}  // namespace vr
 
 extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, const int32_t* offsets,
                          const int32_t* members, const vr_unbind_params* up, uint8_t* bound, double* phi,
@@ -386,9 +666,6 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     VR_WS(cnt, ctx, int, WS_D0, n_groups);
     VR_WS(state, ctx, int, WS_D1, n_groups);
     VR_WS(act, ctx, int, WS_D2, n_groups);
-    VR_WS(ovf, ctx, int, WS_FLAG2, 4);
-    rc = fill_i32(ctx, ovf, 0, 1, st);
-    if (rc) return rc;
     hipLaunchKernelGGL(k_ub_init, dim3(n_groups), dim3(256), 0, st, n_groups, offsets, members, p->qx, p->qy, p->qz,
                        p->vx, p->vy, p->vz, p->mass, p->grid_bits, up->n_min, W, cnt, state, iters, bound, phi);
     VR_LAUNCH_CHECK(ctx);
@@ -398,6 +675,9 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     const float eps2f = (float)eps2g;
     const double scale = -up->G / unit;  // potential = scale * mass * sum(1/r) in grid units
     int tile = up->tile ? up->tile : (ctx->tuned_tile ? ctx->tuned_tile : 256);
+    if (up->persistent)
+        return unbind_persistent(ctx, p, n_groups, offsets, up, W, acc, cnt, state, iters, bound, phi, act,
+                                 eps2f, eps2g, scale, std::min(tile, PERSIST_MAX_TILE), st);
     std::vector<int> hcnt(n_groups), hstate(n_groups), hact;
     std::vector<int4> items;
     for (int pass = 0;; ++pass) {
@@ -441,7 +721,7 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
         VR_TIMED(ctx, "unbind_group", st, nmem,
                  hipLaunchKernelGGL(k_ub_group, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, acc,
                                     eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min, up->n_ref_min,
-                                    up->frame_type, p->grid_bits, bound, phi, ovf));
+                                    up->frame_type, p->grid_bits, bound, phi, up->max_iter));
         VR_LAUNCH_CHECK(ctx);
     }
     return VR_OK;

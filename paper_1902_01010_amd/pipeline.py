@@ -12,7 +12,8 @@ import torch
 
 from . import vr as _vr
 
-KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group")
+KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group",
+           "unbind_persistent")
 
 
 @dataclasses.dataclass

@@ -6,6 +6,8 @@ bound flags) are bit-exact; FP64 reductions agree to round-off (rtol 1e-10);
 R agrees to 1e-4 max(1, |R|) (the outlier classification is compared outside
 that band); potentials agree to 1e-5 relative.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -151,15 +153,21 @@ def _unbind_case(seed, n_groups, n_max, masses=False):
     return w
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("seed,ng,nmax,masses,frame", [(3, 40, 4000, False, 1), (4, 25, 3000, True, 1),
                                                         (5, 25, 3000, False, 0)])
-def test_unbind_parity(ctx, vr, ref, seed, ng, nmax, masses, frame):
+def test_unbind_parity(ctx, vr, ref, seed, ng, nmax, masses, frame, persistent):
     w = _unbind_case(seed, ng, nmax, masses)
     P, Pr = both(ctx, vr, ref, w)
     off, mem = w.groups
     G, eps = w.params["G"], w.params["eps"]
     exp = ref.unbind(Pr, off, mem, G, eps, frame_type=frame)
-    got = ctx.unbind(P, dev_tensor(off), dev_tensor(mem), G, eps, frame_type=frame)
+    got = ctx.unbind(P, dev_tensor(off), dev_tensor(mem), G, eps, frame_type=frame, persistent=persistent)
+    _check_unbind(w, exp, got)
+
+
+def _check_unbind(w, exp, got):
+    off, mem = w.groups
     gb, gphi, git = (got[k].cpu().numpy() for k in ("bound", "phi", "iters"))
     clean = exp["min_margin"] > 1e-5
     assert clean.mean() > 0.8
@@ -175,10 +183,58 @@ def test_unbind_parity(ctx, vr, ref, seed, ng, nmax, masses, frame):
     assert (gb[con] == 0).all()
 
 
-def test_unbind_not_converged(ctx, vr, ref):
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_unbind_not_converged(ctx, vr, ref, persistent):
     w = _unbind_case(3, 3, 800)
     P, _ = both(ctx, vr, ref, w)
     off, mem = w.groups
     with pytest.raises(vr.VrError) as e:
-        ctx.unbind(P, dev_tensor(off), dev_tensor(mem), w.params["G"], w.params["eps"], max_iter=1)
+        ctx.unbind(P, dev_tensor(off), dev_tensor(mem), w.params["G"], w.params["eps"], max_iter=1,
+                   persistent=persistent)
     assert e.value.code == vr.VR_ERR_NOT_CONVERGED
+
+
+def test_unbind_persistent_launch_shapes_and_graph_reuse(ctx, vr, ref):
+    """The persistent path with work items split into several j-ranges,
+    small tiles and few workgroups per CU, called twice in a row with the
+    same arguments (cached graph replayed) and then on a smaller group set
+    (graph captured again); every call matches the oracle."""
+    w = _unbind_case(6, 30, 5000)
+    P, Pr = both(ctx, vr, ref, w)
+    off, mem = w.groups
+    G, eps = w.params["G"], w.params["eps"]
+    exp = ref.unbind(Pr, off, mem, G, eps)
+    saved = {k: ctx.get_tune(k) for k in ("unbind_jchunk", "unbind_bpc")}
+    try:
+        ctx.tune("unbind_jchunk", 256)
+        ctx.tune("unbind_bpc", 1)
+        offd, memd = dev_tensor(off), dev_tensor(mem)
+        for _ in range(2):
+            _check_unbind(w, exp, ctx.unbind(P, offd, memd, G, eps, tile=64))
+        ng2 = 7
+        off2, mem2 = off[:ng2 + 1].copy(), mem[:off[ng2]].copy()
+        exp2 = ref.unbind(Pr, off2, mem2, G, eps)
+        got2 = ctx.unbind(P, dev_tensor(off2), dev_tensor(mem2), G, eps, tile=64)
+        w2 = dataclasses.replace(w, groups=(off2, mem2), meta=dict(w.meta, is_contaminant=np.zeros(w.n, bool)))
+        _check_unbind(w2, exp2, got2)
+        assert (got2["bound"].cpu().numpy()[mem[off[ng2]:]] == 0).all()
+    finally:
+        for k, v in saved.items():
+            ctx.tune(k, v)
+
+
+def test_unbind_persistent_matches_host_planned(ctx, vr, ref):
+    """Both schedules run the same passes: identical bound flags and pass
+    counts, potentials equal up to the order of the FP64 partial sums."""
+    w = _unbind_case(7, 60, 3000)
+    P, _ = both(ctx, vr, ref, w)
+    off, mem = w.groups
+    G, eps = w.params["G"], w.params["eps"]
+    a = ctx.unbind(P, dev_tensor(off), dev_tensor(mem), G, eps, persistent=0)
+    b = ctx.unbind(P, dev_tensor(off), dev_tensor(mem), G, eps, persistent=1)
+    assert torch.equal(a["bound"], b["bound"])
+    assert torch.equal(a["iters"], b["iters"])
+    pa, pb = a["phi"].cpu().numpy(), b["phi"].cpu().numpy()
+    assert (np.isfinite(pa) == np.isfinite(pb)).all()
+    f = np.isfinite(pa)
+    np.testing.assert_allclose(pb[f], pa[f], rtol=1e-9)
