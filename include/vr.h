@@ -71,6 +71,8 @@ int vr_set_timing(vr_ctx* ctx, int enabled);
  * "unbind_jchunk" j-range of one potential work item (256..65536, 4096)
  * "unbind_bpc"    workgroups per CU of the persistent potential kernel
  *                 (0..8, 0 = as many as fit)
+ * "xcd_chunk"     consecutive workgroups of the kNN and linking sweeps kept
+ *                 on one XCD (0..4096, 64; 0 = the dispatcher's order)
  * Returns VR_ERR_INVALID_ARG for an unknown knob or a value out of range;
  * vr_get_tune reads a knob back. */
 int vr_tune(vr_ctx* ctx, const char* knob, int value);

@@ -210,6 +210,9 @@ int vr_tune(vr_ctx* ctx, const char* knob, int value) {
     } else if (k == "unbind_jchunk") {
         if (value < 256 || value > 65536) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_jchunk must be in 256..65536");
         ctx->unbind_jchunk = value;
+    } else if (k == "xcd_chunk") {
+        if (value < 0 || value > 4096) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "xcd_chunk must be in 0..4096");
+        ctx->xcd_chunk = value;
     } else if (k == "unbind_bpc") {
         if (value < 0 || value > 8) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_bpc must be in 0..8");
         ctx->unbind_bpc = value;
@@ -226,6 +229,7 @@ int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value) {
     else if (k == "unbind_tile") *value = ctx->tuned_tile ? ctx->tuned_tile : 256;
     else if (k == "unbind_jchunk") *value = ctx->unbind_jchunk;
     else if (k == "unbind_bpc") *value = ctx->unbind_bpc;
+    else if (k == "xcd_chunk") *value = ctx->xcd_chunk;
     else return VR_ERR_INVALID_ARG;
     return VR_OK;
 }

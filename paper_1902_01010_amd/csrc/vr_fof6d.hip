@@ -157,8 +157,9 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
                                                 const int32_t* __restrict__ shost, const double* __restrict__ ellv,
                                                 const uint32_t* __restrict__ cell_start,
                                                 const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
-                                                uint32_t hmask, int b, int gb, double ell2, int* parent) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                uint32_t hmask, int b, int gb, double ell2, int* parent,
+                                                unsigned xchunk) {
+    const int64_t p = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const uint32_t k = key[p];
     const int nc = 1 << b;
@@ -349,12 +350,12 @@ extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_
         VR_TIMED(ctx, "fof_link6d", st, np,
                  hipLaunchKernelGGL(k_link6d<true>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx,
                                     cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals,
-                                    cl.hmask, b, gb, ell2, parent));
+                                    cl.hmask, b, gb, ell2, parent, (unsigned)ctx->xcd_chunk));
     else
         VR_TIMED(ctx, "fof_link6d", st, np,
                  hipLaunchKernelGGL(k_link6d<false>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx,
                                     cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals,
-                                    cl.hmask, b, gb, ell2, parent));
+                                    cl.hmask, b, gb, ell2, parent, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     rc = fill_i32(ctx, mn, 0x7FFFFFFF, np, st);
     if (rc) return rc;

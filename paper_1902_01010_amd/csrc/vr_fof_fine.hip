@@ -93,8 +93,8 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                    const uint32_t* __restrict__ sz,
                                                    const uint32_t* __restrict__ row_start, FineGrid G, double ell2,
-                                                   int* parent) {
-    const int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                   int* parent, unsigned xchunk) {
+    const int64_t A = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (A >= nfine) return;
     const uint32_t a0 = fine_start[A], a1 = fine_start[A + 1];
     const uint64_t ka = key[a0];
@@ -249,7 +249,7 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     VR_LAUNCH_CHECK(ctx);
     VR_TIMED(ctx, "fof_link3d", st, n,
              hipLaunchKernelGGL(k_link_fine, dim3(grid_for(nfine, 256)), dim3(256), 0, st, (int64_t)nfine, fine_start,
-                                fid, key, sx, sy, sz, row_start, G, ell2, parent));
+                                fid, key, sx, sy, sz, row_start, G, ell2, parent, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_compress_f, dim3(gn), dim3(256), 0, st, n, parent);
     VR_LAUNCH_CHECK(ctx);

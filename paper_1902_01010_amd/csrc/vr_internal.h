@@ -44,6 +44,7 @@ struct vr_ctx {
     int knn_leaf = 64;      // members per leaf of the neighbour-search tree
     int unbind_jchunk = 4096;
     int unbind_bpc = 0;     // workgroups per CU of the persistent potential kernel (0 = occupancy limit)
+    int xcd_chunk = 64;     // consecutive workgroups per XCD in the neighbour sweeps (0 = hardware order)
     // graph of the persistent unbinding passes, reused while its arguments match
     void* cap_stream = nullptr;
     void* ub_graph = nullptr;
@@ -162,6 +163,20 @@ __device__ __forceinline__ int min_image(int d, int gb) {
 }
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// The dispatcher deals workgroups to the eight XCDs in turn.  This renumbers
+// workgroup b of nb so that each XCD takes runs of `chunk` consecutive
+// workgroups: spatially neighbouring work shares one XCD's L2, while the
+// runs still rotate over the XCDs, which keeps their loads balanced.  A
+// bijection of [0, nb); chunk = 0 leaves the numbering alone.
+__device__ __forceinline__ unsigned xcd_swizzle(unsigned b, unsigned nb, unsigned chunk) {
+    if (chunk == 0) return b;
+    const unsigned span = 8u * chunk;
+    const unsigned full = nb - nb % span;
+    if (b >= full) return b;
+    const unsigned s = b / span, w = b % span;
+    return s * span + (w & 7u) * chunk + (w >> 3);
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned l = __lane_id();

@@ -96,14 +96,14 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                                             const float* __restrict__ Me, const int* __restrict__ elem_host,
                                             const int32_t* __restrict__ host_off, const float* __restrict__ vbar,
                                             const float* __restrict__ sigma, int64_t n, int n_se, int n_v, int use_mass,
-                                            double mass_value, int gb, float* __restrict__ R) {
+                                            double mass_value, int gb, float* __restrict__ R, unsigned xchunk) {
     constexpr int NVL = NVR > 0 ? 1 : NSE;
     __shared__ uint64_t heap[NSE][64];
     __shared__ double vd[NVL][64];
     __shared__ int vp[NVL][64];
     __shared__ int stack[STACK];
     const int lane = threadIdx.x;
-    const int64_t qi = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t qi = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * 64 + lane;
     const bool active = qi < nq;
     const int e = active ? (qpos ? (int)qpos[qi] : (int)qi) : 0;
     const int h = active ? elem_host[e] : -1;
@@ -325,7 +325,7 @@ int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree
     VR_TIMED(ctx, "knn", st, nq,
              hipLaunchKernelGGL((k_knn<NSE, NVR>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
                                 tree.F, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n, n_se, n_v,
-                                tree.use_mass, p->mass_value, p->grid_bits, R));
+                                tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
