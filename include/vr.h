@@ -207,6 +207,71 @@ int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, const int32_
               const int32_t* members, const vr_unbind_params* up, uint8_t* bound, double* phi,
               int32_t* iters, void* stream);
 
+/* ---- learned surrogate of R ------------------------------------------------
+ * Predicts the R of vr_local_vdensity from 12 cheap per-particle features
+ * (no neighbour search) with a 12-64-64-64-1 ReLU network; particles whose
+ * prediction lies within a margin of the threshold get the exact R. */
+
+/* Features of every host member (rows in host_members order, m rows =
+ * host_offsets[n_hosts], written to *n_rows; syncs), as BF16 bit patterns,
+ * row-major [m][12], each (x - shift[k]) * scale[k] (shift, scale: HOST
+ * arrays of 12, or NULL for 0 and 1).  With Sigma = sigma(x) of the particle
+ * (eigenvalues l1 <= l2 <= l3, unit eigenvectors e_a), dv = v - vbar(x):
+ *  0     ln rhat, rhat = (3 n_se / (4 pi nhat))^(1/3), nhat = the member count
+ *        of the 27 cells of side f = 2^cell_bits grid units around the
+ *        particle over their volume, or of the 27 cells of side 4f when the
+ *        fine window holds fewer than n_se members;
+ *  1..3  |dv . e_a| / sqrt(l_a);      4..6  ln l_a;      7  ln rho_cell;
+ *  8..10 |(vloc - vbar) . e_a| / sqrt(l_a), vloc = mean velocity of the
+ *        members in the particle's fine cell and its 6 face neighbours;
+ *  11    |v - vloc| / sqrt((l1 + l2 + l3) / 3).
+ * Cells count the members of all listed hosts.  Features 1..11 are NaN if
+ * Sigma is not positive definite.  0 <= cell_bits <= grid_bits - 4. */
+int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
+                   const int32_t* host_members, const float* vbar, const float* sigma, const float* rho_cell,
+                   int32_t n_se, int32_t cell_bits, const float* shift, const float* scale, uint16_t* feat,
+                   int64_t* n_rows, void* stream);
+
+/* Network parameters: one device FP32 vector of VR_MLP_PARAMS values,
+ * W1[12][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], w4[64], b4
+ * (W[i][o] connects input i to output o). */
+#define VR_MLP_PARAMS 9217
+
+/* Rhat[i] for the m feature rows: BF16 inputs, weights and hidden
+ * activations on MFMA with FP32 accumulation, ReLU, FP32 last layer;
+ * NaN for rows with a NaN feature. */
+int vr_mlp_forward(vr_ctx* ctx, const float* weights, int64_t m, const uint16_t* feat, float* Rhat,
+                   void* stream);
+
+/* Gradient (device FP32 [VR_MLP_PARAMS]) of the mean squared error
+ * mean_b (Rhat(row_b) - target[row_b])^2 over a batch of m rows; rows
+ * (device, m entries) picks the rows of feat/target, NULL = rows 0..m-1.
+ * The forward pass is that of vr_mlp_forward; errors flow down through BF16
+ * MFMA products with FP32 accumulation.  loss (device, may be NULL)
+ * receives the batch loss. */
+int vr_mlp_grad(vr_ctx* ctx, const float* weights, int64_t m, const uint16_t* feat, const int32_t* rows,
+                const float* target, float* grad, float* loss, void* stream);
+
+typedef struct {
+    float lr, beta1, beta2, eps;   /* Adam (Kingma & Ba), e.g. 1e-3, 0.9, 0.999, 1e-8 */
+} vr_adam_params;
+
+/* One Adam step (step >= 1, for the bias correction) on the FP32 master
+ * weights with the vr_mlp_grad gradient of the batch; adam_state (device)
+ * holds the first and second moments, 2 * VR_MLP_PARAMS floats, zero at
+ * step 1. */
+int vr_mlp_train_step(vr_ctx* ctx, float* weights, float* adam_state, int64_t m, const uint16_t* feat,
+                      const int32_t* rows, const float* target, const vr_adam_params* ap, int32_t step,
+                      float* loss, void* stream);
+
+/* Band selection of the surrogate path: R[members[i]] = Rhat[i] for the m
+ * rows, and subset receives (in row order) members[i] of the rows with
+ * |Rhat[i] - R_threshold| < margin or Rhat[i] not finite; *n_subset (HOST)
+ * counts them.  Running vr_local_vdensity on the subset then replaces those
+ * entries by the exact R.  Syncs. */
+int vr_rs_select(vr_ctx* ctx, int64_t m, const int32_t* members, const float* Rhat, float R_threshold,
+                 float margin, float* R, int32_t* subset, int64_t* n_subset, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

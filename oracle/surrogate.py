@@ -104,32 +104,36 @@ def forward(w, X, bf16=True):
     return H3 @ w4 + b4[0]
 
 
-def loss_and_grad(w, X, y):
-    """Mean squared error and its exact gradient (FP64, no rounding)."""
+def loss_and_grad(w, X, y, bf16=False):
+    """Mean squared error and its gradient, FP64.  bf16=False: the exact
+    gradient of the unrounded network.  bf16=True: the arithmetic of the
+    training kernels written out: the forward pass of `forward(bf16=True)`,
+    and BF16 rounding of the two factors of every weight-gradient product
+    (errors and activations) and of the weights and errors that carry the
+    error down a layer; bias gradients, the last layer and the ReLU masks use
+    the unrounded values."""
     W1, b1, W2, b2, W3, b3, w4, b4 = unpack(w)
-    X = np.asarray(X, np.float64)
+    q = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))
+    X = q(np.asarray(X, np.float64))
     y = np.asarray(y, np.float64)
     m = X.shape[0]
-    Z1 = X @ W1 + b1
-    H1 = np.maximum(Z1, 0.0)
-    Z2 = H1 @ W2 + b2
-    H2 = np.maximum(Z2, 0.0)
-    Z3 = H2 @ W3 + b3
-    H3 = np.maximum(Z3, 0.0)
+    H1 = np.maximum(X @ q(W1) + b1, 0.0)
+    H2 = np.maximum(q(H1) @ q(W2) + b2, 0.0)
+    H3 = np.maximum(q(H2) @ q(W3) + b3, 0.0)
     out = H3 @ w4 + b4[0]
     r = out - y
     loss = np.mean(r * r)
     g = 2.0 * r / m                       # dL/dout
     gw4 = H3.T @ g
     gb4 = np.array([g.sum()])
-    d3 = np.outer(g, w4) * (Z3 > 0)       # dL/dZ3
-    gW3 = H2.T @ d3
+    d3 = np.outer(g, w4) * (H3 > 0)       # dL/dZ3 (Z > 0 exactly where H > 0)
+    gW3 = q(H2).T @ q(d3)
     gb3 = d3.sum(0)
-    d2 = (d3 @ W3.T) * (Z2 > 0)
-    gW2 = H1.T @ d2
+    d2 = (q(d3) @ q(W3).T) * (H2 > 0)
+    gW2 = q(H1).T @ q(d2)
     gb2 = d2.sum(0)
-    d1 = (d2 @ W2.T) * (Z1 > 0)
-    gW1 = X.T @ d1
+    d1 = (q(d2) @ q(W2).T) * (H1 > 0)
+    gW1 = X.T @ q(d1)
     gb1 = d1.sum(0)
     return loss, pack([gW1, gb1, gW2, gb2, gW3, gb3, gw4, gb4])
 

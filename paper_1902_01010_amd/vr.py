@@ -24,7 +24,10 @@ ENTRY_POINTS = (
     "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
     "vr_host_ellv", "vr_fof6d", "vr_unbind",
+    "vr_rs_features", "vr_mlp_forward", "vr_mlp_grad", "vr_mlp_train_step", "vr_rs_select",
 )
+
+MLP_PARAMS = 9217
 
 
 class VrError(RuntimeError):
@@ -51,6 +54,10 @@ class _UnbindParams(C.Structure):
                 ("frac_ref", C.c_double), ("n_min", C.c_int32), ("n_ref_min", C.c_int32),
                 ("frame_type", C.c_int32), ("max_iter", C.c_int32), ("persistent", C.c_int32),
                 ("tile", C.c_int32)]
+
+
+class _AdamParams(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 _lib = None
@@ -80,17 +87,18 @@ def load_library():
         L.vr_quantize.argtypes = [vp, i64, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
         L.vr_fof3d.argtypes = [vp, P, dbl, vp, vp]
         L.vr_groups.argtypes = [vp, i64, vp, i32, C.POINTER(i32), vp, vp, vp, vp]
-        if hasattr(L, "vr_cell_moments"):
-            L.vr_cell_moments.argtypes = [vp, P, i32, vp, vp, C.POINTER(_CellParams), vp, vp, vp, vp,
-                                          i64, vp, C.POINTER(i64), vp]
-        if hasattr(L, "vr_local_vdensity"):
-            L.vr_local_vdensity.argtypes = [vp, P, i32, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
-        if hasattr(L, "vr_host_ellv"):
-            L.vr_host_ellv.argtypes = [vp, P, i32, vp, vp, dbl, vp, vp]
-        if hasattr(L, "vr_fof6d"):
-            L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
-        if hasattr(L, "vr_unbind"):
-            L.vr_unbind.argtypes = [vp, P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
+        L.vr_cell_moments.argtypes = [vp, P, i32, vp, vp, C.POINTER(_CellParams), vp, vp, vp, vp,
+                                      i64, vp, C.POINTER(i64), vp]
+        L.vr_local_vdensity.argtypes = [vp, P, i32, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
+        L.vr_host_ellv.argtypes = [vp, P, i32, vp, vp, dbl, vp, vp]
+        L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
+        L.vr_unbind.argtypes = [vp, P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
+        fp = C.POINTER(C.c_float)
+        L.vr_rs_features.argtypes = [vp, P, i32, vp, vp, vp, vp, vp, i32, i32, fp, fp, vp, C.POINTER(i64), vp]
+        L.vr_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.vr_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.vr_mlp_train_step.argtypes = [vp, vp, vp, i64, vp, vp, vp, C.POINTER(_AdamParams), i32, vp, vp]
+        L.vr_rs_select.argtypes = [vp, i64, vp, vp, flt, flt, vp, vp, C.POINTER(i64), vp]
         _lib = L
     return _lib
 
@@ -284,3 +292,54 @@ class Context:
         self._check(self.lib.vr_unbind(self.h, C.byref(P.s), ng, _ptr(offsets), _ptr(members), C.byref(up),
                                        _ptr(bound), _ptr(phi), _ptr(iters), _stream()))
         return dict(bound=bound, phi=phi, iters=iters[:ng])
+
+    # ---- learned surrogate of R ------------------------------------------------
+    def rs_features(self, P: Particles, host_offsets, host_members, vbar, sigma, rho_cell, n_se=32,
+                    cell_bits=9, shift=None, scale=None, feat=None):
+        """(m, 12) BF16 feature rows (int16 tensor of bit patterns) of the host members."""
+        nh = host_offsets.shape[0] - 1
+        if feat is None:
+            m = int(host_members.shape[0])
+            feat = torch.empty((max(m, 1), 12), dtype=torch.int16, device=P.device)
+        arr = C.c_float * 12
+        sh = None if shift is None else arr(*[float(x) for x in shift])
+        sc = None if scale is None else arr(*[float(x) for x in scale])
+        rows = C.c_int64(0)
+        self._check(self.lib.vr_rs_features(self.h, C.byref(P.s), nh, _ptr(host_offsets), _ptr(host_members),
+                                            _ptr(vbar), _ptr(sigma), _ptr(rho_cell), int(n_se), int(cell_bits),
+                                            sh, sc, _ptr(feat), C.byref(rows), _stream()))
+        return feat[:rows.value]
+
+    def mlp_forward(self, weights, feat, out=None):
+        m = feat.shape[0]
+        if out is None:
+            out = torch.empty(max(m, 1), dtype=torch.float32, device=feat.device)
+        self._check(self.lib.vr_mlp_forward(self.h, _ptr(weights), m, _ptr(feat), _ptr(out), _stream()))
+        return out[:m]
+
+    def mlp_grad(self, weights, feat, target, rows=None):
+        """(gradient, loss) of the mean squared error over the batch."""
+        m = feat.shape[0] if rows is None else rows.shape[0]
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feat.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        self._check(self.lib.vr_mlp_grad(self.h, _ptr(weights), m, _ptr(feat), _ptr(rows), _ptr(target),
+                                         _ptr(grad), _ptr(loss), _stream()))
+        return grad, loss
+
+    def mlp_train_step(self, weights, adam_state, feat, target, step, rows=None, lr=1e-3, beta1=0.9,
+                       beta2=0.999, eps=1e-8, loss=None):
+        m = feat.shape[0] if rows is None else rows.shape[0]
+        ap = _AdamParams(lr, beta1, beta2, eps)
+        self._check(self.lib.vr_mlp_train_step(self.h, _ptr(weights), _ptr(adam_state), m, _ptr(feat), _ptr(rows),
+                                               _ptr(target), C.byref(ap), int(step), _ptr(loss), _stream()))
+        return loss
+
+    def rs_select(self, members, Rhat, R, R_threshold=2.0, margin=0.5, subset=None):
+        """Writes R[members] = Rhat; returns the band's particle list."""
+        m = members.shape[0]
+        if subset is None:
+            subset = torch.empty(max(m, 1), dtype=torch.int32, device=members.device)
+        ns = C.c_int64(0)
+        self._check(self.lib.vr_rs_select(self.h, m, _ptr(members), _ptr(Rhat), float(R_threshold), float(margin),
+                                          _ptr(R), _ptr(subset), C.byref(ns), _stream()))
+        return subset[:ns.value]

@@ -1,0 +1,207 @@
+"""GPU parity of the learned-surrogate entry points (features, MLP forward,
+gradient, Adam step, band selection) against the CPU oracle.
+
+Tolerances (BF16 has an 8-bit significand, unit roundoff u = 2^-9):
+* features: both sides round the same FP64 value to BF16, so the bit
+  patterns agree except where the two FP64 evaluations straddle a rounding
+  boundary; at most one BF16 step apart, on at most 0.5% of the entries;
+* forward: the same BF16 operands on both sides; the sums differ only in
+  FP32-versus-FP64 accumulation, which can move a hidden activation across
+  a BF16 rounding boundary: |dRhat| <= 2e-2 max(1, |Rhat|), median far below;
+* gradient: against the oracle's model of the kernels' arithmetic (BF16
+  operands of every product, wide sums) the only differences are FP32 versus
+  FP64 sums and the BF16 roundings they flip: relative L2 error per parameter
+  block <= 5e-3; against the exact gradient of the unrounded network, where
+  a few roundings of u per operand chain add up, <= 6e-2 and cosine >= 0.998.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate as S
+from paper_1902_01010_amd import synth
+from tests.gpu_common import both, dev_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vr():
+    from paper_1902_01010_amd import vr as _vr
+    return _vr
+
+
+@pytest.fixture(scope="module")
+def ctx(vr):
+    return vr.Context(0)
+
+
+def _weights(seed, bias_scale=0.1):
+    rng = np.random.default_rng(seed + 1000)
+    w = S.init_params(seed).astype(np.float64)
+    parts = S.unpack(w)
+    for k in (1, 3, 5, 7):
+        parts[k][:] = rng.normal(scale=bias_scale, size=parts[k].shape)
+    return S.pack(parts).astype(np.float32)
+
+
+def _features(seed, m, nan_rows=()):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(m, 12)) * np.array([1, 2, 0.5, 1, 3, 1, 1, 2, 1, 1, 0.3, 1])
+    for r in nan_rows:
+        X[r, 4] = np.nan
+    return S.bf16_bits(X)
+
+
+def _dev_bits(bits):
+    return dev_tensor(bits.view(np.int16))
+
+
+@pytest.mark.parametrize("m", [1, 33, 1000, 4099])
+def test_mlp_forward_parity(ctx, m):
+    w = _weights(1)
+    bits = _features(2, m, nan_rows=[0] if m > 1 else [])
+    X = S.bf16_from_bits(bits)
+    exp = S.forward(w, X, bf16=True)
+    got = ctx.mlp_forward(dev_tensor(w), _dev_bits(bits)).cpu().numpy().astype(np.float64)
+    nan = np.isnan(exp)
+    assert (np.isnan(got) == nan).all()
+    err = np.abs(got[~nan] - exp[~nan]) / np.maximum(1.0, np.abs(exp[~nan]))
+    assert err.max() <= 2e-2, err.max()
+    assert np.median(err) <= 1e-4
+
+
+def test_mlp_forward_closed_form(ctx):
+    """The |x| network of the oracle pins, on the GPU: exact."""
+    W1 = np.zeros((12, 64)); W1[0, 0] = 1.0; W1[0, 1] = -1.0
+    W2 = np.zeros((64, 64)); W2[0, 0] = W2[1, 1] = 1.0
+    W3 = np.zeros((64, 64)); W3[0, 0] = W3[1, 1] = 1.0
+    w4 = np.zeros(64); w4[0] = w4[1] = 1.0
+    w = S.pack([W1, np.zeros(64), W2, np.zeros(64), W3, np.zeros(64), w4, [0.25]]).astype(np.float32)
+    X = np.zeros((70, 12)); X[:, 0] = np.linspace(-4, 4, 70); X[:, 3] = 9.0
+    bits = S.bf16_bits(X)
+    got = ctx.mlp_forward(dev_tensor(w), _dev_bits(bits)).cpu().numpy()
+    np.testing.assert_array_equal(got, np.abs(S.bf16_from_bits(bits)[:, 0]).astype(np.float32) + 0.25)
+
+
+def _block_errors(g, ref):
+    blocks = np.cumsum([0, 12 * 64, 64, 64 * 64, 64, 64 * 64, 64, 64, 1])
+    return [np.linalg.norm(g[a:b] - ref[a:b]) / max(np.linalg.norm(ref[a:b]), 1e-30)
+            for a, b in zip(blocks[:-1], blocks[1:])]
+
+
+@pytest.mark.parametrize("m,use_rows", [(300, True), (128, False), (37, False)])
+def test_mlp_gradient_parity(ctx, m, use_rows):
+    w = _weights(3)
+    n_all = 500
+    bits = _features(4, n_all)
+    rng = np.random.default_rng(5)
+    y_all = rng.normal(size=n_all) * 2
+    rows = rng.permutation(n_all)[:m].astype(np.int32) if use_rows else np.arange(m, dtype=np.int32)
+    X = S.bf16_from_bits(bits)[rows]
+    y = y_all[rows]
+    loss_model, g_model = S.loss_and_grad(w, X, y, bf16=True)
+    _, g_exact = S.loss_and_grad(w, X, y)
+    fd = _dev_bits(bits if use_rows else bits[:m])
+    g, loss = ctx.mlp_grad(dev_tensor(w), fd, dev_tensor(y_all.astype(np.float32)),
+                           rows=dev_tensor(rows) if use_rows else None)
+    g = g.cpu().numpy().astype(np.float64)
+    assert float(loss.item()) == pytest.approx(loss_model, rel=1e-4)
+    # the arithmetic model of the kernels (BF16 operands, wide sums)
+    assert max(_block_errors(g, g_model)) <= 5e-3, _block_errors(g, g_model)
+    # and the exact gradient of the unrounded network
+    assert max(_block_errors(g, g_exact)) <= 6e-2, _block_errors(g, g_exact)
+    assert g @ g_exact / (np.linalg.norm(g) * np.linalg.norm(g_exact)) >= 0.998
+
+
+def test_adam_first_step_against_oracle(ctx):
+    """Step 1 moves every weight by lr g / (|g| + eps) with the batch
+    gradient g; checked where the FP64 gradient is not tiny."""
+    w = _weights(6)
+    bits = _features(7, 256)
+    y = np.random.default_rng(8).normal(size=256).astype(np.float32)
+    _, g_ref = S.loss_and_grad(w, S.bf16_from_bits(bits), y, bf16=True)
+    wd = dev_tensor(w)
+    st = torch.zeros(2 * S.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    lr = 1e-3
+    ctx.mlp_train_step(wd, st, _dev_bits(bits), dev_tensor(y), 1, lr=lr, loss=loss)
+    step = wd.cpu().numpy().astype(np.float64) - w
+    big = np.abs(g_ref) > 1e-2 * np.abs(g_ref).max()
+    exp = -lr * g_ref / (np.abs(g_ref) + 1e-8)
+    assert big.sum() > 1000
+    np.testing.assert_allclose(step[big], exp[big], rtol=2e-2, atol=2e-6)
+    m1 = st[:S.MLP_PARAMS].cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(m1 - 0.1 * g_ref) <= 6e-2 * np.linalg.norm(0.1 * g_ref)
+
+
+def test_training_reduces_loss(ctx):
+    """A few hundred Adam steps on a smooth target lower the loss tenfold."""
+    rng = np.random.default_rng(9)
+    m = 4096
+    X = rng.normal(size=(m, 12))
+    y = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] - np.abs(X[:, 3])).astype(np.float32)
+    bits = S.bf16_bits(X)
+    fd, yd = _dev_bits(bits), dev_tensor(y)
+    wd = dev_tensor(_weights(10, bias_scale=0.0))
+    st = torch.zeros(2 * S.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    first = None
+    for step in range(1, 401):
+        rows = torch.randperm(m, device="cuda", generator=gen)[:512].to(torch.int32)
+        ctx.mlp_train_step(wd, st, fd, yd, step, rows=rows, lr=3e-3, loss=loss)
+        if first is None:
+            first = float(loss.item())
+    full = np.mean((ctx.mlp_forward(wd, fd).cpu().numpy() - y) ** 2)
+    assert full < 0.1 * first, (first, full)
+
+
+def test_rs_select_band(ctx):
+    rng = np.random.default_rng(12)
+    n, m = 5000, 3000
+    members = np.sort(rng.choice(n, m, replace=False)).astype(np.int32)
+    Rhat = rng.normal(2.0, 1.0, m).astype(np.float32)
+    Rhat[::97] = np.nan
+    Rhat[5] = np.inf
+    R = torch.full((n,), -7.0, device="cuda")
+    sub = ctx.rs_select(dev_tensor(members), dev_tensor(Rhat), R, 2.0, 0.3).cpu().numpy()
+    _, band = S.decide(Rhat, np.zeros(m), 2.0, 0.3)
+    np.testing.assert_array_equal(sub, members[band])
+    Rg = R.cpu().numpy()
+    np.testing.assert_array_equal(Rg[members], Rhat)
+    rest = np.setdiff1d(np.arange(n), members)
+    assert (Rg[rest] == -7.0).all()
+
+
+def _halo_hosts(ctx, vr, ref):
+    w = synth.isolated_halo(seed=31, n_host=20000, n_sub=4, sub_range=(500, 2000))
+    P, Pr = both(ctx, vr, ref, w)
+    lab = ref.fof3d(Pr, w.params["ellx"])
+    ng, gof, off, mem = ref.groups(lab, 20)
+    nh = int((np.diff(off) >= 256).sum())
+    hoff, hmem = off[:nh + 1].copy(), mem[:off[nh]].copy()
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    return w, P, Pr, hoff, hmem, cm
+
+
+@pytest.mark.parametrize("cell_bits", [12, 14])
+def test_features_parity(ctx, vr, ref, cell_bits):
+    w, P, Pr, hoff, hmem, cm = _halo_hosts(ctx, vr, ref)
+    shift = np.linspace(-1, 1, 12)
+    scale = np.linspace(0.5, 2.0, 12)
+    raw = S.features(Pr.q, w.v, hmem, cm["vbar"], cm["sigma"], cm["rho_cell"], 32, cell_bits, w.box, w.grid_bits)
+    exp = S.bf16_bits(S.normalise(raw, shift, scale))
+    got = ctx.rs_features(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(cm["vbar"]), dev_tensor(cm["sigma"]),
+                          dev_tensor(cm["rho_cell"]), 32, cell_bits, shift, scale)
+    got = got.cpu().numpy().view(np.uint16)
+    assert got.shape == exp.shape
+    ge, ee = S.bf16_from_bits(got), S.bf16_from_bits(exp)
+    nan = np.isnan(ee)
+    assert (np.isnan(ge) == nan).all()
+    diff = got.astype(np.int32) - exp.astype(np.int32)
+    assert (np.abs(diff[~nan]) <= 1).all()
+    assert (diff[~nan] != 0).mean() <= 5e-3
+    # both windows levels and both branches of the count rule occur
+    nf = np.exp(raw[:, 0])
+    assert nf.min() < nf.max()

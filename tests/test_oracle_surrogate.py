@@ -71,6 +71,36 @@ def test_mlp_gradient_matches_central_differences():
         assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i])), i
 
 
+def test_mlp_gradient_rounded_model_is_exact_on_representable_values():
+    """With small-integer weights, inputs and targets, sparse hidden layers and
+    a power-of-two batch, every operand the rounded model rounds (weights,
+    activations, errors) is already a BF16 number, so the model must equal the
+    exact gradient bit for bit."""
+    rng = np.random.default_rng(12)
+    parts = [rng.integers(-1, 2, (12, 64)), rng.integers(-2, 3, 64), rng.integers(-1, 2, (64, 64)) * (rng.random((64, 64)) < 0.05),
+             rng.integers(-2, 3, 64), rng.integers(-1, 2, (64, 64)) * (rng.random((64, 64)) < 0.05),
+             rng.integers(-2, 3, 64), rng.integers(-1, 2, 64), [1.0]]
+    w = S.pack(parts)
+    X = rng.integers(-3, 4, (16, 12)).astype(float)
+    y = rng.integers(-8, 9, 16).astype(float)
+    l0, g0 = S.loss_and_grad(w, X, y)
+    l1, g1 = S.loss_and_grad(w, X, y, bf16=True)
+    assert np.abs(g0).max() > 0
+    assert l0 == l1
+    np.testing.assert_array_equal(g0, g1)
+
+
+def test_mlp_gradient_rounded_model_close_to_exact():
+    rng = np.random.default_rng(13)
+    w = S.init_params(14).astype(np.float64)
+    X = rng.normal(size=(200, 12))
+    y = rng.normal(size=200)
+    _, g0 = S.loss_and_grad(w, S.bf16_round(X), y)
+    _, g1 = S.loss_and_grad(w, X, y, bf16=True)
+    assert np.linalg.norm(g1 - g0) / np.linalg.norm(g0) < 5e-2
+    assert not np.array_equal(g0, g1)
+
+
 def test_adam_first_step_closed_form_and_torch():
     rng = np.random.default_rng(2)
     w0 = rng.normal(size=50)
