@@ -22,6 +22,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 # Algorithmic work per unit of each timed kernel (the unit is what the
 # library accumulates per launch): bytes for memory-bound kernels, flops for
@@ -36,6 +37,8 @@ KERNEL_MODEL = {
     "unbind_potential": ("alu", 6.0, "ordered pair: 12 flop per unordered pair"),
     "unbind_group": ("hbm", 40.0, "member: coordinates, velocity, potential"),
     "unbind_persistent": ("alu", 6.0, "ordered pair, whole graph-replayed unbinding of one call"),
+    "rs_features": ("hbm", 76.0, "row: q 12, v 12, vbar 12, sigma 24, rho 4, member 4 in; 12 BF16 out"),
+    "mlp_forward": ("mfma", 18048.0, "row: 9,024 multiply-adds of the 12-64-64-64-1 network"),
 }
 
 
@@ -74,6 +77,29 @@ def profiled_traffic(kernel):
         return None
 
 
+def kernel_table(ctx, steps):
+    from paper_1902_01010_amd import pipeline
+
+    kernels = {}
+    for name in pipeline.KERNELS:
+        launches, ms, work = ctx.kernel_time(name)
+        if launches == 0 or name not in KERNEL_MODEL:
+            continue
+        bound, per_unit, _ = KERNEL_MODEL[name]
+        amount = work * per_unit / launches          # bytes or flops per launch
+        avg_s = ms / launches / 1e3
+        if bound == "alu":
+            achieved, peak, unit = amount / avg_s / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+        elif bound == "mfma":
+            achieved, peak, unit = amount / avg_s / 1e12, BF16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+        else:
+            achieved, peak, unit = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        kernels[name] = {"bound": bound, "launches_per_step": launches / steps, "ms_per_step": ms / steps,
+                         "avg_launch_ms": ms / launches, "achieved": achieved, "peak": peak, "unit": unit,
+                         "frac": achieved / peak}
+    return kernels
+
+
 def cpu_baseline(w, prm, side):
     """The oracle pipeline on the particles of the sub-box [0, side)^3."""
     import oracle
@@ -103,6 +129,7 @@ def main():
     ap.add_argument("--n-side", type=int, default=256, help="particles per side of the box (256 = the benchmark)")
     ap.add_argument("--cpu-sample-side", type=float, default=31.25, help="side (Mpc/h) of the oracle's sub-box")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="time the exact path only")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -112,7 +139,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1902_01010_amd import pipeline, synth, vr
+    from paper_1902_01010_amd import pipeline, surrogate, synth, vr
 
     w = synth.cosmo_box(n_side=args.n_side)
     prm = pipeline.Params.from_workload(w)
@@ -126,37 +153,45 @@ def main():
         del a, b
     print(f"[bench] {w.n} particles, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
 
-    def step():
-        return pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)[0]
+    model = None
+    if not args.no_surrogate and os.path.exists(surrogate.MODEL_PATH):
+        model = surrogate.SurrogateModel.load().bind(prm, w.box, w.grid_bits)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        out = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    def timed(mdl):
+        def step():
+            return pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm, model=mdl)[0]
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) * 1e3 / args.steps
+        return ms, kernel_table(ctx, args.steps), res
+
+    ms_per_step, kernels, out = timed(None)
+    ctx.set_timing(False)
     value = w.n / (ms_per_step / 1e3)
-
-    kernels = {}
-    for name in pipeline.KERNELS:
-        launches, ms, work = ctx.kernel_time(name)
-        if launches == 0:
-            continue
-        bound, per_unit, _ = KERNEL_MODEL[name]
-        amount = work * per_unit / launches          # bytes or flops per launch
-        avg_s = ms / launches / 1e3
-        if bound == "alu":
-            achieved, peak, unit = amount / avg_s / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
-        else:
-            achieved, peak, unit = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
-        kernels[name] = {"bound": bound, "launches_per_step": launches / args.steps,
-                         "ms_per_step": ms / args.steps, "avg_launch_ms": ms / launches,
-                         "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak}
+    sur = None
+    if model is not None:
+        ms_s, kernels_s, out_s = timed(model)
+        ctx.set_timing(False)
+        rows = out["members"][:out_s["surrogate"]["n_rows"]].long()
+        r_exact, r_sur = out["R"][rows], out_s["R"][rows]
+        truth, pred = r_exact >= prm.R_threshold, r_sur >= prm.R_threshold
+        tp = int((truth & pred).sum().item())
+        sc = surrogate.score(out_s["surrogate"]["rhat"], r_exact, prm.R_threshold, model.margin)
+        sur = {"value": round(w.n / (ms_s / 1e3), 1), "ms_per_step": round(ms_s, 3),
+               "recall": tp / max(1, int(truth.sum().item())), "precision": tp / max(1, int(pred.sum().item())),
+               "band_frac": out_s["surrogate"]["n_band"] / max(1, out_s["surrogate"]["n_rows"]),
+               "margin": model.margin, "band_for_recall": sc["band_for_recall"],
+               "trained_on": {k: model.meta.get(k) for k in ("train_seeds", "n_side", "epochs", "calib_seed")},
+               "kernels": kernels_s}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     d = kernels[dom]
     traffic = profiled_traffic(dom)
@@ -164,7 +199,11 @@ def main():
                 "frac": round(d["frac"], 5), "traffic": traffic, "kernel": dom}
     if traffic is not None:
         roofline["traffic_unit"] = "bytes per launch"
-
+    # the headline is the surrogate+fallback path only where it keeps the
+    # recall target against the exact path and is the faster of the two
+    path, headline, headline_ms = "exact", value, ms_per_step
+    if sur is not None and sur["recall"] >= 0.995 and sur["value"] > value:
+        path, headline, headline_ms = "surrogate+fallback", sur["value"], sur["ms_per_step"]
     ub = out.get("unbind")
     summary = {"groups_3d": out["n_groups"], "hosts_searched": out["n_hosts"], "particles_searched": out["n_searched"],
                "outliers": int((out["R"] >= prm.R_threshold).sum().item()),
@@ -173,16 +212,17 @@ def main():
         summary["bound_particles"] = int(ub["bound"].sum().item())
         summary["max_unbind_passes"] = int(ub["iters"].max().item())
 
-    rec = {"metric": METRIC, "path": "exact", "value": round(value, 1),
+    rec = {"metric": METRIC, "path": path, "value": round(headline, 1),
            "unit": "particles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "ms_per_step": round(headline_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "int32 grid + f64 tests/moments + f32 potential tiles", "data": "synthetic",
            "config": {"workload": f"synthetic cosmological box {args.n_side}^3 particles, "
                                   f"{w.box:g} Mpc/h periodic, 2^21 grid; NFW halos (dN/dlnN ~ N^-0.9) with "
                                   f"Plummer subhalos + uniform background",
                       "n_particles": w.n, "box_mpc_h": w.box, "b": 0.2, "n_se": prm.n_se, "n_v": prm.n_v,
                       "R_threshold": prm.R_threshold, "parallelism": "1 GPU"},
-           "roofline": roofline, "kernels": kernels, "summary": summary}
+           "roofline": roofline, "kernels": kernels, "summary": summary,
+           "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sub-box sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, prm, args.cpu_sample_side)

@@ -79,18 +79,6 @@ def pack(parts):
     return np.concatenate([np.asarray(p, np.float64).ravel() for p in parts])
 
 
-def init_params(seed):
-    """He-uniform weights, zero biases (a seeded input of the training)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for fan_in, fan_out in ((12, 64), (64, 64), (64, 64)):
-        lim = np.sqrt(6.0 / fan_in)
-        parts += [rng.uniform(-lim, lim, (fan_in, fan_out)), np.zeros(fan_out)]
-    lim = np.sqrt(6.0 / 64)
-    parts += [rng.uniform(-lim, lim, 64), np.zeros(1)]
-    return pack(parts).astype(np.float32)
-
-
 # ---- forward / backward -------------------------------------------------------
 def forward(w, X, bf16=True):
     """Rhat for rows X (m x 12).  bf16=True applies the inference rounding

@@ -2,6 +2,9 @@
 cells and moments -> R -> host velocity linking lengths -> 6D FOF over the
 outliers -> candidate groups -> unbinding.  Every step is a libvr call;
 this module only chains them and selects the searched hosts.
+
+With a trained surrogate model, R comes from the learned path instead:
+features -> network -> band selection -> exact R for the band only.
 """
 from __future__ import annotations
 
@@ -13,7 +16,7 @@ import torch
 from . import vr as _vr
 
 KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group",
-           "unbind_persistent")
+           "unbind_persistent", "rs_features", "mlp_forward")
 
 
 @dataclasses.dataclass
@@ -43,9 +46,25 @@ def device_inputs(w, device="cuda"):
     return x, v, m
 
 
-def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, stage_events=False):
-    """One pass of the hot path over device-resident inputs.  Returns the
-    outputs (device tensors) and counts."""
+def surrogate_R(ctx, P, host_offsets, members, cm, prm: Params, model):
+    """R of every host member by the learned path: the network's prediction,
+    replaced by the exact R inside the band |Rhat - R_threshold| < margin."""
+    feat = ctx.rs_features(P, host_offsets, members, cm["vbar"], cm["sigma"], cm["rho_cell"], prm.n_se,
+                           model.cell_bits, model.shift, model.scale)
+    m = feat.shape[0]
+    rhat = ctx.mlp_forward(model.weights, feat)
+    R = torch.full((P.n,), float("nan"), device=P.device)
+    band = ctx.rs_select(members[:m], rhat, R, prm.R_threshold, model.margin)
+    if band.shape[0] > 0:
+        ctx.local_vdensity(P, host_offsets, members, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v, subset=band, R=R)
+    return R, dict(rhat=rhat, n_band=int(band.shape[0]), n_rows=m)
+
+
+def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, stage_events=False, model=None,
+        until=None):
+    """One pass of the hot path over device-resident inputs (R from the
+    learned path when a surrogate model is given; until="R" stops after R).
+    Returns the outputs (device tensors) and counts."""
     ev = []
 
     def mark(name):
@@ -72,8 +91,14 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
         return out, ev
     cm = ctx.cell_moments(P, host_offsets, members, want_table=False)
     mark("cells")
-    R = ctx.local_vdensity(P, host_offsets, members, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)
+    if model is None:
+        R = ctx.local_vdensity(P, host_offsets, members, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)
+    else:
+        R, out["surrogate"] = surrogate_R(ctx, P, host_offsets, members, cm, prm, model)
     mark("R")
+    out.update(cells=cm, R=R, host_offsets=host_offsets)
+    if until == "R":
+        return out, ev
     ellv = ctx.host_ellv(P, host_offsets, members, prm.alpha_v)
     label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
     mark("fof6d")
@@ -81,7 +106,7 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     mark("subgroups")
     ub = ctx.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc > 0 else None
     mark("unbind")
-    out.update(cells=cm, R=R, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
+    out.update(ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
                sub_members=sub_mem, unbind=ub)
     return out, ev
 

@@ -228,7 +228,9 @@ def cosmo_box(seed=2, n_side=256, box=None, halo_frac=0.45, sub_frac=0.10, n_max
                   host_min=256)
     meta = dict(seed=seed, n_side=n_side, n_halos=nh, n_subhalos=ns, n_background=nb,
                 m_p=m_p, spacing=spacing, n_max=n_max)
-    return _finish("cosmo_box", rng, pos, vel, box, None, m_p, params, meta)
+    # which component drew each particle: 0 halo (NFW), 1 subhalo (Plummer), 2 background
+    comp = np.concatenate([np.zeros(len(hid), np.int8), np.ones(len(sid), np.int8), np.full(nb, 2, np.int8)])
+    return _finish("cosmo_box", rng, pos, vel, box, None, m_p, params, meta, extra=dict(component=comp))
 
 
 def unbind_groups(seed=3, n_groups=50_000, n_max=2_000_000, box=100.0, m=1e8,
@@ -305,3 +307,17 @@ def plummer_sphere(seed=8, n=20000, a=0.01, box=1.0, m=1.0, sigma=50.0):
     pos = 0.5 * box + _unit_vectors(rng, n) * r
     vel = rng.normal(0.0, sigma, size=(3, n))
     return _finish("plummer", rng, pos, vel, box, None, m, dict(a=a), dict(seed=seed))
+
+
+def mlp_init(seed):
+    """Seeded initial parameters of the 12-64-64-64-1 surrogate network in its
+    flat FP32 layout (W1[12][64], b1, W2[64][64], b2, W3[64][64], b3, w4[64],
+    b4): He-uniform weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((12, 64), (64, 64), (64, 64)):
+        lim = np.sqrt(6.0 / fan_in)
+        parts += [rng.uniform(-lim, lim, (fan_in, fan_out)).ravel(), np.zeros(fan_out)]
+    lim = np.sqrt(6.0 / 64)
+    parts += [rng.uniform(-lim, lim, 64), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)

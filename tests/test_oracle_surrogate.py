@@ -5,6 +5,7 @@ import pytest
 import torch
 
 from oracle import surrogate as S
+from paper_1902_01010_amd import synth
 
 
 # ---- BF16 rounding ---------------------------------------------------------------
@@ -56,7 +57,7 @@ def test_mlp_forward_bias_only_and_unpack_layout():
 
 def test_mlp_gradient_matches_central_differences():
     rng = np.random.default_rng(5)
-    w = S.init_params(11).astype(np.float64)
+    w = synth.mlp_init(11).astype(np.float64)
     w[12 * 64:12 * 64 + 64] = rng.normal(scale=0.1, size=64)       # non-zero biases
     X = rng.normal(size=(24, 12))
     y = rng.normal(size=24)
@@ -92,7 +93,7 @@ def test_mlp_gradient_rounded_model_is_exact_on_representable_values():
 
 def test_mlp_gradient_rounded_model_close_to_exact():
     rng = np.random.default_rng(13)
-    w = S.init_params(14).astype(np.float64)
+    w = synth.mlp_init(14).astype(np.float64)
     X = rng.normal(size=(200, 12))
     y = rng.normal(size=200)
     _, g0 = S.loss_and_grad(w, S.bf16_round(X), y)
