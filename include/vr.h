@@ -77,6 +77,16 @@ int vr_set_timing(vr_ctx* ctx, int enabled);
  * vr_get_tune reads a knob back. */
 int vr_tune(vr_ctx* ctx, const char* knob, int value);
 int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value);
+
+/* Autotuner of those knobs.  Unless force is set and if cache_path (may be
+ * NULL) names a readable cache written for this GPU architecture, its knobs
+ * are applied and nothing is timed.  Otherwise the call times vr_unbind
+ * (persistent) over unbind_tile x unbind_jchunk x unbind_bpc on a synthetic
+ * heavy-tailed group set (sizes 32 .. 32768) and vr_local_vdensity over
+ * knn_leaf x xcd_chunk on synthetic hosts, applies the fastest settings and
+ * writes them, with every timing, to cache_path as JSON.  Allocates its
+ * workloads (freed before return); takes a few seconds; syncs. */
+int vr_autotune(vr_ctx* ctx, const char* cache_path, int force);
 int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms,
                    double* work);
 

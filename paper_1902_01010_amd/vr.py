@@ -21,13 +21,14 @@ CELL_COLS = 28
 # Entry points declared in include/vr.h (checked by the CPU test-suite).
 ENTRY_POINTS = (
     "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
-    "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune",
+    "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune", "vr_autotune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
     "vr_host_ellv", "vr_fof6d", "vr_unbind",
     "vr_rs_features", "vr_mlp_forward", "vr_mlp_grad", "vr_mlp_train_step", "vr_rs_select",
 )
 
 MLP_PARAMS = 9217
+TUNE_KNOBS = ("unbind_tile", "unbind_jchunk", "unbind_bpc", "knn_leaf", "xcd_chunk")
 
 
 class VrError(RuntimeError):
@@ -84,6 +85,7 @@ def load_library():
         L.vr_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]
         L.vr_tune.argtypes = [vp, C.c_char_p, C.c_int]
         L.vr_get_tune.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
+        L.vr_autotune.argtypes = [vp, C.c_char_p, C.c_int]
         L.vr_quantize.argtypes = [vp, i64, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
         L.vr_fof3d.argtypes = [vp, P, dbl, vp, vp]
         L.vr_groups.argtypes = [vp, i64, vp, i32, C.POINTER(i32), vp, vp, vp, vp]
@@ -186,6 +188,12 @@ class Context:
 
     def tune(self, knob: str, value: int):
         self._check(self.lib.vr_tune(self.h, knob.encode(), int(value)))
+
+    def autotune(self, cache_path=None, force=False):
+        """Apply cached launch knobs for this GPU, or time the sweeps and write the cache."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.lib.vr_autotune(self.h, path, 1 if force else 0))
+        return {k: self.get_tune(k) for k in TUNE_KNOBS}
 
     def get_tune(self, knob: str) -> int:
         v = C.c_int(0)

@@ -1,0 +1,45 @@
+"""The defaults of the package and of the C ABI bindings against the values
+the paper states (tests/golden/paper_parameters.json, each with its table or
+section)."""
+import inspect
+import json
+import os
+
+import numpy as np
+from scipy import integrate
+
+from paper_1902_01010_amd import pipeline, synth, vr
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_parameters.json")))
+
+
+def g(k):
+    return GOLD[k]["value"]
+
+
+def test_pipeline_defaults_match_the_paper():
+    w = synth.cosmo_box(seed=5, n_side=16)
+    prm = pipeline.Params.from_workload(w)
+    assert prm.alpha_v == g("alpha_v")
+    assert prm.alpha_xs == g("alpha_xS")
+    assert prm.beta_E == g("beta_E")
+    assert prm.n_min == g("N_min")
+    assert np.isclose(prm.ellx, g("ellx_in_mean_spacing") * w.box / 16)
+
+
+def test_binding_defaults_match_the_paper():
+    cm = inspect.signature(vr.Context.cell_moments).parameters
+    assert cm["f_cell"].default == g("f_cell")
+    assert cm["ncell_floor"].default == g("ncell_floor")
+    assert 1.0 / cm["ncell_div"].default == g("ncell_cap_fraction")
+    ub = inspect.signature(vr.Context.unbind).parameters
+    assert ub["beta_E"].default == g("beta_E")
+    assert ub["n_min"].default == g("N_min")
+
+
+def test_epanechnikov_normalisation():
+    """15/(8 pi) makes W(u) = c (1 - u^2) integrate to one over the unit ball."""
+    c = g("epanechnikov_3d_norm")
+    assert np.isclose(c, 15 / (8 * np.pi), rtol=1e-15)
+    val, _ = integrate.quad(lambda u: c * (1 - u * u) * 4 * np.pi * u * u, 0, 1)
+    assert np.isclose(val, 1.0, rtol=1e-12)

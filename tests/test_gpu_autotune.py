@@ -1,0 +1,42 @@
+"""The autotuner: sweeps, cache round trip, and results unchanged under the
+knobs it picks."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_1902_01010_amd import synth
+from tests.gpu_common import both, dev_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_sweep_cache_and_parity(tmp_path, ref):
+    from paper_1902_01010_amd import vr
+    path = tmp_path / "tune.json"
+    ctx = vr.Context(0)
+    knobs = ctx.autotune(path, force=True)
+    data = json.loads(path.read_text())
+    assert data["arch"] == "gfx950"
+    for k in vr.TUNE_KNOBS:
+        assert data[k] == knobs[k]
+    assert knobs["unbind_tile"] in (64, 128, 256, 512, 1024)
+    assert knobs["knn_leaf"] in (16, 32, 48, 64)
+    assert len(data["unbind_sweep"]) == 60 and len(data["knn_sweep"]) == 16
+    best = min(data["unbind_sweep"], key=lambda r: r["ms"])
+    assert (best["tile"], best["jchunk"], best["bpc"]) == (knobs["unbind_tile"], knobs["unbind_jchunk"],
+                                                          knobs["unbind_bpc"])
+    # a fresh context takes the cached knobs without sweeping
+    ctx2 = vr.Context(0)
+    assert ctx2.autotune(path) == knobs
+    # the tuned context still matches the oracle
+    w = synth.unbind_groups(seed=3, n_groups=30, n_max=3000)
+    P, Pr = both(ctx2, vr, ref, w)
+    off, mem = w.groups
+    exp = ref.unbind(Pr, off, mem, w.params["G"], w.params["eps"])
+    got = ctx2.unbind(P, dev_tensor(off), dev_tensor(mem), w.params["G"], w.params["eps"])
+    clean = exp["min_margin"] > 1e-5
+    gb = got["bound"].cpu().numpy()
+    for g in np.nonzero(clean)[0]:
+        m = mem[off[g]:off[g + 1]]
+        assert (gb[m] == exp["bound"][m]).all()
