@@ -48,6 +48,8 @@ METRIC = "particles/s for \u211b+3D/6D FOF+unbind, 256\u00b3; surrogate vs exact
 # WRITE_SIZE runs summarised in profiles/ (copy-calibrated); used only while
 # the kernel's sources hash to what they were when the counters were taken.
 TRAFFIC_PROFILES = {"knn": "profiles/knn_cosmo256_hbm_traffic.txt"}
+# launch knobs picked by vr_autotune on an MI355X (applied when present)
+TUNE_CACHE = os.path.join(ROOT, "paper_1902_01010_amd", "data", "autotune_gfx950.json")
 
 
 def sources_sha256(files):
@@ -121,6 +123,89 @@ def cpu_baseline(w, prm, side):
                       f"({sub.n} particles, {dt:.1f} s on {threads} threads)"}
 
 
+def bench_unbind(args):
+    """Batched unbinding of the 50k-group set (config 3): host-planned passes
+    against the persistent, graph-replayed schedule, on the same groups."""
+    import torch
+    from paper_1902_01010_amd import synth, vr
+
+    w = synth.unbind_groups(seed=3, n_groups=args.unbind_groups)
+    off, mem = w.groups
+    # group table in decreasing size, as vr_groups hands it over (longest first)
+    sizes = np.diff(off)
+    order = np.argsort(-sizes, kind="stable")
+    mem = np.concatenate([mem[off[g]:off[g + 1]] for g in order]).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(sizes[order])]).astype(np.int32)
+    ctx = vr.Context(0)
+    knobs = ctx.autotune(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else {k: ctx.get_tune(k) for k in vr.TUNE_KNOBS}
+    x = torch.from_numpy(w.x).cuda()
+    q = ctx.quantize(x, w.box, w.grid_bits)
+    P = vr.Particles(q, torch.from_numpy(w.v).cuda(), None, w.mass_value, w.box, w.grid_bits)
+    offd, memd = torch.from_numpy(off).cuda(), torch.from_numpy(mem).cuda()
+    G, eps = w.params["G"], w.params["eps"]
+    print(f"[bench] {len(sizes)} groups, {w.n} particles, sum N^2 = {float((sizes.astype(float) ** 2).sum()):.3e}",
+          file=sys.stderr, flush=True)
+    res = {}
+    for name, persistent, timer in (("host_planned", 0, "unbind_potential"), ("persistent", 1, "unbind_persistent")):
+        for _ in range(args.warmup):
+            out = ctx.unbind(P, offd, memd, G, eps, persistent=persistent)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = ctx.unbind(P, offd, memd, G, eps, persistent=persistent)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        launches, kms, pairs = ctx.kernel_time(timer)
+        ctx.set_timing(False)
+        pairs_call = pairs / args.steps
+        res[name] = {"ms_per_call": round(ms, 3), "ordered_pairs_per_call": pairs_call,
+                     "pairs_per_s": pairs_call / (ms / 1e3),
+                     "potential_tflops": pairs_call * 6.0 / (ms / 1e3) / 1e12,
+                     "bound": int(out["bound"].sum().item()), "max_passes": int(out["iters"].max().item())}
+    best = min(res, key=lambda k: res[k]["ms_per_call"])
+    tf = res[best]["potential_tflops"]
+    rec = {"metric": "particles/s for batched unbinding of 50k groups (plain vs persistent)",
+           "path": best, "value": round(w.n / (res[best]["ms_per_call"] / 1e3), 1), "unit": "particles/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[best]["ms_per_call"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 pair tiles + f64 accumulation", "data": "synthetic",
+           "config": {"workload": f"{len(sizes)} groups, sizes dN/dlnN ~ N^-0.9 on [20, 2e6], NFW + Plummer "
+                                  f"subhalos + 20% contaminants at 2 v_esc; {w.n} particles",
+                      "launch_knobs": knobs},
+           "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                        "kernel": "whole unbinding call, 12 flop per unordered pair"},
+           "schedules": res}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = unbind_cpu_baseline(w, off, mem, sizes[order])
+    print(json.dumps(rec), flush=True)
+
+
+def unbind_cpu_baseline(w, off, mem, sizes):
+    """The oracle on every 25th group of at most 20,000 members; the whole
+    set's time is extrapolated through sum N^2 (stated as such)."""
+    import oracle
+
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1), os.cpu_count() or 1)
+    oracle.lib()
+    oracle.set_threads(threads)
+    pick = [g for g in range(len(sizes)) if sizes[g] <= 20000][::25]
+    so = np.concatenate([[0], np.cumsum(sizes[pick])]).astype(np.int32)
+    sm = np.concatenate([mem[off[g]:off[g + 1]] for g in pick]).astype(np.int32)
+    q = oracle.quantize(w.x, w.box, w.grid_bits)
+    P = oracle.Particles(q, w.v, None, w.mass_value, w.box, w.grid_bits)
+    t0 = time.perf_counter()
+    oracle.unbind(P, so, sm, w.params["G"], w.params["eps"])
+    dt = time.perf_counter() - t0
+    s2_sample = float((sizes[pick].astype(float) ** 2).sum())
+    s2_all = float((sizes.astype(float) ** 2).sum())
+    t_all = dt * s2_all / s2_sample
+    return {"value": w.n / t_all, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pick)} groups ({int(sizes[pick].sum())} particles, every 25th group of <= 20000) in "
+                      f"{dt:.1f} s; whole set extrapolated through sum N^2 to {t_all:.0f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +215,9 @@ def main():
     ap.add_argument("--cpu-sample-side", type=float, default=31.25, help="side (Mpc/h) of the oracle's sub-box")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="time the exact path only")
+    ap.add_argument("--workload", choices=("box", "unbind"), default="box",
+                    help="box: the 256^3 hot path (default); unbind: batched unbinding of 50k groups")
+    ap.add_argument("--unbind-groups", type=int, default=50_000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -137,6 +225,8 @@ def main():
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "unbind":
+        return bench_unbind(args)
 
     import torch
     from paper_1902_01010_amd import pipeline, surrogate, synth, vr
@@ -144,6 +234,7 @@ def main():
     w = synth.cosmo_box(n_side=args.n_side)
     prm = pipeline.Params.from_workload(w)
     ctx = vr.Context(0)
+    knobs = ctx.autotune(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else {k: ctx.get_tune(k) for k in vr.TUNE_KNOBS}
     x, v, m = pipeline.device_inputs(w)
     if args.calib_copy_mib:
         a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -220,7 +311,7 @@ def main():
                                   f"{w.box:g} Mpc/h periodic, 2^21 grid; NFW halos (dN/dlnN ~ N^-0.9) with "
                                   f"Plummer subhalos + uniform background",
                       "n_particles": w.n, "box_mpc_h": w.box, "b": 0.2, "n_se": prm.n_se, "n_v": prm.n_v,
-                      "R_threshold": prm.R_threshold, "parallelism": "1 GPU"},
+                      "R_threshold": prm.R_threshold, "parallelism": "1 GPU", "launch_knobs": knobs},
            "roofline": roofline, "kernels": kernels, "summary": summary,
            "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}
     if not args.no_cpu_baseline:

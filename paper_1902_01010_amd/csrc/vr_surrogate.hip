@@ -214,9 +214,13 @@ __global__ __launch_bounds__(256) void k_rs_features(int64_t m, const int32_t* _
                                                      const float* __restrict__ vbar, const float* __restrict__ sigma,
                                                      const float* __restrict__ rho, int64_t n, Level fine,
                                                      Level coarse, const double* __restrict__ vsum, int n_se,
-                                                     double cell_len, FeatNorm nrm, uint16_t* __restrict__ feat) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+                                                     double cell_len, FeatNorm nrm, const uint32_t* __restrict__ order,
+                                                     uint16_t* __restrict__ feat) {
+    // rows are taken in fine-cell order, so neighbouring threads probe the
+    // same cells and the window lookups stay in cache
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t i = order[t];
     const int g = mem[i];
     const uint32_t px = qx[g], py = qy[g], pz = qz[g];
     // 0: radius holding n_se neighbours at the window count density
@@ -683,6 +687,7 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
     Level lv[2];
     const int cb[2] = {cell_bits, cell_bits + 2};
     double* vsum = nullptr;
+    const uint32_t* order = nullptr;
     for (int L = 0; L < 2; ++L) {
         const int b = p->grid_bits - cb[L];
         VR_WS(keys, ctx, uint64_t, WS_A0 + 4 * L, m);
@@ -719,13 +724,14 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
                                host_members, p->vx, p->vy, p->vz, vs);
             VR_LAUNCH_CHECK(ctx);
             vsum = vs;
+            order = rws;
         }
     }
     const double cell_len = ldexp(p->box, cell_bits - p->grid_bits);
     VR_TIMED(ctx, "rs_features", st, m,
              hipLaunchKernelGGL(k_rs_features, dim3(grid_for(m, 256)), dim3(256), 0, st, m, host_members, p->qx,
                                 p->qy, p->qz, p->vx, p->vy, p->vz, vbar, sigma, rho_cell, p->n, lv[0], lv[1], vsum,
-                                n_se, cell_len, nrm, feat));
+                                n_se, cell_len, nrm, order, feat));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }

@@ -71,6 +71,26 @@ __global__ void k_ub_zero(int na, const int* __restrict__ active, const int32_t*
     for (int k = s + threadIdx.x; k < e; k += blockDim.x) acc[k] = 0.0;
 }
 
+// Sum over staged j of m_j / sqrt(r^2 + eps^2) for one i, in FP32 (at most
+// 64 terms, R18).  CHECK = the chunk may hold j == i or, with eps = 0, a
+// coincident pair; otherwise every term is finite and taken.
+template <bool UNIFORM, bool CHECK>
+__device__ __forceinline__ float tile_sum(const float4* __restrict__ sj, int t0, int t1, float xi, float yi, float zi,
+                                          float eps2, int jbase, int i) {
+    float accf = 0.f;
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t) {
+        const float4 q = sj[t];
+        const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+        const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+        float rinv;
+        if (CHECK) rinv = (jbase + t != i && s2 > 0.f) ? rsqrtf(s2) : 0.f;
+        else rinv = rsqrtf(s2);
+        accf = UNIFORM ? accf + rinv : fmaf(q.w, rinv, accf);
+    }
+    return accf;
+}
+
 // Potential tiles: item = (group, i0, j0, j1).
 template <bool UNIFORM>
 __global__ __launch_bounds__(UB) void k_ub_potential(const int4* __restrict__ items, const int32_t* __restrict__ off,
@@ -91,17 +111,13 @@ __global__ __launch_bounds__(UB) void k_ub_potential(const int4* __restrict__ it
             sj[t] = make_float4(W.x[k], W.y[k], W.z[k], UNIFORM ? 1.f : W.m[k]);
         }
         __syncthreads();
+        // rows of this wavefront: [iw, iw + 64)
+        const int iw = it.y + ((int)threadIdx.x & ~63);
         for (int t0 = 0; t0 < jn; t0 += 64) {
             const int t1 = min(t0 + 64, jn);
-            float accf = 0.f;
-            for (int t = t0; t < t1; ++t) {
-                const float4 q = sj[t];
-                const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                const float rinv = (j0 + t != i && s2 > 0.f) ? rsqrtf(s2) : 0.f;
-                accf = UNIFORM ? accf + rinv : fmaf(q.w, rinv, accf);
-            }
-            accd += (double)accf;
+            const bool check = eps2 == 0.f || (j0 + t0 < iw + 64 && j0 + t1 > iw);
+            accd += (double)(check ? tile_sum<UNIFORM, true>(sj, t0, t1, xi, yi, zi, eps2, j0, i)
+                                   : tile_sum<UNIFORM, false>(sj, t0, t1, xi, yi, zi, eps2, j0, i));
         }
     }
     if (valid) atomicAdd(&acc[base + i], accd);
@@ -454,15 +470,9 @@ __global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* 
             __builtin_amdgcn_wave_barrier();
             for (int t0 = 0; t0 < jn; t0 += 64) {
                 const int t1 = min(t0 + 64, jn);
-                float accf = 0.f;
-                for (int t = t0; t < t1; ++t) {
-                    const float4 q = sj[t];
-                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                    const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                    const float rinv = (jb + t != i && s2 > 0.f) ? rsqrtf(s2) : 0.f;
-                    accf = UNIFORM ? accf + rinv : fmaf(q.w, rinv, accf);
-                }
-                accd += (double)accf;
+                const bool check = eps2 == 0.f || (jb + t0 < i0 + 64 && jb + t1 > i0);
+                accd += (double)(check ? tile_sum<UNIFORM, true>(sj, t0, t1, xi, yi, zi, eps2, jb, i)
+                                       : tile_sum<UNIFORM, false>(sj, t0, t1, xi, yi, zi, eps2, jb, i));
             }
         }
         if (valid) atomicAdd(&acc[base + i], accd);
