@@ -4,16 +4,19 @@
 // 64 members, built by the presorted level-synchronous builder); members sit
 // in leaf order, so 64 consecutive queries share leaves.  One wavefront
 // serves 64 queries, one per lane: the wave walks the tree of a host with a
-// shared depth-first stack (near child first), visiting a node when any
-// lane's ball -- radius = its current n_se-th neighbour -- reaches the node's
-// bounding box.  A visited leaf is loaded once, one member per lane, and its
-// members are broadcast lane to lane, so the inner loop touches no memory.
-// Every lane keeps its n_se best keys in a max-heap in LDS; a key packs the
-// exact integer squared distance above the member's rank in its host's
-// ascending index order, so ties break by particle index exactly as the
-// definition says.  The n_v velocity neighbours are then chosen among the
-// n_se by (FP64 dv2, index) and the Epanechnikov estimate and the Gaussian
-// background follow in FP64.
+// shared depth-first stack (near child first, for the centre of the wave's
+// queries), visiting a node when any lane's ball -- radius = its current
+// n_se-th neighbour -- reaches the node's bounding box.  A visited leaf is
+// staged in LDS 64 members at a time.  A first pass over the chunk (the same
+// LDS address for every lane, no divergence) marks in a per-lane bit mask
+// the members whose FP32 squared distance may beat the lane's current worst;
+// a second pass inserts the marked ones with their exact keys, each lane
+// walking its own mask.  Every lane keeps its n_se best keys in a max-heap
+// in LDS; a key packs the exact integer squared distance above the member's
+// rank in its host's ascending index order, so ties break by particle index
+// exactly as the definition says.  The n_v velocity neighbours are then
+// chosen among the n_se by (FP64 dv2, index) and the Epanechnikov estimate
+// and the Gaussian background follow in FP64.
 #include "vr_kd.h"
 
 #include <cmath>
@@ -127,6 +130,16 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         const bool nowrap = root.bmax[0] - root.bmin[0] < half && root.bmax[1] - root.bmin[1] < half &&
                             root.bmax[2] - root.bmin[2] < half;
         const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
+        // the near child is chosen for the centre of this host's queries
+        int64_t sx = mine ? px : 0, sy = mine ? py : 0, sz = mine ? pz : 0;
+        int cnt = mine ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) {
+            sx += __shfl_xor(sx, o, 64);
+            sy += __shfl_xor(sy, o, 64);
+            sz += __shfl_xor(sz, o, 64);
+            cnt += __shfl_xor(cnt, o, 64);
+        }
+        const int ccx = (int)(sx / cnt), ccy = (int)(sy / cnt), ccz = (int)(sz / cnt);
         if (lane == 0) stack[0] = hh;
         int sp = 1;
         __builtin_amdgcn_wave_barrier();
@@ -157,27 +170,35 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                         // current worst key get the exact integer key.
                         cand[lane] = make_float4((float)lx, (float)ly, (float)lz, __builtin_bit_cast(float, le));
                         __builtin_amdgcn_wave_barrier();
-                        float wf = count < n_se ? INFINITY : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                        // pass 1 (no divergence): which candidates may beat this
+                        // lane's current worst key; pass 2: insert them, each lane
+                        // on its own list, so the wave spends max-over-lanes
+                        // insertions per chunk instead of one per candidate that
+                        // any lane takes
+                        const float wf = count < n_se ? INFINITY : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                        uint64_t take = 0;
                         for (int t = 0; t < m; ++t) {
                             const float4 c4 = cand[t];  // same address for every lane: a broadcast
                             const float dxf = c4.x - pxf, dyf = c4.y - pyf, dzf = c4.z - pzf;
                             const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
-                            if (!(mine && d2f <= wf)) continue;
+                            take |= (uint64_t)(d2f <= wf) << t;
+                        }
+                        if (!mine) take = 0;
+                        while (take) {
+                            const int t = __builtin_ctzll(take);
+                            take &= take - 1;
+                            const float4 c4 = cand[t];
                             // |d| < 2^21: unsigned 32-bit squares, exact 64-bit sum
-                            const uint32_t ax = (uint32_t)abs((int)dxf), ay = (uint32_t)abs((int)dyf),
-                                           az = (uint32_t)abs((int)dzf);
+                            const uint32_t ax = (uint32_t)abs((int)(c4.x - pxf)), ay = (uint32_t)abs((int)(c4.y - pyf)),
+                                           az = (uint32_t)abs((int)(c4.z - pzf));
                             const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
                             const uint64_t key = (d2 << POS_BITS) | (uint64_t)__builtin_bit_cast(uint32_t, c4.w);
                             if (count < n_se) {
                                 heap_push(heap, lane, count, key);
-                                if (count == n_se) {
-                                    worst = heap[0][lane];
-                                    wf = (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
-                                }
+                                if (count == n_se) worst = heap[0][lane];
                             } else if (key < worst) {
                                 heap_replace_top(heap, lane, count, key);
                                 worst = heap[0][lane];
-                                wf = (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
                             }
                         }
                         __builtin_amdgcn_wave_barrier();
@@ -210,8 +231,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                 }
             } else {
                 if (sp + 2 > STACK) break;  // cannot happen for trees of depth < 64
-                const int c = nd.dim == 0 ? px : (nd.dim == 1 ? py : pz);
-                const int cf = __shfl(c, fl, 64);
+                const int cf = nd.dim == 0 ? ccx : (nd.dim == 1 ? ccy : ccz);
                 const int nearc = cf < nd.t ? nd.left : nd.right;
                 const int farc = cf < nd.t ? nd.right : nd.left;
                 if (lane == 0) {
