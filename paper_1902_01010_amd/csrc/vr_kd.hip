@@ -152,12 +152,56 @@ __global__ __launch_bounds__(KB) void k_hist(int64_t M, const int* __restrict__ 
     }
 }
 
+// Normalised Shannon entropy of each dimension's histogram (the entropy
+// equation of Sec. 2.2) for every active node: one wavefront per node, one
+// lane per bin, so the logarithms of a node are taken in parallel.
+__global__ __launch_bounds__(256) void k_entropy(int na, const int* __restrict__ active, const KdNode* __restrict__ nodes,
+                                                 int nb, int counts, const uint32_t* __restrict__ hc,
+                                                 const double* __restrict__ hm, double* __restrict__ S) {
+    const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = __lane_id();
+    if (i >= na) return;
+    const KdNode& nd = nodes[active[i]];
+    __shared__ double sh[4][64];
+    __shared__ double stot[4];
+    const int w = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t b0 = ((int64_t)i * 3 + d) * nb;
+        const double h = lane < nb ? (counts ? (double)hc[b0 + lane] : hm[b0 + lane]) : 0.0;
+        // totals and entropy sums run over the bins in order, as a serial
+        // loop would; only the logarithms are spread over the lanes
+        sh[w][lane] = h;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            double tot = 0.0;
+            for (int k = 0; k < nb; ++k) tot += sh[w][k];
+            stot[w] = tot;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const double tot = stot[w];
+        double term = 0.0;
+        if (h > 0) {
+            const double pk = h / tot;
+            term = -pk * log(pk);
+        }
+        __builtin_amdgcn_wave_barrier();
+        sh[w][lane] = term;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            double sacc = 0.0;
+            for (int k = 0; k < nb; ++k) sacc += sh[w][k];
+            S[3 * (int64_t)i + d] = nd.bmax[d] == nd.bmin[d] ? 0.0 : sacc / log((double)nb);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Split decision of every active node and creation of its children.
 __global__ void k_split(int na, const int* __restrict__ active, KdNode* nodes, const int* __restrict__ l0,
                         const int* __restrict__ l1, const int* __restrict__ l2, const int* __restrict__ u0,
-                        const int* __restrict__ u1, const int* __restrict__ u2, int mode, int nb, int counts,
-                        const uint32_t* __restrict__ hc, const double* __restrict__ hm, const int* __restrict__ ncell,
-                        int* next_active, int* leaves, int* counters) {
+                        const int* __restrict__ u1, const int* __restrict__ u2, int mode,
+                        const double* __restrict__ Sdim, const int* __restrict__ ncell, int* next_active, int* leaves,
+                        int* counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= na) return;
     const int id = active[i];
@@ -168,24 +212,7 @@ __global__ void k_split(int na, const int* __restrict__ active, KdNode* nodes, c
             if (nd.bmax[d] > nd.bmin[d] && (best < 0 || nd.bmax[d] - nd.bmin[d] > nd.bmax[best] - nd.bmin[best]))
                 best = d;
     } else {
-        // normalised Shannon entropy of each dimension's mass histogram
-        double S[3];
-        for (int d = 0; d < 3; ++d) {
-            S[d] = 0.0;
-            if (nd.bmax[d] == nd.bmin[d]) continue;
-            const int64_t b0 = ((int64_t)i * 3 + d) * nb;
-            double tot = 0.0;
-            for (int k = 0; k < nb; ++k) tot += counts ? (double)hc[b0 + k] : hm[b0 + k];
-            double sacc = 0.0;
-            for (int k = 0; k < nb; ++k) {
-                const double h = counts ? (double)hc[b0 + k] : hm[b0 + k];
-                if (h > 0) {
-                    const double pk = h / tot;
-                    sacc -= pk * log(pk);
-                }
-            }
-            S[d] = sacc / log((double)nb);
-        }
+        const double S[3] = {Sdim[3 * (int64_t)i], Sdim[3 * (int64_t)i + 1], Sdim[3 * (int64_t)i + 2]};
         for (int d = 0; d < 3; ++d) {
             if (nd.bmax[d] == nd.bmin[d]) continue;
             if (best < 0) { best = d; continue; }
@@ -448,8 +475,16 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
             }
             VR_LAUNCH_CHECK(ctx);
         }
+        double* Sdim = nullptr;
+        if (mode != KD_WIDEST) {
+            Sdim = static_cast<double*>(ws(ctx, WS_KD_S, (size_t)na * 3 * sizeof(double)));
+            if (!Sdim) return VR_ERR_OUT_OF_MEMORY;
+            hipLaunchKernelGGL(k_entropy, dim3(grid_for((int64_t)na * 64, 256)), dim3(256), 0, st, na, cur, nodes,
+                               nbins, counts, hc, hm, Sdim);
+            VR_LAUNCH_CHECK(ctx);
+        }
         hipLaunchKernelGGL(k_split, dim3(grid_for(na, 256)), dim3(256), 0, st, na, cur, nodes, L[0], L[1], L[2], U[0],
-                           U[1], U[2], mode, nbins, counts, hc, hm, ncell_d, nxt, leaves, counters);
+                           U[1], U[2], mode, Sdim, ncell_d, nxt, leaves, counters);
         VR_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_flags, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag);
         VR_LAUNCH_CHECK(ctx);
