@@ -3,10 +3,12 @@
 // Each host gets a median-split KD tree (widest dimension, leaves of at most
 // 64 members, built by the presorted level-synchronous builder); members sit
 // in leaf order, so 64 consecutive queries share leaves.  One wavefront
-// serves 64 queries, one per lane: the wave walks the tree of a host with a
-// shared depth-first stack (near child first, for the centre of the wave's
-// queries), visiting a node when any lane's ball -- radius = its current
-// n_se-th neighbour -- reaches the node's bounding box.  A visited leaf is
+// serves 64 queries, one per lane: the wave first scans the leaves that hold
+// its own queries (which fills every heap with near neighbours), then walks
+// the tree of the host with a shared depth-first stack (near child first,
+// for the centre of the wave's queries), visiting a node when any lane's
+// ball -- radius = its current n_se-th neighbour -- reaches the node's
+// bounding box.  A visited leaf is
 // staged in LDS 64 members at a time.  A first pass over the chunk (the same
 // LDS address for every lane, no divergence) marks in a per-lane bit mask
 // the members whose FP32 squared distance may beat the lane's current worst;
@@ -94,28 +96,119 @@ __device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { retu
 // unrolled insertion network); NVR == 0: any n_v, kept in LDS.
 template <int NSE, int NVR>
 __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, int64_t nq,
-                                            const KdNode* __restrict__ nodes, Elems F, const float* __restrict__ Vx,
-                                            const float* __restrict__ Vy, const float* __restrict__ Vz,
-                                            const float* __restrict__ Me, const int* __restrict__ elem_host,
-                                            const int32_t* __restrict__ host_off, const float* __restrict__ vbar,
-                                            const float* __restrict__ sigma, int64_t n, int n_se, int n_v, int use_mass,
-                                            double mass_value, int gb, float* __restrict__ R, unsigned xchunk) {
+                                            const KdNode* __restrict__ nodes, Elems F, const int* __restrict__ leaf_of,
+                                            const float* __restrict__ Vx, const float* __restrict__ Vy,
+                                            const float* __restrict__ Vz, const float* __restrict__ Me,
+                                            const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
+                                            const float* __restrict__ vbar, const float* __restrict__ sigma, int64_t n,
+                                            int n_se, int n_v, int use_mass, double mass_value, int gb,
+                                            float* __restrict__ R, unsigned xchunk) {
     constexpr int NVL = NVR > 0 ? 1 : NSE;
     __shared__ uint64_t heap[NSE][64];
     __shared__ double vd[NVL][64];
     __shared__ int vp[NVL][64];
     __shared__ int stack[STACK];
+    // the leaf chunk being scanned: x, y, z (exact integers as float) and rank
+    __shared__ float4 cand[64];
     const int lane = threadIdx.x;
     const int64_t qi = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * 64 + lane;
     const bool active = qi < nq;
     const int e = active ? (qpos ? (int)qpos[qi] : (int)qi) : 0;
     const int h = active ? elem_host[e] : -1;
     const int base = active ? host_off[h] : 0;
+    const int own = active ? leaf_of[e] : -1;
     const int px = F.u[0][e], py = F.u[1][e], pz = F.u[2][e];
+    const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
     int count = 0;
     uint64_t worst = ~0ull;
-    // the leaf chunk being scanned: x, y, z (exact integers as float) and rank
-    __shared__ float4 cand[64];
+
+    // Inserts the members of leaf `node` for the lanes in `mine`.
+    auto scan_leaf = [&](int node, bool mine, bool nowrap, int hbase) {
+        const KdNode& nd = nodes[node];
+        const int s = nd.start, t_end = nd.end;
+        for (int c0 = s; c0 < t_end; c0 += 64) {
+            // one member per lane, then shared through LDS or lane reads
+            const int j = c0 + lane;
+            const bool vj = j < t_end;
+            const int lx = vj ? F.u[0][j] : 0, ly = vj ? F.u[1][j] : 0, lz = vj ? F.u[2][j] : 0;
+            const int le = vj ? F.eid[j] - hbase : 0;
+            const int m = min(64, t_end - c0);
+            if (nowrap) {
+                // FP32 prefilter: coordinates are integers below 2^24, so the
+                // differences are exact and the rounded sum of squares is within
+                // 2e-7 of the exact one; only candidates that may beat the
+                // current worst key get the exact integer key.
+                cand[lane] = make_float4((float)lx, (float)ly, (float)lz, __builtin_bit_cast(float, le));
+                __builtin_amdgcn_wave_barrier();
+                // pass 1 (no divergence): which candidates may beat this lane's
+                // current worst key; pass 2: insert them, each lane walking its
+                // own mask, so the wave spends max-over-lanes insertions per
+                // chunk instead of one per candidate that any lane takes
+                const float wf = count < n_se ? INFINITY : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                uint64_t take = 0;
+                for (int t = 0; t < m; ++t) {
+                    const float4 c4 = cand[t];  // same address for every lane: a broadcast
+                    const float dxf = c4.x - pxf, dyf = c4.y - pyf, dzf = c4.z - pzf;
+                    const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
+                    take |= (uint64_t)(d2f <= wf) << t;
+                }
+                if (!mine) take = 0;
+                while (take) {
+                    const int t = __builtin_ctzll(take);
+                    take &= take - 1;
+                    const float4 c4 = cand[t];
+                    // |d| < 2^21: unsigned 32-bit squares, exact 64-bit sum
+                    const uint32_t ax = (uint32_t)abs((int)(c4.x - pxf)), ay = (uint32_t)abs((int)(c4.y - pyf)),
+                                   az = (uint32_t)abs((int)(c4.z - pzf));
+                    const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)__builtin_bit_cast(uint32_t, c4.w);
+                    if (count < n_se) {
+                        heap_push(heap, lane, count, key);
+                        if (count == n_se) worst = heap[0][lane];
+                    } else if (key < worst) {
+                        heap_replace_top(heap, lane, count, key);
+                        worst = heap[0][lane];
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
+            for (int t = 0; t < m; ++t) {
+                const int cx = __builtin_amdgcn_readlane(lx, t);
+                const int cy = __builtin_amdgcn_readlane(ly, t);
+                const int cz = __builtin_amdgcn_readlane(lz, t);
+                const int ce = __builtin_amdgcn_readlane(le, t);
+                const int ddx = min_image(cx - px, gb);
+                const int ddy = min_image(cy - py, gb);
+                const int ddz = min_image(cz - pz, gb);
+                uint64_t d2;
+                if (max(max(abs(ddx), abs(ddy)), abs(ddz)) < 32768)
+                    d2 = (uint64_t)((uint32_t)(ddx * ddx) + (uint32_t)(ddy * ddy) + (uint32_t)(ddz * ddz));
+                else
+                    d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
+                const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)ce;
+                if (mine && (count < n_se || key < worst)) {
+                    if (count < n_se) {
+                        heap_push(heap, lane, count, key);
+                        if (count == n_se) worst = heap[0][lane];
+                    } else {
+                        heap_replace_top(heap, lane, count, key);
+                        worst = heap[0][lane];
+                    }
+                }
+            }
+        }
+    };
+    // whether some lane's ball (radius = its current worst) reaches the box
+    auto needed = [&](const KdNode& nd, bool mine) {
+        const int64_t dx = max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
+        const int64_t dy = max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
+        const int64_t dz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
+        int64_t md2 = dx * dx + dy * dy + dz * dz;
+        if (md2 > (int64_t(1) << 41)) md2 = int64_t(1) << 41;
+        return __ballot(mine && (count < n_se || ((uint64_t)md2 << POS_BITS) <= worst)) != 0;
+    };
+
     bool pending = active;
     while (__ballot(pending)) {
         const uint64_t pm = __ballot(pending);
@@ -129,8 +222,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         const int half = 1 << (gb - 1);
         const bool nowrap = root.bmax[0] - root.bmin[0] < half && root.bmax[1] - root.bmin[1] < half &&
                             root.bmax[2] - root.bmin[2] < half;
-        const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
-        // the near child is chosen for the centre of this host's queries
+        // the centre of this host's queries: near children and visiting order follow it
         int64_t sx = mine ? px : 0, sy = mine ? py : 0, sz = mine ? pz : 0;
         int cnt = mine ? 1 : 0;
         for (int o = 32; o > 0; o >>= 1) {
@@ -140,96 +232,21 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
             cnt += __shfl_xor(cnt, o, 64);
         }
         const int ccx = (int)(sx / cnt), ccy = (int)(sy / cnt), ccz = (int)(sz / cnt);
-        if (lane == 0) stack[0] = hh;
-        int sp = 1;
-        __builtin_amdgcn_wave_barrier();
-        while (sp > 0) {
-            const int node = stack[--sp];
+        // Depth-first walk of the host's tree, near child first; skip_own:
+        // the leaves holding a query of this pass were scanned already.
+        auto walk = [&](bool skip_own) {
+            if (lane == 0) stack[0] = hh;
+            int sp = 1;
             __builtin_amdgcn_wave_barrier();
-            const KdNode& nd = nodes[node];
-            const int64_t dx = max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
-            const int64_t dy = max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
-            const int64_t dz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
-            int64_t md2 = dx * dx + dy * dy + dz * dz;
-            if (md2 > (int64_t(1) << 41)) md2 = int64_t(1) << 41;
-            const bool need = mine && (count < n_se || ((uint64_t)md2 << POS_BITS) <= worst);
-            if (!__ballot(need)) continue;
-            if (nd.dim < 0) {
-                const int s = nd.start, t_end = nd.end;
-                for (int c0 = s; c0 < t_end; c0 += 64) {
-                    // one member per lane, then broadcast lane by lane
-                    const int j = c0 + lane;
-                    const bool vj = j < t_end;
-                    const int lx = vj ? F.u[0][j] : 0, ly = vj ? F.u[1][j] : 0, lz = vj ? F.u[2][j] : 0;
-                    const int le = vj ? F.eid[j] - hbase : 0;
-                    const int m = min(64, t_end - c0);
-                    if (nowrap) {
-                        // FP32 prefilter: coordinates are integers below 2^24, so the
-                        // differences are exact and the rounded sum of squares is within
-                        // 2e-7 of the exact one; only candidates that may beat the
-                        // current worst key get the exact integer key.
-                        cand[lane] = make_float4((float)lx, (float)ly, (float)lz, __builtin_bit_cast(float, le));
-                        __builtin_amdgcn_wave_barrier();
-                        // pass 1 (no divergence): which candidates may beat this
-                        // lane's current worst key; pass 2: insert them, each lane
-                        // on its own list, so the wave spends max-over-lanes
-                        // insertions per chunk instead of one per candidate that
-                        // any lane takes
-                        const float wf = count < n_se ? INFINITY : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
-                        uint64_t take = 0;
-                        for (int t = 0; t < m; ++t) {
-                            const float4 c4 = cand[t];  // same address for every lane: a broadcast
-                            const float dxf = c4.x - pxf, dyf = c4.y - pyf, dzf = c4.z - pzf;
-                            const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
-                            take |= (uint64_t)(d2f <= wf) << t;
-                        }
-                        if (!mine) take = 0;
-                        while (take) {
-                            const int t = __builtin_ctzll(take);
-                            take &= take - 1;
-                            const float4 c4 = cand[t];
-                            // |d| < 2^21: unsigned 32-bit squares, exact 64-bit sum
-                            const uint32_t ax = (uint32_t)abs((int)(c4.x - pxf)), ay = (uint32_t)abs((int)(c4.y - pyf)),
-                                           az = (uint32_t)abs((int)(c4.z - pzf));
-                            const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-                            const uint64_t key = (d2 << POS_BITS) | (uint64_t)__builtin_bit_cast(uint32_t, c4.w);
-                            if (count < n_se) {
-                                heap_push(heap, lane, count, key);
-                                if (count == n_se) worst = heap[0][lane];
-                            } else if (key < worst) {
-                                heap_replace_top(heap, lane, count, key);
-                                worst = heap[0][lane];
-                            }
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                        continue;
-                    }
-                    for (int t = 0; t < m; ++t) {
-                        const int cx = __builtin_amdgcn_readlane(lx, t);
-                        const int cy = __builtin_amdgcn_readlane(ly, t);
-                        const int cz = __builtin_amdgcn_readlane(lz, t);
-                        const int ce = __builtin_amdgcn_readlane(le, t);
-                        const int ddx = min_image(cx - px, gb);
-                        const int ddy = min_image(cy - py, gb);
-                        const int ddz = min_image(cz - pz, gb);
-                        uint64_t d2;
-                        if (max(max(abs(ddx), abs(ddy)), abs(ddz)) < 32768)
-                            d2 = (uint64_t)((uint32_t)(ddx * ddx) + (uint32_t)(ddy * ddy) + (uint32_t)(ddz * ddz));
-                        else
-                            d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
-                        const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)ce;
-                        if (mine && (count < n_se || key < worst)) {
-                            if (count < n_se) {
-                                heap_push(heap, lane, count, key);
-                                if (count == n_se) worst = heap[0][lane];
-                            } else {
-                                heap_replace_top(heap, lane, count, key);
-                                worst = heap[0][lane];
-                            }
-                        }
-                    }
+            while (sp > 0) {
+                const int node = stack[--sp];
+                __builtin_amdgcn_wave_barrier();
+                const KdNode& nd = nodes[node];
+                if (!needed(nd, mine)) continue;
+                if (nd.dim < 0) {
+                    if (!(skip_own && __ballot(mine && own == node))) scan_leaf(node, mine, nowrap, hbase);
+                    continue;
                 }
-            } else {
                 if (sp + 2 > STACK) break;  // cannot happen for trees of depth < 64
                 const int cf = nd.dim == 0 ? ccx : (nd.dim == 1 ? ccy : ccz);
                 const int nearc = cf < nd.t ? nd.left : nd.right;
@@ -241,6 +258,19 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                 sp += 2;
                 __builtin_amdgcn_wave_barrier();
             }
+        };
+        if (!nowrap) {
+            walk(false);
+        } else {
+            // the leaves of the queries themselves first: they fill every
+            // heap with near neighbours, so the walk prunes from its start
+            uint64_t todo = __ballot(mine);
+            while (todo) {
+                const int L = __builtin_amdgcn_readlane(own, __ffsll((unsigned long long)todo) - 1);
+                scan_leaf(L, mine, true, hbase);
+                todo &= ~__ballot(mine && own == L);
+            }
+            walk(true);
         }
         pending = pending && !mine;
     }
@@ -344,7 +374,8 @@ int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree
                const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
     VR_TIMED(ctx, "knn", st, nq,
              hipLaunchKernelGGL((k_knn<NSE, NVR>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
-                                tree.F, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n, n_se, n_v,
+                                tree.F, tree.seg_node, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n,
+                                n_se, n_v,
                                 tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
