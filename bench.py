@@ -149,11 +149,13 @@ def bench_unbind(args):
     for name, persistent, timer in (("host_planned", 0, "unbind_potential"), ("persistent", 1, "unbind_persistent")):
         for _ in range(args.warmup):
             out = ctx.unbind(P, offd, memd, G, eps, persistent=persistent)
+            print(f"[bench] {name}: warmup call done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         ctx.set_timing(True)
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for k in range(args.steps):
             out = ctx.unbind(P, offd, memd, G, eps, persistent=persistent)
+            print(f"[bench] {name}: call {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         launches, kms, pairs = ctx.kernel_time(timer)
@@ -165,7 +167,7 @@ def bench_unbind(args):
                      "bound": int(out["bound"].sum().item()), "max_passes": int(out["iters"].max().item())}
     best = min(res, key=lambda k: res[k]["ms_per_call"])
     tf = res[best]["potential_tflops"]
-    rec = {"metric": "particles/s for batched unbinding of 50k groups (plain vs persistent)",
+    rec = {"metric": f"particles/s for batched unbinding of {len(sizes)} groups (plain vs persistent)",
            "path": best, "value": round(w.n / (res[best]["ms_per_call"] / 1e3), 1), "unit": "particles/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[best]["ms_per_call"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -217,7 +219,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="time the exact path only")
     ap.add_argument("--workload", choices=("box", "unbind"), default="box",
                     help="box: the 256^3 hot path (default); unbind: batched unbinding of 50k groups")
-    ap.add_argument("--unbind-groups", type=int, default=50_000)
+    ap.add_argument("--unbind-groups", type=int, default=5_000,
+                    help="groups of the unbinding workload (50000 = the full set: one call then takes minutes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
