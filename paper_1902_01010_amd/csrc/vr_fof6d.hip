@@ -169,6 +169,10 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
     const int hp = shost[p];
     const double ev = ellv[hp];
     const double ev2 = ev * ev;
+    // t = d2/ell2 + dv2/ev2 is formed with reciprocals first; that differs
+    // from the divided form by a few ulps, so only t within 1e-9 of 1 needs
+    // the divided form itself
+    const double rl2 = 1.0 / ell2, rv2 = 1.0 / ev2;
     uint32_t seen[HALF ? 1 : 27];
     int nseen = 0;
     for (int o = 0; o < 27; ++o) {
@@ -190,15 +194,18 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
         uint32_t s = cell_start[c], e = cell_start[c + 1];
         if (((nk == k) || !HALF) && s <= (uint32_t)p) s = (uint32_t)p + 1;
         for (uint32_t q = s; q < e; ++q) {
-            if (shost[q] != hp) continue;
             const int ddx = min_image((int)sx[q] - px, gb);
             const int ddy = min_image((int)sy[q] - py, gb);
             const int ddz = min_image((int)sz[q] - pz, gb);
             const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+            // d2 >= ell2 makes the rounded d2/ell2 >= 1 and so t >= 1: no link
+            if (d2 >= ell2 || shost[q] != hp) continue;
             const double ax = vpx - (double)svx[q], ay = vpy - (double)svy[q], az = vpz - (double)svz[q];
             const double dv2 = ax * ax + ay * ay + az * az;
-            const double t = d2 / ell2 + dv2 / ev2;
-            if (t < 1.0) uf_union(parent, (int)p, (int)q);
+            const double ta = d2 * rl2 + dv2 * rv2;
+            bool link = ta < 1.0 - 1e-9;
+            if (!link && ta <= 1.0 + 1e-9) link = d2 / ell2 + dv2 / ev2 < 1.0;
+            if (link) uf_union(parent, (int)p, (int)q);
         }
     }
 }
