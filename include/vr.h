@@ -65,7 +65,7 @@ int vr_set_timing(vr_ctx* ctx, int enabled);
 
 /* Launch-shape knobs of the context (integer results never depend on them;
  * FP64 potentials only through the order of their partial sums):
- * "knn_leaf"      members per leaf of the neighbour-search tree (16..64, 64)
+ * "knn_leaf"      members per leaf of the neighbour-search tree (16..256, 64)
  * "unbind_tile"   j-tile of the potential kernel staged in LDS (64..4096, 256;
  *                 the persistent kernel uses at most 1024 per wavefront)
  * "unbind_jchunk" j-range of one potential work item (256..65536, 4096)

@@ -201,7 +201,7 @@ int vr_tune(vr_ctx* ctx, const char* knob, int value) {
     if (!ctx || !knob) return VR_ERR_INVALID_ARG;
     const std::string k = knob;
     if (k == "knn_leaf") {
-        if (value < 16 || value > 64) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "knn_leaf must be in 16..64");
+        if (value < 16 || value > 256) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "knn_leaf must be in 16..256");
         ctx->knn_leaf = value;
     } else if (k == "unbind_tile") {
         if (value < 64 || value > 4096 || (value & 63))

@@ -265,34 +265,45 @@ __global__ void k_flags(int64_t M, const int* __restrict__ seg_node, const KdNod
     flag[l[p]] = (p - nd.start) < (nd.end - nd.start) / 2 ? 1 : 0;
 }
 
-__global__ void k_lflag(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
-                        const int* __restrict__ l, const uint8_t* __restrict__ flag, uint32_t* __restrict__ lf) {
+// The left flags of the three lists at once (list j at lf[j * M + p]).
+__global__ void k_lflag3(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
+                         const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
+                         const uint8_t* __restrict__ flag, uint32_t* __restrict__ lf) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
-    lf[p] = nodes[seg_node[p]].dim >= 0 ? (uint32_t)flag[l[p]] : 0u;
+    const bool split = nodes[seg_node[p]].dim >= 0;
+    lf[p] = split ? (uint32_t)flag[l0[p]] : 0u;
+    lf[M + p] = split ? (uint32_t)flag[l1[p]] : 0u;
+    lf[2 * M + p] = split ? (uint32_t)flag[l2[p]] : 0u;
 }
 
-// Stable partition of one list inside every split node.
-__global__ void k_part(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
-                       const int* __restrict__ l, const uint8_t* __restrict__ flag, const uint32_t* __restrict__ scan,
-                       int* __restrict__ out) {
+// Stable partition of the three lists inside every split node (the scan
+// runs over the three flag arrays back to back; differences are taken
+// inside one list), then the position's node moves to its child.
+__global__ void k_part3(int64_t M, int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
+                        const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
+                        const uint8_t* __restrict__ flag, const uint32_t* __restrict__ scan, int* __restrict__ o0,
+                        int* __restrict__ o1, int* __restrict__ o2) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
     const KdNode& nd = nodes[seg_node[p]];
-    const int e = l[p];
-    if (nd.dim < 0) { out[p] = e; return; }
+    const int e0 = l0[p], e1 = l1[p], e2 = l2[p];
+    if (nd.dim < 0) {
+        o0[p] = e0;
+        o1[p] = e1;
+        o2[p] = e2;
+        return;
+    }
     const int s = nd.start, nl = (nd.end - nd.start) / 2;
-    const int rl = (int)(scan[p] - scan[s]);  // left members before p in the node
-    const int np = flag[e] ? s + rl : s + nl + ((int)p - s - rl);
-    out[np] = e;
-}
-
-__global__ void k_segnode(int64_t M, int* __restrict__ seg_node, const KdNode* __restrict__ nodes) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
-    const KdNode& nd = nodes[seg_node[p]];
-    if (nd.dim < 0) return;
-    seg_node[p] = p < nd.start + (nd.end - nd.start) / 2 ? nd.left : nd.right;
+    const int e[3] = {e0, e1, e2};
+    int* out[3] = {o0, o1, o2};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int rl = (int)(scan[j * M + p] - scan[j * M + s]);  // left members before p in the node
+        const int np = flag[e[j]] ? s + rl : s + nl + ((int)p - s - rl);
+        out[j][np] = e[j];
+    }
+    seg_node[p] = p < s + nl ? nd.left : nd.right;
 }
 
 __global__ void k_leaf_bbox(int nl, const int* __restrict__ leaves, KdNode* nodes, const int* __restrict__ l0,
@@ -378,7 +389,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     while ((1 << hb) <= n_hosts) ++hb;
     // one workspace region holds every array of the build
     Carve cv;
-    int *U[3], *G, *H, *L[3], *Lalt, *seg, *leaf_min, *act0, *act1, *leaves, *ncell_d, *counters;
+    int *U[3], *G, *H, *L[3], *Lalt[3], *seg, *leaf_min, *act0, *act1, *leaves, *ncell_d, *counters;
     float* Ms;
     uint8_t* flag;
     uint32_t* lf;
@@ -391,10 +402,10 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         H = cv.add<int>(M);
         Ms = cv.add<float>(use_mass ? M : 1);
         for (int d = 0; d < 3; ++d) L[d] = cv.add<int>(M);
-        Lalt = cv.add<int>(M);
+        for (int d = 0; d < 3; ++d) Lalt[d] = cv.add<int>(M);
         seg = cv.add<int>(M);
         flag = cv.add<uint8_t>(M);
-        lf = cv.add<uint32_t>(M + 1);
+        lf = cv.add<uint32_t>(3 * M + 1);
         pkey = cv.add<uint64_t>(M);
         nodes = cv.add<KdNode>(node_cap);
         act0 = cv.add<int>(node_cap);
@@ -488,16 +499,13 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         VR_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_flags, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag);
         VR_LAUNCH_CHECK(ctx);
-        for (int j = 0; j < 3; ++j) {
-            hipLaunchKernelGGL(k_lflag, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[j], flag, lf);
-            VR_LAUNCH_CHECK(ctx);
-            if ((rc = scan_u32(ctx, lf, lf, M, nullptr, st))) return rc;
-            hipLaunchKernelGGL(k_part, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[j], flag, lf, Lalt);
-            VR_LAUNCH_CHECK(ctx);
-            std::swap(L[j], Lalt);
-        }
-        hipLaunchKernelGGL(k_segnode, dim3(gM), dim3(256), 0, st, M, seg, nodes);
+        hipLaunchKernelGGL(k_lflag3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf);
         VR_LAUNCH_CHECK(ctx);
+        if ((rc = scan_u32(ctx, lf, lf, 3 * M, nullptr, st))) return rc;
+        hipLaunchKernelGGL(k_part3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf, Lalt[0],
+                           Lalt[1], Lalt[2]);
+        VR_LAUNCH_CHECK(ctx);
+        for (int j = 0; j < 3; ++j) std::swap(L[j], Lalt[j]);
         VR_HIP(ctx, hipMemcpyAsync(counters + 0, counters + 1, sizeof(int), hipMemcpyDeviceToDevice, st));
         VR_HIP(ctx, hipMemcpyAsync(counters + 4, counters + 5, sizeof(int), hipMemcpyDeviceToDevice, st));
         if (ctx->timing) {
