@@ -242,7 +242,7 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
     if (rc) { ctx->timing = saved_timing; return rc; }
     float best_knn = 1e30f;
     std::ostringstream klog;
-    const int leaves[] = {16, 32, 48, 64};
+    const int leaves[] = {32, 48, 64, 96, 128};
     const int xchunks[] = {0, 16, 64, 256};
     for (int L : leaves)
         for (int X : xchunks) {
