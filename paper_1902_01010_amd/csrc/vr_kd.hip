@@ -196,40 +196,73 @@ __global__ __launch_bounds__(256) void k_entropy(int na, const int* __restrict__
     }
 }
 
-// Split decision of every active node and creation of its children.
-__global__ void k_split(int na, const int* __restrict__ active, KdNode* nodes, const int* __restrict__ l0,
-                        const int* __restrict__ l1, const int* __restrict__ l2, const int* __restrict__ u0,
-                        const int* __restrict__ u1, const int* __restrict__ u2, int mode,
-                        const double* __restrict__ Sdim, const int* __restrict__ ncell, int* next_active, int* leaves,
-                        int* counters) {
+// Reserves n slots of a global counter for each lane; one atomic per
+// wavefront.  Every lane of the wavefront must call it.
+__device__ __forceinline__ int wave_reserve(int* counter, int n) {
+    const int lane = __lane_id();
+    int x = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+    }
+    const int total = __shfl(x, 63, 64);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 63, 64);
+    return base + x - n;
+}
+
+// Split decision of every active node and creation of its children.  All
+// lanes run to the end (the counters are reserved per wavefront).
+__global__ __launch_bounds__(256) void k_split(int na, const int* __restrict__ active, KdNode* nodes,
+                                               const int* __restrict__ l0, const int* __restrict__ l1,
+                                               const int* __restrict__ l2, const int* __restrict__ u0,
+                                               const int* __restrict__ u1, const int* __restrict__ u2, int mode,
+                                               const double* __restrict__ Sdim, const int* __restrict__ ncell,
+                                               int* next_active, int* leaves, int* counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= na) return;
-    const int id = active[i];
-    const KdNode nd = nodes[id];
+    const bool valid = i < na;
+    const int id = valid ? active[i] : 0;
+    KdNode nd;
     int best = -1;
-    if (mode == KD_WIDEST) {
-        for (int d = 0; d < 3; ++d)
-            if (nd.bmax[d] > nd.bmin[d] && (best < 0 || nd.bmax[d] - nd.bmin[d] > nd.bmax[best] - nd.bmin[best]))
-                best = d;
-    } else {
-        const double S[3] = {Sdim[3 * (int64_t)i], Sdim[3 * (int64_t)i + 1], Sdim[3 * (int64_t)i + 2]};
-        for (int d = 0; d < 3; ++d) {
-            if (nd.bmax[d] == nd.bmin[d]) continue;
-            if (best < 0) { best = d; continue; }
-            const bool better = mode == KD_MIN_ENTROPY ? (S[d] < S[best] - 1e-12) : (S[d] > S[best] + 1e-12);
-            if (better) best = d;
+    if (valid) {
+        nd = nodes[id];
+        if (mode == KD_WIDEST) {
+            for (int d = 0; d < 3; ++d)
+                if (nd.bmax[d] > nd.bmin[d] && (best < 0 || nd.bmax[d] - nd.bmin[d] > nd.bmax[best] - nd.bmin[best]))
+                    best = d;
+        } else {
+            const double S[3] = {Sdim[3 * (int64_t)i], Sdim[3 * (int64_t)i + 1], Sdim[3 * (int64_t)i + 2]};
+            for (int d = 0; d < 3; ++d) {
+                if (nd.bmax[d] == nd.bmin[d]) continue;
+                if (best < 0) { best = d; continue; }
+                const bool better = mode == KD_MIN_ENTROPY ? (S[d] < S[best] - 1e-12) : (S[d] > S[best] + 1e-12);
+                if (better) best = d;
+            }
         }
     }
-    if (best < 0) {  // every member coincides: the node stays a leaf
+    const bool split = valid && best >= 0;
+    // every member coincides: the node stays a leaf
+    const bool stays = valid && best < 0;
+    const int n = split ? nd.end - nd.start : 0, nl = n / 2;
+    const int nc = split ? ncell[nd.host] : 0;
+    const bool lact = split && nl > nc, ract = split && n - nl > nc;
+    const int c0 = wave_reserve(&counters[3], split ? 2 : 0);
+    const int na0 = wave_reserve(&counters[1], (int)lact + (int)ract);
+    const int nl0 = wave_reserve(&counters[2], (int)stays + (split ? (int)!lact + (int)!ract : 0));
+    int grow = (lact ? nl : 0) + (ract ? n - nl : 0);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) grow += __shfl_xor(grow, o, 64);
+    if (__lane_id() == 0 && grow) atomicAdd(&counters[5], grow);
+    if (stays) {
         nodes[id].slot = -1;
-        leaves[atomicAdd(&counters[2], 1)] = id;
-        return;
+        leaves[nl0] = id;
     }
-    const int n = nd.end - nd.start, nl = n / 2;
+    if (!split) return;
     const int* lb = best == 0 ? l0 : (best == 1 ? l1 : l2);
     const int* ub = best == 0 ? u0 : (best == 1 ? u1 : u2);
     const int t = ub[lb[nd.start + nl]];
-    const int c0 = atomicAdd(&counters[3], 2);
     KdNode L = nd, R = nd;
     L.end = nd.start + nl;
     R.start = nd.start + nl;
@@ -244,13 +277,9 @@ __global__ void k_split(int na, const int* __restrict__ active, KdNode* nodes, c
     nodes[id].t = t;
     nodes[id].left = c0;
     nodes[id].right = c0 + 1;
-    const int nc = ncell[nd.host];
-    int grow = 0;
-    if (nl > nc) { next_active[atomicAdd(&counters[1], 1)] = c0; grow += nl; }
-    else leaves[atomicAdd(&counters[2], 1)] = c0;
-    if (n - nl > nc) { next_active[atomicAdd(&counters[1], 1)] = c0 + 1; grow += n - nl; }
-    else leaves[atomicAdd(&counters[2], 1)] = c0 + 1;
-    if (grow) atomicAdd(&counters[5], grow);
+    int ka = na0, kl = nl0;
+    if (lact) next_active[ka++] = c0; else leaves[kl++] = c0;
+    if (ract) next_active[ka] = c0 + 1; else leaves[kl] = c0 + 1;
 }
 
 // flag[e] = 1 if element e goes to the left child of its (split) node.
