@@ -17,7 +17,6 @@ Host-level steps are independent between hosts, so a host's oracle result
 is its result in the full box.
 """
 import os
-import sys
 
 import numpy as np
 import pytest
@@ -31,8 +30,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def note(msg):
-    # progress outside pytest's capture: a long test still shows it is alive
-    print(f"[fullsize] {msg}", file=sys.__stderr__, flush=True)
+    # shown with the report of a failing test
+    print(f"[fullsize] {msg}", flush=True)
 
 
 @pytest.fixture(scope="module")
