@@ -478,8 +478,8 @@ __device__ __forceinline__ void bias_grad(const f16v d[2], float* gb, int lane, 
 }
 
 // Gradient of the mean squared error over a batch of m rows (rows[] picks
-// them from feat/target, or rows 0..m-1): each workgroup takes 128 rows and
-// writes its partial sums (and its squared-error sum) to part[blockIdx].
+// them from feat/target, or rows 0..m-1): each workgroup takes 128-row tiles
+// and writes its partial sums (and its squared-error sum) to part[blockIdx].
 __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, const bf4* __restrict__ pk, int64_t m,
                                                   const uint16_t* __restrict__ feat, const int32_t* __restrict__ rows,
                                                   const float* __restrict__ target, float* __restrict__ part) {
@@ -491,83 +491,88 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     uint16_t* dl = dl_all[wv];
     uint16_t* ac = ac_all[wv];
-    const int64_t b = (int64_t)blockIdx.x * GROWS + 32 * wv + (lane & 31);
-    const bool valid = b < m;
-    const int64_t row = valid ? (rows ? (int64_t)rows[b] : b) : 0;
     const float inv_m = 1.f / (float)m;
+    // workgroups stride over 128-row tiles, so the partial sums stay one
+    // slot vector per workgroup whatever the batch size
+    for (int64_t tile = blockIdx.x; tile * GROWS < m; tile += gridDim.x) {
+        const int64_t b = tile * GROWS + 32 * wv + (lane & 31);
+        const bool valid = b < m;
+        const int64_t row = valid ? (rows ? (int64_t)rows[b] : b) : 0;
 
-    bf4 x0[2];
-    bool bad;
-    load_inputs(feat, row, valid, lane, x0, bad);
-    f16v h1[2], h2[2], h3[2];
-    bf4 x1[8], x2[8];
-    layer<2>(pk + PK_FWD1, w + OB1, x0, lane, h1);
-    relu_to_operands(h1, x1);
-    layer<8>(pk + PK_FWD2, w + OB2, x1, lane, h2);
-    relu_to_operands(h2, x2);
-    layer<8>(pk + PK_FWD3, w + OB3, x2, lane, h3);
+        bf4 x0[2];
+        bool bad;
+        load_inputs(feat, row, valid, lane, x0, bad);
+        f16v h1[2], h2[2], h3[2];
+        bf4 x1[8], x2[8];
+        layer<2>(pk + PK_FWD1, w + OB1, x0, lane, h1);
+        relu_to_operands(h1, x1);
+        layer<8>(pk + PK_FWD2, w + OB2, x1, lane, h2);
+        relu_to_operands(h2, x2);
+        layer<8>(pk + PK_FWD3, w + OB3, x2, lane, h3);
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) h3[t][j] = fmaxf(h3[t][j], 0.f);
-    const float y = out_layer(w, h3, lane);
-    const float r = valid ? y - target[row] : 0.f;
-    const float gout = 2.f * r * inv_m;              // d loss / d output of this row
-    if (valid && lane < 32) {
-        atomicAdd(&gacc[NPARAM], r * r);
-        atomicAdd(&gacc[OB4], gout);
-    }
-    // layer 4 and the error at the pre-activations of layer 3
-    f16v d3[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int u = 32 * t + acc_row(j, lane);
-            if (valid) atomicAdd(&gacc[OW4 + u], gout * h3[t][j]);
-            d3[t][j] = h3[t][j] > 0.f ? gout * w[OW4 + u] : 0.f;
+            for (int j = 0; j < 16; ++j) h3[t][j] = fmaxf(h3[t][j], 0.f);
+        const float y = out_layer(w, h3, lane);
+        const float r = valid ? y - target[row] : 0.f;
+        const float gout = 2.f * r * inv_m;              // d loss / d output of this row
+        if (valid && lane < 32) {
+            atomicAdd(&gacc[NPARAM], r * r);
+            atomicAdd(&gacc[OB4], gout);
         }
-    bias_grad(d3, gacc + OB3, lane, valid);
-    // W3: delta3 x h2
-    stash(d3, dl, lane);
-    stash(h2, ac, lane);
-    __builtin_amdgcn_wave_barrier();
-    weight_grad(dl, ac, H, gacc + OW3, lane);
-    // delta2 = (W3 delta3) * [h2 > 0]
-    bf4 xd[8];
-    to_operands(d3, xd);
-    f16v d2[2];
-    layer<8>(pk + PK_BWD3, nullptr, xd, lane, d2);
+        // layer 4 and the error at the pre-activations of layer 3
+        f16v d3[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) d2[t][j] = h2[t][j] > 0.f ? d2[t][j] : 0.f;
-    bias_grad(d2, gacc + OB2, lane, valid);
-    __builtin_amdgcn_wave_barrier();
-    stash(d2, dl, lane);
-    stash(h1, ac, lane);
-    __builtin_amdgcn_wave_barrier();
-    weight_grad(dl, ac, H, gacc + OW2, lane);
-    // delta1 = (W2 delta2) * [h1 > 0]
-    f16v d1[2];
-    to_operands(d2, xd);
-    layer<8>(pk + PK_BWD2, nullptr, xd, lane, d1);
+            for (int j = 0; j < 16; ++j) {
+                const int u = 32 * t + acc_row(j, lane);
+                if (valid) atomicAdd(&gacc[OW4 + u], gout * h3[t][j]);
+                d3[t][j] = h3[t][j] > 0.f ? gout * w[OW4 + u] : 0.f;
+            }
+        bias_grad(d3, gacc + OB3, lane, valid);
+        // W3: delta3 x h2
+        stash(d3, dl, lane);
+        stash(h2, ac, lane);
+        __builtin_amdgcn_wave_barrier();
+        weight_grad(dl, ac, H, gacc + OW3, lane);
+        // delta2 = (W3 delta3) * [h2 > 0]
+        bf4 xd[8];
+        to_operands(d3, xd);
+        f16v d2[2];
+        layer<8>(pk + PK_BWD3, nullptr, xd, lane, d2);
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) d1[t][j] = h1[t][j] > 0.f ? d1[t][j] : 0.f;
-    bias_grad(d1, gacc + OB1, lane, valid);
-    __builtin_amdgcn_wave_barrier();
-    stash(d1, dl, lane);
-    // the inputs as a [16][32] tile (rows of absent batch entries are zero)
-    for (int j = 0; j < 4; ++j) {
-        ac[(4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[0][j];
-        ac[(8 + 4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[1][j];
+            for (int j = 0; j < 16; ++j) d2[t][j] = h2[t][j] > 0.f ? d2[t][j] : 0.f;
+        bias_grad(d2, gacc + OB2, lane, valid);
+        __builtin_amdgcn_wave_barrier();
+        stash(d2, dl, lane);
+        stash(h1, ac, lane);
+        __builtin_amdgcn_wave_barrier();
+        weight_grad(dl, ac, H, gacc + OW2, lane);
+        // delta1 = (W2 delta2) * [h1 > 0]
+        f16v d1[2];
+        to_operands(d2, xd);
+        layer<8>(pk + PK_BWD2, nullptr, xd, lane, d1);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) d1[t][j] = h1[t][j] > 0.f ? d1[t][j] : 0.f;
+        bias_grad(d1, gacc + OB1, lane, valid);
+        __builtin_amdgcn_wave_barrier();
+        stash(d1, dl, lane);
+        // the inputs as a [16][32] tile (rows of absent batch entries are zero)
+        for (int j = 0; j < 4; ++j) {
+            ac[(4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[0][j];
+            ac[(8 + 4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[1][j];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // inputs 16..31 of the B tile read the next rows of ac, but only inputs
+        // < 12 are kept (MFMA output columns do not mix)
+        weight_grad(dl, ac, NF, gacc + OW1, lane);
+        __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
-    // inputs 16..31 of the B tile read the next rows of ac, but only inputs
-    // < 12 are kept (MFMA output columns do not mix)
-    weight_grad(dl, ac, NF, gacc + OW1, lane);
     __syncthreads();
     float* dst = part + (int64_t)blockIdx.x * NSLOT;
     for (int k = threadIdx.x; k < NSLOT; k += blockDim.x) dst[k] = gacc[k];
@@ -640,7 +645,7 @@ int run_grad(vr_ctx* ctx, const float* w, int64_t m, const uint16_t* feat, const
     bf4* pk = nullptr;
     int rc = pack_weights(ctx, w, &pk, st);
     if (rc) return rc;
-    const int nwg = (int)((m + GROWS - 1) / GROWS);
+    const int nwg = (int)std::min<int64_t>((m + GROWS - 1) / GROWS, (int64_t)ctx->num_cus * 2);
     VR_WS(part, ctx, float, WS_B8, (size_t)nwg * NSLOT);
     VR_TIMED(ctx, "mlp_grad", st, m,
              hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(64 * GW), 0, st, w, pk, m, feat, rows, target, part));

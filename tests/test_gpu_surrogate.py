@@ -114,6 +114,20 @@ def test_mlp_gradient_parity(ctx, m, use_rows):
     assert g @ g_exact / (np.linalg.norm(g) * np.linalg.norm(g_exact)) >= 0.998
 
 
+def test_mlp_gradient_large_batch(ctx):
+    """More 128-row tiles than workgroups: each workgroup strides over
+    several tiles."""
+    m = 150_000
+    w = _weights(13)
+    bits = _features(14, m)
+    y = np.random.default_rng(15).normal(size=m)
+    loss_model, g_model = S.loss_and_grad(w, S.bf16_from_bits(bits), y, bf16=True)
+    g, loss = ctx.mlp_grad(dev_tensor(w), _dev_bits(bits), dev_tensor(y.astype(np.float32)))
+    g = g.cpu().numpy().astype(np.float64)
+    assert float(loss.item()) == pytest.approx(loss_model, rel=1e-4)
+    assert max(_block_errors(g, g_model)) <= 5e-3, _block_errors(g, g_model)
+
+
 def test_adam_first_step_against_oracle(ctx):
     """Step 1 moves every weight by lr g / (|g| + eps) with the batch
     gradient g; checked where the FP64 gradient is not tiny."""
