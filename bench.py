@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--cpu-sample-side", type=float, default=31.25, help="side (Mpc/h) of the oracle's sub-box")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="time the exact path only")
+    ap.add_argument("--field-6d", action="store_true",
+                    help="hosts are field halos from adaptive 6D FOF inside each 3D group (not the headline path)")
     ap.add_argument("--workload", choices=("box", "unbind"), default="box",
                     help="box: the 256^3 hot path (default); unbind: batched unbinding of 50k groups")
     ap.add_argument("--unbind-groups", type=int, default=5_000,
@@ -236,6 +238,9 @@ def main():
 
     w = synth.cosmo_box(n_side=args.n_side)
     prm = pipeline.Params.from_workload(w)
+    if args.field_6d:
+        import dataclasses
+        prm = dataclasses.replace(prm, field_6d=True)
     ctx = vr.Context(0)
     knobs = ctx.autotune(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else {k: ctx.get_tune(k) for k in vr.TUNE_KNOBS}
     x, v, m = pipeline.device_inputs(w)
@@ -314,7 +319,8 @@ def main():
                                   f"{w.box:g} Mpc/h periodic, 2^21 grid; NFW halos (dN/dlnN ~ N^-0.9) with "
                                   f"Plummer subhalos + uniform background",
                       "n_particles": w.n, "box_mpc_h": w.box, "b": 0.2, "n_se": prm.n_se, "n_v": prm.n_v,
-                      "R_threshold": prm.R_threshold, "parallelism": "1 GPU", "launch_knobs": knobs},
+                      "R_threshold": prm.R_threshold, "field_hosts": "6D FOF" if prm.field_6d else "3D FOF",
+                      "parallelism": "1 GPU", "launch_knobs": knobs},
            "roofline": roofline, "kernels": kernels, "summary": summary,
            "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}
     if not args.no_cpu_baseline:

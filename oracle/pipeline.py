@@ -22,11 +22,20 @@ def run(w, prm, timings=None):
     label = ref.fof3d(P, prm.ellx)
     t = tick("fof3d", t)
     ng, group_of, off, mem = ref.groups(label, prm.n_min)
+    label3d = label
+    if getattr(prm, "field_6d", False) and ng > 0:
+        # field halos (Sec. 2.1, Eq. fof6d): each 3D group re-linked in 6D
+        # with ell_v = alpha_v sigma_v of that group and the full ellx
+        ellv3 = ref.host_ellv(P, off, mem, prm.alpha_v)
+        label = ref.fof6d(P, group_of, ellv3, prm.ellx, None)
+        t = tick("field6d", t)
+        ng, group_of, off, mem = ref.groups(label, prm.n_min)
     sizes = np.diff(off)
     nh = int((sizes >= prm.host_min).sum())
     hoff, hmem = off[:nh + 1], mem[:off[nh]]
     t = tick("groups", t)
-    out = dict(q=q, label=label, n_groups=ng, group_of=group_of, offsets=off, members=mem, n_hosts=nh)
+    out = dict(q=q, label=label, label3d=label3d, n_groups=ng, group_of=group_of, offsets=off, members=mem,
+               n_hosts=nh)
     if nh == 0:
         return out
     cm = ref.cell_moments(P, hoff, hmem)

@@ -32,6 +32,7 @@ class Params:
     beta_E: float = 0.95
     n_min: int = 20
     host_min: int = 256
+    field_6d: bool = False   # field halos by adaptive 6D FOF inside each 3D group (Sec. 2.1, Eq. fof6d)
 
     @classmethod
     def from_workload(cls, w):
@@ -80,11 +81,19 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     label = ctx.fof3d(P, prm.ellx)
     mark("fof3d")
     ng, group_of, offsets, members = ctx.groups(label, prm.n_min)
+    label3d = label
+    if prm.field_6d and ng > 0:
+        # every 3D group is re-linked in 6D with its own velocity scale
+        # alpha_v sigma_v,k and the full ellx; the 6D groups are the halos
+        ellv3 = ctx.host_ellv(P, offsets[:ng + 1], members, prm.alpha_v)
+        label = ctx.fof6d(P, group_of, ellv3, prm.ellx, None)
+        mark("field6d")
+        ng, group_of, offsets, members = ctx.groups(label, prm.n_min)
     sizes = np.diff(offsets.cpu().numpy())
     n_hosts = int((sizes >= prm.host_min).sum())
     host_offsets = offsets[:n_hosts + 1]
     mark("groups")
-    out = dict(q=q, label=label, n_groups=ng, group_of=group_of, offsets=offsets, members=members,
+    out = dict(q=q, label=label, label3d=label3d, n_groups=ng, group_of=group_of, offsets=offsets, members=members,
                n_hosts=n_hosts, n_searched=int(sizes[:n_hosts].sum()))
     if n_hosts == 0:
         out["R"] = torch.full((P.n,), float("nan"), device=x.device)

@@ -238,3 +238,33 @@ def test_unbind_persistent_matches_host_planned(ctx, vr, ref):
     assert (np.isfinite(pa) == np.isfinite(pb)).all()
     f = np.isfinite(pa)
     np.testing.assert_allclose(pb[f], pa[f], rtol=1e-9)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_field_halos_6d_pipeline_parity(ctx, vr, ref, name):
+    """Field halos by adaptive 6D FOF (each 3D group re-linked with its own
+    alpha_v sigma_v and the full ellx), then the substructure search on
+    them: labels and group tables bit-exact, R within its tolerance."""
+    from oracle import pipeline as opipe
+    from paper_1902_01010_amd import pipeline
+    w = CASES[name]()
+    prm = dataclasses.replace(pipeline.Params.from_workload(w), field_6d=True)
+    exp = opipe.run(w, prm)
+    x, v, m = pipeline.device_inputs(w)
+    got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
+    assert (got["label3d"].cpu().numpy() == exp["label3d"]).all()
+    assert (got["label"].cpu().numpy() == exp["label"]).all()
+    assert got["n_groups"] == exp["n_groups"]
+    ng = exp["n_groups"]
+    np.testing.assert_array_equal(got["offsets"].cpu().numpy()[:ng + 1], exp["offsets"][:ng + 1])
+    np.testing.assert_array_equal(got["members"].cpu().numpy()[:exp["offsets"][ng]], exp["members"][:exp["offsets"][ng]])
+    # 6D only splits 3D groups: never more particles grouped, and every 6D
+    # group lies inside one 3D group
+    _, c3 = np.unique(exp["label3d"], return_counts=True)
+    assert exp["offsets"][ng] <= c3[c3 >= 20].sum()
+    lab3 = exp["label3d"]
+    for g in range(ng):
+        mm = exp["members"][exp["offsets"][g]:exp["offsets"][g + 1]]
+        assert (lab3[mm] == lab3[mm[0]]).all()
+    if exp["n_hosts"]:
+        _R_close(got["R"].cpu().numpy(), exp["R"])
