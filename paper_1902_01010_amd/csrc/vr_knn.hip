@@ -108,8 +108,12 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     __shared__ double vd[NVL][64];
     __shared__ int vp[NVL][64];
     __shared__ int stack[STACK];
-    // the leaf chunk being scanned: x, y, z (exact integers as float) and rank
-    __shared__ float4 cand[64];
+    // the leaf chunk being scanned, SoA: x, y, z (exact integers as float)
+    // and rank; four consecutive candidates are one 16-byte broadcast read
+    __shared__ __align__(16) float cxs[64];
+    __shared__ __align__(16) float cys[64];
+    __shared__ __align__(16) float czs[64];
+    __shared__ int crk[64];
     const int lane = threadIdx.x;
     const int64_t qi = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * 64 + lane;
     const bool active = qi < nq;
@@ -121,50 +125,82 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
     int count = 0;
     uint64_t worst = ~0ull;
+    // While a heap is not full it accepts only squared distances <= tau, a
+    // bound that at least n_se members of the host are known to meet (so the
+    // n_se nearest all meet it); NO_BOUND until such a bound is found.
+    constexpr uint64_t NO_BOUND = ~0ull >> POS_BITS;
+    uint64_t tau = NO_BOUND;
+
+    // Stages the members [c0, min(c0 + 64, t_end)) of a leaf in LDS for the
+    // unwrapped (no minimum image) scan; padding slots sit far away.
+    auto stage_chunk = [&](int c0, int t_end, int hbase) {
+        const int j = c0 + lane;
+        const bool vj = j < t_end;
+        cxs[lane] = vj ? (float)F.u[0][j] : 1e30f;
+        cys[lane] = vj ? (float)F.u[1][j] : 1e30f;
+        czs[lane] = vj ? (float)F.u[2][j] : 1e30f;
+        crk[lane] = vj ? F.eid[j] - hbase : 0;
+        __builtin_amdgcn_wave_barrier();
+    };
 
     // Inserts the members of leaf `node` for the lanes in `mine`.
     auto scan_leaf = [&](int node, bool mine, bool nowrap, int hbase) {
         const KdNode& nd = nodes[node];
         const int s = nd.start, t_end = nd.end;
         for (int c0 = s; c0 < t_end; c0 += 64) {
-            // one member per lane, then shared through LDS or lane reads
-            const int j = c0 + lane;
-            const bool vj = j < t_end;
-            const int lx = vj ? F.u[0][j] : 0, ly = vj ? F.u[1][j] : 0, lz = vj ? F.u[2][j] : 0;
-            const int le = vj ? F.eid[j] - hbase : 0;
             const int m = min(64, t_end - c0);
             if (nowrap) {
                 // FP32 prefilter: coordinates are integers below 2^24, so the
                 // differences are exact and the rounded sum of squares is within
                 // 2e-7 of the exact one; only candidates that may beat the
-                // current worst key get the exact integer key.
-                cand[lane] = make_float4((float)lx, (float)ly, (float)lz, __builtin_bit_cast(float, le));
-                __builtin_amdgcn_wave_barrier();
+                // current worst key (or meet tau) get the exact integer key.
+                stage_chunk(c0, t_end, hbase);
                 // pass 1 (no divergence): which candidates may beat this lane's
                 // current worst key; pass 2: insert them, each lane walking its
                 // own mask, so the wave spends max-over-lanes insertions per
-                // chunk instead of one per candidate that any lane takes
-                const float wf = count < n_se ? INFINITY : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
-                uint64_t take = 0;
-                for (int t = 0; t < m; ++t) {
-                    const float4 c4 = cand[t];  // same address for every lane: a broadcast
-                    const float dxf = c4.x - pxf, dyf = c4.y - pyf, dzf = c4.z - pzf;
-                    const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
-                    take |= (uint64_t)(d2f <= wf) << t;
+                // chunk instead of one per candidate that any lane takes.
+                // Pass 1 is unrolled in blocks of 16 candidates with constant
+                // bit positions; bits past the chunk's end are cleared.
+                const float wf = count < n_se ? (tau == NO_BOUND ? INFINITY : (float)tau * 1.000001f + 1.0f)
+                                              : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                uint32_t tk[2] = {0u, 0u};
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (16 * b < m) {
+#pragma unroll
+                        for (int t4 = 0; t4 < 16; t4 += 4) {
+                            const int t = 16 * b + t4;
+                            const float4 X = *reinterpret_cast<const float4*>(&cxs[t]);
+                            const float4 Y = *reinterpret_cast<const float4*>(&cys[t]);
+                            const float4 Z = *reinterpret_cast<const float4*>(&czs[t]);
+                            const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w},
+                                        zs[4] = {Z.x, Z.y, Z.z, Z.w};
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const float dxf = xs[u] - pxf, dyf = ys[u] - pyf, dzf = zs[u] - pzf;
+                                const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
+                                const int bit = t + u;
+                                if (d2f <= wf) tk[bit >> 5] |= 1u << (bit & 31);
+                            }
+                        }
+                    }
                 }
+                uint64_t take = ((uint64_t)tk[1] << 32) | tk[0];
+                if (m < 64) take &= (uint64_t(1) << m) - 1;
                 if (!mine) take = 0;
                 while (take) {
                     const int t = __builtin_ctzll(take);
                     take &= take - 1;
-                    const float4 c4 = cand[t];
                     // |d| < 2^21: unsigned 32-bit squares, exact 64-bit sum
-                    const uint32_t ax = (uint32_t)abs((int)(c4.x - pxf)), ay = (uint32_t)abs((int)(c4.y - pyf)),
-                                   az = (uint32_t)abs((int)(c4.z - pzf));
+                    const uint32_t ax = (uint32_t)abs((int)(cxs[t] - pxf)), ay = (uint32_t)abs((int)(cys[t] - pyf)),
+                                   az = (uint32_t)abs((int)(czs[t] - pzf));
                     const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)__builtin_bit_cast(uint32_t, c4.w);
+                    const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)crk[t];
                     if (count < n_se) {
-                        heap_push(heap, lane, count, key);
-                        if (count == n_se) worst = heap[0][lane];
+                        if (d2 <= tau) {
+                            heap_push(heap, lane, count, key);
+                            if (count == n_se) worst = heap[0][lane];
+                        }
                     } else if (key < worst) {
                         heap_replace_top(heap, lane, count, key);
                         worst = heap[0][lane];
@@ -173,6 +209,11 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                 __builtin_amdgcn_wave_barrier();
                 continue;
             }
+            // one member per lane, shared by lane reads
+            const int j = c0 + lane;
+            const bool vj = j < t_end;
+            const int lx = vj ? F.u[0][j] : 0, ly = vj ? F.u[1][j] : 0, lz = vj ? F.u[2][j] : 0;
+            const int le = vj ? F.eid[j] - hbase : 0;
             for (int t = 0; t < m; ++t) {
                 const int cx = __builtin_amdgcn_readlane(lx, t);
                 const int cy = __builtin_amdgcn_readlane(ly, t);
@@ -206,7 +247,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         const int64_t dz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
         int64_t md2 = dx * dx + dy * dy + dz * dz;
         if (md2 > (int64_t(1) << 41)) md2 = int64_t(1) << 41;
-        return __ballot(mine && (count < n_se || ((uint64_t)md2 << POS_BITS) <= worst)) != 0;
+        return __ballot(mine && (count < n_se ? (uint64_t)md2 <= tau : ((uint64_t)md2 << POS_BITS) <= worst)) != 0;
     };
 
     bool pending = active;
@@ -231,7 +272,11 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
             sz += __shfl_xor(sz, o, 64);
             cnt += __shfl_xor(cnt, o, 64);
         }
-        const int ccx = (int)(sx / cnt), ccy = (int)(sy / cnt), ccz = (int)(sz / cnt);
+        // wave-uniform; the near child is picked arithmetically on the split
+        // dimension (a select over the three would go through memory)
+        const int ccx = __builtin_amdgcn_readfirstlane((int)(sx / cnt));
+        const int ccy = __builtin_amdgcn_readfirstlane((int)(sy / cnt));
+        const int ccz = __builtin_amdgcn_readfirstlane((int)(sz / cnt));
         // Depth-first walk of the host's tree, near child first; skip_own:
         // the leaves holding a query of this pass were scanned already.
         auto walk = [&](bool skip_own) {
@@ -248,7 +293,8 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                     continue;
                 }
                 if (sp + 2 > STACK) break;  // cannot happen for trees of depth < 64
-                const int cf = nd.dim == 0 ? ccx : (nd.dim == 1 ? ccy : ccz);
+                const int dm = nd.dim;
+                const int cf = ccx + (dm >= 1) * (ccy - ccx) + (dm == 2) * (ccz - ccy);
                 const int nearc = cf < nd.t ? nd.left : nd.right;
                 const int farc = cf < nd.t ? nd.right : nd.left;
                 if (lane == 0) {
@@ -262,6 +308,65 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         if (!nowrap) {
             walk(false);
         } else {
+            // The bound tau: a lane's own leaf suggests a squared radius T0
+            // holding about n_se members (its density, n_se / (4/3 pi r^3)).
+            // Members of the wave's own leaves (all in this host) are counted
+            // under eight thresholds T0 * 2^((k-2)/2); the smallest threshold
+            // met by n_se of them, rounded up past the FP32 error of the
+            // counted distances, is a bound that n_se members meet.
+            float thr[8];
+            uint32_t cnt[8];
+            {
+                float T0 = 0.f;
+                if (mine) {
+                    const KdNode& on = nodes[own];
+                    const float vol = (float)(on.bmax[0] - on.bmin[0] + 1) * (float)(on.bmax[1] - on.bmin[1] + 1) *
+                                      (float)(on.bmax[2] - on.bmin[2] + 1);
+                    const float r = cbrtf(3.0f * (float)n_se * vol / (4.0f * (float)M_PI * (float)(on.end - on.start)));
+                    T0 = r * r;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    thr[k] = T0 * exp2f(0.5f * (float)(k - 2));
+                    cnt[k] = 0;
+                }
+            }
+            for (uint64_t todo = __ballot(mine); todo;) {
+                const int L = __builtin_amdgcn_readlane(own, __ffsll((unsigned long long)todo) - 1);
+                const KdNode& nl = nodes[L];
+                for (int c0 = nl.start; c0 < nl.end; c0 += 64) {
+                    stage_chunk(c0, nl.end, hbase);
+                    const int m = min(64, nl.end - c0);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        if (16 * b < m) {
+#pragma unroll
+                            for (int t4 = 0; t4 < 16; t4 += 4) {
+                                const int t = 16 * b + t4;
+                                const float4 X = *reinterpret_cast<const float4*>(&cxs[t]);
+                                const float4 Y = *reinterpret_cast<const float4*>(&cys[t]);
+                                const float4 Z = *reinterpret_cast<const float4*>(&czs[t]);
+                                const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w},
+                                            zs[4] = {Z.x, Z.y, Z.z, Z.w};
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) {
+                                    const float dxf = xs[u] - pxf, dyf = ys[u] - pyf, dzf = zs[u] - pzf;
+                                    const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
+#pragma unroll
+                                    for (int k = 0; k < 8; ++k) cnt[k] += d2f <= thr[k] ? 1u : 0u;
+                                }
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                todo &= ~__ballot(mine && own == L);
+            }
+            if (mine) {
+#pragma unroll
+                for (int k = 7; k >= 0; --k)
+                    if (cnt[k] >= (uint32_t)n_se) tau = (uint64_t)((double)thr[k] * (1.0 + 1e-6)) + 1;
+            }
             // the leaves of the queries themselves first: they fill every
             // heap with near neighbours, so the walk prunes from its start
             uint64_t todo = __ballot(mine);
