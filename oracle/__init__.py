@@ -44,6 +44,16 @@ class _CellParams(C.Structure):
                 ("nbins", C.c_int32), ("split_rule", C.c_int32)]
 
 
+class _EllParams(C.Structure):
+    _fields_ = [("lo", C.c_double), ("width", C.c_double), ("nbins", C.c_int32), ("peak_min", C.c_int32),
+                ("max_merge", C.c_int32), ("golden_iters", C.c_int32)]
+
+
+# fine grid of 1024 bins of 1/32 on [-16, 16); merge to >= 32 in the fullest
+# bin (factor <= 64); 48 golden-section steps
+ELL_DEFAULTS = dict(lo=-16.0, width=1.0 / 32, nbins=1024, peak_min=32, max_merge=64, golden_iters=48)
+
+
 class _UnbindParams(C.Structure):
     _fields_ = [("G", C.c_double), ("eps", C.c_double), ("beta_E", C.c_double),
                 ("frac_ref", C.c_double), ("n_min", C.c_int32), ("n_ref_min", C.c_int32),
@@ -77,6 +87,12 @@ def lib():
         L.vr_ref_host_ellv.argtypes = [P, i32, vp, vp, dbl, vp]
         L.vr_ref_fof6d.argtypes = [P, vp, i32, vp, dbl, vp, flt, vp]
         L.vr_ref_unbind.argtypes = [P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
+        L.vr_ref_ell_fit.argtypes = [i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp]
+        L.vr_ref_ell_cost.argtypes = [i32, vp, vp, dbl, vp]
+        L.vr_ref_ell_cost.restype = dbl
+        L.vr_ref_ell_mean.argtypes = [dbl]
+        L.vr_ref_ell_mean.restype = dbl
+        L.vr_ref_ell_clean.argtypes = [i64, i32, vp, vp, vp, dbl, dbl, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -243,3 +259,51 @@ def unbind(P: Particles, offsets, members, G, eps, beta_E=0.95, frac_ref=0.1, n_
         raise RuntimeError("oracle unbind did not converge within max_iter")
     _check(rc, "unbind")
     return dict(bound=bound, phi=phi, iters=iters[:ng], min_margin=margin[:ng])
+
+
+def ell_fit(R, host_offsets, host_members, ell_init=None, **params):
+    """Per-host skew-Gaussian fit of the binned R values and L = (R - Rbar) /
+    sigma_R (Sec. 2.2, Eqs. skewgaus and ell).  Returns dict(fit (nh, 4):
+    Rbar, sigma_R, s, A; status (nh,); merge (nh,); ell (n,) float32, NaN
+    outside the hosts unless ell_init is given)."""
+    R = np.ascontiguousarray(R, dtype=np.float32)
+    off = np.ascontiguousarray(host_offsets, dtype=np.int32)
+    mem = np.ascontiguousarray(host_members, dtype=np.int32)
+    nh = off.shape[0] - 1
+    ep = _EllParams(**{**ELL_DEFAULTS, **params})
+    fit = np.zeros((max(nh, 1), 4))
+    status = np.zeros(max(nh, 1), np.int32)
+    merge = np.zeros(max(nh, 1), np.int32)
+    ell = np.full(R.shape[0], np.nan, np.float32) if ell_init is None else np.array(ell_init, np.float32)
+    _check(lib().vr_ref_ell_fit(R.shape[0], nh, _p(off), _p(mem), _p(R), C.byref(ep), _p(fit), _p(status),
+                                _p(merge), _p(ell)), "ell_fit")
+    return dict(fit=fit[:nh], status=status[:nh], merge=merge[:nh], ell=ell)
+
+
+def ell_cost(x, w, c):
+    """Cost and (a, p, q) of the log-model least-squares fit at peak c."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    apq = np.zeros(3)
+    J = lib().vr_ref_ell_cost(x.shape[0], _p(x), _p(w), float(c), _p(apq))
+    return J, apq
+
+
+def ell_mean(ell_th):
+    """Expected L of chance outliers above ell_th (closed form after Eq. ellsig)."""
+    return lib().vr_ref_ell_mean(float(ell_th))
+
+
+def ell_clean(ell, offsets, members, label, ell_th=2.5, beta=1.0, n_min=20):
+    """Significance cleaning (Eq. ellsig).  Returns (label, removed): label a
+    copy with removed members -1 and kept ones relabelled by their smallest
+    index; removed[g] = members removed from group g (all when dissolved)."""
+    ell = np.ascontiguousarray(ell, dtype=np.float32)
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    lab = np.array(label, dtype=np.int32)
+    ng = off.shape[0] - 1
+    rem = np.zeros(max(ng, 1), np.int32)
+    _check(lib().vr_ref_ell_clean(ell.shape[0], ng, _p(off), _p(mem), _p(ell), float(ell_th), float(beta),
+                                  int(n_min), _p(lab), _p(rem)), "ell_clean")
+    return lab, rem[:ng]

@@ -43,12 +43,25 @@ def run(w, prm, timings=None):
     R = ref.local_vdensity(P, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
     t = tick("R", t)
     ellv = ref.host_ellv(P, hoff, hmem, prm.alpha_v)
-    label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
-    t = tick("fof6d", t)
+    ell = None
+    if getattr(prm, "use_ell", False):
+        # L = (R - Rbar) / sigma_R from each host's skew-Gaussian fit (Eqs.
+        # skewgaus, ell); outliers are L >= ell_th
+        ell = ref.ell_fit(R, hoff, hmem)["ell"]
+        t = tick("ell", t)
+        label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ell, prm.ell_th)
+        t = tick("fof6d", t)
+        nc, sub_of, sub_off, sub_mem = ref.groups(label6, prm.n_min)
+        # significance cleaning of the candidates (Eq. ellsig)
+        label6, _ = ref.ell_clean(ell, sub_off, sub_mem, label6, prm.ell_th, prm.beta_ell, prm.n_min)
+        t = tick("clean", t)
+    else:
+        label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
+        t = tick("fof6d", t)
     nc, sub_of, sub_off, sub_mem = ref.groups(label6, prm.n_min)
     t = tick("subgroups", t)
     ub = ref.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc else None
     tick("unbind", t)
-    out.update(cells=cm, R=R, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
+    out.update(cells=cm, R=R, ell=ell, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
                sub_members=sub_mem, unbind=ub)
     return out

@@ -775,3 +775,225 @@ extern "C" int vr_ref_unbind(const vr_ref_particles* p, int32_t n_groups, const 
     });
     return status.load();
 }
+
+// ---------------------------------------------------------------------------
+// Normalised ratio L (Sec. 2.2, Eqs. skewgaus and ell): per host, a
+// skew-Gaussian fitted to the binned R distribution gives its peak Rbar and
+// the dispersion sigma_R of its upper side; L = (R - Rbar) / sigma_R.
+
+extern "C" double vr_ref_ell_cost(int32_t nb, const double* x, const double* w, double c, double* apq) {
+    double Sw = 0, Swu = 0, Swv = 0, Swuu = 0, Swvv = 0, Swy = 0, Swuy = 0, Swvy = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const double d = x[b] - c;
+        const double u = x[b] < c ? d * d : 0.0;
+        const double v = x[b] < c ? 0.0 : d * d;
+        const double y = std::log(w[b]);
+        Sw += w[b];
+        Swu += w[b] * u;
+        Swv += w[b] * v;
+        Swuu += w[b] * u * u;
+        Swvv += w[b] * v * v;
+        Swy += w[b] * y;
+        Swuy += w[b] * u * y;
+        Swvy += w[b] * v * y;
+    }
+    const double inf = std::numeric_limits<double>::infinity();
+    if (!(Swuu > 0) || !(Swvv > 0)) return inf;
+    // normal equations of min sum w (y - a + p u + q v)^2; p and q eliminated
+    const double den = Sw - Swu * Swu / Swuu - Swv * Swv / Swvv;
+    if (!(den > 0)) return inf;
+    const double a = (Swy - Swu * Swuy / Swuu - Swv * Swvy / Swvv) / den;
+    const double pp = (Swu * a - Swuy) / Swuu;
+    const double qq = (Swv * a - Swvy) / Swvv;
+    double J = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const double d = x[b] - c;
+        const double u = x[b] < c ? d * d : 0.0;
+        const double v = x[b] < c ? 0.0 : d * d;
+        const double r = std::log(w[b]) - a + pp * u + qq * v;
+        J += w[b] * r * r;
+    }
+    if (apq) {
+        apq[0] = a;
+        apq[1] = pp;
+        apq[2] = qq;
+    }
+    return J;
+}
+
+extern "C" int vr_ref_ell_fit(int64_t n, int32_t n_hosts, const int32_t* host_offsets,
+                              const int32_t* host_members, const float* R, const vr_ref_ell_params* ep,
+                              double* fit, int32_t* status, int32_t* merge, float* ell) {
+    if (!ep || n < 0 || n_hosts < 0) return -1;
+    if (!members_ok(n, n_hosts, host_offsets, host_members)) return -1;
+    if (n_hosts > 0 && (!R || !fit || !status || !ell)) return -1;
+    if (!(ep->width > 0) || ep->nbins < 1 || ep->max_merge < 1 || (ep->max_merge & (ep->max_merge - 1)) ||
+        ep->nbins % ep->max_merge || ep->peak_min < 1 || ep->golden_iters < 0)
+        return -1;
+    const double inv_w = 1.0 / ep->width;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    parallel_for(n_hosts, [&](int64_t h) {
+        // fine histogram of the finite values
+        std::vector<int64_t> fine(ep->nbins, 0);
+        for (int32_t k = host_offsets[h]; k < host_offsets[h + 1]; ++k) {
+            const double r = (double)R[host_members[k]];
+            if (!std::isfinite(r)) continue;
+            const double t = std::floor((r - ep->lo) * inv_w);
+            if (t >= 0 && t < ep->nbins) ++fine[(int64_t)t];
+        }
+        // merge pairs of bins until the fullest holds peak_min
+        int32_t g = 1;
+        std::vector<int64_t> cnt = fine;
+        auto fullest = [](const std::vector<int64_t>& c) {
+            int64_t m = 0;
+            for (int64_t v : c) m = std::max(m, v);
+            return m;
+        };
+        while (g < ep->max_merge && fullest(cnt) < ep->peak_min) {
+            std::vector<int64_t> half(cnt.size() / 2);
+            for (size_t b = 0; b < half.size(); ++b) half[b] = cnt[2 * b] + cnt[2 * b + 1];
+            cnt.swap(half);
+            g *= 2;
+        }
+        if (merge) merge[h] = g;
+        const double step = ep->width * g;
+        std::vector<double> x, w;
+        int64_t bf = -1, bl = -1;
+        for (int64_t b = 0; b < (int64_t)cnt.size(); ++b)
+            if (cnt[b] > 0) {
+                x.push_back(ep->lo + ((double)b + 0.5) * step);
+                w.push_back((double)cnt[b]);
+                if (bf < 0) bf = b;
+                bl = b;
+            }
+        double* f = fit + 4 * h;
+        if (x.empty()) {
+            f[0] = f[1] = f[2] = f[3] = nan;
+            status[h] = -1;
+        } else {
+            const int32_t nb = (int32_t)x.size();
+            double best = std::numeric_limits<double>::infinity(), cbest = 0;
+            if (nb >= 4)
+                for (int64_t b = bf; b <= bl; ++b) {
+                    const double c = ep->lo + ((double)b + 0.5) * step;
+                    const double J = vr_ref_ell_cost(nb, x.data(), w.data(), c, nullptr);
+                    if (J < best) {
+                        best = J;
+                        cbest = c;
+                    }
+                }
+            bool ok = false;
+            if (std::isfinite(best)) {
+                // golden-section refinement over one merged bin either side
+                const double phi = 0.6180339887498949;
+                double lo = cbest - step, hi = cbest + step;
+                double x1 = hi - phi * (hi - lo), x2 = lo + phi * (hi - lo);
+                double f1 = vr_ref_ell_cost(nb, x.data(), w.data(), x1, nullptr);
+                double f2 = vr_ref_ell_cost(nb, x.data(), w.data(), x2, nullptr);
+                for (int32_t it = 0; it < ep->golden_iters; ++it) {
+                    if (f1 < f2) {
+                        hi = x2;
+                        x2 = x1;
+                        f2 = f1;
+                        x1 = hi - phi * (hi - lo);
+                        f1 = vr_ref_ell_cost(nb, x.data(), w.data(), x1, nullptr);
+                    } else {
+                        lo = x1;
+                        x1 = x2;
+                        f1 = f2;
+                        x2 = lo + phi * (hi - lo);
+                        f2 = vr_ref_ell_cost(nb, x.data(), w.data(), x2, nullptr);
+                    }
+                }
+                double c = 0.5 * (lo + hi);
+                if (!(vr_ref_ell_cost(nb, x.data(), w.data(), c, nullptr) <= best)) c = cbest;
+                double apq[3];
+                vr_ref_ell_cost(nb, x.data(), w.data(), c, apq);
+                if (apq[1] > 0 && apq[2] > 0) {
+                    f[0] = c;
+                    f[1] = 1.0 / std::sqrt(2.0 * apq[2]);
+                    f[2] = std::sqrt(apq[2] / apq[1]);
+                    f[3] = std::exp(apq[0]);
+                    ok = true;
+                }
+            }
+            if (!ok) {
+                // moments of the merged histogram
+                double sw = 0, swx = 0, m = 0;
+                for (int32_t b = 0; b < nb; ++b) {
+                    sw += w[b];
+                    swx += w[b] * x[b];
+                    m = std::max(m, w[b]);
+                }
+                const double mean = swx / sw;
+                double sxx = 0;
+                for (int32_t b = 0; b < nb; ++b) sxx += w[b] * (x[b] - mean) * (x[b] - mean);
+                const double sd = std::sqrt(sxx / sw);
+                f[0] = mean;
+                f[1] = sd > 0 ? sd : step;
+                f[2] = 1.0;
+                f[3] = m;
+            }
+            status[h] = ok ? 1 : 0;
+        }
+        for (int32_t k = host_offsets[h]; k < host_offsets[h + 1]; ++k) {
+            const int32_t i = host_members[k];
+            ell[i] = (float)(((double)R[i] - f[0]) / f[1]);
+        }
+    });
+    return 0;
+}
+
+// Expected L of Gaussian chance outliers above ell_th (the closed form that
+// follows Eq. ellsig: a truncated-Gaussian mean).
+extern "C" double vr_ref_ell_mean(double ell_th) {
+    const double pi = 3.14159265358979323846;
+    return std::sqrt(2.0 / pi) * std::exp(-0.5 * ell_th * ell_th) / std::erfc(ell_th / std::sqrt(2.0));
+}
+
+// Significance cleaning (Eq. ellsig): members leave in order of smallest L
+// until the mean L of the rest reaches Lbar (1 + beta / sqrt(N)).
+extern "C" int vr_ref_ell_clean(int64_t n, int32_t n_groups, const int32_t* offsets, const int32_t* members,
+                                const float* ell, double ell_th, double beta, int32_t n_min, int32_t* label,
+                                int32_t* removed) {
+    if (n < 0 || n_groups < 0 || n_min < 1) return -1;
+    if (!members_ok(n, n_groups, offsets, members)) return -1;
+    if (n_groups > 0 && (!ell || !label)) return -1;
+    const double Lbar = vr_ref_ell_mean(ell_th);
+    parallel_for(n_groups, [&](int64_t g) {
+        std::vector<int32_t> S(members + offsets[g], members + offsets[g + 1]);
+        std::vector<int32_t> order = S;
+        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return ell[a] < ell[b] || (ell[a] == ell[b] && a < b);
+        });
+        const int64_t N = (int64_t)order.size();
+        double sum = 0;
+        for (int32_t i : order) sum += (double)ell[i];
+        int64_t k = 0;
+        for (;;) {
+            const int64_t m = N - k;
+            if (m < n_min) {
+                k = N;  // dissolved
+                break;
+            }
+            if (sum / (double)m >= Lbar * (1.0 + beta / std::sqrt((double)m))) break;
+            sum -= (double)ell[order[k]];
+            ++k;
+        }
+        // S is ascending: the kept members in index order start at the root
+        std::vector<char> gone(N, 0);
+        for (int64_t r = 0; r < k; ++r)
+            gone[std::lower_bound(S.begin(), S.end(), order[r]) - S.begin()] = 1;
+        int32_t root = -1;
+        for (int64_t a = 0; a < N; ++a) {
+            if (gone[a]) {
+                label[S[a]] = -1;
+            } else {
+                if (root < 0) root = S[a];
+                label[S[a]] = root;
+            }
+        }
+        if (removed) removed[g] = (int32_t)k;
+    });
+    return 0;
+}

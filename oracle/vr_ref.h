@@ -137,6 +137,56 @@ int vr_ref_unbind(const vr_ref_particles* p, int32_t n_groups,
                   const vr_ref_unbind_params* up,
                   uint8_t* bound, double* phi, int32_t* iters, double* min_margin);
 
+/* ---- Normalised ratio L and significance cleaning (Sec. 2.2) ----------
+ *
+ * Per host, the finite R values of its members are binned on a fixed fine
+ * grid (nbins bins of `width` from `lo`); adjacent bins are merged in pairs
+ * until the fullest merged bin holds >= peak_min (merge factor <= max_merge).
+ * The skew-Gaussian of Eq. skewgaus is fitted to the merged counts n_b at the
+ * bin centres x_b by weighted least squares of ln n_b (weight n_b, the
+ * inverse Poisson variance of ln n_b): for a peak position c the model
+ * ln n = a - p (x-c)^2 [x<c] - q (x-c)^2 [x>=c] is linear in (a, p, q); c is
+ * the merged-bin centre of least cost, refined by golden-section search over
+ * one merged bin either side.  Then Rbar = c, sigma_R = 1/sqrt(2q),
+ * s = sqrt(q/p), A = exp(a), and L = (R - Rbar) / sigma_R (Eq. ell), in FP64
+ * rounded to float.  A host whose fit fails (fewer than 4 non-empty bins, or
+ * p, q not positive) takes the mean and dispersion of its merged histogram
+ * (status 0, s = 1); a host without binned values gets NaN (status -1). */
+typedef struct {
+    double lo;             /* lower edge of the fine grid (-16) */
+    double width;          /* fine bin width (1/32) */
+    int32_t nbins;         /* fine bins (1024), a multiple of max_merge */
+    int32_t peak_min;      /* merge until the fullest merged bin holds this many (32) */
+    int32_t max_merge;     /* largest merge factor, a power of two (64) */
+    int32_t golden_iters;  /* golden-section iterations (48) */
+} vr_ref_ell_params;
+
+/* fit[h*4 + 0..3] = Rbar, sigma_R, s, A; status[h] = 1 fitted, 0 moments,
+ * -1 no binned value; merge[h] (may be NULL) = merge factor; ell[i] for the
+ * members of every host (other entries untouched). */
+int vr_ref_ell_fit(int64_t n, int32_t n_hosts, const int32_t* host_offsets,
+                   const int32_t* host_members, const float* R,
+                   const vr_ref_ell_params* ep, double* fit, int32_t* status,
+                   int32_t* merge, float* ell);
+
+/* Least-squares cost of the log model at peak position c over nb bins
+ * (centres x, counts w > 0); apq (may be NULL) receives a, p, q.  +inf when
+ * a side of c holds no bin. */
+double vr_ref_ell_cost(int32_t nb, const double* x, const double* w, double c, double* apq);
+
+/* Mean L of a unit Gaussian above ell_th (the expected <L> of chance
+ * outliers, the closed form following Eq. ellsig). */
+double vr_ref_ell_mean(double ell_th);
+
+/* Significance cleaning (Eq. ellsig): while a group's mean L is below
+ * Lbar(ell_th) (1 + beta / sqrt(N)), remove its member of smallest L (ties:
+ * smaller index first); below n_min members the group dissolves.  label is
+ * updated in place for the members of every group: removed -> -1, kept ->
+ * the smallest kept index.  removed[g] (may be NULL) = members removed. */
+int vr_ref_ell_clean(int64_t n, int32_t n_groups, const int32_t* offsets,
+                     const int32_t* members, const float* ell, double ell_th,
+                     double beta, int32_t n_min, int32_t* label, int32_t* removed);
+
 #ifdef __cplusplus
 }
 #endif

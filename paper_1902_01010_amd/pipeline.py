@@ -33,6 +33,12 @@ class Params:
     n_min: int = 20
     host_min: int = 256
     field_6d: bool = False   # field halos by adaptive 6D FOF inside each 3D group (Sec. 2.1, Eq. fof6d)
+    # outliers by the normalised ratio L >= ell_th (Sec. 2.2, Eq. ell) instead
+    # of R >= R_threshold, and significance cleaning of the 6D groups with
+    # beta_L (Eq. ellsig)
+    use_ell: bool = False
+    ell_th: float = 2.5
+    beta_ell: float = 1.0
 
     @classmethod
     def from_workload(cls, w):
