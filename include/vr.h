@@ -217,6 +217,54 @@ int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, const int32_
               const int32_t* members, const vr_unbind_params* up, uint8_t* bound, double* phi,
               int32_t* iters, void* stream);
 
+/* ---- normalised ratio L and significance cleaning (Sec. 2.2) ---------------
+ * The paper normalises R by a skew-Gaussian fitted to each host's binned R
+ * distribution (Eq. skewgaus), L = (R - Rbar) / sigma_R (Eq. ell), thresholds
+ * L, and cleans candidate groups by their mean L (Eq. ellsig and the
+ * truncated-Gaussian mean that follows it). */
+typedef struct {
+    double lo;             /* lower edge of the fine R grid (-16) */
+    double width;          /* fine bin width (1/32) */
+    int32_t nbins;         /* fine bins (1024), a multiple of max_merge, <= 4096 */
+    int32_t peak_min;      /* merge bin pairs until the fullest holds this many (32) */
+    int32_t max_merge;     /* largest merge factor, a power of two (64) */
+    int32_t golden_iters;  /* golden-section iterations refining the peak (48), <= 200 */
+} vr_ell_params;
+
+/* Per host h: the finite R of its members are counted on the fine grid
+ * (bin floor((R - lo) / width); values off the grid are not counted); bin
+ * pairs are merged until the fullest merged bin holds peak_min (or the
+ * factor reaches max_merge).  On the non-empty merged bins (centres x_b,
+ * counts n_b) the log model ln n = a - p (x-c)^2 [x<c] - q (x-c)^2 [x>=c] is
+ * fitted by least squares weighted by n_b; for each c it is linear in
+ * (a, p, q); c is the merged-bin centre of least cost, refined by
+ * golden-section search over one merged bin either side.  Output (device):
+ * fit[h][4] = Rbar = c, sigma_R = 1/sqrt(2q), s = sqrt(q/p), A = exp(a);
+ * status[h] = 1 fitted; 0 when fewer than 4 bins are non-empty or p, q are
+ * not positive: then Rbar, sigma_R are the mean and dispersion of the merged
+ * histogram (the merged width if that is 0), s = 1, A = the fullest count;
+ * -1 when no value was counted (Rbar = sigma_R = NaN).  merge[h] (may be
+ * NULL) = merge factor.  ell[i] = (float)(((double)R[i] - Rbar) / sigma_R)
+ * for every member i of every host (NaN stays NaN); other entries are left
+ * alone.  Members of a host are distinct and ascending (as vr_groups gives
+ * them); R, ell: [n] device arrays. */
+int vr_ell_fit(vr_ctx* ctx, int64_t n, int32_t n_hosts, const int32_t* host_offsets,
+               const int32_t* host_members, const float* R, const vr_ell_params* ep, double* fit,
+               int32_t* status, int32_t* merge, float* ell, void* stream);
+
+/* Significance cleaning of candidate groups (offsets/members as vr_groups
+ * gives them): with Lbar = sqrt(2/pi) exp(-ell_th^2/2) / erfc(ell_th/sqrt 2),
+ * a group of N members whose mean L is below Lbar (1 + beta / sqrt(N)) loses
+ * its member of smallest L (ties: smaller index first), repeatedly; once
+ * fewer than n_min remain it is dissolved.  label (device [n]) is updated
+ * for the members of every group: removed -> -1, kept -> the smallest kept
+ * index; other entries are left alone.  removed (device [n_groups], may be
+ * NULL) = members removed per group (N when dissolved).  Means are FP64 sums
+ * of the float L. */
+int vr_ell_clean(vr_ctx* ctx, int64_t n, int32_t n_groups, const int32_t* offsets, const int32_t* members,
+                 const float* ell, double ell_th, double beta, int32_t n_min, int32_t* label,
+                 int32_t* removed, void* stream);
+
 /* ---- learned surrogate of R ------------------------------------------------
  * Predicts the R of vr_local_vdensity from 12 cheap per-particle features
  * (no neighbour search) with a 12-64-64-64-1 ReLU network; particles whose

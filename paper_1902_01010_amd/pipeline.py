@@ -115,8 +115,21 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     if until == "R":
         return out, ev
     ellv = ctx.host_ellv(P, host_offsets, members, prm.alpha_v)
-    label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
-    mark("fof6d")
+    if prm.use_ell:
+        # L from each host's skew-Gaussian fit of R; 6D groups over L >= ell_th,
+        # cleaned by their mean L
+        ef = ctx.ell_fit(R, host_offsets, members)
+        out.update(ell=ef["ell"], ell_fit=ef["fit"], ell_status=ef["status"], ell_merge=ef["merge"])
+        mark("ell")
+        label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th)
+        mark("fof6d")
+        nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
+        if nc > 0:
+            ctx.ell_clean(ef["ell"], sub_off, sub_mem, label6, prm.ell_th, prm.beta_ell, prm.n_min)
+        mark("clean")
+    else:
+        label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
+        mark("fof6d")
     nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
     mark("subgroups")
     ub = ctx.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc > 0 else None

@@ -23,7 +23,7 @@ ENTRY_POINTS = (
     "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
     "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune", "vr_autotune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
-    "vr_host_ellv", "vr_fof6d", "vr_unbind",
+    "vr_host_ellv", "vr_fof6d", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
     "vr_rs_features", "vr_mlp_forward", "vr_mlp_grad", "vr_mlp_train_step", "vr_rs_select",
 )
 
@@ -55,6 +55,16 @@ class _UnbindParams(C.Structure):
                 ("frac_ref", C.c_double), ("n_min", C.c_int32), ("n_ref_min", C.c_int32),
                 ("frame_type", C.c_int32), ("max_iter", C.c_int32), ("persistent", C.c_int32),
                 ("tile", C.c_int32)]
+
+
+class _EllParams(C.Structure):
+    _fields_ = [("lo", C.c_double), ("width", C.c_double), ("nbins", C.c_int32), ("peak_min", C.c_int32),
+                ("max_merge", C.c_int32), ("golden_iters", C.c_int32)]
+
+
+# R grid of the per-host fit: 1024 bins of 1/32 on [-16, 16), bin pairs merged
+# until the fullest holds 32 (factor <= 64), 48 golden-section steps
+ELL_PARAMS = dict(lo=-16.0, width=1.0 / 32, nbins=1024, peak_min=32, max_merge=64, golden_iters=48)
 
 
 class _AdamParams(C.Structure):
@@ -95,6 +105,8 @@ def load_library():
         L.vr_host_ellv.argtypes = [vp, P, i32, vp, vp, dbl, vp, vp]
         L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
         L.vr_unbind.argtypes = [vp, P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
+        L.vr_ell_fit.argtypes = [vp, i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp, vp]
+        L.vr_ell_clean.argtypes = [vp, i64, i32, vp, vp, vp, dbl, dbl, i32, vp, vp, vp]
         fp = C.POINTER(C.c_float)
         L.vr_rs_features.argtypes = [vp, P, i32, vp, vp, vp, vp, vp, i32, i32, fp, fp, vp, C.POINTER(i64), vp]
         L.vr_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
@@ -300,6 +312,34 @@ class Context:
         self._check(self.lib.vr_unbind(self.h, C.byref(P.s), ng, _ptr(offsets), _ptr(members), C.byref(up),
                                        _ptr(bound), _ptr(phi), _ptr(iters), _stream()))
         return dict(bound=bound, phi=phi, iters=iters[:ng])
+
+    # ---- normalised ratio L and cleaning ---------------------------------------
+    def ell_fit(self, R, host_offsets, host_members, ell=None, **params):
+        """Per-host skew-Gaussian fit of the binned R and L = (R - Rbar) / sigma_R.
+        Returns dict(fit (nh, 4) float64: Rbar, sigma_R, s, A; status; merge;
+        ell (n,) float32, NaN outside the hosts unless `ell` is given)."""
+        nh = host_offsets.shape[0] - 1
+        n = R.shape[0]
+        dev = R.device
+        ep = _EllParams(**{**ELL_PARAMS, **params})
+        fit = torch.zeros((max(nh, 1), 4), dtype=torch.float64, device=dev)
+        status = torch.zeros(max(nh, 1), dtype=torch.int32, device=dev)
+        merge = torch.zeros(max(nh, 1), dtype=torch.int32, device=dev)
+        if ell is None:
+            ell = torch.full((n,), float("nan"), dtype=torch.float32, device=dev)
+        self._check(self.lib.vr_ell_fit(self.h, n, nh, _ptr(host_offsets), _ptr(host_members), _ptr(R),
+                                        C.byref(ep), _ptr(fit), _ptr(status), _ptr(merge), _ptr(ell), _stream()))
+        return dict(fit=fit[:nh], status=status[:nh], merge=merge[:nh], ell=ell)
+
+    def ell_clean(self, ell, offsets, members, label, ell_th=2.5, beta=1.0, n_min=20):
+        """Significance cleaning of the groups; updates `label` in place and
+        returns (label, removed per group)."""
+        ng = offsets.shape[0] - 1
+        removed = torch.zeros(max(ng, 1), dtype=torch.int32, device=ell.device)
+        self._check(self.lib.vr_ell_clean(self.h, ell.shape[0], ng, _ptr(offsets), _ptr(members), _ptr(ell),
+                                          float(ell_th), float(beta), int(n_min), _ptr(label), _ptr(removed),
+                                          _stream()))
+        return label, removed[:ng]
 
     # ---- learned surrogate of R ------------------------------------------------
     def rs_features(self, P: Particles, host_offsets, host_members, vbar, sigma, rho_cell, n_se=32,

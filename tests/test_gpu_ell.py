@@ -1,0 +1,179 @@
+"""GPU parity of the normalised ratio L (vr_ell_fit) and of the significance
+cleaning (vr_ell_clean) against the CPU oracle, on the same inputs.
+
+Tolerances: merge factors, statuses, labels and removal counts are exact.
+The fit's FP64 sums run in another order on the GPU.  The cost is flat at
+its minimum, so a rounding change of relative size e in the cost moves the
+peak by about sqrt(e) of its curvature scale: the peak agrees to 1e-4 of a
+merged bin, sigma_R, s, A to 1e-6 relative, L to 1e-6 max(1, |L|), and the
+classification at ell_th = 2.5 outside that band.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1902_01010_amd import synth
+from tests.gpu_common import both, dev_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vr():
+    from paper_1902_01010_amd import vr as _vr
+    return _vr
+
+
+@pytest.fixture(scope="module")
+def ctx(vr):
+    return vr.Context(0)
+
+
+def skew_samples(n, c, sig, s, rng):
+    left = rng.random(n) < s / (1.0 + s)
+    z = np.abs(rng.standard_normal(n))
+    return np.where(left, c - z * s * sig, c + z * sig)
+
+
+def host_set(seed):
+    """Hosts of several sizes and shapes over a shuffled index space, with
+    NaN and inf values, a host of three bins and a host of NaN only."""
+    rng = np.random.default_rng(seed)
+    specs = [(200_000, 0.2, 0.6, 1.4), (40_000, -0.5, 0.5, 1.0), (5000, 0.9, 0.8, 0.7), (1000, 0.0, 0.6, 1.6),
+             (300, 0.3, 0.7, 1.2), (256, -1.0, 0.4, 1.1)]
+    sizes = [s[0] for s in specs] + [12, 10]
+    n = sum(sizes) + 5000
+    perm = rng.permutation(n)
+    R = rng.normal(0, 3, n).astype(np.float32)  # values of non-members
+    off, mem, pos = [0], [], 0
+    for k, sz in enumerate(sizes):
+        m = np.sort(perm[pos:pos + sz])
+        pos += sz
+        if k < len(specs):
+            _, c, sig, s = specs[k]
+            R[m] = skew_samples(sz, c, sig, s, rng)
+            R[m[:3]] = [np.nan, np.inf, 40.0]  # not finite, and off the grid
+        elif k == len(specs):
+            R[m] = rng.choice([0.5, 0.53, 0.56], sz)
+        else:
+            R[m] = np.nan
+        mem.append(m)
+        off.append(off[-1] + sz)
+    return R, np.array(off, np.int32), np.concatenate(mem).astype(np.int32)
+
+
+def check_fit(got, exp, step_of):
+    gs, es = got["status"].cpu().numpy(), exp["status"]
+    gm, em = got["merge"].cpu().numpy(), exp["merge"]
+    np.testing.assert_array_equal(gs, es)
+    np.testing.assert_array_equal(gm, em)
+    gf, ef = got["fit"].cpu().numpy(), exp["fit"]
+    for h in range(len(es)):
+        if es[h] < 0:
+            assert np.isnan(gf[h]).all()
+            continue
+        assert abs(gf[h, 0] - ef[h, 0]) <= 1e-4 * step_of(em[h])
+        np.testing.assert_allclose(gf[h, 1:], ef[h, 1:], rtol=1e-6)
+
+
+def check_ell(g, e, th=2.5):
+    assert (np.isnan(g) == np.isnan(e)).all()
+    assert (np.isinf(g) == np.isinf(e)).all() and (g[np.isinf(e)] == e[np.isinf(e)]).all()
+    fin = np.isfinite(e)
+    err = np.abs(g[fin].astype(np.float64) - e[fin]) / np.maximum(1.0, np.abs(e[fin]))
+    assert err.max() <= 1e-6, err.max()
+    band = np.abs(e.astype(np.float64) - th) <= 1e-5 * th
+    assert ((g >= th) == (e >= th))[~band].all()
+
+
+@pytest.mark.parametrize("params", [{}, dict(nbins=2048, width=1 / 64, lo=-16.0, max_merge=8, peak_min=100),
+                                    dict(golden_iters=0), dict(peak_min=1, max_merge=1)])
+def test_ell_fit_parity(ctx, ref, params):
+    R, off, mem = host_set(1)
+    init = np.full(R.shape[0], -7.0, np.float32)
+    exp = ref.ell_fit(R, off, mem, ell_init=init, **params)
+    got = ctx.ell_fit(dev_tensor(R), dev_tensor(off), dev_tensor(mem), ell=dev_tensor(init), **params)
+    width = params.get("width", 1 / 32)
+    check_fit(got, exp, lambda g: g * width)
+    check_ell(got["ell"].cpu().numpy(), exp["ell"])
+    if not params:
+        assert list(exp["status"]) == [1, 1, 1, 1, 1, 1, 0, -1]
+
+
+def test_ell_fit_rejects_bad_params(ctx, vr):
+    R, off, mem = host_set(2)
+    for bad in (dict(nbins=4096), dict(max_merge=3), dict(nbins=1000), dict(width=0.0), dict(golden_iters=500)):
+        with pytest.raises(vr.VrError):
+            ctx.ell_fit(dev_tensor(R), dev_tensor(off), dev_tensor(mem), **bad)
+
+
+def clean_case(seed, sizes):
+    rng = np.random.default_rng(seed)
+    n = sum(sizes) + 1000
+    ell = rng.normal(3.2, 1.2, n).astype(np.float32)
+    ell[rng.random(n) < 0.2] = np.float32(2.5)
+    ell[rng.random(n) < 0.001] = np.inf
+    perm = rng.permutation(n)
+    groups, pos = [], 0
+    for sz in sizes:
+        groups.append(np.sort(perm[pos:pos + sz]))
+        pos += sz
+    off = np.r_[0, np.cumsum(sizes)].astype(np.int32)
+    mem = np.concatenate(groups).astype(np.int32)
+    label = np.full(n, -3, np.int32)
+    for g in groups:
+        label[g] = g[0]
+    return ell, off, mem, label
+
+
+@pytest.mark.parametrize("seed,sizes", [(5, [20, 21, 25, 40, 60, 150, 400, 900, 3000]), (6, [150_000, 257, 256, 255]),
+                                        (7, [20] * 300)])
+def test_ell_clean_parity(ctx, ref, seed, sizes):
+    ell, off, mem, label = clean_case(seed, sizes)
+    for beta in (0.0, 1.0, 3.0):
+        exp_lab, exp_rem = ref.ell_clean(ell, off, mem, label, 2.5, beta, 20)
+        lab = dev_tensor(label.copy())
+        _, rem = ctx.ell_clean(dev_tensor(ell), dev_tensor(off), dev_tensor(mem), lab, 2.5, beta, 20)
+        np.testing.assert_array_equal(rem.cpu().numpy(), exp_rem)
+        np.testing.assert_array_equal(lab.cpu().numpy(), exp_lab)
+
+
+CASES = {
+    "halo12k": lambda: synth.isolated_halo(seed=21, n_host=12000, n_sub=3, sub_range=(400, 1500)),
+    "box48": lambda: synth.cosmo_box(seed=22, n_side=48),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pipeline_with_ell_stagewise(ctx, vr, ref, name):
+    """The hot path with outliers by L >= 2.5 and cleaning: every stage after
+    R is recomputed by the oracle from the GPU's own inputs to that stage."""
+    from paper_1902_01010_amd import pipeline
+    w = CASES[name]()
+    prm = dataclasses.replace(pipeline.Params.from_workload(w), use_ell=True)
+    x, v, m = pipeline.device_inputs(w)
+    got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
+    assert got["n_hosts"] > 0
+    P, Pr = both(ctx, vr, ref, w)
+    R = got["R"].cpu().numpy()
+    hoff = got["host_offsets"].cpu().numpy()
+    mem = got["members"].cpu().numpy()
+    hmem = mem[:hoff[-1]]
+    e = ref.ell_fit(R, hoff, hmem)
+    check_fit(dict(status=got["ell_status"], merge=got["ell_merge"], fit=got["ell_fit"]), e, lambda g: g / 32)
+    ell = got["ell"].cpu().numpy()
+    check_ell(ell, e["ell"])
+    # 6D groups over L >= 2.5 from the GPU's L, then cleaning
+    gof = got["group_of"].cpu().numpy()
+    host_of = np.where((gof >= 0) & (gof < got["n_hosts"]), gof, -1).astype(np.int32)
+    ellv = ref.host_ellv(Pr, hoff, hmem, prm.alpha_v)
+    lab6 = ref.fof6d(Pr, host_of, ellv, prm.alpha_xs * prm.ellx, ell, prm.ell_th)
+    nc, _, soff, smem = ref.groups(lab6, prm.n_min)
+    lab6c, rem = ref.ell_clean(ell, soff, smem, lab6, prm.ell_th, prm.beta_ell, prm.n_min)
+    np.testing.assert_array_equal(got["label6"].cpu().numpy(), lab6c)
+    nc2, _, soff2, _ = ref.groups(lab6c, prm.n_min)
+    assert got["n_candidates"] == nc2
+    if name == "halo12k":
+        assert nc2 >= 1  # planted subhalos survive the cleaning as candidates
