@@ -161,8 +161,10 @@ int vr_cell_moments(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
  * index); V_k = the n_v members of S_k nearest in velocity; h = velocity
  * distance to the n_v-th; f_l = sum_V m_j W(|dv_j|/h) / (h^3 sum_S m_j) with
  * the 3D Epanechnikov kernel W(u) = 15/(8 pi) (1 - u^2); f_bg = Gaussian at
- * vbar(x_k), sigma(x_k).  2 <= n_v <= n_se <= 64, every host has >= n_se
- * members.  subset (may be NULL = all host members) lists the particles to
+ * vbar(x_k), sigma(x_k).  2 <= n_v <= n_se <= 256 and n_v <= 32 when
+ * n_se > 64 (the paper's defaults, 256 and 32, are the largest case; beyond
+ * n_se = 32 a workgroup's LDS heaps cut the occupancy), every host has
+ * >= n_se members.  subset (may be NULL = all host members) lists the particles to
  * process; R is written only for them (NaN if sigma is not positive
  * definite, +inf if h = 0). */
 int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,

@@ -92,9 +92,10 @@ __device__ __forceinline__ void heap_replace_top(uint64_t (*heap)[64], int lane,
 
 __device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { return a < b || (a == b && pa < pb); }
 
-// NVR > 0: exactly NVR velocity neighbours kept in registers (sorted by an
-// unrolled insertion network); NVR == 0: any n_v, kept in LDS.
-template <int NSE, int NVR>
+// NSE: heap capacity (n_se <= NSE).  NVR > 0: exactly NVR velocity
+// neighbours kept in registers (sorted by an unrolled insertion network);
+// NVR == 0: any n_v <= NVLMAX, kept in LDS.
+template <int NSE, int NVR, int NVLMAX>
 __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, int64_t nq,
                                             const KdNode* __restrict__ nodes, Elems F, const int* __restrict__ leaf_of,
                                             const float* __restrict__ Vx, const float* __restrict__ Vy,
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                                             const float* __restrict__ vbar, const float* __restrict__ sigma, int64_t n,
                                             int n_se, int n_v, int use_mass, double mass_value, int gb,
                                             float* __restrict__ R, unsigned xchunk) {
-    constexpr int NVL = NVR > 0 ? 1 : NSE;
+    constexpr int NVL = NVR > 0 ? 1 : NVLMAX;
     __shared__ uint64_t heap[NSE][64];
     __shared__ double vd[NVL][64];
     __shared__ int vp[NVL][64];
@@ -473,12 +474,12 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     R[g] = (float)(lfl - lfb);
 }
 
-template <int NSE, int NVR>
+template <int NSE, int NVR, int NVLMAX>
 int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx, const float* Vy,
                const float* Vz, const float* Me, const int32_t* host_off, const vr_particles* p, const float* vbar,
                const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
     VR_TIMED(ctx, "knn", st, nq,
-             hipLaunchKernelGGL((k_knn<NSE, NVR>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
+             hipLaunchKernelGGL((k_knn<NSE, NVR, NVLMAX>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
                                 tree.F, tree.seg_node, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n,
                                 n_se, n_v,
                                 tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
@@ -498,8 +499,9 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     int rc = check_particles(ctx, p, true);
     if (rc) return rc;
     if ((rc = check_hosts(ctx, n_hosts, host_offsets, host_members))) return rc;
-    if (n_v < 2 || n_v > n_se || n_se > 64)
-        return set_err(ctx, VR_ERR_INVALID_ARG, "need 2 <= n_v <= n_se <= 64 (got n_se=%d, n_v=%d)", n_se, n_v);
+    if (n_v < 2 || n_v > n_se || n_se > 256 || (n_se > 64 && n_v > 32))
+        return set_err(ctx, VR_ERR_INVALID_ARG,
+                       "need 2 <= n_v <= n_se <= 256, and n_v <= 32 when n_se > 64 (got n_se=%d, n_v=%d)", n_se, n_v);
     if (subset && n_subset < 0) return set_err(ctx, VR_ERR_INVALID_ARG, "n_subset < 0");
     if (n_hosts == 0 || (subset && n_subset == 0)) return VR_OK;
     if (!vbar || !sigma || !R) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
@@ -551,8 +553,14 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         nq = n_subset;
     }
     if (n_se <= 32 && n_v == 8)
-        return launch_knn<32, 8>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 8, 1>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
     if (n_se <= 32)
-        return launch_knn<32, 0>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
-    return launch_knn<64, 0>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    if (n_se <= 64)
+        return launch_knn<64, 0, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    if (n_se <= 128)
+        return launch_knn<128, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R,
+                                      st);
+    // the paper's defaults (n_se 256, n_v 32): 157 KB of LDS, one workgroup per CU
+    return launch_knn<256, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
 }

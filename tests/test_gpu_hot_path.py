@@ -105,6 +105,26 @@ def test_local_vdensity_parity_same_inputs(ctx, ref, case):
     _R_close(got, exp)
 
 
+@pytest.mark.parametrize("n_se,n_v", [(256, 32), (100, 20), (64, 64)])
+def test_local_vdensity_large_neighbour_sets(ctx, ref, case, n_se, n_v):
+    # up to the paper's own defaults, 256 spatial and 32 velocity neighbours
+    P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    exp = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], n_se, n_v)["R"]
+    got = ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(cm["vbar"]),
+                             dev_tensor(cm["sigma"]), n_se, n_v).cpu().numpy()
+    _R_close(got, exp)
+
+
+def test_local_vdensity_rejects_sizes(ctx, vr, case):
+    P, hoff, hmem, w = case["P"], case["hoff"], case["hmem"], case["w"]
+    z = torch.zeros(3 * P.n, dtype=torch.float32, device="cuda")
+    for n_se, n_v in [(257, 8), (128, 33), (8, 9), (8, 1)]:
+        with pytest.raises(vr.VrError):
+            ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), z, torch.zeros(6 * P.n, device="cuda"), n_se,
+                               n_v)
+
+
 def test_local_vdensity_end_to_end(ctx, ref, case):
     P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
     cm = ref.cell_moments(Pr, hoff, hmem)
