@@ -39,6 +39,8 @@ KERNEL_MODEL = {
     "unbind_persistent": ("alu", 6.0, "ordered pair, whole graph-replayed unbinding of one call"),
     "rs_features": ("hbm", 76.0, "row: q 12, v 12, vbar 12, sigma 24, rho 4, member 4 in; 12 BF16 out"),
     "mlp_forward": ("mfma", 18048.0, "row: 9,024 multiply-adds of the 12-64-64-64-1 network"),
+    "ell_fit": ("hbm", 12.0, "member: index 4 + R 4 in, L 4 out"),
+    "ell_clean": ("hbm", 12.0, "member: index 4 + L 4 in, label 4 out"),
 }
 
 
@@ -219,6 +221,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="time the exact path only")
     ap.add_argument("--field-6d", action="store_true",
                     help="hosts are field halos from adaptive 6D FOF inside each 3D group (not the headline path)")
+    ap.add_argument("--ell", action="store_true",
+                    help="outliers by the normalised ratio L >= 2.5 with significance cleaning (not the headline path)")
+    ap.add_argument("--n-se", type=int, default=0, help="spatial neighbours (0 = the workload's 32)")
+    ap.add_argument("--n-v", type=int, default=0, help="velocity neighbours (0 = the workload's 8)")
     ap.add_argument("--workload", choices=("box", "unbind"), default="box",
                     help="box: the 256^3 hot path (default); unbind: batched unbinding of 50k groups")
     ap.add_argument("--unbind-groups", type=int, default=5_000,
@@ -238,9 +244,15 @@ def main():
 
     w = synth.cosmo_box(n_side=args.n_side)
     prm = pipeline.Params.from_workload(w)
+    import dataclasses
     if args.field_6d:
-        import dataclasses
         prm = dataclasses.replace(prm, field_6d=True)
+    if args.ell:
+        prm = dataclasses.replace(prm, use_ell=True)
+    if args.n_se:
+        prm = dataclasses.replace(prm, n_se=args.n_se)
+    if args.n_v:
+        prm = dataclasses.replace(prm, n_v=args.n_v)
     ctx = vr.Context(0)
     knobs = ctx.autotune(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else {k: ctx.get_tune(k) for k in vr.TUNE_KNOBS}
     x, v, m = pipeline.device_inputs(w)
@@ -304,8 +316,9 @@ def main():
     if sur is not None and sur["recall"] >= 0.995 and sur["value"] > value:
         path, headline, headline_ms = "surrogate+fallback", sur["value"], sur["ms_per_step"]
     ub = out.get("unbind")
+    outl = (out["ell"] >= prm.ell_th) if prm.use_ell else (out["R"] >= prm.R_threshold)
     summary = {"groups_3d": out["n_groups"], "hosts_searched": out["n_hosts"], "particles_searched": out["n_searched"],
-               "outliers": int((out["R"] >= prm.R_threshold).sum().item()),
+               "outliers": int(outl.sum().item()),
                "candidates_6d": out.get("n_candidates", 0)}
     if ub is not None:
         summary["bound_particles"] = int(ub["bound"].sum().item())
@@ -320,6 +333,8 @@ def main():
                                   f"Plummer subhalos + uniform background",
                       "n_particles": w.n, "box_mpc_h": w.box, "b": 0.2, "n_se": prm.n_se, "n_v": prm.n_v,
                       "R_threshold": prm.R_threshold, "field_hosts": "6D FOF" if prm.field_6d else "3D FOF",
+                      "outliers": f"L >= {prm.ell_th:g}, cleaned (beta_L {prm.beta_ell:g})" if prm.use_ell
+                      else f"R >= {prm.R_threshold:g}",
                       "parallelism": "1 GPU", "launch_knobs": knobs},
            "roofline": roofline, "kernels": kernels, "summary": summary,
            "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}

@@ -16,7 +16,7 @@ import torch
 from . import vr as _vr
 
 KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group",
-           "unbind_persistent", "rs_features", "mlp_forward")
+           "unbind_persistent", "rs_features", "mlp_forward", "ell_fit", "ell_clean")
 
 
 @dataclasses.dataclass
