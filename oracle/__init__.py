@@ -12,6 +12,7 @@ the C calls and return numpy arrays.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -86,6 +87,7 @@ def lib():
                                             vp, vp]
         L.vr_ref_host_ellv.argtypes = [P, i32, vp, vp, dbl, vp]
         L.vr_ref_fof6d.argtypes = [P, vp, i32, vp, dbl, vp, flt, vp]
+        L.vr_ref_fof_sub.argtypes = [P, vp, i32, vp, dbl, vp, flt, dbl, dbl, vp]
         L.vr_ref_unbind.argtypes = [P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
         L.vr_ref_ell_fit.argtypes = [i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp]
         L.vr_ref_ell_cost.argtypes = [i32, vp, vp, dbl, vp]
@@ -239,6 +241,20 @@ def fof6d(P: Particles, host_of, ellv_host, ellx_s, R=None, R_threshold=2.0):
     lab = np.zeros(P.n, np.int32)
     _check(lib().vr_ref_fof6d(C.byref(P.s), _p(hof), nh, _p(ev), float(ellx_s), _p(Rr),
                               float(R_threshold), _p(lab)), "fof6d")
+    return lab
+
+
+def fof_sub(P: Particles, host_of, n_hosts, vbar, ellx_s, L, L_threshold=2.5, Vr=2.0, cos_op=None,
+            theta_op=math.pi / 10):
+    """The paper's substructure linker (Sec. 2.2, Eq. linkingcriteria); label =
+    smallest participant index of the component, -1 for non-participants."""
+    hof = np.ascontiguousarray(host_of, dtype=np.int32)
+    vb = np.ascontiguousarray(vbar, dtype=np.float32)
+    Lr = np.ascontiguousarray(L, dtype=np.float32)
+    c = math.cos(theta_op) if cos_op is None else float(cos_op)
+    lab = np.zeros(P.n, np.int32)
+    _check(lib().vr_ref_fof_sub(C.byref(P.s), _p(hof), int(n_hosts), _p(vb), float(ellx_s), _p(Lr),
+                                float(L_threshold), float(Vr), c, _p(lab)), "fof_sub")
     return lab
 
 

@@ -683,6 +683,43 @@ extern "C" int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of, i
     return 0;
 }
 
+// The paper's own substructure linker (Sec. 2.2, Eq. linkingcriteria): both
+// particles significant outliers (L >= L_th), closer than the substructure
+// linking length, speeds within a factor Vr and velocity directions within
+// the opening angle, velocities taken relative to the local mean velocity.
+extern "C" int vr_ref_fof_sub(const vr_ref_particles* p, const int32_t* host_of, int32_t n_hosts,
+                              const float* vbar, double ellx_s, const float* L, float L_threshold, double Vr,
+                              double cos_op, int32_t* label) {
+    if (!valid_particles(p) || !has_vel(p) || (p->n > 0 && (!host_of || !vbar || !L || !label))) return -1;
+    if (!(Vr >= 1.0) || !(cos_op >= -1.0 && cos_op <= 1.0) || n_hosts < 0) return -1;
+    const double ell2 = vr_ref_ell2_grid(ellx_s, p->box, p->grid_bits);
+    if (!(ell2 > 0) || !(std::sqrt(ell2) < std::ldexp(1.0, p->grid_bits - 1))) return -1;
+    const int64_t n = p->n;
+    std::vector<int32_t> part;
+    for (int64_t i = 0; i < n; ++i)
+        if (host_of[i] >= 0 && host_of[i] < n_hosts && L[i] >= L_threshold) part.push_back((int32_t)i);
+    auto rel = [&](int64_t i, double* u) {
+        u[0] = (double)p->vx[i] - (double)vbar[i];
+        u[1] = (double)p->vy[i] - (double)vbar[n + i];
+        u[2] = (double)p->vz[i] - (double)vbar[2 * n + i];
+        return std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    };
+    MinUnionFind uf(n);
+    for_grid_pairs(p, part, std::sqrt(ell2), [&](int32_t i, int32_t j) {
+        if (host_of[i] != host_of[j]) return;
+        if (!((double)dist2_grid(p, i, j) < ell2)) return;
+        double ui[3], uj[3];
+        const double si = rel(i, ui), sj = rel(j, uj);
+        if (!(si > 0 && sj > 0)) return;
+        if (!(si <= Vr * sj && sj <= Vr * si)) return;
+        const double dot = ui[0] * uj[0] + ui[1] * uj[1] + ui[2] * uj[2];
+        if (dot >= cos_op * si * sj) uf.unite(i, j);
+    });
+    for (int64_t i = 0; i < n; ++i) label[i] = -1;
+    for (int32_t i : part) label[i] = uf.find(i);
+    return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Unbinding (Sec. 2.2, Eq. binding): remove beta_E T + W >= 0, iterate until
 // no particle is removed; the group is dissolved below N_min members.
