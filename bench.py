@@ -40,6 +40,7 @@ KERNEL_MODEL = {
     "rs_features": ("hbm", 76.0, "row: q 12, v 12, vbar 12, sigma 24, rho 4, member 4 in; 12 BF16 out"),
     "mlp_forward": ("mfma", 18048.0, "row: 9,024 multiply-adds of the 12-64-64-64-1 network"),
     "ell_fit": ("hbm", 12.0, "member: index 4 + R 4 in, L 4 out"),
+    "fof_link_sub": ("hbm", 56.0, "participant: q 12, v 12, vbar 12, host 4, parent 4, u + speed 12 (FP32 equiv.)"),
     "ell_clean": ("hbm", 12.0, "member: index 4 + L 4 in, label 4 out"),
 }
 
@@ -223,6 +224,9 @@ def main():
                     help="hosts are field halos from adaptive 6D FOF inside each 3D group (not the headline path)")
     ap.add_argument("--ell", action="store_true",
                     help="outliers by the normalised ratio L >= 2.5 with significance cleaning (not the headline path)")
+    ap.add_argument("--linker", choices=("6d", "paper"), default="6d",
+                    help="substructure linker with --ell: 6D FOF over outliers, or the paper's speed-ratio and "
+                         "opening-angle criteria")
     ap.add_argument("--n-se", type=int, default=0, help="spatial neighbours (0 = the workload's 32)")
     ap.add_argument("--n-v", type=int, default=0, help="velocity neighbours (0 = the workload's 8)")
     ap.add_argument("--workload", choices=("box", "unbind"), default="box",
@@ -248,7 +252,9 @@ def main():
     if args.field_6d:
         prm = dataclasses.replace(prm, field_6d=True)
     if args.ell:
-        prm = dataclasses.replace(prm, use_ell=True)
+        prm = dataclasses.replace(prm, use_ell=True, linker=args.linker)
+    elif args.linker != "6d":
+        sys.exit("--linker paper needs --ell (its first criterion thresholds L)")
     if args.n_se:
         prm = dataclasses.replace(prm, n_se=args.n_se)
     if args.n_v:
@@ -335,6 +341,7 @@ def main():
                       "R_threshold": prm.R_threshold, "field_hosts": "6D FOF" if prm.field_6d else "3D FOF",
                       "outliers": f"L >= {prm.ell_th:g}, cleaned (beta_L {prm.beta_ell:g})" if prm.use_ell
                       else f"R >= {prm.R_threshold:g}",
+                      "linker": "speed ratio + opening angle" if prm.linker == "paper" else "6D FOF",
                       "parallelism": "1 GPU", "launch_knobs": knobs},
            "roofline": roofline, "kernels": kernels, "summary": summary,
            "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}

@@ -191,6 +191,19 @@ int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of,
              const double* ellv_host, int32_t n_hosts, double ellx_s, const float* R,
              float R_threshold, int32_t* label6, void* stream);
 
+/* The paper's own substructure linker (Sec. 2.2, Eq. linkingcriteria).
+ * Participants: hosted particles (0 <= host_of[i] < n_hosts) with
+ * L[i] >= L_threshold (L: [n], e.g. from vr_ell_fit).  With
+ * u = v - vbar(x) in FP64 (vbar: [3][n] local mean velocity, as
+ * vr_cell_moments gives it) and s = |u|, i and j link iff they share a
+ * host, d2 < (ellx_s in grid units)^2 (exact integer d2), s_i, s_j > 0,
+ * s_i <= Vr s_j and s_j <= Vr s_i, and u_i . u_j >= cos_theta_op (s_i s_j).
+ * label[i] = smallest participant index of the component, -1 otherwise.
+ * Vr >= 1, -1 <= cos_theta_op <= 1, 0 < ellx_s < box/2. */
+int vr_fof_sub(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, int32_t n_hosts,
+               const float* vbar, double ellx_s, const float* L, float L_threshold, double Vr,
+               double cos_theta_op, int32_t* label, void* stream);
+
 typedef struct {
     double G;          /* gravitational constant in the particle units       */
     double eps;        /* Plummer softening length                            */

@@ -49,7 +49,13 @@ def run(w, prm, timings=None):
         # skewgaus, ell); outliers are L >= ell_th
         ell = ref.ell_fit(R, hoff, hmem)["ell"]
         t = tick("ell", t)
-        label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ell, prm.ell_th)
+        if getattr(prm, "linker", "6d") == "paper":
+            # the paper's linker over L >= ell_th (Eq. linkingcriteria)
+            host_of = np.where((group_of >= 0) & (group_of < nh), group_of, -1).astype(np.int32)
+            label6 = ref.fof_sub(P, host_of, nh, cm["vbar"], prm.alpha_xs * prm.ellx, ell, prm.ell_th, prm.Vr,
+                                 theta_op=prm.theta_op)
+        else:
+            label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ell, prm.ell_th)
         t = tick("fof6d", t)
         nc, sub_of, sub_off, sub_mem = ref.groups(label6, prm.n_min)
         # significance cleaning of the candidates (Eq. ellsig)

@@ -713,7 +713,7 @@ extern "C" int vr_ref_fof_sub(const vr_ref_particles* p, const int32_t* host_of,
         if (!(si > 0 && sj > 0)) return;
         if (!(si <= Vr * sj && sj <= Vr * si)) return;
         const double dot = ui[0] * uj[0] + ui[1] * uj[1] + ui[2] * uj[2];
-        if (dot >= cos_op * si * sj) uf.unite(i, j);
+        if (dot >= cos_op * (si * sj)) uf.unite(i, j);
     });
     for (int64_t i = 0; i < n; ++i) label[i] = -1;
     for (int32_t i : part) label[i] = uf.find(i);

@@ -126,7 +126,7 @@ int vr_ref_fof6d(const vr_ref_particles* p, const int32_t* host_of, int32_t n_ho
  * they share a host, d2 < (ellx_s in grid units)^2 (exact integer d2), and
  * with u = v - vbar(x) (FP64, per particle: vbar is [3][n], the local mean
  * velocity of Eq. cellinterp) and speeds s = |u| (both > 0):
- * s_i <= Vr s_j, s_j <= Vr s_i and u_i . u_j >= cos_op s_i s_j.
+ * s_i <= Vr s_j, s_j <= Vr s_i and u_i . u_j >= cos_op (s_i s_j).
  * label = smallest participant index of the component, -1 otherwise. */
 int vr_ref_fof_sub(const vr_ref_particles* p, const int32_t* host_of, int32_t n_hosts,
                    const float* vbar, double ellx_s, const float* L, float L_threshold,

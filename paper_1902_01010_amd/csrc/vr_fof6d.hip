@@ -1,13 +1,16 @@
 // vr_fof6d.hip -- velocity linking length of a host and 6D friends-of-
 // friends over the outliers (Sec. 2.1, Eq. fof6d, with the substructure
-// linking length of Sec. 2.2).
+// linking length of Sec. 2.2), and the paper's own substructure linker
+// (Sec. 2.2, Eq. linkingcriteria).
 //
-// Participants (hosted particles with R at or above the threshold) are
-// compacted, put on their own integer-grid cell list with cells of side
-// 2^s >= ellx_s, and every candidate pair is tested with the FP64 predicate
-// d2 / ells2 + dv2 / ellv^2 < 1 evaluated in exactly that order, d2 being the
-// exact integer squared distance.  Components come from the same lock-free
-// union-find as the 3D search; labels are the smallest participant index.
+// Participants (hosted particles with R, or L, at or above the threshold)
+// are compacted, put on their own integer-grid cell list with cells of side
+// 2^s >= ellx_s, and every candidate pair is tested in FP64, d2 being the
+// exact integer squared distance: for Eq. fof6d d2 / ells2 + dv2 / ellv^2 < 1
+// in exactly that order; for Eq. linkingcriteria d2 < ells2, speeds about
+// the local mean velocity within a factor Vr and directions within the
+// opening angle.  Components come from the same lock-free union-find as the
+// 3D search; labels are the smallest participant index.
 #include "vr_grid.h"
 
 #include <cmath>
@@ -149,7 +152,31 @@ __global__ void k_sorted_attrs(int64_t np, const uint32_t* __restrict__ cidx, co
     shost[p] = host_of[i];
 }
 
-template <bool HALF>
+// Velocity relative to the local mean velocity and its norm, per sorted
+// position (the paper's linker).
+__global__ void k_sorted_u(int64_t np, int64_t n, const int32_t* __restrict__ sorig, const float* __restrict__ vx,
+                           const float* __restrict__ vy, const float* __restrict__ vz, const float* __restrict__ vbar,
+                           double* __restrict__ su0, double* __restrict__ su1, double* __restrict__ su2,
+                           double* __restrict__ ss) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int32_t i = sorig[p];
+    const double u0 = (double)vx[i] - (double)vbar[i];
+    const double u1 = (double)vy[i] - (double)vbar[n + i];
+    const double u2 = (double)vz[i] - (double)vbar[2 * n + i];
+    su0[p] = u0;
+    su1[p] = u1;
+    su2[p] = u2;
+    ss[p] = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+}
+
+struct SubLink {
+    const double *u0, *u1, *u2, *s;  // per sorted position
+    double Vr, cos_op;
+};
+
+// PAPER = false: Eq. fof6d; true: Eq. linkingcriteria (sub.* used, ellv not).
+template <bool HALF, bool PAPER>
 __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __restrict__ key,
                                                 const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                 const uint32_t* __restrict__ sz, const float* __restrict__ svx,
@@ -158,7 +185,7 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
                                                 const uint32_t* __restrict__ cell_start,
                                                 const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                                 uint32_t hmask, int b, int gb, double ell2, int* parent,
-                                                unsigned xchunk) {
+                                                unsigned xchunk, SubLink sub) {
     const int64_t p = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const uint32_t k = key[p];
@@ -167,8 +194,16 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
     const int px = (int)sx[p], py = (int)sy[p], pz = (int)sz[p];
     const double vpx = (double)svx[p], vpy = (double)svy[p], vpz = (double)svz[p];
     const int hp = shost[p];
-    const double ev = ellv[hp];
+    const double ev = PAPER ? 1.0 : ellv[hp];
     const double ev2 = ev * ev;
+    double up0 = 0, up1 = 0, up2 = 0, sp = 0;
+    if constexpr (PAPER) {
+        up0 = sub.u0[p];
+        up1 = sub.u1[p];
+        up2 = sub.u2[p];
+        sp = sub.s[p];
+        if (!(sp > 0)) return;  // no direction: links nothing
+    }
     // t = d2/ell2 + dv2/ev2 is formed with reciprocals first; that differs
     // from the divided form by a few ulps, so only t within 1e-9 of 1 needs
     // the divided form itself
@@ -200,6 +235,13 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
             const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
             // d2 >= ell2 makes the rounded d2/ell2 >= 1 and so t >= 1: no link
             if (d2 >= ell2 || shost[q] != hp) continue;
+            if constexpr (PAPER) {
+                const double sq = sub.s[q];
+                if (!(sq > 0) || !(sp <= sub.Vr * sq && sq <= sub.Vr * sp)) continue;
+                const double dot = up0 * sub.u0[q] + up1 * sub.u1[q] + up2 * sub.u2[q];
+                if (dot >= sub.cos_op * (sp * sq)) uf_union(parent, (int)p, (int)q);
+                continue;
+            }
             const double ax = vpx - (double)svx[q], ay = vpy - (double)svy[q], az = vpz - (double)svz[q];
             const double dv2 = ax * ax + ay * ay + az * az;
             const double ta = d2 * rl2 + dv2 * rv2;
@@ -283,9 +325,18 @@ extern "C" int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
     return VR_OK;
 }
 
-extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, const double* ellv_host,
-                        int32_t n_hosts, double ellx_s, const float* R, float R_threshold, int32_t* label6,
-                        void* stream) {
+namespace {
+
+// Both linkers: sub == nullptr gives Eq. fof6d with ellv_host, otherwise
+// Eq. linkingcriteria with sub->vbar, Vr, cos_op.
+struct SubArgs {
+    const float* vbar;
+    double Vr, cos_op;
+};
+
+int link_outliers(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, const double* ellv_host,
+                  int32_t n_hosts, double ellx_s, const float* R, float R_threshold, int32_t* label6,
+                  const SubArgs* sub, void* stream) {
     if (!ctx) return VR_ERR_INVALID_ARG;
     int rc = check_particles(ctx, p, true);
     if (rc) return rc;
@@ -296,10 +347,11 @@ extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_
     if (n_hosts < 0) return set_err(ctx, VR_ERR_INVALID_ARG, "n_hosts < 0");
     const int64_t n = p->n;
     if (n == 0) return VR_OK;
-    if (!host_of || !label6 || (n_hosts > 0 && !ellv_host)) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
+    if (!host_of || !label6 || (!sub && n_hosts > 0 && !ellv_host) || (sub && (!sub->vbar || !R)))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
     VR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    if (n_hosts > 0) {
+    if (!sub && n_hosts > 0) {
         std::vector<double> ev(n_hosts);
         VR_HIP(ctx, hipMemcpyAsync(ev.data(), ellv_host, n_hosts * sizeof(double), hipMemcpyDeviceToHost, st));
         VR_HIP(ctx, hipStreamSynchronize(st));
@@ -352,17 +404,31 @@ extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_iota_i, dim3(grid_for(np, 256)), dim3(256), 0, st, np, parent);
     VR_LAUNCH_CHECK(ctx);
+    SubLink sl{nullptr, nullptr, nullptr, nullptr, 1.0, 1.0};
+    if (sub) {
+        VR_WS(su0, ctx, double, WS_D4, np);
+        VR_WS(su1, ctx, double, WS_D5, np);
+        VR_WS(su2, ctx, double, WS_D6, np);
+        VR_WS(ss, ctx, double, WS_D7, np);
+        hipLaunchKernelGGL(k_sorted_u, dim3(grid_for(np, 256)), dim3(256), 0, st, np, n, sorig, p->vx, p->vy, p->vz,
+                           sub->vbar, su0, su1, su2, ss);
+        VR_LAUNCH_CHECK(ctx);
+        sl = SubLink{su0, su1, su2, ss, sub->Vr, sub->cos_op};
+    }
     const int b = gb - s;
-    if ((1 << b) >= 3)
-        VR_TIMED(ctx, "fof_link6d", st, np,
-                 hipLaunchKernelGGL(k_link6d<true>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx,
-                                    cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals,
-                                    cl.hmask, b, gb, ell2, parent, (unsigned)ctx->xcd_chunk));
-    else
-        VR_TIMED(ctx, "fof_link6d", st, np,
-                 hipLaunchKernelGGL(k_link6d<false>, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.key, cl.sx,
-                                    cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals,
-                                    cl.hmask, b, gb, ell2, parent, (unsigned)ctx->xcd_chunk));
+    const unsigned xc = (unsigned)ctx->xcd_chunk;
+    const dim3 g(grid_for(np, 256));
+#define VR_LINK6D(HALF, PAPER)                                                                                    \
+    VR_TIMED(ctx, sub ? "fof_link_sub" : "fof_link6d", st, np,                                                  \
+             hipLaunchKernelGGL((k_link6d<HALF, PAPER>), g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, svx, \
+                                svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, \
+                                parent, xc, sl))
+    if ((1 << b) >= 3) {
+        if (sub) VR_LINK6D(true, true); else VR_LINK6D(true, false);
+    } else {
+        if (sub) VR_LINK6D(false, true); else VR_LINK6D(false, false);
+    }
+#undef VR_LINK6D
     VR_LAUNCH_CHECK(ctx);
     rc = fill_i32(ctx, mn, 0x7FFFFFFF, np, st);
     if (rc) return rc;
@@ -371,4 +437,22 @@ extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_
     hipLaunchKernelGGL(k_label6, dim3(grid_for(np, 256)), dim3(256), 0, st, np, parent, sorig, mn, label6);
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
+}
+
+}  // namespace
+
+extern "C" int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, const double* ellv_host,
+                        int32_t n_hosts, double ellx_s, const float* R, float R_threshold, int32_t* label6,
+                        void* stream) {
+    return link_outliers(ctx, p, host_of, ellv_host, n_hosts, ellx_s, R, R_threshold, label6, nullptr, stream);
+}
+
+extern "C" int vr_fof_sub(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, int32_t n_hosts,
+                          const float* vbar, double ellx_s, const float* L, float L_threshold, double Vr,
+                          double cos_theta_op, int32_t* label, void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    if (!(Vr >= 1.0) || !(cos_theta_op >= -1.0 && cos_theta_op <= 1.0))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "need Vr >= 1 and -1 <= cos_theta_op <= 1");
+    const SubArgs sa{vbar, Vr, cos_theta_op};
+    return link_outliers(ctx, p, host_of, nullptr, n_hosts, ellx_s, L, L_threshold, label, &sa, stream);
 }

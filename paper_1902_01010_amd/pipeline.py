@@ -9,6 +9,7 @@ features -> network -> band selection -> exact R for the band only.
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 import torch
@@ -16,7 +17,8 @@ import torch
 from . import vr as _vr
 
 KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group",
-           "unbind_persistent", "rs_features", "mlp_forward", "ell_fit", "ell_clean")
+           "unbind_persistent", "rs_features", "mlp_forward", "ell_fit", "ell_clean",
+           "fof_link_sub")
 
 
 @dataclasses.dataclass
@@ -39,6 +41,12 @@ class Params:
     use_ell: bool = False
     ell_th: float = 2.5
     beta_ell: float = 1.0
+    # "6d": Eq. fof6d over the outliers; "paper": the paper's substructure
+    # linker (Sec. 2.2, Eq. linkingcriteria; needs use_ell): speed ratio Vr
+    # and opening angle theta_op about the local mean velocity
+    linker: str = "6d"
+    Vr: float = 2.0
+    theta_op: float = math.pi / 10
 
     @classmethod
     def from_workload(cls, w):
@@ -121,7 +129,11 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
         ef = ctx.ell_fit(R, host_offsets, members)
         out.update(ell=ef["ell"], ell_fit=ef["fit"], ell_status=ef["status"], ell_merge=ef["merge"])
         mark("ell")
-        label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th)
+        if prm.linker == "paper":
+            label6 = ctx.fof_sub(P, group_of, n_hosts, cm["vbar"], prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th,
+                                 prm.Vr, prm.theta_op)
+        else:
+            label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th)
         mark("fof6d")
         nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
         if nc > 0:

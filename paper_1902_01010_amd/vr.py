@@ -7,6 +7,7 @@ if libvr.so is missing, or no gfx950 device is visible, the calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import torch
@@ -23,7 +24,7 @@ ENTRY_POINTS = (
     "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
     "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune", "vr_autotune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
-    "vr_host_ellv", "vr_fof6d", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
+    "vr_host_ellv", "vr_fof6d", "vr_fof_sub", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
     "vr_rs_features", "vr_mlp_forward", "vr_mlp_grad", "vr_mlp_train_step", "vr_rs_select",
 )
 
@@ -104,6 +105,7 @@ def load_library():
         L.vr_local_vdensity.argtypes = [vp, P, i32, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp]
         L.vr_host_ellv.argtypes = [vp, P, i32, vp, vp, dbl, vp, vp]
         L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
+        L.vr_fof_sub.argtypes = [vp, P, vp, i32, vp, dbl, vp, flt, dbl, dbl, vp, vp]
         L.vr_unbind.argtypes = [vp, P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
         L.vr_ell_fit.argtypes = [vp, i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp, vp]
         L.vr_ell_clean.argtypes = [vp, i64, i32, vp, vp, vp, dbl, dbl, i32, vp, vp, vp]
@@ -300,6 +302,17 @@ class Context:
                                       int(ellv_host.shape[0]), float(ellx_s), _ptr(R), float(R_threshold),
                                       _ptr(label6), _stream()))
         return label6
+
+    def fof_sub(self, P: Particles, host_of, n_hosts, vbar, ellx_s, L, L_threshold=2.5, Vr=2.0,
+                theta_op=math.pi / 10, label=None):
+        """The paper's substructure linker (speed ratio and opening angle about
+        the local mean velocity vbar, over L >= L_threshold)."""
+        if label is None:
+            label = torch.empty(P.n, dtype=torch.int32, device=P.device)
+        self._check(self.lib.vr_fof_sub(self.h, C.byref(P.s), _ptr(host_of), int(n_hosts), _ptr(vbar),
+                                        float(ellx_s), _ptr(L), float(L_threshold), float(Vr),
+                                        math.cos(theta_op), _ptr(label), _stream()))
+        return label
 
     def unbind(self, P: Particles, offsets, members, G, eps, beta_E=0.95, frac_ref=0.1, n_min=20,
                n_ref_min=10, frame_type=1, max_iter=100, persistent=1, tile=0):

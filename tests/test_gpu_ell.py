@@ -177,3 +177,71 @@ def test_pipeline_with_ell_stagewise(ctx, vr, ref, name):
     assert got["n_candidates"] == nc2
     if name == "halo12k":
         assert nc2 >= 1  # planted subhalos survive the cleaning as candidates
+
+
+def _hosts(ref, Pr, w, host_min=256):
+    lab = ref.fof3d(Pr, w.params["ellx"])
+    ng, gof, off, mem = ref.groups(lab, 20)
+    nh = int((np.diff(off) >= host_min).sum())
+    hoff, hmem = off[:nh + 1].copy(), mem[:off[nh]].copy()
+    host_of = np.where((gof >= 0) & (gof < nh), gof, -1).astype(np.int32)
+    return nh, hoff, hmem, host_of
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fof_sub_parity(ctx, vr, ref, name):
+    """The paper's linker on the same L and local mean velocities: labels
+    bit-exact (every decision is the same FP64 expression on both sides)."""
+    import math
+    w = CASES[name]()
+    P, Pr = both(ctx, vr, ref, w)
+    nh, hoff, hmem, host_of = _hosts(ref, Pr, w)
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], 32, 8)["R"]
+    ell = ref.ell_fit(R, hoff, hmem)["ell"]
+    ellxs = 0.5 * w.params["ellx"]
+    for th, Vr, deg in ((2.5, 2.0, 18.0), (1.0, 3.0, 40.0), (0.0, 1.5, 10.0)):
+        exp = ref.fof_sub(Pr, host_of, nh, cm["vbar"], ellxs, ell, th, Vr, theta_op=math.radians(deg))
+        got = ctx.fof_sub(P, dev_tensor(host_of), nh, dev_tensor(cm["vbar"]), ellxs, dev_tensor(ell), th, Vr,
+                          math.radians(deg)).cpu().numpy()
+        np.testing.assert_array_equal(got, exp)
+        if th == 1.0:
+            _, cnt = np.unique(exp[exp >= 0], return_counts=True)
+            assert (cnt >= 2).any()  # real links, not only singletons
+
+
+def test_fof_sub_rejects_bad_arguments(ctx, vr, ref):
+    w = CASES["halo12k"]()
+    P, Pr = both(ctx, vr, ref, w)
+    host = torch.zeros(P.n, dtype=torch.int32, device="cuda")
+    vb = torch.zeros(3 * P.n, device="cuda")
+    L = torch.zeros(P.n, device="cuda")
+    for Vr, th in ((0.5, 0.3), (2.0, float("nan"))):
+        with pytest.raises(vr.VrError):
+            ctx.fof_sub(P, host, 1, vb, 0.5 * w.params["ellx"], L, 2.5, Vr, th)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pipeline_paper_linker_stagewise(ctx, vr, ref, name):
+    """L mode with the paper's linker: the oracle redoes the linking and the
+    cleaning from the GPU's own L and local mean velocities."""
+    from paper_1902_01010_amd import pipeline
+    w = CASES[name]()
+    prm = dataclasses.replace(pipeline.Params.from_workload(w), use_ell=True, linker="paper")
+    x, v, m = pipeline.device_inputs(w)
+    got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
+    P, Pr = both(ctx, vr, ref, w)
+    nh = got["n_hosts"]
+    gof = got["group_of"].cpu().numpy()
+    host_of = np.where((gof >= 0) & (gof < nh), gof, -1).astype(np.int32)
+    ell = got["ell"].cpu().numpy()
+    vbar = got["cells"]["vbar"].cpu().numpy()
+    lab = ref.fof_sub(Pr, host_of, nh, vbar, prm.alpha_xs * prm.ellx, ell, prm.ell_th, prm.Vr,
+                      theta_op=prm.theta_op)
+    nc, _, soff, smem = ref.groups(lab, prm.n_min)
+    labc, _ = ref.ell_clean(ell, soff, smem, lab, prm.ell_th, prm.beta_ell, prm.n_min)
+    np.testing.assert_array_equal(got["label6"].cpu().numpy(), labc)
+    nc2 = ref.groups(labc, prm.n_min)[0]
+    assert got["n_candidates"] == nc2
+    if name == "halo12k":
+        assert nc2 >= 1
