@@ -90,6 +90,39 @@ __device__ __forceinline__ void heap_replace_top(uint64_t (*heap)[64], int lane,
     heap[i][lane] = key;
 }
 
+// ln f_bg (Eq. fvbg): the Gaussian of mean vbar(x) and dispersion sigma(x)
+// of particle g at velocity vq, by a 3x3 Cholesky in FP64; NaN if sigma(x)
+// is not positive definite.
+__device__ __forceinline__ double log_fbg(const float* __restrict__ sigma, const float* __restrict__ vbar, int64_t n,
+                                          int g, double vqx, double vqy, double vqz) {
+    const double S00 = sigma[0 * n + g], S11 = sigma[1 * n + g], S22 = sigma[2 * n + g];
+    const double S10 = sigma[3 * n + g], S20 = sigma[4 * n + g], S21 = sigma[5 * n + g];
+    double lfb = NAN;
+    if (S00 > 0) {
+        const double L00 = sqrt(S00);
+        const double L10 = S10 / L00, L20 = S20 / L00;
+        const double r11 = S11 - L10 * L10;
+        if (r11 > 0) {
+            const double L11 = sqrt(r11);
+            const double L21 = (S21 - L20 * L10) / L11;
+            const double r22 = S22 - L20 * L20 - L21 * L21;
+            if (r22 > 0) {
+                const double L22 = sqrt(r22);
+                const double d0 = vqx - (double)vbar[0 * n + g];
+                const double d1 = vqy - (double)vbar[1 * n + g];
+                const double d2 = vqz - (double)vbar[2 * n + g];
+                const double y0 = d0 / L00;
+                const double y1 = (d1 - L10 * y0) / L11;
+                const double y2 = (d2 - L20 * y0 - L21 * y1) / L22;
+                const double quad = y0 * y0 + y1 * y1 + y2 * y2;
+                const double lndet = 2.0 * (log(L00) + log(L11) + log(L22));
+                lfb = -0.5 * quad - 1.5 * log(2.0 * M_PI) - 0.5 * lndet;
+            }
+        }
+    }
+    return lfb;
+}
+
 __device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { return a < b || (a == b && pa < pb); }
 
 // NSE: heap capacity (n_se <= NSE).  NVR > 0: exactly NVR velocity
@@ -446,31 +479,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     }
     const double lfl = h2 == 0.0 ? INFINITY : log(sw) - 1.5 * log(h2) - log(msum);
     const int g = F.gidx[e];
-    const double S00 = sigma[0 * n + g], S11 = sigma[1 * n + g], S22 = sigma[2 * n + g];
-    const double S10 = sigma[3 * n + g], S20 = sigma[4 * n + g], S21 = sigma[5 * n + g];
-    double lfb = NAN;
-    if (S00 > 0) {
-        const double L00 = sqrt(S00);
-        const double L10 = S10 / L00, L20 = S20 / L00;
-        const double r11 = S11 - L10 * L10;
-        if (r11 > 0) {
-            const double L11 = sqrt(r11);
-            const double L21 = (S21 - L20 * L10) / L11;
-            const double r22 = S22 - L20 * L20 - L21 * L21;
-            if (r22 > 0) {
-                const double L22 = sqrt(r22);
-                const double d0 = vqx - (double)vbar[0 * n + g];
-                const double d1 = vqy - (double)vbar[1 * n + g];
-                const double d2 = vqz - (double)vbar[2 * n + g];
-                const double y0 = d0 / L00;
-                const double y1 = (d1 - L10 * y0) / L11;
-                const double y2 = (d2 - L20 * y0 - L21 * y1) / L22;
-                const double quad = y0 * y0 + y1 * y1 + y2 * y2;
-                const double lndet = 2.0 * (log(L00) + log(L11) + log(L22));
-                lfb = -0.5 * quad - 1.5 * log(2.0 * M_PI) - 0.5 * lndet;
-            }
-        }
-    }
+    const double lfb = log_fbg(sigma, vbar, n, g, vqx, vqy, vqz);
     R[g] = (float)(lfl - lfb);
 }
 
@@ -483,6 +492,223 @@ int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree
                                 tree.F, tree.seg_node, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n,
                                 n_se, n_v,
                                 tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+
+// ---- large neighbour sets (n_se > 64, up to the paper's 256) --------------
+// One wavefront per query.  Candidates of a visited leaf are keyed by the
+// lanes (exact d2 << 22 | rank, minimum image), and those below the current
+// bound W are appended to an LDS buffer.  When the buffer holds n_se + 64
+// keys or more, a bitwise radix select over the wave finds the n_se-th
+// smallest key T; the keys up to T are kept and W = T.  The tree walk (one
+// shared stack, near child first) prunes nodes whose box is no nearer than
+// W allows.  The n_v velocity neighbours are then taken from the n_se by
+// repeated wave-wide minima of (FP64 dv2, rank).
+constexpr int BIG_CAP = 256;              // largest n_se
+constexpr int BIG_BUF = BIG_CAP + 128;    // n_se kept + up to 127 appended
+constexpr int BIG_J = BIG_BUF / 64;       // buffer slots per lane
+
+// The r-th smallest (0-based) of the valid keys k[j] of all lanes.
+__device__ __forceinline__ uint64_t wave_select(const uint64_t (&k)[BIG_J], const bool (&v)[BIG_J], int r) {
+    uint64_t lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int j = 0; j < BIG_J; ++j)
+        if (v[j]) {
+            lo = min(lo, k[j]);
+            hi = max(hi, k[j]);
+        }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (uint64_t)__shfl_xor((unsigned long long)lo, o, 64));
+        hi = max(hi, (uint64_t)__shfl_xor((unsigned long long)hi, o, 64));
+    }
+    if (lo == hi) return lo;
+    // bits above the highest differing one are those of every key
+    const int top = 63 - __clzll(lo ^ hi);
+    uint64_t prefix = top == 63 ? 0 : (lo >> (top + 1)) << (top + 1);
+    for (int bit = top; bit >= 0; --bit) {
+        const uint64_t above = bit == 63 ? 0 : (~0ull << (bit + 1));
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < BIG_J; ++j)
+            c += __popcll(__ballot(v[j] && (k[j] & above) == prefix && !((k[j] >> bit) & 1)));
+        if (r >= c) {
+            r -= c;
+            prefix |= uint64_t(1) << bit;
+        }
+    }
+    return prefix;
+}
+
+__global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpos, int64_t nq,
+                                                const KdNode* __restrict__ nodes, Elems F,
+                                                const float* __restrict__ Vx, const float* __restrict__ Vy,
+                                                const float* __restrict__ Vz, const float* __restrict__ Me,
+                                                const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
+                                                const float* __restrict__ vbar, const float* __restrict__ sigma,
+                                                int64_t n, int n_se, int n_v, int use_mass, double mass_value, int gb,
+                                                float* __restrict__ R, unsigned xchunk) {
+    __shared__ uint64_t buf[BIG_BUF];
+    __shared__ int stack[STACK];
+    __shared__ double sel_d[32];
+    __shared__ int sel_p[32];
+    const int lane = threadIdx.x;
+    const int64_t qi = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk);
+    if (qi >= nq) return;  // uniform
+    const int e = qpos ? (int)qpos[qi] : (int)qi;
+    const int h = elem_host[e];
+    const int base = host_off[h];
+    const int px = F.u[0][e], py = F.u[1][e], pz = F.u[2][e];
+    int nb = 0;            // keys in buf (uniform)
+    uint64_t W = ~0ull;    // keys below W are taken (uniform)
+
+    auto compact = [&]() __attribute__((always_inline)) {
+        uint64_t k[BIG_J];
+        bool v[BIG_J];
+#pragma unroll
+        for (int j = 0; j < BIG_J; ++j) {
+            v[j] = lane + 64 * j < nb;
+            k[j] = v[j] ? buf[lane + 64 * j] : 0;
+        }
+        const uint64_t T = wave_select(k, v, n_se - 1);
+        __builtin_amdgcn_wave_barrier();
+        int at = 0;
+#pragma unroll
+        for (int j = 0; j < BIG_J; ++j) {
+            const bool keep = v[j] && k[j] <= T;
+            const uint64_t m = __ballot(keep);
+            if (keep) buf[at + __popcll(m & lanemask_lt())] = k[j];
+            at += __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        nb = n_se;
+        W = T;
+    };
+    auto scan = [&](int node) __attribute__((always_inline)) {
+        const KdNode& nd = nodes[node];
+        for (int c0 = nd.start; c0 < nd.end; c0 += 64) {
+            const int j = c0 + lane;
+            bool take = false;
+            uint64_t key = 0;
+            if (j < nd.end) {
+                const int64_t dx = min_image(F.u[0][j] - px, gb), dy = min_image(F.u[1][j] - py, gb),
+                              dz = min_image(F.u[2][j] - pz, gb);
+                const uint64_t d2 = (uint64_t)(dx * dx + dy * dy + dz * dz);
+                key = (d2 << POS_BITS) | (uint64_t)(uint32_t)(F.eid[j] - base);
+                take = key < W;
+            }
+            const uint64_t m = __ballot(take);
+            if (take) buf[nb + __popcll(m & lanemask_lt())] = key;
+            nb += __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            if (nb >= n_se + 64) compact();
+        }
+    };
+    if (lane == 0) stack[0] = h;
+    int sp = 1;
+    __builtin_amdgcn_wave_barrier();
+    while (sp > 0) {
+        const int node = stack[--sp];
+        __builtin_amdgcn_wave_barrier();
+        const KdNode& nd = nodes[node];
+        const int64_t bx = max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
+        const int64_t by = max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
+        const int64_t bz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
+        int64_t md2 = bx * bx + by * by + bz * bz;
+        if (md2 > (int64_t(1) << 41)) md2 = int64_t(1) << 41;
+        if (nb >= n_se && ((uint64_t)md2 << POS_BITS) >= W) continue;
+        if (nd.dim < 0) {
+            scan(node);
+            continue;
+        }
+        if (sp + 2 > STACK) break;  // cannot happen for trees of depth < 64
+        const int dm = nd.dim;
+        const int cf = px + (dm >= 1) * (py - px) + (dm == 2) * (pz - py);
+        const int nearc = cf < nd.t ? nd.left : nd.right;
+        const int farc = cf < nd.t ? nd.right : nd.left;
+        if (lane == 0) {
+            stack[sp] = farc;
+            stack[sp + 1] = nearc;
+        }
+        sp += 2;
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (nb > n_se) compact();
+    // the n_se spatial neighbours: velocity distances and the mass of the set
+    const int qe = F.eid[e];
+    const double vqx = (double)Vx[qe], vqy = (double)Vy[qe], vqz = (double)Vz[qe];
+    double dv[BIG_CAP / 64];
+    int ps[BIG_CAP / 64];
+    double msum = 0.0;
+#pragma unroll
+    for (int j = 0; j < BIG_CAP / 64; ++j) {
+        const int a = lane + 64 * j;
+        dv[j] = INFINITY;
+        ps[j] = 0x7FFFFFFF;
+        if (a < n_se) {
+            const int pos = (int)(buf[a] & POS_MASK);
+            const int gp = base + pos;
+            msum += use_mass ? (double)Me[gp] : mass_value;
+            const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
+            dv[j] = ax * ax + ay * ay + az * az;
+            ps[j] = pos;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) msum += __shfl_xor(msum, o, 64);
+    // the n_v nearest in velocity, smallest first, by (dv2, rank)
+    for (int i = 0; i < n_v; ++i) {
+        double bd = INFINITY;
+        int bp = 0x7FFFFFFF;
+#pragma unroll
+        for (int j = 0; j < BIG_CAP / 64; ++j)
+            if (vless(dv[j], ps[j], bd, bp)) {
+                bd = dv[j];
+                bp = ps[j];
+            }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double od = __shfl_xor(bd, o, 64);
+            const int op = __shfl_xor(bp, o, 64);
+            if (vless(od, op, bd, bp)) {
+                bd = od;
+                bp = op;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BIG_CAP / 64; ++j)
+            if (ps[j] == bp) {
+                dv[j] = INFINITY;
+                ps[j] = 0x7FFFFFFF;
+            }
+        if (lane == 0) {
+            sel_d[i] = bd;
+            sel_p[i] = bp;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane != 0) return;
+    const double kW = 15.0 / (8.0 * M_PI);
+    const double h2 = sel_d[n_v - 1];
+    double sw = 0.0;
+    if (h2 != 0.0)
+        for (int a = 0; a < n_v; ++a) {
+            const double m = use_mass ? (double)Me[base + sel_p[a]] : mass_value;
+            sw += m * kW * (1.0 - sel_d[a] / h2);
+        }
+    const double lfl = h2 == 0.0 ? INFINITY : log(sw) - 1.5 * log(h2) - log(msum);
+    const int g = F.gidx[e];
+    R[g] = (float)(lfl - log_fbg(sigma, vbar, n, g, vqx, vqy, vqz));
+}
+
+int launch_knn_big(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx,
+                   const float* Vy, const float* Vz, const float* Me, const int32_t* host_off,
+                   const vr_particles* p, const float* vbar, const float* sigma, int n_se, int n_v, float* R,
+                   hipStream_t st) {
+    if (nq > INT32_MAX) return set_err(ctx, VR_ERR_UNSUPPORTED, "too many queries for one launch");
+    VR_TIMED(ctx, "knn", st, nq,
+             hipLaunchKernelGGL(k_knn_big, dim3((unsigned)std::max<int64_t>(nq, 1)), dim3(64), 0, st, qpos, nq,
+                                tree.nodes, tree.F, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n, n_se,
+                                n_v, tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
@@ -558,9 +784,6 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         return launch_knn<32, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
     if (n_se <= 64)
         return launch_knn<64, 0, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
-    if (n_se <= 128)
-        return launch_knn<128, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R,
-                                      st);
-    // the paper's defaults (n_se 256, n_v 32): 157 KB of LDS, one workgroup per CU
-    return launch_knn<256, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    // larger sets, up to the paper's defaults (n_se 256, n_v 32): a wavefront per query
+    return launch_knn_big(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
 }
