@@ -88,6 +88,7 @@ def lib():
         L.vr_ref_host_ellv.argtypes = [P, i32, vp, vp, dbl, vp]
         L.vr_ref_fof6d.argtypes = [P, vp, i32, vp, dbl, vp, flt, vp]
         L.vr_ref_fof_sub.argtypes = [P, vp, i32, vp, dbl, vp, flt, dbl, dbl, vp]
+        L.vr_ref_sub_grow.argtypes = [P, vp, i32, vp, vp, flt, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i32, vp, vp, vp]
         L.vr_ref_unbind.argtypes = [P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
         L.vr_ref_ell_fit.argtypes = [i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp]
         L.vr_ref_ell_cost.argtypes = [i32, vp, vp, dbl, vp]
@@ -256,6 +257,24 @@ def fof_sub(P: Particles, host_of, n_hosts, vbar, ellx_s, L, L_threshold=2.5, Vr
     _check(lib().vr_ref_fof_sub(C.byref(P.s), _p(hof), int(n_hosts), _p(vb), float(ellx_s), _p(Lr),
                                 float(L_threshold), float(Vr), c, _p(lab)), "fof_sub")
     return lab
+
+
+def sub_grow(P: Particles, host_of, n_hosts, vbar, L, label1, ellx_s, L_threshold=2.5, gamma_L=1.0, gamma_x=2.0,
+             Vr=2.0, gamma_V=1.0, theta_op=math.pi / 10, gamma_theta=1.0, f_merge=0.25, n_min=20):
+    """Second, relaxed stage of the paper's linker: candidate groups of
+    label1 grow into untagged outliers and join when strongly connected.
+    Returns (label, growth rounds)."""
+    hof = np.ascontiguousarray(host_of, dtype=np.int32)
+    vb = np.ascontiguousarray(vbar, dtype=np.float32)
+    Lr = np.ascontiguousarray(L, dtype=np.float32)
+    l1 = np.ascontiguousarray(label1, dtype=np.int32)
+    out = np.zeros(P.n, np.int32)
+    nr = np.zeros(1, np.int32)
+    c = math.cos(min(math.pi, gamma_theta * theta_op))
+    _check(lib().vr_ref_sub_grow(C.byref(P.s), _p(hof), int(n_hosts), _p(vb), _p(Lr), float(L_threshold),
+                                 float(gamma_L), float(ellx_s), float(gamma_x), float(Vr), float(gamma_V), c,
+                                 float(f_merge), int(n_min), _p(l1), _p(out), _p(nr)), "sub_grow")
+    return out, int(nr[0])
 
 
 def unbind(P: Particles, offsets, members, G, eps, beta_E=0.95, frac_ref=0.1, n_min=20,

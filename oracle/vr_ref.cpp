@@ -22,6 +22,7 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <map>
 #include <numeric>
 #include <thread>
 #include <unordered_map>
@@ -717,6 +718,101 @@ extern "C" int vr_ref_fof_sub(const vr_ref_particles* p, const int32_t* host_of,
     });
     for (int64_t i = 0; i < n; ++i) label[i] = -1;
     for (int32_t i : part) label[i] = uf.find(i);
+    return 0;
+}
+
+// Second stage of the paper's linker: the candidate groups grow through
+// relaxed links into untagged outliers, and groups that the relaxed links
+// connect strongly enough (f_merge of either group's first-stage size) join.
+extern "C" int vr_ref_sub_grow(const vr_ref_particles* p, const int32_t* host_of, int32_t n_hosts,
+                               const float* vbar, const float* L, float L_threshold, double gamma_L, double ellx_s,
+                               double gamma_x, double Vr, double gamma_V, double cos_op_relaxed, double f_merge,
+                               int32_t n_min, const int32_t* label1, int32_t* label_out, int32_t* rounds) {
+    if (!valid_particles(p) || !has_vel(p) || (p->n > 0 && (!host_of || !vbar || !L || !label1 || !label_out)))
+        return -1;
+    if (!(gamma_L >= 1.0) || !(gamma_x >= 1.0) || !(gamma_V >= 1.0) || !(Vr >= 1.0) || n_min < 1 ||
+        !(cos_op_relaxed >= -1.0 && cos_op_relaxed <= 1.0) || !(f_merge >= 0) || n_hosts < 0)
+        return -1;
+    const double ell2 = vr_ref_ell2_grid(gamma_x * ellx_s, p->box, p->grid_bits);
+    if (!(ell2 > 0) || !(std::sqrt(ell2) < std::ldexp(1.0, p->grid_bits - 1))) return -1;
+    const int64_t n = p->n;
+    const double Vr2 = gamma_V * Vr;
+    const float Lth2 = (float)((double)L_threshold / gamma_L);
+    // first-stage groups of >= n_min members are the tagged candidates
+    std::vector<int64_t> size(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+        if (label1[i] >= 0) {
+            if (label1[i] >= n) return -1;
+            ++size[label1[i]];
+        }
+    std::vector<int32_t> tag(n, -1);
+    for (int64_t i = 0; i < n; ++i)
+        if (label1[i] >= 0 && size[label1[i]] >= n_min) tag[i] = label1[i];
+    std::vector<int32_t> part;
+    for (int64_t i = 0; i < n; ++i)
+        if (host_of[i] >= 0 && host_of[i] < n_hosts && L[i] >= Lth2) part.push_back((int32_t)i);
+        else if (tag[i] >= 0) return -1;  // a candidate member must be a relaxed participant
+    auto rel = [&](int64_t i, double* u) {
+        u[0] = (double)p->vx[i] - (double)vbar[i];
+        u[1] = (double)p->vy[i] - (double)vbar[n + i];
+        u[2] = (double)p->vz[i] - (double)vbar[2 * n + i];
+        return std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    };
+    // relaxed links as adjacency lists
+    std::unordered_map<int32_t, std::vector<int32_t>> adj;
+    std::vector<std::pair<int32_t, int32_t>> edges;
+    for_grid_pairs(p, part, std::sqrt(ell2), [&](int32_t i, int32_t j) {
+        if (host_of[i] != host_of[j]) return;
+        if (!((double)dist2_grid(p, i, j) < ell2)) return;
+        double ui[3], uj[3];
+        const double si = rel(i, ui), sj = rel(j, uj);
+        if (!(si > 0 && sj > 0)) return;
+        if (!(si <= Vr2 * sj && sj <= Vr2 * si)) return;
+        const double dot = ui[0] * uj[0] + ui[1] * uj[1] + ui[2] * uj[2];
+        if (dot >= cos_op_relaxed * (si * sj)) {
+            adj[i].push_back(j);
+            adj[j].push_back(i);
+            edges.push_back({i, j});
+        }
+    });
+    // growth in synchronous rounds
+    int32_t nr = 0;
+    for (;;) {
+        std::vector<std::pair<int32_t, int32_t>> upd;
+        for (int32_t u : part) {
+            if (tag[u] >= 0) continue;
+            auto it = adj.find(u);
+            if (it == adj.end()) continue;
+            int32_t m = -1;
+            for (int32_t t : it->second)
+                if (tag[t] >= 0 && (m < 0 || tag[t] < m)) m = tag[t];
+            if (m >= 0) upd.push_back({u, m});
+        }
+        if (upd.empty()) break;
+        for (auto& um : upd) tag[um.first] = um.second;
+        ++nr;
+    }
+    if (rounds) *rounds = nr;
+    // relaxed links between different groups, per pair of groups
+    std::map<std::pair<int32_t, int32_t>, int64_t> conn;
+    for (auto& e : edges) {
+        const int32_t a = tag[e.first], b = tag[e.second];
+        if (a < 0 || b < 0 || a == b) continue;
+        ++conn[{std::min(a, b), std::max(a, b)}];
+    }
+    MinUnionFind uf(n);
+    for (auto& kv : conn) {
+        const int32_t a = kv.first.first, b = kv.first.second;
+        if ((double)kv.second > f_merge * (double)size[a] || (double)kv.second > f_merge * (double)size[b]) uf.unite(a, b);
+    }
+    // final label: the smallest index among the members of the joined groups
+    std::vector<int32_t> low(n, INT32_MAX);
+    for (int64_t i = 0; i < n; ++i)
+        if (tag[i] >= 0) {
+            const int32_t r = uf.find(tag[i]);
+            low[r] = std::min(low[r], (int32_t)i);
+        }
+    for (int64_t i = 0; i < n; ++i) label_out[i] = tag[i] >= 0 ? low[uf.find(tag[i])] : -1;
     return 0;
 }
 

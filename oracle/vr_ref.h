@@ -132,6 +132,26 @@ int vr_ref_fof_sub(const vr_ref_particles* p, const int32_t* host_of, int32_t n_
                    const float* vbar, double ellx_s, const float* L, float L_threshold,
                    double Vr, double cos_op, int32_t* label);
 
+/* Second, relaxed stage of the paper's linker (Sec. 2.2, the two-stage
+ * approach after Eq. linkingcriteria).  label1 holds the first-stage
+ * components (smallest index, -1); those of >= n_min members are the
+ * candidate groups, tagged.  Relaxed participants: hosted particles with
+ * L >= L_threshold / gamma_L; relaxed links: the criteria of vr_ref_fof_sub
+ * with linking length gamma_x * ellx_s, speed ratio gamma_V * Vr and
+ * opening angle of cosine cos_op_relaxed.  Growth, in synchronous rounds
+ * until nothing changes: every untagged relaxed participant with a relaxed
+ * link to a particle tagged in the previous round takes the smallest such
+ * tag.  Then, for every pair of groups, the relaxed links between their
+ * members are counted; two groups join when the count exceeds f_merge times
+ * the first-stage size of either (joins are transitive).  label_out =
+ * smallest member index of the final group, -1 for every other particle.
+ * grown (may be NULL) receives the number of growth rounds. */
+int vr_ref_sub_grow(const vr_ref_particles* p, const int32_t* host_of, int32_t n_hosts,
+                    const float* vbar, const float* L, float L_threshold, double gamma_L,
+                    double ellx_s, double gamma_x, double Vr, double gamma_V,
+                    double cos_op_relaxed, double f_merge, int32_t n_min,
+                    const int32_t* label1, int32_t* label_out, int32_t* rounds);
+
 typedef struct {
     double G, eps, beta_E, frac_ref;
     int32_t n_min, n_ref_min, frame_type, max_iter;

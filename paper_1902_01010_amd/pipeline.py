@@ -47,6 +47,16 @@ class Params:
     linker: str = "6d"
     Vr: float = 2.0
     theta_op: float = math.pi / 10
+    # the paper's second, relaxed stage (Sec. 2.2): candidates grow through
+    # links with L >= ell_th / gamma_L, linking length gamma_x alpha_xs ellx,
+    # speed ratio gamma_Vr Vr, angle gamma_theta theta_op; groups join when
+    # their relaxed links exceed f_merge of either's first-stage size
+    sub_grow: bool = True
+    gamma_L: float = 1.0
+    gamma_x: float = 2.0
+    gamma_Vr: float = 1.0
+    gamma_theta: float = 1.0
+    f_merge: float = 0.25
 
     @classmethod
     def from_workload(cls, w):

@@ -25,6 +25,13 @@ def test_pipeline_defaults_match_the_paper():
     assert prm.beta_E == g("beta_E")
     assert prm.n_min == g("N_min")
     assert np.isclose(prm.ellx, g("ellx_in_mean_spacing") * w.box / 16)
+    # the paper's substructure linker and its relaxed second stage
+    assert prm.ell_th == g("ell_threshold") and prm.beta_ell == g("beta_L")
+    assert prm.Vr == g("velocity_ratio")
+    assert np.isclose(np.degrees(prm.theta_op), g("opening_angle_deg"), rtol=1e-14)
+    assert (prm.gamma_L, prm.gamma_x, prm.gamma_Vr, prm.gamma_theta) == (g("gamma_L"), g("gamma_x"), g("gamma_Vr"),
+                                                                         g("gamma_theta"))
+    assert prm.f_merge == g("f_merge")
 
 
 def test_binding_defaults_match_the_paper():
