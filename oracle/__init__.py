@@ -88,6 +88,8 @@ def lib():
         L.vr_ref_host_ellv.argtypes = [P, i32, vp, vp, dbl, vp]
         L.vr_ref_fof6d.argtypes = [P, vp, i32, vp, dbl, vp, flt, vp]
         L.vr_ref_fof_sub.argtypes = [P, vp, i32, vp, dbl, vp, flt, dbl, dbl, vp]
+        L.vr_ref_fof3d_dm.argtypes = [P, dbl, vp, vp]
+        L.vr_ref_assign_baryons.argtypes = [P, i32, vp, vp, vp, vp, dbl, dbl, vp]
         L.vr_ref_sub_grow.argtypes = [P, vp, i32, vp, vp, flt, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i32, vp, vp, vp]
         L.vr_ref_unbind.argtypes = [P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
         L.vr_ref_ell_fit.argtypes = [i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp]
@@ -275,6 +277,27 @@ def sub_grow(P: Particles, host_of, n_hosts, vbar, L, label1, ellx_s, L_threshol
                                  float(gamma_L), float(ellx_s), float(gamma_x), float(Vr), float(gamma_V), c,
                                  float(f_merge), int(n_min), _p(l1), _p(out), _p(nr)), "sub_grow")
     return out, int(nr[0])
+
+
+def fof3d_dm(P: Particles, ellx, is_baryon):
+    """3D FOF of two species: baryons never link to each other (Sec. 2.1)."""
+    ib = np.ascontiguousarray(is_baryon, dtype=np.uint8)
+    lab = np.zeros(P.n, np.int32)
+    _check(lib().vr_ref_fof3d_dm(C.byref(P.s), float(ellx), _p(ib), _p(lab)), "fof3d_dm")
+    return lab
+
+
+def assign_baryons(P: Particles, host_offsets, host_members, is_baryon, sub, ellx, sigma_v, out_init=None):
+    """Baryons take the substructure label of the nearest dark-matter member
+    of their host in phase space (Sec. 2.4, Eq. baryondist)."""
+    off = np.ascontiguousarray(host_offsets, dtype=np.int32)
+    mem = np.ascontiguousarray(host_members, dtype=np.int32)
+    ib = np.ascontiguousarray(is_baryon, dtype=np.uint8)
+    sb = np.ascontiguousarray(sub, dtype=np.int32)
+    out = np.full(P.n, -7, np.int32) if out_init is None else np.array(out_init, np.int32)
+    _check(lib().vr_ref_assign_baryons(C.byref(P.s), off.shape[0] - 1, _p(off), _p(mem), _p(ib), _p(sb),
+                                       float(ellx), float(sigma_v), _p(out)), "assign_baryons")
+    return out
 
 
 def unbind(P: Particles, offsets, members, G, eps, beta_E=0.95, frac_ref=0.1, n_min=20,

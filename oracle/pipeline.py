@@ -54,6 +54,11 @@ def run(w, prm, timings=None):
             host_of = np.where((group_of >= 0) & (group_of < nh), group_of, -1).astype(np.int32)
             label6 = ref.fof_sub(P, host_of, nh, cm["vbar"], prm.alpha_xs * prm.ellx, ell, prm.ell_th, prm.Vr,
                                  theta_op=prm.theta_op)
+            if getattr(prm, "sub_grow", False):
+                # the relaxed second stage: growth and joins
+                label6, _ = ref.sub_grow(P, host_of, nh, cm["vbar"], ell, label6, prm.alpha_xs * prm.ellx,
+                                         prm.ell_th, prm.gamma_L, prm.gamma_x, prm.Vr, prm.gamma_Vr, prm.theta_op,
+                                         prm.gamma_theta, prm.f_merge, prm.n_min)
         else:
             label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ell, prm.ell_th)
         t = tick("fof6d", t)

@@ -817,6 +817,59 @@ extern "C" int vr_ref_sub_grow(const vr_ref_particles* p, const int32_t* host_of
 }
 
 // ---------------------------------------------------------------------------
+// Two species (Sec. 2.1, DM+Baryons mode): dark matter links to dark matter
+// and to baryons, baryons never link to each other.
+extern "C" int vr_ref_fof3d_dm(const vr_ref_particles* p, double ellx, const uint8_t* is_baryon, int32_t* label) {
+    if (!valid_particles(p) || (p->n > 0 && (!label || !is_baryon))) return -1;
+    const double ell2 = vr_ref_ell2_grid(ellx, p->box, p->grid_bits);
+    if (!(ell2 > 0) || !(std::sqrt(ell2) < std::ldexp(1.0, p->grid_bits - 1))) return -1;
+    std::vector<int32_t> all(p->n);
+    std::iota(all.begin(), all.end(), 0);
+    MinUnionFind uf(p->n);
+    for_grid_pairs(p, all, std::sqrt(ell2), [&](int32_t i, int32_t j) {
+        if (is_baryon[i] && is_baryon[j]) return;
+        if ((double)dist2_grid(p, i, j) < ell2) uf.unite(i, j);
+    });
+    for (int64_t i = 0; i < p->n; ++i) label[i] = uf.find((int32_t)i);
+    return 0;
+}
+
+// Baryons take the substructure of the nearest dark-matter member of their
+// host in phase space (Sec. 2.4, Eq. baryondist read with squared terms).
+extern "C" int vr_ref_assign_baryons(const vr_ref_particles* p, int32_t n_hosts, const int32_t* host_offsets,
+                                     const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub,
+                                     double ellx, double sigma_v, int32_t* out) {
+    if (!valid_particles(p) || !has_vel(p) || !members_ok(p->n, n_hosts, host_offsets, host_members)) return -1;
+    if (n_hosts > 0 && (!is_baryon || !sub || !out)) return -1;
+    const double ell2 = vr_ref_ell2_grid(ellx, p->box, p->grid_bits);
+    if (!(ell2 > 0) || !(sigma_v > 0)) return -1;
+    const double sv2 = sigma_v * sigma_v;
+    parallel_for(n_hosts, [&](int64_t h) {
+        std::vector<int32_t> dm;
+        for (int32_t k = host_offsets[h]; k < host_offsets[h + 1]; ++k)
+            if (!is_baryon[host_members[k]]) dm.push_back(host_members[k]);
+        for (int32_t k = host_offsets[h]; k < host_offsets[h + 1]; ++k) {
+            const int32_t i = host_members[k];
+            if (!is_baryon[i]) {
+                out[i] = sub[i];
+                continue;
+            }
+            double best = std::numeric_limits<double>::infinity();
+            int32_t bj = -1;
+            for (int32_t j : dm) {
+                const double D2 = (double)dist2_grid(p, i, j) / ell2 + dv2_of(p, i, j) / sv2;
+                if (D2 < best || (D2 == best && j < bj)) {
+                    best = D2;
+                    bj = j;
+                }
+            }
+            out[i] = bj >= 0 ? sub[bj] : -1;
+        }
+    });
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Unbinding (Sec. 2.2, Eq. binding): remove beta_E T + W >= 0, iterate until
 // no particle is removed; the group is dissolved below N_min members.
 extern "C" int vr_ref_unbind(const vr_ref_particles* p, int32_t n_groups, const int32_t* offsets,

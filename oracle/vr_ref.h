@@ -152,6 +152,22 @@ int vr_ref_sub_grow(const vr_ref_particles* p, const int32_t* host_of, int32_t n
                     double cos_op_relaxed, double f_merge, int32_t n_min,
                     const int32_t* label1, int32_t* label_out, int32_t* rounds);
 
+/* Two species (Sec. 2.1, DM+Baryons mode): 3D FOF in which a baryon
+ * (is_baryon[i] != 0) never initiates links -- pairs link iff d2 < ell2 and
+ * at least one of the two is dark matter.  label = smallest index of the
+ * component (a baryon with no dark matter within ellx stays alone). */
+int vr_ref_fof3d_dm(const vr_ref_particles* p, double ellx, const uint8_t* is_baryon, int32_t* label);
+
+/* Baryons to substructure (Sec. 2.4, Eq. baryondist with squared terms):
+ * within each host, every baryon takes the substructure label sub[j] of
+ * the host's dark-matter member j nearest in phase space,
+ * D2 = d2 / ell2 + dv2 / sigma_v^2 (exact integer d2, FP64 dv2 in x, y, z
+ * order; ties to the smaller index); a host without dark matter gives -1.
+ * Dark-matter members keep sub[j].  out[i] for host members only. */
+int vr_ref_assign_baryons(const vr_ref_particles* p, int32_t n_hosts, const int32_t* host_offsets,
+                          const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub,
+                          double ellx, double sigma_v, int32_t* out);
+
 typedef struct {
     double G, eps, beta_E, frac_ref;
     int32_t n_min, n_ref_min, frame_type, max_iter;
