@@ -41,6 +41,7 @@ KERNEL_MODEL = {
     "mlp_forward": ("mfma", 18048.0, "row: 9,024 multiply-adds of the 12-64-64-64-1 network"),
     "ell_fit": ("hbm", 12.0, "member: index 4 + R 4 in, L 4 out"),
     "fof_link_sub": ("hbm", 52.0, "participant: q 12, host 4, parent 4, u 24 + speed 8 (FP64)"),
+    "sub_grow": ("hbm", 52.0, "relaxed participant per round: q 12, host 4, tag 4 + 4, u 24 + speed 8 (FP64)"),
     "ell_clean": ("hbm", 12.0, "member: index 4 + L 4 in, label 4 out"),
 }
 

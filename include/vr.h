@@ -204,6 +204,60 @@ int vr_fof_sub(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, int32
                const float* vbar, double ellx_s, const float* L, float L_threshold, double Vr,
                double cos_theta_op, int32_t* label, void* stream);
 
+/* The paper's second, relaxed linking stage (Sec. 2.2, the two-stage
+ * approach that follows Eq. linkingcriteria).  label1 (device [n]) holds
+ * first-stage components (smallest index or -1, as vr_fof_sub gives them);
+ * those with >= n_min members are the tagged candidate groups.  Relaxed
+ * participants: hosted particles with L >= (float)(L_threshold / gamma_L);
+ * relaxed links: the criteria of vr_fof_sub with linking length
+ * gamma_x * ellx_s, speed ratio gamma_V * Vr and opening-angle cosine
+ * cos_op_relaxed.  Growth runs in synchronous rounds until nothing changes:
+ * each untagged relaxed participant with a relaxed link to a particle
+ * tagged in the previous round takes the smallest such tag.  Then two
+ * groups join (transitively) when the relaxed links between their members
+ * outnumber f_merge times the first-stage size of either.  label_out
+ * (device [n]) = smallest member index of the final group, -1 elsewhere;
+ * *rounds (HOST, may be NULL) = rounds that tagged someone.  Every member
+ * of a candidate group must be a relaxed participant (else
+ * VR_ERR_INVALID_ARG).  Syncs the stream once per round. */
+int vr_sub_grow(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, int32_t n_hosts,
+                const float* vbar, const float* L, float L_threshold, double gamma_L, double ellx_s,
+                double gamma_x, double Vr, double gamma_V, double cos_op_relaxed, double f_merge,
+                int32_t n_min, const int32_t* label1, int32_t* label_out, int32_t* rounds, void* stream);
+
+/* ---- two species: dark matter and baryons (DM+Baryons mode) -------------- */
+
+/* 3D FOF seeded by dark matter (Sec. 2.1): is_baryon (device [n], 0 = dark
+ * matter) marks baryons, which link to dark matter within ellx but never to
+ * each other.  label[i] = smallest index of i's component (a baryon with no
+ * dark matter within ellx stays alone).  With no baryons this is vr_fof3d. */
+int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, const uint8_t* is_baryon, int32_t* label,
+                void* stream);
+
+/* Baryons to substructure (Sec. 2.4, Eq. baryondist read with squared
+ * terms): within each host (offsets/members as vr_groups gives them; both
+ * species), a baryon takes sub[j] of the host's dark-matter member j that
+ * minimises D2 = d2 / ell2 + dv2 / sigma_v^2 (exact integer d2 in grid
+ * units, ell2 = (ellx in grid units)^2, FP64 dv2 in x, y, z order; ties to
+ * the smaller index), -1 when the host has no dark matter; dark-matter
+ * members copy sub[j].  out (device [n]) is written for host members only.
+ * sub: device [n]. */
+int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
+                      const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub, double ellx,
+                      double sigma_v, int32_t* out, void* stream);
+
+/* Canonical labels: out[i] = smallest j with label[j] == label[i] when that
+ * label (in [0, n)) holds >= min_size particles, else -1; label < 0 gives
+ * -1.  A label >= n is an error (VR_ERR_INVALID_ARG).  Syncs. */
+int vr_relabel_min(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t min_size, int32_t* out, void* stream);
+
+/* Members of each group (offsets/members, device CSR) without the particles
+ * flagged in drop (device [n], e.g. is_baryon): out_offsets (device
+ * [n_groups+1]) and out_members (device, capacity offsets[n_groups]), order
+ * kept.  Syncs once (the offsets are validated on the host). */
+int vr_select_members(vr_ctx* ctx, int64_t n, int32_t n_groups, const int32_t* offsets, const int32_t* members,
+                      const uint8_t* drop, int32_t* out_offsets, int32_t* out_members, void* stream);
+
 typedef struct {
     double G;          /* gravitational constant in the particle units       */
     double eps;        /* Plummer softening length                            */

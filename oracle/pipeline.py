@@ -7,7 +7,7 @@ import numpy as np
 import oracle as ref
 
 
-def run(w, prm, timings=None):
+def run(w, prm, timings=None, is_baryon=None):
     import time
 
     def tick(name, t0):
@@ -19,7 +19,7 @@ def run(w, prm, timings=None):
     q = ref.quantize(w.x, w.box, w.grid_bits)
     P = ref.Particles(q, w.v, w.mass, w.mass_value, w.box, w.grid_bits)
     t = tick("quantize", t)
-    label = ref.fof3d(P, prm.ellx)
+    label = ref.fof3d(P, prm.ellx) if is_baryon is None else ref.fof3d_dm(P, prm.ellx, is_baryon)
     t = tick("fof3d", t)
     ng, group_of, off, mem = ref.groups(label, prm.n_min)
     label3d = label
@@ -38,6 +38,12 @@ def run(w, prm, timings=None):
                n_hosts=nh)
     if nh == 0:
         return out
+    hoff_all, hmem_all = hoff, hmem
+    if is_baryon is not None:
+        # the substructure search runs on the hosts' dark matter
+        keep = is_baryon[hmem] == 0
+        hmem = hmem[keep]
+        hoff = np.r_[0, np.cumsum(np.add.reduceat(keep, hoff[:-1]))].astype(np.int32)
     cm = ref.cell_moments(P, hoff, hmem)
     t = tick("cells", t)
     R = ref.local_vdensity(P, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
@@ -69,6 +75,20 @@ def run(w, prm, timings=None):
     else:
         label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
         t = tick("fof6d", t)
+    if is_baryon is not None:
+        # baryons take the candidate of the nearest dark matter in phase space
+        lab = np.asarray(label6)
+        cnt = np.bincount(lab[lab >= 0], minlength=P.n)
+        sub = np.where((lab >= 0) & (cnt[np.maximum(lab, 0)] >= prm.n_min), lab, -1).astype(np.int32)
+        sv = prm.baryon_sigma_v if prm.baryon_sigma_v > 0 else float(np.median(ellv)) / prm.alpha_v
+        lab_all = ref.assign_baryons(P, hoff_all, hmem_all, is_baryon, sub, prm.ellx, sv,
+                                     out_init=np.full(P.n, -1, np.int32))
+        # canonical labels: the smallest member of each candidate
+        low = np.full(P.n, P.n, np.int64)
+        ok = lab_all >= 0
+        np.minimum.at(low, lab_all[ok], np.nonzero(ok)[0])
+        label6 = np.where(ok, low[np.maximum(lab_all, 0)], -1).astype(np.int32)
+        t = tick("baryons", t)
     nc, sub_of, sub_off, sub_mem = ref.groups(label6, prm.n_min)
     t = tick("subgroups", t)
     ub = ref.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc else None

@@ -13,7 +13,10 @@
 // 3D search; labels are the smallest participant index.
 #include "vr_grid.h"
 
+#include <algorithm>
 #include <cmath>
+#include <unordered_map>
+#include <vector>
 
 namespace vr {
 namespace {
@@ -252,6 +255,155 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
     }
 }
 
+
+// ---- second, relaxed stage of the paper's linker --------------------------
+// Sizes of the first-stage components (labels are particle indices).
+__global__ void k_label_sizes(int64_t n, const int32_t* __restrict__ label1, int* __restrict__ size) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && label1[i] >= 0) atomicAdd(&size[label1[i]], 1);
+}
+
+// A member of a candidate group must be a relaxed participant.
+__global__ void k_check_tagged(int64_t n, const int32_t* __restrict__ label1, const int* __restrict__ size,
+                               int n_min, const uint32_t* __restrict__ flag, int* __restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int l = label1[i];
+    if (l >= 0 && size[l] >= n_min && !flag[i]) atomicOr(bad, 1);
+}
+
+__global__ void k_first_tags(int64_t np, const int32_t* __restrict__ sorig, const int32_t* __restrict__ label1,
+                             const int* __restrict__ size, int n_min, int32_t* __restrict__ tag) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int l = label1[sorig[p]];
+    tag[p] = (l >= 0 && size[l] >= n_min) ? l : -1;
+}
+
+// The relaxed criteria of the paper's linker between sorted positions p, q
+// (same host and d2 < ell2 already known).
+__device__ __forceinline__ bool relaxed_link(const SubLink& sub, double up0, double up1, double up2, double sp, int q) {
+    const double sq = sub.s[q];
+    if (!(sp > 0) || !(sq > 0) || !(sp <= sub.Vr * sq && sq <= sub.Vr * sp)) return false;
+    const double dot = up0 * sub.u0[q] + up1 * sub.u1[q] + up2 * sub.u2[q];
+    return dot >= sub.cos_op * (sp * sq);
+}
+
+// Visits every participant q != p in the 27 cells around p's cell (each once)
+// that shares p's host, lies within ell2 and meets the relaxed criteria.
+template <class F>
+__device__ __forceinline__ void for_relaxed(int64_t p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ sx,
+                                            const uint32_t* __restrict__ sy, const uint32_t* __restrict__ sz,
+                                            const int32_t* __restrict__ shost, const uint32_t* __restrict__ cell_start,
+                                            const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                            uint32_t hmask, int b, int gb, double ell2, const SubLink& sub, F&& visit) {
+    const uint32_t k = key[p];
+    const int nc = 1 << b;
+    const int cx = k & (nc - 1), cy = (k >> b) & (nc - 1), cz = k >> (2 * b);
+    const int px = (int)sx[p], py = (int)sy[p], pz = (int)sz[p];
+    const int hp = shost[p];
+    const double up0 = sub.u0[p], up1 = sub.u1[p], up2 = sub.u2[p], sp = sub.s[p];
+    if (!(sp > 0)) return;
+    // with fewer than 3 cells a side the 27 offsets repeat cells (at most 8
+    // distinct ones): a bit per cell keeps each visit single
+    uint32_t seen = 0;
+    for (int o = 0; o < 27; ++o) {
+        const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+        const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
+        const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
+        const uint32_t nz = (uint32_t)((cz + dz + nc) & (nc - 1));
+        const uint32_t nk = (nz << (2 * b)) | (ny << b) | nx;
+        if (nc < 3) {
+            const uint32_t bit = 1u << (nx + 2 * ny + 4 * nz);
+            if (seen & bit) continue;
+            seen |= bit;
+        }
+        const int c = hash_find(hkeys, hvals, hmask, nk);
+        if (c < 0) continue;
+        for (uint32_t q = cell_start[c]; q < cell_start[c + 1]; ++q) {
+            if ((int64_t)q == p) continue;
+            const int ddx = min_image((int)sx[q] - px, gb);
+            const int ddy = min_image((int)sy[q] - py, gb);
+            const int ddz = min_image((int)sz[q] - pz, gb);
+            const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+            if (d2 >= ell2 || shost[q] != hp) continue;
+            if (relaxed_link(sub, up0, up1, up2, sp, (int)q)) visit((int)q);
+        }
+    }
+}
+
+// One synchronous growth round: an untagged participant takes the smallest
+// tag among its relaxed neighbours tagged in the previous round.
+__global__ __launch_bounds__(256) void k_grow(int64_t np, const uint32_t* __restrict__ key,
+                                              const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
+                                              const uint32_t* __restrict__ sz, const int32_t* __restrict__ shost,
+                                              const uint32_t* __restrict__ cell_start, const uint32_t* __restrict__ hkeys,
+                                              const uint32_t* __restrict__ hvals, uint32_t hmask, int b, int gb,
+                                              double ell2, SubLink sub, const int32_t* __restrict__ tin,
+                                              int32_t* __restrict__ tout, int* __restrict__ changed) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    if (tin[p] >= 0) {
+        tout[p] = tin[p];
+        return;
+    }
+    int m = -1;
+    for_relaxed(p, key, sx, sy, sz, shost, cell_start, hkeys, hvals, hmask, b, gb, ell2, sub, [&](int q) {
+        const int t = tin[q];
+        if (t >= 0 && (m < 0 || t < m)) m = t;
+    });
+    tout[p] = m;
+    if (m >= 0) atomicOr(changed, 1);
+}
+
+// Relaxed links between different groups (each unordered link once, from its
+// lower position): counted, or written as (lower tag, upper tag) keys with the
+// first-stage sizes of both groups.
+template <bool EMIT>
+__global__ __launch_bounds__(256) void k_cross(int64_t np, const uint32_t* __restrict__ key,
+                                               const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
+                                               const uint32_t* __restrict__ sz, const int32_t* __restrict__ shost,
+                                               const uint32_t* __restrict__ cell_start,
+                                               const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                               uint32_t hmask, int b, int gb, double ell2, SubLink sub,
+                                               const int32_t* __restrict__ tag, const int* __restrict__ size,
+                                               unsigned long long* __restrict__ count, int64_t cap,
+                                               uint64_t* __restrict__ pairs, int2* __restrict__ sizes) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int a = tag[p];
+    if (a < 0) return;
+    for_relaxed(p, key, sx, sy, sz, shost, cell_start, hkeys, hvals, hmask, b, gb, ell2, sub, [&](int q) {
+        const int c = tag[q];
+        if ((int64_t)q <= p || c < 0 || c == a) return;
+        const unsigned long long at = atomicAdd(count, 1ull);
+        if (EMIT && (int64_t)at < cap) {
+            const int lo = min(a, c), hi = max(a, c);
+            pairs[at] = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi;
+            sizes[at] = make_int2(size[lo], size[hi]);
+        }
+    });
+}
+
+__global__ void k_remap_tags(int64_t np, const int* __restrict__ remap, int32_t* __restrict__ tag,
+                             const int32_t* __restrict__ sorig, int* __restrict__ low) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int t = tag[p];
+    if (t < 0) return;
+    const int r = remap[t];
+    tag[p] = r;
+    atomicMin(&low[r], sorig[p]);
+}
+
+__global__ void k_grow_labels(int64_t np, const int32_t* __restrict__ tag, const int32_t* __restrict__ sorig,
+                              const int* __restrict__ low, int32_t* __restrict__ label) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int t = tag[p];
+    if (t >= 0) label[sorig[p]] = low[t];
+}
+
 __global__ void k_iota_i(int64_t n, int* p) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (int)i;
@@ -455,4 +607,175 @@ extern "C" int vr_fof_sub(vr_ctx* ctx, const vr_particles* p, const int32_t* hos
         return set_err(ctx, VR_ERR_INVALID_ARG, "need Vr >= 1 and -1 <= cos_theta_op <= 1");
     const SubArgs sa{vbar, Vr, cos_theta_op};
     return link_outliers(ctx, p, host_of, nullptr, n_hosts, ellx_s, L, L_threshold, label, &sa, stream);
+}
+
+namespace {
+__global__ void k_scatter_i(int k, const int* __restrict__ at, const int* __restrict__ val, int* __restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) dst[at[i]] = val[i];
+}
+}  // namespace
+
+extern "C" int vr_sub_grow(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, int32_t n_hosts,
+                           const float* vbar, const float* L, float L_threshold, double gamma_L, double ellx_s,
+                           double gamma_x, double Vr, double gamma_V, double cos_op_relaxed, double f_merge,
+                           int32_t n_min, const int32_t* label1, int32_t* label_out, int32_t* rounds, void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    int rc = check_particles(ctx, p, true);
+    if (rc) return rc;
+    if (!(gamma_L >= 1.0) || !(gamma_x >= 1.0) || !(gamma_V >= 1.0) || !(Vr >= 1.0) || n_min < 1 ||
+        !(cos_op_relaxed >= -1.0 && cos_op_relaxed <= 1.0) || !(f_merge >= 0) || n_hosts < 0)
+        return set_err(ctx, VR_ERR_INVALID_ARG, "need gammas >= 1, Vr >= 1, n_min >= 1, |cos| <= 1, f_merge >= 0");
+    const int gb = p->grid_bits;
+    const double u = gamma_x * ellx_s * ldexp(1.0, gb) / p->box;
+    if (!(u > 0) || !(u < ldexp(1.0, gb - 1)))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "the relaxed linking length must lie in (0, box/2)");
+    const int64_t n = p->n;
+    if (rounds) *rounds = 0;
+    if (n == 0) return VR_OK;
+    if (!host_of || !vbar || !L || !label1 || !label_out) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const double ell2 = u * u;
+    const float Lth2 = (float)((double)L_threshold / gamma_L);
+    VR_WS(flag, ctx, uint32_t, WS_C0, n);
+    VR_WS(pos, ctx, uint32_t, WS_C1, n);
+    VR_WS(bad, ctx, int, WS_FLAG2, 4);
+    VR_WS(tot, ctx, uint32_t, WS_C9, 4);
+    VR_WS(size, ctx, int, WS_B0, n);
+    if ((rc = fill_i32(ctx, bad, 0, 2, st)) || (rc = fill_i32(ctx, size, 0, n, st))) return rc;
+    hipLaunchKernelGGL(k_participants, dim3(grid_for(n, 256)), dim3(256), 0, st, n, host_of, L, Lth2, n_hosts, flag,
+                       bad);
+    hipLaunchKernelGGL(k_label_sizes, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label1, size);
+    hipLaunchKernelGGL(k_check_tagged, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label1, size, n_min, flag, bad);
+    VR_LAUNCH_CHECK(ctx);
+    rc = scan_u32(ctx, flag, pos, n, tot, st);
+    if (rc) return rc;
+    int32_t* pin = reinterpret_cast<int32_t*>(ctx->pinned);
+    VR_HIP(ctx, hipMemcpyAsync(pin, tot, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipMemcpyAsync(pin + 1, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t np = (uint32_t)pin[0];
+    if (pin[1]) return set_err(ctx, VR_ERR_INVALID_ARG, "a member of a candidate group is not a relaxed participant");
+    if ((rc = fill_i32(ctx, label_out, -1, n, st))) return rc;
+    if (np == 0) return VR_OK;
+    VR_WS(cx, ctx, uint32_t, WS_C2, np);
+    VR_WS(cy, ctx, uint32_t, WS_C3, np);
+    VR_WS(cz, ctx, uint32_t, WS_C4, np);
+    VR_WS(orig, ctx, int32_t, WS_C5, np);
+    hipLaunchKernelGGL(k_compact_part, dim3(grid_for(n, 256)), dim3(256), 0, st, n, flag, pos, p->qx, p->qy, p->qz, cx,
+                       cy, cz, orig);
+    VR_LAUNCH_CHECK(ctx);
+    int sb = 0;
+    while ((double)(1 << sb) < u && sb < gb) ++sb;
+    CellList cl;
+    if ((rc = build_cell_list(ctx, np, cx, cy, cz, gb, sb, cl, st))) return rc;
+    VR_WS(sorig, ctx, int32_t, WS_C6, np);
+    VR_WS(svx, ctx, float, WS_C7, np);
+    VR_WS(svy, ctx, float, WS_C8, np);
+    VR_WS(svz, ctx, float, WS_D0, np);
+    VR_WS(shost, ctx, int32_t, WS_D1, np);
+    VR_WS(tagA, ctx, int32_t, WS_D2, np);
+    VR_WS(tagB, ctx, int32_t, WS_D3, np);
+    VR_WS(su0, ctx, double, WS_D4, np);
+    VR_WS(su1, ctx, double, WS_D5, np);
+    VR_WS(su2, ctx, double, WS_D6, np);
+    VR_WS(ss, ctx, double, WS_D7, np);
+    hipLaunchKernelGGL(k_sorted_attrs, dim3(grid_for(np, 256)), dim3(256), 0, st, np, cl.idx, orig, p->vx, p->vy,
+                       p->vz, host_of, sorig, svx, svy, svz, shost);
+    hipLaunchKernelGGL(k_sorted_u, dim3(grid_for(np, 256)), dim3(256), 0, st, np, n, sorig, p->vx, p->vy, p->vz, vbar,
+                       su0, su1, su2, ss);
+    hipLaunchKernelGGL(k_first_tags, dim3(grid_for(np, 256)), dim3(256), 0, st, np, sorig, label1, size, n_min, tagA);
+    VR_LAUNCH_CHECK(ctx);
+    const SubLink sl{su0, su1, su2, ss, gamma_V * Vr, cos_op_relaxed};
+    const int b = gb - sb;
+    const dim3 g(grid_for(np, 256));
+    // growth rounds until nothing changes
+    int nr = 0;
+    for (;;) {
+        if ((rc = fill_i32(ctx, bad, 0, 1, st))) return rc;
+        VR_TIMED(ctx, "sub_grow", st, np,
+                 hipLaunchKernelGGL(k_grow, g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, shost, cl.cell_start,
+                                    cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, sl, tagA, tagB, bad));
+        VR_LAUNCH_CHECK(ctx);
+        VR_HIP(ctx, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipStreamSynchronize(st));
+        std::swap(tagA, tagB);
+        if (!pin[0]) break;
+        ++nr;
+    }
+    if (rounds) *rounds = nr;
+    // relaxed links between different groups: count, then collect
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(tot);
+    if ((rc = fill_u32(ctx, tot, 0u, 2, st))) return rc;
+    hipLaunchKernelGGL(k_cross<false>, g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, shost, cl.cell_start,
+                       cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, sl, tagA, size, cnt, (int64_t)0, nullptr, nullptr);
+    VR_LAUNCH_CHECK(ctx);
+    unsigned long long ncross = 0;
+    if ((rc = read_back(ctx, cnt, &ncross, sizeof ncross, st))) return rc;
+    std::vector<uint64_t> hp(ncross);
+    std::vector<int2> hs(ncross);
+    if (ncross > 0) {
+        VR_WS(pairs, ctx, uint64_t, WS_B3, ncross);
+        VR_WS(psz, ctx, int2, WS_B4, ncross);
+        if ((rc = fill_u32(ctx, tot, 0u, 2, st))) return rc;
+        hipLaunchKernelGGL(k_cross<true>, g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, shost, cl.cell_start,
+                           cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, sl, tagA, size, cnt, (int64_t)ncross, pairs, psz);
+        VR_LAUNCH_CHECK(ctx);
+        VR_HIP(ctx, hipMemcpyAsync(hp.data(), pairs, ncross * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipMemcpyAsync(hs.data(), psz, ncross * sizeof(int2), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipStreamSynchronize(st));
+    }
+    // joins: the relaxed links of a pair of groups against f_merge times the
+    // first-stage size of either; union by smaller label, transitive
+    std::unordered_map<uint64_t, std::pair<int64_t, int2>> per;
+    for (unsigned long long i = 0; i < ncross; ++i) {
+        auto& e = per[hp[i]];
+        ++e.first;
+        e.second = hs[i];
+    }
+    std::unordered_map<int, int> parent;
+    auto find = [&](int x) {
+        for (;;) {
+            auto it = parent.find(x);
+            if (it == parent.end() || it->second == x) return x;
+            x = it->second;
+        }
+    };
+    for (auto& kv : per) {
+        const int a = (int)(kv.first >> 32), c = (int)(kv.first & 0xFFFFFFFFu);
+        const double k = (double)kv.second.first;
+        if (k > f_merge * (double)kv.second.second.x || k > f_merge * (double)kv.second.second.y) {
+            const int ra = find(a), rc2 = find(c);
+            if (ra != rc2) parent[std::max(ra, rc2)] = std::min(ra, rc2);
+        }
+    }
+    std::vector<int> at, val;
+    for (auto& kv : parent) {
+        const int r = find(kv.first);
+        if (r != kv.first) {
+            at.push_back(kv.first);
+            val.push_back(r);
+        }
+    }
+    VR_WS(remap, ctx, int, WS_B1, n);
+    VR_WS(low, ctx, int, WS_B2, n);
+    hipLaunchKernelGGL(k_iota_i, dim3(grid_for(n, 256)), dim3(256), 0, st, n, remap);
+    VR_LAUNCH_CHECK(ctx);
+    if (!at.empty()) {
+        const int k = (int)at.size();
+        VR_WS(dat, ctx, int, WS_B5, k);
+        VR_WS(dval, ctx, int, WS_B6, k);
+        VR_HIP(ctx, hipMemcpyAsync(dat, at.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+        VR_HIP(ctx, hipMemcpyAsync(dval, val.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_scatter_i, dim3(grid_for(k, 256)), dim3(256), 0, st, k, dat, dval, remap);
+        VR_LAUNCH_CHECK(ctx);
+    }
+    if ((rc = fill_i32(ctx, low, 0x7FFFFFFF, n, st))) return rc;
+    hipLaunchKernelGGL(k_remap_tags, g, dim3(256), 0, st, np, remap, tagA, sorig, low);
+    hipLaunchKernelGGL(k_grow_labels, g, dim3(256), 0, st, np, tagA, sorig, low, label_out);
+    VR_LAUNCH_CHECK(ctx);
+    // the host vectors above are copied asynchronously: wait before they go away
+    VR_HIP(ctx, hipStreamSynchronize(st));
+    return VR_OK;
 }

@@ -18,7 +18,7 @@ from . import vr as _vr
 
 KERNELS = ("radix_scatter", "fof_link3d", "kd_level", "knn", "fof_link6d", "unbind_potential", "unbind_group",
            "unbind_persistent", "rs_features", "mlp_forward", "ell_fit", "ell_clean",
-           "fof_link_sub")
+           "fof_link_sub", "sub_grow", "fof_attach", "assign_baryons")
 
 
 @dataclasses.dataclass
@@ -57,6 +57,11 @@ class Params:
     gamma_Vr: float = 1.0
     gamma_theta: float = 1.0
     f_merge: float = 0.25
+    # two species (DM+Baryons mode, Sec. 2.1 and 2.4): baryons never start
+    # 3D links, the substructure search runs on the dark matter, and baryons
+    # join the substructure of the nearest dark matter in phase space with
+    # this sigma_v (0: the median sigma_v of the hosts)
+    baryon_sigma_v: float = 0.0
 
     @classmethod
     def from_workload(cls, w):
@@ -86,10 +91,11 @@ def surrogate_R(ctx, P, host_offsets, members, cm, prm: Params, model):
 
 
 def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, stage_events=False, model=None,
-        until=None):
+        until=None, is_baryon=None):
     """One pass of the hot path over device-resident inputs (R from the
-    learned path when a surrogate model is given; until="R" stops after R).
-    Returns the outputs (device tensors) and counts."""
+    learned path when a surrogate model is given; until="R" stops after R;
+    is_baryon, a uint8 device flag per particle, selects the two-species
+    mode).  Returns the outputs (device tensors) and counts."""
     ev = []
 
     def mark(name):
@@ -102,7 +108,7 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     q = ctx.quantize(x, box, grid_bits)
     P = _vr.Particles(q, v, mass, mass_value, box, grid_bits)
     mark("quantize")
-    label = ctx.fof3d(P, prm.ellx)
+    label = ctx.fof3d(P, prm.ellx) if is_baryon is None else ctx.fof3d_dm(P, prm.ellx, is_baryon)
     mark("fof3d")
     ng, group_of, offsets, members = ctx.groups(label, prm.n_min)
     label3d = label
@@ -122,6 +128,12 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     if n_hosts == 0:
         out["R"] = torch.full((P.n,), float("nan"), device=x.device)
         return out, ev
+    all_members = members
+    if is_baryon is not None:
+        # the substructure search runs on the hosts' dark matter
+        host_offsets, members = ctx.select_members(P.n, host_offsets, members[:int(sizes[:n_hosts].sum())], is_baryon)
+        out.update(host_offsets_all=offsets[:n_hosts + 1], search_members=members,
+                   n_searched=int(host_offsets[-1].item()))
     cm = ctx.cell_moments(P, host_offsets, members, want_table=False)
     mark("cells")
     if model is None:
@@ -142,6 +154,11 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
         if prm.linker == "paper":
             label6 = ctx.fof_sub(P, group_of, n_hosts, cm["vbar"], prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th,
                                  prm.Vr, prm.theta_op)
+            if prm.sub_grow:
+                label6, out["grow_rounds"] = ctx.sub_grow(
+                    P, group_of, n_hosts, cm["vbar"], ef["ell"], label6, prm.alpha_xs * prm.ellx, prm.ell_th,
+                    prm.gamma_L, prm.gamma_x, prm.Vr, prm.gamma_Vr, prm.theta_op, prm.gamma_theta, prm.f_merge,
+                    prm.n_min)
         else:
             label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th)
         mark("fof6d")
@@ -152,6 +169,16 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     else:
         label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
         mark("fof6d")
+    if is_baryon is not None:
+        # baryons join the candidate of the nearest dark matter in phase space
+        sub = ctx.relabel_min(label6, prm.n_min)
+        sv = prm.baryon_sigma_v
+        if sv <= 0:
+            sv = float(np.median(ellv.cpu().numpy())) / prm.alpha_v
+        lab_all = ctx.assign_baryons(P, offsets[:n_hosts + 1], all_members, is_baryon, sub, prm.ellx, sv)
+        label6 = ctx.relabel_min(lab_all, 1)
+        out.update(baryon_sigma_v=sv, label6_dm=sub)
+        mark("baryons")
     nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
     mark("subgroups")
     ub = ctx.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc > 0 else None

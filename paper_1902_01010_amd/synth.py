@@ -227,10 +227,58 @@ def cosmo_box(seed=2, n_side=256, box=None, halo_frac=0.45, sub_frac=0.10, n_max
                   alpha_xs=0.5, eps=0.02 * spacing, G=G_GRAV, beta_E=0.95, n_min=20,
                   host_min=256)
     meta = dict(seed=seed, n_side=n_side, n_halos=nh, n_subhalos=ns, n_background=nb,
-                m_p=m_p, spacing=spacing, n_max=n_max)
+                m_p=m_p, spacing=spacing, n_max=n_max,
+                halos=dict(size=sizes, r200=r200, c=conc, sigma=sig_h, centre=centres, bulk=bulk))
     # which component drew each particle: 0 halo (NFW), 1 subhalo (Plummer), 2 background
     comp = np.concatenate([np.zeros(len(hid), np.int8), np.ones(len(sid), np.int8), np.full(nb, 2, np.int8)])
     return _finish("cosmo_box", rng, pos, vel, box, None, m_p, params, meta, extra=dict(component=comp))
+
+
+def two_species(seed=5, n_side=256, star_per_halo_dm=0.662, disc_frac=0.7, star_mass=0.1):
+    """Dark matter of cosmo_box(seed, n_side) plus star particles of mass
+    star_mass m_p in its halos: per halo round(star_per_halo_dm N) stars, a
+    fraction disc_frac in an exponential disc (radial scale 0.03 r200,
+    height 0.1 of that, random orientation, rotation 150 km/s plus 20 km/s
+    dispersion) and the rest a stellar halo on the halo's NFW profile with
+    dispersion 0.8 sigma_host; stars move with the halo's bulk velocity.
+    512^3 with the default ratio gives the 40M stars of that configuration.
+    meta["is_baryon"] flags the stars; masses are per particle."""
+    dm = cosmo_box(seed=seed, n_side=n_side)
+    rng = np.random.default_rng(seed + 1000)
+    H = dm.meta["halos"]
+    m_p = dm.meta["m_p"]
+    nst = np.rint(star_per_halo_dm * H["size"]).astype(np.int64)
+    nd = np.rint(disc_frac * nst).astype(np.int64)
+    nsh = nst - nd
+    # discs
+    hd = np.repeat(np.arange(len(nst)), nd)
+    h = 0.03 * H["r200"][hd]
+    R = rng.gamma(2.0, 1.0, len(hd)) * h
+    z = rng.laplace(0.0, 0.1, len(hd)) * h
+    phi = rng.uniform(0, 2 * np.pi, len(hd))
+    nrm = _unit_vectors(rng, len(nst))
+    e1 = np.cross(nrm.T, np.where(np.abs(nrm[2:3].T) < 0.9, [[0, 0, 1.0]], [[1.0, 0, 0]]))
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(nrm.T, e1)
+    a1, a2, an = e1[hd].T, e2[hd].T, nrm[:, hd]
+    cph, sph = np.cos(phi), np.sin(phi)
+    pos_d = H["centre"][:, hd] + a1 * (R * cph) + a2 * (R * sph) + an * z
+    vel_d = H["bulk"][:, hd] + 150.0 * (-a1 * sph + a2 * cph) + rng.normal(0, 20.0, (3, len(hd)))
+    # stellar halos
+    hh = np.repeat(np.arange(len(nst)), nsh)
+    r = nfw_radii(rng, len(hh), H["r200"][hh], H["c"][hh])
+    pos_s = H["centre"][:, hh] + _unit_vectors(rng, len(hh)) * r
+    vel_s = H["bulk"][:, hh] + rng.normal(size=(3, len(hh))) * (0.8 * H["sigma"][hh])
+    box = dm.box
+    pos = np.concatenate([dm.x.astype(np.float64), pos_d, pos_s], axis=1)
+    vel = np.concatenate([dm.v.astype(np.float64), vel_d, vel_s], axis=1)
+    n_dm, n_st = dm.n, len(hd) + len(hh)
+    mass = np.concatenate([np.full(n_dm, m_p), np.full(n_st, star_mass * m_p)])
+    isb = np.concatenate([np.zeros(n_dm, np.uint8), np.ones(n_st, np.uint8)])
+    params = dict(dm.params)
+    meta = dict(seed=seed, n_side=n_side, n_dm=n_dm, n_star=n_st, n_disc=len(hd), m_p=m_p,
+                spacing=dm.meta["spacing"])
+    return _finish("two_species", rng, pos, vel, box, mass, m_p, params, meta, extra=dict(is_baryon=isb))
 
 
 def unbind_groups(seed=3, n_groups=50_000, n_max=2_000_000, box=100.0, m=1e8,

@@ -24,7 +24,8 @@ ENTRY_POINTS = (
     "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
     "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune", "vr_autotune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
-    "vr_host_ellv", "vr_fof6d", "vr_fof_sub", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
+    "vr_host_ellv", "vr_fof6d", "vr_fof_sub", "vr_sub_grow", "vr_fof3d_dm", "vr_assign_baryons",
+    "vr_relabel_min", "vr_select_members", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
     "vr_rs_features", "vr_mlp_forward", "vr_mlp_grad", "vr_mlp_train_step", "vr_rs_select",
 )
 
@@ -106,6 +107,12 @@ def load_library():
         L.vr_host_ellv.argtypes = [vp, P, i32, vp, vp, dbl, vp, vp]
         L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
         L.vr_fof_sub.argtypes = [vp, P, vp, i32, vp, dbl, vp, flt, dbl, dbl, vp, vp]
+        L.vr_fof3d_dm.argtypes = [vp, P, dbl, vp, vp, vp]
+        L.vr_assign_baryons.argtypes = [vp, P, i32, vp, vp, vp, vp, dbl, dbl, vp, vp]
+        L.vr_relabel_min.argtypes = [vp, i64, vp, i32, vp, vp]
+        L.vr_select_members.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp]
+        L.vr_sub_grow.argtypes = [vp, P, vp, i32, vp, vp, flt, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i32, vp, vp,
+                                  C.POINTER(i32), vp]
         L.vr_unbind.argtypes = [vp, P, i32, vp, vp, C.POINTER(_UnbindParams), vp, vp, vp, vp]
         L.vr_ell_fit.argtypes = [vp, i64, i32, vp, vp, vp, C.POINTER(_EllParams), vp, vp, vp, vp, vp]
         L.vr_ell_clean.argtypes = [vp, i64, i32, vp, vp, vp, dbl, dbl, i32, vp, vp, vp]
@@ -313,6 +320,54 @@ class Context:
                                         float(ellx_s), _ptr(L), float(L_threshold), float(Vr),
                                         math.cos(theta_op), _ptr(label), _stream()))
         return label
+
+    def sub_grow(self, P: Particles, host_of, n_hosts, vbar, L, label1, ellx_s, L_threshold=2.5, gamma_L=1.0,
+                 gamma_x=2.0, Vr=2.0, gamma_V=1.0, theta_op=math.pi / 10, gamma_theta=1.0, f_merge=0.25, n_min=20,
+                 label=None):
+        """The paper's relaxed second stage: candidate groups of label1 grow and
+        join.  Returns (label, growth rounds)."""
+        if label is None:
+            label = torch.empty(P.n, dtype=torch.int32, device=P.device)
+        nr = C.c_int32(0)
+        self._check(self.lib.vr_sub_grow(self.h, C.byref(P.s), _ptr(host_of), int(n_hosts), _ptr(vbar), _ptr(L),
+                                         float(L_threshold), float(gamma_L), float(ellx_s), float(gamma_x),
+                                         float(Vr), float(gamma_V), math.cos(min(math.pi, gamma_theta * theta_op)),
+                                         float(f_merge), int(n_min), _ptr(label1), _ptr(label), C.byref(nr),
+                                         _stream()))
+        return label, nr.value
+
+    def fof3d_dm(self, P: Particles, ellx, is_baryon, label=None):
+        """3D FOF in which baryons (is_baryon != 0, uint8) never link to each other."""
+        if label is None:
+            label = torch.empty(P.n, dtype=torch.int32, device=P.device)
+        self._check(self.lib.vr_fof3d_dm(self.h, C.byref(P.s), float(ellx), _ptr(is_baryon), _ptr(label), _stream()))
+        return label
+
+    def assign_baryons(self, P: Particles, host_offsets, host_members, is_baryon, sub, ellx, sigma_v, out=None):
+        """Baryons of each host take the substructure label of the nearest dark
+        matter in phase space; dark matter copies its own."""
+        if out is None:
+            out = torch.full((P.n,), -1, dtype=torch.int32, device=P.device)
+        self._check(self.lib.vr_assign_baryons(self.h, C.byref(P.s), host_offsets.shape[0] - 1, _ptr(host_offsets),
+                                               _ptr(host_members), _ptr(is_baryon), _ptr(sub), float(ellx),
+                                               float(sigma_v), _ptr(out), _stream()))
+        return out
+
+    def relabel_min(self, label, min_size=1, out=None):
+        """Canonical smallest-index labels of components with >= min_size members."""
+        if out is None:
+            out = torch.empty_like(label)
+        self._check(self.lib.vr_relabel_min(self.h, label.shape[0], _ptr(label), int(min_size), _ptr(out), _stream()))
+        return out
+
+    def select_members(self, n, offsets, members, drop):
+        """The groups' members without those flagged in drop: (offsets, members)."""
+        ng = offsets.shape[0] - 1
+        out_off = torch.zeros(ng + 1, dtype=torch.int32, device=offsets.device)
+        out_mem = torch.empty(max(1, members.shape[0]), dtype=torch.int32, device=offsets.device)
+        self._check(self.lib.vr_select_members(self.h, int(n), ng, _ptr(offsets), _ptr(members), _ptr(drop),
+                                               _ptr(out_off), _ptr(out_mem), _stream()))
+        return out_off, out_mem
 
     def unbind(self, P: Particles, offsets, members, G, eps, beta_E=0.95, frac_ref=0.1, n_min=20,
                n_ref_min=10, frame_type=1, max_iter=100, persistent=1, tile=0):

@@ -238,6 +238,9 @@ def test_pipeline_paper_linker_stagewise(ctx, vr, ref, name):
     vbar = got["cells"]["vbar"].cpu().numpy()
     lab = ref.fof_sub(Pr, host_of, nh, vbar, prm.alpha_xs * prm.ellx, ell, prm.ell_th, prm.Vr,
                       theta_op=prm.theta_op)
+    lab, nr = ref.sub_grow(Pr, host_of, nh, vbar, ell, lab, prm.alpha_xs * prm.ellx, prm.ell_th, prm.gamma_L,
+                           prm.gamma_x, prm.Vr, prm.gamma_Vr, prm.theta_op, prm.gamma_theta, prm.f_merge, prm.n_min)
+    assert got["grow_rounds"] == nr
     nc, _, soff, smem = ref.groups(lab, prm.n_min)
     labc, _ = ref.ell_clean(ell, soff, smem, lab, prm.ell_th, prm.beta_ell, prm.n_min)
     np.testing.assert_array_equal(got["label6"].cpu().numpy(), labc)
@@ -245,3 +248,63 @@ def test_pipeline_paper_linker_stagewise(ctx, vr, ref, name):
     assert got["n_candidates"] == nc2
     if name == "halo12k":
         assert nc2 >= 1
+
+
+def clumps(seed, n=3000):
+    """Pairs of clumps moving alike, close enough for relaxed links."""
+    rng = np.random.default_rng(seed)
+    c3 = rng.uniform(0.3, 0.7, (8, 3))
+    centres = np.concatenate([c3, c3 + [0.011, 0.0, 0.0]])
+    which = rng.integers(0, 16, n)
+    x = centres[which] + rng.normal(0, 0.003, (n, 3))
+    q = np.floor(x.T * 2 ** 21).astype(np.uint32)
+    vdir = np.tile(rng.normal(0, 1, (8, 3)), (2, 1))
+    v = (vdir[which] * 100 + rng.normal(0, 15, (n, 3))).T.astype(np.float32)
+    vbar = rng.normal(0, 3, (3, n)).astype(np.float32)
+    L = rng.normal(3.0, 0.8, n).astype(np.float32)
+    host = np.where(rng.random(n) < 0.05, -1, rng.integers(0, 2, n)).astype(np.int32)
+    return q, v, vbar, L, host
+
+
+@pytest.mark.parametrize("f_merge,gL,gx,gth", [(0.25, 1.0, 2.0, 1.0), (0.0, 1.2, 2.0, 1.3), (100.0, 1.0, 1.5, 1.0)])
+def test_sub_grow_parity(ctx, vr, ref, f_merge, gL, gx, gth):
+    """Growth and joins on the same first-stage labels: labels and the
+    number of rounds exact."""
+    import math
+    q, v, vbar, L, host = clumps(31)
+    Pr = ref.Particles(q, v, None, 1.0, 1.0, 21)
+    P = vr.Particles(dev_tensor(q), dev_tensor(v), None, 1.0, 1.0, 21)
+    ellxs, th = 0.003, math.pi / 10
+    lab1 = ref.fof_sub(Pr, host, 2, vbar, ellxs, L, 2.5, 2.0, theta_op=th)
+    exp, nr = ref.sub_grow(Pr, host, 2, vbar, L, lab1, ellxs, 2.5, gL, gx, 2.0, 1.0, th, gth, f_merge, 20)
+    got, gnr = ctx.sub_grow(P, dev_tensor(host), 2, dev_tensor(vbar), dev_tensor(L), dev_tensor(lab1), ellxs, 2.5,
+                            gL, gx, 2.0, 1.0, th, gth, f_merge, 20)
+    np.testing.assert_array_equal(got.cpu().numpy(), exp)
+    assert gnr == nr and nr >= 1
+    assert (exp >= 0).sum() > (np.unique(lab1[lab1 >= 0], return_counts=True)[1] >= 20).sum()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sub_grow_parity_on_hosts(ctx, vr, ref, name):
+    import math
+    w = CASES[name]()
+    P, Pr = both(ctx, vr, ref, w)
+    nh, hoff, hmem, host_of = _hosts(ref, Pr, w)
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], 32, 8)["R"]
+    ell = ref.ell_fit(R, hoff, hmem)["ell"]
+    ellxs = 0.5 * w.params["ellx"]
+    lab1 = ref.fof_sub(Pr, host_of, nh, cm["vbar"], ellxs, ell, 2.5, 2.0)
+    exp, nr = ref.sub_grow(Pr, host_of, nh, cm["vbar"], ell, lab1, ellxs)
+    got, gnr = ctx.sub_grow(P, dev_tensor(host_of), nh, dev_tensor(cm["vbar"]), dev_tensor(ell), dev_tensor(lab1),
+                            ellxs)
+    np.testing.assert_array_equal(got.cpu().numpy(), exp)
+    assert gnr == nr
+
+
+def test_sub_grow_rejects_untagged_members(ctx, vr, ref):
+    q, v, vbar, L, host = clumps(32, 500)
+    P = vr.Particles(dev_tensor(q), dev_tensor(v), None, 1.0, 1.0, 21)
+    lab1 = np.zeros(500, np.int32)  # one group of everything, hosts or not
+    with pytest.raises(vr.VrError):
+        ctx.sub_grow(P, dev_tensor(host), 2, dev_tensor(vbar), dev_tensor(L), dev_tensor(lab1), 0.003)

@@ -1,0 +1,129 @@
+"""GPU parity of the two-species steps (DM+Baryons mode) against the oracle:
+3D FOF seeded by dark matter (baryons never link to each other) and the
+assignment of baryons to the substructure of the nearest dark matter in
+phase space.  Labels are integers: compared exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1902_01010_amd import synth
+from tests.gpu_common import both, dev_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vr():
+    from paper_1902_01010_amd import vr as _vr
+    return _vr
+
+
+@pytest.fixture(scope="module")
+def ctx(vr):
+    return vr.Context(0)
+
+
+@pytest.fixture(scope="module", params=[32, 48])
+def box(request, ctx, vr, ref):
+    w = synth.two_species(seed=6, n_side=request.param)
+    P, Pr = both(ctx, vr, ref, w)
+    isb = w.meta["is_baryon"].astype(np.uint8)
+    return dict(w=w, P=P, Pr=Pr, isb=isb)
+
+
+def test_fof3d_dm_parity(ctx, ref, box):
+    w, P, Pr, isb = box["w"], box["P"], box["Pr"], box["isb"]
+    exp = ref.fof3d_dm(Pr, w.params["ellx"], isb)
+    got = ctx.fof3d_dm(P, w.params["ellx"], dev_tensor(isb)).cpu().numpy()
+    np.testing.assert_array_equal(got, exp)
+    # stars join halos: most stars sit in groups with dark matter
+    ng, gof, off, mem = ref.groups(exp, 20)
+    assert (gof[isb == 1] >= 0).mean() > 0.5
+
+
+def test_fof3d_dm_without_baryons_is_fof3d(ctx, ref, box):
+    w, P, Pr = box["w"], box["P"], box["Pr"]
+    z = np.zeros(P.n, np.uint8)
+    got = ctx.fof3d_dm(P, w.params["ellx"], dev_tensor(z)).cpu().numpy()
+    np.testing.assert_array_equal(got, ctx.fof3d(P, w.params["ellx"]).cpu().numpy())
+
+
+def test_fof3d_dm_all_baryons(ctx, ref, box):
+    w, P = box["w"], box["P"]
+    got = ctx.fof3d_dm(P, w.params["ellx"], dev_tensor(np.ones(P.n, np.uint8))).cpu().numpy()
+    np.testing.assert_array_equal(got, np.arange(P.n))
+
+
+@pytest.mark.parametrize("sigma_v", [50.0, 300.0])
+def test_assign_baryons_parity(ctx, ref, box, sigma_v):
+    w, P, Pr, isb = box["w"], box["P"], box["Pr"], box["isb"]
+    lab = ref.fof3d_dm(Pr, w.params["ellx"], isb)
+    ng, gof, off, mem = ref.groups(lab, 20)
+    rng = np.random.default_rng(1)
+    sub = np.where(rng.random(P.n) < 0.3, -1, rng.integers(0, 1000, P.n)).astype(np.int32)
+    init = np.full(P.n, -9, np.int32)
+    exp = ref.assign_baryons(Pr, off, mem, isb, sub, w.params["ellx"], sigma_v, out_init=init)
+    got = ctx.assign_baryons(P, dev_tensor(off), dev_tensor(mem), dev_tensor(isb), dev_tensor(sub),
+                             w.params["ellx"], sigma_v, out=dev_tensor(init)).cpu().numpy()
+    np.testing.assert_array_equal(got, exp)
+    assert (exp[mem][isb[mem] == 1] >= 0).any()
+
+
+def test_assign_baryons_hosts_without_dark_matter(ctx, vr, ref):
+    c = 1 << 20
+    q = np.array([[c, c + 500, c + 9000, c + 9100, c + 9300], [c] * 5, [c] * 5], np.uint32)
+    v = np.zeros((3, 5), np.float32)
+    isb = np.array([1, 1, 0, 1, 0], np.uint8)
+    sub = np.array([-1, -1, 5, -1, 6], np.int32)
+    Pr = ref.Particles(q, v, None, 1.0, 1.0, 21)
+    P = vr.Particles(dev_tensor(q), dev_tensor(v), None, 1.0, 1.0, 21)
+    off = np.array([0, 2, 5], np.int32)  # host 0: two baryons only
+    mem = np.arange(5, dtype=np.int32)
+    exp = ref.assign_baryons(Pr, off, mem, isb, sub, 0.001, 100.0)
+    got = ctx.assign_baryons(P, dev_tensor(off), dev_tensor(mem), dev_tensor(isb), dev_tensor(sub), 0.001,
+                             100.0).cpu().numpy()
+    np.testing.assert_array_equal(got, exp)
+    assert list(got) == [-1, -1, 5, 5, 6]
+
+
+def test_pipeline_species_stagewise(ctx, vr, ref):
+    """The hot path in the two-species mode: 3D labels exact against the
+    oracle; the dark-matter search lists exact; then the substructure and the
+    baryon assignment recomputed by the oracle from the GPU's own R."""
+    from paper_1902_01010_amd import pipeline
+    w = synth.two_species(seed=6, n_side=48)
+    isb = w.meta["is_baryon"].astype(np.uint8)
+    prm = pipeline.Params.from_workload(w)
+    x, v, m = pipeline.device_inputs(w)
+    got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm, is_baryon=dev_tensor(isb))
+    P, Pr = both(ctx, vr, ref, w)
+    lab = ref.fof3d_dm(Pr, prm.ellx, isb)
+    np.testing.assert_array_equal(got["label"].cpu().numpy(), lab)
+    ng, gof, off, mem = ref.groups(lab, prm.n_min)
+    nh = got["n_hosts"]
+    assert nh > 0
+    hoff_all, hmem_all = off[:nh + 1], mem[:off[nh]]
+    keep = isb[hmem_all] == 0
+    hmem = hmem_all[keep]
+    hoff = np.r_[0, np.cumsum(np.add.reduceat(keep, hoff_all[:-1]))].astype(np.int32)
+    np.testing.assert_array_equal(got["host_offsets"].cpu().numpy(), hoff)
+    np.testing.assert_array_equal(got["search_members"].cpu().numpy()[:hoff[-1]], hmem)
+    R = got["R"].cpu().numpy()
+    assert np.isnan(R[isb == 1]).all()
+    host_of = np.where((gof >= 0) & (gof < nh), gof, -1).astype(np.int32)
+    ellv = ref.host_ellv(Pr, hoff, hmem, prm.alpha_v)
+    lab6 = ref.fof6d(Pr, host_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
+    cnt = np.bincount(lab6[lab6 >= 0], minlength=P.n)
+    sub = np.where((lab6 >= 0) & (cnt[np.maximum(lab6, 0)] >= prm.n_min), lab6, -1).astype(np.int32)
+    np.testing.assert_array_equal(got["label6_dm"].cpu().numpy(), sub)
+    sv = got["baryon_sigma_v"]
+    assert sv == pytest.approx(float(np.median(ellv)) / prm.alpha_v, rel=1e-12)
+    out = ref.assign_baryons(Pr, hoff_all, hmem_all, isb, sub, prm.ellx, sv, out_init=np.full(P.n, -1, np.int32))
+    low = np.full(P.n, P.n, np.int64)
+    ok = out >= 0
+    np.minimum.at(low, out[ok], np.nonzero(ok)[0])
+    exp = np.where(ok, low[np.maximum(out, 0)], -1)
+    np.testing.assert_array_equal(got["label6"].cpu().numpy(), exp)
+    # stars joined candidates, and unbinding ran over both species
+    assert (exp[isb == 1] >= 0).any() and got["n_candidates"] > 0
