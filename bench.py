@@ -41,6 +41,8 @@ KERNEL_MODEL = {
     "mlp_forward": ("mfma", 18048.0, "row: 9,024 multiply-adds of the 12-64-64-64-1 network"),
     "ell_fit": ("hbm", 12.0, "member: index 4 + R 4 in, L 4 out"),
     "fof_link_sub": ("hbm", 52.0, "participant: q 12, host 4, parent 4, u 24 + speed 8 (FP64)"),
+    "fof_attach": ("hbm", 16.0, "baryon: q 12 in, parent 4 (dark-matter neighbours read through the cell list)"),
+    "assign_baryons": ("hbm", 28.0, "baryon: q 12, v 12 in, label 4 out"),
     "sub_grow": ("hbm", 52.0, "relaxed participant per round: q 12, host 4, tag 4 + 4, u 24 + speed 8 (FP64)"),
     "ell_clean": ("hbm", 12.0, "member: index 4 + L 4 in, label 4 out"),
 }
@@ -228,6 +230,9 @@ def main():
     ap.add_argument("--linker", choices=("6d", "paper"), default="6d",
                     help="substructure linker with --ell: 6D FOF over outliers, or the paper's speed-ratio and "
                          "opening-angle criteria")
+    ap.add_argument("--species", action="store_true",
+                    help="two species: the box's dark matter plus stars (0.662 per halo particle, 0.1 m_p) in the "
+                         "DM+Baryons mode (not the headline path)")
     ap.add_argument("--n-se", type=int, default=0, help="spatial neighbours (0 = the workload's 32)")
     ap.add_argument("--n-v", type=int, default=0, help="velocity neighbours (0 = the workload's 8)")
     ap.add_argument("--workload", choices=("box", "unbind"), default="box",
@@ -247,7 +252,8 @@ def main():
     import torch
     from paper_1902_01010_amd import pipeline, surrogate, synth, vr
 
-    w = synth.cosmo_box(n_side=args.n_side)
+    print(f"[bench] generating the {args.n_side}^3 box", file=sys.stderr, flush=True)
+    w = synth.two_species(n_side=args.n_side) if args.species else synth.cosmo_box(n_side=args.n_side)
     prm = pipeline.Params.from_workload(w)
     import dataclasses
     if args.field_6d:
@@ -263,6 +269,7 @@ def main():
     ctx = vr.Context(0)
     knobs = ctx.autotune(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else {k: ctx.get_tune(k) for k in vr.TUNE_KNOBS}
     x, v, m = pipeline.device_inputs(w)
+    isb = torch.from_numpy(w.meta["is_baryon"].astype(np.uint8)).cuda() if args.species else None
     if args.calib_copy_mib:
         a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -277,7 +284,7 @@ def main():
 
     def timed(mdl):
         def step():
-            return pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm, model=mdl)[0]
+            return pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm, model=mdl, is_baryon=isb)[0]
 
         for _ in range(args.warmup):
             step()
@@ -337,7 +344,9 @@ def main():
            "dtype": "int32 grid + f64 tests/moments + f32 potential tiles", "data": "synthetic",
            "config": {"workload": f"synthetic cosmological box {args.n_side}^3 particles, "
                                   f"{w.box:g} Mpc/h periodic, 2^21 grid; NFW halos (dN/dlnN ~ N^-0.9) with "
-                                  f"Plummer subhalos + uniform background",
+                                  f"Plummer subhalos + uniform background"
+                                  + (f"; plus {w.meta['n_star']} stars (discs + stellar halos, DM+Baryons mode)"
+                                     if args.species else ""),
                       "n_particles": w.n, "box_mpc_h": w.box, "b": 0.2, "n_se": prm.n_se, "n_v": prm.n_v,
                       "R_threshold": prm.R_threshold, "field_hosts": "6D FOF" if prm.field_6d else "3D FOF",
                       "outliers": f"L >= {prm.ell_th:g}, cleaned (beta_L {prm.beta_ell:g})" if prm.use_ell
@@ -346,7 +355,7 @@ def main():
                       "parallelism": "1 GPU", "launch_knobs": knobs},
            "roofline": roofline, "kernels": kernels, "summary": summary,
            "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.species:
         print("[bench] timing the CPU oracle on a sub-box sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, prm, args.cpu_sample_side)
     print(json.dumps(rec), flush=True)

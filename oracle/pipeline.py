@@ -80,7 +80,8 @@ def run(w, prm, timings=None, is_baryon=None):
         lab = np.asarray(label6)
         cnt = np.bincount(lab[lab >= 0], minlength=P.n)
         sub = np.where((lab >= 0) & (cnt[np.maximum(lab, 0)] >= prm.n_min), lab, -1).astype(np.int32)
-        sv = prm.baryon_sigma_v if prm.baryon_sigma_v > 0 else float(np.median(ellv)) / prm.alpha_v
+        w_dm = np.diff(hoff).astype(np.float64)
+        sv = prm.baryon_sigma_v if prm.baryon_sigma_v > 0 else float(np.sum(w_dm * ellv) / np.sum(w_dm)) / prm.alpha_v
         lab_all = ref.assign_baryons(P, hoff_all, hmem_all, is_baryon, sub, prm.ellx, sv,
                                      out_init=np.full(P.n, -1, np.int32))
         # canonical labels: the smallest member of each candidate

@@ -13,11 +13,13 @@
 // nearest in phase space, D2 = d2 / ell2 + dv2 / sigma_v^2, on a cell list
 // of the hosts' dark matter, ring by ring of cells around its own; once the
 // nearest possible spatial term of the next ring exceeds the best D2 found,
-// nothing further can tie or beat it.  A baryon not settled within 8 rings
-// scans all the dark matter of its host.
+// nothing further can tie or beat it.  A first pass on cells 8 times finer
+// than ellx settles most baryons within two rings; the others search the
+// ellx grid for up to 8 rings, then all the dark matter of their host.
 #include "vr_grid.h"
 #include "vr_kd.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -78,21 +80,52 @@ __device__ __forceinline__ void cells27(int px, int py, int pz, int s, int b, co
     }
 }
 
+// The dark-matter component (its smallest index) of every cell-list
+// position, and per cell that component when all its members share it.
+__global__ void k_cell_roots(int64_t ncell, const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ idx,
+                             const int32_t* __restrict__ orig, const int32_t* __restrict__ labc,
+                             int32_t* __restrict__ proot, int32_t* __restrict__ uroot) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int u = -2;
+    for (uint32_t q = cstart[c]; q < cstart[c + 1]; ++q) {
+        const int r = orig[labc[idx[q]]];
+        proot[q] = r;
+        u = u == -2 ? r : (u == r ? u : -1);
+    }
+    uroot[c] = u < 0 ? -1 : u;
+}
+
+// A baryon joins every dark-matter component with a member closer than
+// ellx.  Components already joined (the last four) are not tested again,
+// so in a dense core one member found near settles whole cells at once.
 __global__ __launch_bounds__(256) void k_attach(int64_t n, const uint8_t* __restrict__ isb,
                                                 const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                                                 const uint32_t* __restrict__ qz, CellList cl,
-                                                const int32_t* __restrict__ orig, int s, int b, int gb, double ell2,
-                                                int* parent) {
+                                                const int32_t* __restrict__ proot, const int32_t* __restrict__ uroot,
+                                                int s, int b, int gb, double ell2, int* parent) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !isb[i]) return;
     const int px = (int)qx[i], py = (int)qy[i], pz = (int)qz[i];
+    int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
     cells27(px, py, pz, s, b, cl.hkeys, cl.hvals, cl.hmask, [&](int c) {
+        const int ur = uroot[c];
+        if (ur >= 0 && (ur == k0 || ur == k1 || ur == k2 || ur == k3)) return;
         for (uint32_t q = cl.cell_start[c]; q < cl.cell_start[c + 1]; ++q) {
+            const int r = proot[q];
+            if (r == k0 || r == k1 || r == k2 || r == k3) continue;
             const int ddx = min_image((int)cl.sx[q] - px, gb);
             const int ddy = min_image((int)cl.sy[q] - py, gb);
             const int ddz = min_image((int)cl.sz[q] - pz, gb);
             const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
-            if (d2 < ell2) uf_union(parent, (int)i, orig[cl.idx[q]]);
+            if (d2 < ell2) {
+                uf_union(parent, (int)i, r);
+                k3 = k2;
+                k2 = k1;
+                k1 = k0;
+                k0 = r;
+                if (ur >= 0) return;  // the cell holds this component only
+            }
         }
     });
 }
@@ -133,6 +166,80 @@ __global__ void k_dm_member_compact(int64_t M, const uint32_t* __restrict__ flag
     dmh[j] = owner[k];
 }
 
+
+// ---- a cell list with 64-bit cell keys (up to 2^21 cells a side) ----------
+constexpr uint64_t EMPTY64 = ~0ull;
+
+__device__ __forceinline__ uint64_t hash64(uint64_t k, uint64_t mask) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k & mask;
+}
+
+struct Grid64 {
+    const uint64_t* hkeys;
+    const uint32_t* hvals;
+    uint64_t hmask;
+    const uint32_t *cell_start, *idx, *sx, *sy, *sz;
+    __device__ __forceinline__ int find(uint64_t k) const {
+        uint64_t h = hash64(k, hmask);
+        for (;;) {
+            const uint64_t kk = hkeys[h];
+            if (kk == k) return (int)hvals[h];
+            if (kk == EMPTY64) return -1;
+            h = (h + 1) & hmask;
+        }
+    }
+};
+
+__global__ void k_key64(int64_t n, const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
+                        const uint32_t* __restrict__ z, int s, int b, uint64_t* __restrict__ key,
+                        uint32_t* __restrict__ idx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = ((uint64_t)(z[i] >> s) << (2 * b)) | ((uint64_t)(y[i] >> s) << b) | (uint64_t)(x[i] >> s);
+    idx[i] = (uint32_t)i;
+}
+
+__global__ void k_gather64(int64_t n, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ x,
+                           const uint32_t* __restrict__ y, const uint32_t* __restrict__ z, const uint64_t* __restrict__ key,
+                           uint32_t* __restrict__ sx, uint32_t* __restrict__ sy, uint32_t* __restrict__ sz,
+                           uint32_t* __restrict__ start) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t i = idx[p];
+    sx[p] = x[i];
+    sy[p] = y[i];
+    sz[p] = z[i];
+    start[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
+}
+
+__global__ void k_starts64(int64_t n, const uint64_t* __restrict__ key, const uint32_t* __restrict__ flag,
+                           const uint32_t* __restrict__ scan, uint32_t* __restrict__ cell_start,
+                           uint64_t* __restrict__ hkeys, uint32_t* __restrict__ hvals, uint64_t hmask) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const bool st = flag[p] != 0;
+    if (p == n - 1) cell_start[st ? scan[p] + 1 : scan[p]] = (uint32_t)n;
+    if (!st) return;
+    const uint32_t c = scan[p];
+    cell_start[c] = (uint32_t)p;
+    const uint64_t k = key[p];
+    uint64_t h = hash64(k, hmask);
+    for (;;) {
+        const unsigned long long old = atomicCAS((unsigned long long*)&hkeys[h], (unsigned long long)EMPTY64,
+                                                 (unsigned long long)k);
+        if (old == EMPTY64) {
+            hvals[h] = c;
+            return;
+        }
+        h = (h + 1) & hmask;
+    }
+}
+
 struct Best {
     double d;
     int j;  // particle index of the dark matter, INT_MAX for none
@@ -150,17 +257,20 @@ __global__ __launch_bounds__(256) void k_assign(int64_t M, const int32_t* __rest
                                                 const int32_t* __restrict__ sub, const uint32_t* __restrict__ qx,
                                                 const uint32_t* __restrict__ qy, const uint32_t* __restrict__ qz,
                                                 const float* __restrict__ vx, const float* __restrict__ vy,
-                                                const float* __restrict__ vz, CellList cl,
+                                                const float* __restrict__ vz, Grid64 cl,
                                                 const uint32_t* __restrict__ cx, const uint32_t* __restrict__ cy,
                                                 const uint32_t* __restrict__ cz, const int32_t* __restrict__ dmi,
                                                 const int32_t* __restrict__ dmh, const uint32_t* __restrict__ dm_off,
-                                                int s, int b, int gb, double ell2, double sv2,
+                                                int s, int b, int gb, double ell2, double sv2, int rmax,
+                                                const uint8_t* __restrict__ todo_in, uint8_t* __restrict__ todo_out,
                                                 int32_t* __restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
+    if (todo_in && !todo_in[k]) return;
     const int i = mem[k];
     if (!isb[i]) {
         out[i] = sub[i];
+        if (todo_out) todo_out[k] = 0;
         return;
     }
     const int h = owner[k];
@@ -179,19 +289,19 @@ __global__ __launch_bounds__(256) void k_assign(int64_t M, const int32_t* __rest
     const int nc = 1 << b;
     const int ox = px >> s, oy = py >> s, oz = pz >> s;
     const double side = (double)(1 << s);
-    // rings up to nc/2 - 1 never meet a cell twice; past 8 rings (a dark-matter
-    // neighbour is normally within one) the host's list is cheaper
-    const int rlim = min(nc / 2 - 1, 8);
+    // rings up to nc/2 - 1 never meet a cell twice; past rmax rings the
+    // next pass (a coarser grid, or the host's whole list) takes over
+    const int rlim = min(nc / 2 - 1, rmax);
     bool done = false;
     for (int r = 0; r <= rlim && !done; ++r) {
         for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy)
                 for (int dx = -r; dx <= r; ++dx) {
                     if (max(max(abs(dx), abs(dy)), abs(dz)) != r) continue;
-                    const uint32_t nx = (uint32_t)((ox + dx + nc) & (nc - 1));
-                    const uint32_t ny = (uint32_t)((oy + dy + nc) & (nc - 1));
-                    const uint32_t nz = (uint32_t)((oz + dz + nc) & (nc - 1));
-                    const int c = hash_find(cl.hkeys, cl.hvals, cl.hmask, (nz << (2 * b)) | (ny << b) | nx);
+                    const uint64_t nx = (uint64_t)((ox + dx + nc) & (nc - 1));
+                    const uint64_t ny = (uint64_t)((oy + dy + nc) & (nc - 1));
+                    const uint64_t nz = (uint64_t)((oz + dz + nc) & (nc - 1));
+                    const int c = cl.find((nz << (2 * b)) | (ny << b) | nx);
                     if (c < 0) continue;
                     for (uint32_t q = cl.cell_start[c]; q < cl.cell_start[c + 1]; ++q) {
                         const uint32_t jc = cl.idx[q];
@@ -202,11 +312,16 @@ __global__ __launch_bounds__(256) void k_assign(int64_t M, const int32_t* __rest
         const double lim = (double)r * side;
         done = lim * lim / ell2 > bst.d;
     }
+    if (!done && todo_out) {
+        todo_out[k] = 1;  // left to the coarse pass
+        return;
+    }
     if (!done) {
         // a sparse host: all of its dark matter
         bst = Best{INFINITY, 0x7FFFFFFF};
         for (uint32_t jc = dm_off[h]; jc < dm_off[h + 1]; ++jc) test(cx[jc], cy[jc], cz[jc], dmi[jc]);
     }
+    if (todo_out) todo_out[k] = 0;
     out[i] = bst.j == 0x7FFFFFFF ? -1 : sub[bst.j];
 }
 
@@ -311,9 +426,14 @@ extern "C" int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, cons
             while ((double)(1 << s) < u && s < gb) ++s;
             CellList cl;
             if ((rc = build_cell_list(ctx, ndm, cx, cy, cz, gb, s, cl, st))) return rc;
+            VR_WS(proot, ctx, int32_t, WS_C7, ndm);
+            VR_WS(uroot, ctx, int32_t, WS_C8, cl.n_cells + 1);
+            hipLaunchKernelGGL(k_cell_roots, dim3(grid_for(cl.n_cells, 256)), dim3(256), 0, st, cl.n_cells,
+                               cl.cell_start, cl.idx, orig, labc, proot, uroot);
+            VR_LAUNCH_CHECK(ctx);
             VR_TIMED(ctx, "fof_attach", st, n - ndm,
                      hipLaunchKernelGGL(k_attach, dim3(grid_for(n, 256)), dim3(256), 0, st, n, is_baryon, p->qx,
-                                        p->qy, p->qz, cl, orig, s, gb - s, gb, u * u, parent));
+                                        p->qy, p->qz, cl, proot, uroot, s, gb - s, gb, u * u, parent));
             VR_LAUNCH_CHECK(ctx);
         }
     }
@@ -321,6 +441,47 @@ extern "C" int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, cons
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
+
+namespace vr {
+namespace {
+
+// Cell list of n points (cells of side 2^s) with 64-bit keys, in workspace
+// slots D2..D9 and the sort slots.
+int build_grid64(vr_ctx* ctx, int64_t n, const uint32_t* x, const uint32_t* y, const uint32_t* z, int gb, int s,
+                 Grid64& g, hipStream_t st) {
+    const int b = gb - s;
+    VR_WS(key, ctx, uint64_t, WS_D2, n);
+    VR_WS(idx, ctx, uint32_t, WS_D3, n);
+    VR_WS(sx, ctx, uint32_t, WS_D4, n);
+    VR_WS(sy, ctx, uint32_t, WS_D5, n);
+    VR_WS(sz, ctx, uint32_t, WS_D6, n);
+    VR_WS(flag, ctx, uint32_t, WS_D7, n);
+    VR_WS(cstart, ctx, uint32_t, WS_D8, n + 1);
+    VR_WS(tot, ctx, uint32_t, WS_FLAG2, 4);
+    hipLaunchKernelGGL(k_key64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, x, y, z, s, b, key, idx);
+    VR_LAUNCH_CHECK(ctx);
+    int rc = sort_pairs_u64(ctx, key, idx, n, 3 * b, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_gather64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, idx, x, y, z, key, sx, sy, sz, flag);
+    VR_LAUNCH_CHECK(ctx);
+    VR_WS(scan, ctx, uint32_t, WS_A0, n);
+    if ((rc = scan_u32(ctx, flag, scan, n, tot, st))) return rc;
+    uint32_t ncell = 0;
+    if ((rc = read_back(ctx, tot, &ncell, sizeof ncell, st))) return rc;
+    uint64_t hsize = 1024;
+    while (hsize < 2ull * ncell) hsize <<= 1;
+    VR_WS(hkeys, ctx, uint64_t, WS_D9, hsize);
+    VR_WS(hvals, ctx, uint32_t, WS_A1, hsize);
+    if ((rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hkeys), 0xFFFFFFFFu, 2 * (int64_t)hsize, st))) return rc;
+    hipLaunchKernelGGL(k_starts64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, flag, scan, cstart, hkeys, hvals,
+                       hsize - 1);
+    VR_LAUNCH_CHECK(ctx);
+    g = Grid64{hkeys, hvals, hsize - 1, cstart, idx, sx, sy, sz};
+    return VR_OK;
+}
+
+}  // namespace
+}  // namespace vr
 
 extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
                                  const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub,
@@ -365,24 +526,41 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     VR_LAUNCH_CHECK(ctx);
     int s = 0;
     while ((double)(1 << s) < u && s < gb) ++s;
-    CellList cl{};
+    Grid64 cl{};
     if (ndm > 0) {
-        if ((rc = build_cell_list(ctx, ndm, cx, cy, cz, gb, s, cl, st))) return rc;
+        // first pass on cells 8 times finer than ellx, two rings: enough where
+        // the dark matter is dense; the rest go to the ellx grid
+        const int sf = std::max(s - 3, 0);
+        if ((rc = build_grid64(ctx, ndm, cx, cy, cz, gb, sf, cl, st))) return rc;
+        VR_WS(todo, ctx, uint8_t, WS_D1, M);
+        VR_TIMED(ctx, "assign_baryons", st, M - ndm,
+                 hipLaunchKernelGGL(k_assign, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner,
+                                    is_baryon, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, cl, cx, cy, cz, dmi, dmh,
+                                    dm_off, sf, gb - sf, gb, u * u, sigma_v * sigma_v, 2, nullptr, todo, out));
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = build_grid64(ctx, ndm, cx, cy, cz, gb, s, cl, st))) return rc;
+        VR_TIMED(ctx, "assign_baryons", st, 0,
+                 hipLaunchKernelGGL(k_assign, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner,
+                                    is_baryon, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, cl, cx, cy, cz, dmi, dmh,
+                                    dm_off, s, gb - s, gb, u * u, sigma_v * sigma_v, 8, todo, nullptr, out));
+        VR_LAUNCH_CHECK(ctx);
+        return VR_OK;
     }
     if (ndm == 0) {
         // no dark matter anywhere: every baryon gets -1 (the kernel's scan
         // would find nothing); a one-entry empty table keeps it in bounds
-        VR_WS(h0, ctx, uint32_t, WS_D0, 4);
-        if ((rc = fill_u32(ctx, h0, 0xFFFFFFFFu, 1, st)) || (rc = fill_u32(ctx, h0 + 1, 0u, 3, st))) return rc;
-        cl.hkeys = h0;
-        cl.hvals = h0 + 1;
+        VR_WS(h0, ctx, uint32_t, WS_D0, 8);
+        if ((rc = fill_u32(ctx, h0, 0xFFFFFFFFu, 2, st)) || (rc = fill_u32(ctx, h0 + 2, 0u, 6, st))) return rc;
+        cl.hkeys = reinterpret_cast<const uint64_t*>(h0);
+        cl.hvals = h0 + 2;
         cl.hmask = 0;
-        cl.cell_start = h0 + 1;
+        cl.cell_start = h0 + 2;
     }
+    // no dark matter at all: every baryon gets -1
     VR_TIMED(ctx, "assign_baryons", st, M - ndm,
              hipLaunchKernelGGL(k_assign, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner, is_baryon,
                                 sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, cl, cx, cy, cz, dmi, dmh, dm_off, s,
-                                gb - s, gb, u * u, sigma_v * sigma_v, out));
+                                gb - s, gb, u * u, sigma_v * sigma_v, 0, nullptr, nullptr, out));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }

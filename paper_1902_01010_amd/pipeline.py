@@ -60,7 +60,7 @@ class Params:
     # two species (DM+Baryons mode, Sec. 2.1 and 2.4): baryons never start
     # 3D links, the substructure search runs on the dark matter, and baryons
     # join the substructure of the nearest dark matter in phase space with
-    # this sigma_v (0: the median sigma_v of the hosts)
+    # this sigma_v (0: the hosts' sigma_v weighted by their dark matter)
     baryon_sigma_v: float = 0.0
 
     @classmethod
@@ -174,7 +174,10 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
         sub = ctx.relabel_min(label6, prm.n_min)
         sv = prm.baryon_sigma_v
         if sv <= 0:
-            sv = float(np.median(ellv.cpu().numpy())) / prm.alpha_v
+            # the typical sigma_v of a searched particle's host: the mean over
+            # hosts of (det Sigma_H)^(1/6) weighted by their dark matter
+            w_dm = np.diff(host_offsets.cpu().numpy()).astype(np.float64)
+            sv = float(np.sum(w_dm * ellv.cpu().numpy()) / np.sum(w_dm)) / prm.alpha_v
         lab_all = ctx.assign_baryons(P, offsets[:n_hosts + 1], all_members, is_baryon, sub, prm.ellx, sv)
         label6 = ctx.relabel_min(lab_all, 1)
         out.update(baryon_sigma_v=sv, label6_dm=sub)

@@ -118,7 +118,8 @@ def test_pipeline_species_stagewise(ctx, vr, ref):
     sub = np.where((lab6 >= 0) & (cnt[np.maximum(lab6, 0)] >= prm.n_min), lab6, -1).astype(np.int32)
     np.testing.assert_array_equal(got["label6_dm"].cpu().numpy(), sub)
     sv = got["baryon_sigma_v"]
-    assert sv == pytest.approx(float(np.median(ellv)) / prm.alpha_v, rel=1e-12)
+    w_dm = np.diff(hoff).astype(np.float64)
+    assert sv == pytest.approx(float(np.sum(w_dm * ellv) / np.sum(w_dm)) / prm.alpha_v, rel=1e-12)
     out = ref.assign_baryons(Pr, hoff_all, hmem_all, isb, sub, prm.ellx, sv, out_init=np.full(P.n, -1, np.int32))
     low = np.full(P.n, P.n, np.int64)
     ok = out >= 0
