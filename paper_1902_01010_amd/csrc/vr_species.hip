@@ -167,77 +167,230 @@ __global__ void k_dm_member_compact(int64_t M, const uint32_t* __restrict__ flag
 }
 
 
-// ---- a cell list with 64-bit cell keys (up to 2^21 cells a side) ----------
-constexpr uint64_t EMPTY64 = ~0ull;
+// ---- phase-space tree over the dark matter of each host --------------------
+// Scaled so that D^2 of Eq. (baryondist) is a plain squared distance in six
+// dimensions: position (unwrapped against a reference member of the host)
+// over ellx, velocity over sigma_v.  A host's dark matter is sorted along a
+// six-dimensional Morton curve; runs of 64 members make the leaves, runs of
+// 64 nodes the next level up, to one root per host.  One wavefront searches
+// for one baryon: a lane per child box (or per leaf member), the nearest box
+// first, boxes whose lower bound exceeds the best D^2 so far dropped.  Leaf
+// members are scored with the exact D^2 of a brute-force scan (ties to the
+// smaller particle index), so the answer does not depend on the tree.
+constexpr int T6_FAN = 64;
+constexpr int T6_MAX_DEPTH = 8;
+constexpr int T6_LEV_SHIFT = 28;
 
-__device__ __forceinline__ uint64_t hash64(uint64_t k, uint64_t mask) {
-    k ^= k >> 33;
-    k *= 0xff51afd7ed558ccdull;
-    k ^= k >> 33;
-    k *= 0xc4ceb9fe1a85ec53ull;
-    k ^= k >> 33;
-    return k & mask;
-}
-
-struct Grid64 {
-    const uint64_t* hkeys;
-    const uint32_t* hvals;
-    uint64_t hmask;
-    const uint32_t *cell_start, *idx, *sx, *sy, *sz;
-    __device__ __forceinline__ int find(uint64_t k) const {
-        uint64_t h = hash64(k, hmask);
-        for (;;) {
-            const uint64_t kk = hkeys[h];
-            if (kk == k) return (int)hvals[h];
-            if (kk == EMPTY64) return -1;
-            h = (h + 1) & hmask;
-        }
-    }
+// per host: reference position, extents of the unwrapped position over all
+// members, order-preserving integer images of the dark matter's velocity
+// extents, and whether every unwrapped difference is the periodic one
+struct HostBox {
+    int ref[3];
+    int umin[3], umax[3];
+    unsigned vmin[3], vmax[3];
+    int ok;
 };
 
-__global__ void k_key64(int64_t n, const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
-                        const uint32_t* __restrict__ z, int s, int b, uint64_t* __restrict__ key,
-                        uint32_t* __restrict__ idx) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    key[i] = ((uint64_t)(z[i] >> s) << (2 * b)) | ((uint64_t)(y[i] >> s) << b) | (uint64_t)(x[i] >> s);
-    idx[i] = (uint32_t)i;
+__device__ __forceinline__ unsigned f2o(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float o2f(unsigned u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }
 
-__global__ void k_gather64(int64_t n, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ x,
-                           const uint32_t* __restrict__ y, const uint32_t* __restrict__ z, const uint64_t* __restrict__ key,
-                           uint32_t* __restrict__ sx, uint32_t* __restrict__ sy, uint32_t* __restrict__ sz,
-                           uint32_t* __restrict__ start) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t i = idx[p];
-    sx[p] = x[i];
-    sy[p] = y[i];
-    sz[p] = z[i];
-    start[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
-}
+struct Tree6 {
+    const int32_t* lvl;  // (depth + 1) x (n_hosts + 1): first node of each host per level; level 0 = members
+    int H1;              // n_hosts + 1
+    int depth;           // levels above the members; the top one has one node per host
+    int base[T6_MAX_DEPTH + 1];  // first box of each level (level >= 1)
+    const float* box;    // 12 floats a node: lower corner, then upper corner
+    const HostBox* hbox;
+    const uint32_t *sx, *sy, *sz;  // members in tree order
+    const float *svx, *svy, *svz;
+    const int32_t* sj;  // particle index
+};
 
-__global__ void k_starts64(int64_t n, const uint64_t* __restrict__ key, const uint32_t* __restrict__ flag,
-                           const uint32_t* __restrict__ scan, uint32_t* __restrict__ cell_start,
-                           uint64_t* __restrict__ hkeys, uint32_t* __restrict__ hvals, uint64_t hmask) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const bool st = flag[p] != 0;
-    if (p == n - 1) cell_start[st ? scan[p] + 1 : scan[p]] = (uint32_t)n;
-    if (!st) return;
-    const uint32_t c = scan[p];
-    cell_start[c] = (uint32_t)p;
-    const uint64_t k = key[p];
-    uint64_t h = hash64(k, hmask);
-    for (;;) {
-        const unsigned long long old = atomicCAS((unsigned long long*)&hkeys[h], (unsigned long long)EMPTY64,
-                                                 (unsigned long long)k);
-        if (old == EMPTY64) {
-            hvals[h] = c;
-            return;
-        }
-        h = (h + 1) & hmask;
+__global__ void k_host_init(int n_hosts, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
+                            const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
+                            const uint32_t* __restrict__ qz, HostBox* __restrict__ hb) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hosts) return;
+    HostBox b;
+    b.ref[0] = b.ref[1] = b.ref[2] = 0;
+    if (off[h] < off[h + 1]) {
+        const int i = mem[off[h]];
+        b.ref[0] = (int)qx[i];
+        b.ref[1] = (int)qy[i];
+        b.ref[2] = (int)qz[i];
     }
+    for (int d = 0; d < 3; ++d) {
+        b.umin[d] = INT_MAX;
+        b.umax[d] = INT_MIN;
+        b.vmin[d] = 0xFFFFFFFFu;
+        b.vmax[d] = 0u;
+    }
+    b.ok = 0;
+    hb[h] = b;
+}
+
+// extents per host; a wavefront whose members share one host reduces first
+__global__ __launch_bounds__(256) void k_host_extent(int64_t M, const int32_t* __restrict__ mem,
+                                                     const int32_t* __restrict__ owner, const uint8_t* __restrict__ isb,
+                                                     const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
+                                                     const uint32_t* __restrict__ qz, const float* __restrict__ vx,
+                                                     const float* __restrict__ vy, const float* __restrict__ vz,
+                                                     int gb, HostBox* __restrict__ hb) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int h = -1;
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    unsigned vlo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, vhi[3] = {0u, 0u, 0u};
+    if (k < M) {
+        h = owner[k];
+        const int i = mem[k];
+        const int q[3] = {(int)qx[i], (int)qy[i], (int)qz[i]};
+        for (int d = 0; d < 3; ++d) lo[d] = hi[d] = min_image(q[d] - hb[h].ref[d], gb);
+        if (!isb[i]) {
+            vlo[0] = vhi[0] = f2o(vx[i]);
+            vlo[1] = vhi[1] = f2o(vy[i]);
+            vlo[2] = vhi[2] = f2o(vz[i]);
+        }
+    }
+    const int h0 = __shfl(h, 0, 64);
+    if (h0 >= 0 && __ballot(h != h0) == 0) {
+        for (int o = 32; o; o >>= 1)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+                hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+                vlo[d] = min(vlo[d], (unsigned)__shfl_xor((int)vlo[d], o, 64));
+                vhi[d] = max(vhi[d], (unsigned)__shfl_xor((int)vhi[d], o, 64));
+            }
+        if (lane_id() != 0) return;
+    } else if (h < 0) {
+        return;
+    }
+    HostBox* b = hb + h;
+    for (int d = 0; d < 3; ++d) {
+        atomicMin(&b->umin[d], lo[d]);
+        atomicMax(&b->umax[d], hi[d]);
+        atomicMin(&b->vmin[d], vlo[d]);
+        atomicMax(&b->vmax[d], vhi[d]);
+    }
+}
+
+__global__ void k_host_ok(int n_hosts, int gb, HostBox* __restrict__ hb) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_hosts) return;
+    const int64_t half = int64_t(1) << (gb - 1);
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) ok = ok && ((int64_t)hb[h].umax[d] - hb[h].umin[d] < half);
+    hb[h].ok = ok ? 1 : 0;
+}
+
+__device__ __forceinline__ void scaled6(const HostBox& b, uint32_t x, uint32_t y, uint32_t z, float vx, float vy,
+                                        float vz, int gb, float ix, float iv, float* o) {
+    o[0] = (float)min_image((int)x - b.ref[0], gb) * ix;
+    o[1] = (float)min_image((int)y - b.ref[1], gb) * ix;
+    o[2] = (float)min_image((int)z - b.ref[2], gb) * ix;
+    o[3] = vx * iv;
+    o[4] = vy * iv;
+    o[5] = vz * iv;
+}
+
+// Morton key of the compacted dark matter: host in the high bits, then
+// mbits interleaved bits of each scaled coordinate over the host's box
+__global__ void k_key6(int64_t ndm, const uint32_t* __restrict__ cx, const uint32_t* __restrict__ cy,
+                       const uint32_t* __restrict__ cz, const int32_t* __restrict__ dmi,
+                       const int32_t* __restrict__ dmh, const float* __restrict__ vx, const float* __restrict__ vy,
+                       const float* __restrict__ vz, const HostBox* __restrict__ hb, int gb, float ix, float iv,
+                       int mbits, uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ndm) return;
+    const int h = dmh[j], i = dmi[j];
+    const HostBox b = hb[h];
+    float y[6], lo[6], ext = 0.f;
+    scaled6(b, cx[j], cy[j], cz[j], vx[i], vy[i], vz[i], gb, ix, iv, y);
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = (float)b.umin[d] * ix;
+        ext = fmaxf(ext, (float)b.umax[d] * ix - lo[d]);
+        lo[d + 3] = o2f(b.vmin[d]) * iv;
+        ext = fmaxf(ext, o2f(b.vmax[d]) * iv - lo[d + 3]);
+    }
+    const uint32_t top = (1u << mbits) - 1u;
+    const float sc = ext > 0.f ? (float)(1u << mbits) / ext : 0.f;
+    uint32_t c[6];
+    for (int d = 0; d < 6; ++d) c[d] = min(top, (uint32_t)fmaxf((y[d] - lo[d]) * sc, 0.f));
+    uint64_t m = 0;
+    for (int bit = mbits - 1; bit >= 0; --bit)
+        for (int d = 0; d < 6; ++d) m = (m << 1) | ((c[d] >> bit) & 1u);
+    key[j] = ((uint64_t)h << (6 * mbits)) | m;
+    val[j] = (uint32_t)j;
+}
+
+__global__ void k_gather6(int64_t ndm, const uint32_t* __restrict__ val, const uint32_t* __restrict__ cx,
+                          const uint32_t* __restrict__ cy, const uint32_t* __restrict__ cz,
+                          const int32_t* __restrict__ dmi, const float* __restrict__ vx, const float* __restrict__ vy,
+                          const float* __restrict__ vz, uint32_t* __restrict__ sx, uint32_t* __restrict__ sy,
+                          uint32_t* __restrict__ sz, float* __restrict__ svx, float* __restrict__ svy,
+                          float* __restrict__ svz, int32_t* __restrict__ sj) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ndm) return;
+    const uint32_t j = val[p];
+    const int i = dmi[j];
+    sx[p] = cx[j];
+    sy[p] = cy[j];
+    sz[p] = cz[j];
+    svx[p] = vx[i];
+    svy[p] = vy[i];
+    svz[p] = vz[i];
+    sj[p] = i;
+}
+
+__device__ __forceinline__ int host_of_node(const int32_t* lvl, int H1, int g) {
+    int lo = 0, hi = H1 - 1;  // last h with lvl[h] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (lvl[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// boxes of level lev: one wavefront per node, a lane per child
+__global__ __launch_bounds__(256) void k_boxes6(int64_t n_nodes, int lev, Tree6 t, int gb, float ix, float iv,
+                                                float* __restrict__ box) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= n_nodes) return;
+    const int lane = (int)lane_id();
+    const int32_t* L = t.lvl + (int64_t)lev * t.H1;
+    const int32_t* C = t.lvl + (int64_t)(lev - 1) * t.H1;
+    const int h = host_of_node(L, t.H1, (int)g);
+    const int c = C[h] + T6_FAN * ((int)g - L[h]) + lane;
+    float lo[6], hi[6];
+    for (int d = 0; d < 6; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    if (c < C[h + 1]) {
+        if (lev == 1) {
+            scaled6(t.hbox[h], t.sx[c], t.sy[c], t.sz[c], t.svx[c], t.svy[c], t.svz[c], gb, ix, iv, lo);
+            for (int d = 0; d < 6; ++d) hi[d] = lo[d];
+        } else {
+            const float* cb = t.box + (int64_t)(t.base[lev - 1] + c) * 12;
+            for (int d = 0; d < 6; ++d) {
+                lo[d] = cb[d];
+                hi[d] = cb[6 + d];
+            }
+        }
+    }
+    for (int o = 32; o; o >>= 1)
+        for (int d = 0; d < 6; ++d) {
+            lo[d] = fminf(lo[d], __shfl_xor(lo[d], o, 64));
+            hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], o, 64));
+        }
+    float* ob = box + (int64_t)(t.base[lev] + g) * 12;
+    if (lane < 6) ob[lane] = lo[lane];
+    else if (lane < 12) ob[lane] = hi[lane - 6];
 }
 
 struct Best {
@@ -252,77 +405,134 @@ __device__ __forceinline__ void consider(Best& bst, double D2, int j) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_assign(int64_t M, const int32_t* __restrict__ mem,
-                                                const int32_t* __restrict__ owner, const uint8_t* __restrict__ isb,
-                                                const int32_t* __restrict__ sub, const uint32_t* __restrict__ qx,
-                                                const uint32_t* __restrict__ qy, const uint32_t* __restrict__ qz,
-                                                const float* __restrict__ vx, const float* __restrict__ vy,
-                                                const float* __restrict__ vz, Grid64 cl,
-                                                const uint32_t* __restrict__ cx, const uint32_t* __restrict__ cy,
-                                                const uint32_t* __restrict__ cz, const int32_t* __restrict__ dmi,
-                                                const int32_t* __restrict__ dmh, const uint32_t* __restrict__ dm_off,
-                                                int s, int b, int gb, double ell2, double sv2, int rmax,
-                                                const uint8_t* __restrict__ todo_in, uint8_t* __restrict__ todo_out,
-                                                int32_t* __restrict__ out) {
+// dark-matter members keep their own label
+__global__ void k_assign_dm(int64_t M, const int32_t* __restrict__ mem, const uint8_t* __restrict__ isb,
+                            const int32_t* __restrict__ sub, int no_dm, int32_t* __restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
-    if (todo_in && !todo_in[k]) return;
     const int i = mem[k];
-    if (!isb[i]) {
-        out[i] = sub[i];
-        if (todo_out) todo_out[k] = 0;
+    if (!isb[i]) out[i] = sub[i];
+    else if (no_dm) out[i] = -1;
+}
+
+__global__ void k_baryon_list(int64_t M, const uint32_t* __restrict__ dmflag, const uint32_t* __restrict__ pos,
+                              int32_t* __restrict__ blist) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < M && !dmflag[k]) blist[k - pos[k]] = (int32_t)k;
+}
+
+// one wavefront per baryon
+__global__ __launch_bounds__(256) void k_assign6(int64_t nb, const int32_t* __restrict__ blist,
+                                                 const int32_t* __restrict__ mem, const int32_t* __restrict__ owner,
+                                                 const int32_t* __restrict__ sub, const uint32_t* __restrict__ qx,
+                                                 const uint32_t* __restrict__ qy, const uint32_t* __restrict__ qz,
+                                                 const float* __restrict__ vx, const float* __restrict__ vy,
+                                                 const float* __restrict__ vz, Tree6 t, int gb, double ell2,
+                                                 double sv2, float ix, float iv, int32_t* __restrict__ out) {
+    __shared__ int2 stack[4][T6_MAX_DEPTH * T6_FAN];
+    const int w = (int)(threadIdx.x >> 6);
+    const int lane = (int)lane_id();
+    const int64_t bi = (int64_t)blockIdx.x * 4 + w;
+    if (bi >= nb) return;
+    const int k = blist[bi];
+    const int i = mem[k], h = owner[k];
+    const int d0 = t.lvl[h], d1 = t.lvl[h + 1];
+    if (d0 == d1) {  // no dark matter in this host
+        if (lane == 0) out[i] = -1;
         return;
     }
-    const int h = owner[k];
     const int px = (int)qx[i], py = (int)qy[i], pz = (int)qz[i];
     const double bx = (double)vx[i], by = (double)vy[i], bz = (double)vz[i];
     Best bst{INFINITY, 0x7FFFFFFF};
-    // D2 = d2 / ell2 + dv2 / sigma_v^2 of the dark matter j at (x, y, z)
-    auto test = [&](uint32_t x, uint32_t y, uint32_t z, int j) {
-        const int ddx = min_image((int)x - px, gb);
-        const int ddy = min_image((int)y - py, gb);
-        const int ddz = min_image((int)z - pz, gb);
-        const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
-        const double ax = bx - (double)vx[j], ay = by - (double)vy[j], az = bz - (double)vz[j];
-        consider(bst, d2 / ell2 + (ax * ax + ay * ay + az * az) / sv2, j);
+    // members [p0, p1) of the tree order, scored exactly, a lane each
+    auto leaf = [&](int p0, int p1) __attribute__((always_inline)) {
+        const int p = p0 + lane;
+        double d = INFINITY;
+        int j = 0x7FFFFFFF;
+        if (p < p1) {
+            const int ddx = min_image((int)t.sx[p] - px, gb);
+            const int ddy = min_image((int)t.sy[p] - py, gb);
+            const int ddz = min_image((int)t.sz[p] - pz, gb);
+            const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+            const double ax = bx - (double)t.svx[p], ay = by - (double)t.svy[p], az = bz - (double)t.svz[p];
+            d = d2 / ell2 + (ax * ax + ay * ay + az * az) / sv2;
+            j = t.sj[p];
+        }
+        for (int o = 32; o; o >>= 1) {
+            const double od = __shfl_xor(d, o, 64);
+            const int oj = __shfl_xor(j, o, 64);
+            if (od < d || (od == d && oj < j)) {
+                d = od;
+                j = oj;
+            }
+        }
+        consider(bst, d, j);
     };
-    const int nc = 1 << b;
-    const int ox = px >> s, oy = py >> s, oz = pz >> s;
-    const double side = (double)(1 << s);
-    // rings up to nc/2 - 1 never meet a cell twice; past rmax rings the
-    // next pass (a coarser grid, or the host's whole list) takes over
-    const int rlim = min(nc / 2 - 1, rmax);
-    bool done = false;
-    for (int r = 0; r <= rlim && !done; ++r) {
-        for (int dz = -r; dz <= r; ++dz)
-            for (int dy = -r; dy <= r; ++dy)
-                for (int dx = -r; dx <= r; ++dx) {
-                    if (max(max(abs(dx), abs(dy)), abs(dz)) != r) continue;
-                    const uint64_t nx = (uint64_t)((ox + dx + nc) & (nc - 1));
-                    const uint64_t ny = (uint64_t)((oy + dy + nc) & (nc - 1));
-                    const uint64_t nz = (uint64_t)((oz + dz + nc) & (nc - 1));
-                    const int c = cl.find((nz << (2 * b)) | (ny << b) | nx);
-                    if (c < 0) continue;
-                    for (uint32_t q = cl.cell_start[c]; q < cl.cell_start[c + 1]; ++q) {
-                        const uint32_t jc = cl.idx[q];
-                        if (dmh[jc] == h) test(cl.sx[q], cl.sy[q], cl.sz[q], dmi[jc]);
-                    }
+    const HostBox hb = t.hbox[h];
+    if (!hb.ok) {
+        // a host wider than half the box: all of its dark matter
+        for (int p0 = d0; p0 < d1; p0 += T6_FAN) leaf(p0, min(p0 + T6_FAN, d1));
+    } else {
+        float y[6];
+        scaled6(hb, (uint32_t)px, (uint32_t)py, (uint32_t)pz, vx[i], vy[i], vz[i], gb, ix, iv, y);
+        const int top = t.depth;
+        const int root = t.lvl[(int64_t)top * t.H1 + h];
+        // every lower bound is shrunk by a margin that covers the rounding
+        // of the scaled coordinates (a few ulps of the largest of them)
+        float amax = 0.f;
+        {
+            const float* rb = t.box + (int64_t)(t.base[top] + root) * 12;
+            for (int d = 0; d < 12; ++d) amax = fmaxf(amax, fabsf(rb[d]));
+            for (int d = 0; d < 6; ++d) amax = fmaxf(amax, fabsf(y[d]));
+        }
+        const float E = amax * 0x1p-19f;
+        int2* stk = stack[w];
+        if (lane == 0) stk[0] = make_int2((top << T6_LEV_SHIFT) | root, __float_as_int(0.f));
+        __builtin_amdgcn_wave_barrier();
+        int sp = 1;
+        while (sp > 0) {
+            --sp;
+            const int2 e = stk[sp];
+            if ((double)__int_as_float(e.y) > bst.d) continue;
+            const int lev = e.x >> T6_LEV_SHIFT;
+            const int node = e.x & ((1 << T6_LEV_SHIFT) - 1);
+            const int32_t* L = t.lvl + (int64_t)lev * t.H1;
+            const int32_t* C = t.lvl + (int64_t)(lev - 1) * t.H1;
+            const int c0 = C[h] + T6_FAN * (node - L[h]);
+            const int c1 = min(c0 + T6_FAN, C[h + 1]);
+            if (lev == 1) {
+                leaf(c0, c1);
+                continue;
+            }
+            const int c = c0 + lane;
+            float lb = INFINITY;
+            if (c < c1) {
+                const float* cb = t.box + (int64_t)(t.base[lev - 1] + c) * 12;
+                lb = 0.f;
+                for (int d = 0; d < 6; ++d) {
+                    const float g = fmaxf(fmaxf(cb[d] - y[d], y[d] - cb[6 + d]) - E, 0.f);
+                    lb += g * g;
                 }
-        // every point beyond ring r lies at least r cells away along an axis
-        const double lim = (double)r * side;
-        done = lim * lim / ell2 > bst.d;
+                lb *= 1.f - 0x1p-20f;
+            }
+            const bool cand = c < c1 && (double)lb <= bst.d;
+            const uint64_t cm = __ballot(cand);
+            if (!cm) continue;
+            float mn = cand ? lb : INFINITY;
+            for (int o = 32; o; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
+            const uint64_t near = __ballot(cand && lb == mn);
+            const int first = __builtin_ctzll(near);
+            const uint64_t others = cm & ~(1ull << first);
+            const int no = __popcll(others);
+            const int2 ent = make_int2(((lev - 1) << T6_LEV_SHIFT) | c, __float_as_int(lb));
+            // the nearest child goes on top, to be opened next
+            if (cand && lane != first) stk[sp + __popcll(others & ((1ull << lane) - 1ull))] = ent;
+            if (lane == first) stk[sp + no] = ent;
+            sp += no + 1;
+            __builtin_amdgcn_wave_barrier();
+        }
     }
-    if (!done && todo_out) {
-        todo_out[k] = 1;  // left to the coarse pass
-        return;
-    }
-    if (!done) {
-        // a sparse host: all of its dark matter
-        bst = Best{INFINITY, 0x7FFFFFFF};
-        for (uint32_t jc = dm_off[h]; jc < dm_off[h + 1]; ++jc) test(cx[jc], cy[jc], cz[jc], dmi[jc]);
-    }
-    if (todo_out) todo_out[k] = 0;
-    out[i] = bst.j == 0x7FFFFFFF ? -1 : sub[bst.j];
+    if (lane == 0) out[i] = bst.j == 0x7FFFFFFF ? -1 : sub[bst.j];
 }
 
 __global__ void k_dm_offsets(int n_hosts, int64_t M, const int32_t* __restrict__ off, const uint32_t* __restrict__ pos,
@@ -442,47 +652,6 @@ extern "C" int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, cons
     return VR_OK;
 }
 
-namespace vr {
-namespace {
-
-// Cell list of n points (cells of side 2^s) with 64-bit keys, in workspace
-// slots D2..D9 and the sort slots.
-int build_grid64(vr_ctx* ctx, int64_t n, const uint32_t* x, const uint32_t* y, const uint32_t* z, int gb, int s,
-                 Grid64& g, hipStream_t st) {
-    const int b = gb - s;
-    VR_WS(key, ctx, uint64_t, WS_D2, n);
-    VR_WS(idx, ctx, uint32_t, WS_D3, n);
-    VR_WS(sx, ctx, uint32_t, WS_D4, n);
-    VR_WS(sy, ctx, uint32_t, WS_D5, n);
-    VR_WS(sz, ctx, uint32_t, WS_D6, n);
-    VR_WS(flag, ctx, uint32_t, WS_D7, n);
-    VR_WS(cstart, ctx, uint32_t, WS_D8, n + 1);
-    VR_WS(tot, ctx, uint32_t, WS_FLAG2, 4);
-    hipLaunchKernelGGL(k_key64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, x, y, z, s, b, key, idx);
-    VR_LAUNCH_CHECK(ctx);
-    int rc = sort_pairs_u64(ctx, key, idx, n, 3 * b, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_gather64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, idx, x, y, z, key, sx, sy, sz, flag);
-    VR_LAUNCH_CHECK(ctx);
-    VR_WS(scan, ctx, uint32_t, WS_A0, n);
-    if ((rc = scan_u32(ctx, flag, scan, n, tot, st))) return rc;
-    uint32_t ncell = 0;
-    if ((rc = read_back(ctx, tot, &ncell, sizeof ncell, st))) return rc;
-    uint64_t hsize = 1024;
-    while (hsize < 2ull * ncell) hsize <<= 1;
-    VR_WS(hkeys, ctx, uint64_t, WS_D9, hsize);
-    VR_WS(hvals, ctx, uint32_t, WS_A1, hsize);
-    if ((rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hkeys), 0xFFFFFFFFu, 2 * (int64_t)hsize, st))) return rc;
-    hipLaunchKernelGGL(k_starts64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, flag, scan, cstart, hkeys, hvals,
-                       hsize - 1);
-    VR_LAUNCH_CHECK(ctx);
-    g = Grid64{hkeys, hvals, hsize - 1, cstart, idx, sx, sy, sz};
-    return VR_OK;
-}
-
-}  // namespace
-}  // namespace vr
-
 extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
                                  const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub,
                                  double ellx, double sigma_v, int32_t* out, void* stream) {
@@ -524,44 +693,105 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     hipLaunchKernelGGL(k_dm_offsets, dim3(grid_for(n_hosts + 1, 256)), dim3(256), 0, st, n_hosts, M, host_offsets,
                        pos, tot, dm_off);
     VR_LAUNCH_CHECK(ctx);
-    int s = 0;
-    while ((double)(1 << s) < u && s < gb) ++s;
-    Grid64 cl{};
-    if (ndm > 0) {
-        // first pass on cells 8 times finer than ellx, two rings: enough where
-        // the dark matter is dense; the rest go to the ellx grid
-        const int sf = std::max(s - 3, 0);
-        if ((rc = build_grid64(ctx, ndm, cx, cy, cz, gb, sf, cl, st))) return rc;
-        VR_WS(todo, ctx, uint8_t, WS_D1, M);
-        VR_TIMED(ctx, "assign_baryons", st, M - ndm,
-                 hipLaunchKernelGGL(k_assign, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner,
-                                    is_baryon, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, cl, cx, cy, cz, dmi, dmh,
-                                    dm_off, sf, gb - sf, gb, u * u, sigma_v * sigma_v, 2, nullptr, todo, out));
-        VR_LAUNCH_CHECK(ctx);
-        if ((rc = build_grid64(ctx, ndm, cx, cy, cz, gb, s, cl, st))) return rc;
-        VR_TIMED(ctx, "assign_baryons", st, 0,
-                 hipLaunchKernelGGL(k_assign, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner,
-                                    is_baryon, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, cl, cx, cy, cz, dmi, dmh,
-                                    dm_off, s, gb - s, gb, u * u, sigma_v * sigma_v, 8, todo, nullptr, out));
+    if (ndm == 0) {
+        hipLaunchKernelGGL(k_assign_dm, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, is_baryon, sub, 1,
+                           out);
         VR_LAUNCH_CHECK(ctx);
         return VR_OK;
     }
-    if (ndm == 0) {
-        // no dark matter anywhere: every baryon gets -1 (the kernel's scan
-        // would find nothing); a one-entry empty table keeps it in bounds
-        VR_WS(h0, ctx, uint32_t, WS_D0, 8);
-        if ((rc = fill_u32(ctx, h0, 0xFFFFFFFFu, 2, st)) || (rc = fill_u32(ctx, h0 + 2, 0u, 6, st))) return rc;
-        cl.hkeys = reinterpret_cast<const uint64_t*>(h0);
-        cl.hvals = h0 + 2;
-        cl.hmask = 0;
-        cl.cell_start = h0 + 2;
-    }
-    // no dark matter at all: every baryon gets -1
-    VR_TIMED(ctx, "assign_baryons", st, M - ndm,
-             hipLaunchKernelGGL(k_assign, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner, is_baryon,
-                                sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, cl, cx, cy, cz, dmi, dmh, dm_off, s,
-                                gb - s, gb, u * u, sigma_v * sigma_v, 0, nullptr, nullptr, out));
+    const int64_t nb = M - ndm;
+    const float ix = (float)(1.0 / u), iv = (float)(1.0 / sigma_v);
+    // per-host boxes and the wrap check
+    VR_WS(hbox, ctx, HostBox, WS_D0, n_hosts);
+    hipLaunchKernelGGL(k_host_init, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, host_offsets,
+                       host_members, p->qx, p->qy, p->qz, hbox);
+    hipLaunchKernelGGL(k_host_extent, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner, is_baryon,
+                       p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, gb, hbox);
+    hipLaunchKernelGGL(k_host_ok, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, gb, hbox);
     VR_LAUNCH_CHECK(ctx);
+    // tree order: by host, then along the Morton curve
+    int hbits = 1;
+    while (hbits < 62 && (int64_t(1) << hbits) < n_hosts) ++hbits;
+    const int mbits = std::min(8, (64 - hbits) / 6);
+    VR_WS(key, ctx, uint64_t, WS_D2, ndm);
+    VR_WS(val, ctx, uint32_t, WS_D3, ndm);
+    hipLaunchKernelGGL(k_key6, dim3(grid_for(ndm, 256)), dim3(256), 0, st, ndm, cx, cy, cz, dmi, dmh, p->vx, p->vy,
+                       p->vz, hbox, gb, ix, iv, mbits, key, val);
+    VR_LAUNCH_CHECK(ctx);
+    if ((rc = sort_pairs_u64(ctx, key, val, ndm, hbits + 6 * mbits, st))) return rc;
+    Tree6 t{};
+    {
+        VR_WS(sx, ctx, uint32_t, WS_D4, ndm);
+        VR_WS(sy, ctx, uint32_t, WS_D5, ndm);
+        VR_WS(sz, ctx, uint32_t, WS_D6, ndm);
+        VR_WS(svx, ctx, float, WS_D7, ndm);
+        VR_WS(svy, ctx, float, WS_D8, ndm);
+        VR_WS(svz, ctx, float, WS_D9, ndm);
+        VR_WS(sj, ctx, int32_t, WS_A0, ndm);
+        hipLaunchKernelGGL(k_gather6, dim3(grid_for(ndm, 256)), dim3(256), 0, st, ndm, val, cx, cy, cz, dmi, p->vx,
+                           p->vy, p->vz, sx, sy, sz, svx, svy, svz, sj);
+        VR_LAUNCH_CHECK(ctx);
+        t.sx = sx;
+        t.sy = sy;
+        t.sz = sz;
+        t.svx = svx;
+        t.svy = svy;
+        t.svz = svz;
+        t.sj = sj;
+    }
+    // level sizes: runs of 64 per host, up to one node per host
+    std::vector<uint32_t> doff(n_hosts + 1);
+    if ((rc = read_back(ctx, dm_off, doff.data(), doff.size() * sizeof(uint32_t), st))) return rc;
+    const int H1 = n_hosts + 1;
+    std::vector<int32_t> lvl(doff.begin(), doff.end());
+    std::vector<int64_t> cnt(n_hosts);
+    for (int h = 0; h < n_hosts; ++h) cnt[h] = (int64_t)doff[h + 1] - doff[h];
+    int depth = 0;
+    int64_t total = 0;
+    for (bool more = true; more;) {
+        if (depth == T6_MAX_DEPTH) return set_err(ctx, VR_ERR_UNSUPPORTED, "phase-space tree too deep");
+        more = false;
+        int64_t run = 0;
+        const size_t at = lvl.size();
+        lvl.resize(at + H1);
+        for (int h = 0; h < n_hosts; ++h) {
+            lvl[at + h] = (int32_t)run;
+            cnt[h] = (cnt[h] + T6_FAN - 1) / T6_FAN;
+            more = more || cnt[h] > 1;
+            run += cnt[h];
+        }
+        lvl[at + n_hosts] = (int32_t)run;
+        ++depth;
+        t.base[depth] = (int)total;
+        total += run;
+        if (run >= (int64_t(1) << T6_LEV_SHIFT) || total >= (int64_t(1) << 31) / 12)
+            return set_err(ctx, VR_ERR_UNSUPPORTED, "phase-space tree too large");
+    }
+    VR_WS(lvl_d, ctx, int32_t, WS_A2, (int64_t)lvl.size());
+    VR_HIP(ctx, hipMemcpyAsync(lvl_d, lvl.data(), lvl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    VR_HIP(ctx, hipStreamSynchronize(st));  // lvl leaves scope
+    VR_WS(box, ctx, float, WS_A1, 12 * total);
+    t.lvl = lvl_d;
+    t.H1 = H1;
+    t.depth = depth;
+    t.box = box;
+    t.hbox = hbox;
+    for (int l = 1; l <= depth; ++l) {
+        const int64_t nl = lvl[(size_t)l * H1 + n_hosts];
+        hipLaunchKernelGGL(k_boxes6, dim3((unsigned)((nl + 3) / 4)), dim3(256), 0, st, nl, l, t, gb, ix, iv, box);
+        VR_LAUNCH_CHECK(ctx);
+    }
+    VR_WS(blist, ctx, int32_t, WS_A3, nb + 1);
+    hipLaunchKernelGGL(k_baryon_list, dim3(grid_for(M, 256)), dim3(256), 0, st, M, flag, pos, blist);
+    hipLaunchKernelGGL(k_assign_dm, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, is_baryon, sub, 0, out);
+    VR_LAUNCH_CHECK(ctx);
+    if (nb > 0) {
+        VR_TIMED(ctx, "assign_baryons", st, nb,
+                 hipLaunchKernelGGL(k_assign6, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, nb, blist,
+                                    host_members, owner, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, t, gb, u * u,
+                                    sigma_v * sigma_v, ix, iv, out));
+        VR_LAUNCH_CHECK(ctx);
+    }
     return VR_OK;
 }
 

@@ -70,6 +70,26 @@ def test_assign_baryons_parity(ctx, ref, box, sigma_v):
     assert (exp[mem][isb[mem] == 1] >= 0).any()
 
 
+def test_assign_baryons_host_wider_than_half_the_box(ctx, vr, ref):
+    """One host holding the whole box, plus a small host: the wide host's
+    members do not fit in half a box, so no unwrapped frame exists for it and
+    it is scanned whole; the small one is searched as usual."""
+    w = synth.two_species(seed=8, n_side=24)
+    P, Pr = both(ctx, vr, ref, w)
+    isb = w.meta["is_baryon"].astype(np.uint8)
+    n = P.n
+    rng = np.random.default_rng(2)
+    small = np.sort(rng.choice(n, 300, replace=False)).astype(np.int32)
+    rest = np.setdiff1d(np.arange(n), small).astype(np.int32)
+    off = np.array([0, rest.size, n], np.int32)
+    mem = np.concatenate([rest, small]).astype(np.int32)
+    sub = rng.integers(-1, 50, n).astype(np.int32)
+    exp = ref.assign_baryons(Pr, off, mem, isb, sub, w.params["ellx"], 200.0)
+    got = ctx.assign_baryons(P, dev_tensor(off), dev_tensor(mem), dev_tensor(isb), dev_tensor(sub),
+                             w.params["ellx"], 200.0).cpu().numpy()
+    np.testing.assert_array_equal(got, exp)
+
+
 def test_assign_baryons_hosts_without_dark_matter(ctx, vr, ref):
     c = 1 << 20
     q = np.array([[c, c + 500, c + 9000, c + 9100, c + 9300], [c] * 5, [c] * 5], np.uint32)
