@@ -57,15 +57,26 @@ __global__ void k_seed_dm(int64_t ndm, const int32_t* __restrict__ orig, const i
     if (k < ndm) parent[orig[k]] = orig[labc[k]];
 }
 
-// The cells around a point: all 27 when the grid has 3 or more a side, else
-// the distinct ones among them.
+// The cells around a point that may hold a point closer than ellx (own cell
+// first): of the 27 when the grid has 3 or more a side, those whose nearest
+// grid point lies within ellx; else the distinct ones among them.
 template <class F>
-__device__ __forceinline__ void cells27(int px, int py, int pz, int s, int b, const uint32_t* __restrict__ hkeys,
-                                        const uint32_t* __restrict__ hvals, uint32_t hmask, F&& visit) {
+__device__ __forceinline__ void cells27(int px, int py, int pz, int s, int b, double ell2,
+                                        const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                        uint32_t hmask, F&& visit) {
     const int nc = 1 << b;
+    const int side = 1 << s;
     const int cx = px >> s, cy = py >> s, cz = pz >> s;
+    const int fx = px & (side - 1), fy = py & (side - 1), fz = pz & (side - 1);
+    // squared distance along one axis to the nearest grid point of the
+    // neighbouring cell at offset d (distinct cells when nc >= 3)
+    auto gap2 = [side](int f, int d) -> double {
+        const double g = d < 0 ? (double)f + 1.0 : (d > 0 ? (double)(side - f) : 0.0);
+        return g * g;
+    };
     uint32_t seen = 0;
-    for (int o = 0; o < 27; ++o) {
+    for (int t = 0; t < 27; ++t) {
+        const int o = (t + 13) % 27;  // the own cell first
         const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
         const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
         const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
@@ -74,6 +85,8 @@ __device__ __forceinline__ void cells27(int px, int py, int pz, int s, int b, co
             const uint32_t bit = 1u << (nx + 2 * ny + 4 * nz);
             if (seen & bit) continue;
             seen |= bit;
+        } else if (gap2(fx, dx) + gap2(fy, dy) + gap2(fz, dz) >= ell2) {
+            continue;  // no member of that cell is closer than ellx
         }
         const int c = hash_find(hkeys, hvals, hmask, (nz << (2 * b)) | (ny << b) | nx);
         if (c >= 0) visit(c);
@@ -108,7 +121,7 @@ __global__ __launch_bounds__(256) void k_attach(int64_t n, const uint8_t* __rest
     if (i >= n || !isb[i]) return;
     const int px = (int)qx[i], py = (int)qy[i], pz = (int)qz[i];
     int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
-    cells27(px, py, pz, s, b, cl.hkeys, cl.hvals, cl.hmask, [&](int c) {
+    cells27(px, py, pz, s, b, ell2, cl.hkeys, cl.hvals, cl.hmask, [&](int c) {
         const int ur = uroot[c];
         if (ur >= 0 && (ur == k0 || ur == k1 || ur == k2 || ur == k3)) return;
         for (uint32_t q = cl.cell_start[c]; q < cl.cell_start[c + 1]; ++q) {
@@ -234,26 +247,61 @@ __global__ void k_host_init(int n_hosts, const int32_t* __restrict__ off, const 
     hb[h] = b;
 }
 
-// extents per host; a wavefront whose members share one host reduces first
+// extents per host: a thread folds 16 members of its block's chunk of 4096
+// (a partial result per host it meets), and a wavefront whose last partial
+// results share one host reduces them before the atomics
+constexpr int EXT_PER_THREAD = 16;
+
 __global__ __launch_bounds__(256) void k_host_extent(int64_t M, const int32_t* __restrict__ mem,
                                                      const int32_t* __restrict__ owner, const uint8_t* __restrict__ isb,
                                                      const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                                                      const uint32_t* __restrict__ qz, const float* __restrict__ vx,
                                                      const float* __restrict__ vy, const float* __restrict__ vz,
                                                      int gb, HostBox* __restrict__ hb) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * (256 * EXT_PER_THREAD) + threadIdx.x;
     int h = -1;
-    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-    unsigned vlo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, vhi[3] = {0u, 0u, 0u};
-    if (k < M) {
-        h = owner[k];
+    int lo[3], hi[3];
+    unsigned vlo[3], vhi[3];
+    auto reset = [&]() __attribute__((always_inline)) {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = INT_MAX;
+            hi[d] = INT_MIN;
+            vlo[d] = 0xFFFFFFFFu;
+            vhi[d] = 0u;
+        }
+    };
+    auto flush = [&](int hh) __attribute__((always_inline)) {
+        HostBox* b = hb + hh;
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&b->umin[d], lo[d]);
+            atomicMax(&b->umax[d], hi[d]);
+            atomicMin(&b->vmin[d], vlo[d]);
+            atomicMax(&b->vmax[d], vhi[d]);
+        }
+    };
+    reset();
+    for (int r = 0; r < EXT_PER_THREAD; ++r) {
+        const int64_t k = base + (int64_t)r * 256;
+        if (k >= M) break;
+        const int hk = owner[k];
+        if (hk != h) {
+            if (h >= 0) flush(h);
+            reset();
+            h = hk;
+        }
         const int i = mem[k];
         const int q[3] = {(int)qx[i], (int)qy[i], (int)qz[i]};
-        for (int d = 0; d < 3; ++d) lo[d] = hi[d] = min_image(q[d] - hb[h].ref[d], gb);
+        for (int d = 0; d < 3; ++d) {
+            const int u = min_image(q[d] - hb[h].ref[d], gb);
+            lo[d] = min(lo[d], u);
+            hi[d] = max(hi[d], u);
+        }
         if (!isb[i]) {
-            vlo[0] = vhi[0] = f2o(vx[i]);
-            vlo[1] = vhi[1] = f2o(vy[i]);
-            vlo[2] = vhi[2] = f2o(vz[i]);
+            const unsigned o[3] = {f2o(vx[i]), f2o(vy[i]), f2o(vz[i])};
+            for (int d = 0; d < 3; ++d) {
+                vlo[d] = min(vlo[d], o[d]);
+                vhi[d] = max(vhi[d], o[d]);
+            }
         }
     }
     const int h0 = __shfl(h, 0, 64);
@@ -265,16 +313,9 @@ __global__ __launch_bounds__(256) void k_host_extent(int64_t M, const int32_t* _
                 vlo[d] = min(vlo[d], (unsigned)__shfl_xor((int)vlo[d], o, 64));
                 vhi[d] = max(vhi[d], (unsigned)__shfl_xor((int)vhi[d], o, 64));
             }
-        if (lane_id() != 0) return;
-    } else if (h < 0) {
-        return;
-    }
-    HostBox* b = hb + h;
-    for (int d = 0; d < 3; ++d) {
-        atomicMin(&b->umin[d], lo[d]);
-        atomicMax(&b->umax[d], hi[d]);
-        atomicMin(&b->vmin[d], vlo[d]);
-        atomicMax(&b->vmax[d], vhi[d]);
+        if (lane_id() == 0) flush(h);
+    } else if (h >= 0) {
+        flush(h);
     }
 }
 
@@ -297,19 +338,11 @@ __device__ __forceinline__ void scaled6(const HostBox& b, uint32_t x, uint32_t y
     o[5] = vz * iv;
 }
 
-// Morton key of the compacted dark matter: host in the high bits, then
-// mbits interleaved bits of each scaled coordinate over the host's box
-__global__ void k_key6(int64_t ndm, const uint32_t* __restrict__ cx, const uint32_t* __restrict__ cy,
-                       const uint32_t* __restrict__ cz, const int32_t* __restrict__ dmi,
-                       const int32_t* __restrict__ dmh, const float* __restrict__ vx, const float* __restrict__ vy,
-                       const float* __restrict__ vz, const HostBox* __restrict__ hb, int gb, float ix, float iv,
-                       int mbits, uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ndm) return;
-    const int h = dmh[j], i = dmi[j];
-    const HostBox b = hb[h];
-    float y[6], lo[6], ext = 0.f;
-    scaled6(b, cx[j], cy[j], cz[j], vx[i], vy[i], vz[i], gb, ix, iv, y);
+// Morton key: host in the high bits, then mbits interleaved bits of each
+// scaled coordinate over the host's box (clamped: baryons may lie outside
+// the dark matter's velocity range)
+__device__ __forceinline__ uint64_t key6(const HostBox& b, int h, const float* y, float ix, float iv, int mbits) {
+    float lo[6], ext = 0.f;
     for (int d = 0; d < 3; ++d) {
         lo[d] = (float)b.umin[d] * ix;
         ext = fmaxf(ext, (float)b.umax[d] * ix - lo[d]);
@@ -323,8 +356,40 @@ __global__ void k_key6(int64_t ndm, const uint32_t* __restrict__ cx, const uint3
     uint64_t m = 0;
     for (int bit = mbits - 1; bit >= 0; --bit)
         for (int d = 0; d < 6; ++d) m = (m << 1) | ((c[d] >> bit) & 1u);
-    key[j] = ((uint64_t)h << (6 * mbits)) | m;
+    return ((uint64_t)h << (6 * mbits)) | m;
+}
+
+// keys of the compacted dark matter
+__global__ void k_key6(int64_t ndm, const uint32_t* __restrict__ cx, const uint32_t* __restrict__ cy,
+                       const uint32_t* __restrict__ cz, const int32_t* __restrict__ dmi,
+                       const int32_t* __restrict__ dmh, const float* __restrict__ vx, const float* __restrict__ vy,
+                       const float* __restrict__ vz, const HostBox* __restrict__ hb, int gb, float ix, float iv,
+                       int mbits, uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ndm) return;
+    const int h = dmh[j], i = dmi[j];
+    const HostBox b = hb[h];
+    float y[6];
+    scaled6(b, cx[j], cy[j], cz[j], vx[i], vy[i], vz[i], gb, ix, iv, y);
+    key[j] = key6(b, h, y, ix, iv, mbits);
     val[j] = (uint32_t)j;
+}
+
+// keys of the baryons (member positions in blist), so that neighbouring
+// wavefronts search neighbouring parts of the tree
+__global__ void k_bkey6(int64_t nb, const int32_t* __restrict__ blist, const int32_t* __restrict__ mem,
+                        const int32_t* __restrict__ owner, const uint32_t* __restrict__ qx,
+                        const uint32_t* __restrict__ qy, const uint32_t* __restrict__ qz, const float* __restrict__ vx,
+                        const float* __restrict__ vy, const float* __restrict__ vz, const HostBox* __restrict__ hb,
+                        int gb, float ix, float iv, int mbits, uint64_t* __restrict__ key) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    const int k = blist[t];
+    const int h = owner[k], i = mem[k];
+    const HostBox b = hb[h];
+    float y[6];
+    scaled6(b, qx[i], qy[i], qz[i], vx[i], vy[i], vz[i], gb, ix, iv, y);
+    key[t] = key6(b, h, y, ix, iv, mbits);
 }
 
 __global__ void k_gather6(int64_t ndm, const uint32_t* __restrict__ val, const uint32_t* __restrict__ cx,
@@ -705,8 +770,8 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     VR_WS(hbox, ctx, HostBox, WS_D0, n_hosts);
     hipLaunchKernelGGL(k_host_init, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, host_offsets,
                        host_members, p->qx, p->qy, p->qz, hbox);
-    hipLaunchKernelGGL(k_host_extent, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, owner, is_baryon,
-                       p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, gb, hbox);
+    hipLaunchKernelGGL(k_host_extent, dim3(grid_for(M, 256 * EXT_PER_THREAD)), dim3(256), 0, st, M, host_members,
+                       owner, is_baryon, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, gb, hbox);
     hipLaunchKernelGGL(k_host_ok, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, gb, hbox);
     VR_LAUNCH_CHECK(ctx);
     // tree order: by host, then along the Morton curve
@@ -783,6 +848,15 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     }
     VR_WS(blist, ctx, int32_t, WS_A3, nb + 1);
     hipLaunchKernelGGL(k_baryon_list, dim3(grid_for(M, 256)), dim3(256), 0, st, M, flag, pos, blist);
+    VR_LAUNCH_CHECK(ctx);
+    if (nb > 1) {
+        VR_WS(bkey, ctx, uint64_t, WS_D2, nb);
+        hipLaunchKernelGGL(k_bkey6, dim3(grid_for(nb, 256)), dim3(256), 0, st, nb, blist, host_members, owner, p->qx,
+                           p->qy, p->qz, p->vx, p->vy, p->vz, hbox, gb, ix, iv, mbits, bkey);
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = sort_pairs_u64(ctx, bkey, reinterpret_cast<uint32_t*>(blist), nb, hbits + 6 * mbits, st)))
+            return rc;
+    }
     hipLaunchKernelGGL(k_assign_dm, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, is_baryon, sub, 0, out);
     VR_LAUNCH_CHECK(ctx);
     if (nb > 0) {
