@@ -486,7 +486,14 @@ __global__ void k_baryon_list(int64_t M, const uint32_t* __restrict__ dmflag, co
     if (k < M && !dmflag[k]) blist[k - pos[k]] = (int32_t)k;
 }
 
-// one wavefront per baryon
+// One wavefront per 64 consecutive baryons of the tree-ordered list.  The
+// lanes of one host walk its tree together: a node is opened when its box
+// may hold a closer member for any of them, and each lane keeps its own
+// best.  Leaves are staged in LDS; a lane scores a member exactly only when
+// a float distance, with a margin for the rounding of the scaled
+// coordinates, does not already rule it out.
+constexpr int T6_WAVES = 4;
+
 __global__ __launch_bounds__(256) void k_assign6(int64_t nb, const int32_t* __restrict__ blist,
                                                  const int32_t* __restrict__ mem, const int32_t* __restrict__ owner,
                                                  const int32_t* __restrict__ sub, const uint32_t* __restrict__ qx,
@@ -494,110 +501,182 @@ __global__ __launch_bounds__(256) void k_assign6(int64_t nb, const int32_t* __re
                                                  const float* __restrict__ vx, const float* __restrict__ vy,
                                                  const float* __restrict__ vz, Tree6 t, int gb, double ell2,
                                                  double sv2, float ix, float iv, int32_t* __restrict__ out) {
-    __shared__ int2 stack[4][T6_MAX_DEPTH * T6_FAN];
+    __shared__ int stack[T6_WAVES][T6_MAX_DEPTH * T6_FAN];
+    __shared__ float4 sya[T6_WAVES][T6_FAN], syb[T6_WAVES][T6_FAN], svl[T6_WAVES][T6_FAN];
+    __shared__ uint4 sqp[T6_WAVES][T6_FAN];
     const int w = (int)(threadIdx.x >> 6);
     const int lane = (int)lane_id();
-    const int64_t bi = (int64_t)blockIdx.x * 4 + w;
-    if (bi >= nb) return;
-    const int k = blist[bi];
-    const int i = mem[k], h = owner[k];
-    const int d0 = t.lvl[h], d1 = t.lvl[h + 1];
-    if (d0 == d1) {  // no dark matter in this host
-        if (lane == 0) out[i] = -1;
-        return;
+    const int64_t wave = (int64_t)blockIdx.x * T6_WAVES + w;
+    if (wave * 64 >= nb) return;
+    const int64_t bi = wave * 64 + lane;
+    const bool valid = bi < nb;
+    int i = 0, h = -1, px = 0, py = 0, pz = 0;
+    float fvx = 0.f, fvy = 0.f, fvz = 0.f;
+    if (valid) {
+        const int k = blist[bi];
+        i = mem[k];
+        h = owner[k];
+        px = (int)qx[i];
+        py = (int)qy[i];
+        pz = (int)qz[i];
+        fvx = vx[i];
+        fvy = vy[i];
+        fvz = vz[i];
     }
-    const int px = (int)qx[i], py = (int)qy[i], pz = (int)qz[i];
-    const double bx = (double)vx[i], by = (double)vy[i], bz = (double)vz[i];
+    const double bx = (double)fvx, by = (double)fvy, bz = (double)fvz;
     Best bst{INFINITY, 0x7FFFFFFF};
-    // members [p0, p1) of the tree order, scored exactly, a lane each
-    auto leaf = [&](int p0, int p1) __attribute__((always_inline)) {
+    int* stk = stack[w];
+    // members [p0, p1) of the tree order into LDS, a lane each
+    auto stage = [&](int p0, int p1, const HostBox& hb) __attribute__((always_inline)) {
         const int p = p0 + lane;
-        double d = INFINITY;
-        int j = 0x7FFFFFFF;
         if (p < p1) {
-            const int ddx = min_image((int)t.sx[p] - px, gb);
-            const int ddy = min_image((int)t.sy[p] - py, gb);
-            const int ddz = min_image((int)t.sz[p] - pz, gb);
-            const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
-            const double ax = bx - (double)t.svx[p], ay = by - (double)t.svy[p], az = bz - (double)t.svz[p];
-            d = d2 / ell2 + (ax * ax + ay * ay + az * az) / sv2;
-            j = t.sj[p];
+            const uint32_t x = t.sx[p], yy = t.sy[p], z = t.sz[p];
+            const float a = t.svx[p], b = t.svy[p], c = t.svz[p];
+            float y6[6];
+            scaled6(hb, x, yy, z, a, b, c, gb, ix, iv, y6);
+            sya[w][lane] = make_float4(y6[0], y6[1], y6[2], y6[3]);
+            syb[w][lane] = make_float4(y6[4], y6[5], 0.f, 0.f);
+            sqp[w][lane] = make_uint4(x, yy, z, (uint32_t)t.sj[p]);
+            svl[w][lane] = make_float4(a, b, c, 0.f);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    // exact D^2 of staged member q, as a brute-force scan computes it
+    auto exact = [&](int q) __attribute__((always_inline)) {
+        const uint4 e = sqp[w][q];
+        const float4 v = svl[w][q];
+        const int ddx = min_image((int)e.x - px, gb);
+        const int ddy = min_image((int)e.y - py, gb);
+        const int ddz = min_image((int)e.z - pz, gb);
+        const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+        const double ax = bx - (double)v.x, ay = by - (double)v.y, az = bz - (double)v.z;
+        consider(bst, d2 / ell2 + (ax * ax + ay * ay + az * az) / sv2, (int)e.w);
+    };
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int hh = __builtin_amdgcn_readfirstlane(__shfl(h, __builtin_ctzll(pending), 64));
+        const bool mine = valid && h == hh;
+        pending &= ~__ballot(mine);
+        const int d0 = t.lvl[hh], d1 = t.lvl[hh + 1];
+        if (d0 == d1) continue;  // no dark matter in this host
+        const HostBox hb = t.hbox[hh];
+        if (!hb.ok) {
+            // a host wider than half the box: all of its dark matter
+            for (int p0 = d0; p0 < d1; p0 += T6_FAN) {
+                const int p1 = min(p0 + T6_FAN, d1);
+                stage(p0, p1, hb);
+                if (mine)
+                    for (int q = 0; q < p1 - p0; ++q) exact(q);
+                __builtin_amdgcn_wave_barrier();
+            }
+            continue;
+        }
+        float y[6];
+        scaled6(hb, (uint32_t)px, (uint32_t)py, (uint32_t)pz, fvx, fvy, fvz, gb, ix, iv, y);
+        // the packet's box, and the margins for the rounding of the scaled
+        // coordinates (a few ulps of the largest of them)
+        float qlo[6], qhi[6], amax = 0.f;
+        for (int d = 0; d < 6; ++d) {
+            qlo[d] = mine ? y[d] : INFINITY;
+            qhi[d] = mine ? y[d] : -INFINITY;
+            if (mine) amax = fmaxf(amax, fabsf(y[d]));
         }
         for (int o = 32; o; o >>= 1) {
-            const double od = __shfl_xor(d, o, 64);
-            const int oj = __shfl_xor(j, o, 64);
-            if (od < d || (od == d && oj < j)) {
-                d = od;
-                j = oj;
+            for (int d = 0; d < 6; ++d) {
+                qlo[d] = fminf(qlo[d], __shfl_xor(qlo[d], o, 64));
+                qhi[d] = fmaxf(qhi[d], __shfl_xor(qhi[d], o, 64));
             }
+            amax = fmaxf(amax, __shfl_xor(amax, o, 64));
         }
-        consider(bst, d, j);
-    };
-    const HostBox hb = t.hbox[h];
-    if (!hb.ok) {
-        // a host wider than half the box: all of its dark matter
-        for (int p0 = d0; p0 < d1; p0 += T6_FAN) leaf(p0, min(p0 + T6_FAN, d1));
-    } else {
-        float y[6];
-        scaled6(hb, (uint32_t)px, (uint32_t)py, (uint32_t)pz, vx[i], vy[i], vz[i], gb, ix, iv, y);
         const int top = t.depth;
-        const int root = t.lvl[(int64_t)top * t.H1 + h];
-        // every lower bound is shrunk by a margin that covers the rounding
-        // of the scaled coordinates (a few ulps of the largest of them)
-        float amax = 0.f;
+        const int root = t.lvl[(int64_t)top * t.H1 + hh];
         {
             const float* rb = t.box + (int64_t)(t.base[top] + root) * 12;
             for (int d = 0; d < 12; ++d) amax = fmaxf(amax, fabsf(rb[d]));
-            for (int d = 0; d < 6; ++d) amax = fmaxf(amax, fabsf(y[d]));
         }
         const float E = amax * 0x1p-19f;
-        int2* stk = stack[w];
-        if (lane == 0) stk[0] = make_int2((top << T6_LEV_SHIFT) | root, __float_as_int(0.f));
+        const double dlt = 5.0 * (double)amax * 0x1p-22;
+        // a float squared distance above thr rules a member out
+        auto thr_of = [&]() __attribute__((always_inline)) -> float {
+            if (!(bst.d < INFINITY)) return INFINITY;
+            const double r = sqrt(bst.d) * (1.0 + 0x1p-40) + dlt;
+            return (float)(r * r * (1.0 + 0x1p-19));
+        };
+        float thr = thr_of();
+        if (lane == 0) stk[0] = (top << T6_LEV_SHIFT) | root;
         __builtin_amdgcn_wave_barrier();
         int sp = 1;
         while (sp > 0) {
             --sp;
-            const int2 e = stk[sp];
-            if ((double)__int_as_float(e.y) > bst.d) continue;
-            const int lev = e.x >> T6_LEV_SHIFT;
-            const int node = e.x & ((1 << T6_LEV_SHIFT) - 1);
+            const int e = __builtin_amdgcn_readfirstlane(stk[sp]);
+            const int lev = e >> T6_LEV_SHIFT;
+            const int node = e & ((1 << T6_LEV_SHIFT) - 1);
+            const float* nbx = t.box + (int64_t)(t.base[lev] + node) * 12;
+            float lb = 0.f;
+            for (int d = 0; d < 6; ++d) {
+                const float g = fmaxf(fmaxf(nbx[d] - y[d], y[d] - nbx[6 + d]) - E, 0.f);
+                lb += g * g;
+            }
+            lb *= 1.f - 0x1p-20f;
+            const bool need = mine && (double)lb <= bst.d;
+            if (!__ballot(need)) continue;
             const int32_t* L = t.lvl + (int64_t)lev * t.H1;
             const int32_t* C = t.lvl + (int64_t)(lev - 1) * t.H1;
-            const int c0 = C[h] + T6_FAN * (node - L[h]);
-            const int c1 = min(c0 + T6_FAN, C[h + 1]);
+            const int c0 = C[hh] + T6_FAN * (node - L[hh]);
+            const int c1 = min(c0 + T6_FAN, C[hh + 1]);
             if (lev == 1) {
-                leaf(c0, c1);
+                stage(c0, c1, hb);
+                if (need) {
+                    for (int q = 0; q < c1 - c0; ++q) {
+                        const float4 A = sya[w][q], B = syb[w][q];
+                        const float e0 = y[0] - A.x, e1 = y[1] - A.y, e2 = y[2] - A.z;
+                        const float e3 = y[3] - A.w, e4 = y[4] - B.x, e5 = y[5] - B.y;
+                        const float dF = e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3 + e4 * e4 + e5 * e5;
+                        if (dF <= thr) {
+                            exact(q);
+                            thr = thr_of();
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
                 continue;
             }
+            // children within reach of a lane that opened this node
+            double mb = need ? bst.d : 0.0;
+            for (int o = 32; o; o >>= 1) mb = fmax(mb, __shfl_xor(mb, o, 64));
             const int c = c0 + lane;
-            float lb = INFINITY;
+            bool keep = false;
+            float key = INFINITY;
             if (c < c1) {
                 const float* cb = t.box + (int64_t)(t.base[lev - 1] + c) * 12;
-                lb = 0.f;
+                float bb = 0.f, cd = 0.f;
                 for (int d = 0; d < 6; ++d) {
-                    const float g = fmaxf(fmaxf(cb[d] - y[d], y[d] - cb[6 + d]) - E, 0.f);
-                    lb += g * g;
+                    const float lo = cb[d], hi = cb[6 + d];
+                    const float g = fmaxf(fmaxf(lo - qhi[d], qlo[d] - hi) - E, 0.f);
+                    bb += g * g;
+                    const float m = 0.5f * (qlo[d] + qhi[d]);
+                    const float gc = fmaxf(fmaxf(lo - m, m - hi), 0.f);
+                    cd += gc * gc;
                 }
-                lb *= 1.f - 0x1p-20f;
+                keep = (double)(bb * (1.f - 0x1p-20f)) <= mb;
+                key = cd;
             }
-            const bool cand = c < c1 && (double)lb <= bst.d;
-            const uint64_t cm = __ballot(cand);
-            if (!cm) continue;
-            float mn = cand ? lb : INFINITY;
+            const uint64_t km = __ballot(keep);
+            if (!km) continue;
+            float mn = keep ? key : INFINITY;
             for (int o = 32; o; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
-            const uint64_t near = __ballot(cand && lb == mn);
-            const int first = __builtin_ctzll(near);
-            const uint64_t others = cm & ~(1ull << first);
+            const int first = __builtin_ctzll(__ballot(keep && key == mn));
+            const uint64_t others = km & ~(1ull << first);
             const int no = __popcll(others);
-            const int2 ent = make_int2(((lev - 1) << T6_LEV_SHIFT) | c, __float_as_int(lb));
-            // the nearest child goes on top, to be opened next
-            if (cand && lane != first) stk[sp + __popcll(others & ((1ull << lane) - 1ull))] = ent;
+            const int ent = ((lev - 1) << T6_LEV_SHIFT) | c;
+            // the child nearest the packet's centre goes on top, opened next
+            if (keep && lane != first) stk[sp + __popcll(others & ((1ull << lane) - 1ull))] = ent;
             if (lane == first) stk[sp + no] = ent;
             sp += no + 1;
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (lane == 0) out[i] = bst.j == 0x7FFFFFFF ? -1 : sub[bst.j];
+    if (valid) out[i] = bst.j == 0x7FFFFFFF ? -1 : sub[bst.j];
 }
 
 __global__ void k_dm_offsets(int n_hosts, int64_t M, const int32_t* __restrict__ off, const uint32_t* __restrict__ pos,
@@ -861,7 +940,8 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     VR_LAUNCH_CHECK(ctx);
     if (nb > 0) {
         VR_TIMED(ctx, "assign_baryons", st, nb,
-                 hipLaunchKernelGGL(k_assign6, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st, nb, blist,
+                 hipLaunchKernelGGL(k_assign6, dim3((unsigned)((nb + 64 * T6_WAVES - 1) / (64 * T6_WAVES))),
+                                    dim3(64 * T6_WAVES), 0, st, nb, blist,
                                     host_members, owner, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, t, gb, u * u,
                                     sigma_v * sigma_v, ix, iv, out));
         VR_LAUNCH_CHECK(ctx);
