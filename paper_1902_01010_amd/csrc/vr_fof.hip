@@ -26,12 +26,11 @@ __global__ void k_quantize(int64_t n, const float* __restrict__ x, const float* 
 }
 
 __global__ void k_cellkey(int64_t n, const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
-                          const uint32_t* __restrict__ qz, int s, int b, uint32_t* __restrict__ key,
+                          const uint32_t* __restrict__ qz, int s, int b, ckey_t* __restrict__ key,
                           uint32_t* __restrict__ idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t cx = qx[i] >> s, cy = qy[i] >> s, cz = qz[i] >> s;
-    key[i] = (cz << (2 * b)) | (cy << b) | cx;
+    key[i] = cell_key(qx[i] >> s, qy[i] >> s, qz[i] >> s, b);
     idx[i] = (uint32_t)i;
 }
 
@@ -46,14 +45,14 @@ __global__ void k_gather3(int64_t n, const uint32_t* __restrict__ idx, const uin
     sz[p] = qz[i];
 }
 
-__global__ void k_cell_flags(int64_t n, const uint32_t* __restrict__ key, uint32_t* __restrict__ flag) {
+__global__ void k_cell_flags(int64_t n, const ckey_t* __restrict__ key, uint32_t* __restrict__ flag) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
 }
 
-__global__ void k_cell_starts(int64_t n, const uint32_t* __restrict__ key, const uint32_t* __restrict__ scan,
-                              uint32_t* __restrict__ cell_start, uint32_t* __restrict__ hkeys,
+__global__ void k_cell_starts(int64_t n, const ckey_t* __restrict__ key, const uint32_t* __restrict__ scan,
+                              uint32_t* __restrict__ cell_start, ckey_t* __restrict__ hkeys,
                               uint32_t* __restrict__ hvals, uint32_t hmask) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -63,10 +62,11 @@ __global__ void k_cell_starts(int64_t n, const uint32_t* __restrict__ key, const
     if (start) {
         const uint32_t c = scan[p];
         cell_start[c] = (uint32_t)p;
-        const uint32_t k = key[p];
-        uint32_t h = hash32(k, hmask);
+        const ckey_t k = key[p];
+        uint32_t h = hash_key(k, hmask);
         for (;;) {
-            uint32_t old = atomicCAS(&hkeys[h], EMPTY, k);
+            const ckey_t old = atomicCAS((unsigned long long*)&hkeys[h], (unsigned long long)EMPTY,
+                                         (unsigned long long)k);
             if (old == EMPTY) { hvals[h] = c; break; }
             h = (h + 1) & hmask;
         }
@@ -78,19 +78,19 @@ __global__ void k_cell_starts(int64_t n, const uint32_t* __restrict__ key, const
 // (when the grid has at least 3 cells per side), otherwise all 26 distinct
 // neighbours with the partner restricted to later positions.
 template <bool HALF>
-__global__ __launch_bounds__(256) void k_link3d(int64_t n, const uint32_t* __restrict__ key,
+__global__ __launch_bounds__(256) void k_link3d(int64_t n, const ckey_t* __restrict__ key,
                                                 const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                 const uint32_t* __restrict__ sz, const uint32_t* __restrict__ cell_start,
-                                                const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                                const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                                 uint32_t hmask, int b, int gb, double ell2, int* parent) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const uint32_t k = key[p];
+    const ckey_t k = key[p];
     const int nc = 1 << b;
-    const int cx = k & (nc - 1), cy = (k >> b) & (nc - 1), cz = k >> (2 * b);
+    const int cx = (int)(k & (nc - 1)), cy = (int)((k >> b) & (nc - 1)), cz = (int)(k >> (2 * b));
     const int px = (int)sx[p], py = (int)sy[p], pz = (int)sz[p];
     constexpr bool half = HALF;
-    uint32_t seen[HALF ? 1 : 27];
+    ckey_t seen[HALF ? 1 : 27];
     int nseen = 0;
     for (int o = 0; o < 27; ++o) {
         const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_link3d(int64_t n, const uint32_t* __res
         const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
         const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
         const uint32_t nz = (uint32_t)((cz + dz + nc) & (nc - 1));
-        const uint32_t nk = (nz << (2 * b)) | (ny << b) | nx;
+        const ckey_t nk = cell_key(nx, ny, nz, b);
         if constexpr (!HALF) {
             bool dup = false;
             for (int t = 0; t < nseen; ++t) dup |= seen[t] == nk;
@@ -262,7 +262,7 @@ namespace vr {
 int build_cell_list(vr_ctx* ctx, int64_t n, const uint32_t* qx, const uint32_t* qy, const uint32_t* qz, int gb,
                     int s, CellList& cl, hipStream_t st) {
     const int b = gb - s;
-    VR_WS(key, ctx, uint32_t, WS_A0, n);
+    VR_WS(key, ctx, ckey_t, WS_A0, n);
     VR_WS(idx, ctx, uint32_t, WS_A1, n);
     VR_WS(sx, ctx, uint32_t, WS_A2, n);
     VR_WS(sy, ctx, uint32_t, WS_A3, n);
@@ -271,7 +271,7 @@ int build_cell_list(vr_ctx* ctx, int64_t n, const uint32_t* qx, const uint32_t* 
     VR_WS(cstart, ctx, uint32_t, WS_A6, n + 1);
     hipLaunchKernelGGL(k_cellkey, dim3(grid_for(n, 256)), dim3(256), 0, st, n, qx, qy, qz, s, b, key, idx);
     VR_LAUNCH_CHECK(ctx);
-    int rc = sort_pairs_u32(ctx, key, idx, n, 3 * b, st);
+    int rc = sort_pairs_u64(ctx, key, idx, n, 3 * b, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(n, 256)), dim3(256), 0, st, n, idx, qx, qy, qz, sx, sy, sz);
     VR_LAUNCH_CHECK(ctx);
@@ -286,9 +286,9 @@ int build_cell_list(vr_ctx* ctx, int64_t n, const uint32_t* qx, const uint32_t* 
     if (rc) return rc;
     uint32_t hsize = 1024;
     while (hsize < 2u * ncell) hsize <<= 1;
-    VR_WS(hkeys, ctx, uint32_t, WS_A7, hsize);
+    VR_WS(hkeys, ctx, ckey_t, WS_A7, hsize);
     VR_WS(hvals, ctx, uint32_t, WS_A8, hsize);
-    rc = fill_u32(ctx, hkeys, EMPTY, hsize, st);
+    rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hkeys), 0xFFFFFFFFu, 2 * (int64_t)hsize, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_cell_starts, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, flag, cstart, hkeys, hvals,
                        hsize - 1);

@@ -180,20 +180,20 @@ struct SubLink {
 
 // PAPER = false: Eq. fof6d; true: Eq. linkingcriteria (sub.* used, ellv not).
 template <bool HALF, bool PAPER>
-__global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __restrict__ key,
+__global__ __launch_bounds__(256) void k_link6d(int64_t np, const ckey_t* __restrict__ key,
                                                 const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                 const uint32_t* __restrict__ sz, const float* __restrict__ svx,
                                                 const float* __restrict__ svy, const float* __restrict__ svz,
                                                 const int32_t* __restrict__ shost, const double* __restrict__ ellv,
                                                 const uint32_t* __restrict__ cell_start,
-                                                const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                                const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                                 uint32_t hmask, int b, int gb, double ell2, int* parent,
                                                 unsigned xchunk, SubLink sub) {
     const int64_t p = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    const uint32_t k = key[p];
+    const ckey_t k = key[p];
     const int nc = 1 << b;
-    const int cx = k & (nc - 1), cy = (k >> b) & (nc - 1), cz = k >> (2 * b);
+    const int cx = (int)(k & (nc - 1)), cy = (int)((k >> b) & (nc - 1)), cz = (int)(k >> (2 * b));
     const int px = (int)sx[p], py = (int)sy[p], pz = (int)sz[p];
     const double vpx = (double)svx[p], vpy = (double)svy[p], vpz = (double)svz[p];
     const int hp = shost[p];
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
     // from the divided form by a few ulps, so only t within 1e-9 of 1 needs
     // the divided form itself
     const double rl2 = 1.0 / ell2, rv2 = 1.0 / ev2;
-    uint32_t seen[HALF ? 1 : 27];
+    ckey_t seen[HALF ? 1 : 27];
     int nseen = 0;
     for (int o = 0; o < 27; ++o) {
         const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const uint32_t* __re
         const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
         const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
         const uint32_t nz = (uint32_t)((cz + dz + nc) & (nc - 1));
-        const uint32_t nk = (nz << (2 * b)) | (ny << b) | nx;
+        const ckey_t nk = cell_key(nx, ny, nz, b);
         if constexpr (!HALF) {
             bool dup = false;
             for (int t = 0; t < nseen; ++t) dup |= seen[t] == nk;
@@ -292,14 +292,14 @@ __device__ __forceinline__ bool relaxed_link(const SubLink& sub, double up0, dou
 // Visits every participant q != p in the 27 cells around p's cell (each once)
 // that shares p's host, lies within ell2 and meets the relaxed criteria.
 template <class F>
-__device__ __forceinline__ void for_relaxed(int64_t p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ sx,
+__device__ __forceinline__ void for_relaxed(int64_t p, const ckey_t* __restrict__ key, const uint32_t* __restrict__ sx,
                                             const uint32_t* __restrict__ sy, const uint32_t* __restrict__ sz,
                                             const int32_t* __restrict__ shost, const uint32_t* __restrict__ cell_start,
-                                            const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                            const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                             uint32_t hmask, int b, int gb, double ell2, const SubLink& sub, F&& visit) {
-    const uint32_t k = key[p];
+    const ckey_t k = key[p];
     const int nc = 1 << b;
-    const int cx = k & (nc - 1), cy = (k >> b) & (nc - 1), cz = k >> (2 * b);
+    const int cx = (int)(k & (nc - 1)), cy = (int)((k >> b) & (nc - 1)), cz = (int)(k >> (2 * b));
     const int px = (int)sx[p], py = (int)sy[p], pz = (int)sz[p];
     const int hp = shost[p];
     const double up0 = sub.u0[p], up1 = sub.u1[p], up2 = sub.u2[p], sp = sub.s[p];
@@ -312,7 +312,7 @@ __device__ __forceinline__ void for_relaxed(int64_t p, const uint32_t* __restric
         const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
         const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
         const uint32_t nz = (uint32_t)((cz + dz + nc) & (nc - 1));
-        const uint32_t nk = (nz << (2 * b)) | (ny << b) | nx;
+        const ckey_t nk = cell_key(nx, ny, nz, b);
         if (nc < 3) {
             const uint32_t bit = 1u << (nx + 2 * ny + 4 * nz);
             if (seen & bit) continue;
@@ -334,10 +334,10 @@ __device__ __forceinline__ void for_relaxed(int64_t p, const uint32_t* __restric
 
 // One synchronous growth round: an untagged participant takes the smallest
 // tag among its relaxed neighbours tagged in the previous round.
-__global__ __launch_bounds__(256) void k_grow(int64_t np, const uint32_t* __restrict__ key,
+__global__ __launch_bounds__(256) void k_grow(int64_t np, const ckey_t* __restrict__ key,
                                               const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                               const uint32_t* __restrict__ sz, const int32_t* __restrict__ shost,
-                                              const uint32_t* __restrict__ cell_start, const uint32_t* __restrict__ hkeys,
+                                              const uint32_t* __restrict__ cell_start, const ckey_t* __restrict__ hkeys,
                                               const uint32_t* __restrict__ hvals, uint32_t hmask, int b, int gb,
                                               double ell2, SubLink sub, const int32_t* __restrict__ tin,
                                               int32_t* __restrict__ tout, int* __restrict__ changed) {
@@ -360,11 +360,11 @@ __global__ __launch_bounds__(256) void k_grow(int64_t np, const uint32_t* __rest
 // lower position): counted, or written as (lower tag, upper tag) keys with the
 // first-stage sizes of both groups.
 template <bool EMIT>
-__global__ __launch_bounds__(256) void k_cross(int64_t np, const uint32_t* __restrict__ key,
+__global__ __launch_bounds__(256) void k_cross(int64_t np, const ckey_t* __restrict__ key,
                                                const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                const uint32_t* __restrict__ sz, const int32_t* __restrict__ shost,
                                                const uint32_t* __restrict__ cell_start,
-                                               const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                               const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                                uint32_t hmask, int b, int gb, double ell2, SubLink sub,
                                                const int32_t* __restrict__ tag, const int* __restrict__ size,
                                                unsigned long long* __restrict__ count, int64_t cap,

@@ -5,22 +5,28 @@
 
 namespace vr {
 
-constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+// Cell keys hold z, y, x cell coordinates of b bits each (b up to 21).
+using ckey_t = uint64_t;
+constexpr ckey_t EMPTY = ~ckey_t(0);
 
-__device__ __forceinline__ uint32_t hash32(uint32_t k, uint32_t mask) {
-    k ^= k >> 16;
-    k *= 0x7feb352du;
-    k ^= k >> 15;
-    k *= 0x846ca68bu;
-    k ^= k >> 16;
-    return k & mask;
+__device__ __forceinline__ ckey_t cell_key(uint32_t x, uint32_t y, uint32_t z, int b) {
+    return ((ckey_t)z << (2 * b)) | ((ckey_t)y << b) | (ckey_t)x;
 }
 
-__device__ __forceinline__ int hash_find(const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
-                                         uint32_t hmask, uint32_t k) {
-    uint32_t h = hash32(k, hmask);
+__device__ __forceinline__ uint32_t hash_key(ckey_t k, uint32_t mask) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return (uint32_t)k & mask;
+}
+
+__device__ __forceinline__ int hash_find(const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                         uint32_t hmask, ckey_t k) {
+    uint32_t h = hash_key(k, hmask);
     for (;;) {
-        uint32_t kk = hkeys[h];
+        const ckey_t kk = hkeys[h];
         if (kk == k) return (int)hvals[h];
         if (kk == EMPTY) return -1;
         h = (h + 1) & hmask;
@@ -73,7 +79,10 @@ __device__ __forceinline__ void wave_atomic_min(int* base, int key, int val, boo
 // original indices, sorted coordinates, cell starts and an open-addressing
 // hash from occupied cell keys to cell numbers.
 struct CellList {
-    uint32_t *key, *idx, *sx, *sy, *sz, *cell_start, *hkeys, *hvals;
+    ckey_t* key;
+    uint32_t *idx, *sx, *sy, *sz, *cell_start;
+    ckey_t* hkeys;
+    uint32_t* hvals;
     uint32_t hmask;
     int64_t n_cells;
 };

@@ -62,7 +62,7 @@ __global__ void k_seed_dm(int64_t ndm, const int32_t* __restrict__ orig, const i
 // grid point lies within ellx; else the distinct ones among them.
 template <class F>
 __device__ __forceinline__ void cells27(int px, int py, int pz, int s, int b, double ell2,
-                                        const uint32_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                        const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                         uint32_t hmask, F&& visit) {
     const int nc = 1 << b;
     const int side = 1 << s;
@@ -88,7 +88,7 @@ __device__ __forceinline__ void cells27(int px, int py, int pz, int s, int b, do
         } else if (gap2(fx, dx) + gap2(fy, dy) + gap2(fz, dz) >= ell2) {
             continue;  // no member of that cell is closer than ellx
         }
-        const int c = hash_find(hkeys, hvals, hmask, (nz << (2 * b)) | (ny << b) | nx);
+        const int c = hash_find(hkeys, hvals, hmask, cell_key(nx, ny, nz, b));
         if (c >= 0) visit(c);
     }
 }
@@ -132,7 +132,14 @@ __global__ __launch_bounds__(256) void k_attach(int64_t n, const uint8_t* __rest
             const int ddz = min_image((int)cl.sz[q] - pz, gb);
             const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
             if (d2 < ell2) {
-                uf_union(parent, (int)i, r);
+                if (k0 < 0) {
+                    // the first component: the baryon hangs below its root.
+                    // Nothing ever links below a baryon, so only this
+                    // thread writes parent[i], and no root is contended.
+                    parent[i] = uf_find(parent, r);
+                } else {
+                    uf_union(parent, (int)i, r);  // a bridge: dark-matter roots meet
+                }
                 k3 = k2;
                 k2 = k1;
                 k1 = k0;
@@ -143,9 +150,27 @@ __global__ __launch_bounds__(256) void k_attach(int64_t n, const uint8_t* __rest
     });
 }
 
-__global__ void k_roots(int64_t n, int* parent, int32_t* __restrict__ label) {
+// Roots are dark matter (the smallest dark-matter index of the component);
+// a baryon hung below one may have a smaller index, so the label is the
+// smallest index over the component, found in three passes.
+__global__ void k_roots(int64_t n, int* parent, int32_t* __restrict__ label, int* __restrict__ low) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) label[i] = uf_find(parent, (int)i);
+    if (i >= n) return;
+    label[i] = uf_find(parent, (int)i);
+    low[i] = (int)i;
+}
+
+__global__ void k_low(int64_t n, const uint8_t* __restrict__ isb, const int32_t* __restrict__ label,
+                      int* __restrict__ low) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !isb[i]) return;
+    const int r = label[i];
+    if (r != (int)i && (int)i < low[r]) atomicMin(&low[r], (int)i);
+}
+
+__global__ void k_low_label(int64_t n, const int* __restrict__ low, int32_t* __restrict__ label) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) label[i] = low[label[i]];
 }
 
 // ---- baryon assignment -----------------------------------------------------
@@ -791,7 +816,10 @@ extern "C" int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, cons
             VR_LAUNCH_CHECK(ctx);
         }
     }
-    hipLaunchKernelGGL(k_roots, dim3(grid_for(n, 256)), dim3(256), 0, st, n, parent, label);
+    VR_WS(low, ctx, int, WS_D3, n);
+    hipLaunchKernelGGL(k_roots, dim3(grid_for(n, 256)), dim3(256), 0, st, n, parent, label, low);
+    hipLaunchKernelGGL(k_low, dim3(grid_for(n, 256)), dim3(256), 0, st, n, is_baryon, label, low);
+    hipLaunchKernelGGL(k_low_label, dim3(grid_for(n, 256)), dim3(256), 0, st, n, low, label);
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }

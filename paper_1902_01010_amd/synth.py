@@ -234,7 +234,7 @@ def cosmo_box(seed=2, n_side=256, box=None, halo_frac=0.45, sub_frac=0.10, n_max
     return _finish("cosmo_box", rng, pos, vel, box, None, m_p, params, meta, extra=dict(component=comp))
 
 
-def two_species(seed=5, n_side=256, star_per_halo_dm=0.662, disc_frac=0.7, star_mass=0.1):
+def two_species(seed=5, n_side=256, star_per_halo_dm=0.662, disc_frac=0.7, star_mass=0.1, dm=None):
     """Dark matter of cosmo_box(seed, n_side) plus star particles of mass
     star_mass m_p in its halos: per halo round(star_per_halo_dm N) stars, a
     fraction disc_frac in an exponential disc (radial scale 0.03 r200,
@@ -242,8 +242,10 @@ def two_species(seed=5, n_side=256, star_per_halo_dm=0.662, disc_frac=0.7, star_
     dispersion) and the rest a stellar halo on the halo's NFW profile with
     dispersion 0.8 sigma_host; stars move with the halo's bulk velocity.
     512^3 with the default ratio gives the 40M stars of that configuration.
-    meta["is_baryon"] flags the stars; masses are per particle."""
-    dm = cosmo_box(seed=seed, n_side=n_side)
+    meta["is_baryon"] flags the stars; masses are per particle.  dm, when
+    given, is that cosmo_box already generated."""
+    if dm is None:
+        dm = cosmo_box(seed=seed, n_side=n_side)
     rng = np.random.default_rng(seed + 1000)
     H = dm.meta["halos"]
     m_p = dm.meta["m_p"]
