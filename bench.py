@@ -233,6 +233,9 @@ def main():
     ap.add_argument("--species", action="store_true",
                     help="two species: the box's dark matter plus stars (0.662 per halo particle, 0.1 m_p) in the "
                          "DM+Baryons mode (not the headline path)")
+    ap.add_argument("--levels", type=int, default=1,
+                    help="levels of the substructure search: bound substructures of >= 256 members searched again "
+                         "(not the headline path)")
     ap.add_argument("--n-se", type=int, default=0, help="spatial neighbours (0 = the workload's 32)")
     ap.add_argument("--n-v", type=int, default=0, help="velocity neighbours (0 = the workload's 8)")
     ap.add_argument("--workload", choices=("box", "unbind"), default="box",
@@ -264,6 +267,8 @@ def main():
         sys.exit("--linker paper needs --ell (its first criterion thresholds L)")
     if args.n_se:
         prm = dataclasses.replace(prm, n_se=args.n_se)
+    if args.levels > 1:
+        prm = dataclasses.replace(prm, levels=args.levels)
     if args.n_v:
         prm = dataclasses.replace(prm, n_v=args.n_v)
     ctx = vr.Context(0)
@@ -337,6 +342,10 @@ def main():
     if ub is not None:
         summary["bound_particles"] = int(ub["bound"].sum().item())
         summary["max_unbind_passes"] = int(ub["iters"].max().item())
+    if out.get("levels"):
+        summary["deeper_levels"] = [{"hosts": lv["n_hosts"], "candidates": lv["n_candidates"],
+                                     "bound": int(lv["unbind"]["bound"].sum().item()) if lv["unbind"] else 0}
+                                    for lv in out["levels"]]
 
     rec = {"metric": METRIC, "path": path, "value": round(headline, 1),
            "unit": "particles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -352,6 +361,7 @@ def main():
                       "outliers": f"L >= {prm.ell_th:g}, cleaned (beta_L {prm.beta_ell:g})" if prm.use_ell
                       else f"R >= {prm.R_threshold:g}",
                       "linker": "speed ratio + opening angle" if prm.linker == "paper" else "6D FOF",
+                      "levels": prm.levels,
                       "parallelism": "1 GPU", "launch_knobs": knobs},
            "roofline": roofline, "kernels": kernels, "summary": summary,
            "exact": {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3)}, "surrogate": sur}

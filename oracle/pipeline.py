@@ -38,12 +38,41 @@ def run(w, prm, timings=None, is_baryon=None):
                n_hosts=nh)
     if nh == 0:
         return out
-    hoff_all, hmem_all = hoff, hmem
+    species = None
     if is_baryon is not None:
         # the substructure search runs on the hosts' dark matter
+        species = (hoff, hmem, is_baryon)
         keep = is_baryon[hmem] == 0
         hmem = hmem[keep]
         hoff = np.r_[0, np.cumsum(np.add.reduceat(keep, hoff[:-1]))].astype(np.int32)
+    res = search(P, group_of, nh, hoff, hmem, prm, tick, species)
+    out.update(res)
+    # the activity chart of the substructure search (Sec. 2.2): substructures
+    # with enough bound members are searched again as hosts, level by level
+    out["levels"] = []
+    for _lev in range(2, getattr(prm, "levels", 1) + 1):
+        if res["unbind"] is None:
+            break
+        lb = np.where(res["unbind"]["bound"] > 0, res["label6"], -1).astype(np.int32)
+        nh2, g2, off2, mem2 = ref.groups(lb, prm.host_min)
+        if nh2 == 0:
+            break
+        res = search(P, g2, nh2, off2, mem2, prm, None, None)
+        res.update(n_hosts=nh2, host_group_of=g2, host_members=mem2, host_offsets=off2)
+        out["levels"].append(res)
+    return out
+
+
+def search(P, group_of, nh, hoff, hmem, prm, tick=None, species=None):
+    """One level of the substructure search (Sec. 2.2) over the hosts
+    [0, nh) of group_of, members hoff/hmem: background by cells, R, the
+    outliers linked, candidates unbound; species = (host offsets and members
+    over both species, is_baryon) adds the baryon assignment (Sec. 2.4)."""
+    import time
+    if tick is None:
+        def tick(name, t0):
+            return time.perf_counter()
+    t = time.perf_counter()
     cm = ref.cell_moments(P, hoff, hmem)
     t = tick("cells", t)
     R = ref.local_vdensity(P, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
@@ -75,7 +104,8 @@ def run(w, prm, timings=None, is_baryon=None):
     else:
         label6 = ref.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
         t = tick("fof6d", t)
-    if is_baryon is not None:
+    if species is not None:
+        hoff_all, hmem_all, is_baryon = species
         # baryons take the candidate of the nearest dark matter in phase space
         lab = np.asarray(label6)
         cnt = np.bincount(lab[lab >= 0], minlength=P.n)
@@ -94,6 +124,5 @@ def run(w, prm, timings=None, is_baryon=None):
     t = tick("subgroups", t)
     ub = ref.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc else None
     tick("unbind", t)
-    out.update(cells=cm, R=R, ell=ell, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
-               sub_members=sub_mem, unbind=ub)
-    return out
+    return dict(cells=cm, R=R, ell=ell, ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
+                sub_members=sub_mem, unbind=ub)

@@ -62,6 +62,11 @@ class Params:
     # join the substructure of the nearest dark matter in phase space with
     # this sigma_v (0: the hosts' sigma_v weighted by their dark matter)
     baryon_sigma_v: float = 0.0
+    # levels of the substructure search: the bound substructures of level l
+    # with >= host_min members are searched in turn as hosts of level l+1
+    # (Sec. 2.2, activity chart of the substructure search); one process
+    # per level, the parameters the same at every level
+    levels: int = 1
 
     @classmethod
     def from_workload(cls, w):
@@ -96,6 +101,8 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     learned path when a surrogate model is given; until="R" stops after R;
     is_baryon, a uint8 device flag per particle, selects the two-species
     mode).  Returns the outputs (device tensors) and counts."""
+    if prm.levels > 1 and is_baryon is not None:
+        raise ValueError("levels > 1 runs on one species only")
     ev = []
 
     def mark(name):
@@ -128,29 +135,60 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
     if n_hosts == 0:
         out["R"] = torch.full((P.n,), float("nan"), device=x.device)
         return out, ev
-    all_members = members
+    species = None
     if is_baryon is not None:
         # the substructure search runs on the hosts' dark matter
+        species = (offsets[:n_hosts + 1], members, is_baryon)
         host_offsets, members = ctx.select_members(P.n, host_offsets, members[:int(sizes[:n_hosts].sum())], is_baryon)
         out.update(host_offsets_all=offsets[:n_hosts + 1], search_members=members,
                    n_searched=int(host_offsets[-1].item()))
+    lev1 = _search(ctx, P, group_of, n_hosts, host_offsets, members, prm, mark, "", model, until, species)
+    out.update(lev1)
+    if until == "R":
+        return out, ev
+    out["levels"] = []
+    res = lev1
+    for lev in range(2, prm.levels + 1):
+        if res["unbind"] is None:
+            break
+        # hosts of the next level: the bound members of this level's
+        # substructures, where >= host_min of them remain
+        lb = torch.where(res["unbind"]["bound"] > 0, res["label6"], torch.full_like(res["label6"], -1))
+        nh, g_of, h_off, h_mem = ctx.groups(lb, prm.host_min)
+        mark(f"L{lev}:groups")
+        if nh == 0:
+            break
+        res = _search(ctx, P, g_of, nh, h_off, h_mem, prm, mark, f"L{lev}:")
+        res.update(n_hosts=nh, host_group_of=g_of, host_members=h_mem)
+        out["levels"].append(res)
+    return out, ev
+
+
+def _search(ctx, P, group_of, n_hosts, host_offsets, members, prm: Params, mark, tag, model=None, until=None,
+            species=None):
+    """One level of the substructure search over the hosts [0, n_hosts) of
+    group_of (members in host_offsets/members): the background by cells,
+    R (or the learned path), the outliers linked into candidates, and the
+    candidates unbound.  species = (host offsets over both species, their
+    members, is_baryon) adds the baryon assignment before unbinding."""
+    out = {}
     cm = ctx.cell_moments(P, host_offsets, members, want_table=False)
-    mark("cells")
+    mark(tag + "cells")
     if model is None:
         R = ctx.local_vdensity(P, host_offsets, members, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)
     else:
         R, out["surrogate"] = surrogate_R(ctx, P, host_offsets, members, cm, prm, model)
-    mark("R")
+    mark(tag + "R")
     out.update(cells=cm, R=R, host_offsets=host_offsets)
     if until == "R":
-        return out, ev
+        return out
     ellv = ctx.host_ellv(P, host_offsets, members, prm.alpha_v)
     if prm.use_ell:
         # L from each host's skew-Gaussian fit of R; 6D groups over L >= ell_th,
         # cleaned by their mean L
         ef = ctx.ell_fit(R, host_offsets, members)
         out.update(ell=ef["ell"], ell_fit=ef["fit"], ell_status=ef["status"], ell_merge=ef["merge"])
-        mark("ell")
+        mark(tag + "ell")
         if prm.linker == "paper":
             label6 = ctx.fof_sub(P, group_of, n_hosts, cm["vbar"], prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th,
                                  prm.Vr, prm.theta_op)
@@ -161,15 +199,16 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
                     prm.n_min)
         else:
             label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, ef["ell"], prm.ell_th)
-        mark("fof6d")
+        mark(tag + "fof6d")
         nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
         if nc > 0:
             ctx.ell_clean(ef["ell"], sub_off, sub_mem, label6, prm.ell_th, prm.beta_ell, prm.n_min)
-        mark("clean")
+        mark(tag + "clean")
     else:
         label6 = ctx.fof6d(P, group_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
-        mark("fof6d")
-    if is_baryon is not None:
+        mark(tag + "fof6d")
+    if species is not None:
+        host_offsets_all, all_members, is_baryon = species
         # baryons join the candidate of the nearest dark matter in phase space
         sub = ctx.relabel_min(label6, prm.n_min)
         sv = prm.baryon_sigma_v
@@ -178,17 +217,17 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
             # hosts of (det Sigma_H)^(1/6) weighted by their dark matter
             w_dm = np.diff(host_offsets.cpu().numpy()).astype(np.float64)
             sv = float(np.sum(w_dm * ellv.cpu().numpy()) / np.sum(w_dm)) / prm.alpha_v
-        lab_all = ctx.assign_baryons(P, offsets[:n_hosts + 1], all_members, is_baryon, sub, prm.ellx, sv)
+        lab_all = ctx.assign_baryons(P, host_offsets_all, all_members, is_baryon, sub, prm.ellx, sv)
         label6 = ctx.relabel_min(lab_all, 1)
         out.update(baryon_sigma_v=sv, label6_dm=sub)
-        mark("baryons")
+        mark(tag + "baryons")
     nc, sub_of, sub_off, sub_mem = ctx.groups(label6, prm.n_min)
-    mark("subgroups")
+    mark(tag + "subgroups")
     ub = ctx.unbind(P, sub_off, sub_mem, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min) if nc > 0 else None
-    mark("unbind")
+    mark(tag + "unbind")
     out.update(ellv=ellv, label6=label6, n_candidates=nc, sub_offsets=sub_off,
                sub_members=sub_mem, unbind=ub)
-    return out, ev
+    return out
 
 
 def stage_times(ev):

@@ -133,11 +133,15 @@ def mean_spacing_for_mass(m_p):
 # ---------------------------------------------------------------------------
 # Workloads
 
-def isolated_halo(seed=1, n_host=100_000, n_sub=5, sub_range=(1000, 10000), box=1.0, m=1e8):
+def isolated_halo(seed=1, n_host=100_000, n_sub=5, sub_range=(1000, 10000), box=1.0, m=1e8, n_subsub=0):
     """Single isolated halo: an NFW host (c=10, r200=0.3 Mpc/h at 1e5 particles)
     with Plummer subhalos (a = 5-15 kpc/h at radii 30-250 kpc/h), Gaussian
     velocities (host sigma 200, subhalo sigma 10-30 km/s, subhalo bulk
-    N(0, 200) per axis), equal masses 1e8 Msun/h, 1 Mpc/h periodic box."""
+    N(0, 200) per axis), equal masses 1e8 Msun/h, 1 Mpc/h periodic box.
+    n_subsub > 0 plants a sub-subhalo of that many particles in the largest
+    subhalo: Plummer a = 0.2 a_sub at radius a_sub from its centre, moving at
+    3 sigma_sub from its bulk velocity, dispersion 0.3 sigma_sub;
+    meta["subsub"] flags its particles."""
     rng = np.random.default_rng(seed)
     scale = (n_host / 1e5) ** (1.0 / 3.0)
     r200, c = 0.3 * scale, 10.0
@@ -156,7 +160,16 @@ def isolated_halo(seed=1, n_host=100_000, n_sub=5, sub_range=(1000, 10000), box=
         sig = rng.uniform(10.0, 30.0)
         bulk = rng.normal(0.0, 200.0, size=(3, 1))
         vel.append(bulk + rng.normal(0.0, sig, size=(3, ns)))
-        subs.append(dict(n=ns, a=a, r=rc, sigma=sig))
+        subs.append(dict(n=ns, a=a, r=rc, sigma=sig, centre=sc[:, 0], bulk=bulk[:, 0]))
+    flag = [np.zeros(sum(p_.shape[1] for p_ in pos), np.uint8)]
+    if n_subsub > 0:
+        big = max(subs, key=lambda d: d["n"])
+        ssc = big["centre"][:, None] + _unit_vectors(rng, 1) * big["a"]
+        pos.append(ssc + _unit_vectors(rng, n_subsub) * plummer_radii(rng, n_subsub, 0.2 * big["a"]))
+        sdir = _unit_vectors(rng, 1)
+        vel.append(big["bulk"][:, None] + 3.0 * big["sigma"] * sdir
+                   + rng.normal(0.0, 0.3 * big["sigma"], size=(3, n_subsub)))
+        flag.append(np.ones(n_subsub, np.uint8))
     pos = np.concatenate(pos, axis=1)
     vel = np.concatenate(vel, axis=1)
     spacing = mean_spacing_for_mass(m)
@@ -164,7 +177,7 @@ def isolated_halo(seed=1, n_host=100_000, n_sub=5, sub_range=(1000, 10000), box=
                   alpha_xs=0.5, eps=0.02 * spacing, G=G_GRAV, beta_E=0.95, n_min=20,
                   host_min=256)
     meta = dict(seed=seed, n_host=n_host, subhalos=subs, spacing=spacing)
-    return _finish("isolated_halo", rng, pos, vel, box, None, m, params, meta)
+    return _finish("isolated_halo", rng, pos, vel, box, None, m, params, meta, extra=dict(subsub=np.concatenate(flag)))
 
 
 def cosmo_box(seed=2, n_side=256, box=None, halo_frac=0.45, sub_frac=0.10, n_max=None):
