@@ -106,10 +106,17 @@ __global__ void k_bbox(int na, const int* __restrict__ active, KdNode* nodes, co
 // Mass histograms (counts for uniform mass) of the active nodes, nb bins per
 // dimension spanning the members' extent.  A block whose positions all
 // belong to one node accumulates in LDS first.
+// The three coordinates carried in list-0 order (null when no histogram
+// needs them), permuted with list 0 at every level.
+struct CoordsL0 {
+    const int* in[3];
+    int* out[3];
+};
+
 template <bool COUNTS>
 __global__ __launch_bounds__(KB) void k_hist(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
-                                             const int* __restrict__ l0, const int* __restrict__ u0,
-                                             const int* __restrict__ u1, const int* __restrict__ u2,
+                                             const int* __restrict__ l0, const int* __restrict__ c0,
+                                             const int* __restrict__ c1, const int* __restrict__ c2,
                                              const float* __restrict__ mass, int nb, uint32_t* __restrict__ hc,
                                              double* __restrict__ hm) {
     __shared__ uint32_t lc[3 * 64];
@@ -127,9 +134,8 @@ __global__ __launch_bounds__(KB) void k_hist(int64_t M, const int* __restrict__ 
         const int id = one ? first : seg_node[p];
         const KdNode& nd = nodes[id];
         if (nd.slot < 0 || nd.dim >= 0) continue;
-        const int e = l0[p];
-        const int u[3] = {u0[e], u1[e], u2[e]};
-        const double w = COUNTS ? 1.0 : (double)mass[e];
+        const int u[3] = {c0[p], c1[p], c2[p]};  // coordinates in list-0 order
+        const double w = COUNTS ? 1.0 : (double)mass[l0[p]];
         for (int d = 0; d < 3; ++d) {
             if (nd.bmax[d] == nd.bmin[d]) continue;
             const int bin = (int)(((int64_t)(u[d] - nd.bmin[d]) * nb) / ((int64_t)nd.bmax[d] - nd.bmin[d] + 1));
@@ -312,7 +318,7 @@ __global__ void k_lflag3(int64_t M, const int* __restrict__ seg_node, const KdNo
 __global__ void k_part3(int64_t M, int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
                         const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
                         const uint8_t* __restrict__ flag, const uint32_t* __restrict__ scan, int* __restrict__ o0,
-                        int* __restrict__ o1, int* __restrict__ o2) {
+                        int* __restrict__ o1, int* __restrict__ o2, CoordsL0 c) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
     const KdNode& nd = nodes[seg_node[p]];
@@ -321,6 +327,9 @@ __global__ void k_part3(int64_t M, int* __restrict__ seg_node, const KdNode* __r
         o0[p] = e0;
         o1[p] = e1;
         o2[p] = e2;
+        if (c.in[0]) {
+            for (int d = 0; d < 3; ++d) c.out[d][p] = c.in[d][p];
+        }
         return;
     }
     const int s = nd.start, nl = (nd.end - nd.start) / 2;
@@ -331,8 +340,23 @@ __global__ void k_part3(int64_t M, int* __restrict__ seg_node, const KdNode* __r
         const int rl = (int)(scan[j * M + p] - scan[j * M + s]);  // left members before p in the node
         const int np = flag[e[j]] ? s + rl : s + nl + ((int)p - s - rl);
         out[j][np] = e[j];
+        if (j == 0 && c.in[0]) {
+            for (int d = 0; d < 3; ++d) c.out[d][np] = c.in[d][p];
+        }
     }
     seg_node[p] = p < s + nl ? nd.left : nd.right;
+}
+
+// coordinates in list-0 order, for the histograms
+__global__ void k_coords_l0(int64_t M, const int* __restrict__ l0, const int* __restrict__ u0,
+                            const int* __restrict__ u1, const int* __restrict__ u2, int* __restrict__ c0,
+                            int* __restrict__ c1, int* __restrict__ c2) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M) return;
+    const int e = l0[p];
+    c0[p] = u0[e];
+    c1[p] = u1[e];
+    c2[p] = u2[e];
 }
 
 __global__ void k_leaf_bbox(int nl, const int* __restrict__ leaves, KdNode* nodes, const int* __restrict__ l0,
@@ -419,6 +443,8 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     // one workspace region holds every array of the build
     Carve cv;
     int *U[3], *G, *H, *L[3], *Lalt[3], *seg, *leaf_min, *act0, *act1, *leaves, *ncell_d, *counters;
+    int *C0[3], *C0alt[3];
+    const int64_t MC = mode != KD_WIDEST ? M : 1;
     float* Ms;
     uint8_t* flag;
     uint32_t* lf;
@@ -432,6 +458,8 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         Ms = cv.add<float>(use_mass ? M : 1);
         for (int d = 0; d < 3; ++d) L[d] = cv.add<int>(M);
         for (int d = 0; d < 3; ++d) Lalt[d] = cv.add<int>(M);
+        for (int d = 0; d < 3; ++d) C0[d] = cv.add<int>(MC);
+        for (int d = 0; d < 3; ++d) C0alt[d] = cv.add<int>(MC);
         seg = cv.add<int>(M);
         flag = cv.add<uint8_t>(M);
         lf = cv.add<uint32_t>(3 * M + 1);
@@ -471,6 +499,11 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         int rc = sort_pairs_u64(ctx, pkey, reinterpret_cast<uint32_t*>(L[d]), M, 22 + hb, st);
         if (rc) return rc;
     }
+    if (mode != KD_WIDEST) {
+        hipLaunchKernelGGL(k_coords_l0, dim3(grid_for(M, 256)), dim3(256), 0, st, M, L[0], U[0], U[1], U[2], C0[0],
+                           C0[1], C0[2]);
+        VR_LAUNCH_CHECK(ctx);
+    }
     hipLaunchKernelGGL(k_roots, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, host_offsets, ncell_d, nodes,
                        act0, counters, leaves, seg);
     VR_LAUNCH_CHECK(ctx);
@@ -504,14 +537,14 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
                 hc = static_cast<uint32_t*>(ws(ctx, WS_KD_HIST, hn * sizeof(uint32_t)));
                 if (!hc) return VR_ERR_OUT_OF_MEMORY;
                 if ((rc = fill_u32(ctx, hc, 0u, hn, st))) return rc;
-                hipLaunchKernelGGL(k_hist<true>, dim3(grid_for(M, HCH)), dim3(KB), 0, st, M, seg, nodes, L[0], U[0],
-                                   U[1], U[2], Ms, nbins, hc, hm);
+                hipLaunchKernelGGL(k_hist<true>, dim3(grid_for(M, HCH)), dim3(KB), 0, st, M, seg, nodes, L[0], C0[0],
+                                   C0[1], C0[2], Ms, nbins, hc, hm);
             } else {
                 hm = static_cast<double*>(ws(ctx, WS_KD_HIST, hn * sizeof(double)));
                 if (!hm) return VR_ERR_OUT_OF_MEMORY;
                 if ((rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hm), 0u, 2 * hn, st))) return rc;
-                hipLaunchKernelGGL(k_hist<false>, dim3(grid_for(M, HCH)), dim3(KB), 0, st, M, seg, nodes, L[0], U[0],
-                                   U[1], U[2], Ms, nbins, hc, hm);
+                hipLaunchKernelGGL(k_hist<false>, dim3(grid_for(M, HCH)), dim3(KB), 0, st, M, seg, nodes, L[0], C0[0],
+                                   C0[1], C0[2], Ms, nbins, hc, hm);
             }
             VR_LAUNCH_CHECK(ctx);
         }
@@ -531,10 +564,15 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         hipLaunchKernelGGL(k_lflag3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf);
         VR_LAUNCH_CHECK(ctx);
         if ((rc = scan_u32(ctx, lf, lf, 3 * M, nullptr, st))) return rc;
+        CoordsL0 cl0{};
+        if (mode != KD_WIDEST) cl0 = CoordsL0{{C0[0], C0[1], C0[2]}, {C0alt[0], C0alt[1], C0alt[2]}};
         hipLaunchKernelGGL(k_part3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf, Lalt[0],
-                           Lalt[1], Lalt[2]);
+                           Lalt[1], Lalt[2], cl0);
         VR_LAUNCH_CHECK(ctx);
-        for (int j = 0; j < 3; ++j) std::swap(L[j], Lalt[j]);
+        for (int j = 0; j < 3; ++j) {
+            std::swap(L[j], Lalt[j]);
+            std::swap(C0[j], C0alt[j]);
+        }
         VR_HIP(ctx, hipMemcpyAsync(counters + 0, counters + 1, sizeof(int), hipMemcpyDeviceToDevice, st));
         VR_HIP(ctx, hipMemcpyAsync(counters + 4, counters + 5, sizeof(int), hipMemcpyDeviceToDevice, st));
         if (ctx->timing) {

@@ -107,6 +107,24 @@ def test_assign_baryons_hosts_without_dark_matter(ctx, vr, ref):
     assert list(got) == [-1, -1, 5, 5, 6]
 
 
+def test_assign_baryons_without_any_dark_matter(ctx, vr, ref):
+    """Every host member a baryon: nothing to take a label from."""
+    c = 1 << 20
+    q = np.array([[c, c + 50, c + 900, c + 950], [c] * 4, [c] * 4], np.uint32)
+    v = np.zeros((3, 4), np.float32)
+    isb = np.ones(4, np.uint8)
+    sub = np.array([3, 4, 5, 6], np.int32)
+    Pr = ref.Particles(q, v, None, 1.0, 1.0, 21)
+    P = vr.Particles(dev_tensor(q), dev_tensor(v), None, 1.0, 1.0, 21)
+    off = np.array([0, 2, 4], np.int32)
+    mem = np.arange(4, dtype=np.int32)
+    exp = ref.assign_baryons(Pr, off, mem, isb, sub, 0.001, 100.0)
+    got = ctx.assign_baryons(P, dev_tensor(off), dev_tensor(mem), dev_tensor(isb), dev_tensor(sub), 0.001,
+                             100.0).cpu().numpy()
+    np.testing.assert_array_equal(got, exp)
+    assert list(got) == [-1, -1, -1, -1]
+
+
 def test_pipeline_species_stagewise(ctx, vr, ref):
     """The hot path in the two-species mode: 3D labels exact against the
     oracle; the dark-matter search lists exact; then the substructure and the
