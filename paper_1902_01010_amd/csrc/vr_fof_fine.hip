@@ -110,6 +110,10 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
     const int64_t f = int64_t(1) << G.k;
     // the own row (x and x+1) and the four following rows (x-1 .. x+1)
     const int rdz[5] = {0, 0, 1, 1, 1}, rdy[5] = {0, 1, -1, 0, 1};
+    // A's root, refreshed only when B's differs: components only merge, so
+    // a root once equal stays equal, and a stale one is one hop from the
+    // current root
+    int ra = uf_find(parent, (int)a0);
     for (int rr = 0; rr < 5; ++rr) {
         const int nz = (cz + rdz[rr]) & ncm, ny = (cy + rdy[rr]) & ncm;
         const uint32_t row = (uint32_t)nz * (uint32_t)G.nc + (uint32_t)ny;
@@ -144,7 +148,9 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
                               lz = gz ? (gz - 1) * f + 1 : 0;
                 const double dmin = (double)(lx * lx + ly * ly + lz * lz);
                 if (dmin >= ell2) continue;
-                const int ra = uf_find(parent, (int)a0), rb = uf_find(parent, (int)b0);
+                const int rb = uf_find(parent, (int)b0);
+                if (rb == ra) continue;
+                ra = uf_find(parent, ra);
                 if (ra == rb) continue;
                 const int64_t ux = (gx + 1) * f - 1, uy = (gy + 1) * f - 1, uz = (gz + 1) * f - 1;
                 const double dmax = (double)(ux * ux + uy * uy + uz * uz);
