@@ -111,8 +111,8 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
     // the own row (x and x+1) and the four following rows (x-1 .. x+1)
     const int rdz[5] = {0, 0, 1, 1, 1}, rdy[5] = {0, 1, -1, 0, 1};
     // A's root, refreshed only when B's differs: components only merge, so
-    // a root once equal stays equal, and a stale one is one hop from the
-    // current root
+    // roots once equal stay equal, and a stale root still lies on the path
+    // to the current one
     int ra = uf_find(parent, (int)a0);
     for (int rr = 0; rr < 5; ++rr) {
         const int nz = (cz + rdz[rr]) & ncm, ny = (cy + rdy[rr]) & ncm;
