@@ -241,7 +241,10 @@ int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, const uint8_t* 
  * units, ell2 = (ellx in grid units)^2, FP64 dv2 in x, y, z order; ties to
  * the smaller index), -1 when the host has no dark matter; dark-matter
  * members copy sub[j].  out (device [n]) is written for host members only.
- * sub: device [n]. */
+ * sub: device [n].  Errors: VR_ERR_INVALID_ARG for ellx outside (0, box/2),
+ * sigma_v <= 0 or NULL arrays; VR_ERR_UNSUPPORTED when a host's dark
+ * matter would need a search tree deeper than 8 levels of 64 (never below
+ * 2^48 members).  Syncs a few times (member counts, tree level sizes). */
 int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
                       const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub, double ellx,
                       double sigma_v, int32_t* out, void* stream);
