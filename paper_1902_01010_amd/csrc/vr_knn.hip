@@ -13,8 +13,11 @@
 // LDS address for every lane, no divergence) marks in a per-lane bit mask
 // the members whose FP32 squared distance may beat the lane's current worst;
 // a second pass inserts the marked ones with their exact keys, each lane
-// walking its own mask.  Every lane keeps its n_se best keys in a max-heap
-// in LDS; a key packs the exact integer squared distance above the member's
+// walking its own mask.  Every lane keeps its n_se best keys, unordered, in
+// LDS slots grouped by eight; the largest key of each group and its slot
+// sit in registers, so replacing the lane's worst key rewrites one slot and
+// rereads that group's eight keys at once, with no chain of dependent LDS
+// reads.  A key packs the exact integer squared distance above the member's
 // rank in its host's ascending index order, so ties break by particle index
 // exactly as the definition says.  The n_v velocity neighbours are then
 // chosen among the n_se by (FP64 dv2, index) and the Epanechnikov estimate
@@ -58,36 +61,6 @@ __global__ void k_subset_pos(int64_t ns, int64_t n, const int32_t* __restrict__ 
     if (p < 0) { atomicOr(bad, 1); p = 0; }
     qpos[s] = (uint32_t)p;
     qval[s] = (uint32_t)s;
-}
-
-__device__ __forceinline__ void heap_push(uint64_t (*heap)[64], int lane, int& count, uint64_t key) {
-    int i = count++;
-    while (i > 0) {
-        const int par = (i - 1) >> 1;
-        const uint64_t pk = heap[par][lane];
-        if (pk >= key) break;
-        heap[i][lane] = pk;
-        i = par;
-    }
-    heap[i][lane] = key;
-}
-
-__device__ __forceinline__ void heap_replace_top(uint64_t (*heap)[64], int lane, int count, uint64_t key) {
-    int i = 0;
-    for (;;) {
-        const int l = 2 * i + 1;
-        if (l >= count) break;
-        int c = l;
-        uint64_t ck = heap[l][lane];
-        if (l + 1 < count) {
-            const uint64_t rk = heap[l + 1][lane];
-            if (rk > ck) { c = l + 1; ck = rk; }
-        }
-        if (ck <= key) break;
-        heap[i][lane] = ck;
-        i = c;
-    }
-    heap[i][lane] = key;
 }
 
 // ln f_bg (Eq. fvbg): the Gaussian of mean vbar(x) and dispersion sigma(x)
@@ -159,6 +132,66 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
     int count = 0;
     uint64_t worst = ~0ull;
+    // the kept keys: slot s of group s / 8; per group its largest key and
+    // that key's slot; wg = the group holding the lane's largest key
+    constexpr int NG = NSE / 8;
+    static_assert(NG <= 8, "slot indices of the group maxima are packed 6 bits each");
+    uint64_t gmx[NG];
+    uint64_t gix = 0;  // slot of group g's largest key in bits [6g, 6g + 6)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) gmx[g] = 0;
+    int wg = 0;
+    const int ngv = (n_se + 7) >> 3;
+    auto top_update = [&]() __attribute__((always_inline)) {
+        uint64_t m = gmx[0];
+        int mg = 0;
+#pragma unroll
+        for (int g = 1; g < NG; ++g)
+            if (g < ngv && gmx[g] > m) {
+                m = gmx[g];
+                mg = g;
+            }
+        worst = m;
+        wg = mg;
+    };
+    // keeps key: appended while fewer than n_se are kept, else it takes the
+    // slot of the largest (the caller has checked key < worst)
+    auto insert = [&](uint64_t key) __attribute__((always_inline)) {
+        if (count < n_se) {
+            const int sl = count++;
+            heap[sl][lane] = key;
+            const int g = sl >> 3;
+            bool up = false;
+#pragma unroll
+            for (int k = 0; k < NG; ++k)
+                if (k == g && ((sl & 7) == 0 || key > gmx[k])) {
+                    gmx[k] = key;
+                    up = true;
+                }
+            if (up) gix = (gix & ~(uint64_t(63) << (6 * g))) | ((uint64_t)sl << (6 * g));
+            if (count == n_se) top_update();
+            return;
+        }
+        const int sl = (int)((gix >> (6 * wg)) & 63);
+        heap[sl][lane] = key;
+        const int s0 = wg << 3, s1 = min(s0 + 8, n_se);
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = heap[s0 + u][lane];
+        uint64_t m = key;
+        int ms = sl;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < s1 && v[u] > m) {
+                m = v[u];
+                ms = s0 + u;
+            }
+#pragma unroll
+        for (int k = 0; k < NG; ++k)
+            if (k == wg) gmx[k] = m;
+        gix = (gix & ~(uint64_t(63) << (6 * wg))) | ((uint64_t)ms << (6 * wg));
+        top_update();
+    };
     // While a heap is not full it accepts only squared distances <= tau, a
     // bound that at least n_se members of the host are known to meet (so the
     // n_se nearest all meet it); NO_BOUND until such a bound is found.
@@ -167,7 +200,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
 
     // Stages the members [c0, min(c0 + 64, t_end)) of a leaf in LDS for the
     // unwrapped (no minimum image) scan; padding slots sit far away.
-    auto stage_chunk = [&](int c0, int t_end, int hbase) {
+    auto stage_chunk = [&](int c0, int t_end, int hbase) __attribute__((always_inline)) {
         const int j = c0 + lane;
         const bool vj = j < t_end;
         cxs[lane] = vj ? (float)F.u[0][j] : 1e30f;
@@ -178,7 +211,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     };
 
     // Inserts the members of leaf `node` for the lanes in `mine`.
-    auto scan_leaf = [&](int node, bool mine, bool nowrap, int hbase) {
+    auto scan_leaf = [&](int node, bool mine, bool nowrap, int hbase) __attribute__((always_inline)) {
         const KdNode& nd = nodes[node];
         const int s = nd.start, t_end = nd.end;
         for (int c0 = s; c0 < t_end; c0 += 64) {
@@ -230,15 +263,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                                    az = (uint32_t)abs((int)(czs[t] - pzf));
                     const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
                     const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)crk[t];
-                    if (count < n_se) {
-                        if (d2 <= tau) {
-                            heap_push(heap, lane, count, key);
-                            if (count == n_se) worst = heap[0][lane];
-                        }
-                    } else if (key < worst) {
-                        heap_replace_top(heap, lane, count, key);
-                        worst = heap[0][lane];
-                    }
+                    if (count < n_se ? d2 <= tau : key < worst) insert(key);
                 }
                 __builtin_amdgcn_wave_barrier();
                 continue;
@@ -262,20 +287,12 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                 else
                     d2 = (uint64_t)((int64_t)ddx * ddx + (int64_t)ddy * ddy + (int64_t)ddz * ddz);
                 const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)ce;
-                if (mine && (count < n_se || key < worst)) {
-                    if (count < n_se) {
-                        heap_push(heap, lane, count, key);
-                        if (count == n_se) worst = heap[0][lane];
-                    } else {
-                        heap_replace_top(heap, lane, count, key);
-                        worst = heap[0][lane];
-                    }
-                }
+                if (mine && (count < n_se || key < worst)) insert(key);
             }
         }
     };
     // whether some lane's ball (radius = its current worst) reaches the box
-    auto needed = [&](const KdNode& nd, bool mine) {
+    auto needed = [&](const KdNode& nd, bool mine) __attribute__((always_inline)) {
         const int64_t dx = max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
         const int64_t dy = max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
         const int64_t dz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         const int ccz = __builtin_amdgcn_readfirstlane((int)(sz / cnt));
         // Depth-first walk of the host's tree, near child first; skip_own:
         // the leaves holding a query of this pass were scanned already.
-        auto walk = [&](bool skip_own) {
+        auto walk = [&](bool skip_own) __attribute__((always_inline)) {
             if (lane == 0) stack[0] = hh;
             int sp = 1;
             __builtin_amdgcn_wave_barrier();
