@@ -134,14 +134,16 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     uint64_t worst = ~0ull;
     // the kept keys: slot s of group s / 8; per group its largest key and
     // that key's slot; wg = the group holding the lane's largest key
-    constexpr int NG = NSE / 8;
-    static_assert(NG <= 8, "slot indices of the group maxima are packed 6 bits each");
+    constexpr int LGS = 3;  // groups of 2^LGS slots
+    constexpr int GS = 1 << LGS;
+    constexpr int NG = NSE >> LGS;
+    static_assert(NG * 6 <= 64, "slot indices of the group maxima are packed 6 bits each");
     uint64_t gmx[NG];
     uint64_t gix = 0;  // slot of group g's largest key in bits [6g, 6g + 6)
 #pragma unroll
     for (int g = 0; g < NG; ++g) gmx[g] = 0;
     int wg = 0;
-    const int ngv = (n_se + 7) >> 3;
+    const int ngv = (n_se + GS - 1) >> LGS;
     auto top_update = [&]() __attribute__((always_inline)) {
         uint64_t m = gmx[0];
         int mg = 0;
@@ -160,11 +162,11 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         if (count < n_se) {
             const int sl = count++;
             heap[sl][lane] = key;
-            const int g = sl >> 3;
+            const int g = sl >> LGS;
             bool up = false;
 #pragma unroll
             for (int k = 0; k < NG; ++k)
-                if (k == g && ((sl & 7) == 0 || key > gmx[k])) {
+                if (k == g && ((sl & (GS - 1)) == 0 || key > gmx[k])) {
                     gmx[k] = key;
                     up = true;
                 }
@@ -174,14 +176,14 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         }
         const int sl = (int)((gix >> (6 * wg)) & 63);
         heap[sl][lane] = key;
-        const int s0 = wg << 3, s1 = min(s0 + 8, n_se);
-        uint64_t v[8];
+        const int s0 = wg << LGS, s1 = min(s0 + GS, n_se);
+        uint64_t v[GS];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = heap[s0 + u][lane];
+        for (int u = 0; u < GS; ++u) v[u] = heap[s0 + u][lane];
         uint64_t m = key;
         int ms = sl;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < GS; ++u)
             if (s0 + u < s1 && v[u] > m) {
                 m = v[u];
                 ms = s0 + u;
