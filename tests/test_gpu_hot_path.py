@@ -141,7 +141,7 @@ def test_local_vdensity_subset_and_other_sizes(ctx, ref, case):
     rng = np.random.default_rng(3)
     sub = np.sort(rng.choice(hmem, size=min(500, len(hmem)), replace=False)).astype(np.int32)
     rng.shuffle(sub)
-    for n_se, n_v in [(32, 8), (16, 4), (48, 16)]:
+    for n_se, n_v in [(32, 8), (16, 4), (48, 16), (20, 5), (33, 7), (63, 9), (9, 2)]:
         exp = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], n_se, n_v, subset=sub)["R"]
         got = ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(cm["vbar"]),
                                  dev_tensor(cm["sigma"]), n_se, n_v, subset=dev_tensor(sub)).cpu().numpy()
