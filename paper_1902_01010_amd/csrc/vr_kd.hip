@@ -87,11 +87,12 @@ __global__ void k_seg_init(int64_t M, const int* __restrict__ host, int* __restr
 
 // Bounding box of every active node from the sorted lists; the root region is
 // its bounding box.
-__global__ void k_bbox(int na, const int* __restrict__ active, KdNode* nodes, const int* __restrict__ l0,
-                       const int* __restrict__ l1, const int* __restrict__ l2, const int* __restrict__ u0,
-                       const int* __restrict__ u1, const int* __restrict__ u2, int n_hosts) {
+__global__ void k_bbox(const int* __restrict__ nact, const int* __restrict__ active, KdNode* nodes,
+                       const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
+                       const int* __restrict__ u0, const int* __restrict__ u1, const int* __restrict__ u2,
+                       int n_hosts) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= na) return;
+    if (i >= *nact) return;
     const int id = active[i];
     KdNode& nd = nodes[id];
     const int s = nd.start, e = nd.end - 1;
@@ -161,12 +162,13 @@ __global__ __launch_bounds__(KB) void k_hist(int64_t M, const int* __restrict__ 
 // Normalised Shannon entropy of each dimension's histogram (the entropy
 // equation of Sec. 2.2) for every active node: one wavefront per node, one
 // lane per bin, so the logarithms of a node are taken in parallel.
-__global__ __launch_bounds__(256) void k_entropy(int na, const int* __restrict__ active, const KdNode* __restrict__ nodes,
-                                                 int nb, int counts, const uint32_t* __restrict__ hc,
-                                                 const double* __restrict__ hm, double* __restrict__ S) {
+__global__ __launch_bounds__(256) void k_entropy(const int* __restrict__ nact, const int* __restrict__ active,
+                                                 const KdNode* __restrict__ nodes, int nb, int counts,
+                                                 const uint32_t* __restrict__ hc, const double* __restrict__ hm,
+                                                 double* __restrict__ S) {
     const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = __lane_id();
-    if (i >= na) return;
+    if (i >= *nact) return;
     const KdNode& nd = nodes[active[i]];
     __shared__ double sh[4][64];
     __shared__ double stot[4];
@@ -221,14 +223,14 @@ __device__ __forceinline__ int wave_reserve(int* counter, int n) {
 
 // Split decision of every active node and creation of its children.  All
 // lanes run to the end (the counters are reserved per wavefront).
-__global__ __launch_bounds__(256) void k_split(int na, const int* __restrict__ active, KdNode* nodes,
+__global__ __launch_bounds__(256) void k_split(const int* nact, const int* __restrict__ active, KdNode* nodes,
                                                const int* __restrict__ l0, const int* __restrict__ l1,
                                                const int* __restrict__ l2, const int* __restrict__ u0,
                                                const int* __restrict__ u1, const int* __restrict__ u2, int mode,
                                                const double* __restrict__ Sdim, const int* __restrict__ ncell,
                                                int* next_active, int* leaves, int* counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < na;
+    const bool valid = i < *nact;
     const int id = valid ? active[i] : 0;
     KdNode nd;
     int best = -1;
@@ -512,13 +514,52 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     int* cur = act0;
     int* nxt = act1;
     const unsigned gM = grid_for(M, 256);
-    for (int level = 0;; ++level) {
-        int c[8];
-        int rc = read_back(ctx, counters, c, sizeof c, st);
-        if (rc) return rc;
-        const int na = c[0];
-        if (na == 0) break;
-        if (level >= 64) return set_err(ctx, VR_ERR_NOT_CONVERGED, "KD build exceeded 64 levels");
+    // Active nodes and their members per level as the sizes alone give them
+    // (a node splits at rank floor(n/2) while it holds more than ncell; the
+    // sizes of one host's nodes on a level are two consecutive integers).
+    // A node of coincident members that stays a leaf only lowers the true
+    // counts, which the kernels read from the device; these bound the grids
+    // and the number of levels, so no level waits for the host.
+    std::vector<int64_t> plan_na, plan_members;
+    {
+        struct Sz { int64_t s0, c0, c1; };  // c0 nodes of size s0, c1 of size s0 + 1
+        std::vector<Sz> sz(n_hosts);
+        for (int h = 0; h < n_hosts; ++h) sz[h] = Sz{(int64_t)off[h + 1] - off[h], 1, 0};
+        for (;;) {
+            int64_t na = 0, mem = 0;
+            for (int h = 0; h < n_hosts; ++h) {
+                Sz& z = sz[h];
+                const int64_t nc = ncell[h];
+                int64_t a0 = z.s0 > nc ? z.c0 : 0, a1 = z.s0 + 1 > nc ? z.c1 : 0;
+                na += a0 + a1;
+                mem += a0 * z.s0 + a1 * (z.s0 + 1);
+                // children of the active ones: floor and ceil halves
+                int64_t lo = INT64_MAX, cnt[3] = {0, 0, 0};
+                const int64_t sizes[2] = {z.s0, z.s0 + 1}, counts[2] = {a0, a1};
+                for (int k = 0; k < 2; ++k)
+                    if (counts[k] > 0) lo = std::min(lo, sizes[k] / 2);
+                if (lo == INT64_MAX) {
+                    z = Sz{0, 0, 0};
+                    continue;
+                }
+                for (int k = 0; k < 2; ++k) {
+                    if (counts[k] == 0) continue;
+                    const int64_t f = sizes[k] / 2, c = sizes[k] - f;
+                    cnt[f - lo] += counts[k];
+                    cnt[c - lo] += counts[k];
+                }
+                // the halves of two consecutive sizes span at most lo .. lo + 1
+                z = Sz{lo, cnt[0], cnt[1] + cnt[2]};
+            }
+            if (na == 0) break;
+            plan_na.push_back(na);
+            plan_members.push_back(mem);
+            if (plan_na.size() > 64) return set_err(ctx, VR_ERR_NOT_CONVERGED, "KD build exceeded 64 levels");
+        }
+    }
+    for (int level = 0; level < (int)plan_na.size(); ++level) {
+        int rc = VR_OK;
+        const int na = (int)plan_na[level];
         hipEvent_t e0 = nullptr;
         if (ctx->timing) {
             e0 = timer_event(ctx);
@@ -526,8 +567,8 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         }
         if ((rc = fill_i32(ctx, counters + 1, 0, 1, st))) return rc;
         if ((rc = fill_i32(ctx, counters + 5, 0, 1, st))) return rc;
-        hipLaunchKernelGGL(k_bbox, dim3(grid_for(na, 256)), dim3(256), 0, st, na, cur, nodes, L[0], L[1], L[2], U[0],
-                           U[1], U[2], n_hosts);
+        hipLaunchKernelGGL(k_bbox, dim3(grid_for(na, 256)), dim3(256), 0, st, counters, cur, nodes, L[0], L[1], L[2],
+                           U[0], U[1], U[2], n_hosts);
         VR_LAUNCH_CHECK(ctx);
         uint32_t* hc = nullptr;
         double* hm = nullptr;
@@ -552,12 +593,12 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         if (mode != KD_WIDEST) {
             Sdim = static_cast<double*>(ws(ctx, WS_KD_S, (size_t)na * 3 * sizeof(double)));
             if (!Sdim) return VR_ERR_OUT_OF_MEMORY;
-            hipLaunchKernelGGL(k_entropy, dim3(grid_for((int64_t)na * 64, 256)), dim3(256), 0, st, na, cur, nodes,
-                               nbins, counts, hc, hm, Sdim);
+            hipLaunchKernelGGL(k_entropy, dim3(grid_for((int64_t)na * 64, 256)), dim3(256), 0, st, counters, cur,
+                               nodes, nbins, counts, hc, hm, Sdim);
             VR_LAUNCH_CHECK(ctx);
         }
-        hipLaunchKernelGGL(k_split, dim3(grid_for(na, 256)), dim3(256), 0, st, na, cur, nodes, L[0], L[1], L[2], U[0],
-                           U[1], U[2], mode, Sdim, ncell_d, nxt, leaves, counters);
+        hipLaunchKernelGGL(k_split, dim3(grid_for(na, 256)), dim3(256), 0, st, counters, cur, nodes, L[0], L[1], L[2],
+                           U[0], U[1], U[2], mode, Sdim, ncell_d, nxt, leaves, counters);
         VR_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_flags, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag);
         VR_LAUNCH_CHECK(ctx);
@@ -578,7 +619,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         if (ctx->timing) {
             hipEvent_t e1 = timer_event(ctx);
             (void)hipEventRecord(e1, st);
-            timer_push(ctx, "kd_level", e0, e1, (double)c[4]);
+            timer_push(ctx, "kd_level", e0, e1, (double)plan_members[level]);
         }
         std::swap(cur, nxt);
     }
