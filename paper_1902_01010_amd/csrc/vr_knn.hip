@@ -440,25 +440,49 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     double msum = 0.0;
     double h2, sw = 0.0;
     const double kW = 15.0 / (8.0 * M_PI);
+    // the neighbours' velocities and masses, eight at a time: the loads of a
+    // batch are issued together and waited for once
+    constexpr int VB = 8;
+    int bpos[VB];
+    float bvx[VB], bvy[VB], bvz[VB], bms[VB];
+    auto fetch = [&](int a0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < VB; ++u) {
+            const int a = a0 + u;
+            bpos[u] = a < n_se ? (int)(heap[a][lane] & POS_MASK) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < VB; ++u) {
+            const int gp = base + bpos[u];
+            bvx[u] = Vx[gp];
+            bvy[u] = Vy[gp];
+            bvz[u] = Vz[gp];
+            bms[u] = use_mass ? Me[gp] : 0.f;
+        }
+    };
     if constexpr (NVR > 0) {
         double vdr[NVR];
         int vpr[NVR];
 #pragma unroll
         for (int i = 0; i < NVR; ++i) { vdr[i] = INFINITY; vpr[i] = 0x7FFFFFFF; }
-        for (int a = 0; a < n_se; ++a) {
-            const int pos = (int)(heap[a][lane] & POS_MASK);
-            const int gp = base + pos;
-            msum += use_mass ? (double)Me[gp] : mass_value;
-            const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
-            const double dv2 = ax * ax + ay * ay + az * az;
+        for (int a0 = 0; a0 < n_se; a0 += VB) {
+            fetch(a0);
 #pragma unroll
-            for (int i = NVR - 1; i > 0; --i) {
-                const bool lp = vless(dv2, pos, vdr[i - 1], vpr[i - 1]);
-                const bool lc = vless(dv2, pos, vdr[i], vpr[i]);
-                vdr[i] = lp ? vdr[i - 1] : (lc ? dv2 : vdr[i]);
-                vpr[i] = lp ? vpr[i - 1] : (lc ? pos : vpr[i]);
+            for (int u = 0; u < VB; ++u) {
+                if (a0 + u >= n_se) break;
+                const int pos = bpos[u];
+                msum += use_mass ? (double)bms[u] : mass_value;
+                const double ax = vqx - (double)bvx[u], ay = vqy - (double)bvy[u], az = vqz - (double)bvz[u];
+                const double dv2 = ax * ax + ay * ay + az * az;
+#pragma unroll
+                for (int i = NVR - 1; i > 0; --i) {
+                    const bool lp = vless(dv2, pos, vdr[i - 1], vpr[i - 1]);
+                    const bool lc = vless(dv2, pos, vdr[i], vpr[i]);
+                    vdr[i] = lp ? vdr[i - 1] : (lc ? dv2 : vdr[i]);
+                    vpr[i] = lp ? vpr[i - 1] : (lc ? pos : vpr[i]);
+                }
+                if (vless(dv2, pos, vdr[0], vpr[0])) { vdr[0] = dv2; vpr[0] = pos; }
             }
-            if (vless(dv2, pos, vdr[0], vpr[0])) { vdr[0] = dv2; vpr[0] = pos; }
         }
         h2 = vdr[NVR - 1];
         if (h2 != 0.0) {
@@ -470,24 +494,26 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         }
     } else {
         int nv = 0;
-        for (int a = 0; a < n_se; ++a) {
-            const int pos = (int)(heap[a][lane] & POS_MASK);
-            const int gp = base + pos;
-            msum += use_mass ? (double)Me[gp] : mass_value;
-            const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
-            const double dv2 = ax * ax + ay * ay + az * az;
-            if (nv == n_v) {
-                if (!vless(dv2, pos, vd[n_v - 1][lane], vp[n_v - 1][lane])) continue;
-                --nv;
+        for (int a0 = 0; a0 < n_se; a0 += VB) {
+            fetch(a0);
+            for (int u = 0; u < VB && a0 + u < n_se; ++u) {
+                const int pos = bpos[u];
+                msum += use_mass ? (double)bms[u] : mass_value;
+                const double ax = vqx - (double)bvx[u], ay = vqy - (double)bvy[u], az = vqz - (double)bvz[u];
+                const double dv2 = ax * ax + ay * ay + az * az;
+                if (nv == n_v) {
+                    if (!vless(dv2, pos, vd[n_v - 1][lane], vp[n_v - 1][lane])) continue;
+                    --nv;
+                }
+                int i = nv++;
+                while (i > 0 && vless(dv2, pos, vd[i - 1][lane], vp[i - 1][lane])) {
+                    vd[i][lane] = vd[i - 1][lane];
+                    vp[i][lane] = vp[i - 1][lane];
+                    --i;
+                }
+                vd[i][lane] = dv2;
+                vp[i][lane] = pos;
             }
-            int i = nv++;
-            while (i > 0 && vless(dv2, pos, vd[i - 1][lane], vp[i - 1][lane])) {
-                vd[i][lane] = vd[i - 1][lane];
-                vp[i][lane] = vp[i - 1][lane];
-                --i;
-            }
-            vd[i][lane] = dv2;
-            vp[i][lane] = pos;
         }
         h2 = vd[n_v - 1][lane];
         if (h2 != 0.0)
