@@ -247,6 +247,7 @@ struct Tree6 {
     const uint32_t *sx, *sy, *sz;  // members in tree order
     const float *svx, *svy, *svz;
     const int32_t* sj;  // particle index
+    const uint64_t* dkey;  // Morton keys of the members in tree order (ascending)
 };
 
 __global__ void k_host_init(int n_hosts, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
@@ -524,8 +525,9 @@ __global__ __launch_bounds__(256) void k_assign6(int64_t nb, const int32_t* __re
                                                  const int32_t* __restrict__ sub, const uint32_t* __restrict__ qx,
                                                  const uint32_t* __restrict__ qy, const uint32_t* __restrict__ qz,
                                                  const float* __restrict__ vx, const float* __restrict__ vy,
-                                                 const float* __restrict__ vz, Tree6 t, int gb, double ell2,
-                                                 double sv2, float ix, float iv, int32_t* __restrict__ out) {
+                                                 const float* __restrict__ vz, const uint64_t* __restrict__ bkey,
+                                                 Tree6 t, int gb, double ell2, double sv2, float ix, float iv,
+                                                 int32_t* __restrict__ out) {
     __shared__ int stack[T6_WAVES][T6_MAX_DEPTH * T6_FAN];
     __shared__ float4 sya[T6_WAVES][T6_FAN], syb[T6_WAVES][T6_FAN], svl[T6_WAVES][T6_FAN];
     __shared__ uint4 sqp[T6_WAVES][T6_FAN];
@@ -598,6 +600,26 @@ __global__ __launch_bounds__(256) void k_assign6(int64_t nb, const int32_t* __re
         }
         float y[6];
         scaled6(hb, (uint32_t)px, (uint32_t)py, (uint32_t)pz, fvx, fvy, fvz, gb, ix, iv, y);
+        if (mine) {
+            // a first best: the eight dark-matter members next to this
+            // baryon along the curve (baryons and dark matter share the key)
+            const uint64_t kb = bkey[bi];
+            int lo = d0, hi = d1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (t.dkey[mid] < kb) lo = mid + 1;
+                else hi = mid;
+            }
+            const int q0 = max(d0, min(lo - 4, d1 - 8)), q1 = min(d1, q0 + 8);
+            for (int q = q0; q < q1; ++q) {
+                const int ddx = min_image((int)t.sx[q] - px, gb);
+                const int ddy = min_image((int)t.sy[q] - py, gb);
+                const int ddz = min_image((int)t.sz[q] - pz, gb);
+                const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+                const double ax = bx - (double)t.svx[q], ay = by - (double)t.svy[q], az = bz - (double)t.svz[q];
+                consider(bst, d2 / ell2 + (ax * ax + ay * ay + az * az) / sv2, t.sj[q]);
+            }
+        }
         // the packet's box, and the margins for the rounding of the scaled
         // coordinates (a few ulps of the largest of them)
         float qlo[6], qhi[6], amax = 0.f;
@@ -910,6 +932,7 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         t.svy = svy;
         t.svz = svz;
         t.sj = sj;
+        t.dkey = key;
     }
     // level sizes: runs of 64 per host, up to one node per host
     std::vector<uint32_t> doff(n_hosts + 1);
@@ -954,24 +977,24 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         VR_LAUNCH_CHECK(ctx);
     }
     VR_WS(blist, ctx, int32_t, WS_A3, nb + 1);
+    VR_WS(bkey, ctx, uint64_t, WS_A5, nb + 1);
     hipLaunchKernelGGL(k_baryon_list, dim3(grid_for(M, 256)), dim3(256), 0, st, M, flag, pos, blist);
     VR_LAUNCH_CHECK(ctx);
-    if (nb > 1) {
-        VR_WS(bkey, ctx, uint64_t, WS_D2, nb);
+    if (nb > 0) {
         hipLaunchKernelGGL(k_bkey6, dim3(grid_for(nb, 256)), dim3(256), 0, st, nb, blist, host_members, owner, p->qx,
                            p->qy, p->qz, p->vx, p->vy, p->vz, hbox, gb, ix, iv, mbits, bkey);
         VR_LAUNCH_CHECK(ctx);
-        if ((rc = sort_pairs_u64(ctx, bkey, reinterpret_cast<uint32_t*>(blist), nb, hbits + 6 * mbits, st)))
-            return rc;
     }
+    if (nb > 1 && (rc = sort_pairs_u64(ctx, bkey, reinterpret_cast<uint32_t*>(blist), nb, hbits + 6 * mbits, st)))
+        return rc;
     hipLaunchKernelGGL(k_assign_dm, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, is_baryon, sub, 0, out);
     VR_LAUNCH_CHECK(ctx);
     if (nb > 0) {
         VR_TIMED(ctx, "assign_baryons", st, nb,
                  hipLaunchKernelGGL(k_assign6, dim3((unsigned)((nb + 64 * T6_WAVES - 1) / (64 * T6_WAVES))),
                                     dim3(64 * T6_WAVES), 0, st, nb, blist,
-                                    host_members, owner, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, t, gb, u * u,
-                                    sigma_v * sigma_v, ix, iv, out));
+                                    host_members, owner, sub, p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, bkey, t, gb,
+                                    u * u, sigma_v * sigma_v, ix, iv, out));
         VR_LAUNCH_CHECK(ctx);
     }
     return VR_OK;
