@@ -69,8 +69,10 @@ __device__ __forceinline__ void wave_atomic_min(int* base, int key, int val, boo
         int v = valid ? val : 0x7FFFFFFF;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-        if ((int)__lane_id() == first) atomicMin(&base[k0], v);
-    } else if (valid) {
+        // values only decrease: a plain read that is already no larger
+        // makes the atomic unnecessary (a stale read only costs the atomic)
+        if ((int)__lane_id() == first && v < base[k0]) atomicMin(&base[k0], v);
+    } else if (valid && val < base[key]) {
         atomicMin(&base[key], val);
     }
 }
