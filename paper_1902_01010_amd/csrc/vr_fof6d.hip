@@ -410,12 +410,15 @@ __global__ void k_iota_i(int64_t n, int* p) {
 }
 
 __global__ void k_compress_min(int64_t np, int* parent, const int32_t* __restrict__ sorig, int* __restrict__ mn) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    int r = (int)p;
-    while (parent[r] != r) r = parent[r];
-    parent[p] = r;
-    atomicMin(&mn[r], sorig[p]);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < np;
+    int r = valid ? (int)p : 0;
+    if (valid) {
+        while (parent[r] != r) r = parent[r];
+        parent[p] = r;
+    }
+    // every lane takes part: neighbours in cell order mostly share a root
+    wave_atomic_min(mn, r, valid ? sorig[p] : 0x7FFFFFFF, valid);
 }
 
 __global__ void k_label6(int64_t np, const int* __restrict__ parent, const int32_t* __restrict__ sorig,
