@@ -379,17 +379,19 @@ __global__ void k_leaf_bbox(int nl, const int* __restrict__ leaves, KdNode* node
 }
 
 // Members by position in list-0 order, and the smallest index of each leaf.
+// c0..c2: the coordinates already in list-0 order, or null (then gathered).
 __global__ void k_final(int64_t M, const int* __restrict__ l0, const int* __restrict__ seg_node,
                         const int* __restrict__ u0, const int* __restrict__ u1, const int* __restrict__ u2,
+                        const int* __restrict__ c0, const int* __restrict__ c1, const int* __restrict__ c2,
                         const int* __restrict__ g, const float* __restrict__ m, Elems F, int* __restrict__ leaf_min) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < M;
     const int e = valid ? l0[p] : 0;
     const int gi = valid ? g[e] : 0x7FFFFFFF;
     if (valid) {
-        F.u[0][p] = u0[e];
-        F.u[1][p] = u1[e];
-        F.u[2][p] = u2[e];
+        F.u[0][p] = c0 ? c0[p] : u0[e];
+        F.u[1][p] = c0 ? c1[p] : u1[e];
+        F.u[2][p] = c0 ? c2[p] : u2[e];
         F.gidx[p] = gi;
         F.eid[p] = e;
         if (m) F.mass[p] = m[e];
@@ -630,8 +632,9 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     hipLaunchKernelGGL(k_leaf_bbox, dim3(grid_for(nleaf, 256)), dim3(256), 0, st, nleaf, leaves, nodes, L[0], L[1],
                        L[2], U[0], U[1], U[2], leaf_min, n_hosts);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_final, dim3(gM), dim3(256), 0, st, M, L[0], seg, U[0], U[1], U[2], G,
-                       use_mass ? Ms : nullptr, F, leaf_min);
+    const bool have_c0 = mode != KD_WIDEST;
+    hipLaunchKernelGGL(k_final, dim3(gM), dim3(256), 0, st, M, L[0], seg, U[0], U[1], U[2], have_c0 ? C0[0] : nullptr,
+                       have_c0 ? C0[1] : nullptr, have_c0 ? C0[2] : nullptr, G, use_mass ? Ms : nullptr, F, leaf_min);
     VR_LAUNCH_CHECK(ctx);
     tree.nodes = nodes;
     tree.leaves = leaves;
