@@ -71,9 +71,11 @@ __global__ void k_ub_zero(int na, const int* __restrict__ active, const int32_t*
     for (int k = s + threadIdx.x; k < e; k += blockDim.x) acc[k] = 0.0;
 }
 
-// Sum over staged j of m_j / sqrt(r^2 + eps^2) for one i, in FP32 (at most
-// 64 terms, R18).  CHECK = the chunk may hold j == i or, with eps = 0, a
-// coincident pair; otherwise every term is finite and taken.
+// Sum over staged j of m_j / sqrt(r^2 + eps^2) for one i, in FP32 over at
+// most 64 terms (the caller adds it to an FP64 accumulator; 64 same-sign
+// FP32 terms stay within 64 * 2^-24 relative).  CHECK = the chunk may hold
+// j == i or, with eps = 0, a coincident pair; otherwise every term is
+// finite and taken.
 template <bool UNIFORM, bool CHECK>
 __device__ __forceinline__ float tile_sum(const float4* __restrict__ sj, int t0, int t1, float xi, float yi, float zi,
                                           float eps2, int jbase, int i) {
