@@ -552,11 +552,18 @@ int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree
 // W allows.  The n_v velocity neighbours are then taken from the n_se by
 // repeated wave-wide minima of (FP64 dv2, rank).
 constexpr int BIG_CAP = 256;              // largest n_se
-constexpr int BIG_BUF = BIG_CAP + 128;    // n_se kept + up to 127 appended
+constexpr int BIG_EXTRA = 192;            // keys appended past n_se before the buffer is cut back
+constexpr int BIG_BUF = BIG_CAP + BIG_EXTRA + 64;  // room for one more leaf chunk
 constexpr int BIG_J = BIG_BUF / 64;       // buffer slots per lane
 
 // The r-th smallest (0-based) of the valid keys k[j] of all lanes.
-__device__ __forceinline__ uint64_t wave_select(const uint64_t (&k)[BIG_J], const bool (&v)[BIG_J], int r) {
+// The key of rank r (0-based) among the valid keys of the wavefront, by a
+// radix select over byte digits: per digit, a histogram of the keys that
+// share the digits chosen so far, and a wave-wide prefix over its 256
+// buckets to find the one holding rank r.  Keys are distinct.  hist: 256
+// words of LDS.
+__device__ __forceinline__ uint64_t wave_select(const uint64_t (&k)[BIG_J], const bool (&v)[BIG_J], int r,
+                                                uint32_t* hist) {
     uint64_t lo = ~0ull, hi = 0;
 #pragma unroll
     for (int j = 0; j < BIG_J; ++j)
@@ -569,19 +576,49 @@ __device__ __forceinline__ uint64_t wave_select(const uint64_t (&k)[BIG_J], cons
         hi = max(hi, (uint64_t)__shfl_xor((unsigned long long)hi, o, 64));
     }
     if (lo == hi) return lo;
-    // bits above the highest differing one are those of every key
-    const int top = 63 - __clzll(lo ^ hi);
-    uint64_t prefix = top == 63 ? 0 : (lo >> (top + 1)) << (top + 1);
-    for (int bit = top; bit >= 0; --bit) {
-        const uint64_t above = bit == 63 ? 0 : (~0ull << (bit + 1));
-        int c = 0;
+    const int lane = (int)lane_id();
+    // digits above the highest differing byte are those of every key
+    int shift = ((63 - __clzll(lo ^ hi)) >> 3) << 3;
+    uint64_t above = shift + 8 >= 64 ? 0 : ~0ull << (shift + 8);
+    uint64_t prefix = lo & above;
+    for (;;) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hist[4 * lane + t] = 0;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j = 0; j < BIG_J; ++j)
-            c += __popcll(__ballot(v[j] && (k[j] & above) == prefix && !((k[j] >> bit) & 1)));
-        if (r >= c) {
-            r -= c;
-            prefix |= uint64_t(1) << bit;
+            if (v[j] && (k[j] & above) == prefix) atomicAdd(&hist[(k[j] >> shift) & 255], 1u);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t c[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) c[t] = hist[4 * lane + t];
+        const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
         }
+        const uint32_t excl = incl - sum;
+        // the lane whose buckets span rank r names the digit
+        int digit = -1;
+        uint32_t below = excl;
+        if ((uint32_t)r >= excl && (uint32_t)r < incl) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (digit < 0 && (uint32_t)r < below + c[t]) digit = 4 * lane + t;
+                else if (digit < 0) below += c[t];
+            }
+        }
+        const uint64_t owner = __ballot(digit >= 0);
+        const int src = __builtin_ctzll(owner);
+        digit = __shfl(digit, src, 64);
+        below = __shfl(below, src, 64);
+        r -= (int)below;
+        prefix |= (uint64_t)digit << shift;
+        __builtin_amdgcn_wave_barrier();
+        if (shift == 0) break;
+        above = ~0ull << shift;
+        shift -= 8;
     }
     return prefix;
 }
@@ -595,6 +632,7 @@ __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpo
                                                 int64_t n, int n_se, int n_v, int use_mass, double mass_value, int gb,
                                                 float* __restrict__ R, unsigned xchunk) {
     __shared__ uint64_t buf[BIG_BUF];
+    __shared__ uint32_t sel_hist[256];
     __shared__ int stack[STACK];
     __shared__ double sel_d[32];
     __shared__ int sel_p[32];
@@ -616,7 +654,7 @@ __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpo
             v[j] = lane + 64 * j < nb;
             k[j] = v[j] ? buf[lane + 64 * j] : 0;
         }
-        const uint64_t T = wave_select(k, v, n_se - 1);
+        const uint64_t T = wave_select(k, v, n_se - 1, sel_hist);
         __builtin_amdgcn_wave_barrier();
         int at = 0;
 #pragma unroll
@@ -647,7 +685,7 @@ __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpo
             if (take) buf[nb + __popcll(m & lanemask_lt())] = key;
             nb += __popcll(m);
             __builtin_amdgcn_wave_barrier();
-            if (nb >= n_se + 64) compact();
+            if (nb >= n_se + BIG_EXTRA) compact();
         }
     };
     if (lane == 0) stack[0] = h;
