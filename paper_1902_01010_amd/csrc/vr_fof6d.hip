@@ -332,28 +332,61 @@ __device__ __forceinline__ void for_relaxed(int64_t p, const ckey_t* __restrict_
     }
 }
 
-// One synchronous growth round: an untagged participant takes the smallest
-// tag among its relaxed neighbours tagged in the previous round.
-__global__ __launch_bounds__(256) void k_grow(int64_t np, const ckey_t* __restrict__ key,
-                                              const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
-                                              const uint32_t* __restrict__ sz, const int32_t* __restrict__ shost,
-                                              const uint32_t* __restrict__ cell_start, const ckey_t* __restrict__ hkeys,
-                                              const uint32_t* __restrict__ hvals, uint32_t hmask, int b, int gb,
-                                              double ell2, SubLink sub, const int32_t* __restrict__ tin,
-                                              int32_t* __restrict__ tout, int* __restrict__ changed) {
+// Synchronous growth rounds: an untagged participant takes the smallest tag
+// among its relaxed neighbours tagged in the previous round.
+// Appends val for each taking lane: one atomic per wavefront.  Every lane of
+// the wavefront must call it.
+__device__ __forceinline__ void wave_append(int* counter, int32_t* list, bool take, int32_t val) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lane = (int)lane_id();
+    const int first = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == first) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, first, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
+// The rounds are pushed from the frontier (the particles tagged in the
+// previous round).  An untagged participant can only border particles
+// tagged in the previous round (a tagged neighbour of an earlier round would
+// have tagged it already), and the relaxed link is symmetric, so the
+// smallest tag pushed to it is the one it would pull.
+__global__ void k_frontier_init(int64_t np, const int32_t* __restrict__ tag, int32_t* __restrict__ prop,
+                                int32_t* __restrict__ front, int* __restrict__ nfront) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    if (tin[p] >= 0) {
-        tout[p] = tin[p];
-        return;
-    }
-    int m = -1;
+    const bool valid = p < np;
+    if (valid) prop[p] = INT_MAX;
+    wave_append(nfront, front, valid && tag[p] >= 0, (int32_t)p);
+}
+
+__global__ __launch_bounds__(256) void k_grow_push(int nf, const int32_t* __restrict__ front, const ckey_t* __restrict__ key,
+                                                   const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
+                                                   const uint32_t* __restrict__ sz, const int32_t* __restrict__ shost,
+                                                   const uint32_t* __restrict__ cell_start,
+                                                   const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                                   uint32_t hmask, int b, int gb, double ell2, SubLink sub,
+                                                   const int32_t* __restrict__ tag, int32_t* __restrict__ prop) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int p = front[i];
+    const int t = tag[p];
     for_relaxed(p, key, sx, sy, sz, shost, cell_start, hkeys, hvals, hmask, b, gb, ell2, sub, [&](int q) {
-        const int t = tin[q];
-        if (t >= 0 && (m < 0 || t < m)) m = t;
+        if (tag[q] < 0) atomicMin(&prop[q], t);
     });
-    tout[p] = m;
-    if (m >= 0) atomicOr(changed, 1);
+}
+
+__global__ void k_grow_apply(int64_t np, int32_t* __restrict__ tag, int32_t* __restrict__ prop,
+                             int32_t* __restrict__ front, int* __restrict__ nfront) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = q < np;
+    const int v = valid ? prop[q] : INT_MAX;
+    const bool got = v != INT_MAX;
+    if (got) {
+        tag[q] = v;
+        prop[q] = INT_MAX;
+    }
+    wave_append(nfront, front, got, (int32_t)q);
 }
 
 // Relaxed links between different groups (each unordered link once, from its
@@ -693,19 +726,28 @@ extern "C" int vr_sub_grow(vr_ctx* ctx, const vr_particles* p, const int32_t* ho
     const SubLink sl{su0, su1, su2, ss, gamma_V * Vr, cos_op_relaxed};
     const int b = gb - sb;
     const dim3 g(grid_for(np, 256));
-    // growth rounds until nothing changes
+    // growth rounds until nothing changes, pushed from each round's frontier
+    VR_WS(front, ctx, int32_t, WS_D8, np);
+    int* nfront = bad + 1;
+    int32_t* prop = tagB;
+    if ((rc = fill_i32(ctx, nfront, 0, 1, st))) return rc;
+    hipLaunchKernelGGL(k_frontier_init, g, dim3(256), 0, st, np, tagA, prop, front, nfront);
+    VR_LAUNCH_CHECK(ctx);
+    VR_HIP(ctx, hipMemcpyAsync(pin, nfront, sizeof(int), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipStreamSynchronize(st));
     int nr = 0;
-    for (;;) {
-        if ((rc = fill_i32(ctx, bad, 0, 1, st))) return rc;
-        VR_TIMED(ctx, "sub_grow", st, np,
-                 hipLaunchKernelGGL(k_grow, g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, shost, cl.cell_start,
-                                    cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, sl, tagA, tagB, bad));
+    for (int nf = pin[0]; nf > 0;) {
+        VR_TIMED(ctx, "sub_grow", st, nf,
+                 hipLaunchKernelGGL(k_grow_push, dim3(grid_for(nf, 256)), dim3(256), 0, st, nf, front, cl.key, cl.sx,
+                                    cl.sy, cl.sz, shost, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, sl,
+                                    tagA, prop));
+        if ((rc = fill_i32(ctx, nfront, 0, 1, st))) return rc;
+        hipLaunchKernelGGL(k_grow_apply, g, dim3(256), 0, st, np, tagA, prop, front, nfront);
         VR_LAUNCH_CHECK(ctx);
-        VR_HIP(ctx, hipMemcpyAsync(pin, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        VR_HIP(ctx, hipMemcpyAsync(pin, nfront, sizeof(int), hipMemcpyDeviceToHost, st));
         VR_HIP(ctx, hipStreamSynchronize(st));
-        std::swap(tagA, tagB);
-        if (!pin[0]) break;
-        ++nr;
+        nf = pin[0];
+        if (nf > 0) ++nr;
     }
     if (rounds) *rounds = nr;
     // relaxed links between different groups: count, then collect
