@@ -211,6 +211,15 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const ckey_t* __rest
     // from the divided form by a few ulps, so only t within 1e-9 of 1 needs
     // the divided form itself
     const double rl2 = 1.0 / ell2, rv2 = 1.0 / ev2;
+    // p's root, refreshed only when a partner's differs (components only
+    // merge), so a link inside one component costs a single find
+    int rp = uf_find(parent, (int)p);
+    auto join = [&](int q) __attribute__((always_inline)) {
+        const int rq = uf_find(parent, q);
+        if (rq == rp) return;
+        rp = uf_find(parent, rp);
+        if (rp != rq) uf_union(parent, rp, rq);
+    };
     ckey_t seen[HALF ? 1 : 27];
     int nseen = 0;
     for (int o = 0; o < 27; ++o) {
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const ckey_t* __rest
                 const double sq = sub.s[q];
                 if (!(sq > 0) || !(sp <= sub.Vr * sq && sq <= sub.Vr * sp)) continue;
                 const double dot = up0 * sub.u0[q] + up1 * sub.u1[q] + up2 * sub.u2[q];
-                if (dot >= sub.cos_op * (sp * sq)) uf_union(parent, (int)p, (int)q);
+                if (dot >= sub.cos_op * (sp * sq)) join((int)q);
                 continue;
             }
             const double ax = vpx - (double)svx[q], ay = vpy - (double)svy[q], az = vpz - (double)svz[q];
@@ -250,7 +259,7 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const ckey_t* __rest
             const double ta = d2 * rl2 + dv2 * rv2;
             bool link = ta < 1.0 - 1e-9;
             if (!link && ta <= 1.0 + 1e-9) link = d2 / ell2 + dv2 / ev2 < 1.0;
-            if (link) uf_union(parent, (int)p, (int)q);
+            if (link) join((int)q);
         }
     }
 }
