@@ -2,20 +2,21 @@
 // Sec. 2.4, Eq. baryondist).
 //
 // 3D FOF with dark-matter-seeded links: the dark matter is compacted and
-// linked by the ordinary 3D FOF; then every baryon scans the 27 cells (of
-// side >= ellx) of a cell list of the dark matter around it and is united,
-// in one lock-free union-find over all particles seeded with the dark-matter
-// components, with every dark-matter particle closer than ellx.  Baryons
-// never test each other.  Union by smaller root keeps the smallest index of
-// a component at its root.
+// linked by the ordinary 3D FOF; then every baryon scans the cells (of side
+// >= ellx) of a cell list of the dark matter around it, its own first, and
+// joins every dark-matter component with a member closer than ellx.  A
+// baryon hangs below the root of the first component it meets; one that
+// meets a second bridges the two roots by the lock-free union-find.
+// Baryons never test each other.  Labels are the smallest index over each
+// component (a baryon may be smaller than its dark-matter root).
 //
-// Baryon assignment: each baryon of a host looks for the host's dark matter
-// nearest in phase space, D2 = d2 / ell2 + dv2 / sigma_v^2, on a cell list
-// of the hosts' dark matter, ring by ring of cells around its own; once the
-// nearest possible spatial term of the next ring exceeds the best D2 found,
-// nothing further can tie or beat it.  A first pass on cells 8 times finer
-// than ellx settles most baryons within two rings; the others search the
-// ellx grid for up to 8 rings, then all the dark matter of their host.
+// Baryon assignment: each baryon of a host takes the label of the host's
+// dark matter nearest in phase space, D2 = d2 / ell2 + dv2 / sigma_v^2.  A
+// host's dark matter is ordered along a six-dimensional Morton curve of the
+// scaled coordinates and boxed in a fanout-64 tree; 64 baryons adjacent on
+// the same curve walk it together in one wavefront, each lane starting from
+// the dark matter next to it on the curve.  Members are scored with the
+// exact D2, so the answer is that of a brute-force scan.
 #include "vr_grid.h"
 #include "vr_kd.h"
 
