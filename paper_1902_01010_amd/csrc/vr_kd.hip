@@ -11,7 +11,11 @@
 // per member, and a stable partition of each list by a global prefix sum
 // (subtracting the prefix at the segment start makes it segmented).  No
 // node is ever handled by a single workgroup, so the few huge top-level
-// nodes cost no more per member than the many small ones.
+// nodes cost no more per member than the many small ones.  The levels and
+// the active-node counts that size their launches follow from the host
+// sizes alone, so the whole build is queued without waiting on the device;
+// the kernels read the true counts, which only nodes of coincident members
+// (kept as leaves) make smaller.
 #include "vr_kd.h"
 
 #include <climits>
