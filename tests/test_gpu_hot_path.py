@@ -76,6 +76,47 @@ def test_cell_moments_parity(ctx, ref, case):
         np.testing.assert_allclose(g[fin], e[fin], rtol=2e-6, atol=1e-6 * np.abs(e[fin]).max())
 
 
+def test_cells_and_R_with_coincident_members(ctx, vr, ref):
+    """Hosts holding groups of exactly coincident members, larger than a
+    cell: KD nodes that cannot be split stay leaves (fewer nodes than the
+    member counts alone would give), and the neighbour sets meet exact
+    distance ties, broken by particle index."""
+    rng = np.random.default_rng(17)
+    c = 1 << 20
+    parts, host = [], []
+    for h, (groups, spread) in enumerate([((150, 150, 150), 450), ((200, 200), 300)]):
+        base = np.array([c + 400000 * h, c, c])[:, None]
+        for g in groups:
+            parts.append(np.repeat(base + rng.integers(-3000, 3000, (3, 1)), g, axis=1))
+            host += [h] * g
+        parts.append(base + rng.normal(0, 3000, (3, spread)).astype(np.int64))
+        host += [h] * spread
+    q = np.concatenate(parts, 1).astype(np.uint32)
+    host = np.array(host)
+    n = q.shape[1]
+    perm = rng.permutation(n)
+    q, host = np.ascontiguousarray(q[:, perm]), host[perm]
+    v = rng.normal(0, 100, (3, n)).astype(np.float32)
+    Pr = ref.Particles(q, v, None, 1.0, 1.0, 21)
+    P = vr.Particles(dev_tensor(q), dev_tensor(v), None, 1.0, 1.0, 21)
+    hmem = np.concatenate([np.nonzero(host == 0)[0], np.nonzero(host == 1)[0]]).astype(np.int32)
+    hoff = np.array([0, (host == 0).sum(), n], np.int32)
+    exp = ref.cell_moments(Pr, hoff, hmem)
+    got = ctx.cell_moments(P, dev_tensor(hoff), dev_tensor(hmem))
+    assert got["n_cells"] == exp["cells"].shape[0]
+    assert (got["cell_of"].cpu().numpy() == exp["cell_of"]).all()
+    for k in ("vbar", "sigma"):
+        g, e = got[k].cpu().numpy(), exp[k]
+        fin = np.isfinite(e)
+        assert (np.isfinite(g) == fin).all()
+        np.testing.assert_allclose(g[fin], e[fin], rtol=2e-6, atol=1e-6 * np.abs(e[fin]).max())
+    for n_se, n_v in [(32, 8), (48, 16), (100, 20)]:
+        e = ref.local_vdensity(Pr, hoff, hmem, exp["vbar"], exp["sigma"], n_se, n_v)["R"]
+        g = ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(exp["vbar"]),
+                               dev_tensor(exp["sigma"]), n_se, n_v).cpu().numpy()
+        _R_close(g, e)
+
+
 def test_host_ellv_parity(ctx, ref, case):
     P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
     exp = ref.host_ellv(Pr, hoff, hmem, 1.25)
