@@ -166,7 +166,8 @@ int vr_cell_moments(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
  * n_se = 32 a workgroup's LDS heaps cut the occupancy), every host has
  * >= n_se members.  subset (may be NULL = all host members) lists the particles to
  * process; R is written only for them (NaN if sigma is not positive
- * definite, +inf if h = 0). */
+ * definite, +inf if h = 0).  VR_ERR_INVALID_ARG, with nothing written to R,
+ * if host_members lists a particle twice or one outside [0, n). */
 int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
                       const int32_t* host_offsets, const int32_t* host_members,
                       const float* vbar, const float* sigma, int32_t n_se, int32_t n_v,

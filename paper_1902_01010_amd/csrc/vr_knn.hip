@@ -33,20 +33,6 @@ constexpr int POS_BITS = 22;
 constexpr uint64_t POS_MASK = (uint64_t(1) << POS_BITS) - 1;
 constexpr int STACK = 128;
 
-// Velocities (and masses) by element id, i.e. in host-member order.
-__global__ void k_gather_vel(int64_t M, const int* __restrict__ mem, const float* __restrict__ vx,
-                             const float* __restrict__ vy, const float* __restrict__ vz, const float* __restrict__ mass,
-                             float* __restrict__ px, float* __restrict__ py, float* __restrict__ pz,
-                             float* __restrict__ pm) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    const int g = mem[k];
-    px[k] = vx[g];
-    py[k] = vy[g];
-    pz[k] = vz[g];
-    if (mass) pm[k] = mass[g];
-}
-
 __global__ void k_pos_of(int64_t M, const int* __restrict__ gidx, int* __restrict__ pos_of) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < M) pos_of[gidx[k]] = (int)k;
@@ -96,6 +82,35 @@ __device__ __forceinline__ double log_fbg(const float* __restrict__ sigma, const
     return lfb;
 }
 
+// rank_of[g] = the position of particle g in host_members (-1 beforehand);
+// a member outside [0, n) or listed twice raises *bad
+__global__ void k_rank_of(int64_t M, int64_t n, const int* __restrict__ mem, int* __restrict__ rank_of,
+                          int* __restrict__ bad) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const int g = mem[k];
+    if (g < 0 || g >= n || atomicExch(&rank_of[g], (int)k) != -1) atomicOr(bad, 1);
+}
+
+// Per host member, at its host rank: (vx, vy, vz, mass) as one 16-byte
+// record, so a neighbour's velocity and mass are one cache line, and the
+// member's ln f_bg, so a query reads 8 bytes instead of nine floats spread
+// over nine arrays.  The pass runs in particle order, where its 12 input
+// arrays are read in full lines; a host's members are scattered over the
+// whole particle range, so a pass in rank order would fetch a line per value.
+__global__ void k_member_records(int64_t n, const int* __restrict__ rank_of, const float* __restrict__ vx,
+                                 const float* __restrict__ vy, const float* __restrict__ vz,
+                                 const float* __restrict__ mass, const float* __restrict__ vbar,
+                                 const float* __restrict__ sigma, float4* __restrict__ V, double* __restrict__ FB) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int k = rank_of[g];
+    if (k < 0) return;
+    const float ux = vx[g], uy = vy[g], uz = vz[g];
+    V[k] = make_float4(ux, uy, uz, mass ? mass[g] : 0.f);
+    FB[k] = log_fbg(sigma, vbar, n, (int)g, (double)ux, (double)uy, (double)uz);
+}
+
 __device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { return a < b || (a == b && pa < pb); }
 
 // NSE: heap capacity (n_se <= NSE).  NVR > 0: exactly NVR velocity
@@ -104,10 +119,8 @@ __device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { retu
 template <int NSE, int NVR, int NVLMAX>
 __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, int64_t nq,
                                             const KdNode* __restrict__ nodes, Elems F, const int* __restrict__ leaf_of,
-                                            const float* __restrict__ Vx, const float* __restrict__ Vy,
-                                            const float* __restrict__ Vz, const float* __restrict__ Me,
+                                            const float4* __restrict__ V, const double* __restrict__ FB,
                                             const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
-                                            const float* __restrict__ vbar, const float* __restrict__ sigma, int64_t n,
                                             int n_se, int n_v, int use_mass, double mass_value, int gb,
                                             float* __restrict__ R, unsigned xchunk) {
     constexpr int NVL = NVR > 0 ? 1 : NVLMAX;
@@ -436,7 +449,8 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     // velocity neighbours among the spatial ones, by (dv2, index); velocities
     // and masses are indexed by element id = host base + rank
     const int qe = F.eid[e];
-    const double vqx = (double)Vx[qe], vqy = (double)Vy[qe], vqz = (double)Vz[qe];
+    const float4 vq = V[qe];
+    const double vqx = (double)vq.x, vqy = (double)vq.y, vqz = (double)vq.z;
     double msum = 0.0;
     double h2, sw = 0.0;
     const double kW = 15.0 / (8.0 * M_PI);
@@ -453,11 +467,11 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         }
 #pragma unroll
         for (int u = 0; u < VB; ++u) {
-            const int gp = base + bpos[u];
-            bvx[u] = Vx[gp];
-            bvy[u] = Vy[gp];
-            bvz[u] = Vz[gp];
-            bms[u] = use_mass ? Me[gp] : 0.f;
+            const float4 w = V[base + bpos[u]];
+            bvx[u] = w.x;
+            bvy[u] = w.y;
+            bvz[u] = w.z;
+            bms[u] = w.w;
         }
     };
     if constexpr (NVR > 0) {
@@ -488,7 +502,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         if (h2 != 0.0) {
 #pragma unroll
             for (int a = 0; a < NVR; ++a) {
-                const double m = use_mass ? (double)Me[base + vpr[a]] : mass_value;
+                const double m = use_mass ? (double)V[base + vpr[a]].w : mass_value;
                 sw += m * kW * (1.0 - vdr[a] / h2);
             }
         }
@@ -518,25 +532,21 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         h2 = vd[n_v - 1][lane];
         if (h2 != 0.0)
             for (int a = 0; a < n_v; ++a) {
-                const double m = use_mass ? (double)Me[base + vp[a][lane]] : mass_value;
+                const double m = use_mass ? (double)V[base + vp[a][lane]].w : mass_value;
                 sw += m * kW * (1.0 - vd[a][lane] / h2);
             }
     }
     const double lfl = h2 == 0.0 ? INFINITY : log(sw) - 1.5 * log(h2) - log(msum);
-    const int g = F.gidx[e];
-    const double lfb = log_fbg(sigma, vbar, n, g, vqx, vqy, vqz);
-    R[g] = (float)(lfl - lfb);
+    R[F.gidx[e]] = (float)(lfl - FB[qe]);
 }
 
 template <int NSE, int NVR, int NVLMAX>
-int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx, const float* Vy,
-               const float* Vz, const float* Me, const int32_t* host_off, const vr_particles* p, const float* vbar,
-               const float* sigma, int n_se, int n_v, float* R, hipStream_t st) {
+int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float4* V,
+               const double* FB, const int32_t* host_off, const vr_particles* p, int n_se, int n_v, float* R,
+               hipStream_t st) {
     VR_TIMED(ctx, "knn", st, nq,
              hipLaunchKernelGGL((k_knn<NSE, NVR, NVLMAX>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
-                                tree.F, tree.seg_node, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n,
-                                n_se, n_v,
-                                tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
+                                tree.F, tree.seg_node, V, FB, tree.elem_host, host_off, n_se, n_v, tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
@@ -625,11 +635,9 @@ __device__ __forceinline__ uint64_t wave_select(const uint64_t (&k)[BIG_J], cons
 
 __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpos, int64_t nq,
                                                 const KdNode* __restrict__ nodes, Elems F,
-                                                const float* __restrict__ Vx, const float* __restrict__ Vy,
-                                                const float* __restrict__ Vz, const float* __restrict__ Me,
+                                                const float4* __restrict__ V, const double* __restrict__ FB,
                                                 const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
-                                                const float* __restrict__ vbar, const float* __restrict__ sigma,
-                                                int64_t n, int n_se, int n_v, int use_mass, double mass_value, int gb,
+                                                int n_se, int n_v, int use_mass, double mass_value, int gb,
                                                 float* __restrict__ R, unsigned xchunk) {
     __shared__ uint64_t buf[BIG_BUF];
     __shared__ uint32_t sel_hist[256];
@@ -720,7 +728,8 @@ __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpo
     if (nb > n_se) compact();
     // the n_se spatial neighbours: velocity distances and the mass of the set
     const int qe = F.eid[e];
-    const double vqx = (double)Vx[qe], vqy = (double)Vy[qe], vqz = (double)Vz[qe];
+    const float4 vq = V[qe];
+    const double vqx = (double)vq.x, vqy = (double)vq.y, vqz = (double)vq.z;
     double dv[BIG_CAP / 64];
     int ps[BIG_CAP / 64];
     double msum = 0.0;
@@ -731,9 +740,9 @@ __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpo
         ps[j] = 0x7FFFFFFF;
         if (a < n_se) {
             const int pos = (int)(buf[a] & POS_MASK);
-            const int gp = base + pos;
-            msum += use_mass ? (double)Me[gp] : mass_value;
-            const double ax = vqx - (double)Vx[gp], ay = vqy - (double)Vy[gp], az = vqz - (double)Vz[gp];
+            const float4 w = V[base + pos];
+            msum += use_mass ? (double)w.w : mass_value;
+            const double ax = vqx - (double)w.x, ay = vqy - (double)w.y, az = vqz - (double)w.z;
             dv[j] = ax * ax + ay * ay + az * az;
             ps[j] = pos;
         }
@@ -775,22 +784,20 @@ __global__ __launch_bounds__(64) void k_knn_big(const uint32_t* __restrict__ qpo
     double sw = 0.0;
     if (h2 != 0.0)
         for (int a = 0; a < n_v; ++a) {
-            const double m = use_mass ? (double)Me[base + sel_p[a]] : mass_value;
+            const double m = use_mass ? (double)V[base + sel_p[a]].w : mass_value;
             sw += m * kW * (1.0 - sel_d[a] / h2);
         }
     const double lfl = h2 == 0.0 ? INFINITY : log(sw) - 1.5 * log(h2) - log(msum);
-    const int g = F.gidx[e];
-    R[g] = (float)(lfl - log_fbg(sigma, vbar, n, g, vqx, vqy, vqz));
+    R[F.gidx[e]] = (float)(lfl - FB[qe]);
 }
 
-int launch_knn_big(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float* Vx,
-                   const float* Vy, const float* Vz, const float* Me, const int32_t* host_off,
-                   const vr_particles* p, const float* vbar, const float* sigma, int n_se, int n_v, float* R,
+int launch_knn_big(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree, const float4* V,
+                   const double* FB, const int32_t* host_off, const vr_particles* p, int n_se, int n_v, float* R,
                    hipStream_t st) {
     if (nq > INT32_MAX) return set_err(ctx, VR_ERR_UNSUPPORTED, "too many queries for one launch");
     VR_TIMED(ctx, "knn", st, nq,
              hipLaunchKernelGGL(k_knn_big, dim3((unsigned)std::max<int64_t>(nq, 1)), dim3(64), 0, st, qpos, nq,
-                                tree.nodes, tree.F, Vx, Vy, Vz, Me, tree.elem_host, host_off, vbar, sigma, p->n, n_se,
+                                tree.nodes, tree.F, V, FB, tree.elem_host, host_off, n_se,
                                 n_v, tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
@@ -822,17 +829,27 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
     for (int h = 0; h < n_hosts; ++h)
         if ((int64_t)off[h + 1] - off[h] > (int64_t(1) << POS_BITS))
             return set_err(ctx, VR_ERR_UNSUPPORTED, "host %d has more than 2^%d members", h, POS_BITS);
+    const int64_t M = off[n_hosts];
+    VR_WS(rank_of, ctx, int32_t, WS_C2, p->n);
+    VR_WS(dup, ctx, int, WS_FLAG, 4);
+    rc = fill_i32(ctx, rank_of, -1, p->n, st);
+    if (rc) return rc;
+    rc = fill_i32(ctx, dup, 0, 1, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_rank_of, dim3(grid_for(M, 256)), dim3(256), 0, st, M, p->n, host_members, rank_of, dup);
+    VR_LAUNCH_CHECK(ctx);
+    int duph = 0;
+    rc = read_back(ctx, dup, &duph, sizeof duph, st);
+    if (rc) return rc;
+    if (duph) return set_err(ctx, VR_ERR_INVALID_ARG, "host_members lists a particle twice or outside [0, n)");
     std::vector<int> nc(n_hosts, ctx->knn_leaf);
     KdTree tree;
     rc = kd_build(ctx, p, n_hosts, host_offsets, host_members, off, nc, KD_WIDEST, 2, tree, st);
     if (rc) return rc;
-    const int64_t M = off[n_hosts];
-    VR_WS(Vx, ctx, float, WS_C0, M);
-    VR_WS(Vy, ctx, float, WS_C1, M);
-    VR_WS(Vz, ctx, float, WS_C2, M);
-    VR_WS(Me, ctx, float, WS_C3, p->mass ? M : 1);
-    hipLaunchKernelGGL(k_gather_vel, dim3(grid_for(M, 256)), dim3(256), 0, st, M, host_members, p->vx, p->vy, p->vz,
-                       p->mass, Vx, Vy, Vz, Me);
+    VR_WS(V, ctx, float4, WS_C0, M);
+    VR_WS(FB, ctx, double, WS_C1, M);
+    hipLaunchKernelGGL(k_member_records, dim3(grid_for(p->n, 256)), dim3(256), 0, st, p->n, rank_of, p->vx, p->vy,
+                       p->vz, p->mass, vbar, sigma, V, FB);
     VR_LAUNCH_CHECK(ctx);
     const uint32_t* qpos = nullptr;
     int64_t nq = M;
@@ -862,11 +879,11 @@ extern "C" int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_h
         nq = n_subset;
     }
     if (n_se <= 32 && n_v == 8)
-        return launch_knn<32, 8, 1>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 8, 1>(ctx, qpos, nq, tree, V, FB, host_offsets, p, n_se, n_v, R, st);
     if (n_se <= 32)
-        return launch_knn<32, 0, 32>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<32, 0, 32>(ctx, qpos, nq, tree, V, FB, host_offsets, p, n_se, n_v, R, st);
     if (n_se <= 64)
-        return launch_knn<64, 0, 64>(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+        return launch_knn<64, 0, 64>(ctx, qpos, nq, tree, V, FB, host_offsets, p, n_se, n_v, R, st);
     // larger sets, up to the paper's defaults (n_se 256, n_v 32): a wavefront per query
-    return launch_knn_big(ctx, qpos, nq, tree, Vx, Vy, Vz, Me, host_offsets, p, vbar, sigma, n_se, n_v, R, st);
+    return launch_knn_big(ctx, qpos, nq, tree, V, FB, host_offsets, p, n_se, n_v, R, st);
 }

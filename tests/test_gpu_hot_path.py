@@ -166,6 +166,20 @@ def test_local_vdensity_rejects_sizes(ctx, vr, case):
                                n_v)
 
 
+def test_local_vdensity_rejects_bad_members(ctx, vr, case):
+    # a particle listed twice, or an index outside [0, n), is an error raised
+    # before any kernel reads through the member list; R stays untouched
+    P, hoff, hmem = case["P"], case["hoff"], case["hmem"]
+    z = torch.zeros(3 * P.n, dtype=torch.float32, device="cuda")
+    s = torch.ones(6 * P.n, dtype=torch.float32, device="cuda")
+    m = np.asarray(hmem).copy()
+    for bad in (np.r_[m[:1], m[:-1]], np.r_[m[:-1], P.n], np.r_[-1, m[1:]]):
+        R = torch.full((P.n,), 7.0, dtype=torch.float32, device="cuda")
+        with pytest.raises(vr.VrError, match="twice or outside"):
+            ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(bad.astype(np.int32)), z, s, 8, 4, R=R)
+        assert bool((R == 7.0).all())
+
+
 def test_local_vdensity_end_to_end(ctx, ref, case):
     P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
     cm = ref.cell_moments(Pr, hoff, hmem)
