@@ -141,6 +141,8 @@ int check_hosts(vr_ctx* ctx, int32_t n_hosts, const int32_t* off, const int32_t*
 // through *total_dev (device pointer, may be null).
 int scan_u32(vr_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev,
              hipStream_t s);
+// Exclusive prefix sum of n bytes into n uint32 values (in and out distinct).
+int scan_u8(vr_ctx* ctx, const uint8_t* in, uint32_t* out, int64_t n, hipStream_t s);
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).  Keys
 // and values are sorted in place (the buffers are overwritten).
 int sort_pairs_u32(vr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits,

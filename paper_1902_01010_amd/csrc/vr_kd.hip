@@ -309,13 +309,13 @@ __global__ void k_flags(int64_t M, const int* __restrict__ seg_node, const KdNod
 // The left flags of the three lists at once (list j at lf[j * M + p]).
 __global__ void k_lflag3(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
                          const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
-                         const uint8_t* __restrict__ flag, uint32_t* __restrict__ lf) {
+                         const uint8_t* __restrict__ flag, uint8_t* __restrict__ lf) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
     const bool split = nodes[seg_node[p]].dim >= 0;
-    lf[p] = split ? (uint32_t)flag[l0[p]] : 0u;
-    lf[M + p] = split ? (uint32_t)flag[l1[p]] : 0u;
-    lf[2 * M + p] = split ? (uint32_t)flag[l2[p]] : 0u;
+    lf[p] = split ? flag[l0[p]] : (uint8_t)0;
+    lf[M + p] = split ? flag[l1[p]] : (uint8_t)0;
+    lf[2 * M + p] = split ? flag[l2[p]] : (uint8_t)0;
 }
 
 // Stable partition of the three lists inside every split node (the scan
@@ -455,6 +455,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     const int64_t MC = mode != KD_WIDEST ? M : 1;
     float* Ms;
     uint8_t* flag;
+    uint8_t* lf8;
     uint32_t* lf;
     uint64_t* pkey;
     KdNode* nodes;
@@ -470,6 +471,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         for (int d = 0; d < 3; ++d) C0alt[d] = cv.add<int>(MC);
         seg = cv.add<int>(M);
         flag = cv.add<uint8_t>(M);
+        lf8 = cv.add<uint8_t>(3 * M);
         lf = cv.add<uint32_t>(3 * M + 1);
         pkey = cv.add<uint64_t>(M);
         nodes = cv.add<KdNode>(node_cap);
@@ -608,9 +610,9 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         VR_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_flags, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag);
         VR_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_lflag3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf);
+        hipLaunchKernelGGL(k_lflag3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf8);
         VR_LAUNCH_CHECK(ctx);
-        if ((rc = scan_u32(ctx, lf, lf, 3 * M, nullptr, st))) return rc;
+        if ((rc = scan_u8(ctx, lf8, lf, 3 * M, st))) return rc;
         CoordsL0 cl0{};
         if (mode != KD_WIDEST) cl0 = CoordsL0{{C0[0], C0[1], C0[2]}, {C0alt[0], C0alt[1], C0alt[2]}};
         hipLaunchKernelGGL(k_part3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf, Lalt[0],

@@ -99,6 +99,66 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t* in, u
     (void)part_raw;
 }
 
+// Byte-input scan (0/1 flags): a lane's eight bytes are one 8-byte word, so
+// the flags cost a quarter of the traffic of a uint32 scan's input.
+__device__ __forceinline__ uint32_t byte_sum(uint32_t x) {
+    return (x & 255u) + ((x >> 8) & 255u) + ((x >> 16) & 255u) + (x >> 24);
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce_u8(const uint8_t* in, int64_t n, uint32_t* part) {
+    __shared__ uint32_t sm[8];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+    if ((((uintptr_t)in) & 7) == 0 && base + SCAN_ITEMS <= n) {
+        const uint2 w = *reinterpret_cast<const uint2*>(in + base);
+        s = byte_sum(w.x) + byte_sum(w.y);
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j)
+            if (base + j < n) s += in[base + j];
+    }
+    uint32_t tot;
+    block_excl_scan(s, sm, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply_u8(const uint8_t* in, uint32_t* out, int64_t n,
+                                                              const uint32_t* part_scanned) {
+    __shared__ uint32_t sm[8];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    const bool full = (int64_t)(blockIdx.x + 1) * SCAN_TILE <= n;
+    uint32_t v[SCAN_ITEMS];
+    if (full && (((uintptr_t)in) & 7) == 0) {
+        const uint2 w = *reinterpret_cast<const uint2*>(in + base);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = (w.x >> (8 * j)) & 255u;
+            v[4 + j] = (w.y >> (8 * j)) & 255u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) v[j] = base + j < n ? (uint32_t)in[base + j] : 0u;
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) s += v[j];
+    uint32_t off = block_excl_scan(s, sm, nullptr) + (part_scanned ? part_scanned[blockIdx.x] : 0u);
+    uint32_t o[SCAN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        o[j] = off;
+        off += v[j];
+    }
+    if (full && (((uintptr_t)out) & 15) == 0) {
+        reinterpret_cast<uint4*>(out + base)[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        reinterpret_cast<uint4*>(out + base)[1] = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j)
+            if (base + j < n) out[base + j] = o[j];
+    }
+}
+
 template <class T>
 __global__ void k_fill(T* p, T v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -270,6 +330,30 @@ int scan_u32(vr_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t n, uint32_t
     if (rc) return rc;
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part, total_dev,
                        nb, nullptr);
+    VR_LAUNCH_CHECK(ctx);
+    return VR_OK;
+}
+
+int scan_u8(vr_ctx* ctx, const uint8_t* in, uint32_t* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return VR_OK;
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply_u8, dim3(1), dim3(SCAN_BLOCK), 0, s, in, out, n, nullptr);
+        VR_LAUNCH_CHECK(ctx);
+        return VR_OK;
+    }
+    // the tile sums take the second scratch slot: scan_u32 below keeps its
+    // own partials in the first, and needs the second only beyond
+    // SCAN_TILE^2 tile sums
+    if (nb > (int64_t)SCAN_TILE * SCAN_TILE)
+        return set_err(ctx, VR_ERR_UNSUPPORTED, "byte scan of %lld elements too deep", (long long)n);
+    uint32_t* part = wsT<uint32_t>(ctx, WS_SCAN_TMP2, nb);
+    if (!part) return VR_ERR_OUT_OF_MEMORY;
+    hipLaunchKernelGGL(k_scan_reduce_u8, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part);
+    VR_LAUNCH_CHECK(ctx);
+    int rc = scan_u32(ctx, part, part, nb, nullptr, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scan_apply_u8, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part);
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
