@@ -312,10 +312,14 @@ __global__ void k_lflag3(int64_t M, const int* __restrict__ seg_node, const KdNo
                          const uint8_t* __restrict__ flag, uint8_t* __restrict__ lf) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
-    const bool split = nodes[seg_node[p]].dim >= 0;
-    lf[p] = split ? flag[l0[p]] : (uint8_t)0;
-    lf[M + p] = split ? flag[l1[p]] : (uint8_t)0;
-    lf[2 * M + p] = split ? flag[l2[p]] : (uint8_t)0;
+    const KdNode& nd = nodes[seg_node[p]];
+    const int dim = nd.dim;
+    // the list sorted along the split dimension has its flag by position,
+    // as k_flags set it; only the other two lists gather
+    const uint8_t own = (p - nd.start) < (nd.end - nd.start) / 2 ? 1 : 0;
+    lf[p] = dim < 0 ? (uint8_t)0 : (dim == 0 ? own : flag[l0[p]]);
+    lf[M + p] = dim < 0 ? (uint8_t)0 : (dim == 1 ? own : flag[l1[p]]);
+    lf[2 * M + p] = dim < 0 ? (uint8_t)0 : (dim == 2 ? own : flag[l2[p]]);
 }
 
 // Stable partition of the three lists inside every split node (the scan
