@@ -118,47 +118,62 @@ struct CoordsL0 {
     int* out[3];
 };
 
+// Nodes of one chunk that get LDS histograms: slots [base, base + HK), base
+// the slot of the chunk's first active end. Deep levels put several small
+// nodes in a chunk; a node outside the window adds to global memory.
+constexpr int HK = 8;
+
 template <bool COUNTS>
 __global__ __launch_bounds__(KB) void k_hist(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
                                              const int* __restrict__ l0, const int* __restrict__ c0,
                                              const int* __restrict__ c1, const int* __restrict__ c2,
                                              const float* __restrict__ mass, int nb, uint32_t* __restrict__ hc,
                                              double* __restrict__ hm) {
-    __shared__ uint32_t lc[3 * 64];
-    __shared__ double lm[3 * 64];
+    __shared__ uint32_t lc[COUNTS ? HK * 3 * 64 : 1];
+    __shared__ double lm[COUNTS ? 1 : HK * 3 * 64];
     const int64_t p0 = (int64_t)blockIdx.x * HCH;
     const int64_t p1 = min(p0 + HCH, M);
-    const int first = seg_node[p0], last = seg_node[p1 - 1];
-    const bool one = first == last;
-    if (one) {
-        if (nodes[first].slot < 0 || nodes[first].dim >= 0) return;  // not an active node this level
-        for (int k = threadIdx.x; k < 3 * nb; k += blockDim.x) { if (COUNTS) lc[k] = 0; else lm[k] = 0.0; }
-        __syncthreads();
+    const KdNode& nf = nodes[seg_node[p0]];
+    const KdNode& nl = nodes[seg_node[p1 - 1]];
+    const bool af = nf.slot >= 0 && nf.dim < 0, al = nl.slot >= 0 && nl.dim < 0;
+    if (&nf == &nl && !af) return;  // one node, not active this level
+    const int base = af ? nf.slot : (al ? max(0, nl.slot - (HK - 1)) : -1);
+    const int nb3 = 3 * nb;
+    for (int k = threadIdx.x; k < HK * nb3; k += blockDim.x) {
+        if (COUNTS) lc[k] = 0;
+        else lm[k] = 0.0;
     }
+    __syncthreads();
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const int id = one ? first : seg_node[p];
-        const KdNode& nd = nodes[id];
+        const KdNode& nd = nodes[seg_node[p]];
         if (nd.slot < 0 || nd.dim >= 0) continue;
+        const int li = base >= 0 ? nd.slot - base : -1;
+        const bool local = li >= 0 && li < HK;
         const int u[3] = {c0[p], c1[p], c2[p]};  // coordinates in list-0 order
         const double w = COUNTS ? 1.0 : (double)mass[l0[p]];
         for (int d = 0; d < 3; ++d) {
             if (nd.bmax[d] == nd.bmin[d]) continue;
             const int bin = (int)(((int64_t)(u[d] - nd.bmin[d]) * nb) / ((int64_t)nd.bmax[d] - nd.bmin[d] + 1));
-            if (one) {
-                if (COUNTS) atomicAdd(&lc[d * nb + bin], 1u); else atomicAdd(&lm[d * nb + bin], w);
+            if (local) {
+                if (COUNTS) atomicAdd(&lc[li * nb3 + d * nb + bin], 1u);
+                else atomicAdd(&lm[li * nb3 + d * nb + bin], w);
             } else {
                 const int64_t at = ((int64_t)nd.slot * 3 + d) * nb + bin;
-                if (COUNTS) atomicAdd(&hc[at], 1u); else atomicAdd(&hm[at], w);
+                if (COUNTS) atomicAdd(&hc[at], 1u);
+                else atomicAdd(&hm[at], w);
             }
         }
     }
-    if (one) {
-        __syncthreads();
-        const int slot = nodes[first].slot;
-        for (int k = threadIdx.x; k < 3 * nb; k += blockDim.x) {
-            const int64_t at = (int64_t)slot * 3 * nb + k;
-            if (COUNTS) { if (lc[k]) atomicAdd(&hc[at], lc[k]); }
-            else if (lm[k] != 0.0) atomicAdd(&hm[at], lm[k]);
+    if (base < 0) return;
+    __syncthreads();
+    // a nonzero entry belongs to an active node seen above, so its slot
+    // base + k / nb3 is in range
+    for (int k = threadIdx.x; k < HK * nb3; k += blockDim.x) {
+        const int64_t at = (int64_t)base * nb3 + k;
+        if (COUNTS) {
+            if (lc[k]) atomicAdd(&hc[at], lc[k]);
+        } else if (lm[k] != 0.0) {
+            atomicAdd(&hm[at], lm[k]);
         }
     }
 }
