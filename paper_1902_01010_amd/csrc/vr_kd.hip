@@ -339,10 +339,11 @@ __global__ void k_lflag3(int64_t M, const int* __restrict__ seg_node, const KdNo
 
 // Stable partition of the three lists inside every split node (the scan
 // runs over the three flag arrays back to back; differences are taken
-// inside one list), then the position's node moves to its child.
+// inside one list), then the position's node moves to its child.  The left
+// flags are read by list position (lf, list j at lf[j * M + p]), coalesced.
 __global__ void k_part3(int64_t M, int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
                         const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
-                        const uint8_t* __restrict__ flag, const uint32_t* __restrict__ scan, int* __restrict__ o0,
+                        const uint8_t* __restrict__ lf, const uint32_t* __restrict__ scan, int* __restrict__ o0,
                         int* __restrict__ o1, int* __restrict__ o2, CoordsL0 c) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
@@ -363,7 +364,7 @@ __global__ void k_part3(int64_t M, int* __restrict__ seg_node, const KdNode* __r
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const int rl = (int)(scan[j * M + p] - scan[j * M + s]);  // left members before p in the node
-        const int np = flag[e[j]] ? s + rl : s + nl + ((int)p - s - rl);
+        const int np = lf[j * M + p] ? s + rl : s + nl + ((int)p - s - rl);
         out[j][np] = e[j];
         if (j == 0 && c.in[0]) {
             for (int d = 0; d < 3; ++d) c.out[d][np] = c.in[d][p];
@@ -634,7 +635,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         if ((rc = scan_u8(ctx, lf8, lf, 3 * M, st))) return rc;
         CoordsL0 cl0{};
         if (mode != KD_WIDEST) cl0 = CoordsL0{{C0[0], C0[1], C0[2]}, {C0alt[0], C0alt[1], C0alt[2]}};
-        hipLaunchKernelGGL(k_part3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf, Lalt[0],
+        hipLaunchKernelGGL(k_part3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], lf8, lf, Lalt[0],
                            Lalt[1], Lalt[2], cl0);
         VR_LAUNCH_CHECK(ctx);
         for (int j = 0; j < 3; ++j) {
