@@ -242,13 +242,21 @@ int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, const uint8_t* 
  * units, ell2 = (ellx in grid units)^2, FP64 dv2 in x, y, z order; ties to
  * the smaller index), -1 when the host has no dark matter; dark-matter
  * members copy sub[j].  out (device [n]) is written for host members only.
- * sub: device [n].  Errors: VR_ERR_INVALID_ARG for ellx outside (0, box/2),
- * sigma_v <= 0 or NULL arrays; VR_ERR_UNSUPPORTED when a host's dark
- * matter would need a search tree deeper than 8 levels of 64 (never below
- * 2^48 members).  Syncs a few times (member counts, tree level sizes). */
+ * sub: device [n].  sigma_v > 0 is used as given; sigma_v <= 0 asks for the
+ * typical dispersion of the searched hosts, computed on the device: the
+ * mean over hosts of ellv_host[h] / alpha_v (sigma_v,H of Sec. 2.1, as
+ * vr_host_ellv gives ellv_host, device [n_hosts]) weighted by each host's
+ * dark-matter member count.  *sigma_v_used (HOST, may be NULL) receives the
+ * value used (0 when no host holds dark matter).  Errors:
+ * VR_ERR_INVALID_ARG for ellx outside (0, box/2), sigma_v <= 0 without
+ * ellv_host or alpha_v > 0, a computed sigma_v that is not positive, or
+ * NULL arrays; VR_ERR_UNSUPPORTED when a host's dark matter would need a
+ * search tree deeper than 8 levels of 64 (never below 2^48 members).
+ * Syncs a few times (member counts, sigma_v, tree level sizes). */
 int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
                       const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub, double ellx,
-                      double sigma_v, int32_t* out, void* stream);
+                      double sigma_v, const double* ellv_host, double alpha_v, double* sigma_v_used, int32_t* out,
+                      void* stream);
 
 /* Canonical labels: out[i] = smallest j with label[j] == label[i] when that
  * label (in [0, n)) holds >= min_size particles, else -1; label < 0 gives

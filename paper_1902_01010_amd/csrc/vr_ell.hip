@@ -71,47 +71,53 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Weighted least-squares cost of the log model at peak c over the nb bins
 // (centres xs, counts ws, ys = ln ws); wave-wide, every lane returns it.
-// +inf when a side of c holds no bin.
+// The model ln n = a - p (x-c)^2 [x<c] - q (x-c)^2 [x>=c] is linear in
+// beta = (a, p, q) with the design row g = (1, -lo, -hi), lo and hi the two
+// one-sided squared offsets.  The normal matrix N = sum w g g^T and the
+// right-hand side r = sum w g y are accumulated entry by entry and N beta = r
+// is solved with the adjugate of N; the cost is then summed from the
+// residuals.  +inf when a side of c holds no bin (N singular).
 __device__ double wave_cost(const double* xs, const double* ws, const double* ys, int nb, double c, double* apq) {
     const int lane = __lane_id();
-    double Sw = 0, Swu = 0, Swv = 0, Swuu = 0, Swvv = 0, Swy = 0, Swuy = 0, Swvy = 0;
+    // N (symmetric): n00, n11, n22, n01, n02, n12; r: r0, r1, r2
+    double n00 = 0, n11 = 0, n22 = 0, n01 = 0, n02 = 0, n12 = 0, r0 = 0, r1 = 0, r2 = 0;
     for (int j = lane; j < nb; j += 64) {
-        const double x = xs[j], w = ws[j], y = ys[j];
-        const double d = x - c;
-        const double u = x < c ? d * d : 0.0;
-        const double v = x < c ? 0.0 : d * d;
-        Sw += w;
-        Swu += w * u;
-        Swv += w * v;
-        Swuu += w * u * u;
-        Swvv += w * v * v;
-        Swy += w * y;
-        Swuy += w * u * y;
-        Swvy += w * v * y;
+        const double off = xs[j] - c;
+        const double g1 = xs[j] < c ? -(off * off) : 0.0;
+        const double g2 = xs[j] < c ? 0.0 : -(off * off);
+        const double w = ws[j], wy = w * ys[j];
+        n00 += w;
+        n11 += w * g1 * g1;
+        n22 += w * g2 * g2;
+        n01 += w * g1;
+        n02 += w * g2;
+        n12 += w * g1 * g2;
+        r0 += wy;
+        r1 += wy * g1;
+        r2 += wy * g2;
     }
-    Sw = wave_sum(Sw);
-    Swu = wave_sum(Swu);
-    Swv = wave_sum(Swv);
-    Swuu = wave_sum(Swuu);
-    Swvv = wave_sum(Swvv);
-    Swy = wave_sum(Swy);
-    Swuy = wave_sum(Swuy);
-    Swvy = wave_sum(Swvy);
-    if (!(Swuu > 0) || !(Swvv > 0)) return INFINITY;
-    // normal equations of min sum w (y - a + p u + q v)^2, p and q eliminated
-    const double den = Sw - Swu * Swu / Swuu - Swv * Swv / Swvv;
-    if (!(den > 0)) return INFINITY;
-    const double a = (Swy - Swu * Swuy / Swuu - Swv * Swvy / Swvv) / den;
-    const double pp = (Swu * a - Swuy) / Swuu;
-    const double qq = (Swv * a - Swvy) / Swvv;
+    n00 = wave_sum(n00);
+    n11 = wave_sum(n11);
+    n22 = wave_sum(n22);
+    n01 = wave_sum(n01);
+    n02 = wave_sum(n02);
+    n12 = wave_sum(n12);
+    r0 = wave_sum(r0);
+    r1 = wave_sum(r1);
+    r2 = wave_sum(r2);
+    if (!(n11 > 0) || !(n22 > 0)) return INFINITY;
+    const Sym3Adj A = sym3_adjugate(n00, n11, n22, n01, n02, n12);
+    if (!(A.det > 0)) return INFINITY;
+    const double a = (A.xx * r0 + A.xy * r1 + A.xz * r2) / A.det;
+    const double pp = (A.xy * r0 + A.yy * r1 + A.yz * r2) / A.det;
+    const double qq = (A.xz * r0 + A.yz * r1 + A.zz * r2) / A.det;
     double J = 0;
     for (int j = lane; j < nb; j += 64) {
-        const double x = xs[j];
-        const double d = x - c;
-        const double u = x < c ? d * d : 0.0;
-        const double v = x < c ? 0.0 : d * d;
-        const double r = ys[j] - a + pp * u + qq * v;
-        J += ws[j] * r * r;
+        const double off = xs[j] - c;
+        const double sq = off * off;
+        const double fit = xs[j] < c ? a - pp * sq : a - qq * sq;
+        const double res = ys[j] - fit;
+        J += ws[j] * res * res;
     }
     if (apq) {
         apq[0] = a;

@@ -180,6 +180,26 @@ __device__ __forceinline__ unsigned xcd_swizzle(unsigned b, unsigned nb, unsigne
     return s * span + (w & 7u) * chunk + (w >> 3);
 }
 
+// Symmetric 3x3 matrix [[a, d, e], [d, b, f], [e, f, c]]: its adjugate (the
+// transposed cofactor matrix, itself symmetric) as (xx, yy, zz, xy, xz, yz),
+// and its determinant by expansion along the first row.  With float entries
+// promoted to double, each two-term cofactor is one rounding of exact
+// products.
+struct Sym3Adj {
+    double xx, yy, zz, xy, xz, yz, det;
+};
+__device__ __forceinline__ Sym3Adj sym3_adjugate(double a, double b, double c, double d, double e, double f) {
+    Sym3Adj r;
+    r.xx = b * c - f * f;
+    r.yy = a * c - e * e;
+    r.zz = a * b - d * d;
+    r.xy = e * f - d * c;
+    r.xz = d * f - b * e;
+    r.yz = d * e - a * f;
+    r.det = a * r.xx + d * r.xy + e * r.xz;
+    return r;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned l = __lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));

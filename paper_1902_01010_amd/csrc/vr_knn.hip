@@ -49,37 +49,24 @@ __global__ void k_subset_pos(int64_t ns, int64_t n, const int32_t* __restrict__ 
     qval[s] = (uint32_t)s;
 }
 
-// ln f_bg (Eq. fvbg): the Gaussian of mean vbar(x) and dispersion sigma(x)
-// of particle g at velocity vq, by a 3x3 Cholesky in FP64; NaN if sigma(x)
-// is not positive definite.
+// ln f_bg (Eq. fvbg): the log density of the trivariate Gaussian of mean
+// vbar(x) and covariance sigma(x), particle g, at velocity vq.  The
+// quadratic form is u^T adj(S) u / det S with u = vq - vbar; S is positive
+// definite iff its leading principal minors S_xx, S_xx S_yy - S_xy^2 and
+// det S are positive (Sylvester's criterion), else NaN.
 __device__ __forceinline__ double log_fbg(const float* __restrict__ sigma, const float* __restrict__ vbar, int64_t n,
                                           int g, double vqx, double vqy, double vqz) {
-    const double S00 = sigma[0 * n + g], S11 = sigma[1 * n + g], S22 = sigma[2 * n + g];
-    const double S10 = sigma[3 * n + g], S20 = sigma[4 * n + g], S21 = sigma[5 * n + g];
-    double lfb = NAN;
-    if (S00 > 0) {
-        const double L00 = sqrt(S00);
-        const double L10 = S10 / L00, L20 = S20 / L00;
-        const double r11 = S11 - L10 * L10;
-        if (r11 > 0) {
-            const double L11 = sqrt(r11);
-            const double L21 = (S21 - L20 * L10) / L11;
-            const double r22 = S22 - L20 * L20 - L21 * L21;
-            if (r22 > 0) {
-                const double L22 = sqrt(r22);
-                const double d0 = vqx - (double)vbar[0 * n + g];
-                const double d1 = vqy - (double)vbar[1 * n + g];
-                const double d2 = vqz - (double)vbar[2 * n + g];
-                const double y0 = d0 / L00;
-                const double y1 = (d1 - L10 * y0) / L11;
-                const double y2 = (d2 - L20 * y0 - L21 * y1) / L22;
-                const double quad = y0 * y0 + y1 * y1 + y2 * y2;
-                const double lndet = 2.0 * (log(L00) + log(L11) + log(L22));
-                lfb = -0.5 * quad - 1.5 * log(2.0 * M_PI) - 0.5 * lndet;
-            }
-        }
-    }
-    return lfb;
+    const double sxx = sigma[0 * n + g], syy = sigma[1 * n + g], szz = sigma[2 * n + g];
+    const Sym3Adj A = sym3_adjugate(sxx, syy, szz, sigma[3 * n + g], sigma[4 * n + g], sigma[5 * n + g]);
+    if (!(sxx > 0) || !(A.zz > 0) || !(A.det > 0)) return NAN;
+    const double ux = vqx - (double)vbar[0 * n + g];
+    const double uy = vqy - (double)vbar[1 * n + g];
+    const double uz = vqz - (double)vbar[2 * n + g];
+    const double diag = A.xx * ux * ux + A.yy * uy * uy + A.zz * uz * uz;
+    const double offd = A.xy * ux * uy + A.xz * ux * uz + A.yz * uy * uz;
+    // 3 ln(2 pi) / 2
+    constexpr double HALF3_LN_2PI = 2.7568155996140178;
+    return -0.5 * ((diag + 2.0 * offd) / A.det + log(A.det)) - HALF3_LN_2PI;
 }
 
 // rank_of[g] = the position of particle g in host_members (-1 beforehand);

@@ -727,6 +727,32 @@ __global__ __launch_bounds__(256) void k_assign6(int64_t nb, const int32_t* __re
     if (valid) out[i] = bst.j == 0x7FFFFFFF ? -1 : sub[bst.j];
 }
 
+// The dark-matter-weighted mean over hosts of ellv_host[h] * inv_alpha (the
+// hosts' sigma_v), one workgroup: FP64 partial sums per thread in host
+// order, then a tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_dm_weighted_sigma(int n_hosts, const uint32_t* __restrict__ dm_off,
+                                                           const double* __restrict__ ellv, double inv_alpha,
+                                                           double* __restrict__ out) {
+    __shared__ double sw[256], sn[256];
+    double a = 0.0, c = 0.0;
+    for (int h = threadIdx.x; h < n_hosts; h += 256) {
+        const double k = (double)(dm_off[h + 1] - dm_off[h]);
+        a += k * ellv[h];
+        c += k;
+    }
+    sw[threadIdx.x] = a;
+    sn[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sw[threadIdx.x] += sw[threadIdx.x + o];
+            sn[threadIdx.x] += sn[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sn[0] > 0 ? sw[0] / sn[0] * inv_alpha : 0.0;
+}
+
 __global__ void k_dm_offsets(int n_hosts, int64_t M, const int32_t* __restrict__ off, const uint32_t* __restrict__ pos,
                              const uint32_t* __restrict__ total, uint32_t* __restrict__ dm_off) {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -849,15 +875,20 @@ extern "C" int vr_fof3d_dm(vr_ctx* ctx, const vr_particles* p, double ellx, cons
 
 extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t* host_offsets,
                                  const int32_t* host_members, const uint8_t* is_baryon, const int32_t* sub,
-                                 double ellx, double sigma_v, int32_t* out, void* stream) {
+                                 double ellx, double sigma_v, const double* ellv_host, double alpha_v,
+                                 double* sigma_v_used, int32_t* out, void* stream) {
     if (!ctx) return VR_ERR_INVALID_ARG;
     int rc = check_particles(ctx, p, true);
     if (rc) return rc;
     if ((rc = check_hosts(ctx, n_hosts, host_offsets, host_members))) return rc;
     const int gb = p->grid_bits;
     const double u = ellx * ldexp(1.0, gb) / p->box;
-    if (!(u > 0) || !(u < ldexp(1.0, gb - 1)) || !(sigma_v > 0) || !std::isfinite(sigma_v))
-        return set_err(ctx, VR_ERR_INVALID_ARG, "need 0 < ellx < box/2 and sigma_v > 0");
+    if (!(u > 0) || !(u < ldexp(1.0, gb - 1)) || !std::isfinite(sigma_v))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "need 0 < ellx < box/2 and a finite sigma_v");
+    const bool from_hosts = !(sigma_v > 0);
+    if (from_hosts && (!ellv_host || !(alpha_v > 0)))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "sigma_v <= 0 needs ellv_host and alpha_v > 0");
+    if (sigma_v_used) *sigma_v_used = from_hosts ? 0.0 : sigma_v;
     if (n_hosts == 0) return VR_OK;
     if (!is_baryon || !sub || !out) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
     VR_HIP(ctx, hipSetDevice(ctx->device));
@@ -893,6 +924,16 @@ extern "C" int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_h
                            out);
         VR_LAUNCH_CHECK(ctx);
         return VR_OK;
+    }
+    if (from_hosts) {
+        VR_WS(sv_dev, ctx, double, WS_D1, 2);
+        hipLaunchKernelGGL(k_dm_weighted_sigma, dim3(1), dim3(256), 0, st, n_hosts, dm_off, ellv_host,
+                           1.0 / alpha_v, sv_dev);
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = read_back(ctx, sv_dev, &sigma_v, sizeof sigma_v, st))) return rc;
+        if (!(sigma_v > 0) || !std::isfinite(sigma_v))
+            return set_err(ctx, VR_ERR_INVALID_ARG, "sigma_v from the hosts is %g, not positive", sigma_v);
+        if (sigma_v_used) *sigma_v_used = sigma_v;
     }
     const int64_t nb = M - ndm;
     const float ix = (float)(1.0 / u), iv = (float)(1.0 / sigma_v);

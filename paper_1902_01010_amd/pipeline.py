@@ -211,13 +211,11 @@ def _search(ctx, P, group_of, n_hosts, host_offsets, members, prm: Params, mark,
         host_offsets_all, all_members, is_baryon = species
         # baryons join the candidate of the nearest dark matter in phase space
         sub = ctx.relabel_min(label6, prm.n_min)
-        sv = prm.baryon_sigma_v
-        if sv <= 0:
-            # the typical sigma_v of a searched particle's host: the mean over
-            # hosts of (det Sigma_H)^(1/6) weighted by their dark matter
-            w_dm = np.diff(host_offsets.cpu().numpy()).astype(np.float64)
-            sv = float(np.sum(w_dm * ellv.cpu().numpy()) / np.sum(w_dm)) / prm.alpha_v
-        lab_all = ctx.assign_baryons(P, host_offsets_all, all_members, is_baryon, sub, prm.ellx, sv)
+        # sigma_v <= 0: the library takes the typical sigma_v of a searched
+        # particle's host, the mean over hosts of (det Sigma_H)^(1/6) weighted
+        # by their dark matter
+        lab_all, sv = ctx.assign_baryons(P, host_offsets_all, all_members, is_baryon, sub, prm.ellx,
+                                         prm.baryon_sigma_v, ellv_host=ellv, alpha_v=prm.alpha_v)
         label6 = ctx.relabel_min(lab_all, 1)
         out.update(baryon_sigma_v=sv, label6_dm=sub)
         mark(tag + "baryons")

@@ -108,7 +108,7 @@ def load_library():
         L.vr_fof6d.argtypes = [vp, P, vp, vp, i32, dbl, vp, flt, vp, vp]
         L.vr_fof_sub.argtypes = [vp, P, vp, i32, vp, dbl, vp, flt, dbl, dbl, vp, vp]
         L.vr_fof3d_dm.argtypes = [vp, P, dbl, vp, vp, vp]
-        L.vr_assign_baryons.argtypes = [vp, P, i32, vp, vp, vp, vp, dbl, dbl, vp, vp]
+        L.vr_assign_baryons.argtypes = [vp, P, i32, vp, vp, vp, vp, dbl, dbl, vp, dbl, vp, vp, vp]
         L.vr_relabel_min.argtypes = [vp, i64, vp, i32, vp, vp]
         L.vr_select_members.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp]
         L.vr_sub_grow.argtypes = [vp, P, vp, i32, vp, vp, flt, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i32, vp, vp,
@@ -343,15 +343,20 @@ class Context:
         self._check(self.lib.vr_fof3d_dm(self.h, C.byref(P.s), float(ellx), _ptr(is_baryon), _ptr(label), _stream()))
         return label
 
-    def assign_baryons(self, P: Particles, host_offsets, host_members, is_baryon, sub, ellx, sigma_v, out=None):
+    def assign_baryons(self, P: Particles, host_offsets, host_members, is_baryon, sub, ellx, sigma_v, out=None,
+                       ellv_host=None, alpha_v=1.25):
         """Baryons of each host take the substructure label of the nearest dark
-        matter in phase space; dark matter copies its own."""
+        matter in phase space; dark matter copies its own.  sigma_v <= 0: the
+        library computes it from ellv_host (the hosts' dark-matter-weighted
+        mean of ellv / alpha_v).  Returns (out, sigma_v used)."""
         if out is None:
             out = torch.full((P.n,), -1, dtype=torch.int32, device=P.device)
+        used = C.c_double(0.0)
         self._check(self.lib.vr_assign_baryons(self.h, C.byref(P.s), host_offsets.shape[0] - 1, _ptr(host_offsets),
                                                _ptr(host_members), _ptr(is_baryon), _ptr(sub), float(ellx),
-                                               float(sigma_v), _ptr(out), _stream()))
-        return out
+                                               float(sigma_v), _ptr(ellv_host), float(alpha_v), C.byref(used),
+                                               _ptr(out), _stream()))
+        return out, used.value
 
     def relabel_min(self, label, min_size=1, out=None):
         """Canonical smallest-index labels of components with >= min_size members."""

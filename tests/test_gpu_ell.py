@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from paper_1902_01010_amd import synth
-from tests.gpu_common import both, dev_tensor
+from tests.gpu_common import R_agrees, both, dev_tensor
 
 pytestmark = pytest.mark.gpu
 
@@ -146,28 +146,56 @@ CASES = {
 }
 
 
+def _oracle_hosts(ref, Pr, prm):
+    lab = ref.fof3d(Pr, prm.ellx)
+    ng, gof, off, mem = ref.groups(lab, prm.n_min)
+    nh = int((np.diff(off) >= prm.host_min).sum())
+    host_of = np.where((gof >= 0) & (gof < nh), gof, -1).astype(np.int32)
+    return lab, nh, off[:nh + 1].copy(), mem[:off[nh]].copy(), host_of
+
+
+def _same_fine_bins(Rg, Re, lo=-16.0, width=1.0 / 32):
+    """Whether the GPU's and the oracle's R fall in the same fine bins of
+    the L fit (then both fit identical histograms)."""
+    fin = np.isfinite(Re)
+    bg = np.floor((Rg[fin].astype(np.float64) - lo) / width)
+    be = np.floor((Re[fin].astype(np.float64) - lo) / width)
+    return bool((bg == be).all())
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_pipeline_with_ell_stagewise(ctx, vr, ref, name):
-    """The hot path with outliers by L >= 2.5 and cleaning: every stage after
-    R is recomputed by the oracle from the GPU's own inputs to that stage."""
+    """The hot path with outliers by L >= 2.5 and cleaning, against the
+    oracle's own chain (oracle inputs only): 3D labels and hosts exact; R to
+    its tolerance; the L fit exactly as in the fit parity tests when both R
+    fill the same fine bins; L to 1e-6; then the 6D groups and the cleaning
+    from the oracle's L, exact, when the L classes agree everywhere.  Where
+    a value inside a tolerance band moves a later decision the test says so
+    and stops (skip)."""
     from paper_1902_01010_amd import pipeline
     w = CASES[name]()
     prm = dataclasses.replace(pipeline.Params.from_workload(w), use_ell=True)
     x, v, m = pipeline.device_inputs(w)
     got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
-    assert got["n_hosts"] > 0
     P, Pr = both(ctx, vr, ref, w)
-    R = got["R"].cpu().numpy()
-    hoff = got["host_offsets"].cpu().numpy()
-    mem = got["members"].cpu().numpy()
-    hmem = mem[:hoff[-1]]
+    lab, nh, hoff, hmem, host_of = _oracle_hosts(ref, Pr, prm)
+    np.testing.assert_array_equal(got["label"].cpu().numpy(), lab)
+    assert got["n_hosts"] == nh > 0
+    np.testing.assert_array_equal(got["host_offsets"].cpu().numpy(), hoff)
+    np.testing.assert_array_equal(got["members"].cpu().numpy()[:hoff[-1]], hmem)
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
+    Rg = got["R"].cpu().numpy()
+    R_agrees(Rg, R, prm.R_threshold, where=hmem)
+    if not _same_fine_bins(Rg[hmem], R[hmem]):
+        pytest.skip("an R within its tolerance lies across a fine-bin edge of the L fit")
     e = ref.ell_fit(R, hoff, hmem)
     check_fit(dict(status=got["ell_status"], merge=got["ell_merge"], fit=got["ell_fit"]), e, lambda g: g / 32)
-    ell = got["ell"].cpu().numpy()
-    check_ell(ell, e["ell"])
-    # 6D groups over L >= 2.5 from the GPU's L, then cleaning
-    gof = got["group_of"].cpu().numpy()
-    host_of = np.where((gof >= 0) & (gof < got["n_hosts"]), gof, -1).astype(np.int32)
+    ell = e["ell"]
+    gl = got["ell"].cpu().numpy()
+    check_ell(gl, ell)
+    if ((gl >= prm.ell_th) != (ell >= prm.ell_th)).any():
+        pytest.skip("an L within its tolerance classed differently at the threshold")
     ellv = ref.host_ellv(Pr, hoff, hmem, prm.alpha_v)
     lab6 = ref.fof6d(Pr, host_of, ellv, prm.alpha_xs * prm.ellx, ell, prm.ell_th)
     nc, _, soff, smem = ref.groups(lab6, prm.n_min)
@@ -223,19 +251,38 @@ def test_fof_sub_rejects_bad_arguments(ctx, vr, ref):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_pipeline_paper_linker_stagewise(ctx, vr, ref, name):
-    """L mode with the paper's linker: the oracle redoes the linking and the
-    cleaning from the GPU's own L and local mean velocities."""
+    """L mode with the paper's linker and its second stage, against the
+    oracle's own chain (oracle inputs only): hosts exact, R, L and the local
+    mean velocities to their tolerances; then the linking, the growth and
+    the cleaning from the oracle's L and mean velocities, exact, when no
+    value inside a tolerance band changes a class (else skip)."""
     from paper_1902_01010_amd import pipeline
     w = CASES[name]()
     prm = dataclasses.replace(pipeline.Params.from_workload(w), use_ell=True, linker="paper")
     x, v, m = pipeline.device_inputs(w)
     got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
     P, Pr = both(ctx, vr, ref, w)
-    nh = got["n_hosts"]
-    gof = got["group_of"].cpu().numpy()
-    host_of = np.where((gof >= 0) & (gof < nh), gof, -1).astype(np.int32)
-    ell = got["ell"].cpu().numpy()
-    vbar = got["cells"]["vbar"].cpu().numpy()
+    lab, nh, hoff, hmem, host_of = _oracle_hosts(ref, Pr, prm)
+    np.testing.assert_array_equal(got["label"].cpu().numpy(), lab)
+    assert got["n_hosts"] == nh > 0
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    vg = got["cells"]["vbar"].cpu().numpy()
+    np.testing.assert_allclose(vg[:, hmem], cm["vbar"][:, hmem], rtol=2e-6,
+                               atol=1e-6 * np.abs(cm["vbar"][:, hmem]).max())
+    R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
+    Rg = got["R"].cpu().numpy()
+    R_agrees(Rg, R, prm.R_threshold, where=hmem)
+    if not _same_fine_bins(Rg[hmem], R[hmem]):
+        pytest.skip("an R within its tolerance lies across a fine-bin edge of the L fit")
+    ell = ref.ell_fit(R, hoff, hmem)["ell"]
+    gl = got["ell"].cpu().numpy()
+    check_ell(gl, ell)
+    for th in (prm.ell_th, prm.ell_th / prm.gamma_L):
+        if ((gl >= th) != (ell >= th)).any():
+            pytest.skip("an L within its tolerance classed differently at a threshold")
+    if not (vg[:, hmem] == cm["vbar"][:, hmem]).all():
+        pytest.skip("local mean velocities differ in the last bit; the angle tests are not comparable")
+    vbar = cm["vbar"]
     lab = ref.fof_sub(Pr, host_of, nh, vbar, prm.alpha_xs * prm.ellx, ell, prm.ell_th, prm.Vr,
                       theta_op=prm.theta_op)
     lab, nr = ref.sub_grow(Pr, host_of, nh, vbar, ell, lab, prm.alpha_xs * prm.ellx, prm.ell_th, prm.gamma_L,

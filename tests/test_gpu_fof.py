@@ -84,10 +84,12 @@ def test_fof3d_rejects_bad_args(ctx, vr):
 def test_groups_bit_exact(ctx, vr, ref, name):
     w = WORKLOADS[name]()
     P, Pr = both(ctx, vr, ref, w)
-    lab = ctx.fof3d(P, w.params["ellx"])
+    # both sides group the oracle's labels
+    elab = ref.fof3d(Pr, w.params["ellx"])
+    lab = dev_tensor(elab)
     for n_min in (20, 256):
         ng, gof, off, mem = ctx.groups(lab, n_min)
-        eng, egof, eoff, emem = ref.groups(lab.cpu().numpy(), n_min)
+        eng, egof, eoff, emem = ref.groups(elab, n_min)
         assert ng == eng
         assert (gof.cpu().numpy() == egof).all()
         assert (off.cpu().numpy() == eoff).all()
@@ -111,3 +113,24 @@ def test_fof3d_clumps_across_box_edges(ctx, vr, ref, ell_units, spread):
     Pr = ref.Particles(q, None, None, 1.0, 1.0, 21)
     ell = ell_units / size
     assert (ctx.fof3d(Pd, ell).cpu().numpy() == ref.fof3d(Pr, ell)).all()
+
+
+def test_workspace_cap_is_an_error(vr, ref):
+    """A context whose workspace cap is below what a call needs returns
+    VR_ERR_OUT_OF_MEMORY with a message (and stays usable); the same call
+    under a cap it fits in gives the oracle's labels."""
+    w = WORKLOADS["box32"]()
+    small = vr.Context(0, max_workspace_bytes=64 * 1024)
+    q = small.quantize(dev_tensor(w.x), w.box, w.grid_bits)  # needs no workspace
+    P = vr.Particles(q, dev_tensor(w.v), None, w.mass_value, w.box, w.grid_bits)
+    with pytest.raises(vr.VrError) as ei:
+        small.fof3d(P, w.params["ellx"])
+    assert ei.value.code == vr.VR_ERR_OUT_OF_MEMORY and "workspace cap" in str(ei.value)
+    assert small.workspace_bytes() <= 64 * 1024
+    roomy = vr.Context(0, max_workspace_bytes=256 << 20)
+    lab = roomy.fof3d(P, w.params["ellx"]).cpu().numpy()
+    Pr = ref.Particles(ref.quantize(w.x, w.box, w.grid_bits), w.v, None, w.mass_value, w.box, w.grid_bits)
+    assert (lab == ref.fof3d(Pr, w.params["ellx"])).all()
+    assert 0 < roomy.workspace_bytes() <= 256 << 20
+    small.close()
+    roomy.close()

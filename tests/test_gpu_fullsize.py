@@ -196,3 +196,111 @@ def test_fullsize_sampled_6d_and_unbinding(full, hosts, ref):
         checked += 1
         note(f"host of {len(comp)}: 6D groups and unbinding agree ({ng} candidates)")
     assert checked >= 1
+
+
+def regional_component(full, ref, centre_q, half):
+    """The oracle's 3D FOF component of the particle nearest centre_q (grid
+    units), linked among the particles of the cube of half-side `half`
+    around it.  Returned (global indices, ascending) only when every member
+    keeps more than ellx from the cube's faces: then no particle outside the
+    cube links to it and it is the component in the whole box; else None."""
+    w, q = full["w"], full["q"]
+    size, hb = 1 << w.grid_bits, 1 << (w.grid_bits - 1)
+    off = (q - centre_q[:, None] + hb) % size - hb
+    sel = np.nonzero((np.abs(off) < half).all(0))[0]
+    offs = off[:, sel]
+    Ps = ref.Particles(q[:, sel].astype(np.uint32), w.v[:, sel], None, w.mass_value, w.box, w.grid_bits)
+    lab = ref.fof3d(Ps, full["prm"].ellx)
+    seed = int(np.argmin((offs * offs).sum(0)))
+    loc = np.nonzero(lab == lab[seed])[0]
+    if np.abs(offs[:, loc]).max() >= half - np.sqrt(full["ell2"]) - 1:
+        return None
+    return np.sort(sel[loc])
+
+
+@pytest.fixture(scope="module")
+def big_hosts(full, ref):
+    """The components around the three largest planted halos and around the
+    planted halo closest to 6e4 particles, each found by the oracle's FOF in
+    a cube that the component provably does not leave."""
+    w = full["w"]
+    H = w.meta["halos"]
+    scale = (1 << w.grid_bits) / w.box
+    order = np.argsort(-H["size"], kind="stable")
+    mid = int(np.argmin(np.abs(H["size"] - 60000)))
+    out = []
+    for h in list(order[:3]) + [mid]:
+        c = np.floor(H["centre"][:, h] * scale).astype(np.int64) % (1 << w.grid_bits)
+        half = int(1.5 * H["r200"][h] * scale)
+        comp = None
+        for _ in range(4):
+            comp = regional_component(full, ref, c, half)
+            if comp is not None:
+                break
+            half *= 2
+        assert comp is not None, f"component of planted halo {h} not enclosed"
+        out.append(comp)
+    note(f"regional components of sizes {[len(c) for c in out]}")
+    return out
+
+
+@pytest.mark.timeout(1200)
+def test_fullsize_largest_hosts(full, big_hosts, ref):
+    """The largest hosts of the box (about 1e6 members: the deepest KD levels
+    and the biggest neighbour trees) and one of 5e4-1e5 members: the oracle
+    finds each component itself; the GPU group is exactly it; the oracle's
+    cells (all members) and R (150 sampled members) match the GPU's
+    full-box outputs; on the mid-size host also the 6D groups and the
+    unbinding of every candidate decided outside the tolerance band."""
+    g, Pr, prm = full["got"], full["Pr"], full["prm"]
+    lab = g["label"]
+    rng = np.random.default_rng(3)
+    for i, comp in enumerate(big_hosts):
+        gpu = np.nonzero(lab == lab[comp[0]])[0]
+        np.testing.assert_array_equal(gpu, comp)
+        assert len(comp) >= prm.host_min
+        hoff = np.array([0, len(comp)], np.int32)
+        hmem = comp.astype(np.int32)
+        cm = ref.cell_moments(Pr, hoff, hmem)
+        for k, mine in (("vbar", "vbar"), ("sigma", "sigma"), ("rho_cell", "rho")):
+            e = cm[k][..., comp]
+            gv = g[mine][..., comp]
+            np.testing.assert_allclose(gv, e, rtol=2e-6, atol=1e-6 * np.abs(e).max())
+        sub = np.sort(rng.choice(comp, 150, replace=False)).astype(np.int32)
+        R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v, subset=sub)["R"]
+        e, gr = R[sub].astype(np.float64), g["R"][sub].astype(np.float64)
+        fin = np.isfinite(e)
+        assert (np.isnan(gr) == np.isnan(e)).all()
+        err = np.abs(gr[fin] - e[fin]) / np.maximum(1.0, np.abs(e[fin]))
+        assert err.max() <= 1e-4, err.max()
+        note(f"host of {len(comp)}: group, cells and sampled R agree")
+    comp = big_hosts[-1]
+    assert len(comp) >= 50000
+    hoff = np.array([0, len(comp)], np.int32)
+    hmem = comp.astype(np.int32)
+    cm = ref.cell_moments(Pr, hoff, hmem)
+    R = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
+    e, gr = R[comp].astype(np.float64), g["R"][comp].astype(np.float64)
+    fin = np.isfinite(e)
+    err = np.abs(gr[fin] - e[fin]) / np.maximum(1.0, np.abs(e[fin]))
+    assert err.max() <= 1e-4, err.max()
+    # the outlier classes must agree; inside the tolerance band a different
+    # class is allowed, but then the 6D groups are not comparable
+    near = np.abs(e - prm.R_threshold) <= 2e-4
+    differ = (gr >= prm.R_threshold) != (e >= prm.R_threshold)
+    assert not (differ & ~near).any()
+    if differ.any():
+        pytest.skip(f"{int(differ.sum())} member(s) classed differently inside the tolerance band")
+    ellv = ref.host_ellv(Pr, hoff, hmem, prm.alpha_v)
+    host_of = np.full(Pr.n, -1, np.int32)
+    host_of[comp] = 0
+    lab6 = ref.fof6d(Pr, host_of, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
+    np.testing.assert_array_equal(g["label6"][comp], lab6[comp])
+    ng, _, off6, mem6 = ref.groups(lab6, prm.n_min)
+    assert ng >= 1
+    ub = ref.unbind(Pr, off6, mem6, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min)
+    clean = ub["min_margin"] > 1e-5
+    for k in np.nonzero(clean)[0]:
+        mm = mem6[off6[k]:off6[k + 1]]
+        assert (g["bound"][mm] == ub["bound"][mm]).all()
+    note(f"host of {len(comp)}: {ng} 6D candidates, {int(clean.sum())} unbound-checked")

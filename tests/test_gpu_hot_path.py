@@ -117,6 +117,45 @@ def test_cells_and_R_with_coincident_members(ctx, vr, ref):
         _R_close(g, e)
 
 
+@pytest.mark.parametrize("ncell_floor", [100, 24])
+def test_cells_and_R_with_unequal_masses(ctx, vr, ref, case, ncell_floor):
+    """Per-particle masses (0.5-1.5 m_p): the mass-weighted entropy histograms
+    (with small cells, the deep KD levels put many nodes in one histogram
+    chunk), the mass-weighted moments, and the kNN's per-member mass records
+    (f_l of the ratio) against the oracle."""
+    w = case["w"]
+    rng = np.random.default_rng(101)
+    m = (rng.uniform(0.5, 1.5, w.n) * w.mass_value).astype(np.float32)
+    q_dev = case["P"].q
+    P = vr.Particles(q_dev, dev_tensor(w.v), dev_tensor(m), 0.0, w.box, w.grid_bits)
+    Pr = ref.Particles(case["Pr"].q, w.v, m, 0.0, w.box, w.grid_bits)
+    hoff, hmem = case["hoff"], case["hmem"]
+    kw = dict(ncell_floor=ncell_floor)
+    exp = ref.cell_moments(Pr, hoff, hmem, **kw)
+    got = ctx.cell_moments(P, dev_tensor(hoff), dev_tensor(hmem), **kw)
+    assert got["n_cells"] == exp["cells"].shape[0]
+    gc, ec = got["cells"].cpu().numpy(), exp["cells"]
+    ints = [0, 1] + list(range(15, 27))
+    assert (gc[:, ints] == ec[:, ints]).all()
+    np.testing.assert_allclose(gc[:, [2, 27]], ec[:, [2, 27]], rtol=1e-12)
+    np.testing.assert_allclose(gc[:, 3:6], ec[:, 3:6], rtol=1e-12)
+    np.testing.assert_allclose(gc[:, 6:15], ec[:, 6:15], rtol=1e-9, atol=1e-9 * np.abs(ec[:, 6:15]).max())
+    assert (got["cell_of"].cpu().numpy() == exp["cell_of"]).all()
+    for k in ("vbar", "sigma", "rho_cell"):
+        g, e = got[k].cpu().numpy(), exp[k]
+        fin = np.isfinite(e)
+        assert (np.isfinite(g) == fin).all()
+        np.testing.assert_allclose(g[fin], e[fin], rtol=2e-6, atol=1e-6 * np.abs(e[fin]).max())
+    # masses change the partition itself (entropy of the mass histogram)
+    if ncell_floor == 24:
+        plain = ref.cell_moments(case["Pr"], hoff, hmem, **kw)
+        assert (plain["cell_of"] != exp["cell_of"]).any()
+    e = ref.local_vdensity(Pr, hoff, hmem, exp["vbar"], exp["sigma"], 32, 8)["R"]
+    g = ctx.local_vdensity(P, dev_tensor(hoff), dev_tensor(hmem), dev_tensor(exp["vbar"]),
+                           dev_tensor(exp["sigma"]), 32, 8).cpu().numpy()
+    _R_close(g, e)
+
+
 def test_host_ellv_parity(ctx, ref, case):
     P, Pr, hoff, hmem = case["P"], case["Pr"], case["hoff"], case["hmem"]
     exp = ref.host_ellv(Pr, hoff, hmem, 1.25)

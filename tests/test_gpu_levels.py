@@ -1,16 +1,19 @@
 """GPU parity of the level-by-level substructure search (Sec. 2.2: the
-bound substructures with >= host_min members searched again as hosts).  The
-second level is recomputed by the oracle from the GPU's own first level:
-host lists and 6D labels exact, R to 1e-4 max(1, |R|), unbinding as in the
-unbinding parity tests (bound flags exact where the binding margin is clear
-of rounding)."""
+bound substructures with >= host_min members searched again as hosts),
+against the oracle's own chain (oracle inputs only): first-level R to
+1e-4 max(1, |R|) and its 6D labels and bound flags exact, so the second
+level's hosts are the same; then the second level's host lists and 6D
+labels exact, R to its tolerance, unbinding as in the unbinding parity tests
+(bound flags exact where the binding margin is clear of rounding).  Where a
+value inside a tolerance band changes a decision the test says so and
+stops (skip)."""
 import dataclasses
 
 import numpy as np
 import pytest
 
 from paper_1902_01010_amd import synth
-from tests.gpu_common import both
+from tests.gpu_common import R_agrees, both
 
 pytestmark = pytest.mark.gpu
 
@@ -34,8 +37,29 @@ def test_levels_stagewise(ctx, vr, ref):
     got, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
     P, Pr = both(ctx, vr, ref, w)
     assert len(got["levels"]) >= 1
-    # level-2 hosts from the GPU's level-1 labels and bound flags
-    l1 = np.where(got["unbind"]["bound"].cpu().numpy() > 0, got["label6"].cpu().numpy(), -1).astype(np.int32)
+    # the oracle's first level, from its own hosts
+    lab = ref.fof3d(Pr, prm.ellx)
+    np.testing.assert_array_equal(got["label"].cpu().numpy(), lab)
+    ng, gof1, off1, mem1 = ref.groups(lab, prm.n_min)
+    nh1 = int((np.diff(off1) >= prm.host_min).sum())
+    hoff1, hmem1 = off1[:nh1 + 1], mem1[:off1[nh1]]
+    cm1 = ref.cell_moments(Pr, hoff1, hmem1)
+    R1 = ref.local_vdensity(Pr, hoff1, hmem1, cm1["vbar"], cm1["sigma"], prm.n_se, prm.n_v)["R"]
+    if not R_agrees(got["R"].cpu().numpy(), R1, prm.R_threshold, where=hmem1):
+        pytest.skip("a first-level R within its tolerance classed differently at the threshold")
+    ellv1 = ref.host_ellv(Pr, hoff1, hmem1, prm.alpha_v)
+    lab61 = ref.fof6d(Pr, gof1, ellv1, prm.alpha_xs * prm.ellx, R1, prm.R_threshold)
+    np.testing.assert_array_equal(got["label6"].cpu().numpy(), lab61)
+    nc1, _, soff1, smem1 = ref.groups(lab61, prm.n_min)
+    ub1 = ref.unbind(Pr, soff1, smem1, prm.G, prm.eps, beta_E=prm.beta_E, n_min=prm.n_min)
+    gb1 = got["unbind"]["bound"].cpu().numpy()
+    for g in range(nc1):
+        mm = smem1[soff1[g]:soff1[g + 1]]
+        if (gb1[mm] != ub1["bound"][mm]).any():
+            assert ub1["min_margin"][g] <= 1e-5, g
+            pytest.skip("a first-level binding decision inside its rounding margin differs")
+    # level-2 hosts from the oracle's first level
+    l1 = np.where(ub1["bound"] > 0, lab61, -1).astype(np.int32)
     nh, gof, off, mem = ref.groups(l1, prm.host_min)
     lv = got["levels"][0]
     assert lv["n_hosts"] == nh > 0
@@ -45,13 +69,12 @@ def test_levels_stagewise(ctx, vr, ref):
     # R of the level-2 hosts against their own background
     cm = ref.cell_moments(Pr, off, mem)
     R = ref.local_vdensity(Pr, off, mem, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)["R"]
-    Rg = lv["R"].cpu().numpy()
     hm = mem[:off[-1]]
-    err = np.abs(Rg[hm] - R[hm]) / np.maximum(1.0, np.abs(R[hm]))
-    assert err.max() <= 1e-4, err.max()
-    # 6D groups from the GPU's R, exact
+    if not R_agrees(lv["R"].cpu().numpy(), R, prm.R_threshold, where=hm):
+        pytest.skip("a second-level R within its tolerance classed differently at the threshold")
+    # 6D groups from the oracle's R, exact
     ellv = ref.host_ellv(Pr, off, mem, prm.alpha_v)
-    lab6 = ref.fof6d(Pr, gof, ellv, prm.alpha_xs * prm.ellx, Rg, prm.R_threshold)
+    lab6 = ref.fof6d(Pr, gof, ellv, prm.alpha_xs * prm.ellx, R, prm.R_threshold)
     np.testing.assert_array_equal(lv["label6"].cpu().numpy(), lab6)
     nc, _, soff, smem = ref.groups(lab6, prm.n_min)
     assert lv["n_candidates"] == nc > 0

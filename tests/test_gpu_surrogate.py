@@ -245,7 +245,11 @@ def test_trained_surrogate_gain_on_a_fresh_box(ctx, vr):
     np.testing.assert_array_equal(r_su[band], r_ex[band])
     np.testing.assert_array_equal(r_su[~band], rhat[~band])
     rec, prec = S.recall_precision(r_su >= prm.R_threshold, r_ex >= prm.R_threshold)
-    assert rec >= 0.99 and prec >= 0.95, (rec, prec)
+    n_out = int((r_ex >= prm.R_threshold).sum())
+    print(f"[surrogate] fresh box: {n_out} exact outliers, recall {rec:.5f}, precision {prec:.4f}, "
+          f"band {band.mean():.3f}", flush=True)
+    # the learned path's target: >= 99.5% of the exact outliers kept
+    assert rec >= 0.995 and prec >= 0.95, (rec, prec)
     assert band.mean() < 0.97, band.mean()
     untrained = dataclasses_replace(model, weights=dev_tensor(synth.mlp_init(7)))
     sx, _ = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm, until="R", model=untrained)
