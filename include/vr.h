@@ -263,6 +263,23 @@ int vr_assign_baryons(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const
  * -1.  A label >= n is an error (VR_ERR_INVALID_ARG).  Syncs. */
 int vr_relabel_min(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t min_size, int32_t* out, void* stream);
 
+/* vr_relabel_min for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, from the same kernels, but its per-label counts, minima
+ * and error flag live in a fixed device array of the library (2 x
+ * VR_NOALLOC_MAX_LABELS + 64 int32, about 32 MiB, held by each GPU the
+ * library runs on until the process ends; its address is taken once per
+ * device by vr_create).  The call allocates nothing: no hipMalloc, no
+ * workspace growth, no host allocation; it clears what it uses with fill
+ * kernels and syncs once (the error flag comes back through the context's
+ * pinned host memory).  n > VR_NOALLOC_MAX_LABELS is VR_ERR_INVALID_ARG.
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents: calls that overlap on one GPU (several streams, threads
+ * or contexts) race and must be serialised by the caller. */
+#define VR_NOALLOC_MAX_LABELS 4194304
+int vr_relabel_min_noalloc(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t min_size, int32_t* out,
+                           void* stream);
+
 /* Members of each group (offsets/members, device CSR) without the particles
  * flagged in drop (device [n], e.g. is_baryon): out_offsets (device
  * [n_groups+1]) and out_members (device, capacity offsets[n_groups]), order

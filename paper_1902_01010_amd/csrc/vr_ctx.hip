@@ -147,6 +147,7 @@ int vr_create(vr_ctx** out, int device, size_t max_workspace_bytes) {
                            device, prop.gcnArchName);
     if (hipSetDevice(device) != hipSuccess)
         return vr::set_err(nullptr, VR_ERR_HIP, "hipSetDevice(%d) failed", device);
+    if (int rc = vr::noalloc_scratch_init(device)) return rc;
     vr_ctx* c = new vr_ctx();
     c->device = device;
     c->num_cus = prop.multiProcessorCount;

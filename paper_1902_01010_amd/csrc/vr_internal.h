@@ -129,6 +129,11 @@ void timer_push(vr_ctx* ctx, const char* name, hipEvent_t e0, hipEvent_t e1, dou
         }                                                                    \
     } while (0)
 
+// Records the device's address of the fixed scratch array of
+// vr_relabel_min_noalloc (vr_species.hip); vr_create calls it with the
+// device current.
+int noalloc_scratch_init(int device);
+
 // Drops the cached unbinding graph (vr_unbind.hip).
 void unbind_release(vr_ctx* ctx);
 

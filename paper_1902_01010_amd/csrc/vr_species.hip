@@ -20,6 +20,8 @@
 #include "vr_grid.h"
 #include "vr_kd.h"
 
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -1064,6 +1066,71 @@ extern "C" int vr_relabel_min(vr_ctx* ctx, int64_t n, const int32_t* label, int3
     int badh = 0;
     if ((rc = read_back(ctx, bad, &badh, sizeof badh, st))) return rc;
     if (badh) return set_err(ctx, VR_ERR_INVALID_ARG, "a label is >= n");
+    return VR_OK;
+}
+
+// ---- vr_relabel_min without allocation ---------------------------------------
+// The counts, minima and error flag of vr_relabel_min_noalloc live in this
+// fixed device array: VR_NOALLOC_MAX_LABELS ints of counts, as many of minima,
+// then the flag.  Each GPU holds its own copy until the process ends; in host
+// code `scratch` names no device address, so kernels only ever get the
+// per-device address that noalloc_scratch_init() takes once per device.
+namespace {
+constexpr int64_t NOALLOC_INTS = 2 * (int64_t)VR_NOALLOC_MAX_LABELS + 64;
+static __device__ __align__(256) int32_t scratch[NOALLOC_INTS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+namespace vr {
+// Called by vr_create with `device` current: records that device's address of
+// `scratch` (once per device; later calls find it recorded).
+int noalloc_scratch_init(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES)
+        return set_err(nullptr, VR_ERR_UNSUPPORTED, "device %d beyond the %d the fixed scratch supports", device,
+                       NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return VR_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_err(nullptr, VR_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                       hipGetErrorString(e));
+    g_scratch_dev[device] = static_cast<int32_t*>(ptr);
+    return VR_OK;
+}
+}  // namespace vr
+
+extern "C" int vr_relabel_min_noalloc(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t min_size, int32_t* out,
+                                      void* stream) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    if (n < 0 || min_size < 1) return set_err(ctx, VR_ERR_INVALID_ARG, "need n >= 0 and min_size >= 1");
+    if (n > (int64_t)VR_NOALLOC_MAX_LABELS)
+        return set_err(ctx, VR_ERR_INVALID_ARG, "n = %lld exceeds the %d labels of the fixed scratch", (long long)n,
+                       VR_NOALLOC_MAX_LABELS);
+    if (n == 0) return VR_OK;
+    if (!label || !out) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL array");
+    int32_t* base = (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) ? g_scratch_dev[ctx->device] : nullptr;
+    if (!base) return set_err(ctx, VR_ERR_HIP, "no scratch address recorded for device %d", ctx->device);
+    VR_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    int32_t* cnt = base;
+    int32_t* low = base + VR_NOALLOC_MAX_LABELS;
+    int32_t* bad = base + 2 * (int64_t)VR_NOALLOC_MAX_LABELS;
+    // what a previous call left behind is cleared by fill kernels
+    int rc;
+    if ((rc = fill_i32(ctx, cnt, 0, n, st)) || (rc = fill_i32(ctx, low, 0x7FFFFFFF, n, st)) ||
+        (rc = fill_i32(ctx, bad, 0, 1, st)))
+        return rc;
+    hipLaunchKernelGGL(k_label_stats, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, cnt, low, bad);
+    hipLaunchKernelGGL(k_label_min, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, cnt, low, min_size, out);
+    VR_LAUNCH_CHECK(ctx);
+    // the flag comes back through the context's pinned host words
+    int32_t* flag_h = reinterpret_cast<int32_t*>(ctx->pinned);
+    VR_HIP(ctx, hipMemcpyAsync(flag_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    VR_HIP(ctx, hipStreamSynchronize(st));
+    if (*flag_h) return set_err(ctx, VR_ERR_INVALID_ARG, "a label is >= n");
     return VR_OK;
 }
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvr.so")
 VR_OK, VR_ERR_INVALID_ARG, VR_ERR_NO_DEVICE, VR_ERR_OUT_OF_MEMORY = 0, -1, -2, -3
 VR_ERR_HIP, VR_ERR_NOT_CONVERGED, VR_ERR_UNSUPPORTED = -4, -5, -6
 CELL_COLS = 28
+NOALLOC_MAX_LABELS = 4194304
 
 # Entry points declared in include/vr.h (checked by the CPU test-suite).
 ENTRY_POINTS = (
@@ -25,7 +26,7 @@ ENTRY_POINTS = (
     "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune", "vr_autotune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
     "vr_host_ellv", "vr_fof6d", "vr_fof_sub", "vr_sub_grow", "vr_fof3d_dm", "vr_assign_baryons",
-    "vr_relabel_min", "vr_select_members", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
+    "vr_relabel_min", "vr_relabel_min_noalloc", "vr_select_members", "vr_unbind", "vr_ell_fit", "vr_ell_clean",
     "vr_rs_features", "vr_mlp_forward", "vr_mlp_grad", "vr_mlp_train_step", "vr_rs_select",
 )
 
@@ -110,6 +111,7 @@ def load_library():
         L.vr_fof3d_dm.argtypes = [vp, P, dbl, vp, vp, vp]
         L.vr_assign_baryons.argtypes = [vp, P, i32, vp, vp, vp, vp, dbl, dbl, vp, dbl, vp, vp, vp]
         L.vr_relabel_min.argtypes = [vp, i64, vp, i32, vp, vp]
+        L.vr_relabel_min_noalloc.argtypes = [vp, i64, vp, i32, vp, vp]
         L.vr_select_members.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp]
         L.vr_sub_grow.argtypes = [vp, P, vp, i32, vp, vp, flt, dbl, dbl, dbl, dbl, dbl, dbl, dbl, i32, vp, vp,
                                   C.POINTER(i32), vp]
@@ -363,6 +365,15 @@ class Context:
         if out is None:
             out = torch.empty_like(label)
         self._check(self.lib.vr_relabel_min(self.h, label.shape[0], _ptr(label), int(min_size), _ptr(out), _stream()))
+        return out
+
+    def relabel_min_noalloc(self, label, min_size=1, out=None):
+        """relabel_min through the entry point that allocates nothing (fixed
+        library scratch; at most NOALLOC_MAX_LABELS labels)."""
+        if out is None:
+            out = torch.empty_like(label)
+        self._check(self.lib.vr_relabel_min_noalloc(self.h, label.shape[0], _ptr(label), int(min_size), _ptr(out),
+                                                    _stream()))
         return out
 
     def select_members(self, n, offsets, members, drop):
