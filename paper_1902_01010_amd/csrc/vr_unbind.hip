@@ -13,6 +13,14 @@
 // 11-bit radix select over (d2, index) keys, takes their mass-weighted mean
 // velocity as the frame, evaluates beta_E T + W, and compacts the survivors
 // in place (stable, so index order is kept).
+//
+// The persistent schedule updates the potential incrementally: the group
+// kernel keeps each survivor's FP64 sum with it and writes the members it
+// removed to a side list; the next pass subtracts those members' terms from
+// the survivors' sums (|S| |D| pairs instead of |S|^2).  A group returns to
+// a full recompute once the members removed since its last one exceed a
+// quarter of its current size, which bounds the error the subtractions add
+// to that of a full FP32-tiled sum (a quarter of it).
 #include "vr_internal.h"
 
 #include <algorithm>
@@ -34,11 +42,21 @@ struct Members {
     float* m;            // null for uniform mass
 };
 
+// Members removed by a group's last pass, at the group's base (stable
+// order), and the per-group bookkeeping of the incremental potential:
+// nrm = members removed by the last pass; since = removed since the last
+// full recompute; mode = 1 when the next pass may subtract them instead of
+// recomputing.
+struct Removed {
+    float *x, *y, *z, *m;
+    int *nrm, *since, *mode;
+};
+
 __global__ void k_ub_init(int ng, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
                           const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                           const uint32_t* __restrict__ qz, const float* __restrict__ vx, const float* __restrict__ vy,
                           const float* __restrict__ vz, const float* __restrict__ mass, int gb, int n_min, Members W,
-                          int* __restrict__ cnt, int* __restrict__ state, int32_t* __restrict__ iters,
+                          Removed Rm, int* __restrict__ cnt, int* __restrict__ state, int32_t* __restrict__ iters,
                           uint8_t* __restrict__ bound, double* __restrict__ phi) {
     const int g = blockIdx.x;
     const int s = off[g], e = off[g + 1];
@@ -61,6 +79,9 @@ __global__ void k_ub_init(int ng, const int32_t* __restrict__ off, const int32_t
         cnt[g] = e - s;
         state[g] = (e - s < n_min) ? ST_DISSOLVED : ST_ACTIVE;
         iters[g] = 0;
+        Rm.nrm[g] = 0;
+        Rm.since[g] = 0;
+        Rm.mode[g] = 0;
     }
 }
 
@@ -181,8 +202,8 @@ __device__ __forceinline__ uint64_t ref_key(const Members& W, int base, int pos,
 
 __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active, const int32_t* __restrict__ off,
                                                  int* __restrict__ cnt, int* __restrict__ state,
-                                                 int32_t* __restrict__ iters, Members W,
-                                                 const double* __restrict__ acc, double eps2g, double scale,
+                                                 int32_t* __restrict__ iters, Members W, Removed Rm,
+                                                 double* __restrict__ acc, double eps2g, double scale,
                                                  double mass_value, double beta_E, double frac_ref, int n_min,
                                                  int n_ref_min, int frame_type, int gb, uint8_t* __restrict__ bound,
                                                  double* __restrict__ phi, int max_iter) {
@@ -319,21 +340,24 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
     }
     bsum<4>(fr, smd);
     const double vr0 = fr[1] / fr[0], vr1 = fr[2] / fr[0], vr2 = fr[3] / fr[0];
-    // 5. energies, removal and stable in-place compaction
-    uint32_t kept = 0;
+    // 5. energies, removal and stable in-place compaction; survivors keep
+    // their sums, removed members go to the side list
+    uint32_t kept = 0, gone = 0;
     for (int c0 = 0; c0 < n; c0 += blockDim.x) {
         const int k = c0 + tid;
         const bool valid = k < n;
         int32_t gi = 0;
         float x = 0, y = 0, z = 0, ux = 0, uy = 0, uz = 0, mm = 0;
+        double a = 0.0;
         bool keep = false;
         if (valid) {
             gi = W.gidx[base + k];
             x = W.x[base + k]; y = W.y[base + k]; z = W.z[base + k];
             ux = W.vx[base + k]; uy = W.vy[base + k]; uz = W.vz[base + k];
             mm = uniform ? 0.f : W.m[base + k];
+            a = acc[base + k];
             const double m = uniform ? mass_value : (double)mm;
-            const double ph = scale * (uniform ? mass_value : 1.0) * acc[base + k];
+            const double ph = scale * (uniform ? mass_value : 1.0) * a;
             const double dx = (double)ux - vr0, dy = (double)uy - vr1, dz = (double)uz - vr2;
             const double T = 0.5 * m * (dx * dx + dy * dy + dz * dz);
             const double Wp = m * ph;
@@ -341,16 +365,23 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
             keep = !(E >= 0.0);
             phi[gi] = ph;
         }
-        uint32_t tot;
+        uint32_t tot, totr;
         const uint32_t r = bscan(keep ? 1u : 0u, smu, &tot);
+        const uint32_t rr = bscan((valid && !keep) ? 1u : 0u, smu, &totr);
         if (keep) {
             const int dst = base + (int)(kept + r);
             W.gidx[dst] = gi;
             W.x[dst] = x; W.y[dst] = y; W.z[dst] = z;
             W.vx[dst] = ux; W.vy[dst] = uy; W.vz[dst] = uz;
             if (!uniform) W.m[dst] = mm;
+            acc[dst] = a;
+        } else if (valid) {
+            const int dst = base + (int)(gone + rr);
+            Rm.x[dst] = x; Rm.y[dst] = y; Rm.z[dst] = z;
+            Rm.m[dst] = uniform ? 1.f : mm;
         }
         kept += tot;
+        gone += totr;
         __syncthreads();
     }
     if (kept == (uint32_t)n) {
@@ -362,6 +393,13 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
     if (tid == 0) {
         cnt[g] = (int)kept;
         iters[g] += 1;
+        // the next pass subtracts the removed terms while those removed since
+        // the last full recompute stay within a quarter of the survivors
+        const int since = Rm.since[g] + (int)gone;
+        const bool incr = 4 * (int64_t)since <= (int64_t)kept;
+        Rm.nrm[g] = (int)gone;
+        Rm.since[g] = incr ? since : 0;
+        Rm.mode[g] = incr ? 1 : 0;
     }
 }
 
@@ -387,6 +425,7 @@ constexpr int PLAN_T = 1024;
 
 __global__ __launch_bounds__(PLAN_T) void k_ub_plan(int ng, const int* __restrict__ cnt, const int* __restrict__ state,
                                                     const int32_t* __restrict__ iters, int max_iter, int jchunk,
+                                                    const int* __restrict__ nrm, const int* __restrict__ mode,
                                                     int* __restrict__ act, int* __restrict__ item_off, UbPlan* plan) {
     __shared__ uint32_t sm[32];
     __shared__ double smd[PLAN_T / 64];
@@ -396,8 +435,10 @@ __global__ __launch_bounds__(PLAN_T) void k_ub_plan(int ng, const int* __restric
         const int g = base + (int)threadIdx.x;
         const bool on = g < ng && state[g] == ST_ACTIVE && iters[g] < max_iter;
         const int n = on ? cnt[g] : 0;
-        pairs += (double)n * (double)(n > 0 ? n - 1 : 0);
-        const uint32_t items = on ? (uint32_t)(((n + 63) / 64) * ((n + jchunk - 1) / jchunk)) : 0u;
+        // j over all members (full) or over the members removed last pass
+        const int nj = (on && mode[g]) ? nrm[g] : n;
+        pairs += (double)n * (double)(on && mode[g] ? nj : (n > 0 ? n - 1 : 0));
+        const uint32_t items = on ? (uint32_t)(((n + 63) / 64) * ((nj + jchunk - 1) / jchunk)) : 0u;
         uint32_t tg, ti;
         const uint32_t pg = bscan(on ? 1u : 0u, sm, &tg);
         const uint32_t pi = bscan(items, sm, &ti);
@@ -423,9 +464,11 @@ __global__ __launch_bounds__(PLAN_T) void k_ub_plan(int ng, const int* __restric
 }
 
 __global__ void k_ub_zero_p(const UbPlan* __restrict__ plan, const int* __restrict__ act,
-                            const int32_t* __restrict__ off, const int* __restrict__ cnt, double* __restrict__ acc) {
+                            const int32_t* __restrict__ off, const int* __restrict__ cnt, const int* __restrict__ mode,
+                            double* __restrict__ acc) {
     if ((int)blockIdx.x >= plan->n_active) return;
     const int g = act[blockIdx.x];
+    if (mode[g]) return;  // sums kept: the pass subtracts
     const int s = off[g], e = s + cnt[g];
     for (int k = s + threadIdx.x; k < e; k += blockDim.x) acc[k] = 0.0;
 }
@@ -435,7 +478,7 @@ __global__ void k_ub_zero_p(const UbPlan* __restrict__ plan, const int* __restri
 template <bool UNIFORM>
 __global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* __restrict__ act,
                                                        const int* __restrict__ item_off, const int32_t* __restrict__ off,
-                                                       const int* __restrict__ cnt, Members W, float eps2,
+                                                       const int* __restrict__ cnt, Members W, Removed Rm, float eps2,
                                                        double* __restrict__ acc, int jchunk, int tile) {
     extern __shared__ float4 sjall[];
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
@@ -454,30 +497,39 @@ __global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* 
         }
         const int g = act[lo];
         const int base = off[g], n = cnt[g];
-        const int njc = (n + jchunk - 1) / jchunk;
+        // full: j over the members; incremental: j over last pass's removed
+        const bool incr = Rm.mode[g] != 0;
+        const int nj = incr ? Rm.nrm[g] : n;
+        const float* __restrict__ jx = incr ? Rm.x : W.x;
+        const float* __restrict__ jy = incr ? Rm.y : W.y;
+        const float* __restrict__ jz = incr ? Rm.z : W.z;
+        const float* __restrict__ jm = incr ? Rm.m : W.m;
+        const int njc = (nj + jchunk - 1) / jchunk;
         const int local = it - item_off[lo];
         const int i0 = (local / njc) * 64, j0 = (local % njc) * jchunk;
-        const int j1 = min(n, j0 + jchunk);
+        const int j1 = min(nj, j0 + jchunk);
         const int i = i0 + lane;
         const bool valid = i < n;
         const float xi = valid ? W.x[base + i] : 0.f, yi = valid ? W.y[base + i] : 0.f, zi = valid ? W.z[base + i] : 0.f;
+        // a removed member is never i itself; only coincident pairs need care
+        const int iself = incr ? -1 : i;
         double accd = 0.0;
         for (int jb = j0; jb < j1; jb += tile) {
             const int jn = min(tile, j1 - jb);
             __builtin_amdgcn_wave_barrier();
             for (int t = lane; t < jn; t += 64) {
                 const int k = base + jb + t;
-                sj[t] = make_float4(W.x[k], W.y[k], W.z[k], UNIFORM ? 1.f : W.m[k]);
+                sj[t] = make_float4(jx[k], jy[k], jz[k], UNIFORM ? 1.f : jm[k]);
             }
             __builtin_amdgcn_wave_barrier();
             for (int t0 = 0; t0 < jn; t0 += 64) {
                 const int t1 = min(t0 + 64, jn);
-                const bool check = eps2 == 0.f || (jb + t0 < i0 + 64 && jb + t1 > i0);
-                accd += (double)(check ? tile_sum<UNIFORM, true>(sj, t0, t1, xi, yi, zi, eps2, jb, i)
-                                       : tile_sum<UNIFORM, false>(sj, t0, t1, xi, yi, zi, eps2, jb, i));
+                const bool check = eps2 == 0.f || (!incr && jb + t0 < i0 + 64 && jb + t1 > i0);
+                accd += (double)(check ? tile_sum<UNIFORM, true>(sj, t0, t1, xi, yi, zi, eps2, jb, iself)
+                                       : tile_sum<UNIFORM, false>(sj, t0, t1, xi, yi, zi, eps2, jb, iself));
             }
         }
-        if (valid) atomicAdd(&acc[base + i], accd);
+        if (valid) atomicAdd(&acc[base + i], incr ? -accd : accd);
     }
 }
 
@@ -511,7 +563,7 @@ constexpr int PASSES_PER_GRAPH = 4;
 // Everything a captured pass depends on; a cached graph is reused only when
 // all of it is unchanged.
 struct UbGraphKey {
-    const void* ptrs[16];
+    const void* ptrs[24];
     int ints[12];
     double dbls[6];
 };
@@ -530,7 +582,7 @@ void ub_graph_release(vr_ctx* ctx) {
 // captured PASSES_PER_GRAPH at a time in a graph that is replayed until no
 // group is active; the host reads two counters per replay.
 int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int32_t* offsets,
-                      const vr_unbind_params* up, const Members& W, double* acc, int* cnt, int* state,
+                      const vr_unbind_params* up, const Members& W, const Removed& Rm, double* acc, int* cnt, int* state,
                       int32_t* iters, uint8_t* bound, double* phi, int* act, float eps2f, double eps2g,
                       double scale, int tile, hipStream_t st) {
     VR_WS(plan, ctx, UbPlan, WS_D4, 1);
@@ -549,8 +601,8 @@ int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int3
 
     UbGraphKey key;
     std::memset(&key, 0, sizeof key);
-    const void* kp[16] = {offsets, W.gidx, W.x, W.y, W.z, W.vx, W.vy, W.vz, W.m, acc, cnt, state, iters, bound, phi,
-                          act};
+    const void* kp[24] = {offsets, W.gidx, W.x, W.y, W.z, W.vx, W.vy, W.vz, W.m, acc, cnt, state, iters, bound, phi,
+                          act, Rm.x, Rm.y, Rm.z, Rm.m, Rm.nrm, Rm.since, Rm.mode, nullptr};
     std::memcpy(key.ptrs, kp, sizeof kp);
     const int ki[12] = {ng, up->max_iter, jchunk, tile, (int)pgrid, up->n_min, up->n_ref_min, up->frame_type,
                         p->grid_bits, uniform ? 1 : 0, 0, 0};
@@ -569,16 +621,16 @@ int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int3
         VR_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < PASSES_PER_GRAPH; ++k) {
             hipLaunchKernelGGL(k_ub_plan, dim3(1), dim3(PLAN_T), 0, cs, ng, cnt, state, iters, up->max_iter, jchunk,
-                               act, item_off, plan);
-            hipLaunchKernelGGL(k_ub_zero_p, dim3(ng), dim3(256), 0, cs, plan, act, offsets, cnt, acc);
+                               Rm.nrm, Rm.mode, act, item_off, plan);
+            hipLaunchKernelGGL(k_ub_zero_p, dim3(ng), dim3(256), 0, cs, plan, act, offsets, cnt, Rm.mode, acc);
             if (uniform)
                 hipLaunchKernelGGL(k_ub_potential_p<true>, dim3(pgrid), dim3(UB), lds, cs, plan, act, item_off,
-                                   offsets, cnt, W, eps2f, acc, jchunk, tile);
+                                   offsets, cnt, W, Rm, eps2f, acc, jchunk, tile);
             else
                 hipLaunchKernelGGL(k_ub_potential_p<false>, dim3(pgrid), dim3(UB), lds, cs, plan, act, item_off,
-                                   offsets, cnt, W, eps2f, acc, jchunk, tile);
+                                   offsets, cnt, W, Rm, eps2f, acc, jchunk, tile);
             hipLaunchKernelGGL(k_ub_group, dim3(ng), dim3(UB), 0, cs, (const int*)nullptr, offsets, cnt, state,
-                               iters, W, acc, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min,
+                               iters, W, Rm, acc, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min,
                                up->n_ref_min, up->frame_type, p->grid_bits, bound, phi, up->max_iter);
         }
         hipLaunchKernelGGL(k_ub_count, dim3(1), dim3(PLAN_T), 0, cs, ng, state, iters, up->max_iter, plan);
@@ -678,8 +730,13 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     VR_WS(cnt, ctx, int, WS_D0, n_groups);
     VR_WS(state, ctx, int, WS_D1, n_groups);
     VR_WS(act, ctx, int, WS_D2, n_groups);
+    Removed Rm;
+    VR_WS(rx, ctx, float, WS_B0, M); VR_WS(ry, ctx, float, WS_B1, M); VR_WS(rz, ctx, float, WS_B2, M);
+    VR_WS(rmass, ctx, float, WS_B3, M);
+    VR_WS(nrm, ctx, int, WS_B4, n_groups); VR_WS(since, ctx, int, WS_B5, n_groups); VR_WS(mode, ctx, int, WS_B6, n_groups);
+    Rm.x = rx; Rm.y = ry; Rm.z = rz; Rm.m = rmass; Rm.nrm = nrm; Rm.since = since; Rm.mode = mode;
     hipLaunchKernelGGL(k_ub_init, dim3(n_groups), dim3(256), 0, st, n_groups, offsets, members, p->qx, p->qy, p->qz,
-                       p->vx, p->vy, p->vz, p->mass, p->grid_bits, up->n_min, W, cnt, state, iters, bound, phi);
+                       p->vx, p->vy, p->vz, p->mass, p->grid_bits, up->n_min, W, Rm, cnt, state, iters, bound, phi);
     VR_LAUNCH_CHECK(ctx);
     const double unit = p->box / ldexp(1.0, p->grid_bits);
     const double epsg = up->eps / unit;
@@ -688,7 +745,7 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     const double scale = -up->G / unit;  // potential = scale * mass * sum(1/r) in grid units
     int tile = up->tile ? up->tile : (ctx->tuned_tile ? ctx->tuned_tile : 256);
     if (up->persistent)
-        return unbind_persistent(ctx, p, n_groups, offsets, up, W, acc, cnt, state, iters, bound, phi, act,
+        return unbind_persistent(ctx, p, n_groups, offsets, up, W, Rm, acc, cnt, state, iters, bound, phi, act,
                                  eps2f, eps2g, scale, std::min(tile, PERSIST_MAX_TILE), st);
     std::vector<int> hcnt(n_groups), hstate(n_groups), hact;
     std::vector<int4> items;
@@ -731,7 +788,7 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
                                         cnt, W, eps2f, acc, tile));
         VR_LAUNCH_CHECK(ctx);
         VR_TIMED(ctx, "unbind_group", st, nmem,
-                 hipLaunchKernelGGL(k_ub_group, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, acc,
+                 hipLaunchKernelGGL(k_ub_group, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, Rm, acc,
                                     eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min, up->n_ref_min,
                                     up->frame_type, p->grid_bits, bound, phi, up->max_iter));
         VR_LAUNCH_CHECK(ctx);

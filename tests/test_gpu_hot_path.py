@@ -339,7 +339,9 @@ def test_unbind_persistent_launch_shapes_and_graph_reuse(ctx, vr, ref):
 
 def test_unbind_persistent_matches_host_planned(ctx, vr, ref):
     """Both schedules run the same passes: identical bound flags and pass
-    counts, potentials equal up to the order of the FP64 partial sums."""
+    counts; potentials equal to the FP32 tile error (the persistent schedule
+    subtracts the removed members' terms where the host-planned one
+    recomputes the sums)."""
     w = _unbind_case(7, 60, 3000)
     P, _ = both(ctx, vr, ref, w)
     off, mem = w.groups
@@ -351,7 +353,7 @@ def test_unbind_persistent_matches_host_planned(ctx, vr, ref):
     pa, pb = a["phi"].cpu().numpy(), b["phi"].cpu().numpy()
     assert (np.isfinite(pa) == np.isfinite(pb)).all()
     f = np.isfinite(pa)
-    np.testing.assert_allclose(pb[f], pa[f], rtol=1e-9)
+    np.testing.assert_allclose(pb[f], pa[f], rtol=2e-6)
 
 
 @pytest.mark.parametrize("name", list(CASES))
