@@ -105,7 +105,26 @@ def kernel_table(ctx, steps):
         kernels[name] = {"bound": bound, "launches_per_step": launches / steps, "ms_per_step": ms / steps,
                          "avg_launch_ms": ms / launches, "achieved": achieved, "peak": peak, "unit": unit,
                          "frac": achieved / peak}
+        if name == "knn":
+            # candidate distances the neighbour searches evaluated (counted on
+            # the device while timing): the kernel's pair work
+            _, _, cand = ctx.kernel_time("knn_candidates")
+            if cand > 0:
+                kernels[name]["candidates_per_s"] = cand / (ms / 1e3)
+                kernels[name]["candidates_per_query"] = cand / work
     return kernels
+
+
+def cpu_model():
+    """The host CPU's model string (lscpu's "Model name", from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(w, prm, side):
@@ -124,9 +143,11 @@ def cpu_baseline(w, prm, side):
     t0 = time.perf_counter()
     opipe.run(sub, prm)
     dt = time.perf_counter() - t0
-    return {"value": sub.n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+    return {"value": sub.n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"all particles of the sub-box [0, {side:g})^3 Mpc/h of the same 256^3 box "
-                      f"({sub.n} particles, {dt:.1f} s on {threads} threads)"}
+                      f"({sub.n} particles, {dt:.1f} s on {threads} threads); hosts are cut at the sub-box faces "
+                      f"and the oracle's brute-force kNN costs O(N_H^2) per host, so this rate is not the "
+                      f"full box's"}
 
 
 def bench_unbind(args):
@@ -209,7 +230,7 @@ def unbind_cpu_baseline(w, off, mem, sizes):
     s2_sample = float((sizes[pick].astype(float) ** 2).sum())
     s2_all = float((sizes.astype(float) ** 2).sum())
     t_all = dt * s2_all / s2_sample
-    return {"value": w.n / t_all, "unit": "particles/s", "cores": threads, "kind": "oracle",
+    return {"value": w.n / t_all, "unit": "particles/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{len(pick)} groups ({int(sizes[pick].sum())} particles, every 25th group of <= 20000) in "
                       f"{dt:.1f} s; whole set extrapolated through sum N^2 to {t_all:.0f} s"}
 
@@ -327,6 +348,9 @@ def main():
     traffic = profiled_traffic(dom)
     roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
                 "frac": round(d["frac"], 5), "traffic": traffic, "kernel": dom}
+    if "candidates_per_s" in d:
+        roofline["candidates_per_s"] = d["candidates_per_s"]
+        roofline["candidates_per_query"] = d["candidates_per_query"]
     if traffic is not None:
         roofline["traffic_unit"] = "bytes per launch"
     # the headline is the surrogate+fallback path only where it keeps the

@@ -59,8 +59,11 @@ size_t vr_workspace_bytes(const vr_ctx* ctx);
  * kernel: "fof_link3d" particles, "kd_level" member visits, "knn" queries,
  * "fof_link6d" participants, "unbind_potential" ordered pairs i != j,
  * "unbind_group" members, "radix_scatter" keys, "unbind_persistent" ordered
- * pairs i != j, timed from the first to the last graph replay of one call).  vr_set_timing also clears
- * the totals.  vr_kernel_time waits for the recorded events. */
+ * pairs i != j, timed from the first to the last graph replay of one call).
+ * The name "knn_candidates" reports the "knn" launches and time with, as the
+ * work, the candidate distances the neighbour searches evaluated (summed by
+ * the kernel itself while timing is on).  vr_set_timing also clears the
+ * totals.  vr_kernel_time waits for the recorded events. */
 int vr_set_timing(vr_ctx* ctx, int enabled);
 
 /* Launch-shape knobs of the context (integer results never depend on them;

@@ -172,6 +172,7 @@ void vr_destroy(vr_ctx* ctx) {
     for (auto& b : ctx->slots)
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->knn_cand) (void)hipFree(ctx->knn_cand);
     delete ctx;
 }
 
@@ -195,6 +196,10 @@ int vr_set_timing(vr_ctx* ctx, int enabled) {
     vr::timers_drain(ctx);
     ctx->timers.clear();
     ctx->timing = enabled ? 1 : 0;
+    if (enabled) {
+        if (!ctx->knn_cand) VR_HIP(ctx, hipMalloc((void**)&ctx->knn_cand, sizeof(unsigned long long)));
+        VR_HIP(ctx, hipMemset(ctx->knn_cand, 0, sizeof(unsigned long long)));
+    }
     return VR_OK;
 }
 
@@ -242,12 +247,23 @@ int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* t
     *launches = 0;
     *total_ms = 0.0;
     *work = 0.0;
+    // "knn_candidates": the kNN launches and time, with the candidate
+    // distances the searches evaluated as the work
+    const bool cand = std::strcmp(kernel, "knn_candidates") == 0;
     for (auto& t : ctx->timers)
-        if (t.name == kernel) {
+        if (t.name == (cand ? "knn" : kernel)) {
             *launches = t.launches;
             *total_ms = t.ms;
             *work = t.work;
         }
+    if (cand) {
+        *work = 0.0;
+        if (ctx->knn_cand) {
+            unsigned long long c = 0;
+            VR_HIP(ctx, hipMemcpy(&c, ctx->knn_cand, sizeof c, hipMemcpyDeviceToHost));
+            *work = (double)c;
+        }
+    }
     return VR_OK;
 }
 

@@ -265,6 +265,178 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const ckey_t* __rest
 }
 
 
+// ---- the linking sweep by tiles ---------------------------------------------
+// One wavefront per tile of (at most) 64 participants of one cell, lane =
+// participant p.  The own cell (candidates after p) and its 13 forward
+// neighbour cells are staged through LDS 64 candidates at a time --
+// coordinates, velocity, host, the paper linker's relative velocity, and the
+// candidate's union-find root as read at staging -- so each candidate is
+// fetched once per wavefront and read by all lanes from LDS.  An FP32
+// distance prefilter (coordinate differences are exact integers below 2^21,
+// the rounded square sum lies within 2e-7 of the exact one) passes every
+// candidate that may lie inside the linking length; those get the exact
+// integer d2 and the FP64 predicate of k_link6d.  A candidate's parent, read
+// at staging, is one of its ancestors: equal to p's root, the pair is already
+// joined and no further global access is needed.
+
+// tiles of 64 participants per cell
+__global__ void k_tile_count(int64_t ncell, const uint32_t* __restrict__ cell_start, uint32_t* __restrict__ cnt) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) cnt[c] = (cell_start[c + 1] - cell_start[c] + 63) >> 6;
+}
+
+__global__ void k_tile_write(int64_t ncell, const uint32_t* __restrict__ cell_start, const uint32_t* __restrict__ toff,
+                             int2* __restrict__ tiles) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const uint32_t s = cell_start[c], e = cell_start[c + 1];
+    uint32_t t = toff[c];
+    for (uint32_t q = s; q < e; q += 64) tiles[t++] = make_int2((int)c, (int)q);
+}
+
+template <bool PAPER>
+__global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ tiles, const uint32_t* __restrict__ ntiles,
+                                                    const ckey_t* __restrict__ key, const uint32_t* __restrict__ sx,
+                                                    const uint32_t* __restrict__ sy, const uint32_t* __restrict__ sz,
+                                                    const float* __restrict__ svx, const float* __restrict__ svy,
+                                                    const float* __restrict__ svz, const int32_t* __restrict__ shost,
+                                                    const double* __restrict__ ellv,
+                                                    const uint32_t* __restrict__ cell_start,
+                                                    const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
+                                                    uint32_t hmask, int b, int gb, double ell2, int* parent,
+                                                    unsigned xchunk, SubLink sub) {
+    __shared__ int cxs[64], cys[64], czs[64], chs[64], crt[64], cq[64];
+    __shared__ float cvx[64], cvy[64], cvz[64];
+    __shared__ double cu0[PAPER ? 64 : 1], cu1[PAPER ? 64 : 1], cu2[PAPER ? 64 : 1], cs_[PAPER ? 64 : 1];
+    const uint32_t t = xcd_swizzle(blockIdx.x, gridDim.x, xchunk);
+    if (t >= ntiles[0]) return;
+    const int lane = (int)threadIdx.x;
+    const int2 tl = tiles[t];
+    const uint32_t q0 = (uint32_t)tl.y, cend = cell_start[tl.x + 1];
+    const uint32_t p = q0 + (uint32_t)lane;
+    bool valid = p < cend;
+    const ckey_t k = key[q0];
+    const int nc = 1 << b;
+    const int cx = (int)(k & (nc - 1)), cy = (int)((k >> b) & (nc - 1)), cz = (int)(k >> (2 * b));
+    // lane o < 14: the candidate range of segment o -- the 13 forward
+    // neighbour cells, then the own cell from the tile's first participant --
+    // all looked up at once
+    uint32_t seg_s = 0, seg_n = 0;
+    if (lane < 14) {
+        if (lane == 13) {
+            seg_s = q0;
+            seg_n = cend - q0;
+        } else {
+            const int o = 14 + lane;  // forward offsets 14..26
+            const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+            const uint32_t nx = (uint32_t)((cx + dx + nc) & (nc - 1));
+            const uint32_t ny = (uint32_t)((cy + dy + nc) & (nc - 1));
+            const uint32_t nz = (uint32_t)((cz + dz + nc) & (nc - 1));
+            const int c2 = hash_find(hkeys, hvals, hmask, cell_key(nx, ny, nz, b));
+            if (c2 >= 0) {
+                seg_s = cell_start[c2];
+                seg_n = cell_start[c2 + 1] - seg_s;
+            }
+        }
+    }
+    // exclusive prefix of the segment lengths over lanes 0..13
+    uint32_t incl = seg_n;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t total = __shfl(incl, 13, 64);
+    const uint32_t seg_b = incl - seg_n;  // first candidate number of this lane's segment
+    const uint32_t own_b = __shfl(seg_b, 13, 64);
+
+    const int px = valid ? (int)sx[p] : 0, py = valid ? (int)sy[p] : 0, pz = valid ? (int)sz[p] : 0;
+    const double vpx = valid ? (double)svx[p] : 0.0, vpy = valid ? (double)svy[p] : 0.0,
+                 vpz = valid ? (double)svz[p] : 0.0;
+    const int hp = valid ? shost[p] : -1;
+    const double ev = (PAPER || !valid) ? 1.0 : ellv[hp];
+    const double ev2 = ev * ev;
+    double up0 = 0, up1 = 0, up2 = 0, sp = 0;
+    if constexpr (PAPER) {
+        if (valid) {
+            up0 = sub.u0[p];
+            up1 = sub.u1[p];
+            up2 = sub.u2[p];
+            sp = sub.s[p];
+        }
+        if (!(sp > 0)) valid = false;  // no direction: links nothing
+    }
+    const double rl2 = 1.0 / ell2, rv2 = 1.0 / ev2;
+    // no candidate with an FP32 square sum above this lies within ell
+    const float ellf = (float)(ell2 * (1.0 + 1e-6)) + 1.0f;
+    int rp = valid ? uf_find(parent, (int)p) : -1;
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+        const uint32_t c = c0 + (uint32_t)lane;
+        // the segment holding candidate c: the last lane o < 14 whose first
+        // candidate number is <= c (empty segments share numbers); every lane
+        // takes part in the shuffles, lanes past the end load nothing
+        int sg = 0;
+#pragma unroll
+        for (int o = 1; o < 14; ++o) {
+            const uint32_t bo = __shfl(seg_b, o, 64);
+            if (bo <= c) sg = o;
+        }
+        const uint32_t q = __shfl(seg_s, sg, 64) + (c - __shfl(seg_b, sg, 64));
+        __builtin_amdgcn_wave_barrier();
+        if (c < total) {
+            cq[lane] = (int)q;
+            cxs[lane] = (int)sx[q];
+            cys[lane] = (int)sy[q];
+            czs[lane] = (int)sz[q];
+            chs[lane] = shost[q];
+            cvx[lane] = svx[q];
+            cvy[lane] = svy[q];
+            cvz[lane] = svz[q];
+            crt[lane] = parent[q];  // an ancestor of q (no path-halving writes)
+            if constexpr (PAPER) {
+                cu0[lane] = sub.u0[q];
+                cu1[lane] = sub.u1[q];
+                cu2[lane] = sub.u2[q];
+                cs_[lane] = sub.s[q];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int m = (int)min(64u, total - c0);
+        if (!valid) continue;
+        for (int j = 0; j < m; ++j) {
+            const int qq = cq[j];
+            // own cell: only the candidates after p
+            if (c0 + (uint32_t)j >= own_b && (uint32_t)qq <= p) continue;
+            const int ddx = min_image(cxs[j] - px, gb);
+            const int ddy = min_image(cys[j] - py, gb);
+            const int ddz = min_image(czs[j] - pz, gb);
+            const float fx = (float)ddx, fy = (float)ddy, fz = (float)ddz;
+            if (fmaf(fx, fx, fmaf(fy, fy, fz * fz)) > ellf || chs[j] != hp) continue;
+            const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
+            if (d2 >= ell2) continue;
+            bool link;
+            if constexpr (PAPER) {
+                const double sq = cs_[j];
+                if (!(sq > 0) || !(sp <= sub.Vr * sq && sq <= sub.Vr * sp)) continue;
+                const double dot = up0 * cu0[j] + up1 * cu1[j] + up2 * cu2[j];
+                link = dot >= sub.cos_op * (sp * sq);
+            } else {
+                const double ax = vpx - (double)cvx[j], ay = vpy - (double)cvy[j], az = vpz - (double)cvz[j];
+                const double dv2 = ax * ax + ay * ay + az * az;
+                const double ta = d2 * rl2 + dv2 * rv2;
+                link = ta < 1.0 - 1e-9;
+                if (!link && ta <= 1.0 + 1e-9) link = d2 / ell2 + dv2 / ev2 < 1.0;
+            }
+            if (!link || crt[j] == rp) continue;
+            const int rq = uf_find(parent, qq);
+            if (rq == rp) continue;
+            rp = uf_find(parent, rp);
+            if (rp != rq) uf_union(parent, rp, rq);
+            rp = uf_find(parent, rp);
+        }
+    }
+}
+
 // ---- second, relaxed stage of the paper's linker --------------------------
 // Sizes of the first-stage components (labels are particle indices).
 __global__ void k_label_sizes(int64_t n, const int32_t* __restrict__ label1, int* __restrict__ size) {
@@ -620,8 +792,25 @@ int link_outliers(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, co
              hipLaunchKernelGGL((k_link6d<HALF, PAPER>), g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, svx, \
                                 svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, \
                                 parent, xc, sl))
-    if ((1 << b) >= 3) {
-        if (sub) VR_LINK6D(true, true); else VR_LINK6D(true, false);
+    if ((1 << b) >= 4) {
+        // tiles of 64 participants per cell: at most ncell + np / 64 of them
+        const int64_t ncell = cl.n_cells;
+        const int64_t tmax = ncell + (np + 63) / 64;
+        VR_WS(tcnt, ctx, uint32_t, WS_D8, ncell + 1);
+        VR_WS(ttot, ctx, uint32_t, WS_D9, 4);
+        VR_WS(tiles, ctx, int2, WS_B7, tmax);
+        hipLaunchKernelGGL(k_tile_count, dim3(grid_for(ncell, 256)), dim3(256), 0, st, ncell, cl.cell_start, tcnt);
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = scan_u32(ctx, tcnt, tcnt, ncell, ttot, st))) return rc;
+        hipLaunchKernelGGL(k_tile_write, dim3(grid_for(ncell, 256)), dim3(256), 0, st, ncell, cl.cell_start, tcnt, tiles);
+        VR_LAUNCH_CHECK(ctx);
+#define VR_LINK6T(PAPER)                                                                                           \
+        VR_TIMED(ctx, sub ? "fof_link_sub" : "fof_link6d", st, np,                                               \
+                 hipLaunchKernelGGL((k_link6d_tile<PAPER>), dim3((unsigned)tmax), dim3(64), 0, st, tiles, ttot, cl.key, \
+                                    cl.sx, cl.sy, cl.sz, svx, svy, svz, shost, ellv_host, cl.cell_start, cl.hkeys,   \
+                                    cl.hvals, cl.hmask, b, gb, ell2, parent, xc, sl))
+        if (sub) VR_LINK6T(true); else VR_LINK6T(false);
+#undef VR_LINK6T
     } else {
         if (sub) VR_LINK6D(false, true); else VR_LINK6D(false, false);
     }

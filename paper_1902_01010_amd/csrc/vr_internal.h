@@ -45,6 +45,8 @@ struct vr_ctx {
     int unbind_jchunk = 4096;
     int unbind_bpc = 0;     // workgroups per CU of the persistent potential kernel (0 = occupancy limit)
     int xcd_chunk = 64;     // consecutive workgroups per XCD in the neighbour sweeps (0 = hardware order)
+    // while timing: candidate distances of the neighbour search (device counter)
+    unsigned long long* knn_cand = nullptr;
     // graph of the persistent unbinding passes, reused while its arguments match
     void* cap_stream = nullptr;
     void* ub_graph = nullptr;

@@ -109,7 +109,8 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                                             const float4* __restrict__ V, const double* __restrict__ FB,
                                             const int* __restrict__ elem_host, const int32_t* __restrict__ host_off,
                                             int n_se, int n_v, int use_mass, double mass_value, int gb,
-                                            float* __restrict__ R, unsigned xchunk) {
+                                            float* __restrict__ R, unsigned xchunk,
+                                            unsigned long long* __restrict__ ncand) {
     constexpr int NVL = NVR > 0 ? 1 : NVLMAX;
     __shared__ uint64_t heap[NSE][64];
     __shared__ double vd[NVL][64];
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
     int count = 0;
     uint64_t worst = ~0ull;
+    unsigned long long wcand = 0;  // wave-uniform
     // the kept keys: slot s of group s / 8; per group its largest key and
     // that key's slot; wg = the group holding the lane's largest key
     constexpr int LGS = 3;  // groups of 2^LGS slots
@@ -218,6 +220,8 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         const int s = nd.start, t_end = nd.end;
         for (int c0 = s; c0 < t_end; c0 += 64) {
             const int m = min(64, t_end - c0);
+            // candidate distances this chunk gives the wave's queries
+            wcand += (unsigned long long)m * (unsigned long long)__popcll(__ballot(mine));
             if (nowrap) {
                 // FP32 prefilter: coordinates are integers below 2^24, so the
                 // differences are exact and the rounded sum of squares is within
@@ -432,6 +436,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
         }
         pending = pending && !mine;
     }
+    if (ncand && lane == 0) atomicAdd(ncand, wcand);
     if (!active) return;
     // velocity neighbours among the spatial ones, by (dv2, index); velocities
     // and masses are indexed by element id = host base + rank
@@ -533,7 +538,8 @@ int launch_knn(vr_ctx* ctx, const uint32_t* qpos, int64_t nq, const KdTree& tree
                hipStream_t st) {
     VR_TIMED(ctx, "knn", st, nq,
              hipLaunchKernelGGL((k_knn<NSE, NVR, NVLMAX>), dim3(grid_for(nq, 64)), dim3(64), 0, st, qpos, nq, tree.nodes,
-                                tree.F, tree.seg_node, V, FB, tree.elem_host, host_off, n_se, n_v, tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk));
+                                tree.F, tree.seg_node, V, FB, tree.elem_host, host_off, n_se, n_v, tree.use_mass, p->mass_value, p->grid_bits, R, (unsigned)ctx->xcd_chunk,
+                                ctx->timing ? ctx->knn_cand : nullptr));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
