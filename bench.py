@@ -211,6 +211,63 @@ def bench_unbind(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_halo(args):
+    """Config 1, the isolated halo (an NFW host of 100k particles with five
+    Plummer subhalos of 1k-10k, 1 Mpc/h box): the oracle's "CPU seconds" per
+    stage, on one thread and on all of the host's cores for one GPU, next to
+    the GPU pipeline's stage times on the same input; the oracle's labels
+    and R are checked against the GPU's on the way."""
+    import torch
+    import oracle
+    import oracle.pipeline as opipe
+    from paper_1902_01010_amd import pipeline, synth, vr
+
+    w = synth.isolated_halo(seed=1)
+    prm = pipeline.Params.from_workload(w)
+    ctx = vr.Context(0)
+    knobs = ctx.autotune(TUNE_CACHE) if os.path.exists(TUNE_CACHE) else {k: ctx.get_tune(k) for k in vr.TUNE_KNOBS}
+    x, v, m = pipeline.device_inputs(w)
+    print(f"[bench] isolated halo: {w.n} particles", file=sys.stderr, flush=True)
+    for _ in range(max(1, args.warmup)):
+        pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm)
+    torch.cuda.synchronize()
+    gpu_ms, stages = [], {}
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        out, ev = pipeline.run(ctx, x, v, m, w.mass_value, w.box, w.grid_bits, prm, stage_events=True)
+        torch.cuda.synchronize()
+        gpu_ms.append((time.perf_counter() - t0) * 1e3)
+        for k, t in pipeline.stage_times(ev).items():
+            stages[k] = stages.get(k, 0.0) + t / args.steps
+    gpu = float(np.median(gpu_ms))
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1), os.cpu_count() or 1)
+    oracle.lib()
+    cpu = {}
+    for nt in (1, threads):
+        oracle.set_threads(nt)
+        tm = {}
+        t0 = time.perf_counter()
+        exp = opipe.run(w, prm, timings=tm)
+        cpu[nt] = {"total_s": time.perf_counter() - t0, "stages_s": tm}
+        print(f"[bench] oracle on {nt} thread(s): {cpu[nt]['total_s']:.1f} s", file=sys.stderr, flush=True)
+    same = bool((out["label"].cpu().numpy() == exp["label"]).all())
+    R, Re = out["R"].cpu().numpy(), exp["R"]
+    fin = np.isfinite(Re)
+    rerr = float(np.max(np.abs(R[fin] - Re[fin]) / np.maximum(1.0, np.abs(Re[fin])))) if fin.any() else 0.0
+    rec = {"metric": "CPU seconds of the oracle per stage (config 1), with the GPU pipeline beside it",
+           "path": "exact", "value": round(w.n / (gpu / 1e3), 1), "unit": "particles/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(gpu, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32 grid + f64 tests/moments + f32 potential tiles",
+           "data": "synthetic",
+           "config": {"workload": f"isolated NFW halo (c=10, 100k particles) + 5 Plummer subhalos of 1k-10k, "
+                                  f"1 Mpc/h box, {w.n} particles", "launch_knobs": knobs},
+           "gpu_stage_ms": {k: round(t, 4) for k, t in stages.items()},
+           "cpu_seconds": {"single_thread": cpu[1], "all_cores": cpu[threads], "cores": threads,
+                           "cpu_model": cpu_model()},
+           "checks": {"labels_equal": same, "max_R_rel_error": rerr}}
+    print(json.dumps(rec), flush=True)
+
+
 def unbind_cpu_baseline(w, off, mem, sizes):
     """The oracle on every 25th group of at most 20,000 members; the whole
     set's time is extrapolated through sum N^2 (stated as such)."""
@@ -259,8 +316,9 @@ def main():
                          "(not the headline path)")
     ap.add_argument("--n-se", type=int, default=0, help="spatial neighbours (0 = the workload's 32)")
     ap.add_argument("--n-v", type=int, default=0, help="velocity neighbours (0 = the workload's 8)")
-    ap.add_argument("--workload", choices=("box", "unbind"), default="box",
-                    help="box: the 256^3 hot path (default); unbind: batched unbinding of 50k groups")
+    ap.add_argument("--workload", choices=("box", "unbind", "halo"), default="box",
+                    help="box: the 256^3 hot path (default); unbind: batched unbinding of 50k groups; "
+                         "halo: the isolated halo of config 1 with the oracle's CPU seconds per stage")
     ap.add_argument("--unbind-groups", type=int, default=5_000,
                     help="groups of the unbinding workload (50000 = the full set: one call then takes minutes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -272,6 +330,8 @@ def main():
         sys.exit(2)
     if args.workload == "unbind":
         return bench_unbind(args)
+    if args.workload == "halo":
+        return bench_halo(args)
 
     import torch
     from paper_1902_01010_amd import pipeline, surrogate, synth, vr

@@ -24,6 +24,7 @@
 #include "vr_internal.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -96,7 +97,10 @@ __global__ void k_ub_zero(int na, const int* __restrict__ active, const int32_t*
 // most 64 terms (the caller adds it to an FP64 accumulator; 64 same-sign
 // FP32 terms stay within 64 * 2^-24 relative).  CHECK = the chunk may hold
 // j == i or, with eps = 0, a coincident pair; otherwise every term is
-// finite and taken.
+// finite and taken.  r^2 + eps^2 is at least min(eps^2, 1) in grid units
+// squared (coordinates are integers), a normal FP32 number (the host refuses
+// a smaller nonzero eps^2), so the hardware reciprocal square root needs no
+// rescaling for subnormal inputs and gives rsqrtf's result.
 template <bool UNIFORM, bool CHECK>
 __device__ __forceinline__ float tile_sum(const float4* __restrict__ sj, int t0, int t1, float xi, float yi, float zi,
                                           float eps2, int jbase, int i) {
@@ -107,8 +111,8 @@ __device__ __forceinline__ float tile_sum(const float4* __restrict__ sj, int t0,
         const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
         float rinv;
-        if (CHECK) rinv = (jbase + t != i && s2 > 0.f) ? rsqrtf(s2) : 0.f;
-        else rinv = rsqrtf(s2);
+        if (CHECK) rinv = (jbase + t != i && s2 > 0.f) ? __builtin_amdgcn_rsqf(s2) : 0.f;
+        else rinv = __builtin_amdgcn_rsqf(s2);
         accf = UNIFORM ? accf + rinv : fmaf(q.w, rinv, accf);
     }
     return accf;
@@ -742,6 +746,9 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     const double epsg = up->eps / unit;
     const double eps2g = epsg * epsg;
     const float eps2f = (float)eps2g;
+    if (eps2f > 0.f && eps2f < FLT_MIN)
+        return set_err(ctx, VR_ERR_UNSUPPORTED, "softening eps = %g is below the FP32 normal range in grid units",
+                       up->eps);
     const double scale = -up->G / unit;  // potential = scale * mass * sum(1/r) in grid units
     int tile = up->tile ? up->tile : (ctx->tuned_tile ? ctx->tuned_tile : 256);
     if (up->persistent)
