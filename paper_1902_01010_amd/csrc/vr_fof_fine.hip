@@ -132,9 +132,17 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
             uint32_t fb0 = fid[lo];
             const uint32_t fb1 = fid[hi - 1];
             if (rr == 0 && px0[pc] == cx && fb0 <= (uint32_t)A) fb0 = (uint32_t)A + 1;  // own coarse cell: later cells
-            for (uint32_t B = fb0; B <= fb1 && fb0 <= fb1; ++B) {
-                const uint32_t b0 = fine_start[B], b1 = fine_start[B + 1];
+            if (fb0 > fb1) continue;
+            // B's first member, key and parent, and the next cell's start are
+            // all loaded at the top of an iteration, with no load waiting for
+            // another: one memory round trip per candidate cell that the
+            // exact box bound or the parent test settles
+            uint32_t next_b0 = fine_start[fb0];
+            for (uint32_t B = fb0; B <= fb1; ++B) {
+                const uint32_t b0 = next_b0, b1 = fine_start[B + 1];
+                next_b0 = b1;
                 const uint64_t kb = key[b0];
+                const int pb = parent[b0];
                 const uint64_t ckb = kb >> lr3;
                 const uint32_t subb = (uint32_t)(kb & ((1ull << lr3) - 1));
                 const int gbx = (int)(ckb & ncm) * G.r + (int)(subb & rm);
@@ -148,7 +156,9 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
                               lz = gz ? (gz - 1) * f + 1 : 0;
                 const double dmin = (double)(lx * lx + ly * ly + lz * lz);
                 if (dmin >= ell2) continue;
-                const int rb = uf_find(parent, (int)b0);
+                // b0's parent is A's (possibly stale) root: one component
+                if (pb == ra) continue;
+                const int rb = uf_find(parent, pb);
                 if (rb == ra) continue;
                 ra = uf_find(parent, ra);
                 if (ra == rb) continue;
