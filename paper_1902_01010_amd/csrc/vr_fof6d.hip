@@ -305,7 +305,10 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
                                                     const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                                     uint32_t hmask, int b, int gb, double ell2, int* parent,
                                                     unsigned xchunk, SubLink sub) {
-    __shared__ int cxs[64], cys[64], czs[64], chs[64], crt[64], cq[64];
+    __shared__ __align__(16) int cxs[64];
+    __shared__ __align__(16) int cys[64];
+    __shared__ __align__(16) int czs[64];
+    __shared__ int chs[64], crt[64], cq[64];
     __shared__ float cvx[64], cvy[64], cvz[64];
     __shared__ double cu0[PAPER ? 64 : 1], cu1[PAPER ? 64 : 1], cu2[PAPER ? 64 : 1], cs_[PAPER ? 64 : 1];
     const uint32_t t = xcd_swizzle(blockIdx.x, gridDim.x, xchunk);
@@ -370,6 +373,11 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
     // no candidate with an FP32 square sum above this lies within ell
     const float ellf = (float)(ell2 * (1.0 + 1e-6)) + 1.0f;
     int rp = valid ? uf_find(parent, (int)p) : -1;
+    // Near the box faces a forward neighbour can sit across the periodic
+    // boundary; elsewhere the plain coordinate differences are the minimum
+    // images (cells span far less than half the box).
+    const int ncm = nc - 1;
+    const bool wrap = cx == 0 || cx == ncm || cy == 0 || cy == ncm || cz == ncm;
     for (uint32_t c0 = 0; c0 < total; c0 += 64) {
         const uint32_t c = c0 + (uint32_t)lane;
         // the segment holding candidate c: the last lane o < 14 whose first
@@ -403,15 +411,44 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
         __builtin_amdgcn_wave_barrier();
         const int m = (int)min(64u, total - c0);
         if (!valid) continue;
-        for (int j = 0; j < m; ++j) {
+        // pass 1, no divergence: a bit per staged candidate whose FP32
+        // squared distance may lie within ell (differences are exact
+        // integers below 2^22; the rounded sum is within 2e-7 of the exact
+        // one, which ellf covers); pass 2 takes the marked ones exactly
+        uint32_t tk[2] = {0u, 0u};
+#pragma unroll
+        for (int b4 = 0; b4 < 16; ++b4) {
+            if (4 * b4 < m) {
+                const int4 X = *reinterpret_cast<const int4*>(&cxs[4 * b4]);
+                const int4 Y = *reinterpret_cast<const int4*>(&cys[4 * b4]);
+                const int4 Z = *reinterpret_cast<const int4*>(&czs[4 * b4]);
+                const int xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int dx = xs[u] - px, dy = ys[u] - py, dz = zs[u] - pz;
+                    if (wrap) {
+                        dx = min_image(dx, gb);
+                        dy = min_image(dy, gb);
+                        dz = min_image(dz, gb);
+                    }
+                    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+                    const int bit = 4 * b4 + u;
+                    if (fmaf(fx, fx, fmaf(fy, fy, fz * fz)) <= ellf) tk[bit >> 5] |= 1u << (bit & 31);
+                }
+            }
+        }
+        uint64_t take = ((uint64_t)tk[1] << 32) | tk[0];
+        if (m < 64) take &= (uint64_t(1) << m) - 1;
+        while (take) {
+            const int j = __builtin_ctzll(take);
+            take &= take - 1;
             const int qq = cq[j];
             // own cell: only the candidates after p
             if (c0 + (uint32_t)j >= own_b && (uint32_t)qq <= p) continue;
+            if (chs[j] != hp) continue;
             const int ddx = min_image(cxs[j] - px, gb);
             const int ddy = min_image(cys[j] - py, gb);
             const int ddz = min_image(czs[j] - pz, gb);
-            const float fx = (float)ddx, fy = (float)ddy, fz = (float)ddz;
-            if (fmaf(fx, fx, fmaf(fy, fy, fz * fz)) > ellf || chs[j] != hp) continue;
             const double d2 = (double)ddx * ddx + (double)ddy * ddy + (double)ddz * ddz;
             if (d2 >= ell2) continue;
             bool link;
