@@ -280,9 +280,20 @@ __global__ __launch_bounds__(256) void k_link6d(int64_t np, const ckey_t* __rest
 // joined and no further global access is needed.
 
 // tiles of 64 participants per cell
+// Tiles of cells with at least HEAVY_CELL participants (subhalo cores, whose
+// tiles carry thousands of candidates each) come first in the list, so they
+// start with the launch instead of finishing after it: cnt[c] counts a heavy
+// cell's tiles, cnt[ncell + c] a light one's, and one scan over both halves
+// gives every cell its first tile.
+constexpr uint32_t HEAVY_CELL = 64;
+
 __global__ void k_tile_count(int64_t ncell, const uint32_t* __restrict__ cell_start, uint32_t* __restrict__ cnt) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncell) cnt[c] = (cell_start[c + 1] - cell_start[c] + 63) >> 6;
+    if (c >= ncell) return;
+    const uint32_t m = cell_start[c + 1] - cell_start[c];
+    const uint32_t nt = (m + 63) >> 6;
+    cnt[c] = m >= HEAVY_CELL ? nt : 0;
+    cnt[ncell + c] = m >= HEAVY_CELL ? 0 : nt;
 }
 
 __global__ void k_tile_write(int64_t ncell, const uint32_t* __restrict__ cell_start, const uint32_t* __restrict__ toff,
@@ -290,7 +301,7 @@ __global__ void k_tile_write(int64_t ncell, const uint32_t* __restrict__ cell_st
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const uint32_t s = cell_start[c], e = cell_start[c + 1];
-    uint32_t t = toff[c];
+    uint32_t t = e - s >= HEAVY_CELL ? toff[c] : toff[ncell + c];
     for (uint32_t q = s; q < e; q += 64) tiles[t++] = make_int2((int)c, (int)q);
 }
 
@@ -833,12 +844,12 @@ int link_outliers(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, co
         // tiles of 64 participants per cell: at most ncell + np / 64 of them
         const int64_t ncell = cl.n_cells;
         const int64_t tmax = ncell + (np + 63) / 64;
-        VR_WS(tcnt, ctx, uint32_t, WS_D8, ncell + 1);
+        VR_WS(tcnt, ctx, uint32_t, WS_D8, 2 * ncell + 1);
         VR_WS(ttot, ctx, uint32_t, WS_D9, 4);
         VR_WS(tiles, ctx, int2, WS_B7, tmax);
         hipLaunchKernelGGL(k_tile_count, dim3(grid_for(ncell, 256)), dim3(256), 0, st, ncell, cl.cell_start, tcnt);
         VR_LAUNCH_CHECK(ctx);
-        if ((rc = scan_u32(ctx, tcnt, tcnt, ncell, ttot, st))) return rc;
+        if ((rc = scan_u32(ctx, tcnt, tcnt, 2 * ncell, ttot, st))) return rc;
         hipLaunchKernelGGL(k_tile_write, dim3(grid_for(ncell, 256)), dim3(256), 0, st, ncell, cl.cell_start, tcnt, tiles);
         VR_LAUNCH_CHECK(ctx);
 #define VR_LINK6T(PAPER)                                                                                           \
