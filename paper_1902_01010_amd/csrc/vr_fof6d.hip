@@ -319,7 +319,8 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
     __shared__ __align__(16) int cxs[64];
     __shared__ __align__(16) int cys[64];
     __shared__ __align__(16) int czs[64];
-    __shared__ int chs[64], crt[64], cq[64];
+    __shared__ __align__(16) int crt[64];
+    __shared__ int chs[64], cq[64];
     __shared__ float cvx[64], cvy[64], cvz[64];
     __shared__ double cu0[PAPER ? 64 : 1], cu1[PAPER ? 64 : 1], cu2[PAPER ? 64 : 1], cs_[PAPER ? 64 : 1];
     const uint32_t t = xcd_swizzle(blockIdx.x, gridDim.x, xchunk);
@@ -411,7 +412,10 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
             cvx[lane] = svx[q];
             cvy[lane] = svy[q];
             cvz[lane] = svz[q];
-            crt[lane] = parent[q];  // an ancestor of q (no path-halving writes)
+            // q's root as of staging (one find per candidate and chunk, all
+            // lanes at once): once a core has merged, a linked pair then
+            // matches the participant's root without a find of its own
+            crt[lane] = uf_find(parent, (int)q);
             if constexpr (PAPER) {
                 cu0[lane] = sub.u0[q];
                 cu1[lane] = sub.u1[q];
@@ -422,10 +426,13 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
         __builtin_amdgcn_wave_barrier();
         const int m = (int)min(64u, total - c0);
         if (!valid) continue;
+        rp = uf_find(parent, rp);  // as fresh as the staged roots
         // pass 1, no divergence: a bit per staged candidate whose FP32
         // squared distance may lie within ell (differences are exact
         // integers below 2^22; the rounded sum is within 2e-7 of the exact
-        // one, which ellf covers); pass 2 takes the marked ones exactly
+        // one, which ellf covers) and whose staged root is not the lane's
+        // (a link inside one component changes nothing); pass 2 takes the
+        // marked ones exactly
         uint32_t tk[2] = {0u, 0u};
 #pragma unroll
         for (int b4 = 0; b4 < 16; ++b4) {
@@ -433,7 +440,9 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
                 const int4 X = *reinterpret_cast<const int4*>(&cxs[4 * b4]);
                 const int4 Y = *reinterpret_cast<const int4*>(&cys[4 * b4]);
                 const int4 Z = *reinterpret_cast<const int4*>(&czs[4 * b4]);
+                const int4 RT = *reinterpret_cast<const int4*>(&crt[4 * b4]);
                 const int xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
+                const int rts[4] = {RT.x, RT.y, RT.z, RT.w};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     int dx = xs[u] - px, dy = ys[u] - py, dz = zs[u] - pz;
@@ -444,7 +453,7 @@ __global__ __launch_bounds__(64) void k_link6d_tile(const int2* __restrict__ til
                     }
                     const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
                     const int bit = 4 * b4 + u;
-                    if (fmaf(fx, fx, fmaf(fy, fy, fz * fz)) <= ellf) tk[bit >> 5] |= 1u << (bit & 31);
+                    if (fmaf(fx, fx, fmaf(fy, fy, fz * fz)) <= ellf && rts[u] != rp) tk[bit >> 5] |= 1u << (bit & 31);
                 }
             }
         }
