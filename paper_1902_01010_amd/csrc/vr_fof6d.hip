@@ -572,18 +572,6 @@ __device__ __forceinline__ void for_relaxed(int64_t p, const ckey_t* __restrict_
 
 // Synchronous growth rounds: an untagged participant takes the smallest tag
 // among its relaxed neighbours tagged in the previous round.
-// Appends val for each taking lane: one atomic per wavefront.  Every lane of
-// the wavefront must call it.
-__device__ __forceinline__ void wave_append(int* counter, int32_t* list, bool take, int32_t val) {
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    const int lane = (int)lane_id();
-    const int first = __builtin_ctzll(m);
-    int base = 0;
-    if (lane == first) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, first, 64);
-    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
-}
 
 // The rounds are pushed from the frontier (the particles tagged in the
 // previous round).  An untagged participant can only border particles

@@ -88,14 +88,25 @@ __global__ void k_rows(int64_t nrows, int64_t n, const uint64_t* __restrict__ ke
     row_start[r] = r == nrows ? (uint32_t)n : lower_bound_u64(key, 0, (uint32_t)n, (uint64_t)r << shift);
 }
 
+// Coarse cells with at least DENSE_CC occupied fine cells (halo cores, where
+// one thread would walk up to 14 x 64 candidate cells one memory round trip
+// at a time) are linked by k_link_tile3 instead, a wavefront each.
+constexpr uint32_t DENSE_CC = 16;
+constexpr int TILE_R = 4;  // fine cells per coarse side where the tiles apply (r^3 <= 64 lanes)
+
 __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t* __restrict__ fine_start,
                                                    const uint32_t* __restrict__ fid, const uint64_t* __restrict__ key,
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                    const uint32_t* __restrict__ sz,
                                                    const uint32_t* __restrict__ row_start, FineGrid G, double ell2,
-                                                   int* parent, unsigned xchunk) {
+                                                   int* parent, unsigned xchunk, const uint32_t* __restrict__ cid,
+                                                   const uint32_t* __restrict__ cfs) {
     const int64_t A = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (A >= nfine) return;
+    if (cid) {
+        const uint32_t c = cid[A];
+        if (cfs[c + 1] - cfs[c] >= DENSE_CC) return;  // linked by k_link_tile3
+    }
     const uint32_t a0 = fine_start[A], a1 = fine_start[A + 1];
     const uint64_t ka = key[a0];
     const int lr3 = 3 * G.lr;
@@ -177,6 +188,212 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
                 }
                 if (hit) uf_union(parent, ra, rb);
             }
+        }
+    }
+}
+
+// coarse-cell starts among the fine cells: flag[F] = 1 where F opens a coarse cell
+__global__ void k_coarse_flags(int64_t nfine, const uint32_t* __restrict__ fine_start,
+                               const uint64_t* __restrict__ key, int lr3, uint32_t* __restrict__ flag) {
+    const int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (F >= nfine) return;
+    flag[F] = (F == 0 || (key[fine_start[F]] >> lr3) != (key[fine_start[F - 1]] >> lr3)) ? 1u : 0u;
+}
+
+// after an exclusive scan of the flags in place: cid[F] = coarse index of F,
+// cfs[c] = first fine cell of coarse cell c, cfs[ncoarse] = nfine
+__global__ void k_coarse_starts(int64_t nfine, const uint32_t* __restrict__ fine_start,
+                                const uint64_t* __restrict__ key, int lr3, uint32_t* __restrict__ cid,
+                                uint32_t* __restrict__ cfs) {
+    const int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (F >= nfine) return;
+    const bool start = F == 0 || (key[fine_start[F]] >> lr3) != (key[fine_start[F - 1]] >> lr3);
+    const uint32_t c = start ? cid[F] : cid[F] - 1;
+    cid[F] = c;
+    if (start) cfs[c] = (uint32_t)F;
+    if (F == nfine - 1) cfs[c + 1] = (uint32_t)nfine;
+}
+
+__global__ void k_dense_cc(int64_t ncoarse, const uint32_t* __restrict__ cfs, int* __restrict__ count,
+                           int32_t* __restrict__ list) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool take = c < ncoarse && cfs[c + 1] - cfs[c] >= DENSE_CC;
+    wave_append(count, list, take, (int32_t)c);
+}
+
+// The root of a without path-halving stores: the staging of a tile walks the
+// roots of all its candidates, which many tiles share, and stores there
+// would make every tile write the same lines.
+__device__ __forceinline__ int uf_root(const int* parent, int a) {
+    int p = parent[a];
+    while (p != a) {
+        a = p;
+        p = parent[a];
+    }
+    return a;
+}
+
+// One wavefront per dense coarse cell, a lane per fine cell A of it.  The
+// candidate fine cells -- the coarse cell's own (numbered first; only those
+// after A count), then those of its 13 forward neighbours -- are staged in
+// LDS 64 at a time with their fine-grid coordinates, first member and
+// union-find root as of staging.  A pass with no divergence marks, per lane,
+// the candidates whose box lower bound may lie within ellx (the bound without
+// its +1 terms, in small integers) and whose root is not the lane's; only the
+// marked ones take the exact bound, the root refresh, the particle tests and
+// the union.  Once a core has merged, its pairs are left out by the mask.
+// It runs twice: first (certain = 1) only for pairs whose boxes lie wholly
+// within ellx, which merges the cores without a particle test; then, after
+// every such link of every tile, for the other pairs, whose particle tests
+// are then needed only where the cores did not already join them.
+__global__ __launch_bounds__(64) void k_link_tile3(const int32_t* __restrict__ dense, const uint32_t* __restrict__ cfs,
+                                                   const uint32_t* __restrict__ fine_start,
+                                                   const uint32_t* __restrict__ fid, const uint64_t* __restrict__ key,
+                                                   const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
+                                                   const uint32_t* __restrict__ sz,
+                                                   const uint32_t* __restrict__ row_start, FineGrid G, double ell2,
+                                                   float tq, int* parent, unsigned xchunk, int certain) {
+    __shared__ __align__(16) int cgx[64];
+    __shared__ __align__(16) int cgy[64];
+    __shared__ __align__(16) int cgz[64];
+    __shared__ __align__(16) int crt[64];
+    __shared__ uint32_t cb0[64], cb1[64], cF[64];
+    const int lane = (int)threadIdx.x;
+    const uint32_t c = (uint32_t)dense[xcd_swizzle(blockIdx.x, gridDim.x, xchunk)];
+    const uint32_t fA0 = cfs[c], nA = cfs[c + 1] - fA0;  // DENSE_CC .. 64
+    const bool valid = (uint32_t)lane < nA;
+    const uint32_t A = fA0 + (valid ? (uint32_t)lane : 0u);
+    const int lr3 = 3 * G.lr;
+    const int rm = G.r - 1, ncm = G.nc - 1;
+    const int fbits = G.gb - G.k;  // fine cells per side = 2^fbits
+    const int64_t f = int64_t(1) << G.k;
+    const uint32_t a0 = fine_start[A], a1 = fine_start[A + 1];
+    const uint64_t ka = key[a0];
+    const uint64_t cka = ka >> lr3;
+    const int cx = (int)(cka & ncm), cy = (int)((cka >> G.b) & ncm), cz = (int)(cka >> (2 * G.b));
+    const uint32_t suba = (uint32_t)(ka & ((1ull << lr3) - 1));
+    const int gax = cx * G.r + (int)(suba & rm);
+    const int gay = cy * G.r + (int)((suba >> G.lr) & rm);
+    const int gaz = cz * G.r + (int)(suba >> (2 * G.lr));
+    // lane q < 14: segment q's fine cells -- the own coarse cell, then the
+    // forward neighbours (+1, 0, 0), (-1..1, +1, 0), (-1..1, -1..1, +1)
+    uint32_t seg_s = 0, seg_n = 0;
+    if (lane == 0) {
+        seg_s = fA0;
+        seg_n = nA;
+    } else if (lane < 14) {
+        int dx, dy, dz;
+        if (lane == 1) { dx = 1; dy = 0; dz = 0; }
+        else if (lane < 5) { dx = lane - 3; dy = 1; dz = 0; }
+        else { dx = (lane - 5) % 3 - 1; dy = (lane - 5) / 3 - 1; dz = 1; }
+        const uint32_t row = (uint32_t)((cz + dz) & ncm) * (uint32_t)G.nc + (uint32_t)((cy + dy) & ncm);
+        const uint64_t cell = (uint64_t)row * (uint64_t)G.nc + (uint64_t)((cx + dx) & ncm);
+        const uint32_t rs = row_start[row], re = row_start[row + 1];
+        const uint32_t lo = lower_bound_u64(key, rs, re, cell << lr3);
+        const uint32_t hi = lower_bound_u64(key, lo, re, (cell + 1) << lr3);
+        if (lo < hi) {
+            seg_s = fid[lo];
+            seg_n = fid[hi - 1] - seg_s + 1;
+        }
+    }
+    uint32_t incl = seg_n;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t total = __shfl(incl, 13, 64);
+    const uint32_t seg_b = incl - seg_n;
+    // near the box faces a forward neighbour can lie across the periodic
+    // boundary; elsewhere plain fine-cell differences are the minimum images
+    const bool wrap = cx == 0 || cx == ncm || cy == 0 || cy == ncm || cz == ncm;
+    int ra = valid ? uf_find(parent, (int)a0) : -1;
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+        const uint32_t cc = c0 + (uint32_t)lane;
+        int sg = 0;
+#pragma unroll
+        for (int o = 1; o < 14; ++o) {
+            const uint32_t bo = __shfl(seg_b, o, 64);
+            if (bo <= cc) sg = o;
+        }
+        const uint32_t F = __shfl(seg_s, sg, 64) + (cc - __shfl(seg_b, sg, 64));
+        __builtin_amdgcn_wave_barrier();
+        if (cc < total) {
+            const uint32_t b0 = fine_start[F], b1 = fine_start[F + 1];
+            const uint64_t kb = key[b0];
+            const uint64_t ckb = kb >> lr3;
+            const uint32_t subb = (uint32_t)(kb & ((1ull << lr3) - 1));
+            cgx[lane] = (int)(ckb & ncm) * G.r + (int)(subb & rm);
+            cgy[lane] = (int)((ckb >> G.b) & ncm) * G.r + (int)((subb >> G.lr) & rm);
+            cgz[lane] = (int)(ckb >> (2 * G.b)) * G.r + (int)(subb >> (2 * G.lr));
+            cb0[lane] = b0;
+            cb1[lane] = b1;
+            cF[lane] = F;
+            crt[lane] = uf_root(parent, (int)b0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int m = (int)min(64u, total - c0);
+        if (!valid) continue;
+        ra = uf_root(parent, ra);
+        uint32_t tk[2] = {0u, 0u};
+#pragma unroll
+        for (int b4 = 0; b4 < 16; ++b4) {
+            if (4 * b4 < m) {
+                const int4 X = *reinterpret_cast<const int4*>(&cgx[4 * b4]);
+                const int4 Y = *reinterpret_cast<const int4*>(&cgy[4 * b4]);
+                const int4 Z = *reinterpret_cast<const int4*>(&cgz[4 * b4]);
+                const int4 RT = *reinterpret_cast<const int4*>(&crt[4 * b4]);
+                const int xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w}, zs[4] = {Z.x, Z.y, Z.z, Z.w};
+                const int rts[4] = {RT.x, RT.y, RT.z, RT.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int dx = xs[u] - gax, dy = ys[u] - gay, dz = zs[u] - gaz;
+                    if (wrap) {
+                        dx = min_image(dx, fbits);
+                        dy = min_image(dy, fbits);
+                        dz = min_image(dz, fbits);
+                    }
+                    // candidates sit in adjacent coarse cells: |d| < 2 r
+                    const int ex = max(abs(dx) - 1, 0), ey = max(abs(dy) - 1, 0), ez = max(abs(dz) - 1, 0);
+                    const int bit = 4 * b4 + u;
+                    if ((float)(ex * ex + ey * ey + ez * ez) < tq && rts[u] != ra) tk[bit >> 5] |= 1u << (bit & 31);
+                }
+            }
+        }
+        uint64_t take = ((uint64_t)tk[1] << 32) | tk[0];
+        if (m < 64) take &= (uint64_t(1) << m) - 1;
+        while (take) {
+            const int j = __builtin_ctzll(take);
+            take &= take - 1;
+            if (c0 + (uint32_t)j < nA && cF[j] <= A) continue;  // own coarse cell: later cells only
+            const int64_t gx = abs(min_image(cgx[j] - gax, fbits));
+            const int64_t gy = abs(min_image(cgy[j] - gay, fbits));
+            const int64_t gz = abs(min_image(cgz[j] - gaz, fbits));
+            const int64_t lx = gx ? (gx - 1) * f + 1 : 0, ly = gy ? (gy - 1) * f + 1 : 0,
+                          lz = gz ? (gz - 1) * f + 1 : 0;
+            if ((double)(lx * lx + ly * ly + lz * lz) >= ell2) continue;
+            const int64_t ux = (gx + 1) * f - 1, uy = (gy + 1) * f - 1, uz = (gz + 1) * f - 1;
+            const bool inside = (double)(ux * ux + uy * uy + uz * uz) < ell2;
+            if (inside != (certain != 0)) continue;
+            int rb = crt[j];
+            if (rb == ra) continue;
+            rb = uf_find(parent, rb);
+            if (rb == ra) continue;
+            ra = uf_find(parent, ra);
+            if (ra == rb) continue;
+            bool hit = inside;
+            const uint32_t q0 = cb0[j], q1 = cb1[j];
+            for (uint32_t pp = a0; pp < a1 && !hit; ++pp) {
+                const int px = (int)sx[pp], py = (int)sy[pp], pz = (int)sz[pp];
+                for (uint32_t q = q0; q < q1; ++q) {
+                    const int dx = min_image((int)sx[q] - px, G.gb);
+                    const int dy = min_image((int)sy[q] - py, G.gb);
+                    const int dz = min_image((int)sz[q] - pz, G.gb);
+                    const double d2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
+                    if (d2 < ell2) { hit = true; break; }
+                }
+            }
+            if (hit) uf_union(parent, ra, rb);
         }
     }
 }
@@ -263,10 +480,53 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     hipLaunchKernelGGL(k_rows, dim3(grid_for(nrows + 1, 256)), dim3(256), 0, st, nrows, n, key, G.b + 3 * G.lr,
                        row_start);
     VR_LAUNCH_CHECK(ctx);
+    // dense coarse cells (fine grids of 4 a side): coarse index per fine
+    // cell, first fine cell per coarse cell, and the list of dense ones
+    const uint32_t* cid = nullptr;
+    const uint32_t* cfs = nullptr;
+    int32_t* dense = nullptr;
+    int ndense = 0;
+    if (G.r == TILE_R) {
+        uint32_t* cid_w = scan;  // the fine-start flags are no longer needed
+        VR_WS(cfs_w, ctx, uint32_t, WS_B2, (int64_t)nfine + 1);
+        VR_WS(dense_w, ctx, int32_t, WS_B3, (int64_t)nfine + 1);
+        VR_WS(cnt, ctx, int, WS_FLAG2, 4);
+        const unsigned gf = grid_for(nfine, 256);
+        hipLaunchKernelGGL(k_coarse_flags, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid_w);
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = scan_u32(ctx, cid_w, cid_w, nfine, tot, st))) return rc;
+        uint32_t ncoarse = 0;
+        if ((rc = read_back(ctx, tot, &ncoarse, sizeof ncoarse, st))) return rc;
+        hipLaunchKernelGGL(k_coarse_starts, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid_w,
+                           cfs_w);
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = fill_i32(ctx, cnt, 0, 1, st))) return rc;
+        hipLaunchKernelGGL(k_dense_cc, dim3(grid_for(ncoarse, 256)), dim3(256), 0, st, (int64_t)ncoarse, cfs_w, cnt,
+                           dense_w);
+        VR_LAUNCH_CHECK(ctx);
+        if ((rc = read_back(ctx, cnt, &ndense, sizeof ndense, st))) return rc;
+        if (ndense > 0) {
+            cid = cid_w;
+            cfs = cfs_w;
+            dense = dense_w;
+        }
+    }
+    // the tile mask keeps B where (f e)^2 summed < ell2 with e = |g| - 1:
+    // e2 < ell2 / f^2, compared in FP32 against a threshold rounded up
+    const double fk = std::ldexp(1.0, k);
+    const float tq = (float)(ell2 / (fk * fk) * (1.0 + 1e-6)) + 1e-6f;
+#define VR_TILE3(CERTAIN)                                                                                        \
+    VR_TIMED(ctx, "fof_link3d", st, 0,                                                                           \
+             hipLaunchKernelGGL(k_link_tile3, dim3((unsigned)ndense), dim3(64), 0, st, dense, cfs, fine_start, fid, \
+                                key, sx, sy, sz, row_start, G, ell2, tq, parent, (unsigned)ctx->xcd_chunk, CERTAIN)); \
+    VR_LAUNCH_CHECK(ctx)
+    if (ndense > 0) { VR_TILE3(1); }
     VR_TIMED(ctx, "fof_link3d", st, n,
              hipLaunchKernelGGL(k_link_fine, dim3(grid_for(nfine, 256)), dim3(256), 0, st, (int64_t)nfine, fine_start,
-                                fid, key, sx, sy, sz, row_start, G, ell2, parent, (unsigned)ctx->xcd_chunk));
+                                fid, key, sx, sy, sz, row_start, G, ell2, parent, (unsigned)ctx->xcd_chunk, cid, cfs));
     VR_LAUNCH_CHECK(ctx);
+    if (ndense > 0) { VR_TILE3(0); }
+#undef VR_TILE3
     hipLaunchKernelGGL(k_compress_f, dim3(gn), dim3(256), 0, st, n, parent);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_root_idx_f, dim3(gn), dim3(256), 0, st, n, parent, idx, mn);

@@ -22,6 +22,19 @@ __device__ __forceinline__ uint32_t hash_key(ckey_t k, uint32_t mask) {
     return (uint32_t)k & mask;
 }
 
+// Appends val for each taking lane: one atomic per wavefront.  Every lane of
+// the wavefront must call it.
+__device__ __forceinline__ void wave_append(int* counter, int32_t* list, bool take, int32_t val) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lane = (int)lane_id();
+    const int first = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == first) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, first, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
 __device__ __forceinline__ int hash_find(const ckey_t* __restrict__ hkeys, const uint32_t* __restrict__ hvals,
                                          uint32_t hmask, ckey_t k) {
     uint32_t h = hash_key(k, hmask);
