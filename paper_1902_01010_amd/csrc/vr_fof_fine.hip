@@ -91,7 +91,7 @@ __global__ void k_rows(int64_t nrows, int64_t n, const uint64_t* __restrict__ ke
 // Coarse cells with at least DENSE_CC occupied fine cells (halo cores, where
 // one thread would walk up to 14 x 64 candidate cells one memory round trip
 // at a time) are linked by k_link_tile3 instead, a wavefront each.
-constexpr uint32_t DENSE_CC = 16;
+constexpr uint32_t DENSE_CC = 48;
 constexpr int TILE_R = 4;  // fine cells per coarse side where the tiles apply (r^3 <= 64 lanes)
 
 __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t* __restrict__ fine_start,
