@@ -297,14 +297,17 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
             }
         }
     };
-    // whether some lane's ball (radius = its current worst) reaches the box
+    // Box distances in FP32: the per-axis gaps are exact integers below
+    // 2^23 and the rounded sum is within 2^-22 of the exact one, so a bound
+    // raised by 2^-20 visits every node the exact test would.
     auto needed = [&](const KdNode& nd, bool mine) __attribute__((always_inline)) {
-        const int64_t dx = max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
-        const int64_t dy = max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
-        const int64_t dz = max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
-        int64_t md2 = dx * dx + dy * dy + dz * dz;
-        if (md2 > (int64_t(1) << 41)) md2 = int64_t(1) << 41;
-        return __ballot(mine && (count < n_se ? (uint64_t)md2 <= tau : ((uint64_t)md2 << POS_BITS) <= worst)) != 0;
+        const float dx = (float)max(max(nd.bmin[0] - px, px - nd.bmax[0]), 0);
+        const float dy = (float)max(max(nd.bmin[1] - py, py - nd.bmax[1]), 0);
+        const float dz = (float)max(max(nd.bmin[2] - pz, pz - nd.bmax[2]), 0);
+        const float md2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float bnd = count < n_se ? (tau == NO_BOUND ? INFINITY : (float)tau * (1.0f + 0x1p-20f) + 1.0f)
+                                       : (float)(worst >> POS_BITS) * (1.0f + 0x1p-20f) + 1.0f;
+        return __ballot(mine && md2 <= bnd) != 0;
     };
 
     bool pending = active;
