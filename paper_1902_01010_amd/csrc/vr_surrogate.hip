@@ -207,54 +207,67 @@ struct FeatNorm {
     float shift[NF], scale[NF];
 };
 
-__global__ __launch_bounds__(256) void k_rs_features(int64_t m, const int32_t* __restrict__ mem,
-                                                     const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
-                                                     const uint32_t* __restrict__ qz, const float* __restrict__ vx,
-                                                     const float* __restrict__ vy, const float* __restrict__ vz,
-                                                     const float* __restrict__ vbar, const float* __restrict__ sigma,
-                                                     const float* __restrict__ rho, int64_t n, Level fine,
-                                                     Level coarse, const double* __restrict__ vsum, int n_se,
-                                                     double cell_len, FeatNorm nrm, const uint32_t* __restrict__ order,
-                                                     uint16_t* __restrict__ feat) {
-    // rows are taken in fine-cell order, so neighbouring threads probe the
-    // same cells and the window lookups stay in cache
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m) return;
-    const int64_t i = order[t];
-    const int g = mem[i];
-    const uint32_t px = qx[g], py = qy[g], pz = qz[g];
-    // 0: radius holding n_se neighbours at the window count density
-    const uint32_t nf = window_count(fine, px >> fine.cbits, py >> fine.cbits, pz >> fine.cbits);
+// What a row's features take from its fine cell alone, once per occupied
+// fine cell (rows of a cell share it): feature 0, the log radius holding
+// n_se neighbours at the density of the 27-cell window (the coarse window
+// where the fine one holds fewer than n_se), and the mean velocity of the
+// cell and its six face neighbours.  cf[4 c .. 4 c + 3] = (f0, vloc).
+__global__ __launch_bounds__(256) void k_rs_cellfeat(uint32_t ncells, const uint64_t* __restrict__ keys,
+                                                     Level fine, Level coarse, const double* __restrict__ vsum,
+                                                     int n_se, double cell_len, double* __restrict__ cf) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const uint64_t key = keys[fine.start[c]];
+    const uint32_t mask = (1u << fine.b) - 1u;
+    const uint32_t cx = (uint32_t)(key & mask), cy = (uint32_t)((key >> fine.b) & mask),
+                   cz = (uint32_t)(key >> (2 * fine.b));
+    const uint32_t nf = window_count(fine, cx, cy, cz);
     double nhat;
     if ((int)nf >= n_se) {
         nhat = (double)nf / (27.0 * cell_len * cell_len * cell_len);
     } else {
-        const uint32_t nc = window_count(coarse, px >> coarse.cbits, py >> coarse.cbits, pz >> coarse.cbits);
+        // the coarse grid's cells are 4 fine cells a side
+        const uint32_t nc = window_count(coarse, cx >> 2, cy >> 2, cz >> 2);
         const double L4 = 4.0 * cell_len;
         nhat = (double)nc / (27.0 * L4 * L4 * L4);
     }
-    double f[NF];
-    f[0] = log(cbrt(3.0 * (double)n_se / (4.0 * M_PI * nhat)));
-    // mean velocity of the own fine cell and its six face neighbours
-    {
-        const uint32_t mask = (1u << fine.b) - 1u;
-        const uint32_t cx = px >> fine.cbits, cy = py >> fine.cbits, cz = pz >> fine.cbits;
-        const int fo[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
-        double s0 = 0, s1 = 0, s2 = 0, cnt = 0;
-        for (int k = 0; k < 7; ++k) {
-            const uint64_t key = cell_key((cx + fo[k][0]) & mask, (cy + fo[k][1]) & mask, (cz + fo[k][2]) & mask,
-                                          fine.b);
-            const int c = find64(fine.hk, fine.hv, fine.hmask, key);
-            if (c < 0) continue;
-            cnt += (double)(fine.start[c + 1] - fine.start[c]);
-            s0 += vsum[3 * (size_t)c];
-            s1 += vsum[3 * (size_t)c + 1];
-            s2 += vsum[3 * (size_t)c + 2];
-        }
-        f[8] = s0 / cnt;   // vloc, turned into features below
-        f[9] = s1 / cnt;
-        f[10] = s2 / cnt;
+    cf[4 * (size_t)c] = log(cbrt(3.0 * (double)n_se / (4.0 * M_PI * nhat)));
+    const int fo[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    double s0 = 0, s1 = 0, s2 = 0, cnt = 0;
+    for (int k = 0; k < 7; ++k) {
+        const uint64_t kk = cell_key((cx + fo[k][0]) & mask, (cy + fo[k][1]) & mask, (cz + fo[k][2]) & mask, fine.b);
+        const int cc = find64(fine.hk, fine.hv, fine.hmask, kk);
+        if (cc < 0) continue;
+        cnt += (double)(fine.start[cc + 1] - fine.start[cc]);
+        s0 += vsum[3 * (size_t)cc];
+        s1 += vsum[3 * (size_t)cc + 1];
+        s2 += vsum[3 * (size_t)cc + 2];
     }
+    cf[4 * (size_t)c + 1] = s0 / cnt;
+    cf[4 * (size_t)c + 2] = s1 / cnt;
+    cf[4 * (size_t)c + 3] = s2 / cnt;
+}
+
+__global__ __launch_bounds__(256) void k_rs_features(int64_t m, const int32_t* __restrict__ mem,
+                                                     const float* __restrict__ vx, const float* __restrict__ vy,
+                                                     const float* __restrict__ vz, const float* __restrict__ vbar,
+                                                     const float* __restrict__ sigma, const float* __restrict__ rho,
+                                                     int64_t n, const uint32_t* __restrict__ head,
+                                                     const uint32_t* __restrict__ cid, const double* __restrict__ cf,
+                                                     FeatNorm nrm, const uint32_t* __restrict__ order,
+                                                     uint16_t* __restrict__ feat) {
+    // rows are taken in fine-cell order (position t of the sorted cell
+    // keys), so neighbouring threads share their cell's values
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t i = order[t];
+    const int g = mem[i];
+    const uint32_t c = head[t] ? cid[t] : cid[t] - 1;  // the row's fine cell (exclusive scan of the heads)
+    double f[NF];
+    f[0] = cf[4 * (size_t)c];
+    f[8] = cf[4 * (size_t)c + 1];  // vloc, turned into features below
+    f[9] = cf[4 * (size_t)c + 2];
+    f[10] = cf[4 * (size_t)c + 3];
     const double vl[3] = {f[8], f[9], f[10]};
     double A[3][3];
     A[0][0] = sigma[g];
@@ -693,6 +706,10 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
     const int cb[2] = {cell_bits, cell_bits + 2};
     double* vsum = nullptr;
     const uint32_t* order = nullptr;
+    const uint32_t* head0 = nullptr;
+    const uint32_t* cid0 = nullptr;
+    const uint64_t* keys0 = nullptr;
+    uint32_t ncell[2] = {0, 0};
     for (int L = 0; L < 2; ++L) {
         const int b = p->grid_bits - cb[L];
         VR_WS(keys, ctx, uint64_t, WS_A0 + 4 * L, m);
@@ -723,7 +740,11 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
                            hk, hv);
         VR_LAUNCH_CHECK(ctx);
         lv[L] = Level{hk, hv, hsize - 1, start, cb[L], b};
+        ncell[L] = ncells;
         if (L == 0) {
+            head0 = flag;
+            cid0 = cid;
+            keys0 = keys;
             VR_WS(vs, ctx, double, WS_B6, 3 * (size_t)ncells);
             hipLaunchKernelGGL(k_rs_vsum, dim3(grid_for(ncells, 256)), dim3(256), 0, st, ncells, start, rws,
                                host_members, p->vx, p->vy, p->vz, vs);
@@ -733,10 +754,14 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
         }
     }
     const double cell_len = ldexp(p->box, cell_bits - p->grid_bits);
+    VR_WS(cf, ctx, double, WS_C0, 4 * (size_t)ncell[0]);
+    VR_TIMED(ctx, "rs_features", st, 0,
+             hipLaunchKernelGGL(k_rs_cellfeat, dim3(grid_for(ncell[0], 256)), dim3(256), 0, st, ncell[0], keys0, lv[0],
+                                lv[1], vsum, n_se, cell_len, cf));
+    VR_LAUNCH_CHECK(ctx);
     VR_TIMED(ctx, "rs_features", st, m,
-             hipLaunchKernelGGL(k_rs_features, dim3(grid_for(m, 256)), dim3(256), 0, st, m, host_members, p->qx,
-                                p->qy, p->qz, p->vx, p->vy, p->vz, vbar, sigma, rho_cell, p->n, lv[0], lv[1], vsum,
-                                n_se, cell_len, nrm, order, feat));
+             hipLaunchKernelGGL(k_rs_features, dim3(grid_for(m, 256)), dim3(256), 0, st, m, host_members, p->vx, p->vy,
+                                p->vz, vbar, sigma, rho_cell, p->n, head0, cid0, cf, nrm, order, feat));
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }
