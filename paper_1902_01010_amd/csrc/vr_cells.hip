@@ -153,19 +153,19 @@ __global__ __launch_bounds__(KB) void k_cell_interp(int ncells, int64_t n, const
     const int c = blockIdx.x;
     const KdNode nd = nodes[cell_node[c]];
     const double* row = table + (int64_t)c * VR_CELL_COLS;
-    if (threadIdx.x == 0) {
-        int set[7], ns = 0;
-        set[ns++] = c;
-        for (int f = 0; f < 6; ++f) {
-            const double nb = row[21 + f];
-            if (nb >= 0) set[ns++] = (int)nb;
+    // the cell and its face neighbours (-x, +x, -y, +y, -z, +z), in that
+    // order: thread a < 7 loads entry a, so the rows arrive in one round trip
+    if (threadIdx.x < 7) {
+        const int a = (int)threadIdx.x;
+        const int id = a == 0 ? c : (int)row[21 + a - 1];  // -1: no neighbour on that face
+        const uint64_t have = __ballot(id >= 0) & 127u;
+        if (id >= 0) {
+            const int slot = __popcll(have & ((1ull << a) - 1ull));
+            const double* r = table + (int64_t)id * VR_CELL_COLS;
+            for (int d = 0; d < 3; ++d) { cx[slot][d] = r[3 + d]; cv[slot][d] = r[6 + d]; }
+            for (int e = 0; e < 6; ++e) cv[slot][3 + e] = r[9 + e];
         }
-        for (int a = 0; a < ns; ++a) {
-            const double* r = table + (int64_t)set[a] * VR_CELL_COLS;
-            for (int d = 0; d < 3; ++d) { cx[a][d] = r[3 + d]; cv[a][d] = r[6 + d]; }
-            for (int e = 0; e < 6; ++e) cv[a][3 + e] = r[9 + e];
-        }
-        s_ns = ns;
+        if (a == 0) s_ns = __popcll(have);
     }
     __syncthreads();
     const int ns = s_ns;
