@@ -84,6 +84,21 @@ __global__ void k_roots(int n_hosts, const int32_t* __restrict__ off, const int*
     (void)seg_node_unused;
 }
 
+// Between two levels: the next level's active-node and member counts become
+// the current ones, and the next ones restart from zero (counters[0] and
+// [4] are this level's, [1] and [5] the next level's).  One thread.
+__global__ void k_level_counters(int* counters, int roll, int clear) {
+    if (threadIdx.x != 0) return;
+    if (roll) {
+        counters[0] = counters[1];
+        counters[4] = counters[5];
+    }
+    if (clear) {
+        counters[1] = 0;
+        counters[5] = 0;
+    }
+}
+
 __global__ void k_seg_init(int64_t M, const int* __restrict__ host, int* __restrict__ seg_node) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < M) seg_node[p] = host[p];  // hosts keep their ranges in every list
@@ -593,8 +608,8 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
             e0 = timer_event(ctx);
             (void)hipEventRecord(e0, st);
         }
-        if ((rc = fill_i32(ctx, counters + 1, 0, 1, st))) return rc;
-        if ((rc = fill_i32(ctx, counters + 5, 0, 1, st))) return rc;
+        hipLaunchKernelGGL(k_level_counters, dim3(1), dim3(64), 0, st, counters, level > 0 ? 1 : 0, 1);
+        VR_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_bbox, dim3(grid_for(na, 256)), dim3(256), 0, st, counters, cur, nodes, L[0], L[1], L[2],
                            U[0], U[1], U[2], n_hosts);
         VR_LAUNCH_CHECK(ctx);
@@ -642,14 +657,16 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
             std::swap(L[j], Lalt[j]);
             std::swap(C0[j], C0alt[j]);
         }
-        VR_HIP(ctx, hipMemcpyAsync(counters + 0, counters + 1, sizeof(int), hipMemcpyDeviceToDevice, st));
-        VR_HIP(ctx, hipMemcpyAsync(counters + 4, counters + 5, sizeof(int), hipMemcpyDeviceToDevice, st));
         if (ctx->timing) {
             hipEvent_t e1 = timer_event(ctx);
             (void)hipEventRecord(e1, st);
             timer_push(ctx, "kd_level", e0, e1, (double)plan_members[level]);
         }
         std::swap(cur, nxt);
+    }
+    if (!plan_na.empty()) {
+        hipLaunchKernelGGL(k_level_counters, dim3(1), dim3(64), 0, st, counters, 1, 0);
+        VR_LAUNCH_CHECK(ctx);
     }
     int c[8];
     int rc = read_back(ctx, counters, c, sizeof c, st);
