@@ -146,8 +146,8 @@ typedef struct {
  * median of the chosen dimension until a node holds at most N_cell members
  * (N_cell = min(max(ceil(f_cell N_H), ncell_floor), N_H / ncell_div)).  For
  * every host member writes vbar[3*n] (component-major), sigma[6*n]
- * (xx,yy,zz,xy,xz,yz), rho_cell[n] and cell_of[n]; other entries are not
- * touched.  Cells are numbered per host (hosts in order, cells by ascending
+ * (xx,yy,zz,xy,xz,yz), rho_cell[n] and cell_of[n] (either may be NULL:
+ * not written); other entries are not touched.  Cells are numbered per host (hosts in order, cells by ascending
  * smallest member).  cell_table (may be NULL) receives VR_CELL_COLS doubles
  * per cell: host, n, M, xbar[3], vbar[3], sigma[6], lo[3], hi[3], face
  * neighbours[6] (-x,+x,-y,+y,-z,+z; -1 none), volume.  *n_cells (HOST).

@@ -195,8 +195,8 @@ __global__ __launch_bounds__(KB) void k_cell_interp(int ncells, int64_t n, const
         const int g = src.gidx[k];
         for (int d = 0; d < 3; ++d) vbar[(int64_t)d * n + g] = (float)o[d];
         for (int e = 0; e < 6; ++e) sigma[(int64_t)e * n + g] = (float)o[3 + e];
-        rho[g] = rho_c;
-        cell_of[g] = (int32_t)(cell_base + c);
+        if (rho) rho[g] = rho_c;
+        if (cell_of) cell_of[g] = (int32_t)(cell_base + c);
     }
 }
 
@@ -220,7 +220,7 @@ extern "C" int vr_cell_moments(vr_ctx* ctx, const vr_particles* p, int32_t n_hos
     if (cp->split_rule != 0 && cp->split_rule != 1) return set_err(ctx, VR_ERR_INVALID_ARG, "split_rule is 0 or 1");
     *n_cells = 0;
     if (n_hosts == 0) return VR_OK;
-    if (!vbar || !sigma || !rho_cell || !cell_of) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL output");
+    if (!vbar || !sigma) return set_err(ctx, VR_ERR_INVALID_ARG, "NULL output");
     VR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     std::vector<int32_t> off;

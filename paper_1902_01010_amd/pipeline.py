@@ -172,7 +172,8 @@ def _search(ctx, P, group_of, n_hosts, host_offsets, members, prm: Params, mark,
     candidates unbound.  species = (host offsets over both species, their
     members, is_baryon) adds the baryon assignment before unbinding."""
     out = {}
-    cm = ctx.cell_moments(P, host_offsets, members, want_table=False)
+    # nothing downstream reads a member's cell index
+    cm = ctx.cell_moments(P, host_offsets, members, want_table=False, want_cell_of=False)
     mark(tag + "cells")
     if model is None:
         R = ctx.local_vdensity(P, host_offsets, members, cm["vbar"], cm["sigma"], prm.n_se, prm.n_v)

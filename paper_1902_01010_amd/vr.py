@@ -260,15 +260,17 @@ class Context:
         return g, gof, off, mem
 
     def cell_moments(self, P: Particles, host_offsets, host_members, f_cell=0.01, ncell_floor=100,
-                     ncell_div=8, nbins=16, split_rule=0, want_table=True, out=None):
+                     ncell_div=8, nbins=16, split_rule=0, want_table=True, out=None, want_rho=True,
+                     want_cell_of=True):
+        """want_rho / want_cell_of False: that output is not written (None)."""
         dev = P.device
         n = P.n
         nh = host_offsets.shape[0] - 1
         if out is None:
             out = dict(vbar=torch.full((3, n), float("nan"), device=dev),
                        sigma=torch.full((6, n), float("nan"), device=dev),
-                       rho_cell=torch.full((n,), float("nan"), device=dev),
-                       cell_of=torch.full((n,), -1, dtype=torch.int32, device=dev))
+                       rho_cell=torch.full((n,), float("nan"), device=dev) if want_rho else None,
+                       cell_of=torch.full((n,), -1, dtype=torch.int32, device=dev) if want_cell_of else None)
         cp = _CellParams(f_cell, ncell_floor, ncell_div, nbins, split_rule)
         ncell = C.c_int64(0)
         cap = 0
