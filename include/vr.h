@@ -145,9 +145,10 @@ typedef struct {
  * minimum image relative to its first member, split recursively at the
  * median of the chosen dimension until a node holds at most N_cell members
  * (N_cell = min(max(ceil(f_cell N_H), ncell_floor), N_H / ncell_div)).  For
- * every host member writes vbar[3*n] (component-major), sigma[6*n]
- * (xx,yy,zz,xy,xz,yz), rho_cell[n] and cell_of[n] (either may be NULL:
- * not written); other entries are not touched.  Cells are numbered per host (hosts in order, cells by ascending
+ * every host member writes vbar[n][3] and sigma[n][6] (particle-major:
+ * vbar[3*i + d], sigma[6*i + e] with e over xx,yy,zz,xy,xz,yz, so one
+ * member's values are contiguous), rho_cell[n] and cell_of[n] (either may
+ * be NULL: not written); other entries are not touched.  Cells are numbered per host (hosts in order, cells by ascending
  * smallest member).  cell_table (may be NULL) receives VR_CELL_COLS doubles
  * per cell: host, n, M, xbar[3], vbar[3], sigma[6], lo[3], hi[3], face
  * neighbours[6] (-x,+x,-y,+y,-z,+z; -1 none), volume.  *n_cells (HOST).
@@ -164,7 +165,8 @@ int vr_cell_moments(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
  * index); V_k = the n_v members of S_k nearest in velocity; h = velocity
  * distance to the n_v-th; f_l = sum_V m_j W(|dv_j|/h) / (h^3 sum_S m_j) with
  * the 3D Epanechnikov kernel W(u) = 15/(8 pi) (1 - u^2); f_bg = Gaussian at
- * vbar(x_k), sigma(x_k).  2 <= n_v <= n_se <= 256 and n_v <= 32 when
+ * vbar(x_k), sigma(x_k) (vbar [n][3], sigma [n][6], particle-major as
+ * vr_cell_moments writes them).  2 <= n_v <= n_se <= 256 and n_v <= 32 when
  * n_se > 64 (the paper's defaults, 256 and 32, are the largest case; beyond
  * n_se = 32 a workgroup's LDS heaps cut the occupancy), every host has
  * >= n_se members.  subset (may be NULL = all host members) lists the particles to
@@ -198,7 +200,7 @@ int vr_fof6d(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of,
 /* The paper's own substructure linker (Sec. 2.2, Eq. linkingcriteria).
  * Participants: hosted particles (0 <= host_of[i] < n_hosts) with
  * L[i] >= L_threshold (L: [n], e.g. from vr_ell_fit).  With
- * u = v - vbar(x) in FP64 (vbar: [3][n] local mean velocity, as
+ * u = v - vbar(x) in FP64 (vbar: [n][3] local mean velocity, as
  * vr_cell_moments gives it) and s = |u|, i and j link iff they share a
  * host, d2 < (ellx_s in grid units)^2 (exact integer d2), s_i, s_j > 0,
  * s_i <= Vr s_j and s_j <= Vr s_i, and u_i . u_j >= cos_theta_op (s_i s_j).
@@ -374,7 +376,8 @@ int vr_ell_clean(vr_ctx* ctx, int64_t n, int32_t n_groups, const int32_t* offset
 /* Features of every host member (rows in host_members order, m rows =
  * host_offsets[n_hosts], written to *n_rows; syncs), as BF16 bit patterns,
  * row-major [m][12], each (x - shift[k]) * scale[k] (shift, scale: HOST
- * arrays of 12, or NULL for 0 and 1).  With Sigma = sigma(x) of the particle
+ * arrays of 12, or NULL for 0 and 1).  vbar [n][3], sigma [n][6] and
+ * rho_cell [n] as vr_cell_moments writes them.  With Sigma = sigma(x) of the particle
  * (eigenvalues l1 <= l2 <= l3, unit eigenvectors e_a), dv = v - vbar(x):
  *  0     ln rhat, rhat = (3 n_se / (4 pi nhat))^(1/3), nhat = the member count
  *        of the 27 cells of side f = 2^cell_bits grid units around the

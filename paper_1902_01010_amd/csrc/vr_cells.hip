@@ -193,8 +193,9 @@ __global__ __launch_bounds__(KB) void k_cell_interp(int ncells, int64_t n, const
             for (int e = 0; e < 9; ++e) o[e] = sv[e] / ws;
         }
         const int g = src.gidx[k];
-        for (int d = 0; d < 3; ++d) vbar[(int64_t)d * n + g] = (float)o[d];
-        for (int e = 0; e < 6; ++e) sigma[(int64_t)e * n + g] = (float)o[3 + e];
+        // particle-major: a member's 3 + 6 values are two contiguous records
+        for (int d = 0; d < 3; ++d) vbar[(int64_t)g * 3 + d] = (float)o[d];
+        for (int e = 0; e < 6; ++e) sigma[(int64_t)g * 6 + e] = (float)o[3 + e];
         if (rho) rho[g] = rho_c;
         if (cell_of) cell_of[g] = (int32_t)(cell_base + c);
     }

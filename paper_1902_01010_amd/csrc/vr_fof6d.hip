@@ -164,9 +164,9 @@ __global__ void k_sorted_u(int64_t np, int64_t n, const int32_t* __restrict__ so
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const int32_t i = sorig[p];
-    const double u0 = (double)vx[i] - (double)vbar[i];
-    const double u1 = (double)vy[i] - (double)vbar[n + i];
-    const double u2 = (double)vz[i] - (double)vbar[2 * n + i];
+    const double u0 = (double)vx[i] - (double)vbar[3 * (int64_t)i];  // particle-major
+    const double u1 = (double)vy[i] - (double)vbar[3 * (int64_t)i + 1];
+    const double u2 = (double)vz[i] - (double)vbar[3 * (int64_t)i + 2];
     su0[p] = u0;
     su1[p] = u1;
     su2[p] = u2;

@@ -54,14 +54,16 @@ __global__ void k_subset_pos(int64_t ns, int64_t n, const int32_t* __restrict__ 
 // quadratic form is u^T adj(S) u / det S with u = vq - vbar; S is positive
 // definite iff its leading principal minors S_xx, S_xx S_yy - S_xy^2 and
 // det S are positive (Sylvester's criterion), else NaN.
-__device__ __forceinline__ double log_fbg(const float* __restrict__ sigma, const float* __restrict__ vbar, int64_t n,
+__device__ __forceinline__ double log_fbg(const float* __restrict__ sigma, const float* __restrict__ vbar,
                                           int g, double vqx, double vqy, double vqz) {
-    const double sxx = sigma[0 * n + g], syy = sigma[1 * n + g], szz = sigma[2 * n + g];
-    const Sym3Adj A = sym3_adjugate(sxx, syy, szz, sigma[3 * n + g], sigma[4 * n + g], sigma[5 * n + g]);
+    const float* s = sigma + (int64_t)g * 6;  // particle-major
+    const double sxx = s[0], syy = s[1], szz = s[2];
+    const Sym3Adj A = sym3_adjugate(sxx, syy, szz, s[3], s[4], s[5]);
     if (!(sxx > 0) || !(A.zz > 0) || !(A.det > 0)) return NAN;
-    const double ux = vqx - (double)vbar[0 * n + g];
-    const double uy = vqy - (double)vbar[1 * n + g];
-    const double uz = vqz - (double)vbar[2 * n + g];
+    const float* vb = vbar + (int64_t)g * 3;
+    const double ux = vqx - (double)vb[0];
+    const double uy = vqy - (double)vb[1];
+    const double uz = vqz - (double)vb[2];
     const double diag = A.xx * ux * ux + A.yy * uy * uy + A.zz * uz * uz;
     const double offd = A.xy * ux * uy + A.xz * ux * uz + A.yz * uy * uz;
     // 3 ln(2 pi) / 2
@@ -95,7 +97,7 @@ __global__ void k_member_records(int64_t n, const int* __restrict__ rank_of, con
     if (k < 0) return;
     const float ux = vx[g], uy = vy[g], uz = vz[g];
     V[k] = make_float4(ux, uy, uz, mass ? mass[g] : 0.f);
-    FB[k] = log_fbg(sigma, vbar, n, (int)g, (double)ux, (double)uy, (double)uz);
+    FB[k] = log_fbg(sigma, vbar, (int)g, (double)ux, (double)uy, (double)uz);
 }
 
 __device__ __forceinline__ bool vless(double a, int pa, double b, int pb) { return a < b || (a == b && pa < pb); }

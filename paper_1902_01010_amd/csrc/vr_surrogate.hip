@@ -270,15 +270,16 @@ __global__ __launch_bounds__(256) void k_rs_features(int64_t m, const int32_t* _
     f[10] = cf[4 * (size_t)c + 3];
     const double vl[3] = {f[8], f[9], f[10]};
     double A[3][3];
-    A[0][0] = sigma[g];
-    A[1][1] = sigma[n + g];
-    A[2][2] = sigma[2 * n + g];
-    A[0][1] = A[1][0] = sigma[3 * n + g];
-    A[0][2] = A[2][0] = sigma[4 * n + g];
-    A[1][2] = A[2][1] = sigma[5 * n + g];
+    const float* sg = sigma + (int64_t)g * 6;  // particle-major
+    A[0][0] = sg[0];
+    A[1][1] = sg[1];
+    A[2][2] = sg[2];
+    A[0][1] = A[1][0] = sg[3];
+    A[0][2] = A[2][0] = sg[4];
+    A[1][2] = A[2][1] = sg[5];
     double lam[3], V[3][3];
     jacobi3(A, lam, V);
-    const double vb[3] = {vbar[g], vbar[n + g], vbar[2 * n + g]};
+    const double vb[3] = {vbar[(int64_t)g * 3], vbar[(int64_t)g * 3 + 1], vbar[(int64_t)g * 3 + 2]};
     const double vv[3] = {vx[g], vy[g], vz[g]};
     const bool ok = lam[0] > 0.0;
     for (int a = 0; a < 3; ++a) {

@@ -138,6 +138,28 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _pm(t, k, output=False):
+    """A per-particle k-vector field held as a (k, n) tensor, in the
+    library's particle-major [n][k] layout.  A (k, n) view of [n][k] storage
+    (what cell_moments returns) is used as it is; a component-major (k, n)
+    array is copied into the library's layout (inputs only); a flat buffer
+    of k n values is taken to be in that layout already.  The caller holds
+    the result until the library call has been enqueued, so that a copy's
+    memory is not handed out again before the kernels that read it."""
+    if t is None:
+        return None
+    if t.dim() == 1 and t.numel() % k == 0:
+        return t
+    if t.dim() != 2 or t.shape[0] != k:
+        raise ValueError(f"expected a ({k}, n) tensor, got {tuple(t.shape)}")
+    tt = t.t()
+    if not tt.is_contiguous():
+        if output:
+            raise ValueError("outputs must be (k, n) views of particle-major [n][k] storage")
+        tt = tt.contiguous()
+    return tt
+
+
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -267,11 +289,13 @@ class Context:
         n = P.n
         nh = host_offsets.shape[0] - 1
         if out is None:
-            out = dict(vbar=torch.full((3, n), float("nan"), device=dev),
-                       sigma=torch.full((6, n), float("nan"), device=dev),
+            # particle-major storage, returned as (3, n) and (6, n) views
+            out = dict(vbar=torch.full((n, 3), float("nan"), device=dev).t(),
+                       sigma=torch.full((n, 6), float("nan"), device=dev).t(),
                        rho_cell=torch.full((n,), float("nan"), device=dev) if want_rho else None,
                        cell_of=torch.full((n,), -1, dtype=torch.int32, device=dev) if want_cell_of else None)
         cp = _CellParams(f_cell, ncell_floor, ncell_div, nbins, split_rule)
+        vb_l, sg_l = _pm(out["vbar"], 3, True), _pm(out["sigma"], 6, True)
         ncell = C.c_int64(0)
         cap = 0
         table = None
@@ -280,7 +304,7 @@ class Context:
             cap = int(host_members.shape[0]) if nh > 0 else 0
             table = torch.empty((max(cap, 1), CELL_COLS), dtype=torch.float64, device=dev)
         self._check(self.lib.vr_cell_moments(self.h, C.byref(P.s), nh, _ptr(host_offsets), _ptr(host_members),
-                                             C.byref(cp), _ptr(out["vbar"]), _ptr(out["sigma"]),
+                                             C.byref(cp), _ptr(vb_l), _ptr(sg_l),
                                              _ptr(out["rho_cell"]), _ptr(out["cell_of"]), cap,
                                              _ptr(table), C.byref(ncell), _stream()))
         out["n_cells"] = ncell.value
@@ -294,8 +318,9 @@ class Context:
             R = torch.full((P.n,), float("nan"), device=P.device)
         nh = host_offsets.shape[0] - 1
         ns = 0 if subset is None else subset.shape[0]
+        vb_l, sg_l = _pm(vbar, 3), _pm(sigma, 6)
         self._check(self.lib.vr_local_vdensity(self.h, C.byref(P.s), nh, _ptr(host_offsets),
-                                               _ptr(host_members), _ptr(vbar), _ptr(sigma), int(n_se),
+                                               _ptr(host_members), _ptr(vb_l), _ptr(sg_l), int(n_se),
                                                int(n_v), _ptr(subset), ns, _ptr(R), _stream()))
         return R
 
@@ -320,7 +345,8 @@ class Context:
         the local mean velocity vbar, over L >= L_threshold)."""
         if label is None:
             label = torch.empty(P.n, dtype=torch.int32, device=P.device)
-        self._check(self.lib.vr_fof_sub(self.h, C.byref(P.s), _ptr(host_of), int(n_hosts), _ptr(vbar),
+        vb_l = _pm(vbar, 3)
+        self._check(self.lib.vr_fof_sub(self.h, C.byref(P.s), _ptr(host_of), int(n_hosts), _ptr(vb_l),
                                         float(ellx_s), _ptr(L), float(L_threshold), float(Vr),
                                         math.cos(theta_op), _ptr(label), _stream()))
         return label
@@ -333,7 +359,8 @@ class Context:
         if label is None:
             label = torch.empty(P.n, dtype=torch.int32, device=P.device)
         nr = C.c_int32(0)
-        self._check(self.lib.vr_sub_grow(self.h, C.byref(P.s), _ptr(host_of), int(n_hosts), _ptr(vbar), _ptr(L),
+        vb_l = _pm(vbar, 3)
+        self._check(self.lib.vr_sub_grow(self.h, C.byref(P.s), _ptr(host_of), int(n_hosts), _ptr(vb_l), _ptr(L),
                                          float(L_threshold), float(gamma_L), float(ellx_s), float(gamma_x),
                                          float(Vr), float(gamma_V), math.cos(min(math.pi, gamma_theta * theta_op)),
                                          float(f_merge), int(n_min), _ptr(label1), _ptr(label), C.byref(nr),
@@ -439,8 +466,9 @@ class Context:
         sh = None if shift is None else arr(*[float(x) for x in shift])
         sc = None if scale is None else arr(*[float(x) for x in scale])
         rows = C.c_int64(0)
+        vb_l, sg_l = _pm(vbar, 3), _pm(sigma, 6)
         self._check(self.lib.vr_rs_features(self.h, C.byref(P.s), nh, _ptr(host_offsets), _ptr(host_members),
-                                            _ptr(vbar), _ptr(sigma), _ptr(rho_cell), int(n_se), int(cell_bits),
+                                            _ptr(vb_l), _ptr(sg_l), _ptr(rho_cell), int(n_se), int(cell_bits),
                                             sh, sc, _ptr(feat), C.byref(rows), _stream()))
         return feat[:rows.value]
 
