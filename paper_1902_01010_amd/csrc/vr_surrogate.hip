@@ -190,16 +190,37 @@ __device__ void jacobi3(double A[3][3], double lam[3], double V[3][3]) {
     }
 }
 
+// Members in the 27 cells around (cx, cy, cz).  Each z-layer's nine
+// lookups go out together: the nine first-probe keys in one round trip,
+// then the hits' values and member ranges; a probe continues one by one
+// only past a collision.
 __device__ __forceinline__ uint32_t window_count(const Level& L, uint32_t cx, uint32_t cy, uint32_t cz) {
     const uint32_t mask = (1u << L.b) - 1u;
     uint32_t n = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const uint64_t k = cell_key((cx + dx) & mask, (cy + dy) & mask, (cz + dz) & mask, L.b);
-                const int c = find64(L.hk, L.hv, L.hmask, k);
-                if (c >= 0) n += L.start[c + 1] - L.start[c];
-            }
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        uint64_t k[9];
+        uint32_t h[9];
+        unsigned long long kk[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int dy = j / 3 - 1, dx = j % 3 - 1;
+            k[j] = cell_key((cx + dx) & mask, (cy + dy) & mask, (cz + dz) & mask, L.b);
+            h[j] = hash64(k[j], L.hmask);
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) kk[j] = L.hk[h[j]];
+        int c[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            if (kk[j] == k[j]) c[j] = (int)L.hv[h[j]];
+            else if (kk[j] == EMPTY64) c[j] = -1;
+            else c[j] = find64(L.hk, L.hv, L.hmask, k[j]);  // past a collision
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j)
+            if (c[j] >= 0) n += L.start[c[j] + 1] - L.start[c[j]];
+    }
     return n;
 }
 
@@ -207,14 +228,27 @@ struct FeatNorm {
     float shift[NF], scale[NF];
 };
 
+// Members in the 27-cell window of every occupied coarse cell (the fallback
+// density of the fine cells inside it), once per coarse cell.
+__global__ __launch_bounds__(256) void k_rs_coarsewin(uint32_t ncells, const uint64_t* __restrict__ keys,
+                                                      Level coarse, uint32_t* __restrict__ cwin) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const uint64_t key = keys[coarse.start[c]];
+    const uint32_t mask = (1u << coarse.b) - 1u;
+    cwin[c] = window_count(coarse, (uint32_t)(key & mask), (uint32_t)((key >> coarse.b) & mask),
+                           (uint32_t)(key >> (2 * coarse.b)));
+}
+
 // What a row's features take from its fine cell alone, once per occupied
 // fine cell (rows of a cell share it): feature 0, the log radius holding
 // n_se neighbours at the density of the 27-cell window (the coarse window
 // where the fine one holds fewer than n_se), and the mean velocity of the
 // cell and its six face neighbours.  cf[4 c .. 4 c + 3] = (f0, vloc).
 __global__ __launch_bounds__(256) void k_rs_cellfeat(uint32_t ncells, const uint64_t* __restrict__ keys,
-                                                     Level fine, Level coarse, const double* __restrict__ vsum,
-                                                     int n_se, double cell_len, double* __restrict__ cf) {
+                                                     Level fine, Level coarse, const uint32_t* __restrict__ cwin,
+                                                     const double* __restrict__ vsum, int n_se, double cell_len,
+                                                     double* __restrict__ cf) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     const uint64_t key = keys[fine.start[c]];
@@ -226,17 +260,39 @@ __global__ __launch_bounds__(256) void k_rs_cellfeat(uint32_t ncells, const uint
     if ((int)nf >= n_se) {
         nhat = (double)nf / (27.0 * cell_len * cell_len * cell_len);
     } else {
-        // the coarse grid's cells are 4 fine cells a side
-        const uint32_t nc = window_count(coarse, cx >> 2, cy >> 2, cz >> 2);
+        // the coarse grid's cells are 4 fine cells a side; the one holding
+        // this fine cell is occupied, and its window count is precomputed
+        const uint32_t cmask = (1u << coarse.b) - 1u;
+        const int c1 = find64(coarse.hk, coarse.hv, coarse.hmask,
+                              cell_key((cx >> 2) & cmask, (cy >> 2) & cmask, (cz >> 2) & cmask, coarse.b));
+        const uint32_t nc = c1 >= 0 ? cwin[c1] : 0u;
         const double L4 = 4.0 * cell_len;
         nhat = (double)nc / (27.0 * L4 * L4 * L4);
     }
     cf[4 * (size_t)c] = log(cbrt(3.0 * (double)n_se / (4.0 * M_PI * nhat)));
     const int fo[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
-    double s0 = 0, s1 = 0, s2 = 0, cnt = 0;
+    // the seven lookups go out together, as in window_count
+    uint64_t fk[7];
+    uint32_t fh[7];
+    unsigned long long fkk[7];
+    int fc[7];
+#pragma unroll
     for (int k = 0; k < 7; ++k) {
-        const uint64_t kk = cell_key((cx + fo[k][0]) & mask, (cy + fo[k][1]) & mask, (cz + fo[k][2]) & mask, fine.b);
-        const int cc = find64(fine.hk, fine.hv, fine.hmask, kk);
+        fk[k] = cell_key((cx + fo[k][0]) & mask, (cy + fo[k][1]) & mask, (cz + fo[k][2]) & mask, fine.b);
+        fh[k] = hash64(fk[k], fine.hmask);
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) fkk[k] = fine.hk[fh[k]];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        if (fkk[k] == fk[k]) fc[k] = (int)fine.hv[fh[k]];
+        else if (fkk[k] == EMPTY64) fc[k] = -1;
+        else fc[k] = find64(fine.hk, fine.hv, fine.hmask, fk[k]);
+    }
+    double s0 = 0, s1 = 0, s2 = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const int cc = fc[k];
         if (cc < 0) continue;
         cnt += (double)(fine.start[cc + 1] - fine.start[cc]);
         s0 += vsum[3 * (size_t)cc];
@@ -710,6 +766,7 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
     const uint32_t* head0 = nullptr;
     const uint32_t* cid0 = nullptr;
     const uint64_t* keys0 = nullptr;
+    const uint64_t* keys1 = nullptr;
     uint32_t ncell[2] = {0, 0};
     for (int L = 0; L < 2; ++L) {
         const int b = p->grid_bits - cb[L];
@@ -742,6 +799,7 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
         VR_LAUNCH_CHECK(ctx);
         lv[L] = Level{hk, hv, hsize - 1, start, cb[L], b};
         ncell[L] = ncells;
+        if (L == 1) keys1 = keys;
         if (L == 0) {
             head0 = flag;
             cid0 = cid;
@@ -756,9 +814,14 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
     }
     const double cell_len = ldexp(p->box, cell_bits - p->grid_bits);
     VR_WS(cf, ctx, double, WS_C0, 4 * (size_t)ncell[0]);
+    VR_WS(cwin, ctx, uint32_t, WS_C1, (size_t)ncell[1]);
+    VR_TIMED(ctx, "rs_features", st, 0,
+             hipLaunchKernelGGL(k_rs_coarsewin, dim3(grid_for(ncell[1], 256)), dim3(256), 0, st, ncell[1], keys1, lv[1],
+                                cwin));
+    VR_LAUNCH_CHECK(ctx);
     VR_TIMED(ctx, "rs_features", st, 0,
              hipLaunchKernelGGL(k_rs_cellfeat, dim3(grid_for(ncell[0], 256)), dim3(256), 0, st, ncell[0], keys0, lv[0],
-                                lv[1], vsum, n_se, cell_len, cf));
+                                lv[1], cwin, vsum, n_se, cell_len, cf));
     VR_LAUNCH_CHECK(ctx);
     VR_TIMED(ctx, "rs_features", st, m,
              hipLaunchKernelGGL(k_rs_features, dim3(grid_for(m, 256)), dim3(256), 0, st, m, host_members, p->vx, p->vy,
