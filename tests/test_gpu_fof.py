@@ -134,3 +134,34 @@ def test_workspace_cap_is_an_error(vr, ref):
     assert 0 < roomy.workspace_bytes() <= 256 << 20
     small.close()
     roomy.close()
+
+
+@pytest.mark.parametrize("seed,wrap", [(11, False), (12, True)])
+def test_fof3d_dense_coarse_cells_bit_exact(ctx, vr, ref, seed, wrap):
+    """Dense cores take the wavefront-per-coarse-cell path of the 3D link
+    (coarse cells with >= 48 occupied fine cells of 4 a side): a compact
+    clump whose core fills whole coarse cells, a looser halo around it and
+    sparse background, against the oracle, bit-exact.  With wrap the clump
+    straddles the periodic corner, so the tiles' neighbour cells cross the
+    box faces.  The test checks that the link ran three launches (the
+    per-thread sweep and the two tile passes), i.e. that the path was taken."""
+    rng = np.random.default_rng(seed)
+    size = 1 << 21
+    ell_u = 1500.0  # grid units: coarse cells of 2048, fine cells of 512 (r = 4)
+    core = rng.normal(0.0, 2500.0, (3, 30000))
+    halo = rng.normal(0.0, 12000.0, (3, 8000))
+    bg = rng.uniform(-size / 2, size / 2, (3, 4000))
+    centre = 0.0 if wrap else size / 2
+    q = np.mod(np.rint(np.concatenate([core, halo, bg], axis=1) + centre), size).astype(np.uint32)
+    Pd = vr.Particles(dev_tensor(q.view(np.int32)), None, None, 1.0, 1.0, 21)
+    Pr = ref.Particles(q, None, None, 1.0, 1.0, 21)
+    ell = ell_u / size
+    ctx.set_timing(True)
+    n0 = ctx.kernel_time("fof_link3d")[0]
+    lab = ctx.fof3d(Pd, ell).cpu().numpy()
+    n1 = ctx.kernel_time("fof_link3d")[0]
+    ctx.set_timing(False)
+    assert n1 - n0 == 3
+    exp = ref.fof3d(Pr, ell)
+    assert (lab == exp).all()
+    assert (np.unique(lab, return_counts=True)[1] > 20000).any()  # the core is one large group
