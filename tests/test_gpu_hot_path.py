@@ -384,3 +384,42 @@ def test_field_halos_6d_pipeline_parity(ctx, vr, ref, name):
         assert (lab3[mm] == lab3[mm[0]]).all()
     if exp["n_hosts"]:
         _R_close(got["R"].cpu().numpy(), exp["R"])
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_fof6d_dense_cells_bit_exact(ctx, vr, ref, seed):
+    """Cells holding hundreds of participants: their tiles run first, many
+    tiles of one cell merge the same core, and the candidate mask leaves
+    out pairs already joined.  One clump is a single velocity population;
+    the other holds two populations 10 units apart in velocity (ellv 2),
+    which must stay two groups; sparse participants and non-participants
+    around them.  Bit-exact against the oracle, with and without R."""
+    rng = np.random.default_rng(seed)
+    size = 1 << 21
+    n_c = 4000
+    ca = rng.normal(0.0, 600.0, (3, n_c)) + size * 0.3
+    cb = rng.normal(0.0, 600.0, (3, n_c)) + size * 0.6
+    sp = rng.uniform(0.25 * size, 0.65 * size, (3, 3000))
+    q = np.mod(np.rint(np.concatenate([ca, cb, sp], axis=1)), size).astype(np.uint32)
+    n = q.shape[1]
+    v = rng.normal(0.0, 1.0, (3, n))
+    v[0, n_c:n_c + n_c // 2] += 5.0
+    v[0, n_c + n_c // 2:2 * n_c] -= 5.0
+    v = v.astype(np.float32)
+    host_of = np.zeros(n, np.int32)
+    host_of[2 * n_c + 2000:] = -1  # some sparse particles outside every host
+    Pd = vr.Particles(dev_tensor(q.view(np.int32)), dev_tensor(v), None, 1.0, 1.0, 21)
+    Pr = ref.Particles(q, v, None, 1.0, 1.0, 21)
+    ellv = np.array([2.0])
+    ellxs = 500.0 / size
+    R = rng.uniform(0.0, 4.0, n).astype(np.float32)
+    for RR in (None, R):
+        exp = ref.fof6d(Pr, host_of, ellv, ellxs, RR, 2.0)
+        got = ctx.fof6d(Pd, dev_tensor(host_of), dev_tensor(ellv), ellxs, None if RR is None else dev_tensor(RR),
+                        2.0).cpu().numpy()
+        assert (got == exp).all()
+        if RR is None:
+            # every hosted particle takes part: clump a, and clump b's two
+            # velocity populations
+            ids, cnt = np.unique(exp[exp >= 0], return_counts=True)
+            assert (cnt > 1000).sum() >= 3
