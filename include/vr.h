@@ -19,6 +19,12 @@
  *    by max_workspace_bytes (VR_ERR_OUT_OF_MEMORY when exceeded).
  *  - A context serves one stream at a time and is not thread-safe; several
  *    contexts may coexist.
+ *  - The KD builds of vr_cell_moments and vr_local_vdensity start from the
+ *    host members sorted along each axis.  A context keeps the sorted lists
+ *    of its last build and reuses them when the next build's members, hosts
+ *    and (unwrapped) coordinates have the same 64-bit content hash; the
+ *    lists take 12 bytes per member of workspace, and are simply not kept
+ *    where the workspace cap leaves no room for them.
  */
 #ifndef VR_H
 #define VR_H

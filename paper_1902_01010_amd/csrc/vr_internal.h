@@ -47,6 +47,13 @@ struct vr_ctx {
     int xcd_chunk = 64;     // consecutive workgroups per XCD in the neighbour sweeps (0 = hardware order)
     // while timing: candidate distances of the neighbour search (device counter)
     unsigned long long* knn_cand = nullptr;
+    // the presorted member lists of the last KD build (workspace slot
+    // WS_KD_PRE), kept for the next build over the same members: their
+    // content hash, sizes and storage
+    unsigned long long kd_pre_hash = 0;
+    int64_t kd_pre_m = -1;
+    int kd_pre_bits = 0;
+    void* kd_pre_ptr = nullptr;
     // graph of the persistent unbinding passes, reused while its arguments match
     void* cap_stream = nullptr;
     void* ub_graph = nullptr;
@@ -65,7 +72,7 @@ enum Slot {
     WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7, WS_B8, WS_B9,
     WS_C0, WS_C1, WS_C2, WS_C3, WS_C4, WS_C5, WS_C6, WS_C7, WS_C8, WS_C9,
     WS_D0, WS_D1, WS_D2, WS_D3, WS_D4, WS_D5, WS_D6, WS_D7, WS_D8, WS_D9,
-    WS_FLAG, WS_FLAG2, WS_KD, WS_KD_HIST, WS_KD_S,
+    WS_FLAG, WS_FLAG2, WS_KD, WS_KD_HIST, WS_KD_S, WS_KD_PRE,
     WS_NSLOTS
 };
 

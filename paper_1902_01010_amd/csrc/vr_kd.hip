@@ -27,29 +27,56 @@ namespace {
 constexpr int KB = 256;
 constexpr int HCH = 2048;  // positions per histogram block
 
-// Element arrays by element id, and the sort keys of the presort.
+// One element's share of the content hash of a build's inputs: a 64-bit
+// mix of its position, member, unwrapped coordinates and host.  The shares
+// are summed, so the hash covers every element whatever the order of the
+// additions.
+__device__ __forceinline__ unsigned long long elem_hash(int64_t e, int i, int a, int b, int c, int h) {
+    uint64_t x = (uint64_t)e * 0x9E3779B97F4A7C15ull;
+    x ^= (uint64_t)(uint32_t)i * 0xC2B2AE3D27D4EB4Full;
+    x ^= (((uint64_t)(uint32_t)a << 32) | (uint32_t)b) * 0x165667B19E3779F9ull;
+    x ^= (((uint64_t)(uint32_t)c << 32) | (uint32_t)h) * 0x27D4EB2F165667C5ull;
+    x ^= x >> 31;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 29;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 32;
+    return (unsigned long long)x;
+}
+
+// Element arrays by element id, and the sort keys of the presort; *hash
+// (zeroed beforehand) receives the content hash of (member, coordinates,
+// host) over all elements.
 __global__ void k_elems(int64_t M, int n_hosts, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
                         const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                         const uint32_t* __restrict__ qz, const float* __restrict__ mass, int gb, int* __restrict__ u0,
                         int* __restrict__ u1, int* __restrict__ u2, int* __restrict__ g, float* __restrict__ m,
-                        int* __restrict__ host) {
+                        int* __restrict__ host, unsigned long long* __restrict__ hash) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= M) return;
-    int lo = 0, hi = n_hosts - 1;  // host with off[h] <= e < off[h+1]
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= e) lo = mid; else hi = mid - 1;
+    unsigned long long hv = 0;
+    if (e < M) {
+        int lo = 0, hi = n_hosts - 1;  // host with off[h] <= e < off[h+1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const int h = lo;
+        const int r = mem[off[h]];
+        const int i = mem[e];
+        const int rx = (int)qx[r], ry = (int)qy[r], rz = (int)qz[r];
+        const int a = rx + min_image((int)qx[i] - rx, gb), b = ry + min_image((int)qy[i] - ry, gb),
+                  c = rz + min_image((int)qz[i] - rz, gb);
+        u0[e] = a;
+        u1[e] = b;
+        u2[e] = c;
+        g[e] = i;
+        host[e] = h;
+        if (mass) m[e] = mass[i];
+        hv = elem_hash(e, i, a, b, c, h);
     }
-    const int h = lo;
-    const int r = mem[off[h]];
-    const int i = mem[e];
-    const int rx = (int)qx[r], ry = (int)qy[r], rz = (int)qz[r];
-    u0[e] = rx + min_image((int)qx[i] - rx, gb);
-    u1[e] = ry + min_image((int)qy[i] - ry, gb);
-    u2[e] = rz + min_image((int)qz[i] - rz, gb);
-    g[e] = i;
-    host[e] = h;
-    if (mass) m[e] = mass[i];
+    // every lane of the wavefront reaches the sum
+    for (int o = 32; o > 0; o >>= 1) hv += (unsigned long long)__shfl_xor((long long)hv, o, 64);
+    if ((threadIdx.x & 63) == 0 && hv) atomicAdd(hash, hv);
 }
 
 __global__ void k_presort_keys(int64_t M, const int* __restrict__ u, const int* __restrict__ host,
@@ -493,6 +520,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     uint8_t* lf8;
     uint32_t* lf;
     uint64_t* pkey;
+    unsigned long long* hsh;
     KdNode* nodes;
     Elems F;
     auto layout = [&]() {
@@ -520,6 +548,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         F.mass = cv.add<float>(use_mass ? M : 1);
         ncell_d = cv.add<int>(n_hosts);
         counters = cv.add<int>(8);
+        hsh = cv.add<unsigned long long>(1);
     };
     layout();
     const size_t total = cv.bytes;
@@ -534,15 +563,50 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     for (int k = 0; k < 8; ++k) init[k] = 0;
     init[3] = n_hosts;
     VR_HIP(ctx, hipMemcpyAsync(counters, init, 8 * sizeof(int), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_elems, dim3(grid_for(M, 256)), dim3(256), 0, st, M, n_hosts, host_offsets, host_members,
-                       p->qx, p->qy, p->qz, p->mass, p->grid_bits, U[0], U[1], U[2], G, Ms, H);
-    VR_LAUNCH_CHECK(ctx);
-    for (int d = 0; d < 3; ++d) {
-        hipLaunchKernelGGL(k_presort_keys, dim3(grid_for(M, 256)), dim3(256), 0, st, M, U[d], H, pkey,
-                           reinterpret_cast<uint32_t*>(L[d]));
-        VR_LAUNCH_CHECK(ctx);
-        int rc = sort_pairs_u64(ctx, pkey, reinterpret_cast<uint32_t*>(L[d]), M, 22 + hb, st);
+    {
+        int rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hsh), 0u, 2, st);
         if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_elems, dim3(grid_for(M, 256)), dim3(256), 0, st, M, n_hosts, host_offsets, host_members,
+                       p->qx, p->qy, p->qz, p->mass, p->grid_bits, U[0], U[1], U[2], G, Ms, H, hsh);
+    VR_LAUNCH_CHECK(ctx);
+    // The three lists sorted by (host, u_d, element) depend only on the
+    // elements' members, unwrapped coordinates and hosts.  The context keeps
+    // the last build's lists and reuses them when this build's content hash,
+    // size and key width match (the entropy cells and the neighbour tree of
+    // one search are built over the same members); without room for them
+    // under the workspace cap it simply sorts.
+    {
+        unsigned long long h64 = 0;
+        int rc = read_back(ctx, hsh, &h64, sizeof h64, st);
+        if (rc) return rc;
+        const int bits = 22 + hb;
+        const std::string err_before = ctx->err;
+        int* pre = static_cast<int*>(ws(ctx, WS_KD_PRE, 3 * (size_t)M * sizeof(int)));
+        if (!pre) ctx->err = err_before;  // no room for the kept lists: not an error
+        const bool hit = pre && ctx->kd_pre_ptr == pre && ctx->kd_pre_m == M && ctx->kd_pre_bits == bits &&
+                         ctx->kd_pre_hash == h64;
+        if (hit) {
+            for (int d = 0; d < 3; ++d)
+                VR_HIP(ctx, hipMemcpyAsync(L[d], pre + d * M, (size_t)M * sizeof(int), hipMemcpyDeviceToDevice, st));
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                hipLaunchKernelGGL(k_presort_keys, dim3(grid_for(M, 256)), dim3(256), 0, st, M, U[d], H, pkey,
+                                   reinterpret_cast<uint32_t*>(L[d]));
+                VR_LAUNCH_CHECK(ctx);
+                if ((rc = sort_pairs_u64(ctx, pkey, reinterpret_cast<uint32_t*>(L[d]), M, bits, st))) return rc;
+            }
+            ctx->kd_pre_m = -1;
+            if (pre) {
+                for (int d = 0; d < 3; ++d)
+                    VR_HIP(ctx, hipMemcpyAsync(pre + d * M, L[d], (size_t)M * sizeof(int), hipMemcpyDeviceToDevice,
+                                               st));
+                ctx->kd_pre_ptr = pre;
+                ctx->kd_pre_m = M;
+                ctx->kd_pre_bits = bits;
+                ctx->kd_pre_hash = h64;
+            }
+        }
     }
     if (mode != KD_WIDEST) {
         hipLaunchKernelGGL(k_coords_l0, dim3(grid_for(M, 256)), dim3(256), 0, st, M, L[0], U[0], U[1], U[2], C0[0],

@@ -423,3 +423,37 @@ def test_fof6d_dense_cells_bit_exact(ctx, vr, ref, seed):
             # velocity populations
             ids, cnt = np.unique(exp[exp >= 0], return_counts=True)
             assert (cnt > 1000).sum() >= 3
+
+
+def test_presort_reuse_follows_content(ctx, vr, ref):
+    """The context reuses the sorted member lists of its last KD build only
+    for the same content: R over the same tensors after their coordinates
+    changed in place still matches the oracle on the changed inputs, and so
+    does R after one member was swapped for another particle (same count,
+    other content)."""
+    w = synth.isolated_halo(seed=7, n_host=6000, n_sub=2, sub_range=(400, 800))
+    P, Pr = both(ctx, vr, ref, w)
+    lab = ref.fof3d(Pr, w.params["ellx"])
+    _, _, off, mem = ref.groups(lab, 20)
+    hoff, hmem = off[:2].copy(), mem[:off[1]].copy()
+    dh, dm = dev_tensor(hoff), dev_tensor(hmem)
+    for step in range(3):
+        gm = ctx.cell_moments(P, dh, dm)
+        got = ctx.local_vdensity(P, dh, dm, gm["vbar"], gm["sigma"], 32, 8).cpu().numpy()
+        cm = ref.cell_moments(Pr, hoff, hmem)
+        exp = ref.local_vdensity(Pr, hoff, hmem, cm["vbar"], cm["sigma"], 32, 8)["R"]
+        _R_close(got, exp)
+        if step == 0:
+            # move some members by a few grid units, in place
+            q = Pr.q.copy()
+            idx = hmem[::7]
+            q[0, idx] = (q[0, idx] + 3) % (1 << w.grid_bits)
+            Pr = ref.Particles(q, w.v, w.mass, w.mass_value, w.box, w.grid_bits)
+            P.q.copy_(dev_tensor(q.view(np.int32)))
+        elif step == 1:
+            # as many members, one of them another particle
+            outside = np.setdiff1d(np.arange(P.n, dtype=np.int32), hmem)
+            hmem = hmem.copy()
+            hmem[len(hmem) // 2] = outside[len(outside) // 2]
+            hmem.sort()
+            dm.copy_(dev_tensor(hmem))
