@@ -66,7 +66,10 @@ def sources_sha256(files):
     return h.hexdigest()
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, knobs=None):
+    """HBM bytes per launch of `kernel` from its committed counter summary,
+    or None when its sources or launch knobs differ from those it was taken
+    with."""
     path = TRAFFIC_PROFILES.get(kernel)
     if not path or not os.path.exists(os.path.join(ROOT, path)):
         return None
@@ -80,6 +83,10 @@ def profiled_traffic(kernel):
         files = kv["sources"].split()
         if sources_sha256(files) != kv["sources_sha256"]:
             return None
+        for item in kv.get("launch_knobs", "").split():
+            k, v = item.split("=")
+            if knobs is not None and int(knobs.get(k, -1)) != int(v):
+                return None
         return float(kv["hbm_bytes_per_dispatch"])
     except (KeyError, ValueError, OSError):
         return None
@@ -405,7 +412,7 @@ def main():
                "kernels": kernels_s}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     d = kernels[dom]
-    traffic = profiled_traffic(dom)
+    traffic = profiled_traffic(dom, knobs)
     roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
                 "frac": round(d["frac"], 5), "traffic": traffic, "kernel": dom}
     if "candidates_per_s" in d:

@@ -92,9 +92,11 @@ int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value);
  * are applied and nothing is timed.  Otherwise the call times vr_unbind
  * (persistent) over unbind_tile x unbind_jchunk x unbind_bpc on a synthetic
  * heavy-tailed group set (sizes 32 .. 32768) and vr_local_vdensity over
- * knn_leaf x xcd_chunk on synthetic hosts, applies the fastest settings and
- * writes them, with every timing, to cache_path as JSON.  Allocates its
- * workloads (freed before return); takes a few seconds; syncs. */
+ * knn_leaf x xcd_chunk on synthetic hosts (2000 cusped halos whose sizes
+ * follow dN/dlnN ~ N^-0.9 on [256, 2^21], 6.6 M members), applies the
+ * fastest settings and writes them, with every timing, to cache_path as
+ * JSON.  Allocates its workloads (freed before return); takes a few
+ * seconds; syncs. */
 int vr_autotune(vr_ctx* ctx, const char* cache_path, int force);
 int vr_kernel_time(vr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms,
                    double* work);

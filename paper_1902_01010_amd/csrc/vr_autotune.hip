@@ -60,6 +60,42 @@ __global__ void k_at_blobs(int ng, const int32_t* __restrict__ off, int gb, doub
     }
 }
 
+// Particles of host g (members off[g] .. off[g+1]-1, contiguous) as a
+// cusped halo: a Hernquist profile (density ~ r^-1 inside the scale radius,
+// like NFW) with scale a = r200 / 10, cut at r200, around a random centre.
+// r200 is that of N particles at 200 times the critical density when the
+// mean spacing is sp grid units (matter density 0.3 critical); velocities
+// Gaussian with dispersion 300 (N / 1e5)^(1/3).
+__global__ void k_at_halos(int ng, const int32_t* __restrict__ off, int gb, double sp, uint64_t seed,
+                           uint32_t* __restrict__ qx, uint32_t* __restrict__ qy, uint32_t* __restrict__ qz,
+                           float* __restrict__ vx, float* __restrict__ vy, float* __restrict__ vz,
+                           int32_t* __restrict__ mem) {
+    const int g = blockIdx.x;
+    if (g >= ng) return;
+    const int s = off[g], e = off[g + 1];
+    const double size = (double)(1u << gb), nh = (double)(e - s);
+    const double cx = unif(seed, g, 0) * size, cy = unif(seed, g, 1) * size, cz = unif(seed, g, 2) * size;
+    const double r200 = sp * cbrt(nh * 0.3 * 3.0 / (4.0 * 3.141592653589793 * 200.0));
+    const double a = 0.1 * r200, smax = 10.0 / 11.0;
+    const double sig = 300.0 * cbrt(nh / 1e5);
+    const uint32_t mask = (1u << gb) - 1u;
+    for (int i = s + threadIdx.x; i < e; i += blockDim.x) {
+        const uint64_t k = (uint64_t)i + 1000003ull * (uint64_t)g;
+        // enclosed-mass fraction u -> radius: (r / (r + a))^2 = u (r200 / (r200 + a))^2
+        const double t = sqrt(unif(seed + 1, k, 0)) * smax, r = a * t / (1.0 - t);
+        const double cth = 2.0 * unif(seed + 1, k, 1) - 1.0, ph = 6.283185307179586 * unif(seed + 1, k, 2);
+        const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+        const double x = cx + r * sth * cos(ph), y = cy + r * sth * sin(ph), z = cz + r * cth;
+        qx[i] = (uint32_t)(int64_t)floor(x) & mask;
+        qy[i] = (uint32_t)(int64_t)floor(y) & mask;
+        qz[i] = (uint32_t)(int64_t)floor(z) & mask;
+        vx[i] = (float)(sig * gauss(seed + 2, k, 0));
+        vy[i] = (float)(sig * gauss(seed + 2, k, 1));
+        vz[i] = (float)(sig * gauss(seed + 2, k, 2));
+        mem[i] = i;
+    }
+}
+
 struct Knobs {
     int unbind_tile = 256, unbind_jchunk = 4096, unbind_bpc = 0, knn_leaf = 64, xcd_chunk = 64;
 };
@@ -210,11 +246,21 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
             }
     apply(ctx, best);
 
-    // ---- neighbour search: 48 hosts of 16384 members -------------------------
-    const int nh = 48, hs = 16384;
-    const int64_t nk = (int64_t)nh * hs;
+    // ---- neighbour search: 2000 hosts, dN/dlnN ~ N^-0.9 on [256, 2^21] -----
+    // Sizes at the mid-quantiles of that distribution (6.6 M members, largest
+    // 1.07 M): the searched hosts of a 256^3 box, whose largest hosts set the
+    // best leaf size.
+    const int nh = 2000;
     std::vector<int32_t> hoff(nh + 1);
-    for (int h = 0; h <= nh; ++h) hoff[h] = h * hs;
+    hoff[0] = 0;
+    {
+        const double sl = 0.9, lo = std::pow(256.0, -sl), hi = std::pow(2097152.0, -sl);
+        for (int h = 0; h < nh; ++h) {
+            const double q = (h + 0.5) / nh;
+            hoff[h + 1] = hoff[h] + (int32_t)std::floor(std::pow(lo - q * (lo - hi), -1.0 / sl));
+        }
+    }
+    const int64_t nk = hoff[nh];
     uint32_t *kx = mem.get<uint32_t>(nk), *ky = mem.get<uint32_t>(nk), *kz = mem.get<uint32_t>(nk);
     float *kvx = mem.get<float>(nk), *kvy = mem.get<float>(nk), *kvz = mem.get<float>(nk);
     int32_t *kmem = mem.get<int32_t>(nk), *khoff = mem.get<int32_t>(nh + 1), *cof = mem.get<int32_t>(nk);
@@ -225,8 +271,8 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
         return set_err(ctx, VR_ERR_OUT_OF_MEMORY, "autotune workload allocation failed");
     }
     VR_HIP(ctx, hipMemcpyAsync(khoff, hoff.data(), hoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_at_blobs, dim3(nh), dim3(256), 0, st, nh, khoff, gb, 4000.0, 100.0, (uint64_t)91, kx, ky, kz,
-                       kvx, kvy, kvz, kmem);
+    hipLaunchKernelGGL(k_at_halos, dim3(nh), dim3(256), 0, st, nh, khoff, gb, (double)(1u << gb) / 256.0,
+                       (uint64_t)91, kx, ky, kz, kvx, kvy, kvz, kmem);
     VR_LAUNCH_CHECK(ctx);
     vr_particles K{};
     K.n = nk;
@@ -242,7 +288,7 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
     if (rc) { ctx->timing = saved_timing; return rc; }
     float best_knn = 1e30f;
     std::ostringstream klog;
-    const int leaves[] = {32, 48, 64, 96, 128};
+    const int leaves[] = {64, 96, 128, 192, 256};
     const int xchunks[] = {0, 16, 64, 256};
     for (int L : leaves)
         for (int X : xchunks) {
@@ -279,7 +325,8 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
           << ",\n  \"unbind_bpc\": " << best.unbind_bpc << ",\n  \"knn_leaf\": " << best.knn_leaf
           << ",\n  \"xcd_chunk\": " << best.xcd_chunk << ",\n"
           << "  \"unbind_workload\": \"" << ng << " groups, " << nu << " particles, sizes 32..32768\",\n"
-          << "  \"knn_workload\": \"" << nh << " hosts of " << hs << " members, n_se 32, n_v 8\",\n"
+          << "  \"knn_workload\": \"" << nh << " Hernquist hosts, dN/dlnN ~ N^-0.9 on [256, 2^21], " << nk
+          << " members, n_se 32, n_v 8\",\n"
           << "  \"unbind_sweep\": [\n" << a << "  ],\n  \"knn_sweep\": [\n" << b << "  ]\n}\n";
     }
     return VR_OK;

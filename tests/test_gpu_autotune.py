@@ -21,7 +21,7 @@ def test_autotune_sweep_cache_and_parity(tmp_path, ref):
     for k in vr.TUNE_KNOBS:
         assert data[k] == knobs[k]
     assert knobs["unbind_tile"] in (64, 128, 256, 512, 1024)
-    assert knobs["knn_leaf"] in (32, 48, 64, 96, 128)
+    assert knobs["knn_leaf"] in (64, 96, 128, 192, 256)
     assert len(data["unbind_sweep"]) == 60 and len(data["knn_sweep"]) == 20
     best = min(data["unbind_sweep"], key=lambda r: r["ms"])
     assert (best["tile"], best["jchunk"], best["bpc"]) == (knobs["unbind_tile"], knobs["unbind_jchunk"],
