@@ -57,6 +57,12 @@ const char* vr_last_error(const vr_ctx* ctx);
 int vr_sync(vr_ctx* ctx, void* stream);
 /* Bytes of workspace currently held by the context. */
 size_t vr_workspace_bytes(const vr_ctx* ctx);
+/* Start of a new particle set: drops what the context carries from one call
+ * to the next for the same particles (the sorted member lists kept from the
+ * last KD build), so the next KD build sorts afresh.  Calls between two
+ * vr_new_snapshot calls may still share those lists when their content
+ * hashes match.  Host-only; never fails on a valid ctx. */
+int vr_new_snapshot(vr_ctx* ctx);
 
 /* Kernel timing, for measurement.  While enabled, the library brackets its
  * main kernels with HIP events recorded on the stream each kernel is

@@ -190,6 +190,12 @@ int vr_sync(vr_ctx* ctx, void* stream) {
 
 size_t vr_workspace_bytes(const vr_ctx* ctx) { return ctx ? ctx->held : 0; }
 
+int vr_new_snapshot(vr_ctx* ctx) {
+    if (!ctx) return VR_ERR_INVALID_ARG;
+    ctx->kd_pre_m = -1;  // the next KD build sorts its members afresh
+    return VR_OK;
+}
+
 int vr_set_timing(vr_ctx* ctx, int enabled) {
     if (!ctx) return VR_ERR_INVALID_ARG;
     VR_HIP(ctx, hipSetDevice(ctx->device));

@@ -269,10 +269,13 @@ int build_cell_list(vr_ctx* ctx, int64_t n, const uint32_t* qx, const uint32_t* 
     VR_WS(sz, ctx, uint32_t, WS_A4, n);
     VR_WS(flag, ctx, uint32_t, WS_A5, n);
     VR_WS(cstart, ctx, uint32_t, WS_A6, n + 1);
-    hipLaunchKernelGGL(k_cellkey, dim3(grid_for(n, 256)), dim3(256), 0, st, n, qx, qy, qz, s, b, key, idx);
-    VR_LAUNCH_CHECK(ctx);
-    int rc = sort_pairs_u64(ctx, key, idx, n, 3 * b, st);
+    ckey_t* kin;
+    uint32_t* iin;
+    int rc = sort_input_u64(ctx, key, idx, n, 3 * b, &kin, &iin);
     if (rc) return rc;
+    hipLaunchKernelGGL(k_cellkey, dim3(grid_for(n, 256)), dim3(256), 0, st, n, qx, qy, qz, s, b, kin, iin);
+    VR_LAUNCH_CHECK(ctx);
+    if ((rc = sort_pairs_u64_from(ctx, kin, iin, key, idx, n, 3 * b, st))) return rc;
     hipLaunchKernelGGL(k_gather3, dim3(grid_for(n, 256)), dim3(256), 0, st, n, idx, qx, qy, qz, sx, sy, sz);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_cell_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, flag);

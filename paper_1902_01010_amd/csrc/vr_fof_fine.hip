@@ -462,10 +462,13 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     VR_WS(mn, ctx, int, WS_B1, n);
     VR_WS(tot, ctx, uint32_t, WS_FLAG, 4);
     const unsigned gn = grid_for(n, 256);
-    hipLaunchKernelGGL(k_finekey, dim3(gn), dim3(256), 0, st, n, p->qx, p->qy, p->qz, G, key, idx);
-    VR_LAUNCH_CHECK(ctx);
-    int rc = sort_pairs_u64(ctx, key, idx, n, key_bits, st);
+    uint64_t* kin;
+    uint32_t* iin;
+    int rc = sort_input_u64(ctx, key, idx, n, key_bits, &kin, &iin);
     if (rc) return rc;
+    hipLaunchKernelGGL(k_finekey, dim3(gn), dim3(256), 0, st, n, p->qx, p->qy, p->qz, G, kin, iin);
+    VR_LAUNCH_CHECK(ctx);
+    if ((rc = sort_pairs_u64_from(ctx, kin, iin, key, idx, n, key_bits, st))) return rc;
     hipLaunchKernelGGL(k_gather_q, dim3(gn), dim3(256), 0, st, n, idx, p->qx, p->qy, p->qz, sx, sy, sz);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_key_flags, dim3(gn), dim3(256), 0, st, n, key, scan);

@@ -591,10 +591,13 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
                 VR_HIP(ctx, hipMemcpyAsync(L[d], pre + d * M, (size_t)M * sizeof(int), hipMemcpyDeviceToDevice, st));
         } else {
             for (int d = 0; d < 3; ++d) {
-                hipLaunchKernelGGL(k_presort_keys, dim3(grid_for(M, 256)), dim3(256), 0, st, M, U[d], H, pkey,
-                                   reinterpret_cast<uint32_t*>(L[d]));
+                uint32_t* ld = reinterpret_cast<uint32_t*>(L[d]);
+                uint64_t* kin;
+                uint32_t* vin;
+                if ((rc = sort_input_u64(ctx, pkey, ld, M, bits, &kin, &vin))) return rc;
+                hipLaunchKernelGGL(k_presort_keys, dim3(grid_for(M, 256)), dim3(256), 0, st, M, U[d], H, kin, vin);
                 VR_LAUNCH_CHECK(ctx);
-                if ((rc = sort_pairs_u64(ctx, pkey, reinterpret_cast<uint32_t*>(L[d]), M, bits, st))) return rc;
+                if ((rc = sort_pairs_u64_from(ctx, kin, vin, pkey, ld, M, bits, st))) return rc;
             }
             ctx->kd_pre_m = -1;
             if (pre) {

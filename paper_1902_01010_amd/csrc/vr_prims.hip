@@ -272,14 +272,38 @@ __global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict_
 }
 
 template <class K>
-int sort_pairs_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
-    if (n <= 1 || bits <= 0) return VR_OK;
+int sort_input_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, K** kin, uint32_t** vin) {
+    *kin = keys;
+    *vin = vals;
+    if (n <= 1 || bits <= 0 || ((bits + 7) / 8) % 2 == 0) return VR_OK;
+    VR_WS(kalt, ctx, K, WS_SORT_KEYS_B, n);
+    VR_WS(valt, ctx, uint32_t, WS_SORT_VALS_B, n);
+    *kin = kalt;
+    *vin = valt;
+    return VR_OK;
+}
+
+// Input pairs in (kin, vin), which is either (keys, vals) or the alternate
+// buffers; passes ping-pong between the two pairs, and the result is copied
+// into (keys, vals) only where it ends in the other one.
+template <class K>
+int sort_pairs_impl(vr_ctx* ctx, K* kin, uint32_t* vin, K* keys, uint32_t* vals, int64_t n, int bits,
+                    hipStream_t s) {
+    if (n <= 1 || bits <= 0) {
+        if (n == 1 && kin != keys) {
+            VR_HIP(ctx, hipMemcpyAsync(keys, kin, sizeof(K), hipMemcpyDeviceToDevice, s));
+            VR_HIP(ctx, hipMemcpyAsync(vals, vin, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        }
+        return VR_OK;
+    }
     const int num_tiles = (int)((n + RS_TILE - 1) / RS_TILE);
     VR_WS(kalt, ctx, K, WS_SORT_KEYS_B, n);
     VR_WS(valt, ctx, uint32_t, WS_SORT_VALS_B, n);
     VR_WS(hist, ctx, uint32_t, WS_SORT_HIST, (int64_t)RS_RADIX * num_tiles);
-    K* k0 = keys; K* k1 = kalt;
-    uint32_t* v0 = vals; uint32_t* v1 = valt;
+    if (kin != keys && (kin != kalt || vin != valt))
+        return set_err(ctx, VR_ERR_INVALID_ARG, "sort input is neither the output nor the alternate buffers");
+    K* k0 = kin; K* k1 = kin == keys ? kalt : keys;
+    uint32_t* v0 = vin; uint32_t* v1 = vin == vals ? valt : vals;
     const int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * 8;
@@ -359,11 +383,21 @@ int scan_u8(vr_ctx* ctx, const uint8_t* in, uint32_t* out, int64_t n, hipStream_
 }
 
 int sort_pairs_u32(vr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
-    return sort_pairs_impl<uint32_t>(ctx, keys, vals, n, bits, s);
+    return sort_pairs_impl<uint32_t>(ctx, keys, vals, keys, vals, n, bits, s);
 }
 
 int sort_pairs_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
-    return sort_pairs_impl<uint64_t>(ctx, keys, vals, n, bits, s);
+    return sort_pairs_impl<uint64_t>(ctx, keys, vals, keys, vals, n, bits, s);
+}
+
+int sort_input_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, uint64_t** kin,
+                   uint32_t** vin) {
+    return sort_input_impl<uint64_t>(ctx, keys, vals, n, bits, kin, vin);
+}
+
+int sort_pairs_u64_from(vr_ctx* ctx, uint64_t* kin, uint32_t* vin, uint64_t* keys, uint32_t* vals, int64_t n,
+                        int bits, hipStream_t s) {
+    return sort_pairs_impl<uint64_t>(ctx, kin, vin, keys, vals, n, bits, s);
 }
 
 int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s) {

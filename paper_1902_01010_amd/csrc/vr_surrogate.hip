@@ -774,10 +774,13 @@ int vr_rs_features(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const in
         VR_WS(rws, ctx, uint32_t, WS_A1 + 4 * L, m);
         VR_WS(flag, ctx, uint32_t, WS_A2 + 4 * L, m);
         VR_WS(cid, ctx, uint32_t, WS_A3 + 4 * L, m);
+        uint64_t* kin;
+        uint32_t* rin;
+        if ((rc = sort_input_u64(ctx, keys, rws, m, 3 * b, &kin, &rin))) return rc;
         hipLaunchKernelGGL(k_rs_keys, dim3(grid_for(m, 256)), dim3(256), 0, st, m, host_members, p->qx, p->qy, p->qz,
-                           cb[L], b, keys, rws);
+                           cb[L], b, kin, rin);
         VR_LAUNCH_CHECK(ctx);
-        if ((rc = sort_pairs_u64(ctx, keys, rws, m, 3 * b, st))) return rc;
+        if ((rc = sort_pairs_u64_from(ctx, kin, rin, keys, rws, m, 3 * b, st))) return rc;
         hipLaunchKernelGGL(k_rs_heads, dim3(grid_for(m, 256)), dim3(256), 0, st, m, keys, flag);
         VR_LAUNCH_CHECK(ctx);
         uint32_t* tot = reinterpret_cast<uint32_t*>(ctx->pinned);

@@ -111,6 +111,7 @@ def run(ctx: _vr.Context, x, v, mass, mass_value, box, grid_bits, prm: Params, s
             e.record()
             ev.append((name, e))
 
+    ctx.new_snapshot()
     mark("start")
     q = ctx.quantize(x, box, grid_bits)
     P = _vr.Particles(q, v, mass, mass_value, box, grid_bits)

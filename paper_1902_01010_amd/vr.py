@@ -22,7 +22,7 @@ NOALLOC_MAX_LABELS = 4194304
 
 # Entry points declared in include/vr.h (checked by the CPU test-suite).
 ENTRY_POINTS = (
-    "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes",
+    "vr_create", "vr_destroy", "vr_last_error", "vr_sync", "vr_workspace_bytes", "vr_new_snapshot",
     "vr_set_timing", "vr_kernel_time", "vr_tune", "vr_get_tune", "vr_autotune",
     "vr_quantize", "vr_fof3d", "vr_groups", "vr_cell_moments", "vr_local_vdensity",
     "vr_host_ellv", "vr_fof6d", "vr_fof_sub", "vr_sub_grow", "vr_fof3d_dm", "vr_assign_baryons",
@@ -93,6 +93,7 @@ def load_library():
         L.vr_last_error.restype = C.c_char_p
         L.vr_sync.argtypes = [vp, vp]
         L.vr_workspace_bytes.argtypes = [vp]
+        L.vr_new_snapshot.argtypes = [vp]
         L.vr_workspace_bytes.restype = sz
         L.vr_set_timing.argtypes = [vp, C.c_int]
         L.vr_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]
@@ -224,6 +225,10 @@ class Context:
 
     def sync(self):
         self._check(self.lib.vr_sync(self.h, _stream()))
+
+    def new_snapshot(self):
+        """Forget state kept from calls on the previous particle set."""
+        self._check(self.lib.vr_new_snapshot(self.h))
 
     def workspace_bytes(self):
         return int(self.lib.vr_workspace_bytes(self.h))

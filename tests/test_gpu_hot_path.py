@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from paper_1902_01010_amd import synth
-from tests.gpu_common import both, dev_tensor
+from tests.gpu_common import both, dev_tensor, gpu_particles
 
 pytestmark = pytest.mark.gpu
 
@@ -423,6 +423,31 @@ def test_fof6d_dense_cells_bit_exact(ctx, vr, ref, seed):
             # velocity populations
             ids, cnt = np.unique(exp[exp >= 0], return_counts=True)
             assert (cnt > 1000).sum() >= 3
+
+
+def test_new_snapshot_drops_kept_sorts(vr):
+    """Two builds over the same content share one set of sorted lists; after
+    vr_new_snapshot the next build sorts again (counted in radix passes)."""
+    c = vr.Context(0)
+    w = synth.isolated_halo(seed=5, n_host=5000, n_sub=1, sub_range=(400, 500))
+    P = gpu_particles(vr, c.quantize(dev_tensor(w.x), w.box, w.grid_bits), w)
+    dh = dev_tensor(np.array([0, w.n], np.int32))
+    dm = dev_tensor(np.arange(w.n, dtype=np.int32))
+
+    def passes(fn):
+        c.set_timing(True)
+        fn()
+        c.sync()
+        n = c.kernel_time("radix_scatter")[0]
+        c.set_timing(False)
+        return n
+
+    first = passes(lambda: c.cell_moments(P, dh, dm))
+    again = passes(lambda: c.cell_moments(P, dh, dm))
+    c.new_snapshot()
+    fresh = passes(lambda: c.cell_moments(P, dh, dm))
+    assert first > 0 and fresh == first
+    assert again < first
 
 
 def test_presort_reuse_follows_content(ctx, vr, ref):
