@@ -23,6 +23,10 @@ struct FineGrid {
     int nc;   // coarse cells per side
 };
 
+// Sort key of particle i: its fine-cell key (coarse cell in row-major order,
+// then the fine cell inside it) above the particle's offsets inside its fine
+// cell (3 k bits), which the sort carries along without ordering by them.
+// With grid_bits <= 21 the whole key takes at most 63 bits.
 __global__ void k_finekey(int64_t n, const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                           const uint32_t* __restrict__ qz, FineGrid G, uint64_t* __restrict__ key,
                           uint32_t* __restrict__ idx) {
@@ -33,19 +37,34 @@ __global__ void k_finekey(int64_t n, const uint32_t* __restrict__ qx, const uint
     const uint32_t m = (uint32_t)G.r - 1;
     const uint64_t sub = ((uint64_t)((z >> G.k) & m) << (2 * G.lr)) | ((uint64_t)((y >> G.k) & m) << G.lr) |
                          (uint64_t)((x >> G.k) & m);
-    key[i] = (ck << (3 * G.lr)) | sub;
+    const uint32_t om = (1u << G.k) - 1u;
+    const uint64_t off = ((uint64_t)(z & om) << (2 * G.k)) | ((uint64_t)(y & om) << G.k) | (uint64_t)(x & om);
+    key[i] = (((ck << (3 * G.lr)) | sub) << (3 * G.k)) | off;
     idx[i] = (uint32_t)i;
 }
 
-__global__ void k_gather_q(int64_t n, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ qx,
-                           const uint32_t* __restrict__ qy, const uint32_t* __restrict__ qz, uint32_t* __restrict__ sx,
+// In place after the sort: the fine-cell key, and the coordinates rebuilt
+// from it and the carried offsets (sequential, where a gather through the
+// sorted order would fetch a cache line per coordinate).
+__global__ void k_decode_q(int64_t n, FineGrid G, uint64_t* __restrict__ key, uint32_t* __restrict__ sx,
                            uint32_t* __restrict__ sy, uint32_t* __restrict__ sz) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const uint32_t i = idx[p];
-    sx[p] = qx[i];
-    sy[p] = qy[i];
-    sz[p] = qz[i];
+    const uint64_t e = key[p];
+    const uint64_t kf = e >> (3 * G.k);
+    const uint32_t om = (1u << G.k) - 1u;
+    const uint32_t ox = (uint32_t)e & om, oy = (uint32_t)(e >> G.k) & om, oz = (uint32_t)(e >> (2 * G.k)) & om;
+    const int lr3 = 3 * G.lr;
+    const uint64_t ck = kf >> lr3;
+    const uint32_t sub = (uint32_t)(kf & ((1ull << lr3) - 1));
+    const uint32_t ncm = (uint32_t)G.nc - 1u, rm = (uint32_t)G.r - 1u;
+    const uint32_t fx = (uint32_t)(ck & ncm) * (uint32_t)G.r + (sub & rm);
+    const uint32_t fy = (uint32_t)((ck >> G.b) & ncm) * (uint32_t)G.r + ((sub >> G.lr) & rm);
+    const uint32_t fz = (uint32_t)(ck >> (2 * G.b)) * (uint32_t)G.r + (sub >> (2 * G.lr));
+    key[p] = kf;
+    sx[p] = (fx << G.k) | ox;
+    sy[p] = (fy << G.k) | oy;
+    sz[p] = (fz << G.k) | oz;
 }
 
 __global__ void k_key_flags(int64_t n, const uint64_t* __restrict__ key, uint32_t* __restrict__ flag) {
@@ -94,21 +113,42 @@ __global__ void k_rows(int64_t nrows, int64_t n, const uint64_t* __restrict__ ke
 constexpr uint32_t DENSE_CC = 48;
 constexpr int TILE_R = 4;  // fine cells per coarse side where the tiles apply (r^3 <= 64 lanes)
 
-__global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t* __restrict__ fine_start,
-                                                   const uint32_t* __restrict__ fid, const uint64_t* __restrict__ key,
+// Number of occupied coarse cells before coarse cell `cell` (row-major
+// index): the prefix count of its 256-cell block plus the occupancy bits
+// below `cell` in that block (eight words, two 16-byte loads).  Occupied
+// cells are numbered in sorted order, so this is also the coarse index of
+// `cell` when it is occupied.
+__device__ __forceinline__ uint32_t coarse_rank(const uint32_t* __restrict__ occ, const uint32_t* __restrict__ pre,
+                                                uint64_t cell) {
+    const uint64_t blk = cell >> 8;
+    const uint4* o = reinterpret_cast<const uint4*>(occ) + 2 * blk;
+    const uint4 lo = o[0], hi = o[1];
+    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    const uint32_t wi = (uint32_t)(cell >> 5) & 7u, bit = (uint32_t)cell & 31u;
+    uint32_t r = pre[blk];
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t m = j < wi ? ~0u : (j == wi ? (1u << bit) - 1u : 0u);
+        r += (uint32_t)__popc(w[j] & m);
+    }
+    return r;
+}
+
+// One thread per fine cell A of the sparse coarse cells.  frec[F] holds
+// fine cell F's key (two words), its first member and its end (bit 31 of
+// the end: F lies in a dense coarse cell).  The fine cells of a run of
+// coarse cells x0 .. x1 in one row are cfs[rank(x0)] .. cfs[rank(x1 + 1)] - 1.
+__global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint4* __restrict__ frec,
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
-                                                   const uint32_t* __restrict__ sz,
-                                                   const uint32_t* __restrict__ row_start, FineGrid G, double ell2,
-                                                   int* parent, unsigned xchunk, const uint32_t* __restrict__ cid,
-                                                   const uint32_t* __restrict__ cfs) {
+                                                   const uint32_t* __restrict__ sz, FineGrid G, double ell2,
+                                                   int* parent, unsigned xchunk, const uint32_t* __restrict__ cfs,
+                                                   const uint32_t* __restrict__ occ, const uint32_t* __restrict__ pre) {
     const int64_t A = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (A >= nfine) return;
-    if (cid) {
-        const uint32_t c = cid[A];
-        if (cfs[c + 1] - cfs[c] >= DENSE_CC) return;  // linked by k_link_tile3
-    }
-    const uint32_t a0 = fine_start[A], a1 = fine_start[A + 1];
-    const uint64_t ka = key[a0];
+    const uint4 fa = frec[A];
+    if (fa.w >> 31) return;  // dense coarse cell: linked by k_link_tile3
+    const uint32_t a0 = fa.z, a1 = fa.w;
+    const uint64_t ka = ((uint64_t)fa.y << 32) | fa.x;
     const int lr3 = 3 * G.lr;
     const int rm = G.r - 1, ncm = G.nc - 1;
     const uint64_t cka = ka >> lr3;
@@ -119,41 +159,71 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
     const int gaz = cz * G.r + (int)(suba >> (2 * G.lr));
     const int fbits = G.gb - G.k;  // fine cells per side = 2^fbits
     const int64_t f = int64_t(1) << G.k;
-    // the own row (x and x+1) and the four following rows (x-1 .. x+1)
-    const int rdz[5] = {0, 0, 1, 1, 1}, rdy[5] = {0, 1, -1, 0, 1};
+    // candidate runs of coarse cells [r_lo, r_hi): the own row (x .. x+1,
+    // from the fine cell after A) and the four following rows (x-1 .. x+1),
+    // two runs a row (the second empty unless the run wraps round the box).
+    // Every index is fixed at compile time, so the runs stay in registers,
+    // and all rank loads are issued before any is used.
+    constexpr int NRUN = 10;
+    uint64_t r_lo[NRUN], r_hi[NRUN];
+#pragma unroll
+    for (int rr = 0; rr < 5; ++rr) {
+        const int dz = rr >= 2 ? 1 : 0, dy = rr == 0 ? 0 : (rr == 1 ? 1 : rr - 3);
+        const uint64_t row = (uint64_t)((cz + dz) & ncm) * (uint64_t)G.nc + (uint64_t)((cy + dy) & ncm);
+        const uint64_t base = row * (uint64_t)G.nc;
+        const int xa = rr == 0 ? cx : cx - 1, xb = cx + 1;
+        if (xa < 0) {
+            r_lo[2 * rr] = base + ncm; r_hi[2 * rr] = base + ncm + 1;
+            r_lo[2 * rr + 1] = base; r_hi[2 * rr + 1] = base + xb + 1;
+        } else if (xb > ncm) {
+            r_lo[2 * rr] = base + xa; r_hi[2 * rr] = base + ncm + 1;
+            r_lo[2 * rr + 1] = base; r_hi[2 * rr + 1] = base + 1;
+        } else {
+            r_lo[2 * rr] = base + xa; r_hi[2 * rr] = base + xb + 1;
+            r_lo[2 * rr + 1] = 0; r_hi[2 * rr + 1] = 0;
+        }
+    }
+    uint32_t c_lo[NRUN], c_hi[NRUN];
+#pragma unroll
+    for (int u = 0; u < NRUN; ++u) {
+        c_lo[u] = c_hi[u] = 0;
+        if (r_lo[u] < r_hi[u]) {
+            c_lo[u] = coarse_rank(occ, pre, r_lo[u]);
+            c_hi[u] = coarse_rank(occ, pre, r_hi[u]);
+        }
+    }
+    uint32_t f_lo[NRUN], f_hi[NRUN];
+#pragma unroll
+    for (int u = 0; u < NRUN; ++u) {
+        f_lo[u] = f_hi[u] = 0;
+        if (c_lo[u] < c_hi[u]) {
+            f_lo[u] = cfs[c_lo[u]];
+            f_hi[u] = cfs[c_hi[u]];
+        }
+    }
     // A's root, refreshed only when B's differs: components only merge, so
     // roots once equal stay equal, and a stale root still lies on the path
     // to the current one
     int ra = uf_find(parent, (int)a0);
-    for (int rr = 0; rr < 5; ++rr) {
-        const int nz = (cz + rdz[rr]) & ncm, ny = (cy + rdy[rr]) & ncm;
-        const uint32_t row = (uint32_t)nz * (uint32_t)G.nc + (uint32_t)ny;
-        const uint32_t rs = row_start[row], re = row_start[row + 1];
-        if (rs == re) continue;
-        const int xa = rr == 0 ? cx : cx - 1, xb = cx + 1;
-        int px0[2], px1[2], np = 0;
-        if (xa < 0) { px0[np] = G.nc - 1; px1[np++] = G.nc - 1; px0[np] = 0; px1[np++] = xb; }
-        else if (xb > ncm) { px0[np] = xa; px1[np++] = ncm; px0[np] = 0; px1[np++] = 0; }
-        else { px0[np] = xa; px1[np++] = xb; }
-        for (int pc = 0; pc < np; ++pc) {
-            const uint64_t base = (uint64_t)row * (uint64_t)G.nc;
-            const uint32_t lo = lower_bound_u64(key, rs, re, (base + (uint64_t)px0[pc]) << lr3);
-            const uint32_t hi = lower_bound_u64(key, lo, re, (base + (uint64_t)px1[pc] + 1) << lr3);
-            if (lo >= hi) continue;
-            uint32_t fb0 = fid[lo];
-            const uint32_t fb1 = fid[hi - 1];
-            if (rr == 0 && px0[pc] == cx && fb0 <= (uint32_t)A) fb0 = (uint32_t)A + 1;  // own coarse cell: later cells
-            if (fb0 > fb1) continue;
-            // B's first member, key and parent, and the next cell's start are
-            // all loaded at the top of an iteration, with no load waiting for
-            // another: one memory round trip per candidate cell that the
-            // exact box bound or the parent test settles
-            uint32_t next_b0 = fine_start[fb0];
-            for (uint32_t B = fb0; B <= fb1; ++B) {
-                const uint32_t b0 = next_b0, b1 = fine_start[B + 1];
-                next_b0 = b1;
-                const uint64_t kb = key[b0];
-                const int pb = parent[b0];
+    for (int u = 0; u < NRUN; ++u) {
+        // run u's fine cells, picked by value so the arrays stay in registers
+        uint32_t B0 = 0, Bend = 0;
+#pragma unroll
+        for (int j = 0; j < NRUN; ++j)
+            if (u == j) { B0 = f_lo[j]; Bend = f_hi[j]; }
+        // the own coarse cell (in the own row's runs): only cells after A
+        if (B0 <= (uint32_t)A && (uint32_t)A < Bend) B0 = (uint32_t)A + 1;
+        for (; B0 < Bend; B0 += 4) {
+            // four candidate records per round trip; the exact box bound
+            // settles most of them without touching their members
+            uint4 fr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (B0 + j < Bend) fr[j] = frec[B0 + j];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (B0 + j >= Bend) break;
+                const uint64_t kb = ((uint64_t)fr[j].y << 32) | fr[j].x;
                 const uint64_t ckb = kb >> lr3;
                 const uint32_t subb = (uint32_t)(kb & ((1ull << lr3) - 1));
                 const int gbx = (int)(ckb & ncm) * G.r + (int)(subb & rm);
@@ -167,6 +237,8 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
                               lz = gz ? (gz - 1) * f + 1 : 0;
                 const double dmin = (double)(lx * lx + ly * ly + lz * lz);
                 if (dmin >= ell2) continue;
+                const uint32_t b0 = fr[j].z, b1 = fr[j].w & 0x7fffffffu;
+                const int pb = parent[b0];
                 // b0's parent is A's (possibly stale) root: one component
                 if (pb == ra) continue;
                 const int rb = uf_find(parent, pb);
@@ -192,6 +264,37 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint32_t
     }
 }
 
+// occupancy bits per 256-cell block (the scan turns them into the prefix
+// counts of coarse_rank); the extra last block counts nothing
+__global__ void k_occ_count(int64_t blocks, const uint32_t* __restrict__ occ, uint32_t* __restrict__ cnt) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > blocks) return;
+    uint32_t c = 0;
+    if (b < blocks) {
+        const uint4* o = reinterpret_cast<const uint4*>(occ) + 2 * b;
+        const uint4 lo = o[0], hi = o[1];
+        c = __popc(lo.x) + __popc(lo.y) + __popc(lo.z) + __popc(lo.w) + __popc(hi.x) + __popc(hi.y) + __popc(hi.z) +
+            __popc(hi.w);
+    }
+    cnt[b] = c;
+}
+
+// fine-cell records for the sweep: key, first member, end | dense << 31
+__global__ void k_frec(int64_t nfine, const uint32_t* __restrict__ fine_start, const uint64_t* __restrict__ key,
+                       const uint32_t* __restrict__ cid, const uint32_t* __restrict__ cfs, int mark_dense,
+                       uint4* __restrict__ frec) {
+    const int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (F >= nfine) return;
+    const uint32_t b0 = fine_start[F], b1 = fine_start[F + 1];
+    const uint64_t k = key[b0];
+    uint32_t dense = 0;
+    if (mark_dense) {
+        const uint32_t c = cid[F];
+        dense = cfs[c + 1] - cfs[c] >= DENSE_CC ? 1u : 0u;
+    }
+    frec[F] = make_uint4((uint32_t)k, (uint32_t)(k >> 32), b0, b1 | (dense << 31));
+}
+
 // coarse-cell starts among the fine cells: flag[F] = 1 where F opens a coarse cell
 __global__ void k_coarse_flags(int64_t nfine, const uint32_t* __restrict__ fine_start,
                                const uint64_t* __restrict__ key, int lr3, uint32_t* __restrict__ flag) {
@@ -204,13 +307,17 @@ __global__ void k_coarse_flags(int64_t nfine, const uint32_t* __restrict__ fine_
 // cfs[c] = first fine cell of coarse cell c, cfs[ncoarse] = nfine
 __global__ void k_coarse_starts(int64_t nfine, const uint32_t* __restrict__ fine_start,
                                 const uint64_t* __restrict__ key, int lr3, uint32_t* __restrict__ cid,
-                                uint32_t* __restrict__ cfs) {
+                                uint32_t* __restrict__ cfs, uint32_t* __restrict__ occ) {
     const int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (F >= nfine) return;
-    const bool start = F == 0 || (key[fine_start[F]] >> lr3) != (key[fine_start[F - 1]] >> lr3);
+    const uint64_t ck = key[fine_start[F]] >> lr3;
+    const bool start = F == 0 || ck != (key[fine_start[F - 1]] >> lr3);
     const uint32_t c = start ? cid[F] : cid[F] - 1;
     cid[F] = c;
-    if (start) cfs[c] = (uint32_t)F;
+    if (start) {
+        cfs[c] = (uint32_t)F;
+        if (occ) atomicOr(&occ[ck >> 5], 1u << (ck & 31));
+    }
     if (F == nfine - 1) cfs[c + 1] = (uint32_t)nfine;
 }
 
@@ -464,12 +571,13 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     const unsigned gn = grid_for(n, 256);
     uint64_t* kin;
     uint32_t* iin;
-    int rc = sort_input_u64(ctx, key, idx, n, key_bits, &kin, &iin);
+    const int off_bits = 3 * k;
+    int rc = sort_input_u64(ctx, key, idx, n, off_bits + key_bits, &kin, &iin, off_bits);
     if (rc) return rc;
     hipLaunchKernelGGL(k_finekey, dim3(gn), dim3(256), 0, st, n, p->qx, p->qy, p->qz, G, kin, iin);
     VR_LAUNCH_CHECK(ctx);
-    if ((rc = sort_pairs_u64_from(ctx, kin, iin, key, idx, n, key_bits, st))) return rc;
-    hipLaunchKernelGGL(k_gather_q, dim3(gn), dim3(256), 0, st, n, idx, p->qx, p->qy, p->qz, sx, sy, sz);
+    if ((rc = sort_pairs_u64_from(ctx, kin, iin, key, idx, n, off_bits + key_bits, st, off_bits))) return rc;
+    hipLaunchKernelGGL(k_decode_q, dim3(gn), dim3(256), 0, st, n, G, key, sx, sy, sz);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_key_flags, dim3(gn), dim3(256), 0, st, n, key, scan);
     VR_LAUNCH_CHECK(ctx);
@@ -480,40 +588,51 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     if ((rc = read_back(ctx, tot, &nfine, sizeof nfine, st))) return rc;
     hipLaunchKernelGGL(k_parent_init, dim3(gn), dim3(256), 0, st, n, fid, fine_start, parent);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_rows, dim3(grid_for(nrows + 1, 256)), dim3(256), 0, st, nrows, n, key, G.b + 3 * G.lr,
-                       row_start);
+    // coarse index per fine cell, first fine cell per coarse cell, the
+    // occupancy bit of every coarse cell with prefix counts per 256 cells
+    // (nc^3 / 8 + nc^3 / 64 bytes), the dense coarse cells (fine grids of 4
+    // a side), and one record per fine cell for the sweep
+    const uint64_t ncell3 = (uint64_t)G.nc * (uint64_t)G.nc * (uint64_t)G.nc;
+    const int64_t oblocks = (int64_t)(ncell3 >> 8) + 1;  // nc >= 4: ncell3 is a multiple of 64
+    uint32_t* cid = scan;  // the fine-start flags are no longer needed
+    VR_WS(cfs, ctx, uint32_t, WS_B2, (int64_t)nfine + 1);
+    VR_WS(occ, ctx, uint32_t, WS_B4, oblocks * 8);
+    VR_WS(pre, ctx, uint32_t, WS_B5, oblocks + 1);
+    VR_WS(frec, ctx, uint4, WS_B6, (int64_t)nfine);
+    if ((rc = fill_u32(ctx, occ, 0u, oblocks * 8, st))) return rc;
+    const unsigned gf = grid_for(nfine, 256);
+    hipLaunchKernelGGL(k_coarse_flags, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid);
     VR_LAUNCH_CHECK(ctx);
-    // dense coarse cells (fine grids of 4 a side): coarse index per fine
-    // cell, first fine cell per coarse cell, and the list of dense ones
-    const uint32_t* cid = nullptr;
-    const uint32_t* cfs = nullptr;
+    if ((rc = scan_u32(ctx, cid, cid, nfine, tot, st))) return rc;
+    uint32_t ncoarse = 0;
+    if ((rc = read_back(ctx, tot, &ncoarse, sizeof ncoarse, st))) return rc;
+    hipLaunchKernelGGL(k_coarse_starts, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid,
+                       cfs, occ);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_occ_count, dim3(grid_for(oblocks, 256)), dim3(256), 0, st, oblocks - 1, occ, pre);
+    VR_LAUNCH_CHECK(ctx);
+    if ((rc = scan_u32(ctx, pre, pre, oblocks, nullptr, st))) return rc;
     int32_t* dense = nullptr;
     int ndense = 0;
     if (G.r == TILE_R) {
-        uint32_t* cid_w = scan;  // the fine-start flags are no longer needed
-        VR_WS(cfs_w, ctx, uint32_t, WS_B2, (int64_t)nfine + 1);
         VR_WS(dense_w, ctx, int32_t, WS_B3, (int64_t)nfine + 1);
         VR_WS(cnt, ctx, int, WS_FLAG2, 4);
-        const unsigned gf = grid_for(nfine, 256);
-        hipLaunchKernelGGL(k_coarse_flags, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid_w);
-        VR_LAUNCH_CHECK(ctx);
-        if ((rc = scan_u32(ctx, cid_w, cid_w, nfine, tot, st))) return rc;
-        uint32_t ncoarse = 0;
-        if ((rc = read_back(ctx, tot, &ncoarse, sizeof ncoarse, st))) return rc;
-        hipLaunchKernelGGL(k_coarse_starts, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid_w,
-                           cfs_w);
-        VR_LAUNCH_CHECK(ctx);
         if ((rc = fill_i32(ctx, cnt, 0, 1, st))) return rc;
-        hipLaunchKernelGGL(k_dense_cc, dim3(grid_for(ncoarse, 256)), dim3(256), 0, st, (int64_t)ncoarse, cfs_w, cnt,
+        hipLaunchKernelGGL(k_dense_cc, dim3(grid_for(ncoarse, 256)), dim3(256), 0, st, (int64_t)ncoarse, cfs, cnt,
                            dense_w);
         VR_LAUNCH_CHECK(ctx);
         if ((rc = read_back(ctx, cnt, &ndense, sizeof ndense, st))) return rc;
         if (ndense > 0) {
-            cid = cid_w;
-            cfs = cfs_w;
             dense = dense_w;
+            // the tiles find their neighbour cells by row
+            hipLaunchKernelGGL(k_rows, dim3(grid_for(nrows + 1, 256)), dim3(256), 0, st, nrows, n, key,
+                               G.b + 3 * G.lr, row_start);
+            VR_LAUNCH_CHECK(ctx);
         }
     }
+    hipLaunchKernelGGL(k_frec, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, cid, cfs,
+                       ndense > 0 ? 1 : 0, frec);
+    VR_LAUNCH_CHECK(ctx);
     // the tile mask keeps B where (f e)^2 summed < ell2 with e = |g| - 1:
     // e2 < ell2 / f^2, compared in FP32 against a threshold rounded up
     const double fk = std::ldexp(1.0, k);
@@ -525,8 +644,8 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     VR_LAUNCH_CHECK(ctx)
     if (ndense > 0) { VR_TILE3(1); }
     VR_TIMED(ctx, "fof_link3d", st, n,
-             hipLaunchKernelGGL(k_link_fine, dim3(grid_for(nfine, 256)), dim3(256), 0, st, (int64_t)nfine, fine_start,
-                                fid, key, sx, sy, sz, row_start, G, ell2, parent, (unsigned)ctx->xcd_chunk, cid, cfs));
+             hipLaunchKernelGGL(k_link_fine, dim3(grid_for(nfine, 256)), dim3(256), 0, st, (int64_t)nfine, frec, sx,
+                                sy, sz, G, ell2, parent, (unsigned)ctx->xcd_chunk, cfs, occ, pre));
     VR_LAUNCH_CHECK(ctx);
     if (ndense > 0) { VR_TILE3(0); }
 #undef VR_TILE3

@@ -167,11 +167,13 @@ int sort_pairs_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int b
 // (keys, vals) ends there without a final copy: the sort's own alternate
 // buffers when it takes an odd number of 8-bit passes, else keys and vals.
 // The pairs are then sorted by sort_pairs_*_from(kin, vin -> keys, vals)
-// with the same n and bits, and nothing may take workspace in between.
+// with the same n, bits and first_bit, and nothing may take workspace in
+// between.  The _from sort orders by key bits [first_bit, bits); lower bits
+// travel with their key (stable).
 int sort_input_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, uint64_t** kin,
-                   uint32_t** vin);
+                   uint32_t** vin, int first_bit = 0);
 int sort_pairs_u64_from(vr_ctx* ctx, uint64_t* kin, uint32_t* vin, uint64_t* keys, uint32_t* vals, int64_t n,
-                        int bits, hipStream_t s);
+                        int bits, hipStream_t s, int first_bit = 0);
 // Fill helpers (kernels, never memset nodes, so they are safe to capture).
 int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s);
 int fill_u32(vr_ctx* ctx, uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

@@ -272,10 +272,11 @@ __global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict_
 }
 
 template <class K>
-int sort_input_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, K** kin, uint32_t** vin) {
+int sort_input_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, K** kin, uint32_t** vin,
+                    int first_bit = 0) {
     *kin = keys;
     *vin = vals;
-    if (n <= 1 || bits <= 0 || ((bits + 7) / 8) % 2 == 0) return VR_OK;
+    if (n <= 1 || bits <= first_bit || ((bits - first_bit + 7) / 8) % 2 == 0) return VR_OK;
     VR_WS(kalt, ctx, K, WS_SORT_KEYS_B, n);
     VR_WS(valt, ctx, uint32_t, WS_SORT_VALS_B, n);
     *kin = kalt;
@@ -288,8 +289,8 @@ int sort_input_impl(vr_ctx* ctx, K* keys, uint32_t* vals, int64_t n, int bits, K
 // into (keys, vals) only where it ends in the other one.
 template <class K>
 int sort_pairs_impl(vr_ctx* ctx, K* kin, uint32_t* vin, K* keys, uint32_t* vals, int64_t n, int bits,
-                    hipStream_t s) {
-    if (n <= 1 || bits <= 0) {
+                    hipStream_t s, int first_bit = 0) {
+    if (n <= 1 || bits <= first_bit) {
         if (n == 1 && kin != keys) {
             VR_HIP(ctx, hipMemcpyAsync(keys, kin, sizeof(K), hipMemcpyDeviceToDevice, s));
             VR_HIP(ctx, hipMemcpyAsync(vals, vin, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
@@ -304,9 +305,9 @@ int sort_pairs_impl(vr_ctx* ctx, K* kin, uint32_t* vin, K* keys, uint32_t* vals,
         return set_err(ctx, VR_ERR_INVALID_ARG, "sort input is neither the output nor the alternate buffers");
     K* k0 = kin; K* k1 = kin == keys ? kalt : keys;
     uint32_t* v0 = vin; uint32_t* v1 = vin == vals ? valt : vals;
-    const int passes = (bits + 7) / 8;
+    const int passes = (bits - first_bit + 7) / 8;
     for (int p = 0; p < passes; ++p) {
-        const int shift = p * 8;
+        const int shift = first_bit + p * 8;
         hipLaunchKernelGGL(k_radix_count<K>, dim3(num_tiles), dim3(RS_BLOCK), 0, s, k0, n, shift, hist,
                            num_tiles);
         VR_LAUNCH_CHECK(ctx);
@@ -391,13 +392,13 @@ int sort_pairs_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int b
 }
 
 int sort_input_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int bits, uint64_t** kin,
-                   uint32_t** vin) {
-    return sort_input_impl<uint64_t>(ctx, keys, vals, n, bits, kin, vin);
+                   uint32_t** vin, int first_bit) {
+    return sort_input_impl<uint64_t>(ctx, keys, vals, n, bits, kin, vin, first_bit);
 }
 
 int sort_pairs_u64_from(vr_ctx* ctx, uint64_t* kin, uint32_t* vin, uint64_t* keys, uint32_t* vals, int64_t n,
-                        int bits, hipStream_t s) {
-    return sort_pairs_impl<uint64_t>(ctx, kin, vin, keys, vals, n, bits, s);
+                        int bits, hipStream_t s, int first_bit) {
+    return sort_pairs_impl<uint64_t>(ctx, kin, vin, keys, vals, n, bits, s, first_bit);
 }
 
 int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s) {
