@@ -114,35 +114,25 @@ constexpr uint32_t DENSE_CC = 48;
 constexpr int TILE_R = 4;  // fine cells per coarse side where the tiles apply (r^3 <= 64 lanes)
 
 // Number of occupied coarse cells before coarse cell `cell` (row-major
-// index): the prefix count of its 256-cell block plus the occupancy bits
-// below `cell` in that block (eight words, two 16-byte loads).  Occupied
-// cells are numbered in sorted order, so this is also the coarse index of
-// `cell` when it is occupied.
-__device__ __forceinline__ uint32_t coarse_rank(const uint32_t* __restrict__ occ, const uint32_t* __restrict__ pre,
+// index): the prefix count of its 64-cell word plus the occupancy bits
+// below `cell` in that word (two independent loads).  Occupied cells are
+// numbered in sorted order, so this is also the coarse index of `cell`
+// when it is occupied.
+__device__ __forceinline__ uint32_t coarse_rank(const uint64_t* __restrict__ occ, const uint32_t* __restrict__ pre,
                                                 uint64_t cell) {
-    const uint64_t blk = cell >> 8;
-    const uint4* o = reinterpret_cast<const uint4*>(occ) + 2 * blk;
-    const uint4 lo = o[0], hi = o[1];
-    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-    const uint32_t wi = (uint32_t)(cell >> 5) & 7u, bit = (uint32_t)cell & 31u;
-    uint32_t r = pre[blk];
-#pragma unroll
-    for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t m = j < wi ? ~0u : (j == wi ? (1u << bit) - 1u : 0u);
-        r += (uint32_t)__popc(w[j] & m);
-    }
-    return r;
+    const uint64_t w = cell >> 6;
+    return pre[w] + (uint32_t)__popcll(occ[w] & ((1ull << (cell & 63)) - 1ull));
 }
 
 // One thread per fine cell A of the sparse coarse cells.  frec[F] holds
 // fine cell F's key (two words), its first member and its end (bit 31 of
 // the end: F lies in a dense coarse cell).  The fine cells of a run of
 // coarse cells x0 .. x1 in one row are cfs[rank(x0)] .. cfs[rank(x1 + 1)] - 1.
-__global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint4* __restrict__ frec,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_link_fine(int64_t nfine, const uint4* __restrict__ frec,
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                    const uint32_t* __restrict__ sz, FineGrid G, double ell2,
                                                    int* parent, unsigned xchunk, const uint32_t* __restrict__ cfs,
-                                                   const uint32_t* __restrict__ occ, const uint32_t* __restrict__ pre) {
+                                                   const uint64_t* __restrict__ occ, const uint32_t* __restrict__ pre) {
     const int64_t A = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
     if (A >= nfine) return;
     const uint4 fa = frec[A];
@@ -264,19 +254,11 @@ __global__ __launch_bounds__(256) void k_link_fine(int64_t nfine, const uint4* _
     }
 }
 
-// occupancy bits per 256-cell block (the scan turns them into the prefix
-// counts of coarse_rank); the extra last block counts nothing
-__global__ void k_occ_count(int64_t blocks, const uint32_t* __restrict__ occ, uint32_t* __restrict__ cnt) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b > blocks) return;
-    uint32_t c = 0;
-    if (b < blocks) {
-        const uint4* o = reinterpret_cast<const uint4*>(occ) + 2 * b;
-        const uint4 lo = o[0], hi = o[1];
-        c = __popc(lo.x) + __popc(lo.y) + __popc(lo.z) + __popc(lo.w) + __popc(hi.x) + __popc(hi.y) + __popc(hi.z) +
-            __popc(hi.w);
-    }
-    cnt[b] = c;
+// occupancy bits per 64-cell word (the scan turns them into the prefix
+// counts of coarse_rank); the extra last word counts nothing
+__global__ void k_occ_count(int64_t words, const uint64_t* __restrict__ occ, uint32_t* __restrict__ cnt) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w <= words) cnt[w] = w < words ? (uint32_t)__popcll(occ[w]) : 0u;
 }
 
 // fine-cell records for the sweep: key, first member, end | dense << 31
@@ -307,7 +289,7 @@ __global__ void k_coarse_flags(int64_t nfine, const uint32_t* __restrict__ fine_
 // cfs[c] = first fine cell of coarse cell c, cfs[ncoarse] = nfine
 __global__ void k_coarse_starts(int64_t nfine, const uint32_t* __restrict__ fine_start,
                                 const uint64_t* __restrict__ key, int lr3, uint32_t* __restrict__ cid,
-                                uint32_t* __restrict__ cfs, uint32_t* __restrict__ occ) {
+                                uint32_t* __restrict__ cfs, unsigned long long* __restrict__ occ) {
     const int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (F >= nfine) return;
     const uint64_t ck = key[fine_start[F]] >> lr3;
@@ -316,7 +298,7 @@ __global__ void k_coarse_starts(int64_t nfine, const uint32_t* __restrict__ fine
     cid[F] = c;
     if (start) {
         cfs[c] = (uint32_t)F;
-        if (occ) atomicOr(&occ[ck >> 5], 1u << (ck & 31));
+        atomicOr(&occ[ck >> 6], 1ull << (ck & 63));
     }
     if (F == nfine - 1) cfs[c + 1] = (uint32_t)nfine;
 }
@@ -589,17 +571,17 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     hipLaunchKernelGGL(k_parent_init, dim3(gn), dim3(256), 0, st, n, fid, fine_start, parent);
     VR_LAUNCH_CHECK(ctx);
     // coarse index per fine cell, first fine cell per coarse cell, the
-    // occupancy bit of every coarse cell with prefix counts per 256 cells
-    // (nc^3 / 8 + nc^3 / 64 bytes), the dense coarse cells (fine grids of 4
+    // occupancy bit of every coarse cell with prefix counts per 64 cells
+    // (nc^3 / 8 + nc^3 / 16 bytes), the dense coarse cells (fine grids of 4
     // a side), and one record per fine cell for the sweep
     const uint64_t ncell3 = (uint64_t)G.nc * (uint64_t)G.nc * (uint64_t)G.nc;
-    const int64_t oblocks = (int64_t)(ncell3 >> 8) + 1;  // nc >= 4: ncell3 is a multiple of 64
+    const int64_t owords = (int64_t)(ncell3 >> 6) + 1;  // nc >= 4: ncell3 is a multiple of 64
     uint32_t* cid = scan;  // the fine-start flags are no longer needed
     VR_WS(cfs, ctx, uint32_t, WS_B2, (int64_t)nfine + 1);
-    VR_WS(occ, ctx, uint32_t, WS_B4, oblocks * 8);
-    VR_WS(pre, ctx, uint32_t, WS_B5, oblocks + 1);
+    VR_WS(occ, ctx, unsigned long long, WS_B4, owords);
+    VR_WS(pre, ctx, uint32_t, WS_B5, owords + 1);
     VR_WS(frec, ctx, uint4, WS_B6, (int64_t)nfine);
-    if ((rc = fill_u32(ctx, occ, 0u, oblocks * 8, st))) return rc;
+    if ((rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(occ), 0u, 2 * owords, st))) return rc;
     const unsigned gf = grid_for(nfine, 256);
     hipLaunchKernelGGL(k_coarse_flags, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid);
     VR_LAUNCH_CHECK(ctx);
@@ -609,9 +591,10 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     hipLaunchKernelGGL(k_coarse_starts, dim3(gf), dim3(256), 0, st, (int64_t)nfine, fine_start, key, 3 * G.lr, cid,
                        cfs, occ);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_occ_count, dim3(grid_for(oblocks, 256)), dim3(256), 0, st, oblocks - 1, occ, pre);
+    hipLaunchKernelGGL(k_occ_count, dim3(grid_for(owords, 256)), dim3(256), 0, st, owords - 1,
+                       reinterpret_cast<const uint64_t*>(occ), pre);
     VR_LAUNCH_CHECK(ctx);
-    if ((rc = scan_u32(ctx, pre, pre, oblocks, nullptr, st))) return rc;
+    if ((rc = scan_u32(ctx, pre, pre, owords, nullptr, st))) return rc;
     int32_t* dense = nullptr;
     int ndense = 0;
     if (G.r == TILE_R) {
@@ -645,7 +628,8 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     if (ndense > 0) { VR_TILE3(1); }
     VR_TIMED(ctx, "fof_link3d", st, n,
              hipLaunchKernelGGL(k_link_fine, dim3(grid_for(nfine, 256)), dim3(256), 0, st, (int64_t)nfine, frec, sx,
-                                sy, sz, G, ell2, parent, (unsigned)ctx->xcd_chunk, cfs, occ, pre));
+                                sy, sz, G, ell2, parent, (unsigned)ctx->xcd_chunk, cfs,
+                                reinterpret_cast<const uint64_t*>(occ), pre));
     VR_LAUNCH_CHECK(ctx);
     if (ndense > 0) { VR_TILE3(0); }
 #undef VR_TILE3

@@ -26,6 +26,7 @@ namespace {
 
 constexpr int KB = 256;
 constexpr int HCH = 2048;  // positions per histogram block
+constexpr int HASH_SLOTS = 256;  // partial sums of the content hash
 
 // One element's share of the content hash of a build's inputs: a 64-bit
 // mix of its position, member, unwrapped coordinates and host.  The shares
@@ -44,9 +45,10 @@ __device__ __forceinline__ unsigned long long elem_hash(int64_t e, int i, int a,
     return (unsigned long long)x;
 }
 
-// Element arrays by element id, and the sort keys of the presort; *hash
-// (zeroed beforehand) receives the content hash of (member, coordinates,
-// host) over all elements.
+// Element arrays by element id, and the sort keys of the presort; the
+// HASH_SLOTS words of hash (zeroed beforehand) receive partial sums of the
+// content hash of (member, coordinates, host) over all elements, one slot
+// per wavefront in turn, so no single address takes every wavefront's add.
 __global__ void k_elems(int64_t M, int n_hosts, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
                         const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                         const uint32_t* __restrict__ qz, const float* __restrict__ mass, int gb, int* __restrict__ u0,
@@ -76,7 +78,8 @@ __global__ void k_elems(int64_t M, int n_hosts, const int32_t* __restrict__ off,
     }
     // every lane of the wavefront reaches the sum
     for (int o = 32; o > 0; o >>= 1) hv += (unsigned long long)__shfl_xor((long long)hv, o, 64);
-    if ((threadIdx.x & 63) == 0 && hv) atomicAdd(hash, hv);
+    if ((threadIdx.x & 63) == 0 && hv)
+        atomicAdd(&hash[((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % HASH_SLOTS], hv);
 }
 
 __global__ void k_presort_keys(int64_t M, const int* __restrict__ u, const int* __restrict__ host,
@@ -548,7 +551,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         F.mass = cv.add<float>(use_mass ? M : 1);
         ncell_d = cv.add<int>(n_hosts);
         counters = cv.add<int>(8);
-        hsh = cv.add<unsigned long long>(1);
+        hsh = cv.add<unsigned long long>(HASH_SLOTS);
     };
     layout();
     const size_t total = cv.bytes;
@@ -564,7 +567,7 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     init[3] = n_hosts;
     VR_HIP(ctx, hipMemcpyAsync(counters, init, 8 * sizeof(int), hipMemcpyHostToDevice, st));
     {
-        int rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hsh), 0u, 2, st);
+        int rc = fill_u32(ctx, reinterpret_cast<uint32_t*>(hsh), 0u, 2 * HASH_SLOTS, st);
         if (rc) return rc;
     }
     hipLaunchKernelGGL(k_elems, dim3(grid_for(M, 256)), dim3(256), 0, st, M, n_hosts, host_offsets, host_members,
@@ -577,9 +580,11 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     // one search are built over the same members); without room for them
     // under the workspace cap it simply sorts.
     {
-        unsigned long long h64 = 0;
-        int rc = read_back(ctx, hsh, &h64, sizeof h64, st);
+        unsigned long long parts[HASH_SLOTS];
+        int rc = read_back(ctx, hsh, parts, sizeof parts, st);
         if (rc) return rc;
+        unsigned long long h64 = 0;
+        for (int k = 0; k < HASH_SLOTS; ++k) h64 += parts[k];
         const int bits = 22 + hb;
         const std::string err_before = ctx->err;
         int* pre = static_cast<int*>(ws(ctx, WS_KD_PRE, 3 * (size_t)M * sizeof(int)));
