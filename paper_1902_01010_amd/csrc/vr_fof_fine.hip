@@ -128,7 +128,7 @@ __device__ __forceinline__ uint32_t coarse_rank(const uint64_t* __restrict__ occ
 // fine cell F's key (two words), its first member and its end (bit 31 of
 // the end: F lies in a dense coarse cell).  The fine cells of a run of
 // coarse cells x0 .. x1 in one row are cfs[rank(x0)] .. cfs[rank(x1 + 1)] - 1.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_link_fine(int64_t nfine, const uint4* __restrict__ frec,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_link_fine(int64_t nfine, const uint4* __restrict__ frec,
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                    const uint32_t* __restrict__ sz, FineGrid G, double ell2,
                                                    int* parent, unsigned xchunk, const uint32_t* __restrict__ cfs,
@@ -203,15 +203,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
             if (u == j) { B0 = f_lo[j]; Bend = f_hi[j]; }
         // the own coarse cell (in the own row's runs): only cells after A
         if (B0 <= (uint32_t)A && (uint32_t)A < Bend) B0 = (uint32_t)A + 1;
-        for (; B0 < Bend; B0 += 4) {
-            // four candidate records per round trip; the exact box bound
+        for (; B0 < Bend; B0 += 2) {
+            // two candidate records per round trip; the exact box bound
             // settles most of them without touching their members
-            uint4 fr[4];
+            uint4 fr[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 2; ++j)
                 if (B0 + j < Bend) fr[j] = frec[B0 + j];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 if (B0 + j >= Bend) break;
                 const uint64_t kb = ((uint64_t)fr[j].y << 32) | fr[j].x;
                 const uint64_t ckb = kb >> lr3;

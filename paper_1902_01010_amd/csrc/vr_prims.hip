@@ -193,6 +193,11 @@ __global__ __launch_bounds__(RS_BLOCK) void k_radix_count(const K* keys, int64_t
     hist[(int64_t)threadIdx.x * num_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one 8-bit digit: every wavefront ranks its 16 x 64 keys
+// by ballots, the block turns the per-wave digit counts into tile offsets,
+// and the tile moves out through LDS in digit order -- the keys first, then
+// the values through the same buffer, so the block needs LDS for one array
+// of keys only (four blocks of 64-bit keys per CU).
 template <class K>
 __global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -203,14 +208,13 @@ __global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict_
     __shared__ uint32_t goff[RS_RADIX];
     __shared__ uint32_t sm[8];
     __shared__ K lk[RS_TILE];
-    __shared__ uint32_t lv[RS_TILE];
+    uint32_t* lv = reinterpret_cast<uint32_t*>(lk);
     const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
     for (int i = tid; i < RS_WAVES * RS_RADIX; i += RS_BLOCK) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
     const int64_t base = tbase + (int64_t)w * (RS_ITEMS * 64);
     K key[RS_ITEMS];
-    uint32_t val[RS_ITEMS];
     uint32_t rank[RS_ITEMS];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -218,7 +222,6 @@ __global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict_
         const int64_t i = base + j * 64 + lane;
         const bool valid = i < n;
         key[j] = valid ? kin[i] : K(0);
-        val[j] = valid ? vin[i] : 0u;
         const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -250,24 +253,41 @@ __global__ __launch_bounds__(RS_BLOCK) void k_radix_scatter(const K* __restrict_
         goff[d] = offs[(int64_t)d * num_tiles + blockIdx.x];
     }
     __syncthreads();
+    // a key's place in the tile, in digit order
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
         const int64_t i = base + j * 64 + lane;
         if (i < n) {
             const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
-            const uint32_t pos = toff[d] + wcnt[w][d] + rank[j];
-            lk[pos] = key[j];
-            lv[pos] = val[j];
+            rank[j] += toff[d] + wcnt[w][d];
+            lk[rank[j]] = key[j];
         }
     }
     __syncthreads();
     const int cnt = (int)((n - tbase) < RS_TILE ? (n - tbase) : RS_TILE);
-    for (int i = tid; i < cnt; i += RS_BLOCK) {
-        const K k = lk[i];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
-        const uint32_t g = goff[d] + (uint32_t)i - toff[d];
-        kout[g] = k;
-        vout[g] = lv[i];
+    uint32_t dst[RS_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int i = tid + j * RS_BLOCK;
+        if (i < cnt) {
+            const K k = lk[i];
+            const uint32_t d = (uint32_t)(k >> shift) & 255u;
+            dst[j] = goff[d] + (uint32_t)i - toff[d];
+            kout[dst[j]] = k;
+        }
+    }
+    __syncthreads();
+    // the values through the same buffer, to the places their keys went
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t i = base + j * 64 + lane;
+        if (i < n) lv[rank[j]] = vin[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int i = tid + j * RS_BLOCK;
+        if (i < cnt) vout[dst[j]] = lv[i];
     }
 }
 
