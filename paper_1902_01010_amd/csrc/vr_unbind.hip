@@ -53,37 +53,52 @@ struct Removed {
     int *nrm, *since, *mode;
 };
 
-__global__ void k_ub_init(int ng, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
+// Member-parallel set-up: member k of group g (found by bisection of the
+// offsets) gets its grid offsets from the group's first member, its
+// velocity and mass; its particle's bound flag and potential are reset.
+__global__ void k_ub_init(int ng, int64_t M, const int32_t* __restrict__ off, const int32_t* __restrict__ mem,
                           const uint32_t* __restrict__ qx, const uint32_t* __restrict__ qy,
                           const uint32_t* __restrict__ qz, const float* __restrict__ vx, const float* __restrict__ vy,
-                          const float* __restrict__ vz, const float* __restrict__ mass, int gb, int n_min, Members W,
-                          Removed Rm, int* __restrict__ cnt, int* __restrict__ state, int32_t* __restrict__ iters,
+                          const float* __restrict__ vz, const float* __restrict__ mass, int gb, Members W,
                           uint8_t* __restrict__ bound, double* __restrict__ phi) {
-    const int g = blockIdx.x;
-    const int s = off[g], e = off[g + 1];
-    const int r = mem[s];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    int lo = 0, hi = ng - 1;  // last group with off[g] <= k
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const int r = mem[off[lo]];
+    const int i = mem[k];
     const int rx = (int)qx[r], ry = (int)qy[r], rz = (int)qz[r];
-    for (int k = s + threadIdx.x; k < e; k += blockDim.x) {
-        const int i = mem[k];
-        W.gidx[k] = i;
-        W.x[k] = (float)min_image((int)qx[i] - rx, gb);
-        W.y[k] = (float)min_image((int)qy[i] - ry, gb);
-        W.z[k] = (float)min_image((int)qz[i] - rz, gb);
-        W.vx[k] = vx[i];
-        W.vy[k] = vy[i];
-        W.vz[k] = vz[i];
-        if (mass) W.m[k] = mass[i];
-        bound[i] = 0;
-        phi[i] = NAN;
-    }
-    if (threadIdx.x == 0) {
-        cnt[g] = e - s;
-        state[g] = (e - s < n_min) ? ST_DISSOLVED : ST_ACTIVE;
-        iters[g] = 0;
-        Rm.nrm[g] = 0;
-        Rm.since[g] = 0;
-        Rm.mode[g] = 0;
-    }
+    W.gidx[k] = i;
+    W.x[k] = (float)min_image((int)qx[i] - rx, gb);
+    W.y[k] = (float)min_image((int)qy[i] - ry, gb);
+    W.z[k] = (float)min_image((int)qz[i] - rz, gb);
+    W.vx[k] = vx[i];
+    W.vy[k] = vy[i];
+    W.vz[k] = vz[i];
+    if (mass) W.m[k] = mass[i];
+    bound[i] = 0;
+    phi[i] = NAN;
+}
+
+// Per-group state, and nbig = the first group with fewer than BIG_GROUP
+// members (*nbig holds ng beforehand): the leading groups up to there take
+// the wide group kernel.
+constexpr int BIG_GROUP = 4096;
+__global__ void k_ub_state(int ng, const int32_t* __restrict__ off, int n_min, Removed Rm, int* __restrict__ cnt,
+                           int* __restrict__ state, int32_t* __restrict__ iters, int* __restrict__ nbig) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int n = off[g + 1] - off[g];
+    cnt[g] = n;
+    state[g] = n < n_min ? ST_DISSOLVED : ST_ACTIVE;
+    iters[g] = 0;
+    Rm.nrm[g] = 0;
+    Rm.since[g] = 0;
+    Rm.mode[g] = 0;
+    if (n < BIG_GROUP) atomicMin(nbig, g);
 }
 
 __global__ void k_ub_zero(int na, const int* __restrict__ active, const int32_t* __restrict__ off,
@@ -204,15 +219,24 @@ __device__ __forceinline__ uint64_t ref_key(const Members& W, int base, int pos,
     return ((uint64_t)(dx * dx + dy * dy + dz * dz) << 22) | (uint64_t)pos;
 }
 
-__global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active, const int32_t* __restrict__ off,
+// One group per workgroup of BS threads.  With split != 0 (no active list)
+// BS = UB_WIDE takes the groups before *nbig and BS = UB the others, so the
+// largest groups get four times the threads.
+constexpr int UB_WIDE = 1024;
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ub_group(const int* __restrict__ active, const int32_t* __restrict__ off,
                                                  int* __restrict__ cnt, int* __restrict__ state,
                                                  int32_t* __restrict__ iters, Members W, Removed Rm,
                                                  double* __restrict__ acc, double eps2g, double scale,
                                                  double mass_value, double beta_E, double frac_ref, int n_min,
                                                  int n_ref_min, int frame_type, int gb, uint8_t* __restrict__ bound,
-                                                 double* __restrict__ phi, int max_iter) {
-    __shared__ double smd[4 * 8];
-    __shared__ uint32_t smu[8];
+                                                 double* __restrict__ phi, int max_iter,
+                                                 const int* __restrict__ nbig) {
+    constexpr int NW = BS / 64;
+    constexpr int BPT = 2048 / BS;  // histogram bins per thread
+    static_assert(BS >= 256 && BS <= 2048 && 2048 % BS == 0, "block size");
+    __shared__ double smd[4 * NW];
+    __shared__ uint32_t smu[NW];
     __shared__ uint32_t hist[2048];
     __shared__ int cand[MAX_CAND];
     __shared__ int s_p, s_bucket;
@@ -221,6 +245,7 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
     __shared__ int s_minpos;
     // with no active list every group has a block and finished ones leave
     const int g = active ? active[blockIdx.x] : (int)blockIdx.x;
+    if (nbig && (BS == UB_WIDE ? g >= *nbig : g < *nbig)) return;
     if (!active && (state[g] != ST_ACTIVE || iters[g] >= max_iter)) return;
     const int base = off[g];
     const int n = cnt[g];
@@ -309,14 +334,14 @@ __global__ __launch_bounds__(UB) void k_ub_group(const int* __restrict__ active,
             }
             __syncthreads();
             uint32_t loc = 0;
-            for (int k = 0; k < 8; ++k) loc += hist[tid * 8 + k];
+            for (int k = 0; k < BPT; ++k) loc += hist[tid * BPT + k];
             uint32_t tot;
             const uint32_t ex = bscan(loc, smu, &tot);
             if (rank >= ex && rank < ex + loc) {
                 uint32_t c = ex;
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t hh = hist[tid * 8 + k];
-                    if (rank < c + hh) { s_bucket = tid * 8 + k; s_below = c; break; }
+                for (int k = 0; k < BPT; ++k) {
+                    const uint32_t hh = hist[tid * BPT + k];
+                    if (rank < c + hh) { s_bucket = tid * BPT + k; s_below = c; break; }
                     c += hh;
                 }
             }
@@ -587,8 +612,8 @@ void ub_graph_release(vr_ctx* ctx) {
 // group is active; the host reads two counters per replay.
 int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int32_t* offsets,
                       const vr_unbind_params* up, const Members& W, const Removed& Rm, double* acc, int* cnt, int* state,
-                      int32_t* iters, uint8_t* bound, double* phi, int* act, float eps2f, double eps2g,
-                      double scale, int tile, hipStream_t st) {
+                      int32_t* iters, uint8_t* bound, double* phi, int* act, const int* nbig, float eps2f,
+                      double eps2g, double scale, int tile, hipStream_t st) {
     VR_WS(plan, ctx, UbPlan, WS_D4, 1);
     VR_WS(item_off, ctx, int, WS_D5, (int64_t)ng + 1);
     const bool uniform = W.m == nullptr;
@@ -606,7 +631,7 @@ int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int3
     UbGraphKey key;
     std::memset(&key, 0, sizeof key);
     const void* kp[24] = {offsets, W.gidx, W.x, W.y, W.z, W.vx, W.vy, W.vz, W.m, acc, cnt, state, iters, bound, phi,
-                          act, Rm.x, Rm.y, Rm.z, Rm.m, Rm.nrm, Rm.since, Rm.mode, nullptr};
+                          act, Rm.x, Rm.y, Rm.z, Rm.m, Rm.nrm, Rm.since, Rm.mode, nbig};
     std::memcpy(key.ptrs, kp, sizeof kp);
     const int ki[12] = {ng, up->max_iter, jchunk, tile, (int)pgrid, up->n_min, up->n_ref_min, up->frame_type,
                         p->grid_bits, uniform ? 1 : 0, 0, 0};
@@ -633,9 +658,12 @@ int unbind_persistent(vr_ctx* ctx, const vr_particles* p, int32_t ng, const int3
             else
                 hipLaunchKernelGGL(k_ub_potential_p<false>, dim3(pgrid), dim3(UB), lds, cs, plan, act, item_off,
                                    offsets, cnt, W, Rm, eps2f, acc, jchunk, tile);
-            hipLaunchKernelGGL(k_ub_group, dim3(ng), dim3(UB), 0, cs, (const int*)nullptr, offsets, cnt, state,
+            hipLaunchKernelGGL(k_ub_group<UB_WIDE>, dim3(ng), dim3(UB_WIDE), 0, cs, (const int*)nullptr, offsets, cnt,
+                               state, iters, W, Rm, acc, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref,
+                               up->n_min, up->n_ref_min, up->frame_type, p->grid_bits, bound, phi, up->max_iter, nbig);
+            hipLaunchKernelGGL(k_ub_group<UB>, dim3(ng), dim3(UB), 0, cs, (const int*)nullptr, offsets, cnt, state,
                                iters, W, Rm, acc, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min,
-                               up->n_ref_min, up->frame_type, p->grid_bits, bound, phi, up->max_iter);
+                               up->n_ref_min, up->frame_type, p->grid_bits, bound, phi, up->max_iter, nbig);
         }
         hipLaunchKernelGGL(k_ub_count, dim3(1), dim3(PLAN_T), 0, cs, ng, state, iters, up->max_iter, plan);
         hipGraph_t graph = nullptr;
@@ -739,8 +767,16 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     VR_WS(rmass, ctx, float, WS_B3, M);
     VR_WS(nrm, ctx, int, WS_B4, n_groups); VR_WS(since, ctx, int, WS_B5, n_groups); VR_WS(mode, ctx, int, WS_B6, n_groups);
     Rm.x = rx; Rm.y = ry; Rm.z = rz; Rm.m = rmass; Rm.nrm = nrm; Rm.since = since; Rm.mode = mode;
-    hipLaunchKernelGGL(k_ub_init, dim3(n_groups), dim3(256), 0, st, n_groups, offsets, members, p->qx, p->qy, p->qz,
-                       p->vx, p->vy, p->vz, p->mass, p->grid_bits, up->n_min, W, Rm, cnt, state, iters, bound, phi);
+    VR_WS(nbig, ctx, int, WS_D6, 1);
+    {
+        int rc = fill_i32(ctx, nbig, n_groups, 1, st);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_ub_state, dim3(grid_for(n_groups, 256)), dim3(256), 0, st, n_groups, offsets, up->n_min, Rm,
+                       cnt, state, iters, nbig);
+    VR_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ub_init, dim3(grid_for(M, 256)), dim3(256), 0, st, n_groups, (int64_t)M, offsets, members,
+                       p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, p->mass, p->grid_bits, W, bound, phi);
     VR_LAUNCH_CHECK(ctx);
     const double unit = p->box / ldexp(1.0, p->grid_bits);
     const double epsg = up->eps / unit;
@@ -752,7 +788,7 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     const double scale = -up->G / unit;  // potential = scale * mass * sum(1/r) in grid units
     int tile = up->tile ? up->tile : (ctx->tuned_tile ? ctx->tuned_tile : 256);
     if (up->persistent)
-        return unbind_persistent(ctx, p, n_groups, offsets, up, W, Rm, acc, cnt, state, iters, bound, phi, act,
+        return unbind_persistent(ctx, p, n_groups, offsets, up, W, Rm, acc, cnt, state, iters, bound, phi, act, nbig,
                                  eps2f, eps2g, scale, std::min(tile, PERSIST_MAX_TILE), st);
     std::vector<int> hcnt(n_groups), hstate(n_groups), hact;
     std::vector<int4> items;
@@ -795,9 +831,10 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
                                         cnt, W, eps2f, acc, tile));
         VR_LAUNCH_CHECK(ctx);
         VR_TIMED(ctx, "unbind_group", st, nmem,
-                 hipLaunchKernelGGL(k_ub_group, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, Rm, acc,
-                                    eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min, up->n_ref_min,
-                                    up->frame_type, p->grid_bits, bound, phi, up->max_iter));
+                 hipLaunchKernelGGL(k_ub_group<UB>, dim3(na), dim3(UB), 0, st, act, offsets, cnt, state, iters, W, Rm,
+                                    acc, eps2g, scale, p->mass_value, up->beta_E, up->frac_ref, up->n_min,
+                                    up->n_ref_min, up->frame_type, p->grid_bits, bound, phi, up->max_iter,
+                                    (const int*)nullptr));
         VR_LAUNCH_CHECK(ctx);
     }
     return VR_OK;
