@@ -66,37 +66,40 @@ __global__ __launch_bounds__(KB) void k_cell_moments(int ncells, const uint32_t*
                                                      const float* __restrict__ vx, const float* __restrict__ vy,
                                                      const float* __restrict__ vz, int use_mass, double mass_value,
                                                      double unit, double* __restrict__ table) {
-    __shared__ double sm[4 * 7];
+    __shared__ double sm[4 * 13];
     const int c = blockIdx.x;
     const KdNode nd = nodes[cell_node[c]];
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    // one pass: velocities are summed relative to the cell's first member,
+    // v0, and the dispersion is E[(v - v0)(v - v0)^T] - (vbar - v0)(vbar - v0)^T,
+    // the same FP64 moments as two passes about vbar up to rounding (both
+    // terms are of the size of the dispersion, since v0 is a member)
+    const int g0 = src.gidx[nd.start];
+    const double v0[3] = {(double)vx[g0], (double)vy[g0], (double)vz[g0]};
+    double acc[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = nd.start + threadIdx.x; k < nd.end; k += blockDim.x) {
         const double m = use_mass ? (double)src.mass[k] : mass_value;
         const int g = src.gidx[k];
+        const double d0 = (double)vx[g] - v0[0], d1 = (double)vy[g] - v0[1], d2 = (double)vz[g] - v0[2];
         acc[0] += m;
         acc[1] += m * ((double)src.u[0][k] * unit);
         acc[2] += m * ((double)src.u[1][k] * unit);
         acc[3] += m * ((double)src.u[2][k] * unit);
-        acc[4] += m * (double)vx[g];
-        acc[5] += m * (double)vy[g];
-        acc[6] += m * (double)vz[g];
+        acc[4] += m * d0;
+        acc[5] += m * d1;
+        acc[6] += m * d2;
+        acc[7] += m * d0 * d0;
+        acc[8] += m * d1 * d1;
+        acc[9] += m * d2 * d2;
+        acc[10] += m * d0 * d1;
+        acc[11] += m * d0 * d2;
+        acc[12] += m * d1 * d2;
     }
-    block_sum_d<7>(acc, sm);
+    block_sum_d<13>(acc, sm);
     const double M = acc[0];
-    const double vb[3] = {acc[4] / M, acc[5] / M, acc[6] / M};
-    double s6[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = nd.start + threadIdx.x; k < nd.end; k += blockDim.x) {
-        const double m = use_mass ? (double)src.mass[k] : mass_value;
-        const int g = src.gidx[k];
-        const double d0 = (double)vx[g] - vb[0], d1 = (double)vy[g] - vb[1], d2 = (double)vz[g] - vb[2];
-        s6[0] += m * d0 * d0;
-        s6[1] += m * d1 * d1;
-        s6[2] += m * d2 * d2;
-        s6[3] += m * d0 * d1;
-        s6[4] += m * d0 * d2;
-        s6[5] += m * d1 * d2;
-    }
-    block_sum_d<6>(s6, sm);
+    const double dm[3] = {acc[4] / M, acc[5] / M, acc[6] / M};  // vbar - v0
+    const double vb[3] = {v0[0] + dm[0], v0[1] + dm[1], v0[2] + dm[2]};
+    const double s6[6] = {acc[7] - M * dm[0] * dm[0], acc[8] - M * dm[1] * dm[1], acc[9] - M * dm[2] * dm[2],
+                          acc[10] - M * dm[0] * dm[1], acc[11] - M * dm[0] * dm[2], acc[12] - M * dm[1] * dm[2]};
     if (threadIdx.x == 0) {
         double* row = table + (int64_t)c * VR_CELL_COLS;
         row[0] = (double)nd.host;

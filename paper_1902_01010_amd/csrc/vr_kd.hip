@@ -354,32 +354,38 @@ __global__ __launch_bounds__(256) void k_split(const int* nact, const int* __res
     if (ract) next_active[ka] = c0 + 1; else leaves[kl] = c0 + 1;
 }
 
-// flag[e] = 1 if element e goes to the left child of its (split) node.
-__global__ void k_flags(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
-                        const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
-                        uint8_t* __restrict__ flag) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M) return;
-    const KdNode& nd = nodes[seg_node[p]];
-    if (nd.dim < 0) return;
-    const int* l = nd.dim == 0 ? l0 : (nd.dim == 1 ? l1 : l2);
-    flag[l[p]] = (p - nd.start) < (nd.end - nd.start) / 2 ? 1 : 0;
-}
-
-// The left flags of the three lists at once (list j at lf[j * M + p]).
+// The left flags of the three lists at once (list j at lf[j * M + p]).  A
+// node splits at rank nl = n / 2 of its list along the split dimension d,
+// which is ordered by (u_d, element): the list along d takes its flag from
+// the position, and an element of the other two lists goes left when its
+// (u_d, element) is below the median's (t, em), em = that list's entry at
+// rank nl.
 __global__ void k_lflag3(int64_t M, const int* __restrict__ seg_node, const KdNode* __restrict__ nodes,
                          const int* __restrict__ l0, const int* __restrict__ l1, const int* __restrict__ l2,
-                         const uint8_t* __restrict__ flag, uint8_t* __restrict__ lf) {
+                         const int* __restrict__ u0, const int* __restrict__ u1, const int* __restrict__ u2,
+                         uint8_t* __restrict__ lf) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= M) return;
     const KdNode& nd = nodes[seg_node[p]];
     const int dim = nd.dim;
-    // the list sorted along the split dimension has its flag by position,
-    // as k_flags set it; only the other two lists gather
-    const uint8_t own = (p - nd.start) < (nd.end - nd.start) / 2 ? 1 : 0;
-    lf[p] = dim < 0 ? (uint8_t)0 : (dim == 0 ? own : flag[l0[p]]);
-    lf[M + p] = dim < 0 ? (uint8_t)0 : (dim == 1 ? own : flag[l1[p]]);
-    lf[2 * M + p] = dim < 0 ? (uint8_t)0 : (dim == 2 ? own : flag[l2[p]]);
+    if (dim < 0) {
+        lf[p] = 0;
+        lf[M + p] = 0;
+        lf[2 * M + p] = 0;
+        return;
+    }
+    const int nl = (nd.end - nd.start) / 2;
+    const uint8_t own = (p - nd.start) < nl ? 1 : 0;
+    const int* ld = dim == 0 ? l0 : (dim == 1 ? l1 : l2);
+    const int* ud = dim == 0 ? u0 : (dim == 1 ? u1 : u2);
+    const int em = ld[nd.start + nl], t = nd.t;
+    auto left = [&](int e) -> uint8_t {
+        const int ue = ud[e];
+        return (ue < t || (ue == t && e < em)) ? 1 : 0;
+    };
+    lf[p] = dim == 0 ? own : left(l0[p]);
+    lf[M + p] = dim == 1 ? own : left(l1[p]);
+    lf[2 * M + p] = dim == 2 ? own : left(l2[p]);
 }
 
 // Stable partition of the three lists inside every split node (the scan
@@ -519,7 +525,6 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
     int *C0[3], *C0alt[3];
     const int64_t MC = mode != KD_WIDEST ? M : 1;
     float* Ms;
-    uint8_t* flag;
     uint8_t* lf8;
     uint32_t* lf;
     uint64_t* pkey;
@@ -536,7 +541,6 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         for (int d = 0; d < 3; ++d) C0[d] = cv.add<int>(MC);
         for (int d = 0; d < 3; ++d) C0alt[d] = cv.add<int>(MC);
         seg = cv.add<int>(M);
-        flag = cv.add<uint8_t>(M);
         lf8 = cv.add<uint8_t>(3 * M);
         lf = cv.add<uint32_t>(3 * M + 1);
         pkey = cv.add<uint64_t>(M);
@@ -715,9 +719,8 @@ int kd_build(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts, const int32_t*
         hipLaunchKernelGGL(k_split, dim3(grid_for(na, 256)), dim3(256), 0, st, counters, cur, nodes, L[0], L[1], L[2],
                            U[0], U[1], U[2], mode, Sdim, ncell_d, nxt, leaves, counters);
         VR_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_flags, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag);
-        VR_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_lflag3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], flag, lf8);
+        hipLaunchKernelGGL(k_lflag3, dim3(gM), dim3(256), 0, st, M, seg, nodes, L[0], L[1], L[2], U[0], U[1], U[2],
+                           lf8);
         VR_LAUNCH_CHECK(ctx);
         if ((rc = scan_u8(ctx, lf8, lf, 3 * M, st))) return rc;
         CoordsL0 cl0{};
