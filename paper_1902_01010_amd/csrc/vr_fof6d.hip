@@ -46,74 +46,55 @@ __device__ __forceinline__ void bsum(double (&v)[N], double* sm) {
 // sigma_v of a host from the mass-weighted dispersion tensor of all members
 // about their mass-weighted mean velocity.  Members are cut into chunks of
 // ELLV_CHUNK; one workgroup sums a chunk and one thread per host adds its
-// chunks in order, so the result does not depend on scheduling.
+// chunks in order, so the result does not depend on scheduling.  One pass:
+// velocities are summed relative to the host's first member v0, and the
+// tensor is E[(v - v0)(v - v0)^T] - (vbar - v0)(vbar - v0)^T, equal to the
+// tensor about vbar up to rounding (v0 is a member, so both terms are of
+// the size of the dispersion).
 constexpr int ELLV_CHUNK = 8192;
+constexpr int ELLV_PART = 10;  // M, sum m (v - v0), sum m (v - v0)(v - v0)^T
 
-__global__ __launch_bounds__(256) void k_ellv_mean(const int4* __restrict__ chunks, const int32_t* __restrict__ mem,
-                                                   const float* __restrict__ vx, const float* __restrict__ vy,
-                                                   const float* __restrict__ vz, const float* __restrict__ mass,
-                                                   double mass_value, double* __restrict__ part) {
-    __shared__ double sm[4 * 4];
-    const int4 c = chunks[blockIdx.x];
-    double a[4] = {0, 0, 0, 0};
-    for (int k = c.y + threadIdx.x; k < c.z; k += blockDim.x) {
-        const int i = mem[k];
-        const double m = mass ? (double)mass[i] : mass_value;
-        a[0] += m;
-        a[1] += m * (double)vx[i];
-        a[2] += m * (double)vy[i];
-        a[3] += m * (double)vz[i];
-    }
-    bsum<4>(a, sm);
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 4; ++q) part[(int64_t)blockIdx.x * 8 + q] = a[q];
-}
-
-__global__ void k_ellv_hostmean(int n_hosts, const int* __restrict__ chunk_off, const double* __restrict__ part,
-                                double* __restrict__ hmean) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n_hosts) return;
-    double a[4] = {0, 0, 0, 0};
-    for (int c = chunk_off[h]; c < chunk_off[h + 1]; ++c)
-        for (int q = 0; q < 4; ++q) a[q] += part[(int64_t)c * 8 + q];
-    hmean[h * 4 + 0] = a[0];
-    for (int d = 0; d < 3; ++d) hmean[h * 4 + 1 + d] = a[1 + d] / a[0];
-}
-
-__global__ __launch_bounds__(256) void k_ellv_disp(const int4* __restrict__ chunks, const int32_t* __restrict__ mem,
-                                                   const float* __restrict__ vx, const float* __restrict__ vy,
-                                                   const float* __restrict__ vz, const float* __restrict__ mass,
-                                                   double mass_value, const double* __restrict__ hmean,
+__global__ __launch_bounds__(256) void k_ellv_sums(const int4* __restrict__ chunks, const int32_t* __restrict__ mem,
+                                                   const int32_t* __restrict__ off, const float* __restrict__ vx,
+                                                   const float* __restrict__ vy, const float* __restrict__ vz,
+                                                   const float* __restrict__ mass, double mass_value,
                                                    double* __restrict__ part) {
-    __shared__ double sm[4 * 6];
+    __shared__ double sm[4 * ELLV_PART];
     const int4 c = chunks[blockIdx.x];
-    const double mv0 = hmean[c.x * 4 + 1], mv1 = hmean[c.x * 4 + 2], mv2 = hmean[c.x * 4 + 3];
-    double a[6] = {0, 0, 0, 0, 0, 0};
+    const int i0 = mem[off[c.x]];
+    const double v0x = (double)vx[i0], v0y = (double)vy[i0], v0z = (double)vz[i0];
+    double a[ELLV_PART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = c.y + threadIdx.x; k < c.z; k += blockDim.x) {
         const int i = mem[k];
         const double m = mass ? (double)mass[i] : mass_value;
-        const double d0 = (double)vx[i] - mv0, d1 = (double)vy[i] - mv1, d2 = (double)vz[i] - mv2;
-        a[0] += m * d0 * d0;
-        a[1] += m * d1 * d1;
-        a[2] += m * d2 * d2;
-        a[3] += m * d0 * d1;
-        a[4] += m * d0 * d2;
-        a[5] += m * d1 * d2;
+        const double d0 = (double)vx[i] - v0x, d1 = (double)vy[i] - v0y, d2 = (double)vz[i] - v0z;
+        a[0] += m;
+        a[1] += m * d0;
+        a[2] += m * d1;
+        a[3] += m * d2;
+        a[4] += m * d0 * d0;
+        a[5] += m * d1 * d1;
+        a[6] += m * d2 * d2;
+        a[7] += m * d0 * d1;
+        a[8] += m * d0 * d2;
+        a[9] += m * d1 * d2;
     }
-    bsum<6>(a, sm);
+    bsum<ELLV_PART>(a, sm);
     if (threadIdx.x == 0)
-        for (int q = 0; q < 6; ++q) part[(int64_t)blockIdx.x * 8 + q] = a[q];
+        for (int q = 0; q < ELLV_PART; ++q) part[(int64_t)blockIdx.x * ELLV_PART + q] = a[q];
 }
 
 __global__ void k_ellv_final(int n_hosts, const int* __restrict__ chunk_off, const double* __restrict__ part,
-                             const double* __restrict__ hmean, double alpha_v, double* __restrict__ ellv) {
+                             double alpha_v, double* __restrict__ ellv) {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= n_hosts) return;
-    double c[6] = {0, 0, 0, 0, 0, 0};
+    double c[ELLV_PART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = chunk_off[h]; k < chunk_off[h + 1]; ++k)
-        for (int q = 0; q < 6; ++q) c[q] += part[(int64_t)k * 8 + q];
-    const double M = hmean[h * 4];
-    const double s00 = c[0] / M, s11 = c[1] / M, s22 = c[2] / M, s01 = c[3] / M, s02 = c[4] / M, s12 = c[5] / M;
+        for (int q = 0; q < ELLV_PART; ++q) c[q] += part[(int64_t)k * ELLV_PART + q];
+    const double M = c[0];
+    const double e0 = c[1] / M, e1 = c[2] / M, e2 = c[3] / M;  // vbar - v0
+    const double s00 = c[4] / M - e0 * e0, s11 = c[5] / M - e1 * e1, s22 = c[6] / M - e2 * e2;
+    const double s01 = c[7] / M - e0 * e1, s02 = c[8] / M - e0 * e2, s12 = c[9] / M - e1 * e2;
     const double det = s00 * (s11 * s22 - s12 * s12) - s01 * (s01 * s22 - s12 * s02) + s02 * (s01 * s12 - s11 * s02);
     ellv[h] = alpha_v * pow(det, 1.0 / 6.0);
 }
@@ -719,20 +700,14 @@ extern "C" int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
     const int nch = (int)chunks.size();
     VR_WS(chunks_d, ctx, int4, WS_D4, nch);
     VR_WS(coff_d, ctx, int, WS_D5, n_hosts + 1);
-    VR_WS(part, ctx, double, WS_D6, (int64_t)nch * 8);
-    VR_WS(hmean, ctx, double, WS_D7, (int64_t)n_hosts * 4);
+    VR_WS(part, ctx, double, WS_D6, (int64_t)nch * ELLV_PART);
     VR_HIP(ctx, hipMemcpyAsync(chunks_d, chunks.data(), nch * sizeof(int4), hipMemcpyHostToDevice, st));
     VR_HIP(ctx, hipMemcpyAsync(coff_d, coff.data(), (n_hosts + 1) * sizeof(int), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_ellv_mean, dim3(nch), dim3(256), 0, st, chunks_d, host_members, p->vx, p->vy, p->vz, p->mass,
-                       p->mass_value, part);
+    hipLaunchKernelGGL(k_ellv_sums, dim3(nch), dim3(256), 0, st, chunks_d, host_members, host_offsets, p->vx, p->vy,
+                       p->vz, p->mass, p->mass_value, part);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ellv_hostmean, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, coff_d, part, hmean);
-    VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ellv_disp, dim3(nch), dim3(256), 0, st, chunks_d, host_members, p->vx, p->vy, p->vz, p->mass,
-                       p->mass_value, hmean, part);
-    VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ellv_final, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, coff_d, part, hmean,
-                       alpha_v, ellv_host);
+    hipLaunchKernelGGL(k_ellv_final, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, coff_d, part, alpha_v,
+                       ellv_host);
     VR_LAUNCH_CHECK(ctx);
     // the host vectors above are copied asynchronously: wait before they go away
     VR_HIP(ctx, hipStreamSynchronize(st));
