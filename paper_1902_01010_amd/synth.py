@@ -297,15 +297,21 @@ def two_species(seed=5, n_side=256, star_per_halo_dm=0.662, disc_frac=0.7, star_
 
 
 def unbind_groups(seed=3, n_groups=50_000, n_max=2_000_000, box=100.0, m=1e8,
-                  contam_frac=0.2, n_sub=5):
+                  contam_frac=0.2, n_sub=5, sizes=None):
     """Groups for batched unbinding: C1-style NFW hosts (c = 10, r200 and
     sigma scaled by (N/1e5)^(1/3)) with Plummer subhalos of 1-10% of N, plus
-    round(0.2 N) contaminants at twice the local escape speed.  Returns the
-    particle set and the (offsets, members) group table."""
+    round(0.2 N) contaminants at twice the local escape speed.  Host sizes
+    are drawn from dN/dlnN ~ N^-0.9 on [20, n_max], or taken from `sizes`
+    (then n_groups = len(sizes)).  Returns the particle set and the
+    (offsets, members) group table."""
     rng = np.random.default_rng(seed)
-    a0, b0 = 20.0 ** -0.9, float(n_max) ** -0.9
-    u = rng.random(n_groups)
-    sizes = np.clip(np.floor((a0 - u * (a0 - b0)) ** (-1.0 / 0.9)), 20, n_max).astype(np.int64)
+    if sizes is None:
+        a0, b0 = 20.0 ** -0.9, float(n_max) ** -0.9
+        u = rng.random(n_groups)
+        sizes = np.clip(np.floor((a0 - u * (a0 - b0)) ** (-1.0 / 0.9)), 20, n_max).astype(np.int64)
+    else:
+        sizes = np.asarray(sizes, dtype=np.int64)
+        n_groups = len(sizes)
     scale = (sizes / 1e5) ** (1.0 / 3.0)
     r200, c = 0.3 * scale, 10.0
     sig = 200.0 * scale

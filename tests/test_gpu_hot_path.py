@@ -308,6 +308,29 @@ def test_unbind_not_converged(ctx, vr, ref, persistent):
     assert e.value.code == vr.VR_ERR_NOT_CONVERGED
 
 
+@pytest.mark.parametrize("order", ["largest_first", "largest_last"])
+def test_unbind_wide_groups_in_either_order(ctx, vr, ref, order):
+    """Groups of 4096 or more members take 1024-thread group passes while they
+    lead the table (the pipeline's size order); after a smaller group they
+    take the 256-thread passes.  Both orders match the oracle group by group."""
+    w = synth.unbind_groups(seed=8, sizes=[3600, 40, 4000, 300, 25, 120, 3500, 60])
+    off, mem = w.groups
+    sizes = np.diff(off)
+    assert (sizes >= 4096).sum() >= 2
+    idx = np.argsort(-sizes, kind="stable")
+    if order == "largest_last":
+        idx = idx[::-1]
+    parts = [mem[off[g]:off[g + 1]] for g in idx]
+    off2 = np.concatenate([[0], np.cumsum([len(q) for q in parts])]).astype(off.dtype)
+    mem2 = np.concatenate(parts).astype(mem.dtype)
+    w2 = dataclasses.replace(w, groups=(off2, mem2))
+    P, Pr = both(ctx, vr, ref, w2)
+    G, eps = w.params["G"], w.params["eps"]
+    exp = ref.unbind(Pr, off2, mem2, G, eps)
+    got = ctx.unbind(P, dev_tensor(off2), dev_tensor(mem2), G, eps, persistent=1)
+    _check_unbind(w2, exp, got)
+
+
 def test_unbind_persistent_launch_shapes_and_graph_reuse(ctx, vr, ref):
     """The persistent path with work items split into several j-ranges,
     small tiles and few workgroups per CU, called twice in a row with the
