@@ -147,16 +147,21 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
 #pragma unroll
     for (int g = 0; g < NG; ++g) gmx[g] = 0;
     int wg = 0;
-    const int ngv = (n_se + GS - 1) >> LGS;
+    // Slots from n_se up hold key 0, which never exceeds a kept key, so the
+    // group maxima need no bound checks (a group whose largest key is 0
+    // takes no replacement: no key is below 0).
+    for (int sl = n_se; sl < NG * GS; ++sl) heap[sl][lane] = 0;
+    // every selection below is a value select, not a branch on the lane's
+    // group index
     auto top_update = [&]() __attribute__((always_inline)) {
         uint64_t m = gmx[0];
         int mg = 0;
 #pragma unroll
-        for (int g = 1; g < NG; ++g)
-            if (g < ngv && gmx[g] > m) {
-                m = gmx[g];
-                mg = g;
-            }
+        for (int g = 1; g < NG; ++g) {
+            const bool gt = gmx[g] > m;
+            m = gt ? gmx[g] : m;
+            mg = gt ? g : mg;
+        }
         worst = m;
         wg = mg;
     };
@@ -167,35 +172,37 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
             const int sl = count++;
             heap[sl][lane] = key;
             const int g = sl >> LGS;
+            const bool first = (sl & (GS - 1)) == 0;
             bool up = false;
 #pragma unroll
-            for (int k = 0; k < NG; ++k)
-                if (k == g && ((sl & (GS - 1)) == 0 || key > gmx[k])) {
-                    gmx[k] = key;
-                    up = true;
-                }
-            if (up) gix = (gix & ~(uint64_t(63) << (6 * g))) | ((uint64_t)sl << (6 * g));
+            for (int k = 0; k < NG; ++k) {
+                const bool u = k == g && (first || key > gmx[k]);
+                gmx[k] = u ? key : gmx[k];
+                up = up || u;
+            }
+            const uint64_t fld = uint64_t(63) << (6 * g);
+            gix = up ? ((gix & ~fld) | ((uint64_t)sl << (6 * g))) : gix;
             if (count == n_se) top_update();
             return;
         }
         const int sl = (int)((gix >> (6 * wg)) & 63);
         heap[sl][lane] = key;
-        const int s0 = wg << LGS, s1 = min(s0 + GS, n_se);
+        const int s0 = wg << LGS;
         uint64_t v[GS];
 #pragma unroll
         for (int u = 0; u < GS; ++u) v[u] = heap[s0 + u][lane];
-        uint64_t m = key;
-        int ms = sl;
+        uint64_t m = v[0];
+        int ms = s0;
 #pragma unroll
-        for (int u = 0; u < GS; ++u)
-            if (s0 + u < s1 && v[u] > m) {
-                m = v[u];
-                ms = s0 + u;
-            }
+        for (int u = 1; u < GS; ++u) {
+            const bool gt = v[u] > m;
+            m = gt ? v[u] : m;
+            ms = gt ? s0 + u : ms;
+        }
 #pragma unroll
-        for (int k = 0; k < NG; ++k)
-            if (k == wg) gmx[k] = m;
-        gix = (gix & ~(uint64_t(63) << (6 * wg))) | ((uint64_t)ms << (6 * wg));
+        for (int k = 0; k < NG; ++k) gmx[k] = k == wg ? m : gmx[k];
+        const uint64_t fld = uint64_t(63) << (6 * wg);
+        gix = (gix & ~fld) | ((uint64_t)ms << (6 * wg));
         top_update();
     };
     // While a heap is not full it accepts only squared distances <= tau, a
@@ -266,10 +273,9 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                 while (take) {
                     const int t = __builtin_ctzll(take);
                     take &= take - 1;
-                    // |d| < 2^21: unsigned 32-bit squares, exact 64-bit sum
-                    const uint32_t ax = (uint32_t)abs((int)(cxs[t] - pxf)), ay = (uint32_t)abs((int)(cys[t] - pyf)),
-                                   az = (uint32_t)abs((int)(czs[t] - pzf));
-                    const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+                    // |d| < 2^21: signed 64-bit squares, exact sum
+                    const int dx = (int)(cxs[t] - pxf), dy = (int)(cys[t] - pyf), dz = (int)(czs[t] - pzf);
+                    const uint64_t d2 = (uint64_t)((int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz);
                     const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)crk[t];
                     if (count < n_se ? d2 <= tau : key < worst) insert(key);
                 }
