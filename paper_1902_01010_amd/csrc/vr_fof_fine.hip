@@ -11,8 +11,10 @@
 // coarse cells.  Exact integer bounds on the squared distance between two
 // fine-cell boxes skip far pairs and link pairs that are entirely within
 // ellx without testing particles; only the remaining pairs test particle
-// pairs, stopping at the first link.  Every decision uses the exact integer
-// squared distance in FP64 against ell2, as the plain definition does.
+// pairs, stopping at the first link.  Every decision compares an exact
+// integer squared distance d2 with l2c = ceil(ell2): for an integer d2,
+// d2 < ell2 exactly when d2 < l2c, so the integer test decides as the plain
+// definition's FP64 test does.
 #include "vr_grid.h"
 
 namespace vr {
@@ -130,7 +132,7 @@ __device__ __forceinline__ uint32_t coarse_rank(const uint64_t* __restrict__ occ
 // coarse cells x0 .. x1 in one row are cfs[rank(x0)] .. cfs[rank(x1 + 1)] - 1.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_link_fine(int64_t nfine, const uint4* __restrict__ frec,
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
-                                                   const uint32_t* __restrict__ sz, FineGrid G, double ell2,
+                                                   const uint32_t* __restrict__ sz, FineGrid G, int64_t l2c,
                                                    int* parent, unsigned xchunk, const uint32_t* __restrict__ cfs,
                                                    const uint64_t* __restrict__ occ, const uint32_t* __restrict__ pre) {
     const int64_t A = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x, xchunk) * blockDim.x + threadIdx.x;
@@ -225,8 +227,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 // exact bounds of the squared distance between the two boxes
                 const int64_t lx = gx ? (gx - 1) * f + 1 : 0, ly = gy ? (gy - 1) * f + 1 : 0,
                               lz = gz ? (gz - 1) * f + 1 : 0;
-                const double dmin = (double)(lx * lx + ly * ly + lz * lz);
-                if (dmin >= ell2) continue;
+                if (lx * lx + ly * ly + lz * lz >= l2c) continue;
                 const uint32_t b0 = fr[j].z, b1 = fr[j].w & 0x7fffffffu;
                 const int pb = parent[b0];
                 // b0's parent is A's (possibly stale) root: one component
@@ -236,16 +237,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 ra = uf_find(parent, ra);
                 if (ra == rb) continue;
                 const int64_t ux = (gx + 1) * f - 1, uy = (gy + 1) * f - 1, uz = (gz + 1) * f - 1;
-                const double dmax = (double)(ux * ux + uy * uy + uz * uz);
-                bool hit = dmax < ell2;
+                bool hit = ux * ux + uy * uy + uz * uz < l2c;
                 for (uint32_t pp = a0; pp < a1 && !hit; ++pp) {
                     const int px = (int)sx[pp], py = (int)sy[pp], pz = (int)sz[pp];
                     for (uint32_t q = b0; q < b1; ++q) {
                         const int dx = min_image((int)sx[q] - px, G.gb);
                         const int dy = min_image((int)sy[q] - py, G.gb);
                         const int dz = min_image((int)sz[q] - pz, G.gb);
-                        const double d2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
-                        if (d2 < ell2) { hit = true; break; }
+                        if ((int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz < l2c) {
+                            hit = true;
+                            break;
+                        }
                     }
                 }
                 if (hit) uf_union(parent, ra, rb);
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(64) void k_link_tile3(const int32_t* __restrict__ d
                                                    const uint32_t* __restrict__ fid, const uint64_t* __restrict__ key,
                                                    const uint32_t* __restrict__ sx, const uint32_t* __restrict__ sy,
                                                    const uint32_t* __restrict__ sz,
-                                                   const uint32_t* __restrict__ row_start, FineGrid G, double ell2,
+                                                   const uint32_t* __restrict__ row_start, FineGrid G, int64_t l2c,
                                                    float tq, int* parent, unsigned xchunk, int certain) {
     __shared__ __align__(16) int cgx[64];
     __shared__ __align__(16) int cgy[64];
@@ -460,9 +462,9 @@ __global__ __launch_bounds__(64) void k_link_tile3(const int32_t* __restrict__ d
             const int64_t gz = abs(min_image(cgz[j] - gaz, fbits));
             const int64_t lx = gx ? (gx - 1) * f + 1 : 0, ly = gy ? (gy - 1) * f + 1 : 0,
                           lz = gz ? (gz - 1) * f + 1 : 0;
-            if ((double)(lx * lx + ly * ly + lz * lz) >= ell2) continue;
+            if (lx * lx + ly * ly + lz * lz >= l2c) continue;
             const int64_t ux = (gx + 1) * f - 1, uy = (gy + 1) * f - 1, uz = (gz + 1) * f - 1;
-            const bool inside = (double)(ux * ux + uy * uy + uz * uz) < ell2;
+            const bool inside = ux * ux + uy * uy + uz * uz < l2c;
             if (inside != (certain != 0)) continue;
             int rb = crt[j];
             if (rb == ra) continue;
@@ -478,8 +480,10 @@ __global__ __launch_bounds__(64) void k_link_tile3(const int32_t* __restrict__ d
                     const int dx = min_image((int)sx[q] - px, G.gb);
                     const int dy = min_image((int)sy[q] - py, G.gb);
                     const int dz = min_image((int)sz[q] - pz, G.gb);
-                    const double d2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
-                    if (d2 < ell2) { hit = true; break; }
+                    if ((int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz < l2c) {
+                        hit = true;
+                        break;
+                    }
                 }
             }
             if (hit) uf_union(parent, ra, rb);
@@ -620,15 +624,16 @@ int fof3d_fine(vr_ctx* ctx, const vr_particles* p, double ell2, int s, int32_t* 
     // e2 < ell2 / f^2, compared in FP32 against a threshold rounded up
     const double fk = std::ldexp(1.0, k);
     const float tq = (float)(ell2 / (fk * fk) * (1.0 + 1e-6)) + 1e-6f;
+    const int64_t l2c = (int64_t)std::ceil(ell2);  // ell2 < 2^40: exact
 #define VR_TILE3(CERTAIN)                                                                                        \
     VR_TIMED(ctx, "fof_link3d", st, 0,                                                                           \
              hipLaunchKernelGGL(k_link_tile3, dim3((unsigned)ndense), dim3(64), 0, st, dense, cfs, fine_start, fid, \
-                                key, sx, sy, sz, row_start, G, ell2, tq, parent, (unsigned)ctx->xcd_chunk, CERTAIN)); \
+                                key, sx, sy, sz, row_start, G, l2c, tq, parent, (unsigned)ctx->xcd_chunk, CERTAIN)); \
     VR_LAUNCH_CHECK(ctx)
     if (ndense > 0) { VR_TILE3(1); }
     VR_TIMED(ctx, "fof_link3d", st, n,
              hipLaunchKernelGGL(k_link_fine, dim3(grid_for(nfine, 256)), dim3(256), 0, st, (int64_t)nfine, frec, sx,
-                                sy, sz, G, ell2, parent, (unsigned)ctx->xcd_chunk, cfs,
+                                sy, sz, G, l2c, parent, (unsigned)ctx->xcd_chunk, cfs,
                                 reinterpret_cast<const uint64_t*>(occ), pre));
     VR_LAUNCH_CHECK(ctx);
     if (ndense > 0) { VR_TILE3(0); }
