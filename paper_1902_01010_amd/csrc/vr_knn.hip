@@ -210,6 +210,8 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
     // n_se nearest all meet it); NO_BOUND until such a bound is found.
     constexpr uint64_t NO_BOUND = ~0ull >> POS_BITS;
     uint64_t tau = NO_BOUND;
+    // the same bound on keys: d2 <= tau exactly when key < (tau + 1) << POS_BITS
+    uint64_t tau_key = ~0ull;
 
     // Stages the members [c0, min(c0 + 64, t_end)) of a leaf in LDS for the
     // unwrapped (no minimum image) scan; padding slots sit far away.
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                     const int dx = (int)(cxs[t] - pxf), dy = (int)(cys[t] - pyf), dz = (int)(czs[t] - pzf);
                     const uint64_t d2 = (uint64_t)((int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz);
                     const uint64_t key = (d2 << POS_BITS) | (uint64_t)(uint32_t)crk[t];
-                    if (count < n_se ? d2 <= tau : key < worst) insert(key);
+                    if (key < (count < n_se ? tau_key : worst)) insert(key);
                 }
                 __builtin_amdgcn_wave_barrier();
                 continue;
@@ -434,6 +436,7 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
 #pragma unroll
                 for (int k = 7; k >= 0; --k)
                     if (cnt[k] >= (uint32_t)n_se) tau = (uint64_t)((double)thr[k] * (1.0 + 1e-6)) + 1;
+                tau_key = tau >= NO_BOUND ? ~0ull : (tau + 1) << POS_BITS;
             }
             // the leaves of the queries themselves first: they fill every
             // heap with near neighbours, so the walk prunes from its start
