@@ -23,9 +23,12 @@ def test_autotune_sweep_cache_and_parity(tmp_path, ref):
     assert knobs["unbind_tile"] in (64, 128, 256, 512, 1024)
     assert knobs["knn_leaf"] in (64, 96, 128, 192, 256)
     assert len(data["unbind_sweep"]) == 60 and len(data["knn_sweep"]) == 20
-    best = min(data["unbind_sweep"], key=lambda r: r["ms"])
-    assert (best["tile"], best["jchunk"], best["bpc"]) == (knobs["unbind_tile"], knobs["unbind_jchunk"],
-                                                          knobs["unbind_bpc"])
+    # the picked setting is a fastest one (times are written to 6 digits,
+    # so several may print the same minimum)
+    fastest = min(r["ms"] for r in data["unbind_sweep"])
+    picked = [r for r in data["unbind_sweep"]
+              if (r["tile"], r["jchunk"], r["bpc"]) == (knobs["unbind_tile"], knobs["unbind_jchunk"], knobs["unbind_bpc"])]
+    assert len(picked) == 1 and picked[0]["ms"] <= fastest * (1 + 1e-5)
     # a fresh context takes the cached knobs without sweeping
     ctx2 = vr.Context(0)
     assert ctx2.autotune(path) == knobs
