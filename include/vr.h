@@ -86,6 +86,10 @@ int vr_set_timing(vr_ctx* ctx, int enabled);
  * "unbind_jchunk" j-range of one potential work item (256..65536, 4096)
  * "unbind_bpc"    workgroups per CU of the persistent potential kernel
  *                 (0..8, 0 = as many as fit)
+ * "unbind_wide"   size class of the persistent schedule: the leading groups
+ *                 with at least this many members (up to the first smaller
+ *                 one) take a 1024-thread workgroup per pass, the others
+ *                 256 threads (256..2^30, 4096)
  * "xcd_chunk"     consecutive workgroups of the kNN and linking sweeps kept
  *                 on one XCD (0..4096, 64; 0 = the dispatcher's order)
  * Returns VR_ERR_INVALID_ARG for an unknown knob or a value out of range;
@@ -96,8 +100,9 @@ int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value);
 /* Autotuner of those knobs.  Unless force is set and if cache_path (may be
  * NULL) names a readable cache written for this GPU architecture, its knobs
  * are applied and nothing is timed.  Otherwise the call times vr_unbind
- * (persistent) over unbind_tile x unbind_jchunk x unbind_bpc on a synthetic
- * heavy-tailed group set (sizes 32 .. 32768) and vr_local_vdensity over
+ * (persistent) over unbind_tile x unbind_jchunk x unbind_bpc, then over
+ * unbind_wide at the fastest of those, on a synthetic heavy-tailed group set
+ * (sizes 32 .. 32768) and vr_local_vdensity over
  * knn_leaf x xcd_chunk on synthetic hosts (2000 cusped halos whose sizes
  * follow dN/dlnN ~ N^-0.9 on [256, 2^21], 6.6 M members), applies the
  * fastest settings and writes them, with every timing, to cache_path as

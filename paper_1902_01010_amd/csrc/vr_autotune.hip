@@ -4,6 +4,7 @@
 //
 // Knobs never change integer results (FP64 sums only through their order):
 //   unbind_tile, unbind_jchunk, unbind_bpc   persistent potential schedule
+//   unbind_wide                              size class of the group kernel
 //   knn_leaf, xcd_chunk                      neighbour-search tree and order
 #include "vr_internal.h"
 
@@ -97,7 +98,7 @@ __global__ void k_at_halos(int ng, const int32_t* __restrict__ off, int gb, doub
 }
 
 struct Knobs {
-    int unbind_tile = 256, unbind_jchunk = 4096, unbind_bpc = 0, knn_leaf = 64, xcd_chunk = 64;
+    int unbind_tile = 256, unbind_jchunk = 4096, unbind_bpc = 0, unbind_wide = 4096, knn_leaf = 64, xcd_chunk = 64;
 };
 
 bool read_cache(const char* path, const char* arch, Knobs& k) {
@@ -116,13 +117,15 @@ bool read_cache(const char* path, const char* arch, Knobs& k) {
         return true;
     };
     return get("unbind_tile", k.unbind_tile) && get("unbind_jchunk", k.unbind_jchunk) &&
-           get("unbind_bpc", k.unbind_bpc) && get("knn_leaf", k.knn_leaf) && get("xcd_chunk", k.xcd_chunk);
+           get("unbind_bpc", k.unbind_bpc) && get("unbind_wide", k.unbind_wide) && get("knn_leaf", k.knn_leaf) &&
+           get("xcd_chunk", k.xcd_chunk);
 }
 
 void apply(vr_ctx* ctx, const Knobs& k) {
     ctx->tuned_tile = k.unbind_tile;
     ctx->unbind_jchunk = k.unbind_jchunk;
     ctx->unbind_bpc = k.unbind_bpc;
+    ctx->unbind_wide = k.unbind_wide;
     ctx->knn_leaf = k.knn_leaf;
     ctx->xcd_chunk = k.xcd_chunk;
 }
@@ -223,6 +226,7 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
         return VR_OK;
     };
     float best_ub = 1e30f;
+    ctx->unbind_wide = best.unbind_wide;  // the default size class while the schedule is swept
     const int tiles[] = {64, 128, 256, 512, 1024};
     const int jchunks[] = {1024, 4096, 16384};
     const int bpcs[] = {0, 1, 2, 4};
@@ -244,6 +248,23 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
                     best.unbind_bpc = b;
                 }
             }
+    apply(ctx, best);
+    // then the size class at that schedule: the group kernel's 1024-thread
+    // form for the leading groups from 1024 members up, ..., or for none
+    std::ostringstream wlog;
+    const int wides[] = {1024, 2048, 4096, 8192, 16384, 1 << 30};
+    float best_w = 1e30f;
+    for (int wm : wides) {
+        ctx->unbind_wide = wm;
+        float ms = 0;
+        int rc = time_unbind(&ms);
+        if (rc) { ctx->timing = saved_timing; return rc; }
+        wlog << "    {\"wide\": " << wm << ", \"ms\": " << ms << "},\n";
+        if (ms < best_w) {
+            best_w = ms;
+            best.unbind_wide = wm;
+        }
+    }
     apply(ctx, best);
 
     // ---- neighbour search: 2000 hosts, dN/dlnN ~ N^-0.9 on [256, 2^21] -----
@@ -330,17 +351,20 @@ extern "C" int vr_autotune(vr_ctx* ctx, const char* cache_path, int force) {
     if (cache_path) {
         std::ofstream f(cache_path);
         if (!f) return set_err(ctx, VR_ERR_INVALID_ARG, "cannot write %s", cache_path);
-        std::string a = log.str(), b = klog.str();
+        std::string a = log.str(), b = klog.str(), c = wlog.str();
         if (!a.empty()) a.erase(a.size() - 2, 1);  // trailing comma
         if (!b.empty()) b.erase(b.size() - 2, 1);
+        if (!c.empty()) c.erase(c.size() - 2, 1);
         f << "{\n  \"arch\": \"" << arch << "\",\n"
           << "  \"unbind_tile\": " << best.unbind_tile << ",\n  \"unbind_jchunk\": " << best.unbind_jchunk
-          << ",\n  \"unbind_bpc\": " << best.unbind_bpc << ",\n  \"knn_leaf\": " << best.knn_leaf
+          << ",\n  \"unbind_bpc\": " << best.unbind_bpc << ",\n  \"unbind_wide\": " << best.unbind_wide
+          << ",\n  \"knn_leaf\": " << best.knn_leaf
           << ",\n  \"xcd_chunk\": " << best.xcd_chunk << ",\n"
           << "  \"unbind_workload\": \"" << ng << " groups, " << nu << " particles, sizes 32..32768\",\n"
           << "  \"knn_workload\": \"" << nh << " Hernquist hosts, dN/dlnN ~ N^-0.9 on [256, 2^21], " << nk
           << " members, n_se 32, n_v 8\",\n"
-          << "  \"unbind_sweep\": [\n" << a << "  ],\n  \"knn_sweep\": [\n" << b << "  ]\n}\n";
+          << "  \"unbind_sweep\": [\n" << a << "  ],\n  \"unbind_wide_sweep\": [\n" << c
+          << "  ],\n  \"knn_sweep\": [\n" << b << "  ]\n}\n";
     }
     return VR_OK;
 }

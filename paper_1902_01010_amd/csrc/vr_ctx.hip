@@ -228,6 +228,10 @@ int vr_tune(vr_ctx* ctx, const char* knob, int value) {
     } else if (k == "unbind_bpc") {
         if (value < 0 || value > 8) return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_bpc must be in 0..8");
         ctx->unbind_bpc = value;
+    } else if (k == "unbind_wide") {
+        if (value < 256 || value > (1 << 30))
+            return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unbind_wide must be in 256..2^30");
+        ctx->unbind_wide = value;
     } else {
         return vr::set_err(ctx, VR_ERR_INVALID_ARG, "unknown knob '%s'", knob);
     }
@@ -241,6 +245,7 @@ int vr_get_tune(const vr_ctx* ctx, const char* knob, int* value) {
     else if (k == "unbind_tile") *value = ctx->tuned_tile ? ctx->tuned_tile : 256;
     else if (k == "unbind_jchunk") *value = ctx->unbind_jchunk;
     else if (k == "unbind_bpc") *value = ctx->unbind_bpc;
+    else if (k == "unbind_wide") *value = ctx->unbind_wide;
     else if (k == "xcd_chunk") *value = ctx->xcd_chunk;
     else return VR_ERR_INVALID_ARG;
     return VR_OK;

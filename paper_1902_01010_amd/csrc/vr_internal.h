@@ -44,6 +44,7 @@ struct vr_ctx {
     int knn_leaf = 64;      // members per leaf of the neighbour-search tree
     int unbind_jchunk = 4096;
     int unbind_bpc = 0;     // workgroups per CU of the persistent potential kernel (0 = occupancy limit)
+    int unbind_wide = 4096; // members from which a leading group takes the 1024-thread group kernel
     int xcd_chunk = 64;     // consecutive workgroups per XCD in the neighbour sweeps (0 = hardware order)
     // while timing: candidate distances of the neighbour search (device counter)
     unsigned long long* knn_cand = nullptr;

@@ -83,12 +83,12 @@ __global__ void k_ub_init(int ng, int64_t M, const int32_t* __restrict__ off, co
     phi[i] = NAN;
 }
 
-// Per-group state, and nbig = the first group with fewer than BIG_GROUP
+// Per-group state, and nbig = the first group with fewer than wide_min
 // members (*nbig holds ng beforehand): the leading groups up to there take
 // the wide group kernel.
-constexpr int BIG_GROUP = 4096;
-__global__ void k_ub_state(int ng, const int32_t* __restrict__ off, int n_min, Removed Rm, int* __restrict__ cnt,
-                           int* __restrict__ state, int32_t* __restrict__ iters, int* __restrict__ nbig) {
+__global__ void k_ub_state(int ng, const int32_t* __restrict__ off, int n_min, int wide_min, Removed Rm,
+                           int* __restrict__ cnt, int* __restrict__ state, int32_t* __restrict__ iters,
+                           int* __restrict__ nbig) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const int n = off[g + 1] - off[g];
@@ -98,7 +98,7 @@ __global__ void k_ub_state(int ng, const int32_t* __restrict__ off, int n_min, R
     Rm.nrm[g] = 0;
     Rm.since[g] = 0;
     Rm.mode[g] = 0;
-    if (n < BIG_GROUP) atomicMin(nbig, g);
+    if (n < wide_min) atomicMin(nbig, g);
 }
 
 __global__ void k_ub_zero(int na, const int* __restrict__ active, const int32_t* __restrict__ off,
@@ -772,8 +772,8 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
         int rc = fill_i32(ctx, nbig, n_groups, 1, st);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_ub_state, dim3(grid_for(n_groups, 256)), dim3(256), 0, st, n_groups, offsets, up->n_min, Rm,
-                       cnt, state, iters, nbig);
+    hipLaunchKernelGGL(k_ub_state, dim3(grid_for(n_groups, 256)), dim3(256), 0, st, n_groups, offsets, up->n_min,
+                       ctx->unbind_wide, Rm, cnt, state, iters, nbig);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ub_init, dim3(grid_for(M, 256)), dim3(256), 0, st, n_groups, (int64_t)M, offsets, members,
                        p->qx, p->qy, p->qz, p->vx, p->vy, p->vz, p->mass, p->grid_bits, W, bound, phi);

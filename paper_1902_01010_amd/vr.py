@@ -31,7 +31,7 @@ ENTRY_POINTS = (
 )
 
 MLP_PARAMS = 9217
-TUNE_KNOBS = ("unbind_tile", "unbind_jchunk", "unbind_bpc", "knn_leaf", "xcd_chunk")
+TUNE_KNOBS = ("unbind_tile", "unbind_jchunk", "unbind_bpc", "unbind_wide", "knn_leaf", "xcd_chunk")
 
 
 class VrError(RuntimeError):

@@ -29,6 +29,11 @@ def test_autotune_sweep_cache_and_parity(tmp_path, ref):
     picked = [r for r in data["unbind_sweep"]
               if (r["tile"], r["jchunk"], r["bpc"]) == (knobs["unbind_tile"], knobs["unbind_jchunk"], knobs["unbind_bpc"])]
     assert len(picked) == 1 and picked[0]["ms"] <= fastest * (1 + 1e-5)
+    # the size class is swept at that schedule; the fastest one is kept
+    wides = data["unbind_wide_sweep"]
+    assert [r["wide"] for r in wides] == [1024, 2048, 4096, 8192, 16384, 1 << 30]
+    assert knobs["unbind_wide"] in [r["wide"] for r in wides]
+    assert min(r["ms"] for r in wides if r["wide"] == knobs["unbind_wide"]) <= min(r["ms"] for r in wides) * (1 + 1e-5)
     # a fresh context takes the cached knobs without sweeping
     ctx2 = vr.Context(0)
     assert ctx2.autotune(path) == knobs

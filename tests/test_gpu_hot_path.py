@@ -331,6 +331,32 @@ def test_unbind_wide_groups_in_either_order(ctx, vr, ref, order):
     _check_unbind(w2, exp, got)
 
 
+@pytest.mark.parametrize("wide", [256, 1 << 30])
+def test_unbind_size_class_knob(ctx, vr, ref, wide):
+    """The size-class knob moves the cut between the 1024- and 256-thread
+    group passes (256: every leading group of >= 256 members is wide; 2^30:
+    none is); the bound sets match the oracle either way, and values outside
+    the knob's range are refused."""
+    w = synth.unbind_groups(seed=8, sizes=[3600, 4000, 3500, 300, 120, 60, 40, 25])
+    off, mem = w.groups
+    P, Pr = both(ctx, vr, ref, w)
+    G, eps = w.params["G"], w.params["eps"]
+    exp = ref.unbind(Pr, off, mem, G, eps)
+    saved = ctx.get_tune("unbind_wide")
+    try:
+        ctx.tune("unbind_wide", wide)
+        assert ctx.get_tune("unbind_wide") == wide
+        got = ctx.unbind(P, dev_tensor(off), dev_tensor(mem), G, eps, persistent=1)
+    finally:
+        ctx.tune("unbind_wide", saved)
+    _check_unbind(w, exp, got)
+    for bad in (255, (1 << 30) + 1):
+        with pytest.raises(vr.VrError) as e:
+            ctx.tune("unbind_wide", bad)
+        assert e.value.code == vr.VR_ERR_INVALID_ARG
+    assert ctx.get_tune("unbind_wide") == saved
+
+
 def test_unbind_persistent_launch_shapes_and_graph_reuse(ctx, vr, ref):
     """The persistent path with work items split into several j-ranges,
     small tiles and few workgroups per CU, called twice in a row with the
