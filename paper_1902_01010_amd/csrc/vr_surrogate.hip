@@ -22,7 +22,8 @@ constexpr int OW1 = 0, OB1 = OW1 + NF * H, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3
               OW4 = OB3 + H, OB4 = OW4 + H, NPARAM = OB4 + 1;
 static_assert(NPARAM == VR_MLP_PARAMS, "parameter layout");
 
-typedef short bf4 __attribute__((ext_vector_type(4)));     // 4 BF16 MFMA operands
+typedef short bf8 __attribute__((ext_vector_type(8)));     // bits of 8 BF16 MFMA operands
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));   // the same, as the MFMA operand type
 typedef float f16v __attribute__((ext_vector_type(16)));   // 32x32 accumulator slice of one lane
 
 // FP32 -> BF16 bits, round to nearest even; NaN stays a (quiet) NaN.
@@ -34,8 +35,14 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ f16v mfma(bf4 a, bf4 b, f16v c) {
-    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+// D (32x32) += A (32x16) B (16x32) on gfx950's BF16 matrix cores: lane l
+// gives row l%32 of A and column l%32 of B, eight K entries each, and the
+// hardware pairs slot s of A's lane half h with slot s of B's lane half h.
+// Which K index a (half, slot) stands for is the caller's choice, the same
+// for both operands.
+__device__ __forceinline__ f16v mfma(bf8 a, bf8 b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0,
+                                                    0);
 }
 
 // ============================================================================
@@ -362,30 +369,37 @@ __global__ __launch_bounds__(256) void k_rs_features(int64_t m, const int32_t* _
 // ============================================================================
 // network
 // ============================================================================
-// BF16 weights pre-arranged as MFMA A operands, one 8-byte group per lane:
-//  fwd1 [2 row tiles][2 k-blocks][64 lanes]   W1^T (inputs 12..15 are zero)
-//  fwd2 [2][8][64], fwd3 [2][8][64]          W2^T, W3^T
-//  bwd3 [2][8][64], bwd2 [2][8][64]          W3, W2 (propagate errors down)
-// For lane l of row tile t and k-block kb the group holds the four entries
-// (row 32 t + l % 32, columns 8 kb + 4 (l / 32) + 0..3) of the matrix.
-constexpr int PK_FWD1 = 0, PK_FWD2 = PK_FWD1 + 2 * 2 * 64, PK_FWD3 = PK_FWD2 + 2 * 8 * 64,
-              PK_BWD3 = PK_FWD3 + 2 * 8 * 64, PK_BWD2 = PK_BWD3 + 2 * 8 * 64, PK_TOTAL = PK_BWD2 + 2 * 8 * 64;
+// K order of the layers: slot s of lane half h in k-block kb is index
+// 16 kb + 8 (s / 4) + 4 h + s % 4.  That is where a lane's accumulator
+// entries of one 32-unit tile already sit (entry j of tile t is unit
+// 32 t + 8 (j / 4) + 4 h + j % 4, i.e. k-block 2 t + j / 8, slot j % 8), so
+// one layer's output becomes the next layer's B operand in registers.
+// BF16 weights pre-arranged as MFMA A operands, one 16-byte group per lane:
+//  fwd1 [2 row tiles][1 k-block][64 lanes]   W1^T (inputs 12..15 are zero)
+//  fwd2 [2][4][64], fwd3 [2][4][64]          W2^T, W3^T
+//  bwd3 [2][4][64], bwd2 [2][4][64]          W3, W2 (propagate errors down)
+// For lane l of row tile t and k-block kb the group holds row 32 t + l % 32
+// of the matrix at the eight columns of that K order.
+constexpr int PK_FWD1 = 0, PK_FWD2 = PK_FWD1 + 2 * 1 * 64, PK_FWD3 = PK_FWD2 + 2 * 4 * 64,
+              PK_BWD3 = PK_FWD3 + 2 * 4 * 64, PK_BWD2 = PK_BWD3 + 2 * 4 * 64, PK_TOTAL = PK_BWD2 + 2 * 4 * 64;
 
-__global__ void k_mlp_pack(const float* __restrict__ w, bf4* __restrict__ pk) {
+__device__ __forceinline__ int layer_k(int kb, int half, int s) { return 16 * kb + 8 * (s >> 2) + 4 * half + (s & 3); }
+
+__global__ void k_mlp_pack(const float* __restrict__ w, bf8* __restrict__ pk) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= PK_TOTAL) return;
     int base, nkb, which;
-    if (e < PK_FWD2) { base = PK_FWD1; nkb = 2; which = 1; }
-    else if (e < PK_FWD3) { base = PK_FWD2; nkb = 8; which = 2; }
-    else if (e < PK_BWD3) { base = PK_FWD3; nkb = 8; which = 3; }
-    else if (e < PK_BWD2) { base = PK_BWD3; nkb = 8; which = -3; }
-    else { base = PK_BWD2; nkb = 8; which = -2; }
+    if (e < PK_FWD2) { base = PK_FWD1; nkb = 1; which = 1; }
+    else if (e < PK_FWD3) { base = PK_FWD2; nkb = 4; which = 2; }
+    else if (e < PK_BWD3) { base = PK_FWD3; nkb = 4; which = 3; }
+    else if (e < PK_BWD2) { base = PK_BWD3; nkb = 4; which = -3; }
+    else { base = PK_BWD2; nkb = 4; which = -2; }
     const int r = e - base;
     const int lane = r & 63, kb = (r >> 6) % nkb, t = (r >> 6) / nkb;
     const int row = 32 * t + (lane & 31);
-    bf4 v;
-    for (int j = 0; j < 4; ++j) {
-        const int col = 8 * kb + 4 * (lane >> 5) + j;
+    bf8 v;
+    for (int j = 0; j < 8; ++j) {
+        const int col = layer_k(kb, lane >> 5, j);
         float x;
         if (which == 1) x = col < NF ? w[OW1 + col * H + row] : 0.f;          // W1^T[out=row][in=col]
         else if (which == 2) x = w[OW2 + col * H + row];                        // W2^T
@@ -400,24 +414,24 @@ __global__ void k_mlp_pack(const float* __restrict__ w, bf4* __restrict__ pk) {
 // Accumulator row of entry j of lane l in a 32x32 tile: 8 (j/4) + 4 (l/32) + j%4.
 __device__ __forceinline__ int acc_row(int j, int lane) { return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3); }
 
-// The inputs of a 32-row tile as B operands: lane l holds row r0 + l%32,
-// inputs 4 (l/32) + 0..3 (k-block 0) and 8 + 4 (l/32) + 0..3 (k-block 1;
-// inputs 12..15 do not exist and are zero).  bad = some input is NaN.
+// The inputs of a 32-row tile as the B operand of the single k-block: lane
+// l holds row r0 + l%32, inputs 4 (l/32) + 0..3 in slots 0..3 and
+// 8 + 4 (l/32) + 0..3 in slots 4..7 (inputs 12..15 do not exist and are
+// zero).  bad = some input is NaN.
 __device__ __forceinline__ void load_inputs(const uint16_t* __restrict__ feat, int64_t row, bool valid, int lane,
-                                            bf4 in[2], bool& bad) {
+                                            bf8& in, bool& bad) {
     const int half = lane >> 5;
-    in[0] = bf4{0, 0, 0, 0};
-    in[1] = bf4{0, 0, 0, 0};
+    in = bf8{0, 0, 0, 0, 0, 0, 0, 0};
     bad = false;
     if (!valid) return;
     const uint16_t* fr = feat + row * NF;
     for (int j = 0; j < 4; ++j) {
         const uint16_t a = fr[4 * half + j];
-        in[0][j] = (short)a;
+        in[j] = (short)a;
         bad |= (a & 0x7FFFu) > 0x7F80u;
         if (half == 0) {
             const uint16_t b = fr[8 + j];
-            in[1][j] = (short)b;
+            in[4 + j] = (short)b;
             bad |= (b & 0x7FFFu) > 0x7F80u;
         }
     }
@@ -426,7 +440,7 @@ __device__ __forceinline__ void load_inputs(const uint16_t* __restrict__ feat, i
 // One dense layer on a 32-row tile: out[t] (t = 2 row tiles of 32 hidden
 // units) = bias + W^T x, x given as nkb B-operand k-blocks.
 template <int NKB>
-__device__ __forceinline__ void layer(const bf4* __restrict__ pk, const float* __restrict__ bias, const bf4* x,
+__device__ __forceinline__ void layer(const bf8* __restrict__ pk, const float* __restrict__ bias, const bf8* x,
                                       int lane, f16v out[2]) {
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -439,25 +453,42 @@ __device__ __forceinline__ void layer(const bf4* __restrict__ pk, const float* _
     }
 }
 
-// ReLU, then the BF16 B operands of the next layer: k-block 4 t + r of the
-// next layer is entries 4 r .. 4 r + 3 of row tile t.
-__device__ __forceinline__ void relu_to_operands(f16v a[2], bf4 x[8]) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            a[t][j] = fmaxf(a[t][j], 0.f);
-            x[4 * t + (j >> 2)][j & 3] = (short)bf16_bits(a[t][j]);
-        }
+// max(x, 0) for every non-NaN x in one integer max: a set sign bit is a
+// negative integer (-0 gives +0).
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// Two FP32 values as packed BF16 bits (gfx950's v_cvt_pk_bf16_f32: round to
+// nearest even, as bf16_bits for every non-NaN value).
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){lo, hi}, bf2v));
 }
 
-// The BF16 B operands of a signed tile (errors flowing down): no ReLU.
-__device__ __forceinline__ void to_operands(const f16v a[2], bf4 x[8]) {
+// The BF16 B operands of the next layer (ReLU first when with_relu is set):
+// entry j of row tile t is slot j % 8 of k-block 2 t + j / 8.
+template <bool with_relu>
+__device__ __forceinline__ void operands(f16v a[2], bf8 x[4]) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[4 * t + (j >> 2)][j & 3] = (short)bf16_bits(a[t][j]);
+        for (int b = 0; b < 2; ++b) {
+            uint32_t p[4];
+#pragma unroll
+            for (int s = 0; s < 8; s += 2) {
+                const int j = 8 * b + s;
+                if (with_relu) {
+                    a[t][j] = relu(a[t][j]);
+                    a[t][j + 1] = relu(a[t][j + 1]);
+                }
+                p[s >> 1] = bf16_pair(a[t][j], a[t][j + 1]);
+            }
+            x[2 * t + b] = __builtin_bit_cast(bf8, (uint4){p[0], p[1], p[2], p[3]});
+        }
 }
+__device__ __forceinline__ void relu_to_operands(f16v a[2], bf8 x[4]) { operands<true>(a, x); }
+// errors flowing down: signed, no ReLU
+__device__ __forceinline__ void to_operands(f16v a[2], bf8 x[4]) { operands<false>(a, x); }
 
 __device__ __forceinline__ float out_layer(const float* __restrict__ w, const f16v h3[2], int lane) {
     float y = 0.f;
@@ -470,7 +501,7 @@ __device__ __forceinline__ float out_layer(const float* __restrict__ w, const f1
 }
 
 // Inference: every wavefront takes 32-row tiles until none are left.
-__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w, const bf4* __restrict__ pk,
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w, const bf8* __restrict__ pk,
                                                      int64_t m, const uint16_t* __restrict__ feat,
                                                      float* __restrict__ out) {
     const int lane = __lane_id();
@@ -480,20 +511,20 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w
     for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
         const int64_t row = tile * 32 + (lane & 31);
         const bool valid = row < m;
-        bf4 x0[2];
+        bf8 x0;
         bool bad;
         load_inputs(feat, row, valid, lane, x0, bad);
         f16v a[2];
-        bf4 x[8];
-        layer<2>(pk + PK_FWD1, w + OB1, x0, lane, a);
+        bf8 x[4];
+        layer<1>(pk + PK_FWD1, w + OB1, &x0, lane, a);
         relu_to_operands(a, x);
-        layer<8>(pk + PK_FWD2, w + OB2, x, lane, a);
+        layer<4>(pk + PK_FWD2, w + OB2, x, lane, a);
         relu_to_operands(a, x);
-        layer<8>(pk + PK_FWD3, w + OB3, x, lane, a);
+        layer<4>(pk + PK_FWD3, w + OB3, x, lane, a);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) a[t][j] = fmaxf(a[t][j], 0.f);
+            for (int j = 0; j < 16; ++j) a[t][j] = relu(a[t][j]);
         const float y = out_layer(w, a, lane);
         bad |= __shfl_xor((int)bad, 32, 64) != 0;
         if (valid && lane < 32) out[row] = bad ? NAN : y;
@@ -515,8 +546,9 @@ __device__ __forceinline__ void stash(const f16v a[2], uint16_t* tile, int lane)
 }
 
 // dW^T[out][in] += sum over the tile's 32 rows of delta[out][row] act[in][row]
-// (MFMA with the rows as the K dimension), added into the LDS gradient at
-// W[in][out]; inputs in >= nin are skipped.
+// (MFMA with the rows as the K dimension, slot s of lane half h in k-block
+// kb = row 16 kb + 8 h + s), added into the LDS gradient at W[in][out];
+// inputs in >= nin are skipped.
 __device__ __forceinline__ void weight_grad(const uint16_t* dl, const uint16_t* ac, int nin, float* gw, int lane) {
     const int half = lane >> 5, l32 = lane & 31;
     const int ntin = (nin + 31) / 32;
@@ -527,9 +559,9 @@ __device__ __forceinline__ void weight_grad(const uint16_t* dl, const uint16_t* 
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[j] = 0.f;
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                const bf4 a = *reinterpret_cast<const bf4*>(dl + (32 * t + l32) * 32 + 8 * kb + 4 * half);
-                const bf4 b = *reinterpret_cast<const bf4*>(ac + (32 * u + l32) * 32 + 8 * kb + 4 * half);
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf8 a = *reinterpret_cast<const bf8*>(dl + (32 * t + l32) * 32 + 16 * kb + 8 * half);
+                const bf8 b = *reinterpret_cast<const bf8*>(ac + (32 * u + l32) * 32 + 16 * kb + 8 * half);
                 acc = mfma(a, b, acc);
             }
             const int in = 32 * u + l32;
@@ -550,7 +582,7 @@ __device__ __forceinline__ void bias_grad(const f16v d[2], float* gb, int lane, 
 // Gradient of the mean squared error over a batch of m rows (rows[] picks
 // them from feat/target, or rows 0..m-1): each workgroup takes 128-row tiles
 // and writes its partial sums (and its squared-error sum) to part[blockIdx].
-__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, const bf4* __restrict__ pk, int64_t m,
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, const bf8* __restrict__ pk, int64_t m,
                                                   const uint16_t* __restrict__ feat, const int32_t* __restrict__ rows,
                                                   const float* __restrict__ target, float* __restrict__ part) {
     __shared__ float gacc[NSLOT];
@@ -569,20 +601,20 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
         const bool valid = b < m;
         const int64_t row = valid ? (rows ? (int64_t)rows[b] : b) : 0;
 
-        bf4 x0[2];
+        bf8 x0;
         bool bad;
         load_inputs(feat, row, valid, lane, x0, bad);
         f16v h1[2], h2[2], h3[2];
-        bf4 x1[8], x2[8];
-        layer<2>(pk + PK_FWD1, w + OB1, x0, lane, h1);
+        bf8 x1[4], x2[4];
+        layer<1>(pk + PK_FWD1, w + OB1, &x0, lane, h1);
         relu_to_operands(h1, x1);
-        layer<8>(pk + PK_FWD2, w + OB2, x1, lane, h2);
+        layer<4>(pk + PK_FWD2, w + OB2, x1, lane, h2);
         relu_to_operands(h2, x2);
-        layer<8>(pk + PK_FWD3, w + OB3, x2, lane, h3);
+        layer<4>(pk + PK_FWD3, w + OB3, x2, lane, h3);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) h3[t][j] = fmaxf(h3[t][j], 0.f);
+            for (int j = 0; j < 16; ++j) h3[t][j] = relu(h3[t][j]);
         const float y = out_layer(w, h3, lane);
         const float r = valid ? y - target[row] : 0.f;
         const float gout = 2.f * r * inv_m;              // d loss / d output of this row
@@ -607,10 +639,10 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
         __builtin_amdgcn_wave_barrier();
         weight_grad(dl, ac, H, gacc + OW3, lane);
         // delta2 = (W3 delta3) * [h2 > 0]
-        bf4 xd[8];
+        bf8 xd[4];
         to_operands(d3, xd);
         f16v d2[2];
-        layer<8>(pk + PK_BWD3, nullptr, xd, lane, d2);
+        layer<4>(pk + PK_BWD3, nullptr, xd, lane, d2);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -624,7 +656,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
         // delta1 = (W2 delta2) * [h1 > 0]
         f16v d1[2];
         to_operands(d2, xd);
-        layer<8>(pk + PK_BWD2, nullptr, xd, lane, d1);
+        layer<4>(pk + PK_BWD2, nullptr, xd, lane, d1);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -634,8 +666,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ w, c
         stash(d1, dl, lane);
         // the inputs as a [16][32] tile (rows of absent batch entries are zero)
         for (int j = 0; j < 4; ++j) {
-            ac[(4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[0][j];
-            ac[(8 + 4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[1][j];
+            ac[(4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[j];
+            ac[(8 + 4 * (lane >> 5) + j) * 32 + (lane & 31)] = (uint16_t)x0[4 + j];
         }
         __builtin_amdgcn_wave_barrier();
         // inputs 16..31 of the B tile read the next rows of ac, but only inputs
@@ -702,8 +734,8 @@ int check_mlp(vr_ctx* ctx, const void* w, int64_t m, const uint16_t* feat) {
     return VR_OK;
 }
 
-int pack_weights(vr_ctx* ctx, const float* w, bf4** out, hipStream_t st) {
-    VR_WS(pk, ctx, bf4, WS_B9, PK_TOTAL);
+int pack_weights(vr_ctx* ctx, const float* w, bf8** out, hipStream_t st) {
+    VR_WS(pk, ctx, bf8, WS_B9, PK_TOTAL);
     hipLaunchKernelGGL(k_mlp_pack, dim3(grid_for(PK_TOTAL, 256)), dim3(256), 0, st, w, pk);
     VR_LAUNCH_CHECK(ctx);
     *out = pk;
@@ -712,7 +744,7 @@ int pack_weights(vr_ctx* ctx, const float* w, bf4** out, hipStream_t st) {
 
 int run_grad(vr_ctx* ctx, const float* w, int64_t m, const uint16_t* feat, const int32_t* rows,
              const float* target, float** part_out, int* nwg_out, hipStream_t st) {
-    bf4* pk = nullptr;
+    bf8* pk = nullptr;
     int rc = pack_weights(ctx, w, &pk, st);
     if (rc) return rc;
     const int nwg = (int)std::min<int64_t>((m + GROWS - 1) / GROWS, (int64_t)ctx->num_cus * 2);
@@ -841,7 +873,7 @@ int vr_mlp_forward(vr_ctx* ctx, const float* weights, int64_t m, const uint16_t*
     if (!Rhat) return set_err(ctx, VR_ERR_INVALID_ARG, "Rhat is NULL");
     VR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    bf4* pk = nullptr;
+    bf8* pk = nullptr;
     if ((rc = pack_weights(ctx, weights, &pk, st))) return rc;
     const int64_t ntiles = (m + 31) / 32;
     const int64_t want = (ntiles + 3) / 4;
