@@ -243,16 +243,23 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                 // current worst key; pass 2: insert them, each lane walking its
                 // own mask, so the wave spends max-over-lanes insertions per
                 // chunk instead of one per candidate that any lane takes.
-                // Pass 1 is unrolled in blocks of 16 candidates with constant
-                // bit positions; bits past the chunk's end are cleared.
+                // Pass 1 is unrolled in blocks of 16 candidates.  The bound
+                // wf enters the FMA chain, dx^2 + dy^2 + (dz^2 - wf), whose
+                // rounding (three roundings of values below max(d2, wf)) stays
+                // inside wf's relative slack, so a negative result marks every
+                // candidate that may be taken; its sign bit is shifted into the
+                // mask from the bottom, candidates from the highest index down,
+                // so candidate t ends at bit t % 32 of word t / 32.  Bits past
+                // the chunk's end are cleared.
                 const float wf = count < n_se ? (tau == NO_BOUND ? INFINITY : (float)tau * 1.000001f + 1.0f)
                                               : (float)(worst >> POS_BITS) * 1.000001f + 1.0f;
+                const float nwf = -wf;
                 uint32_t tk[2] = {0u, 0u};
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
+                for (int b = 3; b >= 0; --b) {
                     if (16 * b < m) {
 #pragma unroll
-                        for (int t4 = 0; t4 < 16; t4 += 4) {
+                        for (int t4 = 12; t4 >= 0; t4 -= 4) {
                             const int t = 16 * b + t4;
                             const float4 X = *reinterpret_cast<const float4*>(&cxs[t]);
                             const float4 Y = *reinterpret_cast<const float4*>(&cys[t]);
@@ -260,11 +267,10 @@ __global__ __launch_bounds__(64) void k_knn(const uint32_t* __restrict__ qpos, i
                             const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w},
                                         zs[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
+                            for (int u = 3; u >= 0; --u) {
                                 const float dxf = xs[u] - pxf, dyf = ys[u] - pyf, dzf = zs[u] - pzf;
-                                const float d2f = fmaf(dxf, dxf, fmaf(dyf, dyf, dzf * dzf));
-                                const int bit = t + u;
-                                if (d2f <= wf) tk[bit >> 5] |= 1u << (bit & 31);
+                                const float sd = fmaf(dxf, dxf, fmaf(dyf, dyf, fmaf(dzf, dzf, nwf)));
+                                tk[b >> 1] = __builtin_amdgcn_alignbit(tk[b >> 1], __float_as_uint(sd), 31);
                             }
                         }
                     }
