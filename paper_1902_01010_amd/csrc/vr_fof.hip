@@ -149,16 +149,33 @@ __global__ void k_write_label(int64_t n, const int* __restrict__ parent, const u
 }
 
 // ---- groups -----------------------------------------------------------------
-// Labels are sorted with their particle indices (stable, so members of one
+// The labelled particles (0 <= label < n) are compacted in index order and
+// sorted with their particle indices by label (stable, so members of one
 // label stay in index order); label runs become segments, kept segments are
 // ordered by (size desc, label asc) and scattered into the member table.
-__global__ void k_label_keys(int64_t n, const int32_t* __restrict__ label, uint32_t* __restrict__ key,
-                             uint32_t* __restrict__ val) {
+// Unlabelled particles never enter the sort: their group_of is -1 at once.
+__global__ void k_label_flags(int64_t n, const int32_t* __restrict__ label, uint8_t* __restrict__ flag,
+                              int32_t* __restrict__ group_of) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int l = label[i];
-    key[i] = (l >= 0 && l < n) ? (uint32_t)l : (uint32_t)n;  // no label: after every label
-    val[i] = (uint32_t)i;
+    const bool has = l >= 0 && l < n;
+    flag[i] = has ? 1 : 0;
+    if (!has) group_of[i] = -1;
+}
+
+__global__ void k_label_total(int64_t n, const uint8_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                              uint32_t* __restrict__ total) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total = pos[n - 1] + flag[n - 1];
+}
+
+__global__ void k_label_keys(int64_t n, const int32_t* __restrict__ label, const uint8_t* __restrict__ flag,
+                             const uint32_t* __restrict__ pos, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const uint32_t k = pos[i];
+    key[k] = (uint32_t)label[i];
+    val[k] = (uint32_t)i;
 }
 
 __global__ void k_run_flags(int64_t n, const uint32_t* __restrict__ key, uint32_t* __restrict__ flag) {
@@ -175,12 +192,12 @@ __global__ void k_run_starts(int64_t n, const uint32_t* __restrict__ key, const 
     if (p == n - 1) run_start[start ? scan[p] + 1 : scan[p]] = (uint32_t)n;
 }
 
-__global__ void k_run_keep(int64_t nrun, int64_t n, const uint32_t* __restrict__ key,
-                           const uint32_t* __restrict__ run_start, int32_t n_min, uint32_t* __restrict__ keep) {
+__global__ void k_run_keep(int64_t nrun, const uint32_t* __restrict__ run_start, int32_t n_min,
+                           uint32_t* __restrict__ keep) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nrun) return;
     const uint32_t a = run_start[s], b = run_start[s + 1];
-    keep[s] = (key[a] < (uint32_t)n && b - a >= (uint32_t)n_min) ? 1u : 0u;
+    keep[s] = b - a >= (uint32_t)n_min ? 1u : 0u;
 }
 
 __global__ void k_run_compact(int64_t nrun, int64_t n, const uint32_t* __restrict__ keep,
@@ -369,27 +386,48 @@ extern "C" int vr_groups(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t n
     VR_WS(kpos, ctx, uint32_t, WS_B7, n);
     VR_WS(run_group, ctx, int32_t, WS_B8, n);
     VR_WS(tot, ctx, uint32_t, WS_FLAG, 4);
-    hipLaunchKernelGGL(k_label_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, key, val);
+    // the labelled particles, compacted in index order: the byte flags live
+    // in keep and their positions in runid until the runs need them
+    uint8_t* flag = reinterpret_cast<uint8_t*>(keep);
+    hipLaunchKernelGGL(k_label_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, flag, group_of);
     VR_LAUNCH_CHECK(ctx);
-    int rc = sort_pairs_u32(ctx, key, val, n, bits_for((uint64_t)n), st);
+    int rc = scan_u8(ctx, flag, runid, n, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, runid);
+    hipLaunchKernelGGL(k_label_total, dim3(1), dim3(64), 0, st, n, flag, runid, tot);
     VR_LAUNCH_CHECK(ctx);
-    rc = scan_u32(ctx, runid, runid, n, tot, st);
+    // labels are below n; the compacted pairs go where the sort ends in place
+    const int kbits = bits_for((uint64_t)(n - 1));
+    uint32_t *kin = key, *vin = val;
+    if ((rc = sort_input_u32(ctx, key, val, n, kbits, &kin, &vin))) return rc;
+    hipLaunchKernelGGL(k_label_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, n, label, flag, runid, kin, vin);
+    VR_LAUNCH_CHECK(ctx);
+    uint32_t m32 = 0;
+    rc = read_back(ctx, tot, &m32, sizeof m32, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_run_starts, dim3(grid_for(n, 256)), dim3(256), 0, st, n, key, runid, run_start);
-    VR_LAUNCH_CHECK(ctx);
+    const int64_t m = m32;  // labelled particles
     uint32_t nrun = 0;
-    rc = read_back(ctx, tot, &nrun, sizeof nrun, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_run_keep, dim3(grid_for(nrun, 256)), dim3(256), 0, st, (int64_t)nrun, n, key, run_start,
-                       n_min, keep);
+    if (m > 0) {
+        rc = sort_pairs_u32_from(ctx, kin, vin, key, val, m, kbits, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_run_flags, dim3(grid_for(m, 256)), dim3(256), 0, st, m, key, runid);
+        VR_LAUNCH_CHECK(ctx);
+        rc = scan_u32(ctx, runid, runid, m, tot, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_run_starts, dim3(grid_for(m, 256)), dim3(256), 0, st, m, key, runid, run_start);
+        VR_LAUNCH_CHECK(ctx);
+        rc = read_back(ctx, tot, &nrun, sizeof nrun, st);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_run_keep, dim3(grid_for(nrun, 256)), dim3(256), 0, st, (int64_t)nrun, run_start, n_min,
+                       keep);
     VR_LAUNCH_CHECK(ctx);
-    rc = scan_u32(ctx, keep, kpos, nrun, tot, st);
-    if (rc) return rc;
     uint32_t ng = 0;
-    rc = read_back(ctx, tot, &ng, sizeof ng, st);
-    if (rc) return rc;
+    if (nrun > 0) {
+        rc = scan_u32(ctx, keep, kpos, nrun, tot, st);
+        if (rc) return rc;
+        rc = read_back(ctx, tot, &ng, sizeof ng, st);
+        if (rc) return rc;
+    }
     *n_groups = (int32_t)ng;
     VR_WS(gkey, ctx, uint32_t, WS_B9, ng + 1);
     VR_WS(grun, ctx, uint32_t, WS_C0, ng + 1);
@@ -409,8 +447,9 @@ extern "C" int vr_groups(vr_ctx* ctx, int64_t n, const int32_t* label, int32_t n
     hipLaunchKernelGGL(k_u32_to_i32, dim3(grid_for((int64_t)ng + 1, 256)), dim3(256), 0, st, (int64_t)ng + 1, gsize,
                        offsets);
     VR_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_group_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, n, runid, run_start, run_group,
-                       gsize, val, group_of, members);
+    if (m > 0)
+        hipLaunchKernelGGL(k_group_scatter, dim3(grid_for(m, 256)), dim3(256), 0, st, m, runid, run_start,
+                           run_group, gsize, val, group_of, members);
     VR_LAUNCH_CHECK(ctx);
     return VR_OK;
 }

@@ -175,6 +175,13 @@ int sort_input_u64(vr_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int b
                    uint32_t** vin, int first_bit = 0);
 int sort_pairs_u64_from(vr_ctx* ctx, uint64_t* kin, uint32_t* vin, uint64_t* keys, uint32_t* vals, int64_t n,
                         int bits, hipStream_t s, int first_bit = 0);
+// The same for 32-bit keys.  The sort may take fewer pairs than the buffers
+// were placed for (a producer that compacts): n of sort_input is then an
+// upper bound of the sort's n, with the same bits.
+int sort_input_u32(vr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits, uint32_t** kin,
+                   uint32_t** vin);
+int sort_pairs_u32_from(vr_ctx* ctx, uint32_t* kin, uint32_t* vin, uint32_t* keys, uint32_t* vals, int64_t n,
+                        int bits, hipStream_t s);
 // Fill helpers (kernels, never memset nodes, so they are safe to capture).
 int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s);
 int fill_u32(vr_ctx* ctx, uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

@@ -421,6 +421,16 @@ int sort_pairs_u64_from(vr_ctx* ctx, uint64_t* kin, uint32_t* vin, uint64_t* key
     return sort_pairs_impl<uint64_t>(ctx, kin, vin, keys, vals, n, bits, s, first_bit);
 }
 
+int sort_input_u32(vr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits, uint32_t** kin,
+                   uint32_t** vin) {
+    return sort_input_impl<uint32_t>(ctx, keys, vals, n, bits, kin, vin);
+}
+
+int sort_pairs_u32_from(vr_ctx* ctx, uint32_t* kin, uint32_t* vin, uint32_t* keys, uint32_t* vals, int64_t n,
+                        int bits, hipStream_t s) {
+    return sort_pairs_impl<uint32_t>(ctx, kin, vin, keys, vals, n, bits, s);
+}
+
 int fill_i32(vr_ctx* ctx, int32_t* p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return VR_OK;
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
