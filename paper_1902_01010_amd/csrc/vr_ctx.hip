@@ -119,10 +119,24 @@ int check_hosts(vr_ctx* ctx, int32_t n_hosts, const int32_t* off, const int32_t*
     return VR_OK;
 }
 
-int read_back(vr_ctx* ctx, const void* dev, void* host, size_t bytes, hipStream_t s) {
-    VR_HIP(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+int copy_to_host(vr_ctx* ctx, void* host, const void* dev, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return VR_OK;
+    if (ctx->stage_bytes < bytes) {
+        if (ctx->stage) (void)hipHostFree(ctx->stage);
+        ctx->stage = nullptr;
+        ctx->stage_bytes = 0;
+        const size_t want = bytes + bytes / 4;
+        VR_HIP(ctx, hipHostMalloc(&ctx->stage, want, hipHostMallocDefault));
+        ctx->stage_bytes = want;
+    }
+    VR_HIP(ctx, hipMemcpyAsync(ctx->stage, dev, bytes, hipMemcpyDeviceToHost, s));
     VR_HIP(ctx, hipStreamSynchronize(s));
+    std::memcpy(host, ctx->stage, bytes);
     return VR_OK;
+}
+
+int read_back(vr_ctx* ctx, const void* dev, void* host, size_t bytes, hipStream_t s) {
+    return copy_to_host(ctx, host, dev, bytes, s);
 }
 
 }  // namespace vr
@@ -156,6 +170,12 @@ int vr_create(vr_ctx** out, int device, size_t max_workspace_bytes) {
         delete c;
         return vr::set_err(nullptr, VR_ERR_HIP, "hipHostMalloc failed");
     }
+    if (hipHostMalloc(&c->stage, 65536, hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return vr::set_err(nullptr, VR_ERR_HIP, "hipHostMalloc failed");
+    }
+    c->stage_bytes = 65536;
     c->slots.resize(vr::WS_NSLOTS);
     *out = c;
     return VR_OK;
@@ -172,6 +192,7 @@ void vr_destroy(vr_ctx* ctx) {
     for (auto& b : ctx->slots)
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->knn_cand) (void)hipFree(ctx->knn_cand);
     delete ctx;
 }

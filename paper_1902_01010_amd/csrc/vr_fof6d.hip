@@ -685,8 +685,8 @@ extern "C" int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
     VR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     std::vector<int32_t> off(n_hosts + 1);
-    VR_HIP(ctx, hipMemcpyAsync(off.data(), host_offsets, (n_hosts + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    VR_HIP(ctx, hipStreamSynchronize(st));
+    int rc0 = copy_to_host(ctx, off.data(), host_offsets, (n_hosts + 1) * sizeof(int32_t), st);
+    if (rc0) return rc0;
     if (off[0] != 0) return set_err(ctx, VR_ERR_INVALID_ARG, "host_offsets[0] must be 0");
     std::vector<int4> chunks;
     std::vector<int> coff(n_hosts + 1, 0);
@@ -742,8 +742,7 @@ int link_outliers(vr_ctx* ctx, const vr_particles* p, const int32_t* host_of, co
     hipStream_t st = (hipStream_t)stream;
     if (!sub && n_hosts > 0) {
         std::vector<double> ev(n_hosts);
-        VR_HIP(ctx, hipMemcpyAsync(ev.data(), ellv_host, n_hosts * sizeof(double), hipMemcpyDeviceToHost, st));
-        VR_HIP(ctx, hipStreamSynchronize(st));
+        if ((rc = copy_to_host(ctx, ev.data(), ellv_host, n_hosts * sizeof(double), st))) return rc;
         for (int h = 0; h < n_hosts; ++h)
             if (!(ev[h] > 0) || !std::isfinite(ev[h]))
                 return set_err(ctx, VR_ERR_INVALID_ARG, "ellv_host[%d] = %g is not a positive number", h, ev[h]);
@@ -985,9 +984,8 @@ extern "C" int vr_sub_grow(vr_ctx* ctx, const vr_particles* p, const int32_t* ho
         hipLaunchKernelGGL(k_cross<true>, g, dim3(256), 0, st, np, cl.key, cl.sx, cl.sy, cl.sz, shost, cl.cell_start,
                            cl.hkeys, cl.hvals, cl.hmask, b, gb, ell2, sl, tagA, size, cnt, (int64_t)ncross, pairs, psz);
         VR_LAUNCH_CHECK(ctx);
-        VR_HIP(ctx, hipMemcpyAsync(hp.data(), pairs, ncross * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        VR_HIP(ctx, hipMemcpyAsync(hs.data(), psz, ncross * sizeof(int2), hipMemcpyDeviceToHost, st));
-        VR_HIP(ctx, hipStreamSynchronize(st));
+        if ((rc = copy_to_host(ctx, hp.data(), pairs, ncross * sizeof(uint64_t), st))) return rc;
+        if ((rc = copy_to_host(ctx, hs.data(), psz, ncross * sizeof(int2), st))) return rc;
     }
     // joins: the relaxed links of a pair of groups against f_merge times the
     // first-stage size of either; union by smaller label, transitive

@@ -40,6 +40,9 @@ struct vr_ctx {
     std::string err;
     // host-pinned scalars for counts returned by syncing calls
     int64_t* pinned = nullptr;
+    // host-pinned staging for copy_to_host (64 KB from creation, grown on demand)
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
     int tuned_tile = 0;     // potential j-tile picked by the autotuner (0 = default)
     int knn_leaf = 64;      // members per leaf of the neighbour-search tree
     int unbind_jchunk = 4096;
@@ -188,6 +191,10 @@ int fill_u32(vr_ctx* ctx, uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int iota_u32(vr_ctx* ctx, uint32_t* p, int64_t n, hipStream_t s);
 // Copy one device scalar to the host and wait.
 int read_back(vr_ctx* ctx, const void* dev, void* host, size_t bytes, hipStream_t s);
+// Copy bytes of device memory to (pageable) host memory through the
+// context's pinned staging buffer, waiting for the stream; the buffer grows
+// (hipHostMalloc) only for reads beyond its size.
+int copy_to_host(vr_ctx* ctx, void* host, const void* dev, size_t bytes, hipStream_t s);
 
 // ---- device helpers --------------------------------------------------------
 __device__ __forceinline__ int min_image(int d, int gb) {

@@ -492,8 +492,8 @@ int read_host_offsets(vr_ctx* ctx, int32_t n_hosts, const int32_t* host_offsets,
                       std::vector<int32_t>& off, hipStream_t st) {
     off.assign(n_hosts + 1, 0);
     if (n_hosts == 0) return VR_OK;
-    VR_HIP(ctx, hipMemcpyAsync(off.data(), host_offsets, (n_hosts + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    VR_HIP(ctx, hipStreamSynchronize(st));
+    int rc0 = copy_to_host(ctx, off.data(), host_offsets, (n_hosts + 1) * sizeof(int32_t), st);
+    if (rc0) return rc0;
     if (off[0] != 0) return set_err(ctx, VR_ERR_INVALID_ARG, "host_offsets[0] must be 0");
     for (int h = 0; h < n_hosts; ++h) {
         const int64_t NH = (int64_t)off[h + 1] - off[h];

@@ -742,8 +742,8 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     VR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     std::vector<int32_t> off(n_groups + 1);
-    VR_HIP(ctx, hipMemcpyAsync(off.data(), offsets, (n_groups + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    VR_HIP(ctx, hipStreamSynchronize(st));
+    int rc0 = copy_to_host(ctx, off.data(), offsets, (n_groups + 1) * sizeof(int32_t), st);
+    if (rc0) return rc0;
     if (off[0] != 0) return set_err(ctx, VR_ERR_INVALID_ARG, "offsets[0] must be 0");
     for (int g = 0; g < n_groups; ++g) {
         if (off[g + 1] < off[g]) return set_err(ctx, VR_ERR_INVALID_ARG, "offsets must be non-decreasing");
@@ -793,9 +793,8 @@ extern "C" int vr_unbind(vr_ctx* ctx, const vr_particles* p, int32_t n_groups, c
     std::vector<int> hcnt(n_groups), hstate(n_groups), hact;
     std::vector<int4> items;
     for (int pass = 0;; ++pass) {
-        VR_HIP(ctx, hipMemcpyAsync(hcnt.data(), cnt, n_groups * sizeof(int), hipMemcpyDeviceToHost, st));
-        VR_HIP(ctx, hipMemcpyAsync(hstate.data(), state, n_groups * sizeof(int), hipMemcpyDeviceToHost, st));
-        VR_HIP(ctx, hipStreamSynchronize(st));
+        if (int rc1 = copy_to_host(ctx, hcnt.data(), cnt, n_groups * sizeof(int), st)) return rc1;
+        if (int rc1 = copy_to_host(ctx, hstate.data(), state, n_groups * sizeof(int), st)) return rc1;
         hact.clear();
         items.clear();
         double pairs = 0.0, nmem = 0.0;
