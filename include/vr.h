@@ -199,7 +199,9 @@ int vr_local_vdensity(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
 
 /* Velocity linking length per host (Sec. 2.1: ellv = alpha_v sigma_v with
  * sigma_v = (det Sigma_H)^(1/6), Sigma_H the mass-weighted dispersion tensor
- * of all members about their mass-weighted mean).  ellv_host[n_hosts]. */
+ * of all members about their mass-weighted mean).  ellv_host[n_hosts].
+ * Syncs once, before its kernels (the host offsets are validated on the
+ * host); the result is ready when the stream reaches it. */
 int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
                  const int32_t* host_offsets, const int32_t* host_members, double alpha_v,
                  double* ellv_host, void* stream);

@@ -1,6 +1,7 @@
 // vr_ctx.hip -- context, workspace pool, errors and argument checks.
 #include "vr_internal.h"
 
+#include <algorithm>
 #include <cstring>
 
 namespace {
@@ -123,6 +124,8 @@ int copy_to_host(vr_ctx* ctx, void* host, const void* dev, size_t bytes, hipStre
     if (bytes == 0) return VR_OK;
     if (ctx->stage_bytes < bytes) {
         if (ctx->stage) (void)hipHostFree(ctx->stage);
+    if (ctx->up) (void)hipHostFree(ctx->up);
+    if (ctx->up_event) (void)hipEventDestroy(ctx->up_event);
         ctx->stage = nullptr;
         ctx->stage_bytes = 0;
         const size_t want = bytes + bytes / 4;
@@ -132,6 +135,38 @@ int copy_to_host(vr_ctx* ctx, void* host, const void* dev, size_t bytes, hipStre
     VR_HIP(ctx, hipMemcpyAsync(ctx->stage, dev, bytes, hipMemcpyDeviceToHost, s));
     VR_HIP(ctx, hipStreamSynchronize(s));
     std::memcpy(host, ctx->stage, bytes);
+    return VR_OK;
+}
+
+void* upload_begin(vr_ctx* ctx, size_t bytes) {
+    if (ctx->up_pending) {
+        const hipError_t e = hipEventSynchronize(ctx->up_event);
+        if (e != hipSuccess) {
+            set_err(ctx, VR_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        ctx->up_pending = false;
+    }
+    if (ctx->up_bytes < bytes) {
+        if (ctx->up) (void)hipHostFree(ctx->up);
+        ctx->up = nullptr;
+        ctx->up_bytes = 0;
+        const size_t want = std::max<size_t>(bytes + bytes / 4, 65536);
+        const hipError_t e = hipHostMalloc(&ctx->up, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            ctx->up = nullptr;
+            set_err(ctx, VR_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        ctx->up_bytes = want;
+    }
+    return ctx->up;
+}
+
+int upload_end(vr_ctx* ctx, hipStream_t s) {
+    if (!ctx->up_event) VR_HIP(ctx, hipEventCreateWithFlags(&ctx->up_event, hipEventDisableTiming));
+    VR_HIP(ctx, hipEventRecord(ctx->up_event, s));
+    ctx->up_pending = true;
     return VR_OK;
 }
 

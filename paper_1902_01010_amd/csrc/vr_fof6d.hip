@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <unordered_map>
 #include <vector>
 
@@ -701,16 +702,23 @@ extern "C" int vr_host_ellv(vr_ctx* ctx, const vr_particles* p, int32_t n_hosts,
     VR_WS(chunks_d, ctx, int4, WS_D4, nch);
     VR_WS(coff_d, ctx, int, WS_D5, n_hosts + 1);
     VR_WS(part, ctx, double, WS_D6, (int64_t)nch * ELLV_PART);
-    VR_HIP(ctx, hipMemcpyAsync(chunks_d, chunks.data(), nch * sizeof(int4), hipMemcpyHostToDevice, st));
-    VR_HIP(ctx, hipMemcpyAsync(coff_d, coff.data(), (n_hosts + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    {
+        // both tables through the pinned upload buffer: no wait here
+        const size_t bc = (size_t)nch * sizeof(int4), bo = (size_t)(n_hosts + 1) * sizeof(int);
+        char* up = static_cast<char*>(upload_begin(ctx, bc + bo));
+        if (!up) return VR_ERR_HIP;
+        std::memcpy(up, chunks.data(), bc);
+        std::memcpy(up + bc, coff.data(), bo);
+        VR_HIP(ctx, hipMemcpyAsync(chunks_d, up, bc, hipMemcpyHostToDevice, st));
+        VR_HIP(ctx, hipMemcpyAsync(coff_d, up + bc, bo, hipMemcpyHostToDevice, st));
+        if (int rc1 = upload_end(ctx, st)) return rc1;
+    }
     hipLaunchKernelGGL(k_ellv_sums, dim3(nch), dim3(256), 0, st, chunks_d, host_members, host_offsets, p->vx, p->vy,
                        p->vz, p->mass, p->mass_value, part);
     VR_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ellv_final, dim3(grid_for(n_hosts, 256)), dim3(256), 0, st, n_hosts, coff_d, part, alpha_v,
                        ellv_host);
     VR_LAUNCH_CHECK(ctx);
-    // the host vectors above are copied asynchronously: wait before they go away
-    VR_HIP(ctx, hipStreamSynchronize(st));
     return VR_OK;
 }
 

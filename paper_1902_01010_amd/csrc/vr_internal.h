@@ -43,6 +43,12 @@ struct vr_ctx {
     // host-pinned staging for copy_to_host (64 KB from creation, grown on demand)
     void* stage = nullptr;
     size_t stage_bytes = 0;
+    // host-pinned staging for uploads, and the event after the last upload
+    // that read it (upload_begin waits for that event before reusing it)
+    void* up = nullptr;
+    size_t up_bytes = 0;
+    hipEvent_t up_event = nullptr;
+    bool up_pending = false;
     int tuned_tile = 0;     // potential j-tile picked by the autotuner (0 = default)
     int knn_leaf = 64;      // members per leaf of the neighbour-search tree
     int unbind_jchunk = 4096;
@@ -195,6 +201,12 @@ int read_back(vr_ctx* ctx, const void* dev, void* host, size_t bytes, hipStream_
 // context's pinned staging buffer, waiting for the stream; the buffer grows
 // (hipHostMalloc) only for reads beyond its size.
 int copy_to_host(vr_ctx* ctx, void* host, const void* dev, size_t bytes, hipStream_t s);
+// Uploads without a sync: upload_begin returns the context's pinned upload
+// buffer with room for bytes (null on failure, error set), once no earlier
+// upload still reads it; the caller fills it, enqueues its host-to-device
+// copies from it, and calls upload_end, which records the event they end at.
+void* upload_begin(vr_ctx* ctx, size_t bytes);
+int upload_end(vr_ctx* ctx, hipStream_t s);
 
 // ---- device helpers --------------------------------------------------------
 __device__ __forceinline__ int min_image(int d, int gb) {

@@ -294,10 +294,16 @@ class Context:
         n = P.n
         nh = host_offsets.shape[0] - 1
         if out is None:
-            # particle-major storage, returned as (3, n) and (6, n) views
-            out = dict(vbar=torch.full((n, 3), float("nan"), device=dev).t(),
-                       sigma=torch.full((n, 6), float("nan"), device=dev).t(),
-                       rho_cell=torch.full((n,), float("nan"), device=dev) if want_rho else None,
+            # particle-major storage, returned as (3, n) and (6, n) views;
+            # the float outputs share one NaN-filled allocation (one fill),
+            # each part starting on a 256-byte boundary
+            a = lambda k: -(-k // 64) * 64  # noqa: E731
+            o1 = a(3 * n)
+            o2 = a(o1 + 6 * n)
+            buf = torch.full((o2 + (n if want_rho else 0),), float("nan"), device=dev)
+            out = dict(vbar=buf[:3 * n].view(n, 3).t(),
+                       sigma=buf[o1:o1 + 6 * n].view(n, 6).t(),
+                       rho_cell=buf[o2:o2 + n] if want_rho else None,
                        cell_of=torch.full((n,), -1, dtype=torch.int32, device=dev) if want_cell_of else None)
         cp = _CellParams(f_cell, ncell_floor, ncell_div, nbins, split_rule)
         vb_l, sg_l = _pm(out["vbar"], 3, True), _pm(out["sigma"], 6, True)
