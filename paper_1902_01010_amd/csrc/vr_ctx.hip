@@ -123,9 +123,7 @@ int check_hosts(vr_ctx* ctx, int32_t n_hosts, const int32_t* off, const int32_t*
 int copy_to_host(vr_ctx* ctx, void* host, const void* dev, size_t bytes, hipStream_t s) {
     if (bytes == 0) return VR_OK;
     if (ctx->stage_bytes < bytes) {
-        if (ctx->stage) (void)hipHostFree(ctx->stage);
-    if (ctx->up) (void)hipHostFree(ctx->up);
-    if (ctx->up_event) (void)hipEventDestroy(ctx->up_event);
+        if (ctx->stage) VR_HIP(ctx, hipHostFree(ctx->stage));
         ctx->stage = nullptr;
         ctx->stage_bytes = 0;
         const size_t want = bytes + bytes / 4;
@@ -148,7 +146,13 @@ void* upload_begin(vr_ctx* ctx, size_t bytes) {
         ctx->up_pending = false;
     }
     if (ctx->up_bytes < bytes) {
-        if (ctx->up) (void)hipHostFree(ctx->up);
+        if (ctx->up) {
+            const hipError_t e = hipHostFree(ctx->up);
+            if (e != hipSuccess) {
+                set_err(ctx, VR_ERR_HIP, "hipHostFree: %s", hipGetErrorString(e));
+                return nullptr;
+            }
+        }
         ctx->up = nullptr;
         ctx->up_bytes = 0;
         const size_t want = std::max<size_t>(bytes + bytes / 4, 65536);
@@ -228,6 +232,8 @@ void vr_destroy(vr_ctx* ctx) {
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
+    if (ctx->up) (void)hipHostFree(ctx->up);
+    if (ctx->up_event) (void)hipEventDestroy(ctx->up_event);
     if (ctx->knn_cand) (void)hipFree(ctx->knn_cand);
     delete ctx;
 }

@@ -116,7 +116,15 @@ inline T* wsT(vr_ctx* ctx, int slot, size_t count) {
             return ::vr::set_err(ctx, VR_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-#define VR_LAUNCH_CHECK(ctx) VR_HIP(ctx, hipGetLastError())
+// The last launch (or an earlier unchecked runtime call) failed; the message
+// names the line that noticed it.
+#define VR_LAUNCH_CHECK(ctx)                                                                       \
+    do {                                                                                           \
+        hipError_t e_ = hipGetLastError();                                                         \
+        if (e_ != hipSuccess)                                                                      \
+            return ::vr::set_err(ctx, VR_ERR_HIP, "launch check at %s:%d: %s", __FILE__, __LINE__, \
+                                 hipGetErrorString(e_));                                           \
+    } while (0)
 
 #define VR_WS(ptr, ctx, T, slot, count)                       \
     T* ptr = ::vr::wsT<T>(ctx, slot, (size_t)(count));        \

@@ -163,6 +163,31 @@ def test_host_ellv_parity(ctx, ref, case):
     np.testing.assert_allclose(got, exp, rtol=1e-12)
 
 
+def test_host_reads_beyond_the_staging_buffer(ctx, vr, ref):
+    """20,000 hosts: the host offsets (80 KB) and the hosts' velocity
+    linking lengths (160 KB) are read back through the context's pinned
+    staging buffer, which grows past its initial 64 KB, while the chunk
+    tables of host_ellv go up through the pinned upload buffer.  host_ellv,
+    fof6d, host_ellv again: the second call reuses the upload buffer after
+    the staging buffer grew, and both calls match the oracle."""
+    w = synth.unbind_groups(seed=11, sizes=[20] * 20_000)
+    off, mem = w.groups
+    assert len(off) - 1 > 16_384
+    P, Pr = both(ctx, vr, ref, w)
+    host_of = np.full(w.n, -1, np.int32)
+    for g in range(len(off) - 1):
+        host_of[mem[off[g]:off[g + 1]]] = g
+    exp = ref.host_ellv(Pr, off, mem, 1.25)
+    off_d, mem_d = dev_tensor(off), dev_tensor(mem)
+    e1 = ctx.host_ellv(P, off_d, mem_d, 1.25)
+    lab = ctx.fof6d(P, dev_tensor(host_of), e1, 0.01 * w.box)
+    e2 = ctx.host_ellv(P, off_d, mem_d, 1.25)
+    lab2 = ctx.fof6d(P, dev_tensor(host_of), e2, 0.01 * w.box)
+    np.testing.assert_allclose(e1.cpu().numpy(), exp, rtol=1e-12)
+    assert (e2.cpu().numpy() == e1.cpu().numpy()).all()
+    assert (lab2.cpu().numpy() == lab.cpu().numpy()).all()
+
+
 def _R_close(g, e):
     fin = np.isfinite(e)
     assert (np.isnan(g) == np.isnan(e)).all()
