@@ -502,8 +502,11 @@ __global__ void k_ub_zero_p(const UbPlan* __restrict__ plan, const int* __restri
     for (int k = s + threadIdx.x; k < e; k += blockDim.x) acc[k] = 0.0;
 }
 
-// Persistent potential kernel: every wavefront pops items until the queue is
-// empty; lane = one i of a 64-row tile, j staged through the wave's LDS slice.
+// Persistent potential kernel: wavefront w takes item w first, then pops
+// items nwaves, nwaves + 1, ... from the queue until it is empty (so a light
+// pass costs no burst of atomics on the queue head, and wavefronts beyond the
+// item count leave at once); lane = one i of a 64-row tile, j staged through
+// the wave's LDS slice.
 template <bool UNIFORM>
 __global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* __restrict__ act,
                                                        const int* __restrict__ item_off, const int32_t* __restrict__ off,
@@ -513,10 +516,9 @@ __global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* 
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     float4* sj = sjall + wv * tile;
     const int na = plan->n_active, total = plan->total_items;
-    for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(&plan->head, 1);
-        it = __shfl(it, 0, 64);
+    const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+    int it = (int)(blockIdx.x * (blockDim.x >> 6)) + wv;
+    for (;; ) {
         if (it >= total) break;
         // the group holding item `it`
         int lo = 0, hi = na - 1;
@@ -559,6 +561,9 @@ __global__ __launch_bounds__(UB) void k_ub_potential_p(UbPlan* plan, const int* 
             }
         }
         if (valid) atomicAdd(&acc[base + i], incr ? -accd : accd);
+        int nx = 0;
+        if (lane == 0) nx = atomicAdd(&plan->head, 1);
+        it = nwaves + __shfl(nx, 0, 64);
     }
 }
 
